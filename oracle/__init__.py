@@ -1,0 +1,208 @@
+"""ctypes front-end of the FP64 C oracle (oracle.c).
+
+TEST INFRASTRUCTURE: imported only by tests/, the smoke check and the
+benchmark's CPU-baseline leg.  Nothing in the product package imports it."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+_lp = C.POINTER(C.c_int64)
+
+
+def _load():
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = os.path.join(HERE, "liboracle.so")
+    if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(os.path.join(HERE, "oracle.c")):
+        from . import build as _b
+        _b.build()
+    lib = C.CDLL(path)
+    vp = C.c_void_p
+    lib.ora_mesh_build.argtypes = [C.c_int64, _dp, C.c_int64, _ip, C.POINTER(vp)]
+    lib.ora_mesh_build.restype = C.c_int
+    lib.ora_mesh_free.argtypes = [vp]
+    for name in ("ora_mesh_edges", "ora_mesh_faces", "ora_mesh_tet_edges", "ora_mesh_tet_faces", "ora_mesh_neighbours"):
+        getattr(lib, name).argtypes = [vp, _ip]
+    lib.ora_mesh_counts.argtypes = [vp, _lp]
+    lib.ora_grad.argtypes = [vp, C.c_int64, _dp]
+    lib.ora_bary.argtypes = [vp, C.c_int64, _dp, _dp]
+    lib.ora_point.argtypes = [vp, C.c_int64, _dp, _dp]
+    lib.ora_whitney1.argtypes = [vp, C.c_int64, _dp, _dp]
+    lib.ora_whitney2.argtypes = [vp, C.c_int64, _dp, _dp]
+    lib.ora_fields.argtypes = [vp, C.c_int64, _dp, C.c_double, C.c_double, _dp, _dp, _dp, _dp, _dp, _dp]
+    lib.ora_boris.argtypes = [_dp, _dp, _dp, C.c_double, C.c_double]
+    lib.ora_step.argtypes = [vp, C.c_int64, _ip, _dp, _dp, C.c_double, C.c_double, C.c_double, C.c_int64,
+                             C.c_double, C.c_double, _dp, _dp, _dp, _dp, _dp, _dp, _ip, C.c_int]
+    lib.ora_step.restype = C.c_int
+    lib.ora_step_one.argtypes = [vp, _ip, _dp, _dp, C.c_double, C.c_double, C.c_double, C.c_int64, C.c_double,
+                                 C.c_double, _dp, _dp, _dp, _dp, _dp, _lp, _ip]
+    lib.ora_step_one.restype = C.c_int
+    lib.ora_charge.argtypes = [vp, C.c_int64, _ip, _dp, C.c_double, C.c_double, _dp]
+    lib.ora_gauss.argtypes = [vp, _dp, _dp, _dp, _dp]
+    lib.ora_locate.argtypes = [vp, _dp, _dp]
+    lib.ora_locate.restype = C.c_int64
+    _LIB = lib
+    return lib
+
+
+def _p(a, ty=_dp):
+    return None if a is None else a.ctypes.data_as(ty)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _cplx(z):
+    """complex128[N] -> contiguous float64[N,2]"""
+    if z is None:
+        return None
+    z = np.asarray(z)
+    if np.iscomplexobj(z):
+        return np.ascontiguousarray(np.stack([z.real, z.imag], axis=1))
+    return _f64(z)
+
+
+class OracleMesh:
+    """Own connectivity of a tet mesh (built by the C oracle)."""
+
+    def __init__(self, xyz, tet_vert):
+        lib = _load()
+        self.xyz = _f64(xyz)
+        self.tv = np.ascontiguousarray(tet_vert, dtype=np.int32)
+        h = C.c_void_p()
+        rc = lib.ora_mesh_build(self.xyz.shape[0], _p(self.xyz), self.tv.shape[0], _p(self.tv, _ip), C.byref(h))
+        if rc != 0:
+            raise ValueError(f"oracle mesh build failed ({rc})")
+        self.h = h
+        cnt = np.zeros(4, dtype=np.int64)
+        lib.ora_mesh_counts(h, _p(cnt, _lp))
+        self.nv, self.ne, self.nf, self.nt = (int(x) for x in cnt)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _LIB is not None:
+            _LIB.ora_mesh_free(self.h)
+            self.h = None
+
+    def _int_table(self, name, cols, rows):
+        out = np.zeros((rows, cols), dtype=np.int32)
+        getattr(_load(), name)(self.h, _p(out, _ip))
+        return out
+
+    def edges(self):
+        return self._int_table("ora_mesh_edges", 2, self.ne)
+
+    def faces(self):
+        return self._int_table("ora_mesh_faces", 3, self.nf)
+
+    def tet_edges(self):
+        return self._int_table("ora_mesh_tet_edges", 6, self.nt)
+
+    def tet_faces(self):
+        return self._int_table("ora_mesh_tet_faces", 4, self.nt)
+
+    def neighbours(self):
+        return self._int_table("ora_mesh_neighbours", 4, self.nt)
+
+    # -- pointwise geometry / basis -------------------------------------------
+    def grad(self, T):
+        g = np.zeros((4, 3))
+        _load().ora_grad(self.h, int(T), _p(g))
+        return g
+
+    def bary(self, T, x):
+        lam = np.zeros(4)
+        _load().ora_bary(self.h, int(T), _p(_f64(x)), _p(lam))
+        return lam
+
+    def point(self, T, lam4):
+        x = np.zeros(3)
+        _load().ora_point(self.h, int(T), _p(_f64(lam4)), _p(x))
+        return x
+
+    def whitney1(self, T, lam4):
+        W = np.zeros((6, 3))
+        _load().ora_whitney1(self.h, int(T), _p(_f64(lam4)), _p(W))
+        return W
+
+    def whitney2(self, T, lam4):
+        W = np.zeros((4, 3))
+        _load().ora_whitney2(self.h, int(T), _p(_f64(lam4)), _p(W))
+        return W
+
+    def fields(self, T, lam4, omega, t, e_env, b_env, e_dc=None, b_dc=None):
+        E = np.zeros(3)
+        B = np.zeros(3)
+        ee, bb = _cplx(e_env), _cplx(b_env)
+        ed = None if e_dc is None else _f64(e_dc)
+        bd = None if b_dc is None else _f64(b_dc)
+        _load().ora_fields(self.h, int(T), _p(_f64(lam4)), float(omega), float(t), _p(ee), _p(ed), _p(bb), _p(bd),
+                           _p(E), _p(B))
+        return E, B
+
+    def locate(self, x):
+        ml = C.c_double()
+        t = _load().ora_locate(self.h, _p(_f64(x)), C.byref(ml))
+        return int(t), ml.value
+
+    # -- the step ---------------------------------------------------------------
+    def step(self, tet, lam, vel, *, q, m, w, step, dt, omega, e_env, b_env, e_dc=None, b_dc=None,
+             dG=None, rho=None, want_hops=False, nthreads=1):
+        """One step for all particles, in place on (tet, lam, vel).  dG / rho
+        accumulate.  Returns (status, hops or None)."""
+        assert tet.dtype == np.int32 and tet.flags.c_contiguous
+        assert lam.dtype == np.float64 and lam.flags.c_contiguous
+        assert vel.dtype == np.float64 and vel.flags.c_contiguous
+        n = tet.shape[0]
+        ee, bb = _cplx(e_env), _cplx(b_env)
+        ed = None if e_dc is None else _f64(e_dc)
+        bd = None if b_dc is None else _f64(b_dc)
+        hops = np.zeros(n, dtype=np.int32) if want_hops else None
+        rc = _load().ora_step(self.h, n, _p(tet, _ip), _p(lam), _p(vel), float(q), float(m), float(w), int(step),
+                              float(dt), float(omega), _p(ee), _p(ed), _p(bb), _p(bd), _p(dG), _p(rho),
+                              _p(hops, _ip), int(nthreads))
+        return rc, hops
+
+    def step_one(self, tet, lam3, v, *, q, m, w, step, dt, omega, e_env, b_env, e_dc=None, b_dc=None, dG=None):
+        """Single particle; returns (status, tet, lam3, v, piece_tets)."""
+        t = np.array([tet], dtype=np.int32)
+        l = _f64(lam3).copy()
+        vv = _f64(v).copy()
+        pt = np.zeros(130, dtype=np.int64)
+        npc = np.zeros(1, dtype=np.int32)
+        if dG is None:
+            dG = np.zeros(self.ne)
+        ee, bb = _cplx(e_env), _cplx(b_env)
+        ed = None if e_dc is None else _f64(e_dc)
+        bd = None if b_dc is None else _f64(b_dc)
+        rc = _load().ora_step_one(self.h, _p(t, _ip), _p(l), _p(vv), float(q), float(m), float(w), int(step),
+                                  float(dt), float(omega), _p(ee), _p(ed), _p(bb), _p(bd), _p(dG),
+                                  _p(pt, _lp), _p(npc, _ip))
+        return rc, int(t[0]), l, vv, pt[: int(npc[0])].copy()
+
+    def charge(self, tet, lam, q, w, rho=None):
+        if rho is None:
+            rho = np.zeros(self.nv)
+        _load().ora_charge(self.h, tet.shape[0], _p(np.ascontiguousarray(tet, dtype=np.int32), _ip),
+                           _p(_f64(lam)), float(q), float(w), _p(rho))
+        return rho
+
+    def gauss(self, dG, rho_new, rho_old):
+        out = np.zeros(2)
+        _load().ora_gauss(self.h, _p(_f64(dG)), _p(_f64(rho_new)), _p(_f64(rho_old)), _p(out))
+        return out[0], out[1]
+
+    def positions(self, tet, lam):
+        """Cartesian positions x = sum_k lambda_k r_k (numpy, for comparisons)."""
+        l0 = 1.0 - lam.sum(axis=1)
+        r = self.xyz[self.tv[tet]]
+        return l0[:, None] * r[:, 0] + lam[:, 0:1] * r[:, 1] + lam[:, 1:2] * r[:, 2] + lam[:, 2:3] * r[:, 3]

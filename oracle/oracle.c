@@ -1,0 +1,525 @@
+/*
+ * FP64 CPU oracle for the envelope-tracking particle-mesh step
+ * (Ramachandran et al., "An Envelope Tracking Approach for Particle in Cell
+ * Simulations").  TEST INFRASTRUCTURE ONLY: it is linked by the test-suite, by
+ * the smoke check and by the CPU-baseline leg of the benchmark, never by the
+ * product path.  It shares no code with the GPU library.
+ *
+ * Plain, slow, scalar C, one particle at a time, in the order the method takes
+ * its steps:
+ *   1. fields at the particle: Whitney edge (E) and face (B) expansions
+ *      (Formulation, "Discretization in Space and Time", the E~/B~ expansion),
+ *      with the envelope modulated by the carrier and the real part taken
+ *      (Particle Push section: dv/dt = q/m Re{E~ e^{j w t}} + v x Re{B~ e^{j w t}});
+ *   2. a Lorentz update at the fine step (the "simpler" scheme of the Particle
+ *      Push section) -- the textbook Boris rotation, non-relativistic;
+ *   3. the straight-line path of the step walked through the mesh;
+ *   4. the path integral of the Whitney 1-forms along each piece, i.e. the
+ *      edge DoFs g_l = <W1_l, G> of G = q * sum_p int dr (eq. g_def and the
+ *      piecewise sum of eq. G_integral).
+ * Each function cites the passage it follows.
+ *
+ * Conventions (shared definitions, own implementation): tet rows are ascending
+ * vertex ids; local edge order (0,1),(0,2),(0,3),(1,2),(1,3),(2,3); local face k
+ * is opposite local vertex k; global edges (a<b) and faces (a<b<c) are numbered
+ * lexicographically; face orientation (r_b-r_a)x(r_c-r_a).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORA_HOP_CAP 64
+
+typedef struct ora_mesh {
+    int64_t nv, nt, ne, nf;
+    double *xyz;       /* nv*3 */
+    int32_t *tv;       /* nt*4, ascending */
+    int32_t *edges;    /* ne*2 */
+    int32_t *faces;    /* nf*3 */
+    int32_t *tet_edge; /* nt*6 */
+    int32_t *tet_face; /* nt*4, face opposite local vertex k */
+    int32_t *nbr;      /* nt*4, tet across face k or -1 */
+} ora_mesh;
+
+static const int LE[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+static const int LF[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+
+static int cmp_i64(const void *a, const void *b) {
+    int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    return (x > y) - (x < y);
+}
+
+static int64_t find_key(const int64_t *keys, int64_t n, int64_t k) {
+    int64_t lo = 0, hi = n - 1;
+    while (lo <= hi) {
+        int64_t mid = (lo + hi) / 2;
+        if (keys[mid] == k) return mid;
+        if (keys[mid] < k) lo = mid + 1; else hi = mid - 1;
+    }
+    return -1;
+}
+
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static void cross3(const double *a, const double *b, double *c) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+static void sub3(const double *a, const double *b, double *c) { c[0] = a[0] - b[0]; c[1] = a[1] - b[1]; c[2] = a[2] - b[2]; }
+
+void ora_mesh_free(ora_mesh *m) {
+    if (!m) return;
+    free(m->xyz); free(m->tv); free(m->edges); free(m->faces);
+    free(m->tet_edge); free(m->tet_face); free(m->nbr);
+    free(m);
+}
+
+/* Mesh sets N, E, F, T and their incidences (Appendix A, first paragraph).
+ * Returns 0 on success, -1 bad input, -4 degenerate tet or non-manifold face. */
+int ora_mesh_build(int64_t nv, const double *xyz, int64_t nt, const int32_t *tv, ora_mesh **out) {
+    *out = NULL;
+    if (nv <= 0 || nt <= 0) return -1;
+    ora_mesh *m = (ora_mesh *)calloc(1, sizeof(ora_mesh));
+    m->nv = nv; m->nt = nt;
+    m->xyz = (double *)malloc(sizeof(double) * 3 * nv);
+    memcpy(m->xyz, xyz, sizeof(double) * 3 * nv);
+    m->tv = (int32_t *)malloc(sizeof(int32_t) * 4 * nt);
+    memcpy(m->tv, tv, sizeof(int32_t) * 4 * nt);
+    for (int64_t t = 0; t < nt; ++t) {
+        const int32_t *v = tv + 4 * t;
+        for (int k = 0; k < 4; ++k)
+            if (v[k] < 0 || v[k] >= nv || (k > 0 && v[k] <= v[k - 1])) { ora_mesh_free(m); return -1; }
+        double a[3], b[3], c[3], bc[3];
+        sub3(xyz + 3 * v[1], xyz + 3 * v[0], a);
+        sub3(xyz + 3 * v[2], xyz + 3 * v[0], b);
+        sub3(xyz + 3 * v[3], xyz + 3 * v[0], c);
+        cross3(b, c, bc);
+        double vol6 = dot3(a, bc);
+        double la = sqrt(dot3(a, a)), lb = sqrt(dot3(b, b)), lc = sqrt(dot3(c, c));
+        if (!(fabs(vol6) > 1e-12 * la * lb * lc)) { ora_mesh_free(m); return -4; }
+    }
+    /* edges */
+    int64_t *ek = (int64_t *)malloc(sizeof(int64_t) * 6 * nt);
+    for (int64_t t = 0; t < nt; ++t)
+        for (int e = 0; e < 6; ++e)
+            ek[6 * t + e] = (int64_t)tv[4 * t + LE[e][0]] * nv + tv[4 * t + LE[e][1]];
+    qsort(ek, 6 * nt, sizeof(int64_t), cmp_i64);
+    int64_t ne = 0;
+    for (int64_t i = 0; i < 6 * nt; ++i)
+        if (i == 0 || ek[i] != ek[i - 1]) ek[ne++] = ek[i];
+    m->ne = ne;
+    m->edges = (int32_t *)malloc(sizeof(int32_t) * 2 * ne);
+    for (int64_t i = 0; i < ne; ++i) { m->edges[2 * i] = (int32_t)(ek[i] / nv); m->edges[2 * i + 1] = (int32_t)(ek[i] % nv); }
+    m->tet_edge = (int32_t *)malloc(sizeof(int32_t) * 6 * nt);
+    for (int64_t t = 0; t < nt; ++t)
+        for (int e = 0; e < 6; ++e)
+            m->tet_edge[6 * t + e] = (int32_t)find_key(ek, ne, (int64_t)tv[4 * t + LE[e][0]] * nv + tv[4 * t + LE[e][1]]);
+    free(ek);
+    /* faces */
+    int64_t *fk = (int64_t *)malloc(sizeof(int64_t) * 4 * nt);
+    for (int64_t t = 0; t < nt; ++t)
+        for (int f = 0; f < 4; ++f)
+            fk[4 * t + f] = ((int64_t)tv[4 * t + LF[f][0]] * nv + tv[4 * t + LF[f][1]]) * nv + tv[4 * t + LF[f][2]];
+    qsort(fk, 4 * nt, sizeof(int64_t), cmp_i64);
+    int64_t nf = 0;
+    for (int64_t i = 0; i < 4 * nt; ++i)
+        if (i == 0 || fk[i] != fk[i - 1]) fk[nf++] = fk[i];
+    m->nf = nf;
+    m->faces = (int32_t *)malloc(sizeof(int32_t) * 3 * nf);
+    for (int64_t i = 0; i < nf; ++i) {
+        int64_t k = fk[i];
+        m->faces[3 * i + 2] = (int32_t)(k % nv); k /= nv;
+        m->faces[3 * i + 1] = (int32_t)(k % nv); k /= nv;
+        m->faces[3 * i + 0] = (int32_t)k;
+    }
+    m->tet_face = (int32_t *)malloc(sizeof(int32_t) * 4 * nt);
+    int64_t *owner0 = (int64_t *)malloc(sizeof(int64_t) * nf);
+    int64_t *owner1 = (int64_t *)malloc(sizeof(int64_t) * nf);
+    for (int64_t i = 0; i < nf; ++i) owner0[i] = owner1[i] = -1;
+    int bad = 0;
+    for (int64_t t = 0; t < nt; ++t)
+        for (int f = 0; f < 4; ++f) {
+            int64_t key = ((int64_t)tv[4 * t + LF[f][0]] * nv + tv[4 * t + LF[f][1]]) * nv + tv[4 * t + LF[f][2]];
+            int64_t id = find_key(fk, nf, key);
+            m->tet_face[4 * t + f] = (int32_t)id;
+            if (owner0[id] < 0) owner0[id] = t;
+            else if (owner1[id] < 0) owner1[id] = t;
+            else bad = 1;
+        }
+    m->nbr = (int32_t *)malloc(sizeof(int32_t) * 4 * nt);
+    for (int64_t t = 0; t < nt; ++t)
+        for (int f = 0; f < 4; ++f) {
+            int64_t id = m->tet_face[4 * t + f];
+            int64_t o = owner0[id] == t ? owner1[id] : owner0[id];
+            m->nbr[4 * t + f] = (int32_t)o;
+        }
+    free(owner0); free(owner1); free(fk);
+    if (bad) { ora_mesh_free(m); return -4; }
+    *out = m;
+    return 0;
+}
+
+void ora_mesh_counts(const ora_mesh *m, int64_t *out4) { out4[0] = m->nv; out4[1] = m->ne; out4[2] = m->nf; out4[3] = m->nt; }
+void ora_mesh_edges(const ora_mesh *m, int32_t *out) { memcpy(out, m->edges, sizeof(int32_t) * 2 * m->ne); }
+void ora_mesh_faces(const ora_mesh *m, int32_t *out) { memcpy(out, m->faces, sizeof(int32_t) * 3 * m->nf); }
+void ora_mesh_tet_edges(const ora_mesh *m, int32_t *out) { memcpy(out, m->tet_edge, sizeof(int32_t) * 6 * m->nt); }
+void ora_mesh_tet_faces(const ora_mesh *m, int32_t *out) { memcpy(out, m->tet_face, sizeof(int32_t) * 4 * m->nt); }
+void ora_mesh_neighbours(const ora_mesh *m, int32_t *out) { memcpy(out, m->nbr, sizeof(int32_t) * 4 * m->nt); }
+
+/* Barycentric gradients of tet T.  lambda_k is affine, 0 on the face opposite
+ * vertex k and 1 at vertex k, so its gradient is a face normal n scaled by
+ * 1/(n.(r_k - r_a)) for any point r_a of that face (W0 = barycentric, App. A). */
+void ora_grad(const ora_mesh *m, int64_t T, double g[4][3]) {
+    const int32_t *v = m->tv + 4 * T;
+    for (int k = 0; k < 4; ++k) {
+        const double *ra = m->xyz + 3 * v[LF[k][0]], *rb = m->xyz + 3 * v[LF[k][1]], *rc = m->xyz + 3 * v[LF[k][2]];
+        const double *rk = m->xyz + 3 * v[k];
+        double ab[3], ac[3], n[3], ak[3];
+        sub3(rb, ra, ab); sub3(rc, ra, ac); cross3(ab, ac, n); sub3(rk, ra, ak);
+        double s = 1.0 / dot3(n, ak);
+        g[k][0] = n[0] * s; g[k][1] = n[1] * s; g[k][2] = n[2] * s;
+    }
+}
+
+/* Cartesian -> barycentric by Cramer's rule (ratio of signed volumes). */
+void ora_bary(const ora_mesh *m, int64_t T, const double *x, double lam[4]) {
+    const int32_t *v = m->tv + 4 * T;
+    for (int k = 0; k < 4; ++k) {
+        const double *ra = m->xyz + 3 * v[LF[k][0]], *rb = m->xyz + 3 * v[LF[k][1]], *rc = m->xyz + 3 * v[LF[k][2]];
+        const double *rk = m->xyz + 3 * v[k];
+        double ab[3], ac[3], n[3], ak[3], ax[3];
+        sub3(rb, ra, ab); sub3(rc, ra, ac); cross3(ab, ac, n); sub3(rk, ra, ak); sub3(x, ra, ax);
+        lam[k] = dot3(n, ax) / dot3(n, ak);
+    }
+}
+
+/* barycentric -> Cartesian: x = sum_k lambda_k r_k */
+void ora_point(const ora_mesh *m, int64_t T, const double lam[4], double *x) {
+    const int32_t *v = m->tv + 4 * T;
+    x[0] = x[1] = x[2] = 0.0;
+    for (int k = 0; k < 4; ++k)
+        for (int c = 0; c < 3; ++c) x[c] += lam[k] * m->xyz[3 * v[k] + c];
+}
+
+/* Whitney edge functions of tet T at barycentric point lam (Formulation, the
+ * E~ expansion, lowest-order edge elements): W1_ij = l_i grad l_j - l_j grad l_i. */
+void ora_whitney1(const ora_mesh *m, int64_t T, const double lam[4], double W[6][3]) {
+    double g[4][3];
+    ora_grad(m, T, g);
+    for (int e = 0; e < 6; ++e) {
+        int i = LE[e][0], j = LE[e][1];
+        for (int c = 0; c < 3; ++c) W[e][c] = lam[i] * g[j][c] - lam[j] * g[i][c];
+    }
+}
+
+/* Whitney face functions (the B~ expansion): for face (i<j<k)
+ * W2 = 2 (l_i gl_j x gl_k + l_j gl_k x gl_i + l_k gl_i x gl_j). */
+void ora_whitney2(const ora_mesh *m, int64_t T, const double lam[4], double W[4][3]) {
+    double g[4][3];
+    ora_grad(m, T, g);
+    for (int f = 0; f < 4; ++f) {
+        int i = LF[f][0], j = LF[f][1], k = LF[f][2];
+        double jk[3], ki[3], ij[3];
+        cross3(g[j], g[k], jk); cross3(g[k], g[i], ki); cross3(g[i], g[j], ij);
+        for (int c = 0; c < 3; ++c) W[f][c] = 2.0 * (lam[i] * jk[c] + lam[j] * ki[c] + lam[k] * ij[c]);
+    }
+}
+
+typedef struct {
+    const double *e_env; /* ne*2 (re,im) */
+    const double *e_dc;  /* ne or NULL */
+    const double *b_env; /* nf*2 */
+    const double *b_dc;  /* nf or NULL */
+} ora_fields_t;
+
+/* Physical fields at (T, lam) and carrier phase (c, s) = (cos wt, sin wt):
+ * E = Re{ sum_e e~_e W1_e e^{jwt} } + sum_e e_dc,e W1_e, and likewise B with W2.
+ * Edge-by-edge sums, no pre-contraction. */
+static void fields_at(const ora_mesh *m, int64_t T, const double lam[4], double c, double s,
+                      const ora_fields_t *F, double E[3], double B[3]) {
+    double W1[6][3], W2[4][3];
+    ora_whitney1(m, T, lam, W1);
+    ora_whitney2(m, T, lam, W2);
+    E[0] = E[1] = E[2] = 0.0;
+    B[0] = B[1] = B[2] = 0.0;
+    for (int e = 0; e < 6; ++e) {
+        int64_t id = m->tet_edge[6 * T + e];
+        double re = F->e_env[2 * id], im = F->e_env[2 * id + 1];
+        double coef = re * c - im * s;           /* Re{(re + j im)(c + j s)} */
+        if (F->e_dc) coef += F->e_dc[id];
+        for (int k = 0; k < 3; ++k) E[k] += coef * W1[e][k];
+    }
+    for (int f = 0; f < 4; ++f) {
+        int64_t id = m->tet_face[4 * T + f];
+        double re = F->b_env[2 * id], im = F->b_env[2 * id + 1];
+        double coef = re * c - im * s;
+        if (F->b_dc) coef += F->b_dc[id];
+        for (int k = 0; k < 3; ++k) B[k] += coef * W2[f][k];
+    }
+}
+
+void ora_fields(const ora_mesh *m, int64_t T, const double lam[4], double omega, double t,
+                const double *e_env, const double *e_dc, const double *b_env, const double *b_dc,
+                double E[3], double B[3]) {
+    ora_fields_t F = {e_env, e_dc, b_env, b_dc};
+    fields_at(m, T, lam, cos(omega * t), sin(omega * t), &F, E, B);
+}
+
+/* Textbook Boris rotation (non-relativistic): half electric kick, magnetic
+ * rotation by the implicit-midpoint rule, half electric kick. */
+static void boris(double v[3], const double E[3], const double B[3], double qm, double dt) {
+    double h = 0.5 * qm * dt;
+    double vm[3], tau[3], sig[3], vp[3], cr[3];
+    for (int k = 0; k < 3; ++k) { vm[k] = v[k] + h * E[k]; tau[k] = h * B[k]; }
+    double t2 = dot3(tau, tau);
+    for (int k = 0; k < 3; ++k) sig[k] = 2.0 * tau[k] / (1.0 + t2);
+    cross3(vm, tau, cr);
+    double vpr[3] = {vm[0] + cr[0], vm[1] + cr[1], vm[2] + cr[2]};
+    cross3(vpr, sig, cr);
+    for (int k = 0; k < 3; ++k) vp[k] = vm[k] + cr[k];
+    for (int k = 0; k < 3; ++k) v[k] = vp[k] + h * E[k];
+}
+
+void ora_boris(double *v, const double *E, const double *B, double qm, double dt) { boris(v, E, B, qm, dt); }
+
+/* Path integral of the six Whitney edge functions of tet T along the straight
+ * piece that starts at barycentric point la and has Cartesian displacement d.
+ * The integrand W1(r).dr is affine along a straight piece, so the midpoint rule
+ * is exact: g_e = W1_e(midpoint) . d. */
+static void piece_integral(const ora_mesh *m, int64_t T, const double la[4], const double dl[4],
+                           const double d[3], double g[6]) {
+    double mid[4], W1[6][3];
+    for (int k = 0; k < 4; ++k) mid[k] = la[k] + 0.5 * dl[k];
+    ora_whitney1(m, T, mid, W1);
+    for (int e = 0; e < 6; ++e) g[e] = dot3(W1[e], d);
+}
+
+typedef struct {
+    int64_t tet;
+    double lam[4];
+    double v[3];
+    int hops;
+    int status; /* 0 ok, -6 hop cap */
+} ora_particle;
+
+/* One fine step of one particle: gather at (x^n, t_n), Boris, walk, deposit.
+ * qw_dG receives q*w*(path integrals) for every piece (6 edges per piece). */
+static void step_one(const ora_mesh *m, ora_particle *P, double c, double s, const ora_fields_t *F,
+                     double qm, double dt, double qw, double *dG, int64_t *piece_tets, int *npieces_out) {
+    double E[3], B[3];
+    fields_at(m, P->tet, P->lam, c, s, F, E, B);
+    boris(P->v, E, B, qm, dt);
+    double d[3] = {dt * P->v[0], dt * P->v[1], dt * P->v[2]};
+    int64_t T = P->tet;
+    double l[4] = {P->lam[0], P->lam[1], P->lam[2], P->lam[3]};
+    int hops = 0, np = 0;
+    P->status = 0;
+    for (;;) {
+        double g[4][3], dl[4];
+        ora_grad(m, T, g);
+        for (int k = 0; k < 4; ++k) dl[k] = dot3(g[k], d);
+        /* line-plane intersection with each face plane the segment leaves through */
+        double smin = 1.0;
+        int kmin = -1;
+        for (int k = 0; k < 4; ++k) {
+            if (dl[k] < 0.0 && l[k] + dl[k] < 0.0) {
+                double sk = l[k] > 0.0 ? l[k] / (-dl[k]) : 0.0;
+                if (kmin < 0 || sk < smin) { smin = sk; kmin = k; }   /* ties: lowest k */
+            }
+        }
+        double gp[6];
+        if (kmin < 0) {
+            piece_integral(m, T, l, dl, d, gp);
+            for (int e = 0; e < 6; ++e) dG[m->tet_edge[6 * T + e]] += qw * gp[e];
+            if (piece_tets) piece_tets[np] = T;
+            ++np;
+            for (int k = 0; k < 4; ++k) l[k] += dl[k];
+            break;
+        }
+        double dp[3] = {smin * d[0], smin * d[1], smin * d[2]};
+        double dlp[4] = {smin * dl[0], smin * dl[1], smin * dl[2], smin * dl[3]};
+        piece_integral(m, T, l, dlp, dp, gp);
+        for (int e = 0; e < 6; ++e) dG[m->tet_edge[6 * T + e]] += qw * gp[e];
+        if (piece_tets && np < ORA_HOP_CAP + 1) piece_tets[np] = T;
+        ++np;
+        /* crossing point: the exit coordinate is exactly 0; the other three are
+         * rescaled to sum to one and handed unchanged to the shared vertices */
+        double lc[4], sum = 0.0;
+        for (int k = 0; k < 4; ++k) lc[k] = (k == kmin) ? 0.0 : l[k] + dlp[k];
+        for (int k = 0; k < 4; ++k) if (k != kmin) { if (lc[k] < 0.0) lc[k] = 0.0; sum += lc[k]; }
+        for (int k = 0; k < 4; ++k) if (k != kmin) lc[k] /= sum;
+        for (int k = 0; k < 3; ++k) d[k] -= dp[k];
+        int64_t nb = m->nbr[4 * T + kmin];
+        if (nb < 0) {
+            /* specular reflection at the domain boundary (the paper is silent on
+             * the particle boundary condition; walls are conductors) */
+            double nn = sqrt(dot3(g[kmin], g[kmin]));
+            double nh[3] = {g[kmin][0] / nn, g[kmin][1] / nn, g[kmin][2] / nn};
+            double dd = dot3(d, nh), vv = dot3(P->v, nh);
+            for (int k = 0; k < 3; ++k) { d[k] -= 2.0 * dd * nh[k]; P->v[k] -= 2.0 * vv * nh[k]; }
+            for (int k = 0; k < 4; ++k) l[k] = lc[k];
+        } else {
+            const int32_t *vt = m->tv + 4 * T, *vn = m->tv + 4 * nb;
+            for (int j = 0; j < 4; ++j) {
+                l[j] = 0.0;
+                for (int i = 0; i < 4; ++i) if (vt[i] == vn[j]) l[j] = lc[i];
+            }
+            T = nb;
+        }
+        if (++hops > ORA_HOP_CAP) { P->status = -6; break; }
+    }
+    P->tet = T;
+    for (int k = 0; k < 4; ++k) P->lam[k] = l[k];
+    P->hops = hops;
+    if (npieces_out) *npieces_out = np;
+}
+
+/*
+ * One step for n particles.  State in and out: tet[n], lam[n*3] (lambda1..3 of
+ * the ascending local order, lambda0 = 1 - sum), vel[n*3] (v^{n-1/2} in,
+ * v^{n+1/2} out).  t_n = step*dt; the carrier phase is evaluated here.
+ * dG[ne] accumulates q*w*path integrals; rho[nv] (optional) accumulates
+ * q*w*lambda_k at the end point.  hops[n] optional.  nthreads <= 1: serial.
+ * Returns 0, or -6 if any particle exceeded the hop cap.
+ */
+int ora_step(const ora_mesh *m, int64_t n, int32_t *tet, double *lam, double *vel,
+             double q, double mass, double w, int64_t step, double dt, double omega,
+             const double *e_env, const double *e_dc, const double *b_env, const double *b_dc,
+             double *dG, double *rho, int32_t *hops, int nthreads) {
+    ora_fields_t F = {e_env, e_dc, b_env, b_dc};
+    double t = (double)step * dt;
+    double c = cos(omega * t), s = sin(omega * t);
+    double qm = q / mass, qw = q * w;
+    int status = 0;
+    int nth = nthreads > 1 ? nthreads : 1;
+#ifndef _OPENMP
+    nth = 1;
+#endif
+    if (nth == 1) {
+        for (int64_t p = 0; p < n; ++p) {
+            ora_particle P;
+            P.tet = tet[p];
+            P.lam[1] = lam[3 * p]; P.lam[2] = lam[3 * p + 1]; P.lam[3] = lam[3 * p + 2];
+            P.lam[0] = 1.0 - P.lam[1] - P.lam[2] - P.lam[3];
+            P.v[0] = vel[3 * p]; P.v[1] = vel[3 * p + 1]; P.v[2] = vel[3 * p + 2];
+            step_one(m, &P, c, s, &F, qm, dt, qw, dG, NULL, NULL);
+            tet[p] = (int32_t)P.tet;
+            lam[3 * p] = P.lam[1]; lam[3 * p + 1] = P.lam[2]; lam[3 * p + 2] = P.lam[3];
+            vel[3 * p] = P.v[0]; vel[3 * p + 1] = P.v[1]; vel[3 * p + 2] = P.v[2];
+            if (hops) hops[p] = P.hops;
+            if (P.status) status = P.status;
+            if (rho) {
+                const int32_t *v = m->tv + 4 * P.tet;
+                for (int k = 0; k < 4; ++k) rho[v[k]] += qw * P.lam[k];
+            }
+        }
+        return status;
+    }
+#ifdef _OPENMP
+    double *priv = (double *)calloc((size_t)nth * (m->ne + (rho ? m->nv : 0)), sizeof(double));
+    #pragma omp parallel num_threads(nth) reduction(min:status)
+    {
+        int tid = omp_get_thread_num();
+        double *mydG = priv + (size_t)tid * (m->ne + (rho ? m->nv : 0));
+        double *myrho = rho ? mydG + m->ne : NULL;
+        #pragma omp for schedule(static)
+        for (int64_t p = 0; p < n; ++p) {
+            ora_particle P;
+            P.tet = tet[p];
+            P.lam[1] = lam[3 * p]; P.lam[2] = lam[3 * p + 1]; P.lam[3] = lam[3 * p + 2];
+            P.lam[0] = 1.0 - P.lam[1] - P.lam[2] - P.lam[3];
+            P.v[0] = vel[3 * p]; P.v[1] = vel[3 * p + 1]; P.v[2] = vel[3 * p + 2];
+            step_one(m, &P, c, s, &F, qm, dt, qw, mydG, NULL, NULL);
+            tet[p] = (int32_t)P.tet;
+            lam[3 * p] = P.lam[1]; lam[3 * p + 1] = P.lam[2]; lam[3 * p + 2] = P.lam[3];
+            vel[3 * p] = P.v[0]; vel[3 * p + 1] = P.v[1]; vel[3 * p + 2] = P.v[2];
+            if (hops) hops[p] = P.hops;
+            if (P.status) status = P.status;
+            if (myrho) {
+                const int32_t *v = m->tv + 4 * P.tet;
+                for (int k = 0; k < 4; ++k) myrho[v[k]] += qw * P.lam[k];
+            }
+        }
+    }
+    for (int th = 0; th < nth; ++th) {
+        double *mydG = priv + (size_t)th * (m->ne + (rho ? m->nv : 0));
+        for (int64_t e = 0; e < m->ne; ++e) dG[e] += mydG[e];
+        if (rho) for (int64_t k = 0; k < m->nv; ++k) rho[k] += mydG[m->ne + k];
+    }
+    free(priv);
+#endif
+    return status;
+}
+
+/* Vertex charge of the particles (rho = q sum_p S(r - r_p) with the W0 shape):
+ * rho_k += q*w*lambda_k(x_p) for the four vertices of the particle's tet. */
+void ora_charge(const ora_mesh *m, int64_t n, const int32_t *tet, const double *lam, double q, double w, double *rho) {
+    for (int64_t p = 0; p < n; ++p) {
+        const int32_t *v = m->tv + 4 * (int64_t)tet[p];
+        double l1 = lam[3 * p], l2 = lam[3 * p + 1], l3 = lam[3 * p + 2];
+        double l[4] = {1.0 - l1 - l2 - l3, l1, l2, l3};
+        for (int k = 0; k < 4; ++k) rho[v[k]] += q * w * l[k];
+    }
+}
+
+/* Discrete continuity residual (section on charge conservation: the discrete
+ * divergence of G is tied to rho).  D is the edge-vertex incidence with -1 at
+ * the tail and +1 at the head; r = D^T dG - (rho_new - rho_old).
+ * out[0] = max|r|, out[1] = max|rho_old|. */
+void ora_gauss(const ora_mesh *m, const double *dG, const double *rho_new, const double *rho_old, double *out) {
+    double *r = (double *)calloc(m->nv, sizeof(double));
+    for (int64_t e = 0; e < m->ne; ++e) {
+        r[m->edges[2 * e + 1]] += dG[e];
+        r[m->edges[2 * e]] -= dG[e];
+    }
+    double rmax = 0.0, pmax = 0.0;
+    for (int64_t k = 0; k < m->nv; ++k) {
+        double v = fabs(r[k] - (rho_new[k] - rho_old[k]));
+        if (v > rmax) rmax = v;
+        if (fabs(rho_old[k]) > pmax) pmax = fabs(rho_old[k]);
+    }
+    out[0] = rmax; out[1] = pmax;
+    free(r);
+}
+
+/* Brute-force point location over all tets: the tet whose barycentrics of x
+ * have the largest minimum (>= -tol means inside).  Returns the tet, writes
+ * the min barycentric to *minlam. */
+int64_t ora_locate(const ora_mesh *m, const double *x, double *minlam) {
+    int64_t best = -1;
+    double bmin = -1e300;
+    for (int64_t t = 0; t < m->nt; ++t) {
+        double l[4];
+        ora_bary(m, t, x, l);
+        double mn = l[0];
+        for (int k = 1; k < 4; ++k) if (l[k] < mn) mn = l[k];
+        if (mn > bmin) { bmin = mn; best = t; }
+    }
+    if (minlam) *minlam = bmin;
+    return best;
+}
+
+/* Single particle, single step, with per-piece tets reported (walk tests). */
+int ora_step_one(const ora_mesh *m, int32_t *tet, double *lam3, double *v, double q, double mass, double w,
+                 int64_t step, double dt, double omega, const double *e_env, const double *e_dc,
+                 const double *b_env, const double *b_dc, double *dG, int64_t *piece_tets, int32_t *npieces) {
+    ora_fields_t F = {e_env, e_dc, b_env, b_dc};
+    double t = (double)step * dt;
+    ora_particle P;
+    P.tet = *tet;
+    P.lam[1] = lam3[0]; P.lam[2] = lam3[1]; P.lam[3] = lam3[2];
+    P.lam[0] = 1.0 - lam3[0] - lam3[1] - lam3[2];
+    P.v[0] = v[0]; P.v[1] = v[1]; P.v[2] = v[2];
+    int np = 0;
+    step_one(m, &P, cos(omega * t), sin(omega * t), &F, q / mass, dt, q * w, dG, piece_tets, &np);
+    *tet = (int32_t)P.tet;
+    lam3[0] = P.lam[1]; lam3[1] = P.lam[2]; lam3[2] = P.lam[3];
+    v[0] = P.v[0]; v[1] = P.v[1]; v[2] = P.v[2];
+    *npieces = np;
+    return P.status;
+}

@@ -1,0 +1,217 @@
+#!/usr/bin/env python3
+"""Throughput of the envelope-tracking particle-mesh step on one MI355X.
+
+A step is one pass of the particle path over all particles: the per-tet
+carrier-rotated field coefficients, the fused gather / Boris push / tet walk /
+path-integral deposit kernel, and the counting sort by tet every
+`--sort-every` steps (amortised, inside the timed region).  The workload is the
+40^3 x 6 jittered Kuhn mesh (384,000 tets) with 10,000,000 electrons
+(Maxwellian, 1e6 m/s), an 8-mode envelope on a 10 GHz carrier, B = 0.5 T, dt =
+1e-12 s.  Inputs are resident in HBM before the timed region starts.
+
+Prints ONE JSON line.  `value` is the float64 form; the mixed form (float32
+gather/push on barycentrics, float64 positions and deposit) is reported under
+"mixed".  The roofline figure is for the dominant kernel (the particle
+kernel), timed with HIP events recorded on its launch stream.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes (what the method must move per unit):
+#  per particle-step: state read + write = 2 x (lam 3x8 + v 3x8 + tet 4) (float64 form)
+#                                         2 x (lam 3x8 + v 3x4 + tet 4) (mixed form)
+#  per tet and step : per-tet field and geometry data read once (~320 B)
+#  per edge and step: the current accumulator read + written once (16 B)
+BYTES_PER_PARTICLE = {"fp64": 104, "mixed": 80}
+BYTES_PER_TET = 320
+BYTES_PER_EDGE = 16
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_form(E, torch, ctx, w, precision, steps, warmup, sort_every, fields):
+    sp = E.Species(w.q, w.m, w.w)
+    parts = E.Particles.from_numpy(w.tet, w.lam, w.vel, w.ids, precision=precision)
+    spare = parts.empty_like()
+    dG = torch.zeros(ctx.n_edge, dtype=torch.float64, device="cuda")
+    # initial sort, then warmup
+    ctx.sort(parts, spare)
+    parts, spare = spare, parts
+    step = 0
+    for _ in range(warmup):
+        ctx.gather_push_deposit(parts, sp, fields, step, w.dt, w.omega, dG)
+        step += 1
+    torch.cuda.synchronize()
+    ctx.kernel_time(reset=True)
+    # --- timed region: exactly `steps` steps
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    for k in range(steps):
+        if sort_every and k % sort_every == 0:
+            ctx.sort(parts, spare)
+            parts, spare = spare, parts
+        ctx.gather_push_deposit(parts, sp, fields, step, w.dt, w.omega, dG, flags=E.STEP_XCD_REMAP | E.STEP_TIMING)
+        step += 1
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_ms = ev0.elapsed_time(ev1)
+    kern_ms, launches = ctx.kernel_time(reset=True)
+    ctx.check()
+    # sort alone
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    nsort = 5
+    for _ in range(nsort):
+        ctx.sort(parts, spare)
+        parts, spare = spare, parts
+    e1.record()
+    torch.cuda.synchronize()
+    sort_ms = e0.elapsed_time(e1) / nsort
+    # continuity residual (timed separately): rho before / after one more step
+    rho0 = torch.zeros(ctx.n_vert, dtype=torch.float64, device="cuda")
+    rho1 = torch.zeros_like(rho0)
+    dGs = torch.zeros_like(dG)
+    ctx.vertex_charge(parts, sp, rho0)
+    ctx.gather_push_deposit(parts, sp, fields, step, w.dt, w.omega, dGs)
+    torch.cuda.synchronize()
+    g0 = torch.cuda.Event(enable_timing=True)
+    g1 = torch.cuda.Event(enable_timing=True)
+    g0.record()
+    ctx.vertex_charge(parts, sp, rho1)
+    r, p = ctx.gauss_residual(dGs, rho1, rho0)
+    g1.record()
+    torch.cuda.synchronize()
+    gauss_ms = g0.elapsed_time(g1)
+    n = parts.n
+    return {
+        "ms_per_step": total_ms / steps,
+        "wall_s": wall,
+        "kernel_ms": kern_ms / max(launches, 1),
+        "launches": launches,
+        "sort_ms": sort_ms,
+        "gauss_rel": r / p,
+        "gauss_ms": gauss_ms,
+        "value": n * steps / (total_ms * 1e-3),
+    }
+
+
+def cpu_baseline(w, nthreads, steps):
+    import oracle
+    M = oracle.OracleMesh(w.xyz, w.tet_vert)
+    tet, lam, vel = w.tet.copy(), w.lam.copy(), w.vel.copy()
+    dG = np.zeros(M.ne)
+    t0 = time.perf_counter()
+    cpu0 = time.process_time()
+    for s in range(steps):
+        rc, _ = M.step(tet, lam, vel, q=w.q, m=w.m, w=w.w, step=s, dt=w.dt, omega=w.omega, e_env=w.e_env,
+                       b_env=w.b_env, b_dc=w.b_dc, dG=dG, nthreads=nthreads)
+    wall = time.perf_counter() - t0
+    cpu = time.process_time() - cpu0
+    return tet.shape[0] * steps / wall, wall, cpu
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--particles", type=int, default=None, help="override the particle count (default 1e7)")
+    ap.add_argument("--sort-every", type=int, default=10)
+    ap.add_argument("--forms", default="fp64,mixed")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-threads", type=int, default=0, help="0 = min(16, host cores)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the multi-GPU path is a design, not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2208_12795_amd import etpic as E
+    from paper_2208_12795_amd import synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    t0 = time.perf_counter()
+    w = synth.make_workload(2, n_particles=args.particles)
+    log(f"[bench] workload generated in {time.perf_counter() - t0:.1f}s: N_p={w.tet.shape[0]} N_t={w.tet_vert.shape[0]}")
+    ctx = E.Context(0)
+    ctx.upload_mesh(w.xyz, w.tet_vert)
+    fields = E.Fields.from_numpy(w.e_env, w.b_env, None, w.b_dc)
+    res = {}
+    for form in args.forms.split(","):
+        prec = E.FP64 if form == "fp64" else E.MIXED
+        res[form] = run_form(E, torch, ctx, w, prec, args.steps, args.warmup, args.sort_every, fields)
+        log(f"[bench] {form}: {json.dumps(res[form])}")
+    n_p, n_t, n_e = w.tet.shape[0], w.tet_vert.shape[0], ctx.n_edge
+
+    def roofline(form):
+        r = res[form]
+        bytes_launch = BYTES_PER_PARTICLE[form] * n_p + BYTES_PER_TET * n_t + BYTES_PER_EDGE * n_e
+        ach = bytes_launch / (r["kernel_ms"] * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": bytes_launch, "kernel_ms": round(r["kernel_ms"], 5)}
+
+    main_form = "fp64" if "fp64" in res else next(iter(res))
+    r = res[main_form]
+    line = {
+        "metric": "particle-steps/s (gather+push+deposit), FP64 vs FP32-mixed, % of HBM peak",
+        "value": r["value"],
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if main_form == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "40^3x6 jittered Kuhn tet mesh (384,000 tets), 1e7 electrons, 8-mode envelope "
+                               "10 GHz, B 0.5 T, dt 1e-12 s, sort every %d steps" % args.sort_every,
+                   "n_particles": n_p, "n_tets": n_t, "n_edges": n_e, "parallelism": "single GPU"},
+        "roofline": roofline(main_form),
+        "sort_ms": r["sort_ms"],
+        "gauss_rel": r["gauss_rel"],
+        "gauss_ms": r["gauss_ms"],
+    }
+    if "mixed" in res and main_form != "mixed":
+        m = res["mixed"]
+        line["mixed"] = {"value": m["value"], "ms_per_step": m["ms_per_step"], "dtype": "f32 gather/push, f64 deposit",
+                         "speedup_vs_fp64": m["value"] / r["value"], "roofline": roofline("mixed"),
+                         "gauss_rel": m["gauss_rel"]}
+    if not args.no_cpu_baseline:
+        nth = args.cpu_threads or max(1, min(16, os.cpu_count() or 1))
+        val, wall, cpu = cpu_baseline(w, nth, args.cpu_steps)
+        line["cpu_baseline"] = {"value": val, "unit": "particle-steps/s", "cores": nth, "kind": "oracle",
+                                "sample": f"all {n_p} particles, first {args.cpu_steps} steps (float64 oracle, "
+                                          f"OpenMP over particles); wall {wall:.1f}s, cpu {cpu:.1f}s"}
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

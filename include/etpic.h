@@ -1,0 +1,195 @@
+/*
+ * etpic -- C ABI of the envelope-tracking particle-mesh step on AMD MI355X.
+ *
+ * The step is the data-parallel particle part of the envelope-tracking
+ * EM-FEMPIC method (Ramachandran, Crawford, O'Connor, Luginsland, Shanker):
+ *   gather  : fields at each particle from the Whitney edge (E) and face (B)
+ *             expansions (Formulation, "Discretization in Space and Time"),
+ *             whose complex envelope DoFs are modulated by the carrier
+ *             e^{j w t} and taken as the real part (Particle Push section,
+ *             the Lorentz update with the fast carrier treated analytically);
+ *   push    : a Lorentz update at the fine step (the "simpler" scheme of the
+ *             Particle Push section), here the Boris rotation, with a
+ *             tet-to-tet walk of the straight path;
+ *   deposit : the edge DoFs of G, the time integral of the current, which is
+ *             q times the path integral of the trajectory (eq. g_def; edge
+ *             DoFs g_l = <W1_l, G>; the trajectory summed over fine steps,
+ *             eq. G_integral and the sum that follows it).
+ *
+ * Conventions (all arrays are plain pointers):
+ *  - tet rows list vertex ids in ascending order; barycentrics lam1..lam3 refer
+ *    to local vertices 1..3 of that order and lam0 = 1 - lam1 - lam2 - lam3;
+ *  - local edges (0,1),(0,2),(0,3),(1,2),(1,3),(2,3); local face k is opposite
+ *    local vertex k;
+ *  - edges are (a<b) pairs numbered lexicographically and oriented a->b; faces
+ *    are (a<b<c) triples numbered lexicographically, oriented by
+ *    (r_b - r_a) x (r_c - r_a);
+ *  - complex DoFs are interleaved (re, im) float64 pairs (complex128 layout);
+ *  - the physical fields are Re{env * e^{j w t}} + dc with t = step*dt.
+ *
+ * Ownership: the library owns the mesh tables and a small scratch area, both
+ * allocated once in etpic_mesh_upload and freed by etpic_destroy.  Particle
+ * arrays, field DoFs and outputs are device buffers owned by the caller; they
+ * must stay valid until the work queued on `stream` has finished.  No entry
+ * point other than etpic_mesh_upload allocates device memory.
+ *
+ * Errors: every entry point returns an etpic status (0 = OK).  On failure the
+ * message is available from etpic_last_error() (thread-local).  Errors found
+ * inside kernels (walk hop cap, NaN) set bits in a device status word that
+ * etpic_check() reads.  No C++ exception crosses this boundary.  A context is
+ * not thread-safe: use one context per host thread.
+ * `stream` is a hipStream_t passed as void* (NULL = default stream).
+ */
+#ifndef ETPIC_H
+#define ETPIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum etpic_status {
+    ETPIC_OK = 0,
+    ETPIC_EINVAL = -1,    /* bad argument (null pointer, size, precision) */
+    ETPIC_ESTATE = -2,    /* no mesh uploaded yet */
+    ETPIC_EHIP = -3,      /* HIP runtime error; message carries hipGetErrorString */
+    ETPIC_EMESH = -4,     /* unsorted row, degenerate tet or non-manifold face */
+    ETPIC_EPARTICLE = -5, /* particle tet index out of range */
+    ETPIC_EWALK = -6,     /* a particle exceeded the walk hop cap */
+    ETPIC_ENAN = -7,      /* non-finite value met in a kernel */
+    ETPIC_ENOCONV = -8    /* iterative solve did not converge */
+};
+
+enum etpic_precision {
+    ETPIC_FP64 = 0,  /* gather, push and deposit in float64; velocities float64 */
+    ETPIC_MIXED = 1  /* gather and push in float32 on tet-local barycentrics,
+                        velocities float32; positions, deposit and charge float64 */
+};
+
+/* bits of the device status word read by etpic_check */
+enum etpic_device_flags {
+    ETPIC_DEV_HOPCAP = 1u, /* walk hop cap reached (particle left where it stopped) */
+    ETPIC_DEV_NAN = 2u,    /* non-finite field or velocity */
+    ETPIC_DEV_BADTET = 4u  /* tet index outside [0, N_t) */
+};
+
+/* flags of etpic_gather_push_deposit */
+enum etpic_step_flags {
+    ETPIC_STEP_XCD_REMAP = 1u, /* map consecutive particle blocks to one XCD (default on) */
+    ETPIC_STEP_TIMING = 2u     /* bracket the particle kernel with HIP events (etpic_kernel_time) */
+};
+
+#define ETPIC_HOP_CAP 64
+
+typedef struct etpic_ctx etpic_ctx;
+
+/* Particle state, structure of arrays on the device, length n each.
+ * lam[k]: float64 barycentric lam_{k+1} in the particle's tet.
+ * vel[k]: velocity component k at the half step (v^{n-1/2} in, v^{n+1/2} out);
+ *         float64 for ETPIC_FP64, float32 for ETPIC_MIXED.
+ * tet:    int32 tet index.  id: int64 particle id, carried by etpic_sort (may be NULL). */
+typedef struct {
+    int64_t n;
+    double *lam[3];
+    void *vel[3];
+    int32_t *tet;
+    int64_t *id;
+} etpic_particles;
+
+/* Field DoFs on the device.  e_env: 2*N_e float64 (complex edge envelope);
+ * e_dc: N_e float64 or NULL (real unmodulated edge DoFs); b_env: 2*N_f float64
+ * (complex face envelope); b_dc: N_f float64 or NULL (real unmodulated face DoFs). */
+typedef struct {
+    const double *e_env;
+    const double *e_dc;
+    const double *b_env;
+    const double *b_dc;
+} etpic_fields;
+
+/* Species: charge q [C], mass m [kg], macroparticle weight w. */
+typedef struct {
+    double q, m, w;
+} etpic_species;
+
+/* Thread-local message of the last failing call ("" if none). */
+const char *etpic_last_error(void);
+
+/* Create a context bound to HIP device `device`.  *out receives the handle. */
+int etpic_create(etpic_ctx **out, int device);
+
+/* Destroy a context and free the device memory it owns.  NULL is accepted. */
+int etpic_destroy(etpic_ctx *ctx);
+
+/* Upload a tet mesh (Appendix A: the sets N, E, F, T).  Host arrays:
+ * xyz_host[3*n_vert] (x,y,z per vertex), tet_vert_host[4*n_tet] ascending per row.
+ * Builds the canonical edges/faces, tet->edge/face/neighbour tables and the
+ * barycentric gradients on the host, then allocates and fills the device tables
+ * (synchronously).  Replaces any previous mesh.  Errors: EINVAL, EMESH, EHIP. */
+int etpic_mesh_upload(etpic_ctx *ctx, int64_t n_vert, const double *xyz_host, int64_t n_tet,
+                      const int32_t *tet_vert_host);
+
+/* Host only (no context, no GPU): the canonical numbering of a mesh, as
+ * etpic_mesh_upload would build it.  counts_out[4] = {N_n, N_e, N_f, N_t};
+ * edge_vert_host (2*N_e int32) and face_vert_host (3*N_f int32) are filled when
+ * non-NULL (call once with NULLs to size them).  Errors: EINVAL, EMESH. */
+int etpic_mesh_canonical(int64_t n_vert, const double *xyz_host, int64_t n_tet, const int32_t *tet_vert_host,
+                         int64_t counts_out[4], int32_t *edge_vert_host, int32_t *face_vert_host);
+
+/* counts_out[4] = {N_n, N_e, N_f, N_t} of the uploaded mesh.  ESTATE if none. */
+int etpic_mesh_counts(const etpic_ctx *ctx, int64_t counts_out[4]);
+
+/* Canonical edge list, host buffer of 2*N_e int32 (a<b per edge). */
+int etpic_mesh_edges(const etpic_ctx *ctx, int32_t *edge_vert_host);
+
+/* Canonical face list, host buffer of 3*N_f int32 (a<b<c per face). */
+int etpic_mesh_faces(const etpic_ctx *ctx, int32_t *face_vert_host);
+
+/* One fine step of every particle, asynchronous on `stream`:
+ * gather E, B at (x^n, t_n = step*dt) with the carrier (cos w t_n, sin w t_n)
+ * evaluated on the host in float64; Boris update v^{n-1/2} -> v^{n+1/2};
+ * walk the straight path x^n -> x^n + dt v^{n+1/2} through the mesh
+ * (specular reflection at the domain boundary, hop cap ETPIC_HOP_CAP);
+ * dG[N_e] += q w * (path integral of each Whitney edge function);
+ * rho[N_n] += q w * lam_k(x^{n+1}) if rho != NULL.
+ * dG and rho accumulate (the caller zeroes them).  The particle state is
+ * updated in place.  Errors: EINVAL, ESTATE, EHIP; in-kernel errors via
+ * etpic_check. */
+int etpic_gather_push_deposit(etpic_ctx *ctx, const etpic_particles *p, int precision, const etpic_species *sp,
+                              const etpic_fields *f, int64_t step, double dt, double omega, double *dG,
+                              double *rho, uint32_t flags, void *stream);
+
+/* Counting sort of the particles by tet (histogram, exclusive scan, scatter):
+ * src -> dst (distinct buffers, same n and precision); the order among
+ * particles of one tet is unspecified.  Asynchronous on `stream`. */
+int etpic_sort(etpic_ctx *ctx, const etpic_particles *src, const etpic_particles *dst, int precision,
+               void *stream);
+
+/* rho[N_n] += q w * lam_k for the four vertices of every particle's tet
+ * (the W0 shape; Formulation, the particle charge density). Asynchronous. */
+int etpic_vertex_charge(etpic_ctx *ctx, const etpic_particles *p, const etpic_species *sp, double *rho,
+                        void *stream);
+
+/* Discrete continuity residual r = D^T dG - (rho_new - rho_old), D the edge-vertex
+ * incidence (-1 tail, +1 head) (section on discretization and exact charge
+ * conservation).  Synchronises `stream`; out_host[0] = max|r|,
+ * out_host[1] = max|rho_old|. */
+int etpic_gauss_residual(etpic_ctx *ctx, const double *dG, const double *rho_new, const double *rho_old,
+                         double out_host[2], void *stream);
+
+/* Time spent in the particle kernel of the steps launched with ETPIC_STEP_TIMING
+ * since the last reset, measured with HIP events recorded on the launch stream
+ * around that kernel alone.  Synchronises on the last recorded event.
+ * total_ms_out: sum of the kernel durations; launches_out: how many; reset != 0
+ * clears the record afterwards. */
+int etpic_kernel_time(etpic_ctx *ctx, double *total_ms_out, int64_t *launches_out, int reset);
+
+/* Synchronise `stream`, return and clear the device status word in *device_flags.
+ * Returns EWALK / ENAN / EPARTICLE for the first set bit, OK otherwise. */
+int etpic_check(etpic_ctx *ctx, void *stream, uint32_t *device_flags);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ETPIC_H */

@@ -1,0 +1,136 @@
+// Host-side canonicalisation of a tet mesh for the etpic library: the sets of
+// edges and faces with their global numbering, the tet -> edge / face /
+// neighbour incidences, the barycentric gradients of every tet, and the
+// vertex -> edge incidence used by the continuity residual.
+#include "mesh_host.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+
+namespace etpic {
+
+namespace {
+
+inline int64_t edge_key(int64_t nv, int64_t a, int64_t b) { return a * nv + b; }
+inline int64_t face_key(int64_t nv, int64_t a, int64_t b, int64_t c) { return (a * nv + b) * nv + c; }
+
+int64_t index_of(const std::vector<int64_t> &sorted, int64_t key) {
+    auto it = std::lower_bound(sorted.begin(), sorted.end(), key);
+    if (it == sorted.end() || *it != key) return -1;
+    return it - sorted.begin();
+}
+
+}  // namespace
+
+int build_host_mesh(int64_t nv, const double *xyz, int64_t nt, const int32_t *tv, HostMesh &M, std::string &err) {
+    if (nv <= 0 || nt <= 0 || !xyz || !tv) { err = "empty mesh or null pointer"; return -1; }
+    if (nv > (int64_t)2000000 || nt > (int64_t)INT32_MAX / 8) { err = "mesh too large for 32-bit tables"; return -1; }
+    M = HostMesh();
+    M.nv = nv;
+    M.nt = nt;
+    M.grad.resize((size_t)nt * 12);
+    // validation + barycentric gradients: with columns c_k = r_k - r_0 (k = 1..3)
+    // and J = [c1 c2 c3], (lam1, lam2, lam3) = J^{-1} (x - r0), so the gradients
+    // are the rows of J^{-1} = [c2 x c3; c3 x c1; c1 x c2] / det J.
+    for (int64_t t = 0; t < nt; ++t) {
+        const int32_t *v = tv + 4 * t;
+        for (int k = 0; k < 4; ++k) {
+            if (v[k] < 0 || v[k] >= nv) { err = "tet " + std::to_string(t) + ": vertex id out of range"; return -1; }
+            if (k > 0 && v[k] <= v[k - 1]) { err = "tet " + std::to_string(t) + ": vertex ids not ascending"; return -4; }
+        }
+        double c[3][3];
+        for (int k = 0; k < 3; ++k)
+            for (int d = 0; d < 3; ++d) c[k][d] = xyz[3 * v[k + 1] + d] - xyz[3 * v[0] + d];
+        auto cross = [](const double *a, const double *b, double *o) {
+            o[0] = a[1] * b[2] - a[2] * b[1];
+            o[1] = a[2] * b[0] - a[0] * b[2];
+            o[2] = a[0] * b[1] - a[1] * b[0];
+        };
+        double r1[3], r2[3], r3[3];
+        cross(c[1], c[2], r1);
+        cross(c[2], c[0], r2);
+        cross(c[0], c[1], r3);
+        double det = c[0][0] * r1[0] + c[0][1] * r1[1] + c[0][2] * r1[2];
+        double l0 = std::sqrt(c[0][0] * c[0][0] + c[0][1] * c[0][1] + c[0][2] * c[0][2]);
+        double l1 = std::sqrt(c[1][0] * c[1][0] + c[1][1] * c[1][1] + c[1][2] * c[1][2]);
+        double l2 = std::sqrt(c[2][0] * c[2][0] + c[2][1] * c[2][1] + c[2][2] * c[2][2]);
+        if (!(std::fabs(det) > 1e-12 * l0 * l1 * l2)) { err = "tet " + std::to_string(t) + ": degenerate"; return -4; }
+        double *g = &M.grad[(size_t)t * 12];
+        for (int d = 0; d < 3; ++d) {
+            g[3 + d] = r1[d] / det;
+            g[6 + d] = r2[d] / det;
+            g[9 + d] = r3[d] / det;
+            g[d] = -(g[3 + d] + g[6 + d] + g[9 + d]);
+        }
+    }
+    // edges
+    std::vector<int64_t> ek((size_t)nt * 6);
+    for (int64_t t = 0; t < nt; ++t)
+        for (int e = 0; e < 6; ++e) ek[6 * t + e] = edge_key(nv, tv[4 * t + kLocalEdge[e][0]], tv[4 * t + kLocalEdge[e][1]]);
+    std::sort(ek.begin(), ek.end());
+    ek.erase(std::unique(ek.begin(), ek.end()), ek.end());
+    M.ne = (int64_t)ek.size();
+    M.edges.resize((size_t)M.ne * 2);
+    for (int64_t i = 0; i < M.ne; ++i) {
+        M.edges[2 * i] = (int32_t)(ek[i] / nv);
+        M.edges[2 * i + 1] = (int32_t)(ek[i] % nv);
+    }
+    // faces
+    std::vector<int64_t> fk((size_t)nt * 4);
+    for (int64_t t = 0; t < nt; ++t)
+        for (int f = 0; f < 4; ++f)
+            fk[4 * t + f] = face_key(nv, tv[4 * t + kLocalFace[f][0]], tv[4 * t + kLocalFace[f][1]], tv[4 * t + kLocalFace[f][2]]);
+    std::vector<int64_t> fs(fk);
+    std::sort(fs.begin(), fs.end());
+    fs.erase(std::unique(fs.begin(), fs.end()), fs.end());
+    M.nf = (int64_t)fs.size();
+    M.faces.resize((size_t)M.nf * 3);
+    for (int64_t i = 0; i < M.nf; ++i) {
+        int64_t k = fs[i];
+        M.faces[3 * i + 2] = (int32_t)(k % nv);
+        k /= nv;
+        M.faces[3 * i + 1] = (int32_t)(k % nv);
+        M.faces[3 * i] = (int32_t)(k / nv);
+    }
+    // tet records and neighbours (each face has one or two owning tets)
+    M.topo.assign((size_t)nt, TetTopo{});
+    std::vector<int64_t> own0((size_t)M.nf, -1), own1((size_t)M.nf, -1);
+    for (int64_t t = 0; t < nt; ++t) {
+        TetTopo &r = M.topo[t];
+        for (int k = 0; k < 4; ++k) r.v[k] = tv[4 * t + k];
+        for (int e = 0; e < 6; ++e)
+            r.e[e] = (int32_t)index_of(ek, edge_key(nv, tv[4 * t + kLocalEdge[e][0]], tv[4 * t + kLocalEdge[e][1]]));
+        for (int f = 0; f < 4; ++f) {
+            int64_t id = index_of(fs, fk[4 * t + f]);
+            r.f[f] = (int32_t)id;
+            if (own0[id] < 0) own0[id] = t;
+            else if (own1[id] < 0) own1[id] = t;
+            else { err = "face shared by more than two tets (tet " + std::to_string(t) + ")"; return -4; }
+        }
+        r.pad[0] = r.pad[1] = 0;
+    }
+    for (int64_t t = 0; t < nt; ++t) {
+        TetTopo &r = M.topo[t];
+        for (int f = 0; f < 4; ++f) {
+            int64_t id = r.f[f];
+            r.n[f] = (int32_t)(own0[id] == t ? own1[id] : own0[id]);
+        }
+    }
+    // vertex -> incident edges (CSR), sign carried in the low bit (1 = head)
+    M.v2e_ptr.assign((size_t)nv + 1, 0);
+    for (int64_t e = 0; e < M.ne; ++e) {
+        M.v2e_ptr[M.edges[2 * e] + 1]++;
+        M.v2e_ptr[M.edges[2 * e + 1] + 1]++;
+    }
+    for (int64_t k = 0; k < nv; ++k) M.v2e_ptr[k + 1] += M.v2e_ptr[k];
+    M.v2e_code.resize((size_t)M.ne * 2);
+    std::vector<int32_t> fill(M.v2e_ptr.begin(), M.v2e_ptr.end() - 1);
+    for (int64_t e = 0; e < M.ne; ++e) {
+        M.v2e_code[fill[M.edges[2 * e]]++] = (int32_t)(e << 1);
+        M.v2e_code[fill[M.edges[2 * e + 1]]++] = (int32_t)((e << 1) | 1);
+    }
+    return 0;
+}
+
+}  // namespace etpic

@@ -1,0 +1,307 @@
+"""Python binding of libetpic (ctypes): argument marshalling only.
+
+Every step of the particle path runs in the HIP kernels of libetpic.so; this
+module converts torch tensors (device memory, streams) into the plain pointers
+of the C ABI declared in include/etpic.h.  If the library is missing, every
+entry point raises: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libetpic.so")
+
+OK, EINVAL, ESTATE, EHIP, EMESH, EPARTICLE, EWALK, ENAN, ENOCONV = 0, -1, -2, -3, -4, -5, -6, -7, -8
+FP64, MIXED = 0, 1
+DEV_HOPCAP, DEV_NAN, DEV_BADTET = 1, 2, 4
+STEP_XCD_REMAP = 1
+STEP_TIMING = 2
+HOP_CAP = 64
+
+EXPORTS = (
+    "etpic_last_error", "etpic_create", "etpic_destroy", "etpic_mesh_upload", "etpic_mesh_canonical",
+    "etpic_mesh_counts", "etpic_mesh_edges", "etpic_mesh_faces", "etpic_gather_push_deposit", "etpic_sort",
+    "etpic_vertex_charge", "etpic_gauss_residual", "etpic_kernel_time", "etpic_check",
+)
+
+
+class EtpicError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"etpic error {code}: {msg}")
+        self.code = code
+
+
+class _Particles(C.Structure):
+    _fields_ = [("n", C.c_int64), ("lam", C.c_void_p * 3), ("vel", C.c_void_p * 3), ("tet", C.c_void_p),
+                ("id", C.c_void_p)]
+
+
+class _Fields(C.Structure):
+    _fields_ = [("e_env", C.c_void_p), ("e_dc", C.c_void_p), ("b_env", C.c_void_p), ("b_dc", C.c_void_p)]
+
+
+class _Species(C.Structure):
+    _fields_ = [("q", C.c_double), ("m", C.c_double), ("w", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libetpic.so (built in-tree by build.py); raise if it is absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libetpic.so not built ({LIB_PATH}); run paper_2208_12795_amd/build.py")
+    L = C.CDLL(LIB_PATH)
+    vp, i64p, i32p, dp = C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_double)
+    L.etpic_last_error.restype = C.c_char_p
+    L.etpic_create.argtypes = [C.POINTER(vp), C.c_int]
+    L.etpic_destroy.argtypes = [vp]
+    L.etpic_mesh_upload.argtypes = [vp, C.c_int64, dp, C.c_int64, i32p]
+    L.etpic_mesh_canonical.argtypes = [C.c_int64, dp, C.c_int64, i32p, i64p, i32p, i32p]
+    L.etpic_mesh_counts.argtypes = [vp, i64p]
+    L.etpic_mesh_edges.argtypes = [vp, i32p]
+    L.etpic_mesh_faces.argtypes = [vp, i32p]
+    L.etpic_gather_push_deposit.argtypes = [vp, C.POINTER(_Particles), C.c_int, C.POINTER(_Species),
+                                            C.POINTER(_Fields), C.c_int64, C.c_double, C.c_double, vp, vp,
+                                            C.c_uint32, vp]
+    L.etpic_sort.argtypes = [vp, C.POINTER(_Particles), C.POINTER(_Particles), C.c_int, vp]
+    L.etpic_vertex_charge.argtypes = [vp, C.POINTER(_Particles), C.POINTER(_Species), vp, vp]
+    L.etpic_gauss_residual.argtypes = [vp, vp, vp, vp, dp, vp]
+    L.etpic_kernel_time.argtypes = [vp, dp, i64p, C.c_int]
+    L.etpic_check.argtypes = [vp, vp, C.POINTER(C.c_uint32)]
+    for name in EXPORTS:
+        if name != "etpic_last_error":
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _chk(rc):
+    if rc != OK:
+        raise EtpicError(rc, lib().etpic_last_error().decode())
+    return rc
+
+
+def _np_ptr(a, ty):
+    return a.ctypes.data_as(C.POINTER(ty))
+
+
+def _dptr(t):
+    """device pointer of a torch tensor (None -> NULL)"""
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def mesh_canonical(xyz, tet_vert):
+    """Host-only canonical numbering (no GPU needed): (counts[4], edges[N_e,2], faces[N_f,3])."""
+    L = lib()
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    tv = np.ascontiguousarray(tet_vert, dtype=np.int32)
+    cnt = np.zeros(4, dtype=np.int64)
+    _chk(L.etpic_mesh_canonical(xyz.shape[0], _np_ptr(xyz, C.c_double), tv.shape[0], _np_ptr(tv, C.c_int32),
+                                _np_ptr(cnt, C.c_int64), None, None))
+    edges = np.zeros((cnt[1], 2), dtype=np.int32)
+    faces = np.zeros((cnt[2], 3), dtype=np.int32)
+    _chk(L.etpic_mesh_canonical(xyz.shape[0], _np_ptr(xyz, C.c_double), tv.shape[0], _np_ptr(tv, C.c_int32),
+                                _np_ptr(cnt, C.c_int64), _np_ptr(edges, C.c_int32), _np_ptr(faces, C.c_int32)))
+    return cnt, edges, faces
+
+
+@dataclass
+class Species:
+    q: float
+    m: float
+    w: float = 1.0
+
+    def c(self):
+        return _Species(self.q, self.m, self.w)
+
+
+class Particles:
+    """Structure-of-arrays particle state on the device (torch tensors).
+
+    lam: float64 [3, N] (lam1, lam2, lam3); vel: [3, N] float64 (FP64) or
+    float32 (MIXED); tet: int32 [N]; ids: int64 [N] or None."""
+
+    def __init__(self, lam, vel, tet, ids=None):
+        self.lam, self.vel, self.tet, self.ids = lam, vel, tet, ids
+
+    @property
+    def n(self):
+        return int(self.tet.shape[0])
+
+    @property
+    def precision(self):
+        import torch
+        return FP64 if self.vel.dtype == torch.float64 else MIXED
+
+    @classmethod
+    def from_numpy(cls, tet, lam, vel, ids=None, precision=FP64, device="cuda"):
+        import torch
+        vdt = torch.float64 if precision == FP64 else torch.float32
+        lam_t = torch.from_numpy(np.ascontiguousarray(np.asarray(lam, np.float64).T)).to(device)
+        vel_t = torch.from_numpy(np.ascontiguousarray(np.asarray(vel, np.float64).T)).to(device=device, dtype=vdt)
+        tet_t = torch.from_numpy(np.ascontiguousarray(tet, dtype=np.int32)).to(device)
+        ids_t = None if ids is None else torch.from_numpy(np.ascontiguousarray(ids, dtype=np.int64)).to(device)
+        return cls(lam_t.contiguous(), vel_t.contiguous(), tet_t, ids_t)
+
+    def empty_like(self):
+        import torch
+        return Particles(torch.empty_like(self.lam), torch.empty_like(self.vel), torch.empty_like(self.tet),
+                         None if self.ids is None else torch.empty_like(self.ids))
+
+    def clone(self):
+        return Particles(self.lam.clone(), self.vel.clone(), self.tet.clone(),
+                         None if self.ids is None else self.ids.clone())
+
+    def to_numpy(self):
+        return (self.tet.cpu().numpy(), self.lam.double().cpu().numpy().T.copy(),
+                self.vel.double().cpu().numpy().T.copy(), None if self.ids is None else self.ids.cpu().numpy())
+
+    def desc(self):
+        for t in (self.lam, self.vel):
+            assert t.is_contiguous() and t.dim() == 2 and t.shape[0] == 3
+        assert self.tet.is_contiguous() and self.tet.dtype.itemsize == 4
+        d = _Particles()
+        d.n = self.n
+        for k in range(3):
+            d.lam[k] = self.lam[k].data_ptr()
+            d.vel[k] = self.vel[k].data_ptr()
+        d.tet = self.tet.data_ptr()
+        d.id = None if self.ids is None else self.ids.data_ptr()
+        return d
+
+
+class Fields:
+    """Field DoFs on the device: e_env float64 [N_e, 2], b_env float64 [N_f, 2],
+    optional e_dc float64 [N_e], b_dc float64 [N_f]."""
+
+    def __init__(self, e_env, b_env, e_dc=None, b_dc=None):
+        self.e_env, self.b_env, self.e_dc, self.b_dc = e_env, b_env, e_dc, b_dc
+
+    @classmethod
+    def from_numpy(cls, e_env, b_env, e_dc=None, b_dc=None, device="cuda"):
+        import torch
+
+        def cplx(z):
+            z = np.asarray(z)
+            return torch.from_numpy(np.ascontiguousarray(np.stack([z.real, z.imag], axis=1), dtype=np.float64)).to(device)
+
+        def real(x):
+            return None if x is None else torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to(device)
+        return cls(cplx(e_env), cplx(b_env), real(e_dc), real(b_dc))
+
+    def desc(self):
+        for t in (self.e_env, self.b_env, self.e_dc, self.b_dc):
+            assert t is None or t.is_contiguous()
+        return _Fields(self.e_env.data_ptr(), None if self.e_dc is None else self.e_dc.data_ptr(),
+                       self.b_env.data_ptr(), None if self.b_dc is None else self.b_dc.data_ptr())
+
+
+class Context:
+    """One etpic context bound to one HIP device."""
+
+    def __init__(self, device=0):
+        self._h = C.c_void_p()
+        _chk(lib().etpic_create(C.byref(self._h), int(device)))
+        self.counts = None
+
+    def close(self):
+        if self._h:
+            lib().etpic_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # mesh -----------------------------------------------------------------------
+    def upload_mesh(self, xyz, tet_vert):
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        tv = np.ascontiguousarray(tet_vert, dtype=np.int32)
+        _chk(lib().etpic_mesh_upload(self._h, xyz.shape[0], _np_ptr(xyz, C.c_double), tv.shape[0],
+                                     _np_ptr(tv, C.c_int32)))
+        cnt = np.zeros(4, dtype=np.int64)
+        _chk(lib().etpic_mesh_counts(self._h, _np_ptr(cnt, C.c_int64)))
+        self.counts = tuple(int(x) for x in cnt)
+        return self.counts
+
+    @property
+    def n_vert(self):
+        return self.counts[0]
+
+    @property
+    def n_edge(self):
+        return self.counts[1]
+
+    @property
+    def n_face(self):
+        return self.counts[2]
+
+    @property
+    def n_tet(self):
+        return self.counts[3]
+
+    def edges(self):
+        out = np.zeros((self.n_edge, 2), dtype=np.int32)
+        _chk(lib().etpic_mesh_edges(self._h, _np_ptr(out, C.c_int32)))
+        return out
+
+    def faces(self):
+        out = np.zeros((self.n_face, 3), dtype=np.int32)
+        _chk(lib().etpic_mesh_faces(self._h, _np_ptr(out, C.c_int32)))
+        return out
+
+    # particle step ----------------------------------------------------------------
+    def gather_push_deposit(self, parts, species, fields, step, dt, omega, dG, rho=None, flags=STEP_XCD_REMAP,
+                            stream=None):
+        d = parts.desc()
+        sp = species.c()
+        fd = fields.desc()
+        _chk(lib().etpic_gather_push_deposit(self._h, C.byref(d), parts.precision, C.byref(sp), C.byref(fd),
+                                             int(step), float(dt), float(omega), _dptr(dG), _dptr(rho),
+                                             int(flags), _stream(stream)))
+
+    def sort(self, src, dst, stream=None):
+        a, b = src.desc(), dst.desc()
+        _chk(lib().etpic_sort(self._h, C.byref(a), C.byref(b), src.precision, _stream(stream)))
+
+    def vertex_charge(self, parts, species, rho, stream=None):
+        d = parts.desc()
+        sp = species.c()
+        _chk(lib().etpic_vertex_charge(self._h, C.byref(d), C.byref(sp), _dptr(rho), _stream(stream)))
+
+    def gauss_residual(self, dG, rho_new, rho_old, stream=None):
+        out = np.zeros(2)
+        _chk(lib().etpic_gauss_residual(self._h, _dptr(dG), _dptr(rho_new), _dptr(rho_old),
+                                        _np_ptr(out, C.c_double), _stream(stream)))
+        return float(out[0]), float(out[1])
+
+    def kernel_time(self, reset=True):
+        """(total ms, launches) of the particle kernel in steps run with STEP_TIMING."""
+        ms = C.c_double(0.0)
+        n = C.c_int64(0)
+        _chk(lib().etpic_kernel_time(self._h, C.byref(ms), C.byref(n), int(bool(reset))))
+        return ms.value, n.value
+
+    def check(self, stream=None, raise_on_error=True):
+        word = C.c_uint32(0)
+        rc = lib().etpic_check(self._h, _stream(stream), C.byref(word))
+        if raise_on_error:
+            _chk(rc)
+        return rc, int(word.value)

@@ -1,0 +1,66 @@
+"""Host-side checks of the C-ABI library (no GPU): it loads, exports every symbol
+declared in include/etpic.h, and its host canonicalisation of a mesh agrees
+bit for bit with the oracle's and the input generator's numbering."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2208_12795_amd import etpic, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    txt = open(os.path.join(ROOT, "include", "etpic.h")).read()
+    return sorted(set(re.findall(r"\b(etpic_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = etpic.lib()
+    declared = header_symbols()
+    assert len(declared) >= 12
+    for name in declared:
+        assert hasattr(L, name), name
+    assert sorted(etpic.EXPORTS) == declared
+
+
+@pytest.mark.parametrize("n", [(1, 1, 1), (3, 2, 4), (5, 5, 5)])
+def test_canonical_numbering_matches_oracle(ora, n):
+    xyz, tv = synth.kuhn_mesh(n, (1.0, 2.0, 1.5), 0.1, np.random.default_rng(5))
+    cnt, edges, faces = etpic.mesh_canonical(xyz, tv)
+    M = ora.OracleMesh(xyz, tv)
+    assert tuple(cnt) == (M.nv, M.ne, M.nf, M.nt)
+    assert np.array_equal(edges, M.edges())
+    assert np.array_equal(faces, M.faces())
+    assert np.array_equal(edges, synth.mesh_edges(tv, xyz.shape[0]))
+
+
+def test_canonical_rejects_bad_meshes():
+    xyz = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1.0], [1, 1, 1.0]])
+    with pytest.raises(etpic.EtpicError) as e:
+        etpic.mesh_canonical(xyz, np.array([[0, 2, 1, 3]], np.int32))
+    assert e.value.code == etpic.EMESH
+    with pytest.raises(etpic.EtpicError) as e:
+        etpic.mesh_canonical(xyz, np.array([[0, 1, 2, 9]], np.int32))
+    assert e.value.code == etpic.EINVAL
+    flat = xyz.copy()
+    flat[3] = [1, 1, 0]
+    with pytest.raises(etpic.EtpicError) as e:
+        etpic.mesh_canonical(flat, np.array([[0, 1, 2, 3]], np.int32))
+    assert e.value.code == etpic.EMESH
+    # three tets sharing one face -> non-manifold
+    xyz3 = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1.0], [0.2, 0.2, -1], [0.3, 0.3, 2.0]])
+    tv3 = np.array([[0, 1, 2, 3], [0, 1, 2, 4], [0, 1, 2, 5]], np.int32)
+    with pytest.raises(etpic.EtpicError) as e:
+        etpic.mesh_canonical(xyz3, tv3)
+    assert e.value.code == etpic.EMESH
+
+
+def test_no_cpu_fallback_without_library(monkeypatch, tmp_path):
+    """The binding refuses to run when the HIP library is absent."""
+    monkeypatch.setattr(etpic, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(etpic, "_lib", None)
+    with pytest.raises(RuntimeError):
+        etpic.lib()

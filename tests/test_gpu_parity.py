@@ -1,0 +1,223 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Every case starts both sides from the same seeded state and compares one step
+(v, positions, edge currents); multi-step cases also check the discrete
+continuity law on the GPU every step.  Tolerances: float64 form 1e-12
+relative, mixed form 2e-5 relative (positions beyond the float64 storage
+quantum, see parity_util)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2208_12795_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from parity_util import assert_within, step_errors  # noqa: E402
+
+NTH = max(1, min(16, os.cpu_count() or 1))
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def E():
+    from paper_2208_12795_amd import etpic
+    return etpic
+
+
+def setup(E, torch, w, precision):
+    ctx = E.Context(0)
+    ctx.upload_mesh(w.xyz, w.tet_vert)
+    assert np.array_equal(ctx.edges(), w.edges)
+    assert np.array_equal(ctx.faces(), w.faces)
+    parts = E.Particles.from_numpy(w.tet, w.lam, w.vel, w.ids, precision=precision)
+    fields = E.Fields.from_numpy(w.e_env, w.b_env, None, w.b_dc)
+    return ctx, parts, fields
+
+
+def oracle_step(M, state, w, step, nthreads=1, omega=None, dt=None):
+    tet, lam, vel = (np.ascontiguousarray(a).copy() for a in state)
+    dG = np.zeros(M.ne)
+    rc, _ = M.step(tet, lam, vel, q=w.q, m=w.m, w=w.w, step=step, dt=w.dt if dt is None else dt,
+                   omega=w.omega if omega is None else omega, e_env=w.e_env, b_env=w.b_env, b_dc=w.b_dc, dG=dG,
+                   nthreads=nthreads)
+    return rc, (tet, lam, vel), dG
+
+
+def run_case(E, torch, ora, w, steps, precision, tol, check_every=1, dt=None):
+    print(f"[case] {w.name} N={w.tet.shape[0]} steps={steps} precision={precision}", flush=True)
+    ctx, parts, fields = setup(E, torch, w, precision)
+    M = ora.OracleMesh(w.xyz, w.tet_vert)
+    sp = E.Species(w.q, w.m, w.w)
+    dev = "cuda"
+    rho_old = torch.zeros(ctx.n_vert, dtype=torch.float64, device=dev)
+    ctx.vertex_charge(parts, sp, rho_old)
+    worst = {}
+    worst_gauss = 0.0
+    dt = w.dt if dt is None else dt
+    for s in range(steps):
+        tin, lin, vin, _ = parts.to_numpy()
+        dG = torch.zeros(ctx.n_edge, dtype=torch.float64, device=dev)
+        ctx.gather_push_deposit(parts, sp, fields, s, dt, w.omega, dG)
+        rho_new = torch.zeros_like(rho_old)
+        ctx.vertex_charge(parts, sp, rho_new)
+        r, p = ctx.gauss_residual(dG, rho_new, rho_old)
+        worst_gauss = max(worst_gauss, r / p)
+        assert r / p <= 1e-12, (s, r / p)
+        if s % check_every == 0:
+            rc, o, dGo = oracle_step(M, (tin, lin, vin), w, s, nthreads=NTH, dt=dt)
+            assert rc == 0
+            tg, lg, vg, _ = parts.to_numpy()
+            err = step_errors(w.xyz, w.tet_vert, (tin, lin, vin), (tg, lg, vg), o, dG.cpu().numpy(), dGo)
+            assert err["tet_mismatch"] <= 2 + 1e-4 * len(tg), err
+            assert_within(err, tol, f"step {s}")
+            for k, v in err.items():
+                worst[k] = max(worst.get(k, 0.0), v)
+        rho_old = rho_new
+    ctx.check()
+    print(f"[case] {w.name} worst {worst} gauss {worst_gauss:.2e}", flush=True)
+    ctx.close()
+    return worst
+
+
+def test_small_config_fp64_every_step(E, torch_cuda, ora):
+    """1,000 electrons on the 750-tet unit cube, 100 steps, float64 form."""
+    run_case(E, torch_cuda, ora, synth.make_workload(1), 100, E.FP64, 1e-12)
+
+
+def test_small_config_mixed(E, torch_cuda, ora):
+    """Same case in the mixed form: float32 gather/push, float64 positions and deposit."""
+    run_case(E, torch_cuda, ora, synth.make_workload(1), 30, E.MIXED, 2e-5)
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 2e-5)])
+def test_crossing_heavy(E, torch_cuda, ora, precision, tol):
+    """Steps of 0.1-0.5 cell: most particles cross faces, several per step, and
+    many hit the walls (reflection)."""
+    w = synth.make_workload(1, n_particles=4000)
+    w.vel = w.vel * 40.0
+    run_case(E, torch_cuda, ora, w, 12, precision, tol, dt=1e-8)
+
+
+def test_ragged_and_multi_tile(E, torch_cuda, ora):
+    """A particle count that spans several 256-lane blocks with a ragged tail,
+    on the 40^3 mesh (384k tets)."""
+    w = synth.make_workload(2, n_particles=200_003)
+    run_case(E, torch_cuda, ora, w, 3, E.FP64, 1e-12)
+
+
+def test_omega_zero_matches_regular(E, torch_cuda):
+    """At w = 0 the GPU envelope run equals the GPU run with real DoFs Re(e~):
+    the carrier factor is exactly one (reduction to the regular scheme)."""
+    torch = torch_cuda
+    w = synth.make_workload(1, omega=0.0)
+    ctx, p1, f1 = setup(E, torch, w, E.FP64)
+    p2 = p1.clone()
+    f2 = E.Fields.from_numpy(np.zeros_like(w.e_env), w.b_env, w.e_env.real, w.b_dc)
+    sp = E.Species(w.q, w.m, w.w)
+    g1 = torch.zeros(ctx.n_edge, dtype=torch.float64, device="cuda")
+    g2 = torch.zeros_like(g1)
+    for s in range(5):
+        ctx.gather_push_deposit(p1, sp, f1, s, w.dt, 0.0, g1)
+        ctx.gather_push_deposit(p2, sp, f2, s, w.dt, 0.0, g2)
+    a, b = p1.to_numpy(), p2.to_numpy()
+    for x, y in zip(a[:3], b[:3]):
+        assert np.array_equal(x, y)
+    assert torch.allclose(g1, g2, rtol=1e-14, atol=0)
+
+
+def test_sort_permutation_invariance(E, torch_cuda, ora):
+    """Counting sort: output sorted by tet, a permutation of the input (ids carried),
+    and a step after the sort gives the same currents as without it."""
+    torch = torch_cuda
+    w = synth.make_workload(2, n_particles=300_000)
+    ctx, parts, fields = setup(E, torch, w, E.FP64)
+    dst = parts.empty_like()
+    ctx.sort(parts, dst)
+    t0, l0, v0, i0 = parts.to_numpy()
+    t1, l1, v1, i1 = dst.to_numpy()
+    assert np.all(np.diff(t1) >= 0)
+    assert np.array_equal(np.sort(i1), np.arange(len(i1)))
+    assert np.array_equal(t1, t0[i1]) and np.array_equal(l1, l0[i1]) and np.array_equal(v1, v0[i1])
+    sp = E.Species(w.q, w.m, w.w)
+    g0 = torch.zeros(ctx.n_edge, dtype=torch.float64, device="cuda")
+    g1 = torch.zeros_like(g0)
+    ctx.gather_push_deposit(parts, sp, fields, 7, w.dt, w.omega, g0)
+    ctx.gather_push_deposit(dst, sp, fields, 7, w.dt, w.omega, g1)
+    assert torch.allclose(g0, g1, rtol=0, atol=1e-13 * g0.abs().max().item())
+    ctx.check()
+
+
+def test_sort_mixed_and_counts_histogram(E, torch_cuda):
+    torch = torch_cuda
+    w = synth.make_workload(1, n_particles=5000)
+    ctx, parts, fields = setup(E, torch, w, E.MIXED)
+    dst = parts.empty_like()
+    ctx.sort(parts, dst)
+    t1, l1, v1, i1 = dst.to_numpy()
+    assert np.all(np.diff(t1) >= 0)
+    assert np.array_equal(np.bincount(t1, minlength=ctx.n_tet), np.bincount(w.tet, minlength=ctx.n_tet))
+    assert np.array_equal(v1.astype(np.float32), w.vel[i1].astype(np.float32))
+
+
+def test_edge_cases(E, torch_cuda, ora):
+    """Empty input; all particles in one tet (atomic contention); particles
+    exactly on vertices and faces."""
+    torch = torch_cuda
+    w = synth.make_workload(1)
+    ctx, _, fields = setup(E, torch, w, E.FP64)
+    sp = E.Species(w.q, w.m, w.w)
+    dG = torch.zeros(ctx.n_edge, dtype=torch.float64, device="cuda")
+    empty = E.Particles.from_numpy(np.zeros(0, np.int32), np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0, np.int64))
+    ctx.gather_push_deposit(empty, sp, fields, 0, w.dt, w.omega, dG)
+    assert dG.abs().max().item() == 0.0
+    M = ora.OracleMesh(w.xyz, w.tet_vert)
+    rng = np.random.default_rng(9)
+    n = 20000
+    tet = np.full(n, 123, np.int32)
+    g = rng.standard_exponential((n, 4))
+    lam = (g / g.sum(1, keepdims=True))[:, 1:]
+    lam[:8] = [[1, 0, 0], [0, 1, 0], [0, 0, 1], [0, 0, 0], [0.5, 0.5, 0], [0, 0.3, 0.7], [0.2, 0.3, 0.5], [1 / 3] * 3]
+    vel = synth.maxwellian(n, 1e5, rng)
+    parts = E.Particles.from_numpy(tet, lam, vel, np.arange(n))
+    ctx.gather_push_deposit(parts, sp, fields, 4, w.dt, w.omega, dG)
+    rc, o, dGo = oracle_step(M, (tet, np.ascontiguousarray(lam), vel), w, 4)
+    tg, lg, vg, _ = parts.to_numpy()
+    err = step_errors(w.xyz, w.tet_vert, (tet, lam, vel), (tg, lg, vg), o, dG.cpu().numpy(), dGo)
+    assert_within(err, 1e-12, "one tet")
+    ctx.check()
+
+
+def test_device_errors_are_reported(E, torch_cuda, ora):
+    """Host-forced error paths: a tet index out of range and a displacement of
+    ~1000 box lengths (hop cap) are flagged through etpic_check; the kernels
+    still exit normally."""
+    torch = torch_cuda
+    w = synth.make_workload(1, n_particles=64)
+    ctx, parts, fields = setup(E, torch, w, E.FP64)
+    sp = E.Species(w.q, w.m, w.w)
+    dG = torch.zeros(ctx.n_edge, dtype=torch.float64, device="cuda")
+    bad = parts.clone()
+    bad.tet[5] = ctx.n_tet + 3
+    ctx.gather_push_deposit(bad, sp, fields, 0, w.dt, w.omega, dG)
+    rc, word = ctx.check(raise_on_error=False)
+    assert rc == E.EPARTICLE and word & E.DEV_BADTET
+    rc, word = ctx.check(raise_on_error=False)
+    assert rc == 0 and word == 0
+    fast = parts.clone()
+    fast.vel.fill_(1e3)
+    ctx.gather_push_deposit(fast, E.Species(w.q, w.m * 1e30, w.w), fields, 0, 1.0, 0.0, dG)
+    rc, word = ctx.check(raise_on_error=False)
+    assert rc == E.EWALK and word & E.DEV_HOPCAP
+    with pytest.raises(E.EtpicError):
+        ctx.gather_push_deposit(parts, E.Species(w.q, 0.0, w.w), fields, 0, w.dt, w.omega, dG)

@@ -78,7 +78,9 @@ enum etpic_device_flags {
 /* flags of etpic_gather_push_deposit */
 enum etpic_step_flags {
     ETPIC_STEP_XCD_REMAP = 1u, /* map consecutive particle blocks to one XCD (default on) */
-    ETPIC_STEP_TIMING = 2u     /* bracket the particle kernel with HIP events (etpic_kernel_time) */
+    ETPIC_STEP_TIMING = 2u,    /* bracket the particle kernel with HIP events (etpic_kernel_time) */
+    ETPIC_STEP_UNSTAGED = 4u   /* per-tet coefficient table in HBM + one-lane-per-particle kernel with
+                                  direct atomics, instead of the fused LDS-staged kernel (comparison) */
 };
 
 #define ETPIC_HOP_CAP 64

@@ -21,7 +21,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/etpic.h"
+#include "etpic.h"
 #include "mesh_host.hpp"
 
 using etpic::TetTopo;
@@ -47,6 +47,39 @@ int fail(int code, const char *fmt, ...) {
     } while (0)
 
 constexpr int kBlock = 256;
+
+// Runs of equal key among the 64 lanes of a wavefront (particles are kept
+// sorted by tet, so neighbouring lanes mostly share a key).  head: first lane
+// of a run; head_lane / run_end: first and last lane of this lane's run.
+struct WaveRuns {
+    int lane, head_lane, run_end;
+    bool head;
+};
+
+__device__ __forceinline__ WaveRuns wave_runs(int key) {
+    WaveRuns r;
+    r.lane = threadIdx.x & 63;
+    const int prev = __shfl_up(key, 1);
+    r.head = r.lane == 0 || key != prev;
+    const unsigned long long hm = __ballot(r.head);
+    const unsigned long long upto = r.lane == 63 ? ~0ull : ((2ull << r.lane) - 1ull);  // lanes 0..lane
+    const unsigned long long after = hm & ~upto;
+    r.head_lane = 63 - __clzll((long long)(hm & upto));
+    r.run_end = after ? (__ffsll((unsigned long long)after) - 2) : 63;
+    return r;
+}
+
+// Segmented suffix sum: after the call the head lane of each run holds the
+// run's total (other lanes hold partial sums).
+template <typename T>
+__device__ __forceinline__ T run_total(T x, const WaveRuns &r) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const T y = __shfl_down(x, off);
+        if (r.lane + off <= r.run_end) x += y;
+    }
+    return x;
+}
 
 // ------------------------------------------------------------------ per-tet coefficients
 // W1_ij = l_i grad l_j - l_j grad l_i  =>  eps_ij W1_ij adds eps_ij grad l_j to A_i and
@@ -168,7 +201,8 @@ __device__ __noinline__ int walk(const StepArgs<Real> &a, int T, double l[4], do
             for (int c = 0; c < 3; ++c) g[k][c] = gp[3 * k + c];
         double dl[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) dl[k] = g[k][0] * d[0] + g[k][1] * d[1] + g[k][2] * d[2];
+        for (int k = 1; k < 4; ++k) dl[k] = g[k][0] * d[0] + g[k][1] * d[1] + g[k][2] * d[2];
+        dl[0] = -(dl[1] + dl[2] + dl[3]);
         double smin = 1.0;
         int kmin = -1;
 #pragma unroll
@@ -278,13 +312,16 @@ __global__ void __launch_bounds__(kBlock) k_gpd(StepArgs<Real> a) {
     // displacement and barycentric increments in the home tet
     Real dx[3] = {a.dt_r * v[0], a.dt_r * v[1], a.dt_r * v[2]};
     const Real *gr = a.grad_r + (int64_t)T * 12;
+    // lam0 is stored implicitly (1 - lam1 - lam2 - lam3), so its increment is taken
+    // as minus the sum of the other three, in float64: the deposit and the stored
+    // end point then see the same four increments (continuity to float64 rounding).
     double dl[4];
+#pragma unroll
+    for (int k = 1; k < 4; ++k) dl[k] = (double)(gr[3 * k] * dx[0] + gr[3 * k + 1] * dx[1] + gr[3 * k + 2] * dx[2]);
+    dl[0] = -(dl[1] + dl[2] + dl[3]);
     bool stays = true;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        dl[k] = (double)(gr[3 * k] * dx[0] + gr[3 * k + 1] * dx[1] + gr[3 * k + 2] * dx[2]);
-        stays = stays && (l[k] + dl[k] >= 0.0);
-    }
+    for (int k = 0; k < 4; ++k) stays = stays && (l[k] + dl[k] >= 0.0);
     if (stays) {
         const TetTopo tp = a.topo[T];
         deposit_piece(a.dG, tp, l, dl, a.qw);
@@ -311,25 +348,307 @@ __global__ void __launch_bounds__(kBlock) k_gpd(StepArgs<Real> a) {
     }
 }
 
+// ------------------------------------------------------------------ fused staged step
+// One block of kBlock threads takes kBlock consecutive particles.  Runs of equal
+// tet in thread order (particles are kept sorted by tet) become "slots".  For up
+// to kSlots slots at a time, 8 threads per slot build the carrier-rotated
+// Whitney coefficients of that tet straight from the edge/face DoFs into LDS
+// (A_k and C_k, one thread per vertex k each).  Every particle then gathers from
+// LDS, pushes, and -- if it stays in its tet, which is the common case --
+// deposits its six path integrals into the slot's LDS accumulators (float64
+// LDS atomics).  The accumulators are flushed with one float64 global atomic
+// per (slot, edge).  Particles that leave their tet walk and deposit every
+// piece with global atomics.
+constexpr int kSlots = 32;
+
+template <typename Real>
+struct StageLds {
+    Real coef[kSlots][24];
+    Real grad[kSlots][9];
+    double acc[kSlots][6];
+    double racc[kSlots][4];
+    int32_t edge[kSlots][6];
+    int32_t vert[kSlots][4];
+    int32_t tet[kSlots];
+    int32_t wave_last[kBlock / 64];
+    int32_t wave_heads[kBlock / 64];
+};
+
+struct FieldPtrs {
+    const double2 *e_env;
+    const double *e_dc;
+    const double2 *b_env;
+    const double *b_dc;
+    double c, s;   // cos(w t_n), sin(w t_n)
+};
+
+// local edge index of the vertex pair {i, j}, i < j
+__device__ __forceinline__ int local_edge(int i, int j) { return i == 0 ? j - 1 : (i == 1 ? j + 1 : 5); }
+
+// Part `part` (0..7) of the coefficients of tet T into slot s:
+//   part k < 4 : A_k = sum_{j != k} sign(j - k) eps_{kj} grad l_j   (E = sum_k l_k A_k)
+//   part 4 + k : C_k = 2 sum_{faces f containing k} beta_f (grad l_a x grad l_b),
+//                (k, a, b) the cyclic order of f's ascending triple starting at k.
+// eps and beta are the real parts Re{dof e^{jwt}} + dc of the edge and face DoFs.
+template <typename Real>
+__device__ __forceinline__ void stage_part(StageLds<Real> &L, int s, int part, int T, const TetTopo *__restrict__ topo,
+                                           const double *__restrict__ grad, const FieldPtrs &F) {
+    const double *gp = grad + (int64_t)T * 12;
+    double g[4][3];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) g[k][d] = gp[3 * k + d];
+    const int32_t *tp = reinterpret_cast<const int32_t *>(topo + T);
+    if (part < 4) {
+        const int k = part;
+        double A[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (j == k) continue;
+            const int id = tp[local_edge(min(j, k), max(j, k))];
+            const double2 z = F.e_env[id];
+            double eps = z.x * F.c - z.y * F.s;
+            if (F.e_dc) eps += F.e_dc[id];
+            if (j < k) eps = -eps;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) A[d] += eps * g[j][d];
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) L.coef[s][3 * k + d] = (Real)A[d];
+        if (k < 3) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) L.grad[s][3 * k + d] = (Real)g[k + 1][d];
+        } else {
+#pragma unroll
+            for (int e = 0; e < 6; ++e) L.edge[s][e] = tp[e];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) L.vert[s][v] = tp[10 + v];
+        }
+        L.racc[s][k] = 0.0;
+        L.acc[s][k] = 0.0;
+    } else {
+        const int k = part - 4;
+        double Cv[3] = {0.0, 0.0, 0.0};
+        const int lf[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            if (f == k) continue;
+            int a, b;
+            if (lf[f][0] == k) { a = lf[f][1]; b = lf[f][2]; }
+            else if (lf[f][1] == k) { a = lf[f][2]; b = lf[f][0]; }
+            else { a = lf[f][0]; b = lf[f][1]; }
+            const int id = tp[6 + f];
+            const double2 z = F.b_env[id];
+            double beta = z.x * F.c - z.y * F.s;
+            if (F.b_dc) beta += F.b_dc[id];
+            beta *= 2.0;
+            Cv[0] += beta * (g[a][1] * g[b][2] - g[a][2] * g[b][1]);
+            Cv[1] += beta * (g[a][2] * g[b][0] - g[a][0] * g[b][2]);
+            Cv[2] += beta * (g[a][0] * g[b][1] - g[a][1] * g[b][0]);
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) L.coef[s][12 + 3 * k + d] = (Real)Cv[d];
+        if (k < 2) L.acc[s][4 + k] = 0.0;
+    }
+}
+
+template <typename Real>
+__global__ void __launch_bounds__(kBlock) k_step(StepArgs<Real> a, FieldPtrs F, int remap) {
+    __shared__ StageLds<Real> L;
+    unsigned blk = blockIdx.x;
+    if (remap) {
+        // the dispatcher deals blocks round-robin over the 8 XCDs; give each XCD
+        // one contiguous range of particles (hence of tets and edges in its L2)
+        const unsigned G = gridDim.x, q = G / 8, r = G % 8, x = blk % 8, j = blk / 8;
+        blk = x * q + min(x, r) + j;
+    }
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int64_t p = (int64_t)blk * kBlock + tid;
+    int T = -1;
+    if (p < a.n) {
+        T = a.tet[p];
+        if ((unsigned)T >= (unsigned)a.nt) {
+            atomicOr(a.status, (unsigned)ETPIC_DEV_BADTET);
+            T = -1;
+        }
+    }
+    const bool act = T >= 0;
+    double l[4];
+    Real v[3];
+    if (act) {
+        l[1] = a.lam1[p];
+        l[2] = a.lam2[p];
+        l[3] = a.lam3[p];
+        v[0] = a.v0[p];
+        v[1] = a.v1[p];
+        v[2] = a.v2[p];
+    }
+    // runs of equal tet -> slots
+    int prevT = __shfl_up(T, 1);
+    if (lane == 63) L.wave_last[wid] = T;
+    __syncthreads();
+    if (lane == 0) prevT = wid == 0 ? -2 : L.wave_last[wid - 1];
+    const bool head = act && T != prevT;
+    const unsigned long long hm = __ballot(head);
+    const unsigned long long upto = lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1ull);
+    const int incl = __popcll(hm & upto);
+    if (lane == 0) L.wave_heads[wid] = __popcll(hm);
+    __syncthreads();
+    int before = 0, nslot = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+        const int c = L.wave_heads[w];
+        before += w < wid ? c : 0;
+        nslot += c;
+    }
+    const int slot = before + incl - 1;
+    const WaveRuns runs = wave_runs(act ? slot : -1);
+    for (int lo = 0; lo < nslot; lo += kSlots) {
+        const int cnt = min(kSlots, nslot - lo);
+        if (head && slot >= lo && slot < lo + cnt) L.tet[slot - lo] = T;
+        __syncthreads();
+        {
+            const int s = tid >> 3, part = tid & 7;
+            if (s < cnt) stage_part<Real>(L, s, part, L.tet[s], a.topo, a.grad, F);
+        }
+        __syncthreads();
+        const bool here = act && slot >= lo && slot < lo + cnt;
+        double g6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // this lane's in-tet path integrals
+        double r4[4] = {0.0, 0.0, 0.0, 0.0};             // this lane's end-point barycentrics
+        if (here) {
+            const int s = slot - lo;
+            l[0] = 1.0 - l[1] - l[2] - l[3];
+            const Real *cf = L.coef[s];
+            Real E[3], B[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                E[d] = (Real)l[0] * cf[d] + (Real)l[1] * cf[3 + d] + (Real)l[2] * cf[6 + d] + (Real)l[3] * cf[9 + d];
+                B[d] = (Real)l[0] * cf[12 + d] + (Real)l[1] * cf[15 + d] + (Real)l[2] * cf[18 + d] +
+                       (Real)l[3] * cf[21 + d];
+            }
+            const Real h = a.h;
+            Real vm[3], tau[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                vm[d] = v[d] + h * E[d];
+                tau[d] = h * B[d];
+            }
+            const Real t2 = tau[0] * tau[0] + tau[1] * tau[1] + tau[2] * tau[2];
+            const Real sg = (Real)2 / ((Real)1 + t2);
+            const Real vr[3] = {vm[0] + (vm[1] * tau[2] - vm[2] * tau[1]), vm[1] + (vm[2] * tau[0] - vm[0] * tau[2]),
+                                vm[2] + (vm[0] * tau[1] - vm[1] * tau[0])};
+            v[0] = vm[0] + sg * (vr[1] * tau[2] - vr[2] * tau[1]) + h * E[0];
+            v[1] = vm[1] + sg * (vr[2] * tau[0] - vr[0] * tau[2]) + h * E[1];
+            v[2] = vm[2] + sg * (vr[0] * tau[1] - vr[1] * tau[0]) + h * E[2];
+            if (!(isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]))) atomicOr(a.status, (unsigned)ETPIC_DEV_NAN);
+            const Real dx[3] = {a.dt_r * v[0], a.dt_r * v[1], a.dt_r * v[2]};
+            const Real *gr = L.grad[s];
+            double dl[4];
+#pragma unroll
+            for (int k = 1; k < 4; ++k)
+                dl[k] = (double)(gr[3 * k - 3] * dx[0] + gr[3 * k - 2] * dx[1] + gr[3 * k - 1] * dx[2]);
+            dl[0] = -(dl[1] + dl[2] + dl[3]);
+            const bool stays = (l[0] + dl[0] >= 0.0) && (l[1] + dl[1] >= 0.0) && (l[2] + dl[2] >= 0.0) &&
+                               (l[3] + dl[3] >= 0.0);
+            int Tend = T;
+            if (stays) {
+                double m[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) m[k] = l[k] + 0.5 * dl[k];
+                const int le[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+#pragma unroll
+                for (int e = 0; e < 6; ++e) g6[e] = m[le[e][0]] * dl[le[e][1]] - m[le[e][1]] * dl[le[e][0]];
+#pragma unroll
+                for (int k = 1; k < 4; ++k) l[k] += dl[k];
+            } else {
+                double d[3] = {(double)dx[0], (double)dx[1], (double)dx[2]};
+                Tend = walk<Real>(a, T, l, d, v);
+                a.tet[p] = Tend;
+            }
+            a.lam1[p] = l[1];
+            a.lam2[p] = l[2];
+            a.lam3[p] = l[3];
+            a.v0[p] = v[0];
+            a.v1[p] = v[1];
+            a.v2[p] = v[2];
+            if (a.rho) {
+                const double l0 = 1.0 - l[1] - l[2] - l[3];
+                if (Tend == T) {
+                    r4[0] = l0;
+                    r4[1] = l[1];
+                    r4[2] = l[2];
+                    r4[3] = l[3];
+                } else {
+                    const TetTopo tp = a.topo[Tend];
+                    unsafeAtomicAdd(&a.rho[tp.v[0]], a.qw * l0);
+                    unsafeAtomicAdd(&a.rho[tp.v[1]], a.qw * l[1]);
+                    unsafeAtomicAdd(&a.rho[tp.v[2]], a.qw * l[2]);
+                    unsafeAtomicAdd(&a.rho[tp.v[3]], a.qw * l[3]);
+                }
+            }
+        }
+        // wave-level segmented reduction over runs of equal slot, then one LDS
+        // atomic per (run, edge) from the run's head lane
+#pragma unroll
+        for (int e = 0; e < 6; ++e) g6[e] = run_total(g6[e], runs);
+        if (a.rho) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) r4[k] = run_total(r4[k], runs);
+        }
+        if (here && runs.head) {
+            const int s = slot - lo;
+#pragma unroll
+            for (int e = 0; e < 6; ++e) unsafeAtomicAdd(&L.acc[s][e], g6[e]);
+            if (a.rho) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) unsafeAtomicAdd(&L.racc[s][k], r4[k]);
+            }
+        }
+        __syncthreads();
+        for (int t = tid; t < cnt * 10; t += kBlock) {
+            if (t < cnt * 6) {
+                const int s = t / 6, e = t - 6 * s;
+                const double val = L.acc[s][e];
+                if (val != 0.0) unsafeAtomicAdd(&a.dG[L.edge[s][e]], a.qw * val);
+            } else if (a.rho) {
+                const int u = t - cnt * 6, s = u >> 2, k = u & 3;
+                const double val = L.racc[s][k];
+                if (val != 0.0) unsafeAtomicAdd(&a.rho[L.vert[s][k]], a.qw * val);
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------------------ vertex charge
 __global__ void __launch_bounds__(kBlock) k_charge(int64_t n, int64_t nt, const double *__restrict__ lam1,
                                                    const double *__restrict__ lam2, const double *__restrict__ lam3,
                                                    const int32_t *__restrict__ tet, const TetTopo *__restrict__ topo,
                                                    double qw, double *__restrict__ rho, unsigned *status) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const int T = tet[p];
-    if ((unsigned)T >= (unsigned)nt) {
-        atomicOr(status, (unsigned)ETPIC_DEV_BADTET);
-        return;
+    int T = -1;
+    double l[4] = {0.0, 0.0, 0.0, 0.0};
+    if (p < n) {
+        T = tet[p];
+        if ((unsigned)T >= (unsigned)nt) {
+            atomicOr(status, (unsigned)ETPIC_DEV_BADTET);
+            T = -1;
+        } else {
+            l[1] = lam1[p];
+            l[2] = lam2[p];
+            l[3] = lam3[p];
+            l[0] = 1.0 - l[1] - l[2] - l[3];
+        }
     }
-    const double l1 = lam1[p], l2 = lam2[p], l3 = lam3[p];
-    const double l0 = 1.0 - l1 - l2 - l3;
-    const TetTopo tp = topo[T];
-    unsafeAtomicAdd(&rho[tp.v[0]], qw * l0);
-    unsafeAtomicAdd(&rho[tp.v[1]], qw * l1);
-    unsafeAtomicAdd(&rho[tp.v[2]], qw * l2);
-    unsafeAtomicAdd(&rho[tp.v[3]], qw * l3);
+    const WaveRuns r = wave_runs(T);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) l[k] = run_total(l[k], r);
+    if (r.head && T >= 0) {
+        const TetTopo tp = topo[T];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) unsafeAtomicAdd(&rho[tp.v[k]], qw * l[k]);
+    }
 }
 
 // ------------------------------------------------------------------ continuity residual
@@ -373,13 +692,16 @@ __global__ void __launch_bounds__(kBlock) k_fill_u32(unsigned *__restrict__ x, i
 __global__ void __launch_bounds__(kBlock) k_hist(int64_t n, int64_t nt, const int32_t *__restrict__ tet,
                                                  unsigned *__restrict__ count, unsigned *status) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const int T = tet[p];
-    if ((unsigned)T >= (unsigned)nt) {
-        atomicOr(status, (unsigned)ETPIC_DEV_BADTET);
-        return;
+    int T = -1;
+    if (p < n) {
+        T = tet[p];
+        if ((unsigned)T >= (unsigned)nt) {
+            atomicOr(status, (unsigned)ETPIC_DEV_BADTET);
+            T = -1;
+        }
     }
-    atomicAdd(&count[T], 1u);
+    const WaveRuns r = wave_runs(T);
+    if (r.head && T >= 0) atomicAdd(&count[T], (unsigned)(r.run_end - r.lane + 1));
 }
 
 constexpr int kScanTile = 1024;   // elements per block in the block-local scan (4 per thread)
@@ -451,10 +773,18 @@ __global__ void __launch_bounds__(kBlock) k_scatter(int64_t n, int64_t nt, const
                                                     unsigned *__restrict__ cursor, etpic_particles src,
                                                     etpic_particles dst) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const int T = tet[p];
-    if ((unsigned)T >= (unsigned)nt) return;
-    const unsigned q = atomicAdd(&cursor[T], 1u);
+    int T = -1;
+    if (p < n) {
+        T = tet[p];
+        if ((unsigned)T >= (unsigned)nt) T = -1;
+    }
+    // one cursor atomic per run of equal tet; lanes of a run keep their order
+    const WaveRuns r = wave_runs(T);
+    unsigned base = 0;
+    if (r.head && T >= 0) base = atomicAdd(&cursor[T], (unsigned)(r.run_end - r.lane + 1));
+    base = __shfl(base, r.head_lane);
+    if (T < 0) return;
+    const unsigned q = base + (unsigned)(r.lane - r.head_lane);
     dst.tet[q] = T;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -501,6 +831,59 @@ struct etpic_ctx {
         return ETPIC_OK;
     }
 
+    template <typename Real>
+    int launch_step(const etpic_particles *p, const etpic_species *sp, const etpic_fields *f, double c, double s,
+                    double h, double dt, double *dG, double *rho, uint32_t flags, void *stream) {
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        const int64_t nt = host.nt;
+        StepArgs<Real> a{};
+        a.n = p->n;
+        a.nt = nt;
+        a.lam1 = p->lam[0];
+        a.lam2 = p->lam[1];
+        a.lam3 = p->lam[2];
+        a.v0 = static_cast<Real *>(p->vel[0]);
+        a.v1 = static_cast<Real *>(p->vel[1]);
+        a.v2 = static_cast<Real *>(p->vel[2]);
+        a.tet = p->tet;
+        a.coef = static_cast<const Real *>(d_coef);
+        a.grad_r = grad_table<Real>();
+        a.grad = d_grad64;
+        a.topo = d_topo;
+        a.dG = dG;
+        a.rho = rho;
+        a.status = d_status;
+        a.qw = sp->q * sp->w;
+        a.h = (Real)h;
+        a.dt_r = (Real)dt;
+        const bool unstaged = flags & ETPIC_STEP_UNSTAGED;
+        if (unstaged) {
+            k_tet_coef<Real><<<grid_for(nt), kBlock, 0, st>>>(nt, d_topo, d_grad64,
+                                                              reinterpret_cast<const double2 *>(f->e_env), f->e_dc,
+                                                              reinterpret_cast<const double2 *>(f->b_env), f->b_dc, c,
+                                                              s, static_cast<Real *>(d_coef));
+            HIP_TRY(hipGetLastError());
+        }
+        hipEvent_t ev0 = nullptr, ev1 = nullptr;
+        if (flags & ETPIC_STEP_TIMING) {
+            if (int r = timing_pair(&ev0, &ev1)) return r;
+            HIP_TRY(hipEventRecord(ev0, st));
+        }
+        if (unstaged) {
+            k_gpd<Real><<<grid_for(p->n), kBlock, 0, st>>>(a);
+        } else {
+            FieldPtrs F{reinterpret_cast<const double2 *>(f->e_env), f->e_dc,
+                        reinterpret_cast<const double2 *>(f->b_env), f->b_dc, c, s};
+            k_step<Real><<<grid_for(p->n), kBlock, 0, st>>>(a, F, (flags & ETPIC_STEP_XCD_REMAP) ? 1 : 0);
+        }
+        HIP_TRY(hipGetLastError());
+        if (ev1) HIP_TRY(hipEventRecord(ev1, st));
+        return ETPIC_OK;
+    }
+
+    template <typename Real>
+    const Real *grad_table() const;
+
     void release() {
         (void)hipFree(d_topo);
         (void)hipFree(d_grad64);
@@ -519,6 +902,11 @@ struct etpic_ctx {
         has_mesh = false;
     }
 };
+
+template <>
+const double *etpic_ctx::grad_table<double>() const { return d_grad64; }
+template <>
+const float *etpic_ctx::grad_table<float>() const { return d_grad32; }
 
 namespace {
 
@@ -663,7 +1051,6 @@ int etpic_mesh_faces(const etpic_ctx *ctx, int32_t *face_vert_host) {
 int etpic_gather_push_deposit(etpic_ctx *ctx, const etpic_particles *p, int precision, const etpic_species *sp,
                               const etpic_fields *f, int64_t step, double dt, double omega, double *dG,
                               double *rho, uint32_t flags, void *stream) {
-    (void)flags;
     if (!ctx || !sp || !f || !dG) return fail(ETPIC_EINVAL, "null argument");
     if (!ctx->has_mesh) return fail(ETPIC_ESTATE, "no mesh uploaded");
     if (int r = check_particles(ctx, p)) return r;
@@ -671,84 +1058,14 @@ int etpic_gather_push_deposit(etpic_ctx *ctx, const etpic_particles *p, int prec
     if (precision != ETPIC_FP64 && precision != ETPIC_MIXED) return fail(ETPIC_EINVAL, "bad precision %d", precision);
     if (!(std::isfinite(dt) && std::isfinite(omega) && sp->m != 0.0 && std::isfinite(sp->q) && std::isfinite(sp->m)))
         return fail(ETPIC_EINVAL, "non-finite dt / omega or zero mass");
+    if (p->n == 0) return ETPIC_OK;
     if (int r = set_device(ctx)) return r;
-    hipStream_t st = static_cast<hipStream_t>(stream);
     // carrier phase in float64 on the host (t_n = step*dt), argument reduced by libm
     const double t = (double)step * dt;
     const double c = std::cos(omega * t), s = std::sin(omega * t);
-    const int64_t nt = ctx->host.nt;
     const double h = sp->q * dt / (2.0 * sp->m);
-    if (precision == ETPIC_FP64) {
-        k_tet_coef<double><<<grid_for(nt), kBlock, 0, st>>>(nt, ctx->d_topo, ctx->d_grad64,
-                                                            reinterpret_cast<const double2 *>(f->e_env), f->e_dc,
-                                                            reinterpret_cast<const double2 *>(f->b_env), f->b_dc, c,
-                                                            s, static_cast<double *>(ctx->d_coef));
-        HIP_TRY(hipGetLastError());
-        if (p->n == 0) return ETPIC_OK;
-        StepArgs<double> a{};
-        a.n = p->n;
-        a.nt = nt;
-        a.lam1 = p->lam[0];
-        a.lam2 = p->lam[1];
-        a.lam3 = p->lam[2];
-        a.v0 = static_cast<double *>(p->vel[0]);
-        a.v1 = static_cast<double *>(p->vel[1]);
-        a.v2 = static_cast<double *>(p->vel[2]);
-        a.tet = p->tet;
-        a.coef = static_cast<const double *>(ctx->d_coef);
-        a.grad_r = ctx->d_grad64;
-        a.grad = ctx->d_grad64;
-        a.topo = ctx->d_topo;
-        a.dG = dG;
-        a.rho = rho;
-        a.status = ctx->d_status;
-        a.qw = sp->q * sp->w;
-        a.h = h;
-        a.dt_r = dt;
-        hipEvent_t ev0 = nullptr, ev1 = nullptr;
-        if (flags & ETPIC_STEP_TIMING) {
-            if (int r = ctx->timing_pair(&ev0, &ev1)) return r;
-            HIP_TRY(hipEventRecord(ev0, st));
-        }
-        k_gpd<double><<<grid_for(p->n), kBlock, 0, st>>>(a);
-        if (ev1) HIP_TRY(hipEventRecord(ev1, st));
-    } else {
-        k_tet_coef<float><<<grid_for(nt), kBlock, 0, st>>>(nt, ctx->d_topo, ctx->d_grad64,
-                                                           reinterpret_cast<const double2 *>(f->e_env), f->e_dc,
-                                                           reinterpret_cast<const double2 *>(f->b_env), f->b_dc, c, s,
-                                                           static_cast<float *>(ctx->d_coef));
-        HIP_TRY(hipGetLastError());
-        if (p->n == 0) return ETPIC_OK;
-        StepArgs<float> a{};
-        a.n = p->n;
-        a.nt = nt;
-        a.lam1 = p->lam[0];
-        a.lam2 = p->lam[1];
-        a.lam3 = p->lam[2];
-        a.v0 = static_cast<float *>(p->vel[0]);
-        a.v1 = static_cast<float *>(p->vel[1]);
-        a.v2 = static_cast<float *>(p->vel[2]);
-        a.tet = p->tet;
-        a.coef = static_cast<const float *>(ctx->d_coef);
-        a.grad_r = ctx->d_grad32;
-        a.grad = ctx->d_grad64;
-        a.topo = ctx->d_topo;
-        a.dG = dG;
-        a.rho = rho;
-        a.status = ctx->d_status;
-        a.qw = sp->q * sp->w;
-        a.h = (float)h;
-        a.dt_r = (float)dt;
-        hipEvent_t ev0 = nullptr, ev1 = nullptr;
-        if (flags & ETPIC_STEP_TIMING) {
-            if (int r = ctx->timing_pair(&ev0, &ev1)) return r;
-            HIP_TRY(hipEventRecord(ev0, st));
-        }
-        k_gpd<float><<<grid_for(p->n), kBlock, 0, st>>>(a);
-        if (ev1) HIP_TRY(hipEventRecord(ev1, st));
-    }
-    HIP_TRY(hipGetLastError());
-    return ETPIC_OK;
+    if (precision == ETPIC_FP64) return ctx->launch_step<double>(p, sp, f, c, s, h, dt, dG, rho, flags, stream);
+    return ctx->launch_step<float>(p, sp, f, c, s, h, dt, dG, rho, flags, stream);
 }
 
 int etpic_vertex_charge(etpic_ctx *ctx, const etpic_particles *p, const etpic_species *sp, double *rho,

@@ -64,3 +64,15 @@ def test_no_cpu_fallback_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(etpic, "_lib", None)
     with pytest.raises(RuntimeError):
         etpic.lib()
+
+
+def test_binding_constants_match_header():
+    """Every ETPIC_* enum value of the header has the same value in the binding."""
+    txt = open(os.path.join(ROOT, "include", "etpic.h")).read()
+    vals = dict((k, int(v.rstrip("u"))) for k, v in re.findall(r"\bETPIC_([A-Z0-9_]+)\s*=\s*(-?\d+u?)", txt))
+    assert len(vals) >= 15
+    alias = {"DEV_HOPCAP": "DEV_HOPCAP", "HOP_CAP": "HOP_CAP"}
+    for k, v in vals.items():
+        name = alias.get(k, k.replace("STEP_", "STEP_"))
+        assert getattr(etpic, name) == v, k
+    assert etpic.HOP_CAP == int(re.search(r"ETPIC_HOP_CAP\s+(\d+)", txt).group(1))

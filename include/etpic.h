@@ -37,7 +37,9 @@
  * message is available from etpic_last_error() (thread-local).  Errors found
  * inside kernels (walk hop cap, NaN) set bits in a device status word that
  * etpic_check() reads.  No C++ exception crosses this boundary.  A context is
- * not thread-safe: use one context per host thread.
+ * not thread-safe: use one context per host thread, and order the calls made
+ * on one context (same stream, or synchronise between streams): its step
+ * calls share a small device work queue.
  * `stream` is a hipStream_t passed as void* (NULL = default stream).
  */
 #ifndef ETPIC_H
@@ -78,16 +80,14 @@ enum etpic_device_flags {
 /* flags of etpic_gather_push_deposit */
 enum etpic_step_flags {
     ETPIC_STEP_XCD_REMAP = 1u, /* map consecutive particle blocks to one XCD (default on) */
-    ETPIC_STEP_TIMING = 2u,    /* bracket the particle kernel with HIP events (etpic_kernel_time) */
-    ETPIC_STEP_UNSTAGED = 4u   /* per-tet coefficient table in HBM + one-lane-per-particle kernel with
-                                  direct atomics, instead of the fused LDS-staged kernel (comparison) */
+    ETPIC_STEP_TIMING = 2u     /* bracket the particle kernel with HIP events (etpic_kernel_time) */
 };
 
 #define ETPIC_HOP_CAP 64
 
 typedef struct etpic_ctx etpic_ctx;
 
-/* Particle state, structure of arrays on the device, length n each.
+/* Particle state, structure of arrays on the device, length n each (n <= 2^30).
  * lam[k]: float64 barycentric lam_{k+1} in the particle's tet.
  * vel[k]: velocity component k at the half step (v^{n-1/2} in, v^{n+1/2} out);
  *         float64 for ETPIC_FP64, float32 for ETPIC_MIXED.

@@ -6,9 +6,11 @@
 //                 B(x) = sum_i lam_i C_i inside a tet (both expansions are affine
 //                 in lam), where A_i, C_i fold the real parts Re{dof e^{jwt}} + dc
 //                 of the 6 edge and 4 face DoFs into the gradients.
-//   k_gpd         per particle: gather, Boris push, barycentric walk, path
-//                 integral deposit onto edges (float64 atomics), optional
-//                 vertex charge.
+//   k_step        per particle, tet-sorted: per-tet coefficients staged in LDS,
+//                 gather, Boris push, in-tet path-integral deposit reduced
+//                 over runs of equal tet (wave) and slots (LDS), float64
+//                 atomics; particles leaving their tet are queued.
+//   k_walk        the queued particles: barycentric walk, reflection, deposit.
 //   k_hist/k_scan*/k_scatter   counting sort by tet.
 //   k_charge      vertex charge of the particles.
 //   k_gauss       continuity residual D^T dG - (rho_new - rho_old).
@@ -47,6 +49,8 @@ int fail(int code, const char *fmt, ...) {
     } while (0)
 
 constexpr int kBlock = 256;
+constexpr unsigned kWalkQueueCap = 1u << 22;  // blocks; bounds N_p by 2^30
+constexpr unsigned kWalkBlocks = 1024;        // grid of the walk kernel
 
 // Runs of equal key among the 64 lanes of a wavefront (particles are kept
 // sorted by tet, so neighbouring lanes mostly share a key).  head: first lane
@@ -156,17 +160,23 @@ struct StepArgs {
     double *lam1, *lam2, *lam3;
     Real *v0, *v1, *v2;
     int32_t *tet;
-    const Real *coef;          // nt*24
-    const Real *grad_r;        // nt*12 in Real
-    const double *grad;        // nt*12 float64
+    const double *grad;        // nt*12 float64 barycentric gradients
     const TetTopo *topo;
     double *dG;
     double *rho;
     unsigned *status;
+    unsigned *walk_queue;      // blocks holding particles that left their tet
+    unsigned *walk_ctr;        // [0] queue length, [1] walk blocks done
     double qw;
     Real h;                    // q dt / (2 m)
     Real dt_r;
 };
+
+// A particle that leaves its tet is marked in place (tet = -(T + 2)) by the
+// step kernel, which keeps its start barycentrics and stores its new velocity;
+// the block's index goes to the walk queue.  k_walk then walks it.
+__device__ __forceinline__ int walker_mark(int T) { return -(T + 2); }
+__device__ __forceinline__ int walker_tet(int marked) { return -marked - 2; }
 
 // q w * path integral of the six edge functions along one straight piece inside
 // a tet: with lam linear along the piece, int W1_ij . dr = m_i dl_j - m_j dl_i,
@@ -190,7 +200,7 @@ __device__ __forceinline__ void deposit_piece(double *__restrict__ dG, const Tet
 // handed to the neighbour's shared vertices; at a boundary face the remaining
 // displacement and the velocity are reflected about the face normal.
 template <typename Real>
-__device__ __noinline__ int walk(const StepArgs<Real> &a, int T, double l[4], double d[3], Real v[3]) {
+__device__ __forceinline__ int walk(const StepArgs<Real> &a, int T, double l[4], double d[3], Real v[3]) {
     int hops = 0;
     for (;;) {
         const double *gp = a.grad + (int64_t)T * 12;
@@ -216,6 +226,17 @@ __device__ __noinline__ int walk(const StepArgs<Real> &a, int T, double l[4], do
             }
         }
         const TetTopo tp = a.topo[T];
+        // values at the exit face, selected without dynamic register indexing
+        double gx = 0.0, gy = 0.0, gz = 0.0;
+        int nb = -1;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (k == kmin) {
+                gx = g[k][0];
+                gy = g[k][1];
+                gz = g[k][2];
+                nb = tp.n[k];
+            }
         if (kmin < 0) {
             deposit_piece(a.dG, tp, l, dl, a.qw);
 #pragma unroll
@@ -236,10 +257,9 @@ __device__ __noinline__ int walk(const StepArgs<Real> &a, int T, double l[4], do
         for (int k = 0; k < 4; ++k) lc[k] /= sum;
 #pragma unroll
         for (int c = 0; c < 3; ++c) d[c] -= smin * d[c];
-        const int nb = tp.n[kmin];
         if (nb < 0) {
-            double nn = sqrt(g[kmin][0] * g[kmin][0] + g[kmin][1] * g[kmin][1] + g[kmin][2] * g[kmin][2]);
-            double nh[3] = {g[kmin][0] / nn, g[kmin][1] / nn, g[kmin][2] / nn};
+            const double nn = sqrt(gx * gx + gy * gy + gz * gz);
+            const double nh[3] = {gx / nn, gy / nn, gz / nn};
             double dd = d[0] * nh[0] + d[1] * nh[1] + d[2] * nh[2];
             Real vv = v[0] * (Real)nh[0] + v[1] * (Real)nh[1] + v[2] * (Real)nh[2];
 #pragma unroll
@@ -267,85 +287,6 @@ __device__ __noinline__ int walk(const StepArgs<Real> &a, int T, double l[4], do
         }
     }
     return T;
-}
-
-template <typename Real>
-__global__ void __launch_bounds__(kBlock) k_gpd(StepArgs<Real> a) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= a.n) return;
-    int T = a.tet[p];
-    if ((unsigned)T >= (unsigned)a.nt) {
-        atomicOr(a.status, (unsigned)ETPIC_DEV_BADTET);
-        return;
-    }
-    double l[4];
-    l[1] = a.lam1[p];
-    l[2] = a.lam2[p];
-    l[3] = a.lam3[p];
-    l[0] = 1.0 - l[1] - l[2] - l[3];
-    Real v[3] = {a.v0[p], a.v1[p], a.v2[p]};
-    // gather: E = sum_k lam_k A_k, B = sum_k lam_k C_k
-    const Real *cf = a.coef + (int64_t)T * 24;
-    Real E[3], B[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        E[d] = (Real)l[0] * cf[d] + (Real)l[1] * cf[3 + d] + (Real)l[2] * cf[6 + d] + (Real)l[3] * cf[9 + d];
-        B[d] = (Real)l[0] * cf[12 + d] + (Real)l[1] * cf[15 + d] + (Real)l[2] * cf[18 + d] + (Real)l[3] * cf[21 + d];
-    }
-    // Boris: half kick, rotation (implicit midpoint in v x B), half kick
-    const Real h = a.h;
-    Real vm[3], tau[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        vm[d] = v[d] + h * E[d];
-        tau[d] = h * B[d];
-    }
-    const Real t2 = tau[0] * tau[0] + tau[1] * tau[1] + tau[2] * tau[2];
-    const Real sg = (Real)2 / ((Real)1 + t2);
-    Real vr[3] = {vm[0] + (vm[1] * tau[2] - vm[2] * tau[1]), vm[1] + (vm[2] * tau[0] - vm[0] * tau[2]),
-                  vm[2] + (vm[0] * tau[1] - vm[1] * tau[0])};
-    Real vp[3] = {vm[0] + sg * (vr[1] * tau[2] - vr[2] * tau[1]), vm[1] + sg * (vr[2] * tau[0] - vr[0] * tau[2]),
-                  vm[2] + sg * (vr[0] * tau[1] - vr[1] * tau[0])};
-#pragma unroll
-    for (int d = 0; d < 3; ++d) v[d] = vp[d] + h * E[d];
-    if (!(isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]))) atomicOr(a.status, (unsigned)ETPIC_DEV_NAN);
-    // displacement and barycentric increments in the home tet
-    Real dx[3] = {a.dt_r * v[0], a.dt_r * v[1], a.dt_r * v[2]};
-    const Real *gr = a.grad_r + (int64_t)T * 12;
-    // lam0 is stored implicitly (1 - lam1 - lam2 - lam3), so its increment is taken
-    // as minus the sum of the other three, in float64: the deposit and the stored
-    // end point then see the same four increments (continuity to float64 rounding).
-    double dl[4];
-#pragma unroll
-    for (int k = 1; k < 4; ++k) dl[k] = (double)(gr[3 * k] * dx[0] + gr[3 * k + 1] * dx[1] + gr[3 * k + 2] * dx[2]);
-    dl[0] = -(dl[1] + dl[2] + dl[3]);
-    bool stays = true;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) stays = stays && (l[k] + dl[k] >= 0.0);
-    if (stays) {
-        const TetTopo tp = a.topo[T];
-        deposit_piece(a.dG, tp, l, dl, a.qw);
-#pragma unroll
-        for (int k = 1; k < 4; ++k) l[k] += dl[k];
-    } else {
-        double d[3] = {(double)dx[0], (double)dx[1], (double)dx[2]};
-        T = walk<Real>(a, T, l, d, v);
-        a.tet[p] = T;
-    }
-    a.lam1[p] = l[1];
-    a.lam2[p] = l[2];
-    a.lam3[p] = l[3];
-    a.v0[p] = v[0];
-    a.v1[p] = v[1];
-    a.v2[p] = v[2];
-    if (a.rho) {
-        const TetTopo tp = a.topo[T];
-        const double l0 = 1.0 - l[1] - l[2] - l[3];
-        unsafeAtomicAdd(&a.rho[tp.v[0]], a.qw * l0);
-        unsafeAtomicAdd(&a.rho[tp.v[1]], a.qw * l[1]);
-        unsafeAtomicAdd(&a.rho[tp.v[2]], a.qw * l[2]);
-        unsafeAtomicAdd(&a.rho[tp.v[3]], a.qw * l[3]);
-    }
 }
 
 // ------------------------------------------------------------------ fused staged step
@@ -385,6 +326,60 @@ struct FieldPtrs {
 // local edge index of the vertex pair {i, j}, i < j
 __device__ __forceinline__ int local_edge(int i, int j) { return i == 0 ? j - 1 : (i == 1 ? j + 1 : 5); }
 
+template <int K, typename Real>
+__device__ __forceinline__ void stage_A(StageLds<Real> &L, int s, const int32_t *tp, const double g[4][3],
+                                        const FieldPtrs &F) {
+    double A[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (j == K) continue;
+        const int id = tp[local_edge(j < K ? j : K, j < K ? K : j)];
+        const double2 z = F.e_env[id];
+        double eps = z.x * F.c - z.y * F.s;
+        if (F.e_dc) eps += F.e_dc[id];
+        if (j < K) eps = -eps;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) A[d] += eps * g[j][d];
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) L.coef[s][3 * K + d] = (Real)A[d];
+    if (K < 3) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) L.grad[s][3 * K + d] = (Real)g[K + 1][d];
+    } else {
+#pragma unroll
+        for (int e = 0; e < 6; ++e) L.edge[s][e] = tp[e];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) L.vert[s][v] = tp[10 + v];
+    }
+    L.racc[s][K] = 0.0;
+    L.acc[s][K] = 0.0;
+}
+
+template <int K, typename Real>
+__device__ __forceinline__ void stage_C(StageLds<Real> &L, int s, const int32_t *tp, const double g[4][3],
+                                        const FieldPtrs &F) {
+    double Cv[3] = {0.0, 0.0, 0.0};
+    constexpr int lf[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        if (f == K) continue;
+        const int a = lf[f][0] == K ? lf[f][1] : (lf[f][1] == K ? lf[f][2] : lf[f][0]);
+        const int b = lf[f][0] == K ? lf[f][2] : (lf[f][1] == K ? lf[f][0] : lf[f][1]);
+        const int id = tp[6 + f];
+        const double2 z = F.b_env[id];
+        double beta = z.x * F.c - z.y * F.s;
+        if (F.b_dc) beta += F.b_dc[id];
+        beta *= 2.0;
+        Cv[0] += beta * (g[a][1] * g[b][2] - g[a][2] * g[b][1]);
+        Cv[1] += beta * (g[a][2] * g[b][0] - g[a][0] * g[b][2]);
+        Cv[2] += beta * (g[a][0] * g[b][1] - g[a][1] * g[b][0]);
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) L.coef[s][12 + 3 * K + d] = (Real)Cv[d];
+    if (K < 2) L.acc[s][4 + K] = 0.0;
+}
+
 // Part `part` (0..7) of the coefficients of tet T into slot s:
 //   part k < 4 : A_k = sum_{j != k} sign(j - k) eps_{kj} grad l_j   (E = sum_k l_k A_k)
 //   part 4 + k : C_k = 2 sum_{faces f containing k} beta_f (grad l_a x grad l_b),
@@ -400,56 +395,15 @@ __device__ __forceinline__ void stage_part(StageLds<Real> &L, int s, int part, i
 #pragma unroll
         for (int d = 0; d < 3; ++d) g[k][d] = gp[3 * k + d];
     const int32_t *tp = reinterpret_cast<const int32_t *>(topo + T);
-    if (part < 4) {
-        const int k = part;
-        double A[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            if (j == k) continue;
-            const int id = tp[local_edge(min(j, k), max(j, k))];
-            const double2 z = F.e_env[id];
-            double eps = z.x * F.c - z.y * F.s;
-            if (F.e_dc) eps += F.e_dc[id];
-            if (j < k) eps = -eps;
-#pragma unroll
-            for (int d = 0; d < 3; ++d) A[d] += eps * g[j][d];
-        }
-#pragma unroll
-        for (int d = 0; d < 3; ++d) L.coef[s][3 * k + d] = (Real)A[d];
-        if (k < 3) {
-#pragma unroll
-            for (int d = 0; d < 3; ++d) L.grad[s][3 * k + d] = (Real)g[k + 1][d];
-        } else {
-#pragma unroll
-            for (int e = 0; e < 6; ++e) L.edge[s][e] = tp[e];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) L.vert[s][v] = tp[10 + v];
-        }
-        L.racc[s][k] = 0.0;
-        L.acc[s][k] = 0.0;
-    } else {
-        const int k = part - 4;
-        double Cv[3] = {0.0, 0.0, 0.0};
-        const int lf[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
-#pragma unroll
-        for (int f = 0; f < 4; ++f) {
-            if (f == k) continue;
-            int a, b;
-            if (lf[f][0] == k) { a = lf[f][1]; b = lf[f][2]; }
-            else if (lf[f][1] == k) { a = lf[f][2]; b = lf[f][0]; }
-            else { a = lf[f][0]; b = lf[f][1]; }
-            const int id = tp[6 + f];
-            const double2 z = F.b_env[id];
-            double beta = z.x * F.c - z.y * F.s;
-            if (F.b_dc) beta += F.b_dc[id];
-            beta *= 2.0;
-            Cv[0] += beta * (g[a][1] * g[b][2] - g[a][2] * g[b][1]);
-            Cv[1] += beta * (g[a][2] * g[b][0] - g[a][0] * g[b][2]);
-            Cv[2] += beta * (g[a][0] * g[b][1] - g[a][1] * g[b][0]);
-        }
-#pragma unroll
-        for (int d = 0; d < 3; ++d) L.coef[s][12 + 3 * k + d] = (Real)Cv[d];
-        if (k < 2) L.acc[s][4 + k] = 0.0;
+    switch (part) {
+        case 0: stage_A<0>(L, s, tp, g, F); break;
+        case 1: stage_A<1>(L, s, tp, g, F); break;
+        case 2: stage_A<2>(L, s, tp, g, F); break;
+        case 3: stage_A<3>(L, s, tp, g, F); break;
+        case 4: stage_C<0>(L, s, tp, g, F); break;
+        case 5: stage_C<1>(L, s, tp, g, F); break;
+        case 6: stage_C<2>(L, s, tp, g, F); break;
+        default: stage_C<3>(L, s, tp, g, F); break;
     }
 }
 
@@ -504,6 +458,7 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs<Real> a, FieldPtrs F, 
     }
     const int slot = before + incl - 1;
     const WaveRuns runs = wave_runs(act ? slot : -1);
+    int walker = 0;
     for (int lo = 0; lo < nslot; lo += kSlots) {
         const int cnt = min(kSlots, nslot - lo);
         if (head && slot >= lo && slot < lo + cnt) L.tet[slot - lo] = T;
@@ -551,7 +506,6 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs<Real> a, FieldPtrs F, 
             dl[0] = -(dl[1] + dl[2] + dl[3]);
             const bool stays = (l[0] + dl[0] >= 0.0) && (l[1] + dl[1] >= 0.0) && (l[2] + dl[2] >= 0.0) &&
                                (l[3] + dl[3] >= 0.0);
-            int Tend = T;
             if (stays) {
                 double m[4];
 #pragma unroll
@@ -561,32 +515,22 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs<Real> a, FieldPtrs F, 
                 for (int e = 0; e < 6; ++e) g6[e] = m[le[e][0]] * dl[le[e][1]] - m[le[e][1]] * dl[le[e][0]];
 #pragma unroll
                 for (int k = 1; k < 4; ++k) l[k] += dl[k];
-            } else {
-                double d[3] = {(double)dx[0], (double)dx[1], (double)dx[2]};
-                Tend = walk<Real>(a, T, l, d, v);
-                a.tet[p] = Tend;
-            }
-            a.lam1[p] = l[1];
-            a.lam2[p] = l[2];
-            a.lam3[p] = l[3];
-            a.v0[p] = v[0];
-            a.v1[p] = v[1];
-            a.v2[p] = v[2];
-            if (a.rho) {
-                const double l0 = 1.0 - l[1] - l[2] - l[3];
-                if (Tend == T) {
-                    r4[0] = l0;
+                a.lam1[p] = l[1];
+                a.lam2[p] = l[2];
+                a.lam3[p] = l[3];
+                if (a.rho) {
+                    r4[0] = 1.0 - l[1] - l[2] - l[3];
                     r4[1] = l[1];
                     r4[2] = l[2];
                     r4[3] = l[3];
-                } else {
-                    const TetTopo tp = a.topo[Tend];
-                    unsafeAtomicAdd(&a.rho[tp.v[0]], a.qw * l0);
-                    unsafeAtomicAdd(&a.rho[tp.v[1]], a.qw * l[1]);
-                    unsafeAtomicAdd(&a.rho[tp.v[2]], a.qw * l[2]);
-                    unsafeAtomicAdd(&a.rho[tp.v[3]], a.qw * l[3]);
                 }
+            } else {
+                a.tet[p] = walker_mark(T);
+                walker = 1;
             }
+            a.v0[p] = v[0];
+            a.v1[p] = v[1];
+            a.v2[p] = v[2];
         }
         // wave-level segmented reduction over runs of equal slot, then one LDS
         // atomic per (run, edge) from the run's head lane
@@ -618,6 +562,56 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs<Real> a, FieldPtrs F, 
             }
         }
         __syncthreads();
+    }
+    if (__syncthreads_or(walker) && tid == 0) a.walk_queue[atomicAdd(&a.walk_ctr[0], 1u)] = blk;
+}
+
+// Walks the marked particles of the queued blocks: every piece of their path
+// is deposited with global atomics, and the end point, reflected velocity and
+// new tet are stored.  Blocks stride over the queue; the last block to finish
+// resets the counters for the next step.
+template <typename Real>
+__global__ void __launch_bounds__(kBlock) k_walk(StepArgs<Real> a) {
+    const unsigned count = __atomic_load_n(&a.walk_ctr[0], __ATOMIC_RELAXED);
+    for (unsigned i = blockIdx.x; i < count; i += gridDim.x) {
+        const int64_t p = (int64_t)a.walk_queue[i] * kBlock + threadIdx.x;
+        if (p >= a.n) continue;
+        const int marked = a.tet[p];
+        if (marked > -2) continue;
+        int T = walker_tet(marked);
+        if (T >= a.nt) continue;
+        double l[4];
+        l[1] = a.lam1[p];
+        l[2] = a.lam2[p];
+        l[3] = a.lam3[p];
+        l[0] = 1.0 - l[1] - l[2] - l[3];
+        Real v[3] = {a.v0[p], a.v1[p], a.v2[p]};
+        const Real dx[3] = {a.dt_r * v[0], a.dt_r * v[1], a.dt_r * v[2]};
+        double d[3] = {(double)dx[0], (double)dx[1], (double)dx[2]};
+        T = walk<Real>(a, T, l, d, v);
+        a.tet[p] = T;
+        a.lam1[p] = l[1];
+        a.lam2[p] = l[2];
+        a.lam3[p] = l[3];
+        a.v0[p] = v[0];
+        a.v1[p] = v[1];
+        a.v2[p] = v[2];
+        if (a.rho) {
+            const TetTopo tp = a.topo[T];
+            const double l0 = 1.0 - l[1] - l[2] - l[3];
+            unsafeAtomicAdd(&a.rho[tp.v[0]], a.qw * l0);
+            unsafeAtomicAdd(&a.rho[tp.v[1]], a.qw * l[1]);
+            unsafeAtomicAdd(&a.rho[tp.v[2]], a.qw * l[2]);
+            unsafeAtomicAdd(&a.rho[tp.v[3]], a.qw * l[3]);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&a.walk_ctr[1], 1u) == gridDim.x - 1) {
+            a.walk_ctr[0] = 0u;
+            a.walk_ctr[1] = 0u;
+        }
     }
 }
 
@@ -805,11 +799,12 @@ struct etpic_ctx {
     bool has_mesh = false;
     TetTopo *d_topo = nullptr;
     double *d_grad64 = nullptr;
-    float *d_grad32 = nullptr;
     void *d_coef = nullptr;          // nt*24 doubles (float table uses the first half)
     int32_t *d_v2e_ptr = nullptr;
     int32_t *d_v2e_code = nullptr;
     unsigned *d_status = nullptr;    // device status word
+    unsigned *d_walk_queue = nullptr;  // kWalkQueueCap block indices
+    unsigned *d_walk_ctr = nullptr;    // 2 counters of the walk queue
     unsigned long long *d_red = nullptr;  // 2 words for the residual maxima
     unsigned *d_count = nullptr;     // nt+1 counting-sort counters
     unsigned *d_tilesum = nullptr;   // scan tile totals
@@ -846,48 +841,35 @@ struct etpic_ctx {
         a.v1 = static_cast<Real *>(p->vel[1]);
         a.v2 = static_cast<Real *>(p->vel[2]);
         a.tet = p->tet;
-        a.coef = static_cast<const Real *>(d_coef);
-        a.grad_r = grad_table<Real>();
         a.grad = d_grad64;
         a.topo = d_topo;
         a.dG = dG;
         a.rho = rho;
         a.status = d_status;
+        a.walk_queue = d_walk_queue;
+        a.walk_ctr = d_walk_ctr;
         a.qw = sp->q * sp->w;
         a.h = (Real)h;
         a.dt_r = (Real)dt;
-        const bool unstaged = flags & ETPIC_STEP_UNSTAGED;
-        if (unstaged) {
-            k_tet_coef<Real><<<grid_for(nt), kBlock, 0, st>>>(nt, d_topo, d_grad64,
-                                                              reinterpret_cast<const double2 *>(f->e_env), f->e_dc,
-                                                              reinterpret_cast<const double2 *>(f->b_env), f->b_dc, c,
-                                                              s, static_cast<Real *>(d_coef));
-            HIP_TRY(hipGetLastError());
-        }
         hipEvent_t ev0 = nullptr, ev1 = nullptr;
         if (flags & ETPIC_STEP_TIMING) {
             if (int r = timing_pair(&ev0, &ev1)) return r;
             HIP_TRY(hipEventRecord(ev0, st));
         }
-        if (unstaged) {
-            k_gpd<Real><<<grid_for(p->n), kBlock, 0, st>>>(a);
-        } else {
-            FieldPtrs F{reinterpret_cast<const double2 *>(f->e_env), f->e_dc,
-                        reinterpret_cast<const double2 *>(f->b_env), f->b_dc, c, s};
-            k_step<Real><<<grid_for(p->n), kBlock, 0, st>>>(a, F, (flags & ETPIC_STEP_XCD_REMAP) ? 1 : 0);
-        }
+        FieldPtrs F{reinterpret_cast<const double2 *>(f->e_env), f->e_dc, reinterpret_cast<const double2 *>(f->b_env),
+                    f->b_dc, c, s};
+        k_step<Real><<<grid_for(p->n), kBlock, 0, st>>>(a, F, (flags & ETPIC_STEP_XCD_REMAP) ? 1 : 0);
         HIP_TRY(hipGetLastError());
         if (ev1) HIP_TRY(hipEventRecord(ev1, st));
+        k_walk<Real><<<kWalkBlocks, kBlock, 0, st>>>(a);
+        HIP_TRY(hipGetLastError());
         return ETPIC_OK;
     }
 
-    template <typename Real>
-    const Real *grad_table() const;
 
     void release() {
         (void)hipFree(d_topo);
         (void)hipFree(d_grad64);
-        (void)hipFree(d_grad32);
         (void)hipFree(d_coef);
         (void)hipFree(d_v2e_ptr);
         (void)hipFree(d_v2e_code);
@@ -895,7 +877,6 @@ struct etpic_ctx {
         (void)hipFree(d_tilesum);
         d_topo = nullptr;
         d_grad64 = nullptr;
-        d_grad32 = nullptr;
         d_coef = nullptr;
         d_v2e_ptr = d_v2e_code = nullptr;
         d_count = d_tilesum = nullptr;
@@ -903,10 +884,6 @@ struct etpic_ctx {
     }
 };
 
-template <>
-const double *etpic_ctx::grad_table<double>() const { return d_grad64; }
-template <>
-const float *etpic_ctx::grad_table<float>() const { return d_grad32; }
 
 namespace {
 
@@ -918,7 +895,7 @@ int set_device(const etpic_ctx *ctx) {
 int check_particles(const etpic_ctx *ctx, const etpic_particles *p) {
     if (!p) return fail(ETPIC_EINVAL, "null particle descriptor");
     if (p->n < 0) return fail(ETPIC_EINVAL, "negative particle count");
-    if (p->n > (int64_t)UINT32_MAX) return fail(ETPIC_EINVAL, "particle count above 2^32-1");
+    if (p->n > (int64_t)kWalkQueueCap * kBlock) return fail(ETPIC_EINVAL, "particle count above 2^30");
     if (p->n == 0) return ETPIC_OK;
     for (int k = 0; k < 3; ++k)
         if (!p->lam[k] || !p->vel[k]) return fail(ETPIC_EINVAL, "null particle array");
@@ -945,10 +922,16 @@ int etpic_create(etpic_ctx **out, int device) {
     hipError_t e = hipSetDevice(device);
     if (e == hipSuccess) e = hipMalloc(&c->d_status, sizeof(unsigned));
     if (e == hipSuccess) e = hipMalloc(&c->d_red, 2 * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMalloc(&c->d_walk_queue, sizeof(unsigned) * kWalkQueueCap);
+    if (e == hipSuccess) e = hipMalloc(&c->d_walk_ctr, 2 * sizeof(unsigned));
     if (e == hipSuccess) e = hipMemset(c->d_status, 0, sizeof(unsigned));
+    if (e == hipSuccess) e = hipMemset(c->d_walk_ctr, 0, 2 * sizeof(unsigned));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         (void)hipFree(c->d_status);
         (void)hipFree(c->d_red);
+        (void)hipFree(c->d_walk_queue);
+        (void)hipFree(c->d_walk_ctr);
         delete c;
         return fail(ETPIC_EHIP, "context setup: %s", hipGetErrorString(e));
     }
@@ -963,6 +946,8 @@ int etpic_destroy(etpic_ctx *ctx) {
     ctx->release();
     (void)hipFree(ctx->d_status);
     (void)hipFree(ctx->d_red);
+    (void)hipFree(ctx->d_walk_queue);
+    (void)hipFree(ctx->d_walk_ctr);
     for (auto &e : ctx->timing) {
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
@@ -987,10 +972,8 @@ int etpic_mesh_upload(etpic_ctx *ctx, int64_t n_vert, const double *xyz_host, in
     HIP_TRY(hipDeviceSynchronize());
     ctx->release();
     const int64_t nt = M.nt;
-    std::vector<float> g32(M.grad.begin(), M.grad.end());
     HIP_TRY(hipMalloc(&ctx->d_topo, sizeof(TetTopo) * nt));
     HIP_TRY(hipMalloc(&ctx->d_grad64, sizeof(double) * 12 * nt));
-    HIP_TRY(hipMalloc(&ctx->d_grad32, sizeof(float) * 12 * nt));
     HIP_TRY(hipMalloc(&ctx->d_coef, sizeof(double) * 24 * nt));
     HIP_TRY(hipMalloc(&ctx->d_v2e_ptr, sizeof(int32_t) * (M.nv + 1)));
     HIP_TRY(hipMalloc(&ctx->d_v2e_code, sizeof(int32_t) * 2 * M.ne));
@@ -999,7 +982,6 @@ int etpic_mesh_upload(etpic_ctx *ctx, int64_t n_vert, const double *xyz_host, in
     HIP_TRY(hipMalloc(&ctx->d_tilesum, sizeof(unsigned) * ctx->tiles));
     HIP_TRY(hipMemcpy(ctx->d_topo, M.topo.data(), sizeof(TetTopo) * nt, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(ctx->d_grad64, M.grad.data(), sizeof(double) * 12 * nt, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(ctx->d_grad32, g32.data(), sizeof(float) * 12 * nt, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(ctx->d_v2e_ptr, M.v2e_ptr.data(), sizeof(int32_t) * (M.nv + 1), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(ctx->d_v2e_code, M.v2e_code.data(), sizeof(int32_t) * 2 * M.ne, hipMemcpyHostToDevice));
     ctx->host = std::move(M);

@@ -21,7 +21,6 @@ FP64, MIXED = 0, 1
 DEV_HOPCAP, DEV_NAN, DEV_BADTET = 1, 2, 4
 STEP_XCD_REMAP = 1
 STEP_TIMING = 2
-STEP_UNSTAGED = 4
 HOP_CAP = 64
 
 EXPORTS = (

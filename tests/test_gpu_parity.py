@@ -91,12 +91,11 @@ def run_case(E, torch, ora, w, steps, precision, tol, check_every=1, dt=None, fl
     return worst
 
 
-@pytest.mark.parametrize("variant", ["staged", "unstaged", "staged_no_remap"])
+@pytest.mark.parametrize("variant", ["remap", "no_remap"])
 def test_small_config_fp64_every_step(E, torch_cuda, ora, variant):
-    """1,000 electrons on the 750-tet unit cube, 100 steps, float64 form; the
-    fused LDS-staged kernel (with and without the XCD block remap) and the
-    unstaged comparison kernel."""
-    flags = {"staged": E.STEP_XCD_REMAP, "unstaged": E.STEP_UNSTAGED, "staged_no_remap": 0}[variant]
+    """1,000 electrons on the 750-tet unit cube, 100 steps, float64 form, with and
+    without the XCD block remap."""
+    flags = {"remap": E.STEP_XCD_REMAP, "no_remap": 0}[variant]
     run_case(E, torch_cuda, ora, synth.make_workload(1), 100, E.FP64, 1e-12, flags=flags)
 
 
@@ -105,13 +104,13 @@ def test_small_config_mixed(E, torch_cuda, ora):
     run_case(E, torch_cuda, ora, synth.make_workload(1), 30, E.MIXED, 2e-5)
 
 
-@pytest.mark.parametrize("precision,tol,unstaged", [(0, 1e-12, 0), (1, 2e-5, 0), (0, 1e-12, 1), (1, 2e-5, 1)])
-def test_crossing_heavy(E, torch_cuda, ora, precision, tol, unstaged):
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 2e-5)])
+def test_crossing_heavy(E, torch_cuda, ora, precision, tol):
     """Steps of 0.1-0.5 cell: most particles cross faces, several per step, and
     many hit the walls (reflection)."""
     w = synth.make_workload(1, n_particles=4000)
     w.vel = w.vel * 40.0
-    run_case(E, torch_cuda, ora, w, 12, precision, tol, dt=1e-8, flags=E.STEP_UNSTAGED if unstaged else None)
+    run_case(E, torch_cuda, ora, w, 12, precision, tol, dt=1e-8)
 
 
 @pytest.mark.parametrize("presort", [False, True])

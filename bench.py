@@ -26,14 +26,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes (what the method must move per unit):
+# Algorithmic bytes of the particle kernel (what it must move per unit):
 #  per particle-step: state read + write = 2 x (lam 3x8 + v 3x8 + tet 4) (float64 form)
 #                                         2 x (lam 3x8 + v 3x4 + tet 4) (mixed form)
-#  per tet and step : per-tet field and geometry data read once (~320 B)
+#  per tet and step : its coefficient row (24 reals), gradient row (9 reals) and
+#                     edge ids (6 x 4 B), read once: 288 B (float64), 156 B (mixed)
 #  per edge and step: the current accumulator read + written once (16 B)
 BYTES_PER_PARTICLE = {"fp64": 104, "mixed": 80}
-BYTES_PER_TET = 320
+BYTES_PER_TET = {"fp64": 288, "mixed": 156}
 BYTES_PER_EDGE = 16
+COPY_CALIB_BYTES = 1 << 30
 
 
 def log(*a):
@@ -70,7 +72,7 @@ def run_form(E, torch, ctx, w, precision, steps, warmup, sort_every, fields):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     total_ms = ev0.elapsed_time(ev1)
-    kern_ms, launches = ctx.kernel_time(reset=True)
+    kt, launches = ctx.kernel_time(reset=True)
     ctx.check()
     # sort alone
     torch.cuda.synchronize()
@@ -103,7 +105,9 @@ def run_form(E, torch, ctx, w, precision, steps, warmup, sort_every, fields):
     return {
         "ms_per_step": total_ms / steps,
         "wall_s": wall,
-        "kernel_ms": kern_ms / max(launches, 1),
+        "kernel_ms": kt["push"] / max(launches, 1),
+        "coef_ms": kt["coef"] / max(launches, 1),
+        "walk_ms": kt["walk"] / max(launches, 1),
         "launches": launches,
         "sort_ms": sort_ms,
         "gauss_rel": r / p,
@@ -138,6 +142,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--cpu-threads", type=int, default=0, help="0 = min(16, host cores)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -154,6 +160,19 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.calibrate_copy:
+        src = torch.empty(COPY_CALIB_BYTES // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        c0 = torch.cuda.Event(enable_timing=True)
+        c1 = torch.cuda.Event(enable_timing=True)
+        c0.record()
+        dst.copy_(src)
+        c1.record()
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: {COPY_CALIB_BYTES} B read + written in {c0.elapsed_time(c1):.3f} ms "
+            f"({2 * COPY_CALIB_BYTES / (c0.elapsed_time(c1) * 1e-3) / 1e9:.0f} GB/s)")
+        del src, dst
     t0 = time.perf_counter()
     w = synth.make_workload(2, n_particles=args.particles)
     log(f"[bench] workload generated in {time.perf_counter() - t0:.1f}s: N_p={w.tet.shape[0]} N_t={w.tet_vert.shape[0]}")
@@ -169,7 +188,7 @@ def main():
 
     def roofline(form):
         r = res[form]
-        bytes_launch = BYTES_PER_PARTICLE[form] * n_p + BYTES_PER_TET * n_t + BYTES_PER_EDGE * n_e
+        bytes_launch = BYTES_PER_PARTICLE[form] * n_p + BYTES_PER_TET[form] * n_t + BYTES_PER_EDGE * n_e
         ach = bytes_launch / (r["kernel_ms"] * 1e-3) / 1e9
         return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,

@@ -80,14 +80,14 @@ enum etpic_device_flags {
 /* flags of etpic_gather_push_deposit */
 enum etpic_step_flags {
     ETPIC_STEP_XCD_REMAP = 1u, /* map consecutive particle blocks to one XCD (default on) */
-    ETPIC_STEP_TIMING = 2u     /* bracket the particle kernel with HIP events (etpic_kernel_time) */
+    ETPIC_STEP_TIMING = 2u     /* bracket the step's kernels with HIP events (etpic_kernel_time) */
 };
 
 #define ETPIC_HOP_CAP 64
 
 typedef struct etpic_ctx etpic_ctx;
 
-/* Particle state, structure of arrays on the device, length n each (n <= 2^30).
+/* Particle state, structure of arrays on the device, length n each (n <= 2^29).
  * lam[k]: float64 barycentric lam_{k+1} in the particle's tet.
  * vel[k]: velocity component k at the half step (v^{n-1/2} in, v^{n+1/2} out);
  *         float64 for ETPIC_FP64, float32 for ETPIC_MIXED.
@@ -180,12 +180,46 @@ int etpic_vertex_charge(etpic_ctx *ctx, const etpic_particles *p, const etpic_sp
 int etpic_gauss_residual(etpic_ctx *ctx, const double *dG, const double *rho_new, const double *rho_old,
                          double out_host[2], void *stream);
 
-/* Time spent in the particle kernel of the steps launched with ETPIC_STEP_TIMING
- * since the last reset, measured with HIP events recorded on the launch stream
- * around that kernel alone.  Synchronises on the last recorded event.
- * total_ms_out: sum of the kernel durations; launches_out: how many; reset != 0
- * clears the record afterwards. */
-int etpic_kernel_time(etpic_ctx *ctx, double *total_ms_out, int64_t *launches_out, int reset);
+/* ---- Differentiation (float64 form only) --------------------------------
+ * Reverse-mode derivative of nsteps particle steps with respect to the
+ * complex edge envelope, for a loss of the final particle state, with step
+ * checkpointing (the state is kept every `checkpoint_every` steps and each
+ * segment is recomputed from its checkpoint during the reverse sweep).  The
+ * gradient follows the convention dL/dRe(e) + j dL/dIm(e) (the one PyTorch
+ * uses for real losses of complex tensors).  The face envelope and the dc
+ * DoFs are held fixed; the tet sequence and wall reflections of every step
+ * are those of the forward run (the step map is piecewise smooth). */
+
+/* Device workspace in bytes for n particles, nsteps steps, checkpoint_every >= 1. */
+int etpic_adjoint_workspace(const etpic_ctx *ctx, int64_t n, int nsteps, int checkpoint_every, size_t *bytes_out);
+
+/* nsteps float64 steps (times step0, step0+1, ...) of the particles p, in
+ * place, exactly as etpic_gather_push_deposit, recording the checkpoints in
+ * `workspace` (device, >= etpic_adjoint_workspace bytes).  dG (N_e)
+ * accumulates the deposit, or NULL to discard it.  Asynchronous. */
+int etpic_forward_checkpointed(etpic_ctx *ctx, const etpic_particles *p, const etpic_species *sp,
+                               const etpic_fields *f, int64_t step0, int nsteps, double dt, double omega,
+                               int checkpoint_every, void *workspace, size_t workspace_bytes, double *dG,
+                               void *stream);
+
+/* Reverse sweep of the run recorded by etpic_forward_checkpointed (same n,
+ * species, fields, step0, nsteps, dt, omega, checkpoint_every, workspace).
+ * vbar[k], xbar[k]: device float64 arrays of n.  In: adjoints of the final
+ * velocity (v^{n+1/2} after the last step) and final Cartesian position.  Out:
+ * adjoints of the initial velocity and position.  grad_e (2*N_e float64,
+ * interleaved complex) accumulates the envelope gradient.  Asynchronous. */
+int etpic_backward(etpic_ctx *ctx, int64_t n, const etpic_species *sp, const etpic_fields *f, int64_t step0,
+                   int nsteps, double dt, double omega, int checkpoint_every, void *workspace,
+                   size_t workspace_bytes, double *const vbar[3], double *const xbar[3], double *grad_e,
+                   void *stream);
+
+/* Kernel times of the steps launched with ETPIC_STEP_TIMING since the last
+ * reset, from HIP events recorded on the launch stream around each kernel:
+ * ms_out[0] = particle kernel (gather, push, in-tet deposit), ms_out[1] =
+ * per-tet coefficient kernel, ms_out[2] = walk kernel, summed over the steps.
+ * Synchronises on the last event.  *launches_out = number of timed steps;
+ * reset != 0 clears the record afterwards. */
+int etpic_kernel_time(etpic_ctx *ctx, double ms_out[3], int64_t *launches_out, int reset);
 
 /* Synchronise `stream`, return and clear the device status word in *device_flags.
  * Returns EWALK / ENAN / EPARTICLE for the first set bit, OK otherwise. */

@@ -48,6 +48,9 @@ def _load():
     lib.ora_step_one.restype = C.c_int
     lib.ora_charge.argtypes = [vp, C.c_int64, _ip, _dp, C.c_double, C.c_double, _dp]
     lib.ora_gauss.argtypes = [vp, _dp, _dp, _dp, _dp]
+    lib.ora_vjp.argtypes = [vp, C.c_int64, _ip, _dp, _dp, C.c_double, C.c_double, C.c_double, C.c_int64, C.c_int,
+                            C.c_double, C.c_double, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, C.c_int]
+    lib.ora_vjp.restype = C.c_int
     lib.ora_locate.argtypes = [vp, _dp, _dp]
     lib.ora_locate.restype = C.c_int64
     _LIB = lib
@@ -206,3 +209,26 @@ class OracleMesh:
         l0 = 1.0 - lam.sum(axis=1)
         r = self.xyz[self.tv[tet]]
         return l0[:, None] * r[:, 0] + lam[:, 0:1] * r[:, 1] + lam[:, 1:2] * r[:, 2] + lam[:, 2:3] * r[:, 3]
+
+
+def _vjp_method(self, tet, lam, vel, *, q, m, w, step0, nsteps, dt, omega, e_env, b_env, vbar, xbar=None,
+                e_dc=None, b_dc=None, nthreads=1):
+    """Reverse-mode gradient of nsteps steps from (tet, lam, vel): returns
+    (status, grad_e complex128[N_e], vbar0[N,3], xbar0[N,3]) for the given
+    adjoints vbar (final velocity) and xbar (final position, default 0)."""
+    n = tet.shape[0]
+    g = np.zeros(2 * self.ne)
+    vb0 = np.zeros((n, 3))
+    xb0 = np.zeros((n, 3))
+    ee, bb = _cplx(e_env), _cplx(b_env)
+    ed = None if e_dc is None else _f64(e_dc)
+    bd = None if b_dc is None else _f64(b_dc)
+    xb = None if xbar is None else _f64(xbar)
+    rc = _load().ora_vjp(self.h, n, _p(np.ascontiguousarray(tet, dtype=np.int32), _ip), _p(_f64(lam)),
+                         _p(_f64(vel)), float(q), float(m), float(w), int(step0), int(nsteps), float(dt), float(omega),
+                         _p(ee), _p(ed), _p(bb), _p(bd), _p(_f64(vbar)), _p(xb), _p(g), _p(vb0), _p(xb0),
+                         int(nthreads))
+    return rc, g[0::2] + 1j * g[1::2], vb0, xb0
+
+
+OracleMesh.vjp = _vjp_method

@@ -310,7 +310,8 @@ typedef struct {
 /* One fine step of one particle: gather at (x^n, t_n), Boris, walk, deposit.
  * qw_dG receives q*w*(path integrals) for every piece (6 edges per piece). */
 static void step_one(const ora_mesh *m, ora_particle *P, double c, double s, const ora_fields_t *F,
-                     double qm, double dt, double qw, double *dG, int64_t *piece_tets, int *npieces_out) {
+                     double qm, double dt, double qw, double *dG, int64_t *piece_tets, int *npieces_out,
+                     double *R) {
     double E[3], B[3];
     fields_at(m, P->tet, P->lam, c, s, F, E, B);
     boris(P->v, E, B, qm, dt);
@@ -362,6 +363,16 @@ static void step_one(const ora_mesh *m, ora_particle *P, double c, double s, con
             double nh[3] = {g[kmin][0] / nn, g[kmin][1] / nn, g[kmin][2] / nn};
             double dd = dot3(d, nh), vv = dot3(P->v, nh);
             for (int k = 0; k < 3; ++k) { d[k] -= 2.0 * dd * nh[k]; P->v[k] -= 2.0 * vv * nh[k]; }
+            if (R) {   /* R <- (I - 2 n n^T) R : the linear part of the reflected end point */
+                double Rn[9];
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j) {
+                        double acc = 0.0;
+                        for (int k = 0; k < 3; ++k) acc += ((i == k ? 1.0 : 0.0) - 2.0 * nh[i] * nh[k]) * R[3 * k + j];
+                        Rn[3 * i + j] = acc;
+                    }
+                memcpy(R, Rn, sizeof Rn);
+            }
             for (int k = 0; k < 4; ++k) l[k] = lc[k];
         } else {
             const int32_t *vt = m->tv + 4 * T, *vn = m->tv + 4 * nb;
@@ -407,7 +418,7 @@ int ora_step(const ora_mesh *m, int64_t n, int32_t *tet, double *lam, double *ve
             P.lam[1] = lam[3 * p]; P.lam[2] = lam[3 * p + 1]; P.lam[3] = lam[3 * p + 2];
             P.lam[0] = 1.0 - P.lam[1] - P.lam[2] - P.lam[3];
             P.v[0] = vel[3 * p]; P.v[1] = vel[3 * p + 1]; P.v[2] = vel[3 * p + 2];
-            step_one(m, &P, c, s, &F, qm, dt, qw, dG, NULL, NULL);
+            step_one(m, &P, c, s, &F, qm, dt, qw, dG, NULL, NULL, NULL);
             tet[p] = (int32_t)P.tet;
             lam[3 * p] = P.lam[1]; lam[3 * p + 1] = P.lam[2]; lam[3 * p + 2] = P.lam[3];
             vel[3 * p] = P.v[0]; vel[3 * p + 1] = P.v[1]; vel[3 * p + 2] = P.v[2];
@@ -434,7 +445,7 @@ int ora_step(const ora_mesh *m, int64_t n, int32_t *tet, double *lam, double *ve
             P.lam[1] = lam[3 * p]; P.lam[2] = lam[3 * p + 1]; P.lam[3] = lam[3 * p + 2];
             P.lam[0] = 1.0 - P.lam[1] - P.lam[2] - P.lam[3];
             P.v[0] = vel[3 * p]; P.v[1] = vel[3 * p + 1]; P.v[2] = vel[3 * p + 2];
-            step_one(m, &P, c, s, &F, qm, dt, qw, mydG, NULL, NULL);
+            step_one(m, &P, c, s, &F, qm, dt, qw, mydG, NULL, NULL, NULL);
             tet[p] = (int32_t)P.tet;
             lam[3 * p] = P.lam[1]; lam[3 * p + 1] = P.lam[2]; lam[3 * p + 2] = P.lam[3];
             vel[3 * p] = P.v[0]; vel[3 * p + 1] = P.v[1]; vel[3 * p + 2] = P.v[2];
@@ -516,10 +527,144 @@ int ora_step_one(const ora_mesh *m, int32_t *tet, double *lam3, double *v, doubl
     P.lam[0] = 1.0 - lam3[0] - lam3[1] - lam3[2];
     P.v[0] = v[0]; P.v[1] = v[1]; P.v[2] = v[2];
     int np = 0;
-    step_one(m, &P, cos(omega * t), sin(omega * t), &F, q / mass, dt, q * w, dG, piece_tets, &np);
+    step_one(m, &P, cos(omega * t), sin(omega * t), &F, q / mass, dt, q * w, dG, piece_tets, &np, NULL);
     *tet = (int32_t)P.tet;
     lam3[0] = P.lam[1]; lam3[1] = P.lam[2]; lam3[2] = P.lam[3];
     v[0] = P.v[0]; v[1] = P.v[1]; v[2] = P.v[2];
     *npieces = np;
     return P.status;
+}
+
+/* ------------------------------------------------------------------------
+ * Reverse-mode derivative of nsteps particle steps (the gradient path of the
+ * differentiation workload).  For each particle independently (the fields are
+ * given, so trajectories do not interact): run the steps forward keeping the
+ * state before every step and the linear part R of that step's wall
+ * reflections, then go backwards through position update, Boris and gather.
+ * Given vbar / xbar, the adjoints of the final velocity and (Cartesian)
+ * position, accumulate into grad_e[2*ne] the gradient with respect to the
+ * complex edge envelope in the convention d/dRe + j d/dIm, and return the
+ * adjoints of the initial velocity and position if asked.  Tet sequences and
+ * reflections are those of the forward run (the map is piecewise smooth).
+ * The face envelope and the dc DoFs are held fixed.
+ */
+static void boris_fwd(const double v[3], const double E[3], const double B[3], double h, double vm[3], double tau[3],
+                      double sig[3], double vpr[3], double out[3]) {
+    double cr[3];
+    for (int k = 0; k < 3; ++k) { vm[k] = v[k] + h * E[k]; tau[k] = h * B[k]; }
+    double t2 = dot3(tau, tau);
+    for (int k = 0; k < 3; ++k) sig[k] = 2.0 * tau[k] / (1.0 + t2);
+    cross3(vm, tau, cr);
+    for (int k = 0; k < 3; ++k) vpr[k] = vm[k] + cr[k];
+    cross3(vpr, sig, cr);
+    for (int k = 0; k < 3; ++k) out[k] = vm[k] + cr[k] + h * E[k];
+}
+
+/* adjoint of boris_fwd: given obar (adjoint of out) produce vbar, Ebar, Bbar */
+static void boris_vjp(const double vm[3], const double tau[3], const double sig[3], const double vpr[3], double h,
+                      const double obar[3], double vbar[3], double Ebar[3], double Bbar[3]) {
+    double vmbar[3], vprbar[3], sigbar[3], taubar[3], cr[3];
+    /* out = vm + vpr x sig + h E */
+    for (int k = 0; k < 3; ++k) { vmbar[k] = obar[k]; Ebar[k] = h * obar[k]; }
+    cross3(sig, obar, vprbar);              /* d(vpr x sig)/dvpr ^T obar = sig x obar */
+    cross3(obar, vpr, sigbar);              /* d(vpr x sig)/dsig ^T obar = obar x vpr */
+    /* vpr = vm + vm x tau */
+    cross3(tau, vprbar, cr);
+    for (int k = 0; k < 3; ++k) vmbar[k] += vprbar[k] + cr[k];
+    cross3(vprbar, vm, taubar);
+    /* sig = 2 tau / (1 + |tau|^2) */
+    double t2 = dot3(tau, tau), den = 1.0 + t2, st = dot3(sigbar, tau);
+    for (int k = 0; k < 3; ++k) taubar[k] += 2.0 * sigbar[k] / den - 4.0 * st * tau[k] / (den * den);
+    /* tau = h B ; vm = v + h E */
+    for (int k = 0; k < 3; ++k) { Bbar[k] = h * taubar[k]; vbar[k] = vmbar[k]; Ebar[k] += h * vmbar[k]; }
+}
+
+int ora_vjp(const ora_mesh *m, int64_t n, const int32_t *tet0, const double *lam0, const double *vel0, double q,
+            double mass, double w, int64_t step0, int nsteps, double dt, double omega, const double *e_env,
+            const double *e_dc, const double *b_env, const double *b_dc, const double *vbar_in,
+            const double *xbar_in, double *grad_e, double *vbar_out, double *xbar_out, int nthreads) {
+    ora_fields_t F = {e_env, e_dc, b_env, b_dc};
+    double qm = q / mass, h = 0.5 * qm * dt;
+    int status = 0;
+    int nth = nthreads > 1 ? nthreads : 1;
+#ifndef _OPENMP
+    nth = 1;
+#endif
+    double *priv = (double *)calloc((size_t)nth * 2 * m->ne, sizeof(double));
+    #pragma omp parallel num_threads(nth) reduction(min:status)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *g = priv + (size_t)tid * 2 * m->ne;
+        ora_particle *st = (ora_particle *)malloc(sizeof(ora_particle) * (nsteps + 1));
+        double *Rs = (double *)malloc(sizeof(double) * 9 * (nsteps + 1));
+        double *dummy = (double *)calloc(m->ne, sizeof(double));
+        #pragma omp for schedule(static)
+        for (int64_t p = 0; p < n; ++p) {
+            ora_particle P;
+            P.tet = tet0[p];
+            P.lam[1] = lam0[3 * p]; P.lam[2] = lam0[3 * p + 1]; P.lam[3] = lam0[3 * p + 2];
+            P.lam[0] = 1.0 - P.lam[1] - P.lam[2] - P.lam[3];
+            for (int k = 0; k < 3; ++k) P.v[k] = vel0[3 * p + k];
+            for (int k = 0; k < nsteps; ++k) {
+                st[k] = P;
+                double *R = Rs + 9 * k;
+                for (int i = 0; i < 9; ++i) R[i] = (i % 4 == 0) ? 1.0 : 0.0;
+                double t = (double)(step0 + k) * dt;
+                step_one(m, &P, cos(omega * t), sin(omega * t), &F, qm, dt, 0.0, dummy, NULL, NULL, R);
+                if (P.status) status = P.status;
+            }
+            double vb[3], xb[3];
+            for (int k = 0; k < 3; ++k) { vb[k] = vbar_in[3 * p + k]; xb[k] = xbar_in ? xbar_in[3 * p + k] : 0.0; }
+            for (int k = nsteps - 1; k >= 0; --k) {
+                const ora_particle *S = &st[k];
+                const double *R = Rs + 9 * k;
+                double t = (double)(step0 + k) * dt, c = cos(omega * t), sn = sin(omega * t);
+                double E[3], B[3];
+                fields_at(m, S->tet, S->lam, c, sn, &F, E, B);
+                double vm[3], tau[3], sig[3], vpr[3], out[3];
+                boris_fwd(S->v, E, B, h, vm, tau, sig, vpr, out);
+                /* x_{k+1} = R (x_k + dt out) + const ; v_{k+1} = R out */
+                double ob[3], xk[3];
+                for (int i = 0; i < 3; ++i) {
+                    ob[i] = 0.0; xk[i] = 0.0;
+                    for (int j = 0; j < 3; ++j) { ob[i] += R[3 * j + i] * (vb[j] + dt * xb[j]); xk[i] += R[3 * j + i] * xb[j]; }
+                }
+                double vin[3], Eb[3], Bb[3];
+                boris_vjp(vm, tau, sig, vpr, h, ob, vin, Eb, Bb);
+                /* gather: E = sum_e eps_e W1_e(x), B = sum_f beta_f W2_f(x), W affine in x */
+                double gr[4][3];
+                ora_grad(m, S->tet, gr);
+                for (int e = 0; e < 6; ++e) {
+                    int i = LE[e][0], j = LE[e][1];
+                    int64_t id = m->tet_edge[6 * S->tet + e];
+                    double eps = F.e_env[2 * id] * c - F.e_env[2 * id + 1] * sn + (F.e_dc ? F.e_dc[id] : 0.0);
+                    double Ei = dot3(Eb, gr[i]), Ej = dot3(Eb, gr[j]);
+                    for (int b = 0; b < 3; ++b) xk[b] += eps * (Ej * gr[i][b] - Ei * gr[j][b]);
+                    double wdot = S->lam[i] * Ej - S->lam[j] * Ei;          /* Ebar . W1_e(x_k) */
+                    g[2 * id] += wdot * c;
+                    g[2 * id + 1] -= wdot * sn;
+                }
+                for (int f = 0; f < 4; ++f) {
+                    int i = LF[f][0], j = LF[f][1], kk = LF[f][2];
+                    int64_t id = m->tet_face[4 * S->tet + f];
+                    double beta = F.b_env[2 * id] * c - F.b_env[2 * id + 1] * sn + (F.b_dc ? F.b_dc[id] : 0.0);
+                    double jk[3], ki[3], ij[3];
+                    cross3(gr[j], gr[kk], jk); cross3(gr[kk], gr[i], ki); cross3(gr[i], gr[j], ij);
+                    double a1 = dot3(Bb, jk), a2 = dot3(Bb, ki), a3 = dot3(Bb, ij);
+                    for (int b = 0; b < 3; ++b) xk[b] += 2.0 * beta * (a1 * gr[i][b] + a2 * gr[j][b] + a3 * gr[kk][b]);
+                }
+                for (int i = 0; i < 3; ++i) { vb[i] = vin[i]; xb[i] = xk[i]; }
+            }
+            if (vbar_out) for (int k = 0; k < 3; ++k) vbar_out[3 * p + k] = vb[k];
+            if (xbar_out) for (int k = 0; k < 3; ++k) xbar_out[3 * p + k] = xb[k];
+        }
+        free(st); free(Rs); free(dummy);
+    }
+    for (int th = 0; th < nth; ++th)
+        for (int64_t i = 0; i < 2 * m->ne; ++i) grad_e[i] += priv[(size_t)th * 2 * m->ne + i];
+    free(priv);
+    return status;
 }

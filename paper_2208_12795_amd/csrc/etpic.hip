@@ -6,10 +6,10 @@
 //                 B(x) = sum_i lam_i C_i inside a tet (both expansions are affine
 //                 in lam), where A_i, C_i fold the real parts Re{dof e^{jwt}} + dc
 //                 of the 6 edge and 4 face DoFs into the gradients.
-//   k_step        per particle, tet-sorted: per-tet coefficients staged in LDS,
-//                 gather, Boris push, in-tet path-integral deposit reduced
-//                 over runs of equal tet (wave) and slots (LDS), float64
-//                 atomics; particles leaving their tet are queued.
+//   k_push        per particle, tet-sorted: gather from the coefficient row,
+//                 Boris push, in-tet path-integral deposit reduced over runs
+//                 of equal tet in each wavefront, float64 atomics; particles
+//                 leaving their tet are queued.
 //   k_walk        the queued particles: barycentric walk, reflection, deposit.
 //   k_hist/k_scan*/k_scatter   counting sort by tet.
 //   k_charge      vertex charge of the particles.
@@ -22,6 +22,8 @@
 #include <cstring>
 #include <string>
 #include <vector>
+#include <array>
+#include <algorithm>
 
 #include "etpic.h"
 #include "mesh_host.hpp"
@@ -49,7 +51,7 @@ int fail(int code, const char *fmt, ...) {
     } while (0)
 
 constexpr int kBlock = 256;
-constexpr unsigned kWalkQueueCap = 1u << 22;  // blocks; bounds N_p by 2^30
+constexpr unsigned kWalkQueueCap = 1u << 23;  // wavefronts; bounds N_p by 2^29
 constexpr unsigned kWalkBlocks = 1024;        // grid of the walk kernel
 
 // Runs of equal key among the 64 lanes of a wavefront (particles are kept
@@ -160,7 +162,9 @@ struct StepArgs {
     double *lam1, *lam2, *lam3;
     Real *v0, *v1, *v2;
     int32_t *tet;
-    const double *grad;        // nt*12 float64 barycentric gradients
+    const Real *coef;          // nt*24: A_0..3, C_0..3 of this step (k_tet_coef)
+    const Real *gpush;         // nt*12: grad l_1, grad l_2, grad l_3, 0 (in Real)
+    const double *grad;        // nt*12 float64 barycentric gradients grad l_0..3
     const TetTopo *topo;
     double *dG;
     double *rho;
@@ -174,7 +178,7 @@ struct StepArgs {
 
 // A particle that leaves its tet is marked in place (tet = -(T + 2)) by the
 // step kernel, which keeps its start barycentrics and stores its new velocity;
-// the block's index goes to the walk queue.  k_walk then walks it.
+// its wavefront's index goes to the walk queue.  k_walk then walks it.
 __device__ __forceinline__ int walker_mark(int T) { return -(T + 2); }
 __device__ __forceinline__ int walker_tet(int marked) { return -marked - 2; }
 
@@ -199,8 +203,11 @@ __device__ __forceinline__ void deposit_piece(double *__restrict__ dG, const Tet
 // coordinate is set to exactly 0, the other three are rescaled to sum to one and
 // handed to the neighbour's shared vertices; at a boundary face the remaining
 // displacement and the velocity are reflected about the face normal.
-template <typename Real>
-__device__ __forceinline__ int walk(const StepArgs<Real> &a, int T, double l[4], double d[3], Real v[3]) {
+// With kTrack (used by the adjoint) nothing is deposited and R accumulates the
+// linear part of the step's reflections (R <- (I - 2 n n^T) R per wall hit):
+// the end point is R (x + dt v) + const and the stored velocity is R v.
+template <typename Real, bool kTrack>
+__device__ __forceinline__ int walk(const StepArgs<Real> &a, int T, double l[4], double d[3], Real v[3], double *R) {
     int hops = 0;
     for (;;) {
         const double *gp = a.grad + (int64_t)T * 12;
@@ -238,7 +245,7 @@ __device__ __forceinline__ int walk(const StepArgs<Real> &a, int T, double l[4],
                 nb = tp.n[k];
             }
         if (kmin < 0) {
-            deposit_piece(a.dG, tp, l, dl, a.qw);
+            if (!kTrack) deposit_piece(a.dG, tp, l, dl, a.qw);
 #pragma unroll
             for (int k = 0; k < 4; ++k) l[k] += dl[k];
             break;
@@ -246,7 +253,7 @@ __device__ __forceinline__ int walk(const StepArgs<Real> &a, int T, double l[4],
         double dlp[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) dlp[k] = smin * dl[k];
-        deposit_piece(a.dG, tp, l, dlp, a.qw);
+        if (!kTrack) deposit_piece(a.dG, tp, l, dlp, a.qw);
         double lc[4], sum = 0.0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -266,6 +273,14 @@ __device__ __forceinline__ int walk(const StepArgs<Real> &a, int T, double l[4],
             for (int c = 0; c < 3; ++c) {
                 d[c] -= 2.0 * dd * nh[c];
                 v[c] -= (Real)2 * vv * (Real)nh[c];
+            }
+            if (kTrack) {
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const double col = nh[0] * R[j] + nh[1] * R[3 + j] + nh[2] * R[6 + j];
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) R[3 * i + j] -= 2.0 * nh[i] * col;
+                }
             }
 #pragma unroll
             for (int k = 0; k < 4; ++k) l[k] = lc[k];
@@ -289,127 +304,18 @@ __device__ __forceinline__ int walk(const StepArgs<Real> &a, int T, double l[4],
     return T;
 }
 
-// ------------------------------------------------------------------ fused staged step
-// One block of kBlock threads takes kBlock consecutive particles.  Runs of equal
-// tet in thread order (particles are kept sorted by tet) become "slots".  For up
-// to kSlots slots at a time, 8 threads per slot build the carrier-rotated
-// Whitney coefficients of that tet straight from the edge/face DoFs into LDS
-// (A_k and C_k, one thread per vertex k each).  Every particle then gathers from
-// LDS, pushes, and -- if it stays in its tet, which is the common case --
-// deposits its six path integrals into the slot's LDS accumulators (float64
-// LDS atomics).  The accumulators are flushed with one float64 global atomic
-// per (slot, edge).  Particles that leave their tet walk and deposit every
-// piece with global atomics.
-constexpr int kSlots = 32;
-
+// ------------------------------------------------------------------ particle step
+// One lane per particle, particles kept sorted by tet.  Each lane reads its
+// tet's row of this step's coefficient table (lanes of a run share the row, so
+// the loads coalesce), gathers E and B, applies the Boris update and, if the
+// particle stays in its tet (the common case), computes the six in-tet path
+// integrals.  These are summed over each run of equal tet within the
+// wavefront (segmented reduction through lane shuffles); the run's first lane
+// adds the sums to the edges with float64 global atomics.  There are no block
+// barriers, so latency is hidden by occupancy alone.  Particles that leave
+// their tet are marked and their wavefront queued for k_walk.
 template <typename Real>
-struct StageLds {
-    Real coef[kSlots][24];
-    Real grad[kSlots][9];
-    double acc[kSlots][6];
-    double racc[kSlots][4];
-    int32_t edge[kSlots][6];
-    int32_t vert[kSlots][4];
-    int32_t tet[kSlots];
-    int32_t wave_last[kBlock / 64];
-    int32_t wave_heads[kBlock / 64];
-};
-
-struct FieldPtrs {
-    const double2 *e_env;
-    const double *e_dc;
-    const double2 *b_env;
-    const double *b_dc;
-    double c, s;   // cos(w t_n), sin(w t_n)
-};
-
-// local edge index of the vertex pair {i, j}, i < j
-__device__ __forceinline__ int local_edge(int i, int j) { return i == 0 ? j - 1 : (i == 1 ? j + 1 : 5); }
-
-template <int K, typename Real>
-__device__ __forceinline__ void stage_A(StageLds<Real> &L, int s, const int32_t *tp, const double g[4][3],
-                                        const FieldPtrs &F) {
-    double A[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        if (j == K) continue;
-        const int id = tp[local_edge(j < K ? j : K, j < K ? K : j)];
-        const double2 z = F.e_env[id];
-        double eps = z.x * F.c - z.y * F.s;
-        if (F.e_dc) eps += F.e_dc[id];
-        if (j < K) eps = -eps;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) A[d] += eps * g[j][d];
-    }
-#pragma unroll
-    for (int d = 0; d < 3; ++d) L.coef[s][3 * K + d] = (Real)A[d];
-    if (K < 3) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) L.grad[s][3 * K + d] = (Real)g[K + 1][d];
-    } else {
-#pragma unroll
-        for (int e = 0; e < 6; ++e) L.edge[s][e] = tp[e];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) L.vert[s][v] = tp[10 + v];
-    }
-    L.racc[s][K] = 0.0;
-    L.acc[s][K] = 0.0;
-}
-
-template <int K, typename Real>
-__device__ __forceinline__ void stage_C(StageLds<Real> &L, int s, const int32_t *tp, const double g[4][3],
-                                        const FieldPtrs &F) {
-    double Cv[3] = {0.0, 0.0, 0.0};
-    constexpr int lf[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
-#pragma unroll
-    for (int f = 0; f < 4; ++f) {
-        if (f == K) continue;
-        const int a = lf[f][0] == K ? lf[f][1] : (lf[f][1] == K ? lf[f][2] : lf[f][0]);
-        const int b = lf[f][0] == K ? lf[f][2] : (lf[f][1] == K ? lf[f][0] : lf[f][1]);
-        const int id = tp[6 + f];
-        const double2 z = F.b_env[id];
-        double beta = z.x * F.c - z.y * F.s;
-        if (F.b_dc) beta += F.b_dc[id];
-        beta *= 2.0;
-        Cv[0] += beta * (g[a][1] * g[b][2] - g[a][2] * g[b][1]);
-        Cv[1] += beta * (g[a][2] * g[b][0] - g[a][0] * g[b][2]);
-        Cv[2] += beta * (g[a][0] * g[b][1] - g[a][1] * g[b][0]);
-    }
-#pragma unroll
-    for (int d = 0; d < 3; ++d) L.coef[s][12 + 3 * K + d] = (Real)Cv[d];
-    if (K < 2) L.acc[s][4 + K] = 0.0;
-}
-
-// Part `part` (0..7) of the coefficients of tet T into slot s:
-//   part k < 4 : A_k = sum_{j != k} sign(j - k) eps_{kj} grad l_j   (E = sum_k l_k A_k)
-//   part 4 + k : C_k = 2 sum_{faces f containing k} beta_f (grad l_a x grad l_b),
-//                (k, a, b) the cyclic order of f's ascending triple starting at k.
-// eps and beta are the real parts Re{dof e^{jwt}} + dc of the edge and face DoFs.
-template <typename Real>
-__device__ __forceinline__ void stage_part(StageLds<Real> &L, int s, int part, int T, const TetTopo *__restrict__ topo,
-                                           const double *__restrict__ grad, const FieldPtrs &F) {
-    const double *gp = grad + (int64_t)T * 12;
-    double g[4][3];
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) g[k][d] = gp[3 * k + d];
-    const int32_t *tp = reinterpret_cast<const int32_t *>(topo + T);
-    switch (part) {
-        case 0: stage_A<0>(L, s, tp, g, F); break;
-        case 1: stage_A<1>(L, s, tp, g, F); break;
-        case 2: stage_A<2>(L, s, tp, g, F); break;
-        case 3: stage_A<3>(L, s, tp, g, F); break;
-        case 4: stage_C<0>(L, s, tp, g, F); break;
-        case 5: stage_C<1>(L, s, tp, g, F); break;
-        case 6: stage_C<2>(L, s, tp, g, F); break;
-        default: stage_C<3>(L, s, tp, g, F); break;
-    }
-}
-
-template <typename Real>
-__global__ void __launch_bounds__(kBlock) k_step(StepArgs<Real> a, FieldPtrs F, int remap) {
-    __shared__ StageLds<Real> L;
+__global__ void __launch_bounds__(kBlock) k_push(StepArgs<Real> a, int remap) {
     unsigned blk = blockIdx.x;
     if (remap) {
         // the dispatcher deals blocks round-robin over the 8 XCDs; give each XCD
@@ -417,8 +323,7 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs<Real> a, FieldPtrs F, 
         const unsigned G = gridDim.x, q = G / 8, r = G % 8, x = blk % 8, j = blk / 8;
         blk = x * q + min(x, r) + j;
     }
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int64_t p = (int64_t)blk * kBlock + tid;
+    const int64_t p = (int64_t)blk * kBlock + threadIdx.x;
     int T = -1;
     if (p < a.n) {
         T = a.tet[p];
@@ -428,153 +333,113 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs<Real> a, FieldPtrs F, 
         }
     }
     const bool act = T >= 0;
-    double l[4];
-    Real v[3];
+    double g6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // this lane's in-tet path integrals
+    double r4[4] = {0.0, 0.0, 0.0, 0.0};             // this lane's end-point barycentrics
+    int walker = 0;
     if (act) {
+        double l[4];
         l[1] = a.lam1[p];
         l[2] = a.lam2[p];
         l[3] = a.lam3[p];
-        v[0] = a.v0[p];
-        v[1] = a.v1[p];
-        v[2] = a.v2[p];
-    }
-    // runs of equal tet -> slots
-    int prevT = __shfl_up(T, 1);
-    if (lane == 63) L.wave_last[wid] = T;
-    __syncthreads();
-    if (lane == 0) prevT = wid == 0 ? -2 : L.wave_last[wid - 1];
-    const bool head = act && T != prevT;
-    const unsigned long long hm = __ballot(head);
-    const unsigned long long upto = lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1ull);
-    const int incl = __popcll(hm & upto);
-    if (lane == 0) L.wave_heads[wid] = __popcll(hm);
-    __syncthreads();
-    int before = 0, nslot = 0;
+        l[0] = 1.0 - l[1] - l[2] - l[3];
+        Real v[3] = {a.v0[p], a.v1[p], a.v2[p]};
+        const Real *cf = a.coef + (int64_t)T * 24;
+        Real E[3], B[3];
 #pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) {
-        const int c = L.wave_heads[w];
-        before += w < wid ? c : 0;
-        nslot += c;
-    }
-    const int slot = before + incl - 1;
-    const WaveRuns runs = wave_runs(act ? slot : -1);
-    int walker = 0;
-    for (int lo = 0; lo < nslot; lo += kSlots) {
-        const int cnt = min(kSlots, nslot - lo);
-        if (head && slot >= lo && slot < lo + cnt) L.tet[slot - lo] = T;
-        __syncthreads();
-        {
-            const int s = tid >> 3, part = tid & 7;
-            if (s < cnt) stage_part<Real>(L, s, part, L.tet[s], a.topo, a.grad, F);
+        for (int d = 0; d < 3; ++d) {
+            E[d] = (Real)l[0] * cf[d] + (Real)l[1] * cf[3 + d] + (Real)l[2] * cf[6 + d] + (Real)l[3] * cf[9 + d];
+            B[d] = (Real)l[0] * cf[12 + d] + (Real)l[1] * cf[15 + d] + (Real)l[2] * cf[18 + d] + (Real)l[3] * cf[21 + d];
         }
-        __syncthreads();
-        const bool here = act && slot >= lo && slot < lo + cnt;
-        double g6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // this lane's in-tet path integrals
-        double r4[4] = {0.0, 0.0, 0.0, 0.0};             // this lane's end-point barycentrics
-        if (here) {
-            const int s = slot - lo;
-            l[0] = 1.0 - l[1] - l[2] - l[3];
-            const Real *cf = L.coef[s];
-            Real E[3], B[3];
+        // Boris: half kick, rotation (implicit midpoint in v x B), half kick
+        const Real h = a.h;
+        Real vm[3], tau[3];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                E[d] = (Real)l[0] * cf[d] + (Real)l[1] * cf[3 + d] + (Real)l[2] * cf[6 + d] + (Real)l[3] * cf[9 + d];
-                B[d] = (Real)l[0] * cf[12 + d] + (Real)l[1] * cf[15 + d] + (Real)l[2] * cf[18 + d] +
-                       (Real)l[3] * cf[21 + d];
-            }
-            const Real h = a.h;
-            Real vm[3], tau[3];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                vm[d] = v[d] + h * E[d];
-                tau[d] = h * B[d];
-            }
-            const Real t2 = tau[0] * tau[0] + tau[1] * tau[1] + tau[2] * tau[2];
-            const Real sg = (Real)2 / ((Real)1 + t2);
-            const Real vr[3] = {vm[0] + (vm[1] * tau[2] - vm[2] * tau[1]), vm[1] + (vm[2] * tau[0] - vm[0] * tau[2]),
-                                vm[2] + (vm[0] * tau[1] - vm[1] * tau[0])};
-            v[0] = vm[0] + sg * (vr[1] * tau[2] - vr[2] * tau[1]) + h * E[0];
-            v[1] = vm[1] + sg * (vr[2] * tau[0] - vr[0] * tau[2]) + h * E[1];
-            v[2] = vm[2] + sg * (vr[0] * tau[1] - vr[1] * tau[0]) + h * E[2];
-            if (!(isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]))) atomicOr(a.status, (unsigned)ETPIC_DEV_NAN);
-            const Real dx[3] = {a.dt_r * v[0], a.dt_r * v[1], a.dt_r * v[2]};
-            const Real *gr = L.grad[s];
-            double dl[4];
-#pragma unroll
-            for (int k = 1; k < 4; ++k)
-                dl[k] = (double)(gr[3 * k - 3] * dx[0] + gr[3 * k - 2] * dx[1] + gr[3 * k - 1] * dx[2]);
-            dl[0] = -(dl[1] + dl[2] + dl[3]);
-            const bool stays = (l[0] + dl[0] >= 0.0) && (l[1] + dl[1] >= 0.0) && (l[2] + dl[2] >= 0.0) &&
-                               (l[3] + dl[3] >= 0.0);
-            if (stays) {
-                double m[4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) m[k] = l[k] + 0.5 * dl[k];
-                const int le[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
-#pragma unroll
-                for (int e = 0; e < 6; ++e) g6[e] = m[le[e][0]] * dl[le[e][1]] - m[le[e][1]] * dl[le[e][0]];
-#pragma unroll
-                for (int k = 1; k < 4; ++k) l[k] += dl[k];
-                a.lam1[p] = l[1];
-                a.lam2[p] = l[2];
-                a.lam3[p] = l[3];
-                if (a.rho) {
-                    r4[0] = 1.0 - l[1] - l[2] - l[3];
-                    r4[1] = l[1];
-                    r4[2] = l[2];
-                    r4[3] = l[3];
-                }
-            } else {
-                a.tet[p] = walker_mark(T);
-                walker = 1;
-            }
-            a.v0[p] = v[0];
-            a.v1[p] = v[1];
-            a.v2[p] = v[2];
+        for (int d = 0; d < 3; ++d) {
+            vm[d] = v[d] + h * E[d];
+            tau[d] = h * B[d];
         }
-        // wave-level segmented reduction over runs of equal slot, then one LDS
-        // atomic per (run, edge) from the run's head lane
+        const Real t2 = tau[0] * tau[0] + tau[1] * tau[1] + tau[2] * tau[2];
+        const Real sg = (Real)2 / ((Real)1 + t2);
+        const Real vr[3] = {vm[0] + (vm[1] * tau[2] - vm[2] * tau[1]), vm[1] + (vm[2] * tau[0] - vm[0] * tau[2]),
+                            vm[2] + (vm[0] * tau[1] - vm[1] * tau[0])};
+        v[0] = vm[0] + sg * (vr[1] * tau[2] - vr[2] * tau[1]) + h * E[0];
+        v[1] = vm[1] + sg * (vr[2] * tau[0] - vr[0] * tau[2]) + h * E[1];
+        v[2] = vm[2] + sg * (vr[0] * tau[1] - vr[1] * tau[0]) + h * E[2];
+        if (!(isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]))) atomicOr(a.status, (unsigned)ETPIC_DEV_NAN);
+        // displacement and barycentric increments; lam0 is stored implicitly
+        // (1 - lam1 - lam2 - lam3), so its increment is minus the sum of the
+        // other three, in float64: deposit and stored end point see the same
+        // four increments (continuity to float64 rounding)
+        const Real dx[3] = {a.dt_r * v[0], a.dt_r * v[1], a.dt_r * v[2]};
+        const Real *gr = a.gpush + (int64_t)T * 12;
+        double dl[4];
 #pragma unroll
-        for (int e = 0; e < 6; ++e) g6[e] = run_total(g6[e], runs);
+        for (int k = 1; k < 4; ++k)
+            dl[k] = (double)(gr[3 * k - 3] * dx[0] + gr[3 * k - 2] * dx[1] + gr[3 * k - 1] * dx[2]);
+        dl[0] = -(dl[1] + dl[2] + dl[3]);
+        const bool stays = (l[0] + dl[0] >= 0.0) && (l[1] + dl[1] >= 0.0) && (l[2] + dl[2] >= 0.0) &&
+                           (l[3] + dl[3] >= 0.0);
+        if (stays) {
+            // path integral of W1_ij along the straight piece: m_i dl_j - m_j dl_i,
+            // m the midpoint barycentrics (exact: the integrand is affine on the piece)
+            double m[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) m[k] = l[k] + 0.5 * dl[k];
+            constexpr int le[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+#pragma unroll
+            for (int e = 0; e < 6; ++e) g6[e] = m[le[e][0]] * dl[le[e][1]] - m[le[e][1]] * dl[le[e][0]];
+#pragma unroll
+            for (int k = 1; k < 4; ++k) l[k] += dl[k];
+            a.lam1[p] = l[1];
+            a.lam2[p] = l[2];
+            a.lam3[p] = l[3];
+            if (a.rho) {
+                r4[0] = 1.0 - l[1] - l[2] - l[3];
+                r4[1] = l[1];
+                r4[2] = l[2];
+                r4[3] = l[3];
+            }
+        } else {
+            a.tet[p] = walker_mark(T);
+            walker = 1;
+        }
+        a.v0[p] = v[0];
+        a.v1[p] = v[1];
+        a.v2[p] = v[2];
+    }
+    // segmented reduction over runs of equal tet; the run's first lane adds to HBM
+    const WaveRuns runs = wave_runs(T);
+#pragma unroll
+    for (int e = 0; e < 6; ++e) g6[e] = run_total(g6[e], runs);
+    if (a.rho) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) r4[k] = run_total(r4[k], runs);
+    }
+    if (act && runs.head) {
+        const TetTopo *tp = a.topo + T;
+#pragma unroll
+        for (int e = 0; e < 6; ++e)
+            if (g6[e] != 0.0) unsafeAtomicAdd(&a.dG[tp->e[e]], a.qw * g6[e]);
         if (a.rho) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) r4[k] = run_total(r4[k], runs);
+            for (int k = 0; k < 4; ++k)
+                if (r4[k] != 0.0) unsafeAtomicAdd(&a.rho[tp->v[k]], a.qw * r4[k]);
         }
-        if (here && runs.head) {
-            const int s = slot - lo;
-#pragma unroll
-            for (int e = 0; e < 6; ++e) unsafeAtomicAdd(&L.acc[s][e], g6[e]);
-            if (a.rho) {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) unsafeAtomicAdd(&L.racc[s][k], r4[k]);
-            }
-        }
-        __syncthreads();
-        for (int t = tid; t < cnt * 10; t += kBlock) {
-            if (t < cnt * 6) {
-                const int s = t / 6, e = t - 6 * s;
-                const double val = L.acc[s][e];
-                if (val != 0.0) unsafeAtomicAdd(&a.dG[L.edge[s][e]], a.qw * val);
-            } else if (a.rho) {
-                const int u = t - cnt * 6, s = u >> 2, k = u & 3;
-                const double val = L.racc[s][k];
-                if (val != 0.0) unsafeAtomicAdd(&a.rho[L.vert[s][k]], a.qw * val);
-            }
-        }
-        __syncthreads();
     }
-    if (__syncthreads_or(walker) && tid == 0) a.walk_queue[atomicAdd(&a.walk_ctr[0], 1u)] = blk;
+    if (__ballot(walker) && runs.lane == 0)
+        a.walk_queue[atomicAdd(&a.walk_ctr[0], 1u)] = (unsigned)(((int64_t)blk * kBlock + threadIdx.x) >> 6);
 }
 
-// Walks the marked particles of the queued blocks: every piece of their path
-// is deposited with global atomics, and the end point, reflected velocity and
-// new tet are stored.  Blocks stride over the queue; the last block to finish
-// resets the counters for the next step.
+// Walks the marked particles of the queued wavefronts: every piece of their
+// path is deposited with global atomics, and the end point, reflected velocity
+// and new tet are stored.  Each wavefront strides over the queue; the last
+// block to finish resets the counters for the next step.
 template <typename Real>
 __global__ void __launch_bounds__(kBlock) k_walk(StepArgs<Real> a) {
     const unsigned count = __atomic_load_n(&a.walk_ctr[0], __ATOMIC_RELAXED);
-    for (unsigned i = blockIdx.x; i < count; i += gridDim.x) {
-        const int64_t p = (int64_t)a.walk_queue[i] * kBlock + threadIdx.x;
+    const unsigned wpb = kBlock / 64;
+    for (unsigned i = blockIdx.x * wpb + (threadIdx.x >> 6); i < count; i += gridDim.x * wpb) {
+        const int64_t p = (int64_t)a.walk_queue[i] * 64 + (threadIdx.x & 63);
         if (p >= a.n) continue;
         const int marked = a.tet[p];
         if (marked > -2) continue;
@@ -588,7 +453,7 @@ __global__ void __launch_bounds__(kBlock) k_walk(StepArgs<Real> a) {
         Real v[3] = {a.v0[p], a.v1[p], a.v2[p]};
         const Real dx[3] = {a.dt_r * v[0], a.dt_r * v[1], a.dt_r * v[2]};
         double d[3] = {(double)dx[0], (double)dx[1], (double)dx[2]};
-        T = walk<Real>(a, T, l, d, v);
+        T = walk<Real, false>(a, T, l, d, v, nullptr);
         a.tet[p] = T;
         a.lam1[p] = l[1];
         a.lam2[p] = l[2];
@@ -611,6 +476,170 @@ __global__ void __launch_bounds__(kBlock) k_walk(StepArgs<Real> a) {
         if (atomicAdd(&a.walk_ctr[1], 1u) == gridDim.x - 1) {
             a.walk_ctr[0] = 0u;
             a.walk_ctr[1] = 0u;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ adjoint step
+// Reverse of one float64 step for every particle, given the state before the
+// step (recomputed from a checkpoint) and the adjoints of the state after it.
+// Recomputes gather, Boris and the walk's reflections, then back-propagates:
+//   x_{k+1} = R (x_k + dt v+) + const, v_{k+1} = R v+         (walk, reflections R)
+//   v+ = Boris(v_k, E, B)                                        (vjp written out)
+//   E = sum_i l_i(x) A_i, B = sum_i l_i(x) C_i                  (affine in x)
+// and accumulates the gradient with respect to the complex edge envelope,
+// dL/dRe e_e + j dL/dIm e_e = (Ebar . W1_e(x_k)) e^{-j w t_k}, reduced over runs
+// of equal tet before the float64 atomics.
+struct AdjArgs {
+    const double *lam1, *lam2, *lam3;
+    const double *v0, *v1, *v2;
+    const int32_t *tet;
+    double *vb0, *vb1, *vb2;
+    double *xb0, *xb1, *xb2;
+    double *grad_e;
+    double c, s, dt;
+};
+
+__global__ void __launch_bounds__(kBlock) k_adjoint(StepArgs<double> a, AdjArgs b) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int T = -1;
+    if (p < a.n) {
+        T = b.tet[p];
+        if ((unsigned)T >= (unsigned)a.nt) {
+            atomicOr(a.status, (unsigned)ETPIC_DEV_BADTET);
+            T = -1;
+        }
+    }
+    double ge[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) ge[k] = 0.0;
+    if (T >= 0) {
+        double l[4];
+        l[1] = b.lam1[p];
+        l[2] = b.lam2[p];
+        l[3] = b.lam3[p];
+        l[0] = 1.0 - l[1] - l[2] - l[3];
+        const double v[3] = {b.v0[p], b.v1[p], b.v2[p]};
+        const double *cf = a.coef + (int64_t)T * 24;
+        double E[3], B[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            E[d] = l[0] * cf[d] + l[1] * cf[3 + d] + l[2] * cf[6 + d] + l[3] * cf[9 + d];
+            B[d] = l[0] * cf[12 + d] + l[1] * cf[15 + d] + l[2] * cf[18 + d] + l[3] * cf[21 + d];
+        }
+        const double h = a.h;
+        double vm[3], tau[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            vm[d] = v[d] + h * E[d];
+            tau[d] = h * B[d];
+        }
+        const double t2 = tau[0] * tau[0] + tau[1] * tau[1] + tau[2] * tau[2];
+        const double den = 1.0 + t2;
+        const double sg = 2.0 / den;
+        const double vr[3] = {vm[0] + (vm[1] * tau[2] - vm[2] * tau[1]), vm[1] + (vm[2] * tau[0] - vm[0] * tau[2]),
+                              vm[2] + (vm[0] * tau[1] - vm[1] * tau[0])};
+        double out[3];
+        out[0] = vm[0] + sg * (vr[1] * tau[2] - vr[2] * tau[1]) + h * E[0];
+        out[1] = vm[1] + sg * (vr[2] * tau[0] - vr[0] * tau[2]) + h * E[1];
+        out[2] = vm[2] + sg * (vr[0] * tau[1] - vr[1] * tau[0]) + h * E[2];
+        // reflections of this step (identity unless the particle left its tet)
+        double R[9] = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0};
+        const double dx[3] = {a.dt_r * out[0], a.dt_r * out[1], a.dt_r * out[2]};
+        const double *gp = a.grad + (int64_t)T * 12;
+        double g[4][3];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) g[k][d] = gp[3 * k + d];
+        {
+            const double *gr = a.gpush + (int64_t)T * 12;
+            double dl[4];
+#pragma unroll
+            for (int k = 1; k < 4; ++k) dl[k] = gr[3 * k - 3] * dx[0] + gr[3 * k - 2] * dx[1] + gr[3 * k - 1] * dx[2];
+            dl[0] = -(dl[1] + dl[2] + dl[3]);
+            const bool stays = (l[0] + dl[0] >= 0.0) && (l[1] + dl[1] >= 0.0) && (l[2] + dl[2] >= 0.0) &&
+                               (l[3] + dl[3] >= 0.0);
+            if (!stays) {
+                double lw[4] = {l[0], l[1], l[2], l[3]};
+                double dw[3] = {dx[0], dx[1], dx[2]};
+                double vw[3] = {out[0], out[1], out[2]};
+                walk<double, true>(a, T, lw, dw, vw, R);
+            }
+        }
+        const double xb[3] = {b.xb0[p], b.xb1[p], b.xb2[p]};
+        const double vb[3] = {b.vb0[p], b.vb1[p], b.vb2[p]};
+        double ob[3], xk[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            ob[i] = 0.0;
+            xk[i] = 0.0;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                ob[i] += R[3 * j + i] * (vb[j] + a.dt_r * xb[j]);
+                xk[i] += R[3 * j + i] * xb[j];
+            }
+        }
+        // Boris vjp: out = vm + vr x sig + h E, vr = vm + vm x tau, sig = 2 tau / (1 + |tau|^2)
+        const double sig[3] = {sg * tau[0], sg * tau[1], sg * tau[2]};
+        double Eb[3], Bb[3], vmb[3], vrb[3], sigb[3], taub[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            vmb[d] = ob[d];
+            Eb[d] = h * ob[d];
+        }
+        vrb[0] = sig[1] * ob[2] - sig[2] * ob[1];
+        vrb[1] = sig[2] * ob[0] - sig[0] * ob[2];
+        vrb[2] = sig[0] * ob[1] - sig[1] * ob[0];
+        sigb[0] = ob[1] * vr[2] - ob[2] * vr[1];
+        sigb[1] = ob[2] * vr[0] - ob[0] * vr[2];
+        sigb[2] = ob[0] * vr[1] - ob[1] * vr[0];
+        vmb[0] += vrb[0] + (tau[1] * vrb[2] - tau[2] * vrb[1]);
+        vmb[1] += vrb[1] + (tau[2] * vrb[0] - tau[0] * vrb[2]);
+        vmb[2] += vrb[2] + (tau[0] * vrb[1] - tau[1] * vrb[0]);
+        taub[0] = vrb[1] * vm[2] - vrb[2] * vm[1];
+        taub[1] = vrb[2] * vm[0] - vrb[0] * vm[2];
+        taub[2] = vrb[0] * vm[1] - vrb[1] * vm[0];
+        const double st = sigb[0] * tau[0] + sigb[1] * tau[1] + sigb[2] * tau[2];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            taub[d] += 2.0 * sigb[d] / den - 4.0 * st * tau[d] / (den * den);
+            Bb[d] = h * taub[d];
+            Eb[d] += h * vmb[d];
+        }
+        // gather vjp: position and edge DoFs
+        double Eg[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double ae = cf[3 * k] * Eb[0] + cf[3 * k + 1] * Eb[1] + cf[3 * k + 2] * Eb[2];
+            const double cb = cf[12 + 3 * k] * Bb[0] + cf[12 + 3 * k + 1] * Bb[1] + cf[12 + 3 * k + 2] * Bb[2];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) xk[d] += g[k][d] * (ae + cb);
+            Eg[k] = Eb[0] * g[k][0] + Eb[1] * g[k][1] + Eb[2] * g[k][2];
+        }
+        constexpr int le[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+            const double we = l[le[e][0]] * Eg[le[e][1]] - l[le[e][1]] * Eg[le[e][0]];
+            ge[2 * e] = we * b.c;
+            ge[2 * e + 1] = -we * b.s;
+        }
+        b.vb0[p] = vmb[0];
+        b.vb1[p] = vmb[1];
+        b.vb2[p] = vmb[2];
+        b.xb0[p] = xk[0];
+        b.xb1[p] = xk[1];
+        b.xb2[p] = xk[2];
+    }
+    const WaveRuns runs = wave_runs(T);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) ge[k] = run_total(ge[k], runs);
+    if (T >= 0 && runs.head) {
+        const TetTopo *tp = a.topo + T;
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+            unsafeAtomicAdd(&b.grad_e[2 * (int64_t)tp->e[e]], ge[2 * e]);
+            unsafeAtomicAdd(&b.grad_e[2 * (int64_t)tp->e[e] + 1], ge[2 * e + 1]);
         }
     }
 }
@@ -799,6 +828,8 @@ struct etpic_ctx {
     bool has_mesh = false;
     TetTopo *d_topo = nullptr;
     double *d_grad64 = nullptr;
+    double *d_gpush64 = nullptr;     // nt*12: grad l_1..3 then 3 zeros
+    float *d_gpush32 = nullptr;
     void *d_coef = nullptr;          // nt*24 doubles (float table uses the first half)
     int32_t *d_v2e_ptr = nullptr;
     int32_t *d_v2e_code = nullptr;
@@ -809,31 +840,30 @@ struct etpic_ctx {
     unsigned *d_count = nullptr;     // nt+1 counting-sort counters
     unsigned *d_tilesum = nullptr;   // scan tile totals
     int64_t tiles = 0;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> timing;   // recorded (start, stop) pairs
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> spare;    // created, unused pairs
+    // HIP events bracketing the kernels of steps run with ETPIC_STEP_TIMING:
+    // 4 events per step (before the coefficient kernel, before and after the
+    // particle kernel, after the walk kernel)
+    std::vector<std::array<hipEvent_t, 4>> timing;
+    std::vector<std::array<hipEvent_t, 4>> spare;
 
-    int timing_pair(hipEvent_t *a, hipEvent_t *b) {
+    int timing_events(hipEvent_t **ev) {
         if (spare.empty()) {
-            hipEvent_t x, y;
-            HIP_TRY(hipEventCreate(&x));
-            HIP_TRY(hipEventCreate(&y));
-            spare.emplace_back(x, y);
+            std::array<hipEvent_t, 4> e{};
+            for (auto &x : e) HIP_TRY(hipEventCreate(&x));
+            spare.push_back(e);
         }
-        *a = spare.back().first;
-        *b = spare.back().second;
+        timing.push_back(spare.back());
         spare.pop_back();
-        timing.emplace_back(*a, *b);
+        *ev = timing.back().data();
         return ETPIC_OK;
     }
 
     template <typename Real>
-    int launch_step(const etpic_particles *p, const etpic_species *sp, const etpic_fields *f, double c, double s,
-                    double h, double dt, double *dG, double *rho, uint32_t flags, void *stream) {
-        hipStream_t st = static_cast<hipStream_t>(stream);
-        const int64_t nt = host.nt;
+    StepArgs<Real> step_args(const etpic_particles *p, const etpic_species *sp, double dt, double *dG,
+                             double *rho) const {
         StepArgs<Real> a{};
         a.n = p->n;
-        a.nt = nt;
+        a.nt = host.nt;
         a.lam1 = p->lam[0];
         a.lam2 = p->lam[1];
         a.lam3 = p->lam[2];
@@ -841,6 +871,8 @@ struct etpic_ctx {
         a.v1 = static_cast<Real *>(p->vel[1]);
         a.v2 = static_cast<Real *>(p->vel[2]);
         a.tet = p->tet;
+        a.coef = static_cast<const Real *>(d_coef);
+        a.gpush = gpush_table<Real>();
         a.grad = d_grad64;
         a.topo = d_topo;
         a.dG = dG;
@@ -849,27 +881,50 @@ struct etpic_ctx {
         a.walk_queue = d_walk_queue;
         a.walk_ctr = d_walk_ctr;
         a.qw = sp->q * sp->w;
-        a.h = (Real)h;
+        a.h = (Real)(sp->q * dt / (2.0 * sp->m));
         a.dt_r = (Real)dt;
-        hipEvent_t ev0 = nullptr, ev1 = nullptr;
+        return a;
+    }
+
+    // One step: carrier phase in float64 on the host (t_n = step*dt, argument
+    // reduced by libm), per-tet coefficients, particle kernel, walk kernel.
+    template <typename Real>
+    int step(const etpic_particles *p, const etpic_species *sp, const etpic_fields *f, int64_t step, double dt,
+             double omega, double *dG, double *rho, uint32_t flags, void *stream) {
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        const int64_t nt = host.nt;
+        const double t = (double)step * dt;
+        const double c = std::cos(omega * t), s = std::sin(omega * t);
+        StepArgs<Real> a = step_args<Real>(p, sp, dt, dG, rho);
+        hipEvent_t *ev = nullptr;
         if (flags & ETPIC_STEP_TIMING) {
-            if (int r = timing_pair(&ev0, &ev1)) return r;
-            HIP_TRY(hipEventRecord(ev0, st));
+            if (int r = timing_events(&ev)) return r;
+            HIP_TRY(hipEventRecord(ev[0], st));
         }
-        FieldPtrs F{reinterpret_cast<const double2 *>(f->e_env), f->e_dc, reinterpret_cast<const double2 *>(f->b_env),
-                    f->b_dc, c, s};
-        k_step<Real><<<grid_for(p->n), kBlock, 0, st>>>(a, F, (flags & ETPIC_STEP_XCD_REMAP) ? 1 : 0);
+        k_tet_coef<Real><<<grid_for(nt), kBlock, 0, st>>>(nt, d_topo, d_grad64,
+                                                          reinterpret_cast<const double2 *>(f->e_env), f->e_dc,
+                                                          reinterpret_cast<const double2 *>(f->b_env), f->b_dc, c, s,
+                                                          static_cast<Real *>(d_coef));
         HIP_TRY(hipGetLastError());
-        if (ev1) HIP_TRY(hipEventRecord(ev1, st));
+        if (ev) HIP_TRY(hipEventRecord(ev[1], st));
+        k_push<Real><<<grid_for(p->n), kBlock, 0, st>>>(a, (flags & ETPIC_STEP_XCD_REMAP) ? 1 : 0);
+        HIP_TRY(hipGetLastError());
+        if (ev) HIP_TRY(hipEventRecord(ev[2], st));
         k_walk<Real><<<kWalkBlocks, kBlock, 0, st>>>(a);
         HIP_TRY(hipGetLastError());
+        if (ev) HIP_TRY(hipEventRecord(ev[3], st));
         return ETPIC_OK;
     }
 
 
+    template <typename Real>
+    const Real *gpush_table() const;
+
     void release() {
         (void)hipFree(d_topo);
         (void)hipFree(d_grad64);
+        (void)hipFree(d_gpush64);
+        (void)hipFree(d_gpush32);
         (void)hipFree(d_coef);
         (void)hipFree(d_v2e_ptr);
         (void)hipFree(d_v2e_code);
@@ -877,6 +932,8 @@ struct etpic_ctx {
         (void)hipFree(d_tilesum);
         d_topo = nullptr;
         d_grad64 = nullptr;
+        d_gpush64 = nullptr;
+        d_gpush32 = nullptr;
         d_coef = nullptr;
         d_v2e_ptr = d_v2e_code = nullptr;
         d_count = d_tilesum = nullptr;
@@ -884,6 +941,11 @@ struct etpic_ctx {
     }
 };
 
+
+template <>
+const double *etpic_ctx::gpush_table<double>() const { return d_gpush64; }
+template <>
+const float *etpic_ctx::gpush_table<float>() const { return d_gpush32; }
 
 namespace {
 
@@ -895,12 +957,65 @@ int set_device(const etpic_ctx *ctx) {
 int check_particles(const etpic_ctx *ctx, const etpic_particles *p) {
     if (!p) return fail(ETPIC_EINVAL, "null particle descriptor");
     if (p->n < 0) return fail(ETPIC_EINVAL, "negative particle count");
-    if (p->n > (int64_t)kWalkQueueCap * kBlock) return fail(ETPIC_EINVAL, "particle count above 2^30");
+    if (p->n > (int64_t)kWalkQueueCap * 64) return fail(ETPIC_EINVAL, "particle count above 2^29");
     if (p->n == 0) return ETPIC_OK;
     for (int k = 0; k < 3; ++k)
         if (!p->lam[k] || !p->vel[k]) return fail(ETPIC_EINVAL, "null particle array");
     if (!p->tet) return fail(ETPIC_EINVAL, "null tet array");
     (void)ctx;
+    return ETPIC_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Workspace of the differentiation entry points: ncp checkpoints and
+// checkpoint_every segment slots, each a float64 particle state (lam, v, tet),
+// then a scratch current accumulator.
+struct AdjLayout {
+    size_t arr8, arr4, state, slots_off, dG_off, total;
+    int ncp;
+};
+
+AdjLayout adj_layout(int64_t n, int64_t ne, int nsteps, int every) {
+    AdjLayout L{};
+    L.arr8 = align256(sizeof(double) * (size_t)n);
+    L.arr4 = align256(sizeof(int32_t) * (size_t)n);
+    L.state = 6 * L.arr8 + L.arr4;
+    L.ncp = (nsteps + every - 1) / every;
+    L.slots_off = (size_t)L.ncp * L.state;
+    L.dG_off = L.slots_off + (size_t)every * L.state;
+    L.total = L.dG_off + align256(sizeof(double) * (size_t)ne);
+    return L;
+}
+
+etpic_particles state_view(void *ws, size_t off, const AdjLayout &L, int64_t n) {
+    char *b = static_cast<char *>(ws) + off;
+    etpic_particles q{};
+    q.n = n;
+    for (int k = 0; k < 3; ++k) {
+        q.lam[k] = reinterpret_cast<double *>(b + k * L.arr8);
+        q.vel[k] = b + (3 + k) * L.arr8;
+    }
+    q.tet = reinterpret_cast<int32_t *>(b + 6 * L.arr8);
+    q.id = nullptr;
+    return q;
+}
+
+int copy_state(const etpic_particles &src, const etpic_particles &dst, int64_t n, hipStream_t st) {
+    for (int k = 0; k < 3; ++k) {
+        HIP_TRY(hipMemcpyAsync(dst.lam[k], src.lam[k], sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(dst.vel[k], src.vel[k], sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    }
+    HIP_TRY(hipMemcpyAsync(dst.tet, src.tet, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
+    return ETPIC_OK;
+}
+
+int check_step_args(const etpic_ctx *ctx, const etpic_species *sp, const etpic_fields *f, double dt, double omega) {
+    if (!ctx || !sp || !f) return fail(ETPIC_EINVAL, "null argument");
+    if (!ctx->has_mesh) return fail(ETPIC_ESTATE, "no mesh uploaded");
+    if (!f->e_env || !f->b_env) return fail(ETPIC_EINVAL, "null envelope DoFs");
+    if (!(std::isfinite(dt) && std::isfinite(omega) && sp->m != 0.0 && std::isfinite(sp->q) && std::isfinite(sp->m)))
+        return fail(ETPIC_EINVAL, "non-finite dt / omega or zero mass");
     return ETPIC_OK;
 }
 
@@ -948,14 +1063,10 @@ int etpic_destroy(etpic_ctx *ctx) {
     (void)hipFree(ctx->d_red);
     (void)hipFree(ctx->d_walk_queue);
     (void)hipFree(ctx->d_walk_ctr);
-    for (auto &e : ctx->timing) {
-        (void)hipEventDestroy(e.first);
-        (void)hipEventDestroy(e.second);
-    }
-    for (auto &e : ctx->spare) {
-        (void)hipEventDestroy(e.first);
-        (void)hipEventDestroy(e.second);
-    }
+    for (auto &e : ctx->timing)
+        for (auto x : e) (void)hipEventDestroy(x);
+    for (auto &e : ctx->spare)
+        for (auto x : e) (void)hipEventDestroy(x);
     delete ctx;
     return ETPIC_OK;
 }
@@ -974,6 +1085,19 @@ int etpic_mesh_upload(etpic_ctx *ctx, int64_t n_vert, const double *xyz_host, in
     const int64_t nt = M.nt;
     HIP_TRY(hipMalloc(&ctx->d_topo, sizeof(TetTopo) * nt));
     HIP_TRY(hipMalloc(&ctx->d_grad64, sizeof(double) * 12 * nt));
+    HIP_TRY(hipMalloc(&ctx->d_gpush64, sizeof(double) * 12 * nt));
+    HIP_TRY(hipMalloc(&ctx->d_gpush32, sizeof(float) * 12 * nt));
+    {
+        std::vector<double> gp64((size_t)nt * 12, 0.0);
+        std::vector<float> gp32((size_t)nt * 12, 0.0f);
+        for (int64_t t = 0; t < nt; ++t)
+            for (int k = 0; k < 9; ++k) {
+                gp64[12 * t + k] = M.grad[12 * t + 3 + k];
+                gp32[12 * t + k] = (float)M.grad[12 * t + 3 + k];
+            }
+        HIP_TRY(hipMemcpy(ctx->d_gpush64, gp64.data(), sizeof(double) * 12 * nt, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(ctx->d_gpush32, gp32.data(), sizeof(float) * 12 * nt, hipMemcpyHostToDevice));
+    }
     HIP_TRY(hipMalloc(&ctx->d_coef, sizeof(double) * 24 * nt));
     HIP_TRY(hipMalloc(&ctx->d_v2e_ptr, sizeof(int32_t) * (M.nv + 1)));
     HIP_TRY(hipMalloc(&ctx->d_v2e_code, sizeof(int32_t) * 2 * M.ne));
@@ -1033,21 +1157,110 @@ int etpic_mesh_faces(const etpic_ctx *ctx, int32_t *face_vert_host) {
 int etpic_gather_push_deposit(etpic_ctx *ctx, const etpic_particles *p, int precision, const etpic_species *sp,
                               const etpic_fields *f, int64_t step, double dt, double omega, double *dG,
                               double *rho, uint32_t flags, void *stream) {
-    if (!ctx || !sp || !f || !dG) return fail(ETPIC_EINVAL, "null argument");
-    if (!ctx->has_mesh) return fail(ETPIC_ESTATE, "no mesh uploaded");
+    if (int r = check_step_args(ctx, sp, f, dt, omega)) return r;
+    if (!dG) return fail(ETPIC_EINVAL, "null current accumulator");
     if (int r = check_particles(ctx, p)) return r;
-    if (!f->e_env || !f->b_env) return fail(ETPIC_EINVAL, "null envelope DoFs");
     if (precision != ETPIC_FP64 && precision != ETPIC_MIXED) return fail(ETPIC_EINVAL, "bad precision %d", precision);
-    if (!(std::isfinite(dt) && std::isfinite(omega) && sp->m != 0.0 && std::isfinite(sp->q) && std::isfinite(sp->m)))
-        return fail(ETPIC_EINVAL, "non-finite dt / omega or zero mass");
     if (p->n == 0) return ETPIC_OK;
     if (int r = set_device(ctx)) return r;
-    // carrier phase in float64 on the host (t_n = step*dt), argument reduced by libm
-    const double t = (double)step * dt;
-    const double c = std::cos(omega * t), s = std::sin(omega * t);
-    const double h = sp->q * dt / (2.0 * sp->m);
-    if (precision == ETPIC_FP64) return ctx->launch_step<double>(p, sp, f, c, s, h, dt, dG, rho, flags, stream);
-    return ctx->launch_step<float>(p, sp, f, c, s, h, dt, dG, rho, flags, stream);
+    if (precision == ETPIC_FP64) return ctx->step<double>(p, sp, f, step, dt, omega, dG, rho, flags, stream);
+    return ctx->step<float>(p, sp, f, step, dt, omega, dG, rho, flags, stream);
+}
+
+int etpic_adjoint_workspace(const etpic_ctx *ctx, int64_t n, int nsteps, int checkpoint_every, size_t *bytes_out) {
+    if (!ctx || !bytes_out) return fail(ETPIC_EINVAL, "null argument");
+    if (!ctx->has_mesh) return fail(ETPIC_ESTATE, "no mesh uploaded");
+    if (n < 0 || nsteps < 0 || checkpoint_every < 1) return fail(ETPIC_EINVAL, "bad sizes");
+    *bytes_out = adj_layout(n, ctx->host.ne, nsteps, checkpoint_every).total;
+    return ETPIC_OK;
+}
+
+int etpic_forward_checkpointed(etpic_ctx *ctx, const etpic_particles *p, const etpic_species *sp,
+                               const etpic_fields *f, int64_t step0, int nsteps, double dt, double omega,
+                               int checkpoint_every, void *workspace, size_t workspace_bytes, double *dG,
+                               void *stream) {
+    if (int r = check_step_args(ctx, sp, f, dt, omega)) return r;
+    if (int r = check_particles(ctx, p)) return r;
+    if (nsteps < 0 || checkpoint_every < 1 || !workspace) return fail(ETPIC_EINVAL, "bad sizes or null workspace");
+    const AdjLayout L = adj_layout(p->n, ctx->host.ne, nsteps, checkpoint_every);
+    if (workspace_bytes < L.total) return fail(ETPIC_EINVAL, "workspace too small (%zu < %zu)", workspace_bytes, L.total);
+    if (p->n == 0 || nsteps == 0) return ETPIC_OK;
+    if (int r = set_device(ctx)) return r;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double *acc = dG ? dG : reinterpret_cast<double *>(static_cast<char *>(workspace) + L.dG_off);
+    for (int k = 0; k < nsteps; ++k) {
+        if (k % checkpoint_every == 0)
+            if (int r = copy_state(*p, state_view(workspace, (size_t)(k / checkpoint_every) * L.state, L, p->n), p->n, st))
+                return r;
+        if (int r = ctx->step<double>(p, sp, f, step0 + k, dt, omega, acc, nullptr, ETPIC_STEP_XCD_REMAP, stream))
+            return r;
+    }
+    return ETPIC_OK;
+}
+
+int etpic_backward(etpic_ctx *ctx, int64_t n, const etpic_species *sp, const etpic_fields *f, int64_t step0,
+                   int nsteps, double dt, double omega, int checkpoint_every, void *workspace,
+                   size_t workspace_bytes, double *const vbar[3], double *const xbar[3], double *grad_e,
+                   void *stream) {
+    if (int r = check_step_args(ctx, sp, f, dt, omega)) return r;
+    if (n < 0 || nsteps < 0 || checkpoint_every < 1 || !workspace || !grad_e || !vbar || !xbar)
+        return fail(ETPIC_EINVAL, "bad sizes or null pointer");
+    for (int k = 0; k < 3; ++k)
+        if (!vbar[k] || !xbar[k]) return fail(ETPIC_EINVAL, "null adjoint array");
+    if (n > (int64_t)kWalkQueueCap * 64) return fail(ETPIC_EINVAL, "particle count above 2^29");
+    const AdjLayout L = adj_layout(n, ctx->host.ne, nsteps, checkpoint_every);
+    if (workspace_bytes < L.total) return fail(ETPIC_EINVAL, "workspace too small (%zu < %zu)", workspace_bytes, L.total);
+    if (n == 0 || nsteps == 0) return ETPIC_OK;
+    if (int r = set_device(ctx)) return r;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double *scratch_dG = reinterpret_cast<double *>(static_cast<char *>(workspace) + L.dG_off);
+    const int64_t nt = ctx->host.nt;
+    for (int seg = L.ncp - 1; seg >= 0; --seg) {
+        const int k0 = seg * checkpoint_every, k1 = std::min(nsteps, k0 + checkpoint_every);
+        // recompute the states before steps k0 .. k1-1 into the slots
+        const etpic_particles first = state_view(workspace, L.slots_off, L, n);
+        if (int r = copy_state(state_view(workspace, (size_t)seg * L.state, L, n), first, n, st)) return r;
+        for (int k = k0; k < k1 - 1; ++k) {
+            const etpic_particles cur = state_view(workspace, L.slots_off + (size_t)(k - k0) * L.state, L, n);
+            const etpic_particles nxt = state_view(workspace, L.slots_off + (size_t)(k - k0 + 1) * L.state, L, n);
+            if (int r = copy_state(cur, nxt, n, st)) return r;
+            if (int r = ctx->step<double>(&nxt, sp, f, step0 + k, dt, omega, scratch_dG, nullptr,
+                                          ETPIC_STEP_XCD_REMAP, stream))
+                return r;
+        }
+        for (int k = k1 - 1; k >= k0; --k) {
+            const etpic_particles cur = state_view(workspace, L.slots_off + (size_t)(k - k0) * L.state, L, n);
+            const double t = (double)(step0 + k) * dt;
+            const double c = std::cos(omega * t), s = std::sin(omega * t);
+            k_tet_coef<double><<<grid_for(nt), kBlock, 0, st>>>(nt, ctx->d_topo, ctx->d_grad64,
+                                                                reinterpret_cast<const double2 *>(f->e_env), f->e_dc,
+                                                                reinterpret_cast<const double2 *>(f->b_env), f->b_dc,
+                                                                c, s, static_cast<double *>(ctx->d_coef));
+            HIP_TRY(hipGetLastError());
+            StepArgs<double> a = ctx->step_args<double>(&cur, sp, dt, scratch_dG, nullptr);
+            AdjArgs b{};
+            b.lam1 = cur.lam[0];
+            b.lam2 = cur.lam[1];
+            b.lam3 = cur.lam[2];
+            b.v0 = static_cast<const double *>(cur.vel[0]);
+            b.v1 = static_cast<const double *>(cur.vel[1]);
+            b.v2 = static_cast<const double *>(cur.vel[2]);
+            b.tet = cur.tet;
+            b.vb0 = vbar[0];
+            b.vb1 = vbar[1];
+            b.vb2 = vbar[2];
+            b.xb0 = xbar[0];
+            b.xb1 = xbar[1];
+            b.xb2 = xbar[2];
+            b.grad_e = grad_e;
+            b.c = c;
+            b.s = s;
+            b.dt = dt;
+            k_adjoint<<<grid_for(n), kBlock, 0, st>>>(a, b);
+            HIP_TRY(hipGetLastError());
+        }
+    }
+    return ETPIC_OK;
 }
 
 int etpic_vertex_charge(etpic_ctx *ctx, const etpic_particles *p, const etpic_species *sp, double *rho,
@@ -1111,17 +1324,19 @@ int etpic_sort(etpic_ctx *ctx, const etpic_particles *src, const etpic_particles
     return ETPIC_OK;
 }
 
-int etpic_kernel_time(etpic_ctx *ctx, double *total_ms_out, int64_t *launches_out, int reset) {
-    if (!ctx) return fail(ETPIC_EINVAL, "null context");
+int etpic_kernel_time(etpic_ctx *ctx, double ms_out[3], int64_t *launches_out, int reset) {
+    if (!ctx || !ms_out) return fail(ETPIC_EINVAL, "null argument");
     if (int r = set_device(ctx)) return r;
-    double total = 0.0;
+    double tot[3] = {0.0, 0.0, 0.0};
     for (auto &e : ctx->timing) {
-        HIP_TRY(hipEventSynchronize(e.second));
-        float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, e.first, e.second));
-        total += ms;
+        HIP_TRY(hipEventSynchronize(e[3]));
+        float m[3] = {0.f, 0.f, 0.f};
+        HIP_TRY(hipEventElapsedTime(&m[0], e[1], e[2]));   // particle kernel
+        HIP_TRY(hipEventElapsedTime(&m[1], e[0], e[1]));   // coefficient kernel
+        HIP_TRY(hipEventElapsedTime(&m[2], e[2], e[3]));   // walk kernel
+        for (int k = 0; k < 3; ++k) tot[k] += m[k];
     }
-    if (total_ms_out) *total_ms_out = total;
+    for (int k = 0; k < 3; ++k) ms_out[k] = tot[k];
     if (launches_out) *launches_out = (int64_t)ctx->timing.size();
     if (reset) {
         for (auto &e : ctx->timing) ctx->spare.push_back(e);

@@ -27,6 +27,7 @@ EXPORTS = (
     "etpic_last_error", "etpic_create", "etpic_destroy", "etpic_mesh_upload", "etpic_mesh_canonical",
     "etpic_mesh_counts", "etpic_mesh_edges", "etpic_mesh_faces", "etpic_gather_push_deposit", "etpic_sort",
     "etpic_vertex_charge", "etpic_gauss_residual", "etpic_kernel_time", "etpic_check",
+    "etpic_adjoint_workspace", "etpic_forward_checkpointed", "etpic_backward",
 )
 
 
@@ -76,6 +77,13 @@ def lib():
     L.etpic_vertex_charge.argtypes = [vp, C.POINTER(_Particles), C.POINTER(_Species), vp, vp]
     L.etpic_gauss_residual.argtypes = [vp, vp, vp, vp, dp, vp]
     L.etpic_kernel_time.argtypes = [vp, dp, i64p, C.c_int]
+    L.etpic_adjoint_workspace.argtypes = [vp, C.c_int64, C.c_int, C.c_int, C.POINTER(C.c_size_t)]
+    L.etpic_forward_checkpointed.argtypes = [vp, C.POINTER(_Particles), C.POINTER(_Species), C.POINTER(_Fields),
+                                             C.c_int64, C.c_int, C.c_double, C.c_double, C.c_int, vp, C.c_size_t,
+                                             vp, vp]
+    L.etpic_backward.argtypes = [vp, C.c_int64, C.POINTER(_Species), C.POINTER(_Fields), C.c_int64, C.c_int,
+                                 C.c_double, C.c_double, C.c_int, vp, C.c_size_t, C.c_void_p * 3, C.c_void_p * 3,
+                                 vp, vp]
     L.etpic_check.argtypes = [vp, vp, C.POINTER(C.c_uint32)]
     for name in EXPORTS:
         if name != "etpic_last_error":
@@ -293,11 +301,40 @@ class Context:
         return float(out[0]), float(out[1])
 
     def kernel_time(self, reset=True):
-        """(total ms, launches) of the particle kernel in steps run with STEP_TIMING."""
-        ms = C.c_double(0.0)
+        """({"push", "coef", "walk"} total ms, steps) of the kernels of steps run with STEP_TIMING."""
+        ms = np.zeros(3)
         n = C.c_int64(0)
-        _chk(lib().etpic_kernel_time(self._h, C.byref(ms), C.byref(n), int(bool(reset))))
-        return ms.value, n.value
+        _chk(lib().etpic_kernel_time(self._h, _np_ptr(ms, C.c_double), C.byref(n), int(bool(reset))))
+        return {"push": float(ms[0]), "coef": float(ms[1]), "walk": float(ms[2])}, n.value
+
+    # differentiation (float64) -----------------------------------------------------
+    def adjoint_workspace_bytes(self, n, nsteps, checkpoint_every):
+        b = C.c_size_t(0)
+        _chk(lib().etpic_adjoint_workspace(self._h, int(n), int(nsteps), int(checkpoint_every), C.byref(b)))
+        return b.value
+
+    def forward_checkpointed(self, parts, species, fields, step0, nsteps, dt, omega, checkpoint_every, workspace,
+                             dG=None, stream=None):
+        d = parts.desc()
+        sp = species.c()
+        fd = fields.desc()
+        _chk(lib().etpic_forward_checkpointed(self._h, C.byref(d), C.byref(sp), C.byref(fd), int(step0), int(nsteps),
+                                              float(dt), float(omega), int(checkpoint_every),
+                                              C.c_void_p(workspace.data_ptr()), workspace.numel(), _dptr(dG),
+                                              _stream(stream)))
+
+    def backward(self, n, species, fields, step0, nsteps, dt, omega, checkpoint_every, workspace, vbar, xbar,
+                 grad_e, stream=None):
+        """vbar, xbar: float64 [3, n] (in: final adjoints, out: initial); grad_e float64 [N_e, 2] accumulates."""
+        for t in (vbar, xbar):
+            assert t.is_contiguous() and t.shape[0] == 3
+        sp = species.c()
+        fd = fields.desc()
+        vb = (C.c_void_p * 3)(*[vbar[k].data_ptr() for k in range(3)])
+        xb = (C.c_void_p * 3)(*[xbar[k].data_ptr() for k in range(3)])
+        _chk(lib().etpic_backward(self._h, int(n), C.byref(sp), C.byref(fd), int(step0), int(nsteps), float(dt),
+                                  float(omega), int(checkpoint_every), C.c_void_p(workspace.data_ptr()),
+                                  workspace.numel(), vb, xb, _dptr(grad_e), _stream(stream)))
 
     def check(self, stream=None, raise_on_error=True):
         word = C.c_uint32(0)

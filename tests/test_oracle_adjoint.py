@@ -1,0 +1,95 @@
+"""Pins of the oracle's reverse-mode gradient of the particle steps.
+
+L = kinetic energy after K steps, sum_p m w |v_p|^2 / 2; gradient with respect
+to the complex edge envelope e~ in the convention dL/dRe + j dL/dIm (the one
+PyTorch uses for real losses of complex tensors)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2208_12795_amd import synth
+
+
+def ke_and_final(M, w, tet, lam, vel, e_env, nsteps, step0=0):
+    t, l, v = tet.copy(), lam.copy(), vel.copy()
+    for s in range(nsteps):
+        rc, _ = M.step(t, l, v, q=w.q, m=w.m, w=w.w, step=step0 + s, dt=w.dt, omega=w.omega, e_env=e_env,
+                       b_env=w.b_env, b_dc=w.b_dc, dG=np.zeros(M.ne))
+        assert rc == 0
+    return v
+
+
+def test_torch_complex_gradient_convention():
+    """PyTorch's gradient of a real loss of a complex tensor is dL/dRe + j dL/dIm:
+    for L = |z|^2 it is 2z.  The adjoint returns its gradient in this form."""
+    torch = pytest.importorskip("torch")
+    z = torch.tensor([1.5 - 0.5j, -2.0 + 3.0j], dtype=torch.complex128, requires_grad=True)
+    (z.abs() ** 2).sum().backward()
+    assert torch.allclose(z.grad, 2 * z.detach())
+
+
+def test_adjoint_uniform_field_closed_form(ora):
+    """Uniform envelope alpha*E0 x-hat, B = 0: v_x(K) = v_x(0) + (q/m) E0 dt sum_n Re(alpha e^{j w t_n}),
+    so dKE/dalpha (convention d/dRe + j d/dIm) = m w v_x (q/m) E0 dt sum_n e^{-j w t_n}, and by the chain
+    rule it equals sum_e grad_e (E0 . d_e) for e~_e = alpha E0 . d_e."""
+    xyz, tv = synth.kuhn_mesh((3, 3, 3), (1.0, 1.0, 1.0), 0.1, np.random.default_rng(21))
+    M = ora.OracleMesh(xyz, tv)
+    ed = M.edges()
+    E0 = 800.0
+    u = (xyz[ed[:, 1]] - xyz[ed[:, 0]]) @ np.array([E0, 0.0, 0.0])
+    alpha = 0.7 - 0.4j
+    rng = np.random.default_rng(3)
+    n = 5
+    tet = rng.integers(0, M.nt, n).astype(np.int32)
+    g = rng.standard_exponential((n, 4))
+    lam = np.ascontiguousarray((g / g.sum(1, keepdims=True))[:, 1:])
+    vel = rng.standard_normal((n, 3)) * 1e4
+    omega, dt, K = 2 * np.pi * 1e9, 1e-11, 17
+    q, m, wgt = synth.Q_E, synth.M_E, 2.0
+    zero_b = np.zeros(M.nf, complex)
+    t, l, v = tet.copy(), lam.copy(), vel.copy()
+    for s in range(K):
+        M.step(t, l, v, q=q, m=m, w=wgt, step=s, dt=dt, omega=omega, e_env=alpha * u, b_env=zero_b,
+               dG=np.zeros(M.ne))
+    rc, grad, vb0, xb0 = M.vjp(tet, lam, vel, q=q, m=m, w=wgt, step0=0, nsteps=K, dt=dt, omega=omega,
+                               e_env=alpha * u, b_env=zero_b, vbar=m * wgt * v)
+    assert rc == 0
+    phase = sum(np.exp(-1j * omega * s * dt) for s in range(K))
+    ref = (m * wgt * v[:, 0]).sum() * (q / m) * E0 * dt * phase
+    got = (grad * u).sum()
+    assert abs(got - ref) < 1e-10 * abs(ref)
+    # velocity adjoint of a uniform-field run is the seed itself (dv_K/dv_0 = I)
+    assert np.allclose(vb0, m * wgt * v, rtol=1e-12)
+    assert np.allclose(xb0, 0.0, atol=1e-30)
+
+
+@pytest.mark.parametrize("omega_scale", [1.0, 0.0])
+def test_adjoint_against_central_differences(ora, omega_scale):
+    """Full gradient (edge gather, B rotation, position feedback through the
+    affine fields, crossings) against central differences of the oracle's own
+    forward run, in factored form sum_p m w (v+ - v-).(v+ + v-)/2 / (2h)."""
+    w = synth.make_workload(1, n_particles=300, omega=None if omega_scale else 0.0)
+    M = ora.OracleMesh(w.xyz, w.tet_vert)
+    K = 20
+    vK = ke_and_final(M, w, w.tet, w.lam, w.vel, w.e_env, K)
+    rc, grad, _, _ = M.vjp(w.tet, w.lam, w.vel, q=w.q, m=w.m, w=w.w, step0=0, nsteps=K, dt=w.dt, omega=w.omega,
+                           e_env=w.e_env, b_env=w.b_env, b_dc=w.b_dc, vbar=w.m * w.w * vK)
+    assert rc == 0
+    rng = np.random.default_rng(5)
+    # probe edges the particles actually see
+    seen = np.unique(M.tet_edges()[w.tet].ravel())
+    probes = rng.choice(seen, 12, replace=False)
+    h = 1e-3 * np.abs(w.e_env).max()
+    for e in probes:
+        for part, unit in (("re", 1.0), ("im", 1j)):
+            ep = w.e_env.copy()
+            em = w.e_env.copy()
+            ep[e] += unit * h
+            em[e] -= unit * h
+            vp = ke_and_final(M, w, w.tet, w.lam, w.vel, ep, K)
+            vm = ke_and_final(M, w, w.tet, w.lam, w.vel, em, K)
+            fd = (0.5 * w.m * w.w * ((vp - vm) * (vp + vm)).sum()) / (2 * h)
+            g = grad[e].real if part == "re" else grad[e].imag
+            scale = np.abs(grad).max()
+            assert abs(fd - g) <= 1e-6 * scale + 1e-6 * abs(g), (e, part, fd, g)

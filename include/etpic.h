@@ -213,6 +213,44 @@ int etpic_backward(etpic_ctx *ctx, int64_t n, const etpic_species *sp, const etp
                    size_t workspace_bytes, double *const vbar[3], double *const xbar[3], double *grad_e,
                    void *stream);
 
+/* ---- Field-coefficient update (side path, timed separately) ---------------
+ * Eliminating the face envelope from the envelope Maxwell curl equations
+ * (Formulation: the curl equations with the carrier) and testing with the
+ * Whitney edge functions gives, for the complex edge envelope e,
+ *     M e'' + 2 j w M e' + (K - w^2 M) e = -e^{-j w t} g''
+ * with M = eps-weighted edge mass matrix, K = (1/mu)-weighted curl-curl
+ * matrix (Appendix A: [*eps] and the curl matrices) and g the deposited edge
+ * DoFs of G.  It is stepped with Newmark-beta, gamma = 1/2, beta = 1/4
+ * (Formulation), in acceleration form; the implicit system
+ *     A = (1 + j w dt - w^2 dt^2 / 4) M + (dt^2 / 4) K
+ * is complex symmetric and solved by Jacobi-preconditioned COCG with a CSR
+ * sparse matrix-vector product.  Boundary edges are perfect-conductor
+ * (tangential field zero).  The face envelope follows the envelope Faraday law
+ * (j w + d/dt) b = -C e (C the face-edge incidence, (C e)_f = e_ab + e_bc - e_ac
+ * for face (a<b<c)) with the trapezoidal rule.  This simplified update stands
+ * in for the paper's quasi-Helmholtz solver, which is not built. */
+
+/* Assemble M, K (host), the preconditioner and the device work vectors for
+ * field step dt, carrier w, permittivity eps, permeability mu (allocates). */
+int etpic_field_setup(etpic_ctx *ctx, double dt, double omega, double eps, double mu);
+
+/* Number of stored entries of the CSR pattern (M and K share it). */
+int etpic_field_nnz(const etpic_ctx *ctx, int64_t *nnz_out);
+
+/* y = alpha M x + beta K x for complex x, y (2*N_e float64 each, device),
+ * complex alpha, real beta.  Asynchronous. */
+int etpic_field_spmv(etpic_ctx *ctx, const double *x, double *y, double alpha_re, double alpha_im, double beta,
+                     void *stream);
+
+/* One field step to time t_next: u = e, v = e', a = e'' (2*N_e float64 each,
+ * complex, device, updated in place), b = face envelope (2*N_f, in place),
+ * gdd = g'' at t_next (N_e float64, device, NULL = 0).  COCG stops when
+ * ||r|| / ||rhs|| <= tol (checked every 5 iterations) or after max_iter;
+ * *iters_out, *resid_out report it.  Synchronises `stream`.  ENOCONV (state
+ * left unchanged) if the tolerance is not reached. */
+int etpic_field_step(etpic_ctx *ctx, double t_next, double *u, double *v, double *a, double *b, const double *gdd,
+                     double tol, int max_iter, int *iters_out, double *resid_out, void *stream);
+
 /* Kernel times of the steps launched with ETPIC_STEP_TIMING since the last
  * reset, from HIP events recorded on the launch stream around each kernel:
  * ms_out[0] = particle kernel (gather, push, in-tet deposit), ms_out[1] =

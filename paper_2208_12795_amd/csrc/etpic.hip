@@ -26,6 +26,7 @@
 #include <algorithm>
 
 #include "etpic.h"
+#include "field_host.hpp"
 #include "mesh_host.hpp"
 
 using etpic::TetTopo;
@@ -52,7 +53,7 @@ int fail(int code, const char *fmt, ...) {
 
 constexpr int kBlock = 256;
 constexpr unsigned kWalkQueueCap = 1u << 23;  // wavefronts; bounds N_p by 2^29
-constexpr unsigned kWalkBlocks = 1024;        // grid of the walk kernel
+constexpr unsigned kWalkBlocks = 256;         // grid of the walk kernel
 
 // Runs of equal key among the 64 lanes of a wavefront (particles are kept
 // sorted by tet, so neighbouring lanes mostly share a key).  head: first lane
@@ -88,71 +89,90 @@ __device__ __forceinline__ T run_total(T x, const WaveRuns &r) {
 }
 
 // ------------------------------------------------------------------ per-tet coefficients
-// W1_ij = l_i grad l_j - l_j grad l_i  =>  eps_ij W1_ij adds eps_ij grad l_j to A_i and
-// -eps_ij grad l_i to A_j.  W2 of face (a<b<c) = 2(l_a gb x gc + l_b gc x ga + l_c ga x gb).
+// Inside a tet both field expansions are affine in the barycentrics:
+//   E = sum_k l_k A_k,  A_k = sum_{j != k} sign(j - k) eps_{kj} grad l_j
+//     (from W1_ij = l_i grad l_j - l_j grad l_i, edge (i<j) oriented i -> j);
+//   B = sum_k l_k C_k,  C_k = 2 sum_{faces f containing k} beta_f (grad l_a x grad l_b)
+//     (from W2 of face (a<b<c) = 2(l_a gb x gc + l_b gc x ga + l_c ga x gb); (k, a, b)
+//     the cyclic order of f's ascending triple starting at k).
+// eps, beta: the real parts Re{dof e^{jwt}} + dc of the edge and face DoFs at this
+// step.  Two threads per tet: one for A_0..3, one for C_0..3.
+struct FieldPtrs {
+    const double2 *e_env;
+    const double *e_dc;
+    const double2 *b_env;
+    const double *b_dc;
+    double c, s;   // cos(w t_n), sin(w t_n)
+};
+
+// local edge index of the vertex pair {i, j}, i < j
+__host__ __device__ constexpr int local_edge(int i, int j) { return i == 0 ? j - 1 : (i == 1 ? j + 1 : 5); }
+
+template <int K>
+__device__ __forceinline__ void coef_A(const int32_t *tp, const double g[4][3], const FieldPtrs &F, double A[3]) {
+    A[0] = A[1] = A[2] = 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (j == K) continue;
+        const int id = tp[local_edge(j < K ? j : K, j < K ? K : j)];
+        const double2 z = F.e_env[id];
+        double eps = z.x * F.c - z.y * F.s;
+        if (F.e_dc) eps += F.e_dc[id];
+        if (j < K) eps = -eps;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) A[d] += eps * g[j][d];
+    }
+}
+
+template <int K>
+__device__ __forceinline__ void coef_C(const int32_t *tp, const double g[4][3], const FieldPtrs &F, double Cv[3]) {
+    Cv[0] = Cv[1] = Cv[2] = 0.0;
+    constexpr int lf[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        if (f == K) continue;
+        const int a = lf[f][0] == K ? lf[f][1] : (lf[f][1] == K ? lf[f][2] : lf[f][0]);
+        const int b = lf[f][0] == K ? lf[f][2] : (lf[f][1] == K ? lf[f][0] : lf[f][1]);
+        const int id = tp[6 + f];
+        const double2 z = F.b_env[id];
+        double beta = z.x * F.c - z.y * F.s;
+        if (F.b_dc) beta += F.b_dc[id];
+        beta *= 2.0;
+        Cv[0] += beta * (g[a][1] * g[b][2] - g[a][2] * g[b][1]);
+        Cv[1] += beta * (g[a][2] * g[b][0] - g[a][0] * g[b][2]);
+        Cv[2] += beta * (g[a][0] * g[b][1] - g[a][1] * g[b][0]);
+    }
+}
+
 template <typename Real>
 __global__ void __launch_bounds__(kBlock) k_tet_coef(int64_t nt, const TetTopo *__restrict__ topo,
-                                                     const double *__restrict__ grad,
-                                                     const double2 *__restrict__ e_env,
-                                                     const double *__restrict__ e_dc,
-                                                     const double2 *__restrict__ b_env,
-                                                     const double *__restrict__ b_dc, double c, double s,
+                                                     const double *__restrict__ grad, FieldPtrs F,
                                                      Real *__restrict__ coef) {
-    int64_t T = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t T = t >> 1;
+    const int part = (int)(t & 1);   // 0: A_0..3 (edges), 1: C_0..3 (faces)
     if (T >= nt) return;
-    const TetTopo tp = topo[T];
     double g[4][3];
 #pragma unroll
     for (int k = 0; k < 4; ++k)
 #pragma unroll
         for (int d = 0; d < 3; ++d) g[k][d] = grad[T * 12 + 3 * k + d];
-    double A[4][3] = {}, C[4][3] = {};
-    const int le[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
-    const int lf[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
-#pragma unroll
-    for (int e = 0; e < 6; ++e) {
-        const int i = le[e][0], j = le[e][1];
-        const double2 z = e_env[tp.e[e]];
-        double eps = z.x * c - z.y * s;
-        if (e_dc) eps += e_dc[tp.e[e]];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            A[i][d] += eps * g[j][d];
-            A[j][d] -= eps * g[i][d];
-        }
+    const int32_t *tp = reinterpret_cast<const int32_t *>(topo + T);
+    double o[12];
+    if (part == 0) {
+        coef_A<0>(tp, g, F, o);
+        coef_A<1>(tp, g, F, o + 3);
+        coef_A<2>(tp, g, F, o + 6);
+        coef_A<3>(tp, g, F, o + 9);
+    } else {
+        coef_C<0>(tp, g, F, o);
+        coef_C<1>(tp, g, F, o + 3);
+        coef_C<2>(tp, g, F, o + 6);
+        coef_C<3>(tp, g, F, o + 9);
     }
+    Real *dst = coef + T * 24 + 12 * part;   // A_k at 3k, C_k at 12 + 3k
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
-        const int a = lf[f][0], b = lf[f][1], cc = lf[f][2];
-        const double2 z = b_env[tp.f[f]];
-        double beta = z.x * c - z.y * s;
-        if (b_dc) beta += b_dc[tp.f[f]];
-        beta *= 2.0;
-        double x_bc[3], x_ca[3], x_ab[3];
-        x_bc[0] = g[b][1] * g[cc][2] - g[b][2] * g[cc][1];
-        x_bc[1] = g[b][2] * g[cc][0] - g[b][0] * g[cc][2];
-        x_bc[2] = g[b][0] * g[cc][1] - g[b][1] * g[cc][0];
-        x_ca[0] = g[cc][1] * g[a][2] - g[cc][2] * g[a][1];
-        x_ca[1] = g[cc][2] * g[a][0] - g[cc][0] * g[a][2];
-        x_ca[2] = g[cc][0] * g[a][1] - g[cc][1] * g[a][0];
-        x_ab[0] = g[a][1] * g[b][2] - g[a][2] * g[b][1];
-        x_ab[1] = g[a][2] * g[b][0] - g[a][0] * g[b][2];
-        x_ab[2] = g[a][0] * g[b][1] - g[a][1] * g[b][0];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            C[a][d] += beta * x_bc[d];
-            C[b][d] += beta * x_ca[d];
-            C[cc][d] += beta * x_ab[d];
-        }
-    }
-    Real *o = coef + T * 24;
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            o[3 * k + d] = (Real)A[k][d];
-            o[12 + 3 * k + d] = (Real)C[k][d];
-        }
+    for (int d = 0; d < 12; ++d) dst[d] = (Real)o[d];
 }
 
 // ------------------------------------------------------------------ particle step
@@ -817,11 +837,326 @@ __global__ void __launch_bounds__(kBlock) k_scatter(int64_t n, int64_t nt, const
     if (src.id && dst.id) dst.id[q] = src.id[p];
 }
 
+// ------------------------------------------------------------------ field update
+// Implicit envelope field step on the Whitney edge space (a side path of the
+// particle step, timed separately).  Eliminating B~ from the envelope Maxwell
+// equations (Formulation: the curl equations with the carrier) and testing
+// with W1 gives
+//   M e'' + 2 j w M e' + (K - w^2 M) e = f,   f = -e^{-j w t} g''
+// (M = eps-mass, K = curl-curl, g the deposited edge DoFs of G), stepped with
+// Newmark-beta (gamma = 1/2, beta = 1/4, Formulation) in acceleration form:
+//   A a_{n+1} = f_{n+1} - M (2 j w v* - w^2 u*) - K u*,   A = (1 + j w dt - w^2 dt^2/4) M + (dt^2/4) K,
+//   u* = u + dt v + dt^2/4 a,  v* = v + dt/2 a,  u_{n+1} = u* + dt^2/4 a_{n+1},  v_{n+1} = v* + dt/2 a_{n+1}.
+// A is complex symmetric: Jacobi-preconditioned COCG.  The face envelope
+// follows the discrete envelope Faraday law (j w + d/dt) b = -C e with the
+// trapezoidal rule.
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+    const double d = b.x * b.x + b.y * b.y;
+    return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+
+constexpr int kRowLanes = 8;   // lanes per CSR row
+
+struct FieldCsr {
+    int64_t ne;
+    const int32_t *rowptr, *col;
+    const double *M, *K;
+    const uint8_t *dir;
+};
+
+// Row-wise (M x1)_i and (K x2)_i with kRowLanes lanes per row, summed across
+// those lanes; every lane of the group returns the totals.
+__device__ __forceinline__ void csr_row2(const FieldCsr &S, int64_t row, int sub, const double2 *__restrict__ x1,
+                                         const double2 *__restrict__ x2, double2 &m1, double2 &k2) {
+    m1 = make_double2(0.0, 0.0);
+    k2 = make_double2(0.0, 0.0);
+    if (row < S.ne) {
+        for (int32_t j = S.rowptr[row] + sub; j < S.rowptr[row + 1]; j += kRowLanes) {
+            const int32_t c = S.col[j];
+            const double mv = S.M[j], kv = S.K[j];
+            const double2 a = x1[c], b = x2[c];
+            m1.x += mv * a.x;
+            m1.y += mv * a.y;
+            k2.x += kv * b.x;
+            k2.y += kv * b.y;
+        }
+    }
+#pragma unroll
+    for (int off = kRowLanes / 2; off > 0; off >>= 1) {
+        m1.x += __shfl_xor(m1.x, off);
+        m1.y += __shfl_xor(m1.y, off);
+        k2.x += __shfl_xor(k2.x, off);
+        k2.y += __shfl_xor(k2.y, off);
+    }
+}
+
+// block-level sum of up to 4 doubles into partial[blockIdx.x * 4 + k]
+__device__ __forceinline__ void block_sum4(double v[4], double *partial) {
+    __shared__ double sh[kBlock / 64][4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) sh[wid][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double s = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) s += sh[w][threadIdx.x];
+        partial[blockIdx.x * 4 + threadIdx.x] = s;
+    }
+}
+
+// y = alpha M x + beta K x (complex alpha, real beta)
+__global__ void __launch_bounds__(kBlock) k_field_spmv(FieldCsr S, double2 alpha, double beta,
+                                                       const double2 *__restrict__ x, double2 *__restrict__ y) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t row = t / kRowLanes;
+    const int sub = (int)(t % kRowLanes);
+    double2 m, k;
+    csr_row2(S, row, sub, x, x, m, k);
+    if (row < S.ne && sub == 0) y[row] = cadd(cmul(alpha, m), cscale(k, beta));
+}
+
+// Newmark predictor: us = u + dt v + dt^2/4 a, vs = v + dt/2 a, w = 2 j w vs - w^2 us
+__global__ void __launch_bounds__(kBlock) k_nm_predict(int64_t ne, const double2 *__restrict__ u,
+                                                       const double2 *__restrict__ v, const double2 *__restrict__ a,
+                                                       double2 *__restrict__ us, double2 *__restrict__ vs,
+                                                       double2 *__restrict__ w, double dt, double omega) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ne) return;
+    const double2 ui = u[i], vi = v[i], ai = a[i];
+    const double2 usi = cadd(cadd(ui, cscale(vi, dt)), cscale(ai, 0.25 * dt * dt));
+    const double2 vsi = cadd(vi, cscale(ai, 0.5 * dt));
+    us[i] = usi;
+    vs[i] = vsi;
+    w[i] = csub(cmul(make_double2(0.0, 2.0 * omega), vsi), cscale(usi, omega * omega));
+}
+
+// rhs = f - M w - K us with f = -e^{-j w t} g'';  boundary rows 0.  partial[4b+0] = |rhs|^2
+__global__ void __launch_bounds__(kBlock) k_nm_rhs(FieldCsr S, const double2 *__restrict__ w,
+                                                   const double2 *__restrict__ us, const double *__restrict__ gdd,
+                                                   double c, double s, double2 *__restrict__ rhs,
+                                                   double *__restrict__ partial) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t row = t / kRowLanes;
+    const int sub = (int)(t % kRowLanes);
+    double2 m, k;
+    csr_row2(S, row, sub, w, us, m, k);
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (row < S.ne && sub == 0) {
+        double2 r = make_double2(0.0, 0.0);
+        if (!S.dir[row]) {
+            const double g = gdd ? gdd[row] : 0.0;
+            // -e^{-j w t} g = -(c - j s) g
+            r = make_double2(-c * g - m.x - k.x, s * g - m.y - k.y);
+        }
+        rhs[row] = r;
+        v[0] = r.x * r.x + r.y * r.y;
+    }
+    block_sum4(v, partial);
+}
+
+// COCG start: x = 0, r = rhs, z = Dinv r, p = z; partial: rho = r.z (re, im), |r|^2
+__global__ void __launch_bounds__(kBlock) k_cocg_init(int64_t ne, const double2 *__restrict__ rhs,
+                                                      const double2 *__restrict__ dinv, double2 *__restrict__ x,
+                                                      double2 *__restrict__ r, double2 *__restrict__ z,
+                                                      double2 *__restrict__ p, double *__restrict__ partial) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (i < ne) {
+        const double2 ri = rhs[i];
+        const double2 zi = cmul(dinv[i], ri);
+        x[i] = make_double2(0.0, 0.0);
+        r[i] = ri;
+        z[i] = zi;
+        p[i] = zi;
+        const double2 rz = cmul(ri, zi);
+        v[0] = rz.x;
+        v[1] = rz.y;
+        v[2] = ri.x * ri.x + ri.y * ri.y;
+    }
+    block_sum4(v, partial);
+}
+
+// q = A p and partial p.q (unconjugated)
+__global__ void __launch_bounds__(kBlock) k_cocg_apply(FieldCsr S, double2 alpha, double beta,
+                                                       const double2 *__restrict__ p, double2 *__restrict__ q,
+                                                       double *__restrict__ partial) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t row = t / kRowLanes;
+    const int sub = (int)(t % kRowLanes);
+    double2 m, k;
+    csr_row2(S, row, sub, p, p, m, k);
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (row < S.ne && sub == 0) {
+        const double2 qi = cadd(cmul(alpha, m), cscale(k, beta));
+        q[row] = qi;
+        const double2 pq = cmul(p[row], qi);
+        v[0] = pq.x;
+        v[1] = pq.y;
+    }
+    block_sum4(v, partial);
+}
+
+// Sums nb block partials (4 each) in a fixed order into out[0..3].
+__global__ void __launch_bounds__(kBlock) k_reduce4(int64_t nb, const double *__restrict__ partial,
+                                                    double *__restrict__ out) {
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t b = threadIdx.x; b < nb; b += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] += partial[4 * b + k];
+    __shared__ double sh[kBlock / 64][4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) sh[wid][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double s = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) s += sh[w][threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+}
+
+// scalars (device): sc[0..1] rho, sc[2..3] p.q, sc[4..5] alpha, sc[6..7] rho_new / beta, sc[8] |r|^2, sc[9] |b|^2
+// x += alpha p, r -= alpha q, z = Dinv r; partial: r.z (re, im), |r|^2
+__global__ void __launch_bounds__(kBlock) k_cocg_update(int64_t ne, const double *__restrict__ sc,
+                                                        const double2 *__restrict__ dinv, const double2 *__restrict__ p,
+                                                        const double2 *__restrict__ q, double2 *__restrict__ x,
+                                                        double2 *__restrict__ r, double2 *__restrict__ z,
+                                                        double *__restrict__ partial) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double2 al = make_double2(sc[4], sc[5]);
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (i < ne) {
+        x[i] = cadd(x[i], cmul(al, p[i]));
+        const double2 ri = csub(r[i], cmul(al, q[i]));
+        r[i] = ri;
+        const double2 zi = cmul(dinv[i], ri);
+        z[i] = zi;
+        const double2 rz = cmul(ri, zi);
+        v[0] = rz.x;
+        v[1] = rz.y;
+        v[2] = ri.x * ri.x + ri.y * ri.y;
+    }
+    block_sum4(v, partial);
+}
+
+// alpha = rho / (p.q) from the reduced p.q in red[0..1]
+__global__ void k_cocg_alpha(double *__restrict__ sc, const double *__restrict__ red) {
+    if (threadIdx.x == 0) {
+        const double2 pq = make_double2(red[0], red[1]);
+        const double2 al = (pq.x == 0.0 && pq.y == 0.0) ? make_double2(0.0, 0.0) : cdiv(make_double2(sc[0], sc[1]), pq);
+        sc[2] = pq.x;
+        sc[3] = pq.y;
+        sc[4] = al.x;
+        sc[5] = al.y;
+    }
+}
+
+// beta = rho_new / rho, rho = rho_new, |r|^2 from red[0..2]
+__global__ void k_cocg_beta(double *__restrict__ sc, const double *__restrict__ red) {
+    if (threadIdx.x == 0) {
+        const double2 rn = make_double2(red[0], red[1]);
+        const double2 ro = make_double2(sc[0], sc[1]);
+        const double2 be = (ro.x == 0.0 && ro.y == 0.0) ? make_double2(0.0, 0.0) : cdiv(rn, ro);
+        sc[0] = rn.x;
+        sc[1] = rn.y;
+        sc[6] = be.x;
+        sc[7] = be.y;
+        sc[8] = red[2];
+    }
+}
+
+// start: rho and |r|^2 from red, |b|^2 from red2[0]
+__global__ void k_cocg_start(double *__restrict__ sc, const double *__restrict__ red, const double *__restrict__ red2) {
+    if (threadIdx.x == 0) {
+        sc[0] = red[0];
+        sc[1] = red[1];
+        sc[8] = red[2];
+        sc[9] = red2[0];
+    }
+}
+
+// p = z + beta p
+__global__ void __launch_bounds__(kBlock) k_cocg_dir(int64_t ne, const double *__restrict__ sc,
+                                                     const double2 *__restrict__ z, double2 *__restrict__ p) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ne) p[i] = cadd(z[i], cmul(make_double2(sc[6], sc[7]), p[i]));
+}
+
+// faces: (1 + j w dt/2) b_new = (1 - j w dt/2) b - dt/2 C (u + u_new), u_new = us + dt^2/4 x,
+// (C e)_f = e_ab + e_bc - e_ac
+__global__ void __launch_bounds__(kBlock) k_nm_faraday(int64_t nf, const int32_t *__restrict__ fe,
+                                                       const double2 *__restrict__ u, const double2 *__restrict__ us,
+                                                       const double2 *__restrict__ x, double2 *__restrict__ b,
+                                                       double dt, double omega) {
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    const double q = 0.25 * dt * dt;
+    double2 cs = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int32_t e = fe[3 * f + k];
+        const double2 sum = cadd(u[e], cadd(us[e], cscale(x[e], q)));
+        cs = (k == 2) ? csub(cs, sum) : cadd(cs, sum);
+    }
+    const double2 num = csub(cmul(make_double2(1.0, -0.5 * omega * dt), b[f]), cscale(cs, 0.5 * dt));
+    b[f] = cdiv(num, make_double2(1.0, 0.5 * omega * dt));
+}
+
+// u = us + dt^2/4 x, v = vs + dt/2 x, a = x
+__global__ void __launch_bounds__(kBlock) k_nm_correct(int64_t ne, const double2 *__restrict__ us,
+                                                       const double2 *__restrict__ vs, const double2 *__restrict__ x,
+                                                       double2 *__restrict__ u, double2 *__restrict__ v,
+                                                       double2 *__restrict__ a, double dt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ne) return;
+    const double2 xi = x[i];
+    u[i] = cadd(us[i], cscale(xi, 0.25 * dt * dt));
+    v[i] = cadd(vs[i], cscale(xi, 0.5 * dt));
+    a[i] = xi;
+}
+
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
 
 // =============================================================================== context
+// Device state of the field update (allocated by etpic_field_setup).
+struct FieldState {
+    bool ready = false;
+    double dt = 0, omega = 0, eps = 0, mu = 0;
+    int64_t ne = 0, nf = 0, nnz = 0;
+    int32_t *rowptr = nullptr, *col = nullptr, *face_edge = nullptr;
+    double *M = nullptr, *K = nullptr;
+    uint8_t *dir = nullptr;
+    double2 *dinv = nullptr;
+    double2 *vec = nullptr;     // 9 work vectors of ne: us, vs, w, rhs, x, r, z, p, q
+    double *partial = nullptr;  // 4 per block
+    double *red = nullptr;      // 8: reductions (4) and |rhs|^2 (4)
+    double *sc = nullptr;       // 10 scalars of the iteration
+    int64_t nb = 0;
+
+    double2 *v(int k) const { return vec + (size_t)k * ne; }
+    FieldCsr csr() const { return FieldCsr{ne, rowptr, col, M, K, dir}; }
+    void release() {
+        for (void *q : {(void *)rowptr, (void *)col, (void *)face_edge, (void *)M, (void *)K, (void *)dir,
+                        (void *)dinv, (void *)vec, (void *)partial, (void *)red, (void *)sc})
+            (void)hipFree(q);
+        *this = FieldState();
+    }
+};
+
 struct etpic_ctx {
     int device = 0;
     etpic::HostMesh host;
@@ -840,6 +1175,7 @@ struct etpic_ctx {
     unsigned *d_count = nullptr;     // nt+1 counting-sort counters
     unsigned *d_tilesum = nullptr;   // scan tile totals
     int64_t tiles = 0;
+    FieldState field;
     // HIP events bracketing the kernels of steps run with ETPIC_STEP_TIMING:
     // 4 events per step (before the coefficient kernel, before and after the
     // particle kernel, after the walk kernel)
@@ -901,10 +1237,9 @@ struct etpic_ctx {
             if (int r = timing_events(&ev)) return r;
             HIP_TRY(hipEventRecord(ev[0], st));
         }
-        k_tet_coef<Real><<<grid_for(nt), kBlock, 0, st>>>(nt, d_topo, d_grad64,
-                                                          reinterpret_cast<const double2 *>(f->e_env), f->e_dc,
-                                                          reinterpret_cast<const double2 *>(f->b_env), f->b_dc, c, s,
-                                                          static_cast<Real *>(d_coef));
+        const FieldPtrs F{reinterpret_cast<const double2 *>(f->e_env), f->e_dc,
+                          reinterpret_cast<const double2 *>(f->b_env), f->b_dc, c, s};
+        k_tet_coef<Real><<<grid_for(2 * nt), kBlock, 0, st>>>(nt, d_topo, d_grad64, F, static_cast<Real *>(d_coef));
         HIP_TRY(hipGetLastError());
         if (ev) HIP_TRY(hipEventRecord(ev[1], st));
         k_push<Real><<<grid_for(p->n), kBlock, 0, st>>>(a, (flags & ETPIC_STEP_XCD_REMAP) ? 1 : 0);
@@ -937,6 +1272,7 @@ struct etpic_ctx {
         d_coef = nullptr;
         d_v2e_ptr = d_v2e_code = nullptr;
         d_count = d_tilesum = nullptr;
+        field.release();
         has_mesh = false;
     }
 };
@@ -1232,10 +1568,10 @@ int etpic_backward(etpic_ctx *ctx, int64_t n, const etpic_species *sp, const etp
             const etpic_particles cur = state_view(workspace, L.slots_off + (size_t)(k - k0) * L.state, L, n);
             const double t = (double)(step0 + k) * dt;
             const double c = std::cos(omega * t), s = std::sin(omega * t);
-            k_tet_coef<double><<<grid_for(nt), kBlock, 0, st>>>(nt, ctx->d_topo, ctx->d_grad64,
-                                                                reinterpret_cast<const double2 *>(f->e_env), f->e_dc,
-                                                                reinterpret_cast<const double2 *>(f->b_env), f->b_dc,
-                                                                c, s, static_cast<double *>(ctx->d_coef));
+            const FieldPtrs F{reinterpret_cast<const double2 *>(f->e_env), f->e_dc,
+                              reinterpret_cast<const double2 *>(f->b_env), f->b_dc, c, s};
+            k_tet_coef<double><<<grid_for(2 * nt), kBlock, 0, st>>>(nt, ctx->d_topo, ctx->d_grad64, F,
+                                                                    static_cast<double *>(ctx->d_coef));
             HIP_TRY(hipGetLastError());
             StepArgs<double> a = ctx->step_args<double>(&cur, sp, dt, scratch_dG, nullptr);
             AdjArgs b{};
@@ -1320,6 +1656,140 @@ int etpic_sort(etpic_ctx *ctx, const etpic_particles *src, const etpic_particles
         k_scatter<double><<<grid_for(n), kBlock, 0, st>>>(n, nt, src->tet, ctx->d_count, *src, *dst);
     else
         k_scatter<float><<<grid_for(n), kBlock, 0, st>>>(n, nt, src->tet, ctx->d_count, *src, *dst);
+    HIP_TRY(hipGetLastError());
+    return ETPIC_OK;
+}
+
+int etpic_field_setup(etpic_ctx *ctx, double dt, double omega, double eps, double mu) {
+    if (!ctx) return fail(ETPIC_EINVAL, "null context");
+    if (!ctx->has_mesh) return fail(ETPIC_ESTATE, "no mesh uploaded");
+    if (!(dt > 0.0) || !std::isfinite(omega) || !(eps > 0.0) || !(mu > 0.0))
+        return fail(ETPIC_EINVAL, "dt, eps, mu must be positive and omega finite");
+    std::string err;
+    etpic::FieldSystem S;
+    if (etpic::build_field_system(ctx->host, eps, mu, S, err) != 0) return fail(ETPIC_EINVAL, "field: %s", err.c_str());
+    if (int r = set_device(ctx)) return r;
+    HIP_TRY(hipDeviceSynchronize());
+    FieldState &F = ctx->field;
+    F.release();
+    F.dt = dt;
+    F.omega = omega;
+    F.eps = eps;
+    F.mu = mu;
+    F.ne = S.ne;
+    F.nf = S.nf;
+    F.nnz = S.nnz;
+    const int64_t ne = S.ne;
+    // Jacobi preconditioner: inverse diagonal of A = alpha M + beta K
+    const double ar = 1.0 - 0.25 * omega * omega * dt * dt, ai = omega * dt, beta = 0.25 * dt * dt;
+    std::vector<double2> dinv((size_t)ne);
+    for (int64_t i = 0; i < ne; ++i) {
+        double mii = 0.0, kii = 0.0;
+        for (int32_t j = S.rowptr[i]; j < S.rowptr[i + 1]; ++j)
+            if (S.col[j] == i) {
+                mii = S.M[j];
+                kii = S.K[j];
+            }
+        const double dr = ar * mii + beta * kii, di = ai * mii, den = dr * dr + di * di;
+        if (!(den > 0.0)) return fail(ETPIC_EMESH, "field: zero diagonal at edge %lld", (long long)i);
+        dinv[i] = make_double2(dr / den, -di / den);
+    }
+    F.nb = (int64_t)grid_for(ne * kRowLanes);
+    HIP_TRY(hipMalloc(&F.rowptr, sizeof(int32_t) * (ne + 1)));
+    HIP_TRY(hipMalloc(&F.col, sizeof(int32_t) * S.nnz));
+    HIP_TRY(hipMalloc(&F.M, sizeof(double) * S.nnz));
+    HIP_TRY(hipMalloc(&F.K, sizeof(double) * S.nnz));
+    HIP_TRY(hipMalloc(&F.dir, sizeof(uint8_t) * ne));
+    HIP_TRY(hipMalloc(&F.face_edge, sizeof(int32_t) * 3 * S.nf));
+    HIP_TRY(hipMalloc(&F.dinv, sizeof(double2) * ne));
+    HIP_TRY(hipMalloc(&F.vec, sizeof(double2) * 9 * ne));
+    HIP_TRY(hipMalloc(&F.partial, sizeof(double) * 4 * F.nb));
+    HIP_TRY(hipMalloc(&F.red, sizeof(double) * 8));
+    HIP_TRY(hipMalloc(&F.sc, sizeof(double) * 10));
+    HIP_TRY(hipMemcpy(F.rowptr, S.rowptr.data(), sizeof(int32_t) * (ne + 1), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(F.col, S.col.data(), sizeof(int32_t) * S.nnz, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(F.M, S.M.data(), sizeof(double) * S.nnz, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(F.K, S.K.data(), sizeof(double) * S.nnz, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(F.dir, S.dirichlet.data(), sizeof(uint8_t) * ne, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(F.face_edge, S.face_edge.data(), sizeof(int32_t) * 3 * S.nf, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(F.dinv, dinv.data(), sizeof(double2) * ne, hipMemcpyHostToDevice));
+    F.ready = true;
+    return ETPIC_OK;
+}
+
+int etpic_field_nnz(const etpic_ctx *ctx, int64_t *nnz_out) {
+    if (!ctx || !nnz_out) return fail(ETPIC_EINVAL, "null argument");
+    if (!ctx->field.ready) return fail(ETPIC_ESTATE, "etpic_field_setup not called");
+    *nnz_out = ctx->field.nnz;
+    return ETPIC_OK;
+}
+
+int etpic_field_spmv(etpic_ctx *ctx, const double *x, double *y, double alpha_re, double alpha_im, double beta,
+                     void *stream) {
+    if (!ctx || !x || !y) return fail(ETPIC_EINVAL, "null argument");
+    if (!ctx->field.ready) return fail(ETPIC_ESTATE, "etpic_field_setup not called");
+    if (int r = set_device(ctx)) return r;
+    const FieldState &F = ctx->field;
+    k_field_spmv<<<grid_for(F.ne * kRowLanes), kBlock, 0, static_cast<hipStream_t>(stream)>>>(
+        F.csr(), make_double2(alpha_re, alpha_im), beta, reinterpret_cast<const double2 *>(x),
+        reinterpret_cast<double2 *>(y));
+    HIP_TRY(hipGetLastError());
+    return ETPIC_OK;
+}
+
+int etpic_field_step(etpic_ctx *ctx, double t_next, double *u, double *v, double *a, double *b, const double *gdd,
+                     double tol, int max_iter, int *iters_out, double *resid_out, void *stream) {
+    if (!ctx || !u || !v || !a || !b) return fail(ETPIC_EINVAL, "null argument");
+    if (!ctx->field.ready) return fail(ETPIC_ESTATE, "etpic_field_setup not called");
+    if (!(tol > 0.0) || max_iter < 1 || !std::isfinite(t_next)) return fail(ETPIC_EINVAL, "bad tol / max_iter / time");
+    if (int r = set_device(ctx)) return r;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const FieldState &F = ctx->field;
+    const int64_t ne = F.ne;
+    const unsigned ge = grid_for(ne), gr = grid_for(ne * kRowLanes);
+    const double dt = F.dt, w = F.omega;
+    const double2 alpha = make_double2(1.0 - 0.25 * w * w * dt * dt, w * dt);
+    const double beta = 0.25 * dt * dt;
+    const double c = std::cos(w * t_next), s = std::sin(w * t_next);
+    double2 *U = reinterpret_cast<double2 *>(u), *V = reinterpret_cast<double2 *>(v), *A = reinterpret_cast<double2 *>(a);
+    double2 *us = F.v(0), *vs = F.v(1), *wv = F.v(2), *rhs = F.v(3), *x = F.v(4), *r = F.v(5), *z = F.v(6), *p = F.v(7),
+            *q = F.v(8);
+    k_nm_predict<<<ge, kBlock, 0, st>>>(ne, U, V, A, us, vs, wv, dt, w);
+    k_nm_rhs<<<gr, kBlock, 0, st>>>(F.csr(), wv, us, gdd, c, s, rhs, F.partial);
+    k_reduce4<<<1, kBlock, 0, st>>>(gr, F.partial, F.red + 4);
+    k_cocg_init<<<ge, kBlock, 0, st>>>(ne, rhs, F.dinv, x, r, z, p, F.partial);
+    k_reduce4<<<1, kBlock, 0, st>>>(ge, F.partial, F.red);
+    k_cocg_start<<<1, 64, 0, st>>>(F.sc, F.red, F.red + 4);
+    HIP_TRY(hipGetLastError());
+    double hs[10];
+    HIP_TRY(hipMemcpyAsync(hs, F.sc, sizeof hs, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const double bnorm2 = hs[9];
+    double rel = bnorm2 > 0.0 ? std::sqrt(hs[8] / bnorm2) : 0.0;
+    int it = 0;
+    const int check = 5;
+    while (rel > tol && it < max_iter) {
+        k_cocg_apply<<<gr, kBlock, 0, st>>>(F.csr(), alpha, beta, p, q, F.partial);
+        k_reduce4<<<1, kBlock, 0, st>>>(gr, F.partial, F.red);
+        k_cocg_alpha<<<1, 64, 0, st>>>(F.sc, F.red);
+        k_cocg_update<<<ge, kBlock, 0, st>>>(ne, F.sc, F.dinv, p, q, x, r, z, F.partial);
+        k_reduce4<<<1, kBlock, 0, st>>>(ge, F.partial, F.red);
+        k_cocg_beta<<<1, 64, 0, st>>>(F.sc, F.red);
+        k_cocg_dir<<<ge, kBlock, 0, st>>>(ne, F.sc, z, p);
+        HIP_TRY(hipGetLastError());
+        ++it;
+        if (it % check == 0 || it == max_iter) {
+            HIP_TRY(hipMemcpyAsync(hs, F.sc, sizeof hs, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            rel = std::sqrt(hs[8] / bnorm2);
+            if (!std::isfinite(rel)) break;
+        }
+    }
+    if (iters_out) *iters_out = it;
+    if (resid_out) *resid_out = rel;
+    if (!(rel <= tol)) return fail(ETPIC_ENOCONV, "COCG: relative residual %.3e after %d iterations", rel, it);
+    k_nm_faraday<<<grid_for(F.nf), kBlock, 0, st>>>(F.nf, F.face_edge, U, us, x, reinterpret_cast<double2 *>(b), dt, w);
+    k_nm_correct<<<ge, kBlock, 0, st>>>(ne, us, vs, x, U, V, A, dt);
     HIP_TRY(hipGetLastError());
     return ETPIC_OK;
 }

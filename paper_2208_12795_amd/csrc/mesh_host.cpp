@@ -30,6 +30,7 @@ int build_host_mesh(int64_t nv, const double *xyz, int64_t nt, const int32_t *tv
     M.nv = nv;
     M.nt = nt;
     M.grad.resize((size_t)nt * 12);
+    M.vol.resize((size_t)nt);
     // validation + barycentric gradients: with columns c_k = r_k - r_0 (k = 1..3)
     // and J = [c1 c2 c3], (lam1, lam2, lam3) = J^{-1} (x - r0), so the gradients
     // are the rows of J^{-1} = [c2 x c3; c3 x c1; c1 x c2] / det J.
@@ -56,6 +57,7 @@ int build_host_mesh(int64_t nv, const double *xyz, int64_t nt, const int32_t *tv
         double l1 = std::sqrt(c[1][0] * c[1][0] + c[1][1] * c[1][1] + c[1][2] * c[1][2]);
         double l2 = std::sqrt(c[2][0] * c[2][0] + c[2][1] * c[2][1] + c[2][2] * c[2][2]);
         if (!(std::fabs(det) > 1e-12 * l0 * l1 * l2)) { err = "tet " + std::to_string(t) + ": degenerate"; return -4; }
+        M.vol[t] = std::fabs(det) / 6.0;
         double *g = &M.grad[(size_t)t * 12];
         for (int d = 0; d < 3; ++d) {
             g[3 + d] = r1[d] / det;

@@ -27,6 +27,7 @@ struct HostMesh {
     std::vector<int32_t> faces;     // nf*3, (a<b<c), lexicographic
     std::vector<TetTopo> topo;      // nt
     std::vector<double> grad;       // nt*12: grad lambda_0..3 (x,y,z each)
+    std::vector<double> vol;        // nt: |volume|
     std::vector<int32_t> v2e_ptr;   // nv+1: CSR of vertex -> incident edges
     std::vector<int32_t> v2e_code;  // 2*ne: (edge << 1) | (vertex is the head)
 };

@@ -28,6 +28,7 @@ EXPORTS = (
     "etpic_mesh_counts", "etpic_mesh_edges", "etpic_mesh_faces", "etpic_gather_push_deposit", "etpic_sort",
     "etpic_vertex_charge", "etpic_gauss_residual", "etpic_kernel_time", "etpic_check",
     "etpic_adjoint_workspace", "etpic_forward_checkpointed", "etpic_backward",
+    "etpic_field_setup", "etpic_field_nnz", "etpic_field_spmv", "etpic_field_step",
 )
 
 
@@ -85,6 +86,11 @@ def lib():
                                  C.c_double, C.c_double, C.c_int, vp, C.c_size_t, C.c_void_p * 3, C.c_void_p * 3,
                                  vp, vp]
     L.etpic_check.argtypes = [vp, vp, C.POINTER(C.c_uint32)]
+    L.etpic_field_setup.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_double]
+    L.etpic_field_nnz.argtypes = [vp, i64p]
+    L.etpic_field_spmv.argtypes = [vp, vp, vp, C.c_double, C.c_double, C.c_double, vp]
+    L.etpic_field_step.argtypes = [vp, C.c_double, vp, vp, vp, vp, vp, C.c_double, C.c_int, C.POINTER(C.c_int),
+                                   dp, vp]
     for name in EXPORTS:
         if name != "etpic_last_error":
             getattr(L, name).restype = C.c_int
@@ -335,6 +341,29 @@ class Context:
         _chk(lib().etpic_backward(self._h, int(n), C.byref(sp), C.byref(fd), int(step0), int(nsteps), float(dt),
                                   float(omega), int(checkpoint_every), C.c_void_p(workspace.data_ptr()),
                                   workspace.numel(), vb, xb, _dptr(grad_e), _stream(stream)))
+
+    # field update (side path) -------------------------------------------------------
+    def field_setup(self, dt, omega, eps, mu):
+        _chk(lib().etpic_field_setup(self._h, float(dt), float(omega), float(eps), float(mu)))
+        n = C.c_int64(0)
+        _chk(lib().etpic_field_nnz(self._h, C.byref(n)))
+        return n.value
+
+    def field_spmv(self, x, y, alpha, beta, stream=None):
+        """y = alpha M x + beta K x; x, y float64 [N_e, 2] (complex)."""
+        _chk(lib().etpic_field_spmv(self._h, _dptr(x), _dptr(y), float(np.real(alpha)), float(np.imag(alpha)),
+                                    float(beta), _stream(stream)))
+
+    def field_step(self, t_next, u, v, a, b, gdd=None, tol=1e-12, max_iter=500, stream=None, raise_on_error=True):
+        """One Newmark step in place on u, v, a (float64 [N_e, 2]) and b (float64 [N_f, 2]);
+        returns (status, iterations, relative residual)."""
+        it = C.c_int(0)
+        res = C.c_double(0.0)
+        rc = lib().etpic_field_step(self._h, float(t_next), _dptr(u), _dptr(v), _dptr(a), _dptr(b), _dptr(gdd),
+                                    float(tol), int(max_iter), C.byref(it), C.byref(res), _stream(stream))
+        if raise_on_error:
+            _chk(rc)
+        return rc, it.value, res.value
 
     def check(self, stream=None, raise_on_error=True):
         word = C.c_uint32(0)

@@ -90,25 +90,37 @@ def mesh_faces(tet_vert, n_vert):
     return np.stack([ab // n_vert, ab % n_vert, c], axis=1).astype(np.int32)
 
 
+def _cross_cols(a, b):
+    """row-wise cross product of [N,3] arrays, column by column (large N)"""
+    return np.stack([a[:, 1] * b[:, 2] - a[:, 2] * b[:, 1],
+                     a[:, 2] * b[:, 0] - a[:, 0] * b[:, 2],
+                     a[:, 0] * b[:, 1] - a[:, 1] * b[:, 0]], axis=1)
+
+
 def tet_volumes(xyz, tet_vert):
     """Signed volumes (geometry of the generated mesh; used for sampling)."""
-    r = xyz[tet_vert]
-    a, b, c = r[:, 1] - r[:, 0], r[:, 2] - r[:, 0], r[:, 3] - r[:, 0]
-    return np.einsum("ij,ij->i", a, np.cross(b, c)) / 6.0
+    r0 = xyz[tet_vert[:, 0]]
+    a, b, c = xyz[tet_vert[:, 1]] - r0, xyz[tet_vert[:, 2]] - r0, xyz[tet_vert[:, 3]] - r0
+    return (a * _cross_cols(b, c)).sum(axis=1) / 6.0
 
 
 # --------------------------------------------------------------------- particles
 def uniform_particles(xyz, tet_vert, n, rng):
-    """Positions uniform in the domain: tet chosen with probability |vol|,
-    barycentrics ~ Dirichlet(1,1,1,1) (uniform inside a tet)."""
+    """Positions uniform in the domain: tet chosen with probability |vol| (by
+    rejection against the largest volume), barycentrics ~ Dirichlet(1,1,1,1)
+    (uniform inside a tet)."""
     vol = np.abs(tet_volumes(xyz, tet_vert))
-    cdf = np.cumsum(vol)
-    cdf /= cdf[-1]
-    tet = np.searchsorted(cdf, rng.random(n), side="right").astype(np.int32)
-    tet = np.minimum(tet, tet_vert.shape[0] - 1)
+    acc = vol / vol.max()
+    nt = tet_vert.shape[0]
+    tet = np.empty(0, dtype=np.int64)
+    while tet.size < n:
+        m = int((n - tet.size) / acc.mean() * 1.05) + 64
+        cand = rng.integers(0, nt, m)
+        tet = np.concatenate([tet, cand[rng.random(m) < acc[cand]]])
+    tet = tet[:n].astype(np.int32)
     g = rng.standard_exponential((n, 4))
-    lam = g / g.sum(axis=1, keepdims=True)
-    return tet, np.ascontiguousarray(lam[:, 1:])
+    g /= g.sum(axis=1, keepdims=True)
+    return tet, np.ascontiguousarray(g[:, 1:])
 
 
 def reference_located(u, n, extent):
@@ -123,13 +135,17 @@ def reference_located(u, n, extent):
     cell = np.floor(s).astype(np.int64)
     cell = np.clip(cell, 0, np.array([nx - 1, ny - 1, nz - 1]))
     f = np.clip(s - cell, 0.0, 1.0)
-    order = np.argsort(-f, axis=1, kind="stable")
-    perm_index = {p: i for i, p in enumerate(PERMS)}
-    code = order[:, 0] * 9 + order[:, 1] * 3 + order[:, 2]
+    # descending order of the three fractional coordinates (ties: lower axis first)
+    f0, f1, f2 = f[:, 0], f[:, 1], f[:, 2]
+    ge01, ge02, ge12 = f0 >= f1, f0 >= f2, f1 >= f2
+    first = np.where(ge01 & ge02, 0, np.where(~ge01 & ge12, 1, 2))     # largest, lowest axis on ties
+    last = np.where(ge02 & ge12, 2, np.where(ge01, 1, 0))               # smallest, highest axis on ties
+    mid = 3 - first - last
+    order = np.stack([first, mid, last], axis=1)
     lut = np.full(27, -1, dtype=np.int64)
-    for p, i in perm_index.items():
+    for i, p in enumerate(PERMS):
         lut[p[0] * 9 + p[1] * 3 + p[2]] = i
-    pidx = lut[code]
+    pidx = lut[order[:, 0] * 9 + order[:, 1] * 3 + order[:, 2]]
     fs = np.take_along_axis(f, order, axis=1)
     lam = np.stack([1.0 - fs[:, 0], fs[:, 0] - fs[:, 1], fs[:, 1] - fs[:, 2], fs[:, 2]], axis=1)
     cid = cell[:, 0] + nx * (cell[:, 1] + ny * cell[:, 2])
@@ -186,8 +202,8 @@ def mode_edge_dofs(xyz, edges, amp, extent, rng, n_modes=8):
 
 def uniform_face_flux(xyz, faces, b0):
     """Flux of a uniform B0 through each oriented face: B0 . (r_b-r_a)x(r_c-r_a)/2."""
-    ra, rb, rc = xyz[faces[:, 0]], xyz[faces[:, 1]], xyz[faces[:, 2]]
-    area = 0.5 * np.cross(rb - ra, rc - ra)
+    ra = xyz[faces[:, 0]]
+    area = 0.5 * _cross_cols(xyz[faces[:, 1]] - ra, xyz[faces[:, 2]] - ra)
     return area @ np.asarray(b0, dtype=np.float64)
 
 

@@ -208,10 +208,17 @@ def test_edge_cases(E, torch_cuda, ora):
     ctx.check()
 
 
+def ctx_tet_with_edge(w, e):
+    """a tet that has edge e (from the generator's numbering)"""
+    a, b = w.edges[e]
+    tv = w.tet_vert
+    return int(np.flatnonzero(np.any(tv == a, axis=1) & np.any(tv == b, axis=1))[0])
+
+
 def test_device_errors_are_reported(E, torch_cuda, ora):
-    """Host-forced error paths: a tet index out of range and a displacement of
-    ~1000 box lengths (hop cap) are flagged through etpic_check; the kernels
-    still exit normally."""
+    """Host-forced error paths: a tet index out of range, a NaN field DoF and a
+    displacement of ~1000 box lengths (hop cap) are flagged through
+    etpic_check; the kernels still exit normally."""
     torch = torch_cuda
     w = synth.make_workload(1, n_particles=64)
     ctx, parts, fields = setup(E, torch, w, E.FP64)
@@ -224,6 +231,11 @@ def test_device_errors_are_reported(E, torch_cuda, ora):
     assert rc == E.EPARTICLE and word & E.DEV_BADTET
     rc, word = ctx.check(raise_on_error=False)
     assert rc == 0 and word == 0
+    nan_f = E.Fields.from_numpy(np.where(np.arange(ctx.n_edge) == 7, np.nan, w.e_env), w.b_env, None, w.b_dc)
+    hit = E.Particles.from_numpy(np.full(64, ctx_tet_with_edge(w, 7), np.int32), w.lam[:64], w.vel[:64])
+    ctx.gather_push_deposit(hit, sp, nan_f, 0, w.dt, w.omega, dG)
+    rc, word = ctx.check(raise_on_error=False)
+    assert rc == E.ENAN and word & E.DEV_NAN
     fast = parts.clone()
     fast.vel.fill_(1e3)
     ctx.gather_push_deposit(fast, E.Species(w.q, w.m * 1e30, w.w), fields, 0, 1.0, 0.0, dG)
@@ -231,3 +243,49 @@ def test_device_errors_are_reported(E, torch_cuda, ora):
     assert rc == E.EWALK and word & E.DEV_HOPCAP
     with pytest.raises(E.EtpicError):
         ctx.gather_push_deposit(parts, E.Species(w.q, 0.0, w.w), fields, 0, w.dt, w.omega, dG)
+
+
+def full_size_step(E, torch, ora, w, precision, tol, sort_first=True):
+    """One step of the whole workload on the GPU (sorted by tet, as the benchmark
+    runs it) against the oracle on the same state; plus the continuity residual."""
+    ctx = E.Context(0)
+    ctx.upload_mesh(w.xyz, w.tet_vert)
+    parts = E.Particles.from_numpy(w.tet, w.lam, w.vel, w.ids, precision=precision)
+    fields = E.Fields.from_numpy(w.e_env, w.b_env, None, w.b_dc)
+    sp = E.Species(w.q, w.m, w.w)
+    if sort_first:
+        dst = parts.empty_like()
+        ctx.sort(parts, dst)
+        parts = dst
+    tin, lin, vin, ids = parts.to_numpy()
+    rho0 = torch.zeros(ctx.n_vert, dtype=torch.float64, device="cuda")
+    rho1 = torch.zeros_like(rho0)
+    dG = torch.zeros(ctx.n_edge, dtype=torch.float64, device="cuda")
+    ctx.vertex_charge(parts, sp, rho0)
+    ctx.gather_push_deposit(parts, sp, fields, 17, w.dt, w.omega, dG)
+    ctx.vertex_charge(parts, sp, rho1)
+    r, p = ctx.gauss_residual(dG, rho1, rho0)
+    ctx.check()
+    M = ora.OracleMesh(w.xyz, w.tet_vert)
+    vin64 = vin.astype(np.float64)
+    rc, o, dGo = oracle_step(M, (tin, lin, vin64), w, 17, nthreads=NTH)
+    assert rc == 0
+    tg, lg, vg, _ = parts.to_numpy()
+    err = step_errors(w.xyz, w.tet_vert, (tin, lin, vin64), (tg, lg, vg), o, dG.cpu().numpy(), dGo)
+    print(f"[full-size {w.name} N={len(tg)} precision={precision}] {err} gauss {r / p:.2e}", flush=True)
+    assert r / p <= 1e-12
+    assert err["tet_mismatch"] <= 2 + 1e-5 * len(tg), err
+    assert_within(err, tol, "full size")
+    ctx.close()
+
+
+def test_full_size_fp64_40cube(E, torch_cuda, ora):
+    """The benchmark workload at its real size: 40^3 x 6 tets, 1e7 electrons,
+    float64, launch configuration of the benchmark (sorted, XCD remap)."""
+    full_size_step(E, torch_cuda, ora, synth.make_workload(2), E.FP64, 1e-12)
+
+
+def test_full_size_mixed_40cube_5e7(E, torch_cuda, ora):
+    """Precision form at its real size: 40^3 x 6 tets, 5e7 electrons, float32
+    gather/push with float64 positions and deposit, against the float64 oracle."""
+    full_size_step(E, torch_cuda, ora, synth.make_workload(3), E.MIXED, 2e-5)

@@ -27,14 +27,18 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # Algorithmic bytes of the particle kernel (what it must move per unit):
-#  per particle-step: state read + write = 2 x (lam 3x8 + v 3x8 + tet 4) (float64 form)
-#                                         2 x (lam 3x8 + v 3x4 + tet 4) (mixed form)
+#  per particle-step: state read (tet 4 B, lam 3x8, v 3x8) and written back
+#                     (lam 3x8, v 3x8): 100 B in float64; v is float32 in the
+#                     mixed form: 76 B.  (The tet id is rewritten only for the
+#                     particles that leave their tet, by the walk kernel.)
 #  per tet and step : its coefficient row (24 reals), gradient row (9 reals) and
 #                     edge ids (6 x 4 B), read once: 288 B (float64), 156 B (mixed)
 #  per edge and step: the current accumulator read + written once (16 B)
-BYTES_PER_PARTICLE = {"fp64": 104, "mixed": 80}
+BYTES_PER_PARTICLE = {"fp64": 100, "mixed": 76}
 BYTES_PER_TET = {"fp64": 288, "mixed": 156}
 BYTES_PER_EDGE = 16
+KERNEL_NAME = {"fp64": "k_push<double>", "mixed": "k_push<float>"}
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_push_hbm_traffic_40cube_1e7.md")
 COPY_CALIB_BYTES = 1 << 30
 
 
@@ -155,7 +159,7 @@ def main():
     import torch
 
     from paper_2208_12795_amd import etpic as E
-    from paper_2208_12795_amd import synth
+    from paper_2208_12795_amd import rocprof_summary, synth
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -190,8 +194,11 @@ def main():
         r = res[form]
         bytes_launch = BYTES_PER_PARTICLE[form] * n_p + BYTES_PER_TET[form] * n_t + BYTES_PER_EDGE * n_e
         ach = bytes_launch / (r["kernel_ms"] * 1e-3) / 1e9
+        traffic = None
+        if args.particles is None:
+            traffic = rocprof_summary.read_traffic(TRAFFIC_SUMMARY, KERNEL_NAME[form])
         return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": KERNEL_NAME[form],
                 "bytes_per_launch": bytes_launch, "kernel_ms": round(r["kernel_ms"], 5)}
 
     main_form = "fp64" if "fp64" in res else next(iter(res))

@@ -76,15 +76,30 @@ __device__ __forceinline__ WaveRuns wave_runs(int key) {
     return r;
 }
 
-// Segmented suffix sum: after the call the head lane of each run holds the
-// run's total (other lanes hold partial sums).
-template <typename T>
-__device__ __forceinline__ T run_total(T x, const WaveRuns &r) {
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const T y = __shfl_down(x, off);
-        if (r.lane + off <= r.run_end) x += y;
-    }
+// Lane value x of the DPP source selected by kCtrl (row shift or row broadcast);
+// lanes whose row is off in kRowMask, or whose source is out of the row, get 0.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ double dpp_get(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), kCtrl, kRowMask, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), kCtrl, kRowMask, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Segmented inclusive prefix sum over the wave: after the call the LAST lane of
+// each run (lane == run_end) holds the run's total.  Hillis-Steele within rows
+// of 16 lanes by DPP row shifts (1, 2, 4, 8), then the row broadcasts of lane 15
+// (into rows 1, 3) and lane 31 (into rows 2, 3); a lane only adds a partial sum
+// whose lanes all belong to its own run, selected by a 0/1 factor rather than a
+// branch.
+__device__ __forceinline__ double run_total(double x, const WaveRuns &r) {
+    const int h = r.head_lane, l = r.lane;
+    x = fma(dpp_get<0x111, 0xf>(x), l - 1 >= h ? 1.0 : 0.0, x);   // row_shr:1
+    x = fma(dpp_get<0x112, 0xf>(x), l - 2 >= h ? 1.0 : 0.0, x);   // row_shr:2
+    x = fma(dpp_get<0x114, 0xf>(x), l - 4 >= h ? 1.0 : 0.0, x);   // row_shr:4
+    x = fma(dpp_get<0x118, 0xf>(x), l - 8 >= h ? 1.0 : 0.0, x);   // row_shr:8
+    x = fma(dpp_get<0x142, 0xa>(x), h < (l & 48) ? 1.0 : 0.0, x); // row_bcast:15
+    x = fma(dpp_get<0x143, 0xc>(x), h < 32 ? 1.0 : 0.0, x);       // row_bcast:31
     return x;
 }
 
@@ -330,7 +345,7 @@ __device__ __forceinline__ int walk(const StepArgs<Real> &a, int T, double l[4],
 // the loads coalesce), gathers E and B, applies the Boris update and, if the
 // particle stays in its tet (the common case), computes the six in-tet path
 // integrals.  These are summed over each run of equal tet within the
-// wavefront (segmented reduction through lane shuffles); the run's first lane
+// wavefront (segmented scan by DPP lane moves); the run's last lane
 // adds the sums to the edges with float64 global atomics.  There are no block
 // barriers, so latency is hidden by occupancy alone.  Particles that leave
 // their tet are marked and their wavefront queued for k_walk.
@@ -427,7 +442,7 @@ __global__ void __launch_bounds__(kBlock) k_push(StepArgs<Real> a, int remap) {
         a.v1[p] = v[1];
         a.v2[p] = v[2];
     }
-    // segmented reduction over runs of equal tet; the run's first lane adds to HBM
+    // segmented reduction over runs of equal tet; the run's last lane adds to HBM
     const WaveRuns runs = wave_runs(T);
 #pragma unroll
     for (int e = 0; e < 6; ++e) g6[e] = run_total(g6[e], runs);
@@ -435,7 +450,7 @@ __global__ void __launch_bounds__(kBlock) k_push(StepArgs<Real> a, int remap) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) r4[k] = run_total(r4[k], runs);
     }
-    if (act && runs.head) {
+    if (act && runs.lane == runs.run_end) {
         const TetTopo *tp = a.topo + T;
 #pragma unroll
         for (int e = 0; e < 6; ++e)
@@ -654,7 +669,7 @@ __global__ void __launch_bounds__(kBlock) k_adjoint(StepArgs<double> a, AdjArgs 
     const WaveRuns runs = wave_runs(T);
 #pragma unroll
     for (int k = 0; k < 12; ++k) ge[k] = run_total(ge[k], runs);
-    if (T >= 0 && runs.head) {
+    if (T >= 0 && runs.lane == runs.run_end) {
         const TetTopo *tp = a.topo + T;
 #pragma unroll
         for (int e = 0; e < 6; ++e) {
@@ -687,7 +702,7 @@ __global__ void __launch_bounds__(kBlock) k_charge(int64_t n, int64_t nt, const 
     const WaveRuns r = wave_runs(T);
 #pragma unroll
     for (int k = 0; k < 4; ++k) l[k] = run_total(l[k], r);
-    if (r.head && T >= 0) {
+    if (r.lane == r.run_end && T >= 0) {
         const TetTopo tp = topo[T];
 #pragma unroll
         for (int k = 0; k < 4; ++k) unsafeAtomicAdd(&rho[tp.v[k]], qw * l[k]);

@@ -1,0 +1,128 @@
+"""Condense rocprofv3 CSV output into the short text summaries kept under profiles/.
+
+Two summaries:
+
+* kernel statistics (``--kernel-trace --stats``): calls and average / min / max
+  duration per kernel;
+* HBM bytes from two counter runs (``--pmc FETCH_SIZE``, then ``--pmc
+  WRITE_SIZE``, both in KiB per dispatch).  Each counter is scaled by what it
+  reads for a plain device copy of known size in the same run (the largest
+  ``__amd_rocclr_copyBuffer`` dispatch, ``bench.py --calibrate-copy``: 1 GiB read
+  and 1 GiB written), so the scaled figure is in bytes of HBM traffic.
+
+The counter summary records the SHA-256 of the HIP source the counters were
+taken on; ``bench.py`` reports the traffic only while that source is unchanged.
+
+    python -m paper_2208_12795_amd.rocprof_summary stats  <dir> <prefix> <out.md> --command "..."
+    python -m paper_2208_12795_amd.rocprof_summary traffic <fetch_dir> <write_dir> <prefix> <out.md> --command "..."
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import hashlib
+import os
+import re
+
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+CALIB_BYTES = 1 << 30
+HIP_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "etpic.hip")
+
+
+def source_sha256(path: str = HIP_SOURCE) -> str:
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def short_name(name: str) -> str:
+    n = name.replace("(anonymous namespace)::", "")
+    if n.startswith("void "):
+        n = n[5:]
+    return n.split("(")[0]
+
+
+def load_counters(path: str) -> dict:
+    per = collections.defaultdict(list)
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            per[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return per
+
+
+def stats_summary(prof_dir: str, prefix: str, command: str) -> str:
+    with open(os.path.join(prof_dir, f"{prefix}_kernel_stats.csv")) as f:
+        rows = list(csv.DictReader(f))
+    out = ["# rocprofv3 kernel statistics", "", "Command:", "", "```", command, "```", "",
+           "| kernel | calls | avg us | min us | max us | % of GPU time |", "|---|---|---|---|---|---|"]
+    for r in rows:
+        out.append(f"| `{short_name(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                   f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
+    return "\n".join(out) + "\n"
+
+
+def traffic_summary(fetch_dir: str, write_dir: str, prefix: str, command: str, sha: str) -> str:
+    fetch = load_counters(os.path.join(fetch_dir, f"{prefix}_counter_collection.csv"))
+    write = load_counters(os.path.join(write_dir, f"{prefix}_counter_collection.csv"))
+    f_copy, w_copy = max(fetch[COPY_KERNEL]), max(write[COPY_KERNEL])
+    sf = CALIB_BYTES / 1024 / f_copy
+    sw = CALIB_BYTES / 1024 / w_copy
+    out = ["# HBM traffic per dispatch from FETCH_SIZE / WRITE_SIZE", "", "Commands (one counter per run):", "",
+           "```", command, "```", "",
+           f"source_sha256: {sha}", "",
+           f"Copy calibration (`{COPY_KERNEL}`, {CALIB_BYTES} B read and written): FETCH_SIZE {f_copy:.0f} KiB, "
+           f"WRITE_SIZE {w_copy:.0f} KiB per dispatch; scale factors {sf:.4f} (fetch), {sw:.4f} (write).", "",
+           "| kernel | dispatches | FETCH_SIZE KiB (raw mean) | WRITE_SIZE KiB (raw mean) | HBM bytes (scaled) |",
+           "|---|---|---|---|---|"]
+    tagged = []
+    for k in sorted(set(fetch) & set(write), key=lambda k: -sum(fetch[k]) / len(fetch[k])):
+        if k == COPY_KERNEL:
+            continue
+        fm = sum(fetch[k]) / len(fetch[k])
+        wm = sum(write[k]) / len(write[k])
+        tot = (fm * sf + wm * sw) * 1024
+        out.append(f"| `{short_name(k)}` | {len(fetch[k])} | {fm:.0f} | {wm:.0f} | {tot:.4g} |")
+        tagged.append(f"traffic_bytes {short_name(k)}: {int(round(tot))}")
+    return "\n".join(out + ["", "Machine-readable:", "", "```"] + tagged + ["```"]) + "\n"
+
+
+def read_traffic(path: str, kernel: str, sha: str | None = None):
+    """Scaled HBM bytes per dispatch of `kernel` from a traffic summary, or None
+    if the file is missing, lacks the kernel, or was taken on another source."""
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"^source_sha256: ([0-9a-f]{64})$", text, re.M)
+    if not m or m.group(1) != (sha or source_sha256()):
+        return None
+    m = re.search(r"^traffic_bytes " + re.escape(kernel) + r": (\d+)$", text, re.M)
+    return int(m.group(1)) if m else None
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="mode", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("dir")
+    s.add_argument("prefix")
+    s.add_argument("out")
+    s.add_argument("--command", required=True)
+    t = sub.add_parser("traffic")
+    t.add_argument("fetch_dir")
+    t.add_argument("write_dir")
+    t.add_argument("prefix")
+    t.add_argument("out")
+    t.add_argument("--command", required=True)
+    t.add_argument("--sha", default=None, help="SHA-256 of the HIP source profiled (default: the current one)")
+    a = ap.parse_args()
+    if a.mode == "stats":
+        text = stats_summary(a.dir, a.prefix, a.command)
+    else:
+        text = traffic_summary(a.fetch_dir, a.write_dir, a.prefix, a.command, a.sha or source_sha256())
+    with open(a.out, "w") as f:
+        f.write(text)
+    print(text)
+
+
+if __name__ == "__main__":
+    main()

@@ -191,6 +191,28 @@ __global__ void __launch_bounds__(kBlock) k_tet_coef(int64_t nt, const TetTopo *
 }
 
 // ------------------------------------------------------------------ particle step
+// What the particle kernel reads per tet besides this step's coefficients: the
+// barycentric gradients grad l_1..3 (9 reals, in the kernel's precision) and the
+// six global edge ids, packed in one row so that a run's lanes touch one
+// contiguous record (float64: 9 doubles + 6 int32 = 96 B; float32: 9 floats,
+// one pad, 6 int32 = 64 B).
+template <typename Real>
+struct PushRow;
+template <>
+struct PushRow<double> {
+    static constexpr int kStride = 12;   // doubles per row
+    static constexpr int kEdges = 9;     // first edge id at this Real offset
+};
+template <>
+struct PushRow<float> {
+    static constexpr int kStride = 16;
+    static constexpr int kEdges = 10;
+};
+template <typename Real>
+__device__ __forceinline__ const int32_t *push_row_edges(const Real *row) {
+    return reinterpret_cast<const int32_t *>(row + PushRow<Real>::kEdges);
+}
+
 template <typename Real>
 struct StepArgs {
     int64_t n, nt;
@@ -198,7 +220,7 @@ struct StepArgs {
     Real *v0, *v1, *v2;
     int32_t *tet;
     const Real *coef;          // nt*24: A_0..3, C_0..3 of this step (k_tet_coef)
-    const Real *gpush;         // nt*12: grad l_1, grad l_2, grad l_3, 0 (in Real)
+    const Real *gpush;         // nt rows of PushRow<Real>::kStride: grad l_1..3, then the 6 edge ids
     const double *grad;        // nt*12 float64 barycentric gradients grad l_0..3
     const TetTopo *topo;
     double *dG;
@@ -406,7 +428,7 @@ __global__ void __launch_bounds__(kBlock) k_push(StepArgs<Real> a, int remap) {
         // other three, in float64: deposit and stored end point see the same
         // four increments (continuity to float64 rounding)
         const Real dx[3] = {a.dt_r * v[0], a.dt_r * v[1], a.dt_r * v[2]};
-        const Real *gr = a.gpush + (int64_t)T * 12;
+        const Real *gr = a.gpush + (int64_t)T * PushRow<Real>::kStride;
         double dl[4];
 #pragma unroll
         for (int k = 1; k < 4; ++k)
@@ -451,11 +473,12 @@ __global__ void __launch_bounds__(kBlock) k_push(StepArgs<Real> a, int remap) {
         for (int k = 0; k < 4; ++k) r4[k] = run_total(r4[k], runs);
     }
     if (act && runs.lane == runs.run_end) {
-        const TetTopo *tp = a.topo + T;
+        const int32_t *ed = push_row_edges(a.gpush + (int64_t)T * PushRow<Real>::kStride);
 #pragma unroll
         for (int e = 0; e < 6; ++e)
-            if (g6[e] != 0.0) unsafeAtomicAdd(&a.dG[tp->e[e]], a.qw * g6[e]);
+            if (g6[e] != 0.0) unsafeAtomicAdd(&a.dG[ed[e]], a.qw * g6[e]);
         if (a.rho) {
+            const TetTopo *tp = a.topo + T;
 #pragma unroll
             for (int k = 0; k < 4; ++k)
                 if (r4[k] != 0.0) unsafeAtomicAdd(&a.rho[tp->v[k]], a.qw * r4[k]);
@@ -588,7 +611,7 @@ __global__ void __launch_bounds__(kBlock) k_adjoint(StepArgs<double> a, AdjArgs 
 #pragma unroll
             for (int d = 0; d < 3; ++d) g[k][d] = gp[3 * k + d];
         {
-            const double *gr = a.gpush + (int64_t)T * 12;
+            const double *gr = a.gpush + (int64_t)T * PushRow<double>::kStride;
             double dl[4];
 #pragma unroll
             for (int k = 1; k < 4; ++k) dl[k] = gr[3 * k - 3] * dx[0] + gr[3 * k - 2] * dx[1] + gr[3 * k - 1] * dx[2];
@@ -1178,8 +1201,8 @@ struct etpic_ctx {
     bool has_mesh = false;
     TetTopo *d_topo = nullptr;
     double *d_grad64 = nullptr;
-    double *d_gpush64 = nullptr;     // nt*12: grad l_1..3 then 3 zeros
-    float *d_gpush32 = nullptr;
+    double *d_gpush64 = nullptr;     // nt rows of PushRow<double>
+    float *d_gpush32 = nullptr;       // nt rows of PushRow<float>
     void *d_coef = nullptr;          // nt*24 doubles (float table uses the first half)
     int32_t *d_v2e_ptr = nullptr;
     int32_t *d_v2e_code = nullptr;
@@ -1436,18 +1459,22 @@ int etpic_mesh_upload(etpic_ctx *ctx, int64_t n_vert, const double *xyz_host, in
     const int64_t nt = M.nt;
     HIP_TRY(hipMalloc(&ctx->d_topo, sizeof(TetTopo) * nt));
     HIP_TRY(hipMalloc(&ctx->d_grad64, sizeof(double) * 12 * nt));
-    HIP_TRY(hipMalloc(&ctx->d_gpush64, sizeof(double) * 12 * nt));
-    HIP_TRY(hipMalloc(&ctx->d_gpush32, sizeof(float) * 12 * nt));
     {
-        std::vector<double> gp64((size_t)nt * 12, 0.0);
-        std::vector<float> gp32((size_t)nt * 12, 0.0f);
-        for (int64_t t = 0; t < nt; ++t)
+        constexpr int s64 = PushRow<double>::kStride, s32 = PushRow<float>::kStride;
+        HIP_TRY(hipMalloc(&ctx->d_gpush64, sizeof(double) * s64 * nt));
+        HIP_TRY(hipMalloc(&ctx->d_gpush32, sizeof(float) * s32 * nt));
+        std::vector<double> gp64((size_t)nt * s64, 0.0);
+        std::vector<float> gp32((size_t)nt * s32, 0.0f);
+        for (int64_t t = 0; t < nt; ++t) {
             for (int k = 0; k < 9; ++k) {
-                gp64[12 * t + k] = M.grad[12 * t + 3 + k];
-                gp32[12 * t + k] = (float)M.grad[12 * t + 3 + k];
+                gp64[s64 * t + k] = M.grad[12 * t + 3 + k];
+                gp32[s32 * t + k] = (float)M.grad[12 * t + 3 + k];
             }
-        HIP_TRY(hipMemcpy(ctx->d_gpush64, gp64.data(), sizeof(double) * 12 * nt, hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(ctx->d_gpush32, gp32.data(), sizeof(float) * 12 * nt, hipMemcpyHostToDevice));
+            std::memcpy(&gp64[s64 * t + PushRow<double>::kEdges], M.topo[t].e, sizeof(int32_t) * 6);
+            std::memcpy(&gp32[s32 * t + PushRow<float>::kEdges], M.topo[t].e, sizeof(int32_t) * 6);
+        }
+        HIP_TRY(hipMemcpy(ctx->d_gpush64, gp64.data(), sizeof(double) * s64 * nt, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(ctx->d_gpush32, gp32.data(), sizeof(float) * s32 * nt, hipMemcpyHostToDevice));
     }
     HIP_TRY(hipMalloc(&ctx->d_coef, sizeof(double) * 24 * nt));
     HIP_TRY(hipMalloc(&ctx->d_v2e_ptr, sizeof(int32_t) * (M.nv + 1)));

@@ -148,6 +148,29 @@ int etpic_mesh_edges(const etpic_ctx *ctx, int32_t *edge_vert_host);
 /* Canonical face list, host buffer of 3*N_f int32 (a<b<c per face). */
 int etpic_mesh_faces(const etpic_ctx *ctx, int32_t *face_vert_host);
 
+/* Particle upload from Cartesian positions (Problem Statement: particles are
+ * points r_p; this library keeps each as its tet and barycentrics).
+ * xyz[0..2]: device float64 arrays of length p->n (x, y, z of each point).
+ * hint: device int32[p->n] start tets, or NULL; an entry outside [0, N_t)
+ * means "no hint".  Each point is located by a straight walk from the centroid
+ * of its start tet (the hint, else the tet registered for the point's cell of a
+ * uniform grid built at mesh upload); p->tet and p->lam receive the tet and
+ * lam_1..3 = grad lam_k . (x - r_0) of that tet (a point on a shared face may
+ * land in either tet).  p->vel and p->id are not touched.  Synchronises
+ * `stream`.  A point outside a boundary face by at most 1e-10 in barycentric
+ * terms counts as on it (lam may then be slightly negative).  Points outside
+ * the mesh, non-finite points, and points the straight
+ * walk cannot reach (a non-convex domain without a good hint) get tet -1 and
+ * make the call return EPARTICLE with their count; the others are located.
+ * Errors: EINVAL, ESTATE, EPARTICLE, EHIP. */
+int etpic_particles_locate(etpic_ctx *ctx, const etpic_particles *p, const double *const xyz[3],
+                           const int32_t *hint, void *stream);
+
+/* Cartesian positions x = sum_k lam_k r_k of the particles into the device
+ * float64 arrays xyz[0..2] (length p->n).  A tet index outside [0, N_t) gives
+ * NaN and the BADTET device flag.  Asynchronous on `stream`. */
+int etpic_particles_positions(etpic_ctx *ctx, const etpic_particles *p, double *const xyz[3], void *stream);
+
 /* One fine step of every particle, asynchronous on `stream`:
  * gather E, B at (x^n, t_n = step*dt) with the carrier (cos w t_n, sin w t_n)
  * evaluated on the host in float64; Boris update v^{n-1/2} -> v^{n+1/2};

@@ -702,6 +702,147 @@ __global__ void __launch_bounds__(kBlock) k_adjoint(StepArgs<double> a, AdjArgs 
     }
 }
 
+// ------------------------------------------------------------------ point location
+// Particles enter as Cartesian points; the step works on (tet, barycentrics).
+// A point is located by a straight walk from the centroid of a start tet (the
+// caller's hint, else the tet of the point's start-grid cell) to the point:
+// each hop leaves the current tet through the face whose barycentric reaches
+// zero first and enters the neighbour.  The final barycentrics are recomputed
+// from the point itself, lam_k = grad l_k . (x - r_0) (k = 1..3).  A walk that
+// reaches a boundary face or the hop cap marks the point as not located; a
+// point within kLocateTol (in barycentric terms) outside a boundary face counts
+// as on it, so points on the domain boundary are located.
+constexpr int kLocateHopCap = 4096;
+constexpr double kLocateTol = 1e-10;
+
+struct GridArgs {
+    const int32_t *cell;
+    double lo[3], inv[3];
+    int dims[3];
+};
+
+__global__ void __launch_bounds__(kBlock) k_locate(int64_t n, const double *__restrict__ x0,
+                                                   const double *__restrict__ x1, const double *__restrict__ x2,
+                                                   const int32_t *__restrict__ hint, int64_t nt,
+                                                   const TetTopo *__restrict__ topo, const double *__restrict__ grad,
+                                                   const double *__restrict__ xyz, GridArgs G,
+                                                   double *__restrict__ lam1, double *__restrict__ lam2,
+                                                   double *__restrict__ lam3, int32_t *__restrict__ tet,
+                                                   unsigned *__restrict__ fails) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const double x[3] = {x0[p], x1[p], x2[p]};
+    bool ok = isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]);
+    int T = hint ? hint[p] : -1;
+    if (ok && (unsigned)T >= (unsigned)nt) {
+        int64_t c[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double f = floor((x[d] - G.lo[d]) * G.inv[d]);
+            c[d] = (int64_t)fmin(fmax(f, 0.0), (double)(G.dims[d] - 1));
+        }
+        T = G.cell[c[0] + (int64_t)G.dims[0] * (c[1] + (int64_t)G.dims[1] * c[2])];
+    }
+    if (ok) {
+        // start at the centroid of T (barycentrics 1/4) with displacement x - centroid
+        double l[4] = {0.25, 0.25, 0.25, 0.25}, d[3] = {x[0], x[1], x[2]};
+        {
+            const TetTopo tp = topo[T];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) d[c] -= 0.25 * xyz[3 * (int64_t)tp.v[k] + c];
+        }
+        int hops = 0;
+        for (;;) {
+            const double *gp = grad + (int64_t)T * 12;
+            const TetTopo tp = topo[T];
+            double dl[4];
+#pragma unroll
+            for (int k = 1; k < 4; ++k) dl[k] = gp[3 * k] * d[0] + gp[3 * k + 1] * d[1] + gp[3 * k + 2] * d[2];
+            dl[0] = -(dl[1] + dl[2] + dl[3]);
+            double smin = 1.0;
+            int kmin = -1;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (dl[k] < 0.0 && l[k] + dl[k] < 0.0 && !(tp.n[k] < 0 && l[k] + dl[k] >= -kLocateTol)) {
+                    const double sk = l[k] > 0.0 ? l[k] / (-dl[k]) : 0.0;
+                    if (kmin < 0 || sk < smin) {
+                        smin = sk;
+                        kmin = k;
+                    }
+                }
+            if (kmin < 0) break;
+            int nb = -1;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (k == kmin) nb = tp.n[k];
+            if (nb < 0 || ++hops > kLocateHopCap) {
+                ok = false;
+                break;
+            }
+            double lc[4], sum = 0.0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                lc[k] = (k == kmin) ? 0.0 : fmax(l[k] + smin * dl[k], 0.0);
+                sum += lc[k];
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) d[c] -= smin * d[c];
+            const TetTopo tn = topo[nb];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                double v = 0.0;
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (tp.v[i] == tn.v[j]) v = lc[i] / sum;
+                l[j] = v;
+            }
+            T = nb;
+        }
+    }
+    if (!ok) {
+        tet[p] = -1;
+        atomicAdd(fails, 1u);
+        return;
+    }
+    const TetTopo tp = topo[T];
+    const double *r0 = xyz + 3 * (int64_t)tp.v[0];
+    const double dx[3] = {x[0] - r0[0], x[1] - r0[1], x[2] - r0[2]};
+    const double *gp = grad + (int64_t)T * 12;
+    lam1[p] = gp[3] * dx[0] + gp[4] * dx[1] + gp[5] * dx[2];
+    lam2[p] = gp[6] * dx[0] + gp[7] * dx[1] + gp[8] * dx[2];
+    lam3[p] = gp[9] * dx[0] + gp[10] * dx[1] + gp[11] * dx[2];
+    tet[p] = T;
+}
+
+// x = sum_k lam_k r_k of every particle (lam_0 = 1 - lam_1 - lam_2 - lam_3).
+__global__ void __launch_bounds__(kBlock) k_positions(int64_t n, int64_t nt, const double *__restrict__ lam1,
+                                                      const double *__restrict__ lam2, const double *__restrict__ lam3,
+                                                      const int32_t *__restrict__ tet, const TetTopo *__restrict__ topo,
+                                                      const double *__restrict__ xyz, double *__restrict__ x0,
+                                                      double *__restrict__ x1, double *__restrict__ x2,
+                                                      unsigned *__restrict__ status) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int T = tet[p];
+    if ((unsigned)T >= (unsigned)nt) {
+        atomicOr(status, (unsigned)ETPIC_DEV_BADTET);
+        x0[p] = x1[p] = x2[p] = NAN;
+        return;
+    }
+    const double l[4] = {1.0 - lam1[p] - lam2[p] - lam3[p], lam1[p], lam2[p], lam3[p]};
+    const TetTopo tp = topo[T];
+    double x[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) x[c] += l[k] * xyz[3 * (int64_t)tp.v[k] + c];
+    x0[p] = x[0];
+    x1[p] = x[1];
+    x2[p] = x[2];
+}
+
 // ------------------------------------------------------------------ vertex charge
 __global__ void __launch_bounds__(kBlock) k_charge(int64_t n, int64_t nt, const double *__restrict__ lam1,
                                                    const double *__restrict__ lam2, const double *__restrict__ lam3,
@@ -1206,6 +1347,9 @@ struct etpic_ctx {
     void *d_coef = nullptr;          // nt*24 doubles (float table uses the first half)
     int32_t *d_v2e_ptr = nullptr;
     int32_t *d_v2e_code = nullptr;
+    double *d_xyz = nullptr;         // 3*nv vertex coordinates
+    int32_t *d_grid = nullptr;       // start tets of the point-location grid
+    GridArgs grid{};
     unsigned *d_status = nullptr;    // device status word
     unsigned *d_walk_queue = nullptr;  // kWalkQueueCap block indices
     unsigned *d_walk_ctr = nullptr;    // 2 counters of the walk queue
@@ -1301,6 +1445,8 @@ struct etpic_ctx {
         (void)hipFree(d_coef);
         (void)hipFree(d_v2e_ptr);
         (void)hipFree(d_v2e_code);
+        (void)hipFree(d_xyz);
+        (void)hipFree(d_grid);
         (void)hipFree(d_count);
         (void)hipFree(d_tilesum);
         d_topo = nullptr;
@@ -1309,6 +1455,9 @@ struct etpic_ctx {
         d_gpush32 = nullptr;
         d_coef = nullptr;
         d_v2e_ptr = d_v2e_code = nullptr;
+        d_xyz = nullptr;
+        d_grid = nullptr;
+        grid = GridArgs{};
         d_count = d_tilesum = nullptr;
         field.release();
         has_mesh = false;
@@ -1477,6 +1626,20 @@ int etpic_mesh_upload(etpic_ctx *ctx, int64_t n_vert, const double *xyz_host, in
         HIP_TRY(hipMemcpy(ctx->d_gpush32, gp32.data(), sizeof(float) * s32 * nt, hipMemcpyHostToDevice));
     }
     HIP_TRY(hipMalloc(&ctx->d_coef, sizeof(double) * 24 * nt));
+    {
+        etpic::StartGrid sg;
+        etpic::build_start_grid(M, xyz_host, 2.0, sg);
+        HIP_TRY(hipMalloc(&ctx->d_xyz, sizeof(double) * 3 * M.nv));
+        HIP_TRY(hipMalloc(&ctx->d_grid, sizeof(int32_t) * sg.cell.size()));
+        HIP_TRY(hipMemcpy(ctx->d_xyz, xyz_host, sizeof(double) * 3 * M.nv, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(ctx->d_grid, sg.cell.data(), sizeof(int32_t) * sg.cell.size(), hipMemcpyHostToDevice));
+        ctx->grid.cell = ctx->d_grid;
+        for (int d = 0; d < 3; ++d) {
+            ctx->grid.lo[d] = sg.lo[d];
+            ctx->grid.inv[d] = sg.inv[d];
+            ctx->grid.dims[d] = sg.dims[d];
+        }
+    }
     HIP_TRY(hipMalloc(&ctx->d_v2e_ptr, sizeof(int32_t) * (M.nv + 1)));
     HIP_TRY(hipMalloc(&ctx->d_v2e_code, sizeof(int32_t) * 2 * M.ne));
     HIP_TRY(hipMalloc(&ctx->d_count, sizeof(unsigned) * (nt + 1)));
@@ -1638,6 +1801,46 @@ int etpic_backward(etpic_ctx *ctx, int64_t n, const etpic_species *sp, const etp
             HIP_TRY(hipGetLastError());
         }
     }
+    return ETPIC_OK;
+}
+
+int etpic_particles_locate(etpic_ctx *ctx, const etpic_particles *p, const double *const xyz[3],
+                           const int32_t *hint, void *stream) {
+    if (!ctx || !p || !xyz) return fail(ETPIC_EINVAL, "null argument");
+    if (!ctx->has_mesh) return fail(ETPIC_ESTATE, "no mesh uploaded");
+    if (p->n < 0 || p->n > (int64_t)kWalkQueueCap * 64) return fail(ETPIC_EINVAL, "particle count outside [0, 2^29]");
+    if (p->n == 0) return ETPIC_OK;
+    if (!p->lam[0] || !p->lam[1] || !p->lam[2] || !p->tet || !xyz[0] || !xyz[1] || !xyz[2])
+        return fail(ETPIC_EINVAL, "null particle or position array");
+    if (int r = set_device(ctx)) return r;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    unsigned *fails = reinterpret_cast<unsigned *>(ctx->d_red);
+    k_fill_u32<<<1, kBlock, 0, st>>>(fails, 1, 0u);
+    k_locate<<<grid_for(p->n), kBlock, 0, st>>>(p->n, xyz[0], xyz[1], xyz[2], hint, ctx->host.nt, ctx->d_topo,
+                                                ctx->d_grad64, ctx->d_xyz, ctx->grid, p->lam[0], p->lam[1],
+                                                p->lam[2], p->tet, fails);
+    HIP_TRY(hipGetLastError());
+    unsigned nfail = 0;
+    HIP_TRY(hipMemcpyAsync(&nfail, fails, sizeof nfail, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (nfail)
+        return fail(ETPIC_EPARTICLE, "%u of %lld points not located (outside the mesh, non-finite, or not reachable by "
+                    "a straight walk from the start tet); their tet is set to -1", nfail, (long long)p->n);
+    return ETPIC_OK;
+}
+
+int etpic_particles_positions(etpic_ctx *ctx, const etpic_particles *p, double *const xyz[3], void *stream) {
+    if (!ctx || !p || !xyz) return fail(ETPIC_EINVAL, "null argument");
+    if (!ctx->has_mesh) return fail(ETPIC_ESTATE, "no mesh uploaded");
+    if (p->n < 0 || p->n > (int64_t)kWalkQueueCap * 64) return fail(ETPIC_EINVAL, "particle count outside [0, 2^29]");
+    if (p->n == 0) return ETPIC_OK;
+    if (!p->lam[0] || !p->lam[1] || !p->lam[2] || !p->tet || !xyz[0] || !xyz[1] || !xyz[2])
+        return fail(ETPIC_EINVAL, "null particle or position array");
+    if (int r = set_device(ctx)) return r;
+    k_positions<<<grid_for(p->n), kBlock, 0, static_cast<hipStream_t>(stream)>>>(
+        p->n, ctx->host.nt, p->lam[0], p->lam[1], p->lam[2], p->tet, ctx->d_topo, ctx->d_xyz, xyz[0], xyz[1], xyz[2],
+        ctx->d_status);
+    HIP_TRY(hipGetLastError());
     return ETPIC_OK;
 }
 

@@ -135,4 +135,64 @@ int build_host_mesh(int64_t nv, const double *xyz, int64_t nt, const int32_t *tv
     return 0;
 }
 
+void build_start_grid(const HostMesh &m, const double *xyz, double tets_per_cell, StartGrid &g) {
+    double lo[3] = {xyz[0], xyz[1], xyz[2]}, hi[3] = {xyz[0], xyz[1], xyz[2]};
+    for (int64_t i = 1; i < m.nv; ++i)
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = std::min(lo[d], xyz[3 * i + d]);
+            hi[d] = std::max(hi[d], xyz[3 * i + d]);
+        }
+    double ext[3], vol = 1.0;
+    for (int d = 0; d < 3; ++d) {
+        ext[d] = std::max(hi[d] - lo[d], 1e-300);
+        vol *= ext[d];
+    }
+    const double cells = std::max(1.0, std::min((double)m.nt / tets_per_cell, (double)(1 << 24)));
+    const double h = std::cbrt(vol / cells);
+    int64_t total = 1;
+    for (int d = 0; d < 3; ++d) {
+        g.dims[d] = (int32_t)std::max(1.0, std::min(std::ceil(ext[d] / h), 4096.0));
+        g.lo[d] = lo[d];
+        g.inv[d] = g.dims[d] / ext[d];
+        total *= g.dims[d];
+    }
+    g.cell.assign((size_t)total, -1);
+    auto cell_of = [&](const double *x) {
+        int64_t c[3];
+        for (int d = 0; d < 3; ++d)
+            c[d] = std::min<int64_t>(g.dims[d] - 1, std::max<int64_t>(0, (int64_t)std::floor((x[d] - g.lo[d]) * g.inv[d])));
+        return c[0] + g.dims[0] * (c[1] + (int64_t)g.dims[1] * c[2]);
+    };
+    for (int64_t t = 0; t < m.nt; ++t) {
+        double c[3] = {0, 0, 0};
+        for (int k = 0; k < 4; ++k)
+            for (int d = 0; d < 3; ++d) c[d] += 0.25 * xyz[3 * m.topo[t].v[k] + d];
+        int32_t &slot = g.cell[(size_t)cell_of(c)];
+        if (slot < 0) slot = (int32_t)t;
+    }
+    // cells without a centroid take a face-neighbour cell's tet, in passes
+    const int64_t nx = g.dims[0], ny = g.dims[1], nz = g.dims[2];
+    for (bool changed = true; changed;) {
+        changed = false;
+        std::vector<int32_t> prev(g.cell);
+        for (int64_t k = 0; k < nz; ++k)
+            for (int64_t j = 0; j < ny; ++j)
+                for (int64_t i = 0; i < nx; ++i) {
+                    const int64_t id = i + nx * (j + ny * k);
+                    if (prev[id] >= 0) continue;
+                    const int64_t nb[6][3] = {{i - 1, j, k}, {i + 1, j, k}, {i, j - 1, k},
+                                              {i, j + 1, k}, {i, j, k - 1}, {i, j, k + 1}};
+                    for (const auto &q : nb) {
+                        if (q[0] < 0 || q[0] >= nx || q[1] < 0 || q[1] >= ny || q[2] < 0 || q[2] >= nz) continue;
+                        const int32_t t = prev[q[0] + nx * (q[1] + ny * q[2])];
+                        if (t >= 0) {
+                            g.cell[id] = t;
+                            changed = true;
+                            break;
+                        }
+                    }
+                }
+    }
+}
+
 }  // namespace etpic

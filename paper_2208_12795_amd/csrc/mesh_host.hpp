@@ -32,6 +32,19 @@ struct HostMesh {
     std::vector<int32_t> v2e_code;  // 2*ne: (edge << 1) | (vertex is the head)
 };
 
+// Uniform grid over the mesh's bounding box that gives every cell one tet to
+// start a point-location walk from (a tet whose centroid lies in the cell, or,
+// for a cell holding no centroid, one borrowed from a nearby cell).
+struct StartGrid {
+    double lo[3] = {0, 0, 0};    // box corner
+    double inv[3] = {1, 1, 1};   // cells per unit length, per axis
+    int32_t dims[3] = {1, 1, 1};
+    std::vector<int32_t> cell;    // dims[0]*dims[1]*dims[2], x fastest
+};
+
+// About one cell per `tets_per_cell` tets (at least one cell per axis).
+void build_start_grid(const HostMesh &m, const double *xyz, double tets_per_cell, StartGrid &g);
+
 // Builds every table from the raw mesh.  Returns 0, -1 (bad input) or -4
 // (unsorted row, degenerate tet, non-manifold face); err gets the reason.
 int build_host_mesh(int64_t nv, const double *xyz, int64_t nt, const int32_t *tv, HostMesh &out,

@@ -29,6 +29,7 @@ EXPORTS = (
     "etpic_vertex_charge", "etpic_gauss_residual", "etpic_kernel_time", "etpic_check",
     "etpic_adjoint_workspace", "etpic_forward_checkpointed", "etpic_backward",
     "etpic_field_setup", "etpic_field_nnz", "etpic_field_spmv", "etpic_field_step",
+    "etpic_particles_locate", "etpic_particles_positions",
 )
 
 
@@ -86,6 +87,8 @@ def lib():
                                  C.c_double, C.c_double, C.c_int, vp, C.c_size_t, C.c_void_p * 3, C.c_void_p * 3,
                                  vp, vp]
     L.etpic_check.argtypes = [vp, vp, C.POINTER(C.c_uint32)]
+    L.etpic_particles_locate.argtypes = [vp, C.POINTER(_Particles), C.c_void_p * 3, vp, vp]
+    L.etpic_particles_positions.argtypes = [vp, C.POINTER(_Particles), C.c_void_p * 3, vp]
     L.etpic_field_setup.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_double]
     L.etpic_field_nnz.argtypes = [vp, i64p]
     L.etpic_field_spmv.argtypes = [vp, vp, vp, C.c_double, C.c_double, C.c_double, vp]
@@ -294,6 +297,29 @@ class Context:
     def sort(self, src, dst, stream=None):
         a, b = src.desc(), dst.desc()
         _chk(lib().etpic_sort(self._h, C.byref(a), C.byref(b), src.precision, _stream(stream)))
+
+    def locate(self, xyz, parts, hint=None, stream=None, raise_on_error=True):
+        """Locate the points xyz (float64 [3, N] on the device) into parts.tet /
+        parts.lam (parts.vel is not touched).  hint: int32 [N] start tets or None.
+        Returns the status (OK, or EPARTICLE when some points were not located
+        and raise_on_error is False; those get tet -1)."""
+        assert xyz.is_contiguous() and xyz.dim() == 2 and xyz.shape[0] == 3 and xyz.shape[1] == parts.n
+        d = parts.desc()
+        x = (C.c_void_p * 3)(*[xyz[k].data_ptr() for k in range(3)])
+        rc = lib().etpic_particles_locate(self._h, C.byref(d), x, _dptr(hint), _stream(stream))
+        if rc != OK and (raise_on_error or rc != EPARTICLE):
+            _chk(rc)
+        return rc
+
+    def positions(self, parts, xyz=None, stream=None):
+        """Cartesian positions of the particles, float64 [3, N] on the device."""
+        import torch
+        if xyz is None:
+            xyz = torch.empty((3, parts.n), dtype=torch.float64, device=parts.lam.device)
+        d = parts.desc()
+        x = (C.c_void_p * 3)(*[xyz[k].data_ptr() for k in range(3)])
+        _chk(lib().etpic_particles_positions(self._h, C.byref(d), x, _stream(stream)))
+        return xyz
 
     def vertex_charge(self, parts, species, rho, stream=None):
         d = parts.desc()

@@ -2,12 +2,15 @@
 """Throughput of the envelope-tracking particle-mesh step on one MI355X.
 
 A step is one pass of the particle path over all particles: the per-tet
-carrier-rotated field coefficients, the fused gather / Boris push / tet walk /
-path-integral deposit kernel, and the counting sort by tet every
-`--sort-every` steps (amortised, inside the timed region).  The workload is the
-40^3 x 6 jittered Kuhn mesh (384,000 tets) with 10,000,000 electrons
-(Maxwellian, 1e6 m/s), an 8-mode envelope on a 10 GHz carrier, B = 0.5 T, dt =
-1e-12 s.  Inputs are resident in HBM before the timed region starts.
+carrier-rotated field coefficients (k_tet_coef), the particle kernel (gather,
+Boris push, in-tet path-integral deposit with same-tet sums before the edge
+atomics; k_push), the walk of the particles that left their tet (k_walk), and
+the counting sort by tet every `--sort-every` steps (amortised, inside the
+timed region).  Default workload: the 40^3 x 6 jittered Kuhn mesh (384,000
+tets) with 10,000,000 electrons (Maxwellian, 1e6 m/s), an 8-mode envelope on a
+10 GHz carrier, B = 0.5 T, dt = 1e-12 s; `--workload large-box` runs the 2:1:1
+160x80x80 x 6 mesh with 2e8 electrons (bunch + background, B = 1 T along x).
+Inputs are resident in HBM before the timed region starts.
 
 Prints ONE JSON line.  `value` is the float64 form; the mixed form (float32
 gather/push on barycentrics, float64 positions and deposit) is reported under
@@ -40,6 +43,14 @@ BYTES_PER_EDGE = 16
 KERNEL_NAME = {"fp64": "k_push<double>", "mixed": "k_push<float>"}
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_push_hbm_traffic_40cube_1e7.md")
 COPY_CALIB_BYTES = 1 << 30
+CPU_SAMPLE_MAX = 10_000_000
+WORKLOADS = {
+    "40cube": (2, "40^3x6 jittered Kuhn tet mesh (384,000 tets), 1e7 electrons (Maxwellian 1e6 m/s), "
+                  "8-mode envelope on a 10 GHz carrier, B 0.5 T, dt 1e-12 s"),
+    "large-box": (5, "2:1:1 box, 160x80x80x6 jittered Kuhn tets (6,144,000), 2e8 electrons: half a Gaussian "
+                     "bunch (sigma 0.1, drift 1e7 m/s along x), half uniform background (1e6 m/s), 8-mode "
+                     "envelope on a 10 GHz carrier, B 1 T along x, dt 1e-12 s"),
+}
 
 
 def log(*a):
@@ -120,10 +131,10 @@ def run_form(E, torch, ctx, w, precision, steps, warmup, sort_every, fields):
     }
 
 
-def cpu_baseline(w, nthreads, steps):
+def cpu_baseline(w, nthreads, steps, stride):
     import oracle
     M = oracle.OracleMesh(w.xyz, w.tet_vert)
-    tet, lam, vel = w.tet.copy(), w.lam.copy(), w.vel.copy()
+    tet, lam, vel = (np.ascontiguousarray(a[::stride]) for a in (w.tet, w.lam, w.vel))
     dG = np.zeros(M.ne)
     t0 = time.perf_counter()
     cpu0 = time.process_time()
@@ -138,6 +149,8 @@ def cpu_baseline(w, nthreads, steps):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="40cube",
+                    help="40cube: the throughput workload (default); large-box: the 2:1:1 bunch workload")
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--particles", type=int, default=None, help="override the particle count (default 1e7)")
@@ -178,7 +191,8 @@ def main():
             f"({2 * COPY_CALIB_BYTES / (c0.elapsed_time(c1) * 1e-3) / 1e9:.0f} GB/s)")
         del src, dst
     t0 = time.perf_counter()
-    w = synth.make_workload(2, n_particles=args.particles)
+    cfg, desc = WORKLOADS[args.workload]
+    w = synth.make_workload(cfg, n_particles=args.particles)
     log(f"[bench] workload generated in {time.perf_counter() - t0:.1f}s: N_p={w.tet.shape[0]} N_t={w.tet_vert.shape[0]}")
     ctx = E.Context(0)
     ctx.upload_mesh(w.xyz, w.tet_vert)
@@ -195,7 +209,7 @@ def main():
         bytes_launch = BYTES_PER_PARTICLE[form] * n_p + BYTES_PER_TET[form] * n_t + BYTES_PER_EDGE * n_e
         ach = bytes_launch / (r["kernel_ms"] * 1e-3) / 1e9
         traffic = None
-        if args.particles is None:
+        if args.particles is None and args.workload == "40cube":
             traffic = rocprof_summary.read_traffic(TRAFFIC_SUMMARY, KERNEL_NAME[form])
         return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": KERNEL_NAME[form],
@@ -216,8 +230,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if main_form == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "40^3x6 jittered Kuhn tet mesh (384,000 tets), 1e7 electrons, 8-mode envelope "
-                               "10 GHz, B 0.5 T, dt 1e-12 s, sort every %d steps" % args.sort_every,
+        "config": {"workload": desc + ", sort every %d steps" % args.sort_every,
                    "n_particles": n_p, "n_tets": n_t, "n_edges": n_e, "parallelism": "single GPU"},
         "roofline": roofline(main_form),
         "sort_ms": r["sort_ms"],
@@ -231,9 +244,11 @@ def main():
                          "gauss_rel": m["gauss_rel"]}
     if not args.no_cpu_baseline:
         nth = args.cpu_threads or max(1, min(16, os.cpu_count() or 1))
-        val, wall, cpu = cpu_baseline(w, nth, args.cpu_steps)
+        stride = max(1, n_p // CPU_SAMPLE_MAX)
+        val, wall, cpu = cpu_baseline(w, nth, args.cpu_steps, stride)
+        which = f"all {n_p} particles" if stride == 1 else f"every {stride}th of the {n_p} particles"
         line["cpu_baseline"] = {"value": val, "unit": "particle-steps/s", "cores": nth, "kind": "oracle",
-                                "sample": f"all {n_p} particles, first {args.cpu_steps} steps (float64 oracle, "
+                                "sample": f"{which}, first {args.cpu_steps} steps (float64 oracle, "
                                           f"OpenMP over particles); wall {wall:.1f}s, cpu {cpu:.1f}s"}
     print(json.dumps(line), flush=True)
     ctx.close()

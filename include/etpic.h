@@ -80,7 +80,19 @@ enum etpic_device_flags {
 /* flags of etpic_gather_push_deposit */
 enum etpic_step_flags {
     ETPIC_STEP_XCD_REMAP = 1u, /* map consecutive particle blocks to one XCD (default on) */
-    ETPIC_STEP_TIMING = 2u     /* bracket the step's kernels with HIP events (etpic_kernel_time) */
+    ETPIC_STEP_TIMING = 2u,    /* bracket the step's kernels with HIP events (etpic_kernel_time) */
+    /* slices of 64 particles per wavefront of the particle kernel; without one
+     * of these the library picks 1, 4 or 16 from the last etpic_sort's mean,
+     * over particles, of the number of particles in the same tet (1 before any
+     * sort).  Longer slices cut same-address atomics where thousands of
+     * particles share a tet. */
+    ETPIC_STEP_SLICES_1 = 4u,
+    ETPIC_STEP_SLICES_4 = 8u,
+    ETPIC_STEP_SLICES_16 = 16u,
+    /* queue the particles that leave their tet by 64-particle slice, the path
+     * the library otherwise takes only when more than 2^23 particles leave
+     * their tet in one step (exercises that path) */
+    ETPIC_STEP_WALK_BY_SLICE = 32u
 };
 
 #define ETPIC_HOP_CAP 64

@@ -52,8 +52,10 @@ int fail(int code, const char *fmt, ...) {
     } while (0)
 
 constexpr int kBlock = 256;
-constexpr unsigned kWalkQueueCap = 1u << 23;  // wavefronts; bounds N_p by 2^29
+constexpr unsigned kWalkQueueCap = 1u << 23;  // entries of each walk queue; N_p <= 64 * kWalkQueueCap
+constexpr unsigned kQueueSkip = 0xffffffffu;  // particle-queue entry to skip
 constexpr unsigned kWalkBlocks = 256;         // grid of the walk kernel
+constexpr int64_t kMinPushWaves = 16384;      // 256 CUs x 64 wavefronts
 
 // Runs of equal key among the 64 lanes of a wavefront (particles are kept
 // sorted by tet, so neighbouring lanes mostly share a key).  head: first lane
@@ -63,9 +65,9 @@ struct WaveRuns {
     bool head;
 };
 
-__device__ __forceinline__ WaveRuns wave_runs(int key) {
+__device__ __forceinline__ WaveRuns wave_runs(int key, int lane = threadIdx.x & 63) {
     WaveRuns r;
-    r.lane = threadIdx.x & 63;
+    r.lane = lane;
     const int prev = __shfl_up(key, 1);
     r.head = r.lane == 0 || key != prev;
     const unsigned long long hm = __ballot(r.head);
@@ -226,8 +228,10 @@ struct StepArgs {
     double *dG;
     double *rho;
     unsigned *status;
-    unsigned *walk_queue;      // blocks holding particles that left their tet
-    unsigned *walk_ctr;        // [0] queue length, [1] walk blocks done
+    unsigned *walk_queue;      // particles that left their tet
+    unsigned *slice_queue;     // 64-particle slices whose walkers did not fit in walk_queue
+    unsigned *walk_ctr;        // [0] walk_queue length, [1] walk blocks done, [2] slice_queue length
+    int walk_by_slice;         // queue every walker by its slice (the overflow path)
     double qw;
     Real h;                    // q dt / (2 m)
     Real dt_r;
@@ -361,6 +365,23 @@ __device__ __forceinline__ int walk(const StepArgs<Real> &a, int T, double l[4],
     return T;
 }
 
+
+// q w * (the run's path-integral sums) onto the six edges of tet T, and
+// q w * (its end-point barycentric sums) onto the four vertices if rho is kept.
+template <typename Real>
+__device__ __forceinline__ void flush_run(const StepArgs<Real> &a, int T, const double g6[6], const double r4[4]) {
+    const int32_t *ed = push_row_edges(a.gpush + (int64_t)T * PushRow<Real>::kStride);
+#pragma unroll
+    for (int e = 0; e < 6; ++e)
+        if (g6[e] != 0.0) unsafeAtomicAdd(&a.dG[ed[e]], a.qw * g6[e]);
+    if (a.rho) {
+        const TetTopo *tp = a.topo + T;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (r4[k] != 0.0) unsafeAtomicAdd(&a.rho[tp->v[k]], a.qw * r4[k]);
+    }
+}
+
 // ------------------------------------------------------------------ particle step
 // One lane per particle, particles kept sorted by tet.  Each lane reads its
 // tet's row of this step's coefficient table (lanes of a run share the row, so
@@ -370,9 +391,17 @@ __device__ __forceinline__ int walk(const StepArgs<Real> &a, int T, double l[4],
 // wavefront (segmented scan by DPP lane moves); the run's last lane
 // adds the sums to the edges with float64 global atomics.  There are no block
 // barriers, so latency is hidden by occupancy alone.  Particles that leave
-// their tet are marked and their wavefront queued for k_walk.
-template <typename Real>
-__global__ void __launch_bounds__(kBlock) k_push(StepArgs<Real> a, int remap) {
+// their tet are marked and their 64-particle slice queued for k_walk.
+//
+// A wavefront handles kSlices consecutive slices of 64 particles.  With more
+// than one, the run that reaches lane 63 stays open: its sums are parked in
+// LDS and taken over by lane 0 of the next slice if the tet continues, so a
+// tet holding thousands of particles is flushed a few times instead of once
+// per wavefront (same-address atomics from many wavefronts serialise).  With
+// about one wavefront's worth of particles per tet or fewer, one slice per
+// wavefront keeps more wavefronts in flight and is faster.
+template <typename Real, int kSlices>
+__device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) {
     unsigned blk = blockIdx.x;
     if (remap) {
         // the dispatcher deals blocks round-robin over the 8 XCDs; give each XCD
@@ -380,153 +409,229 @@ __global__ void __launch_bounds__(kBlock) k_push(StepArgs<Real> a, int remap) {
         const unsigned G = gridDim.x, q = G / 8, r = G % 8, x = blk % 8, j = blk / 8;
         blk = x * q + min(x, r) + j;
     }
-    const int64_t p = (int64_t)blk * kBlock + threadIdx.x;
-    int T = -1;
-    if (p < a.n) {
-        T = a.tet[p];
-        if ((unsigned)T >= (unsigned)a.nt) {
-            atomicOr(a.status, (unsigned)ETPIC_DEV_BADTET);
-            T = -1;
-        }
-    }
-    const bool act = T >= 0;
-    double g6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // this lane's in-tet path integrals
-    double r4[4] = {0.0, 0.0, 0.0, 0.0};             // this lane's end-point barycentrics
-    int walker = 0;
-    if (act) {
-        double l[4];
-        l[1] = a.lam1[p];
-        l[2] = a.lam2[p];
-        l[3] = a.lam3[p];
-        l[0] = 1.0 - l[1] - l[2] - l[3];
-        Real v[3] = {a.v0[p], a.v1[p], a.v2[p]};
-        const Real *cf = a.coef + (int64_t)T * 24;
-        Real E[3], B[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            E[d] = (Real)l[0] * cf[d] + (Real)l[1] * cf[3 + d] + (Real)l[2] * cf[6 + d] + (Real)l[3] * cf[9 + d];
-            B[d] = (Real)l[0] * cf[12 + d] + (Real)l[1] * cf[15 + d] + (Real)l[2] * cf[18 + d] + (Real)l[3] * cf[21 + d];
-        }
-        // Boris: half kick, rotation (implicit midpoint in v x B), half kick
-        const Real h = a.h;
-        Real vm[3], tau[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            vm[d] = v[d] + h * E[d];
-            tau[d] = h * B[d];
-        }
-        const Real t2 = tau[0] * tau[0] + tau[1] * tau[1] + tau[2] * tau[2];
-        const Real sg = (Real)2 / ((Real)1 + t2);
-        const Real vr[3] = {vm[0] + (vm[1] * tau[2] - vm[2] * tau[1]), vm[1] + (vm[2] * tau[0] - vm[0] * tau[2]),
-                            vm[2] + (vm[0] * tau[1] - vm[1] * tau[0])};
-        v[0] = vm[0] + sg * (vr[1] * tau[2] - vr[2] * tau[1]) + h * E[0];
-        v[1] = vm[1] + sg * (vr[2] * tau[0] - vr[0] * tau[2]) + h * E[1];
-        v[2] = vm[2] + sg * (vr[0] * tau[1] - vr[1] * tau[0]) + h * E[2];
-        if (!(isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]))) atomicOr(a.status, (unsigned)ETPIC_DEV_NAN);
-        // displacement and barycentric increments; lam0 is stored implicitly
-        // (1 - lam1 - lam2 - lam3), so its increment is minus the sum of the
-        // other three, in float64: deposit and stored end point see the same
-        // four increments (continuity to float64 rounding)
-        const Real dx[3] = {a.dt_r * v[0], a.dt_r * v[1], a.dt_r * v[2]};
-        const Real *gr = a.gpush + (int64_t)T * PushRow<Real>::kStride;
-        double dl[4];
-#pragma unroll
-        for (int k = 1; k < 4; ++k)
-            dl[k] = (double)(gr[3 * k - 3] * dx[0] + gr[3 * k - 2] * dx[1] + gr[3 * k - 1] * dx[2]);
-        dl[0] = -(dl[1] + dl[2] + dl[3]);
-        const bool stays = (l[0] + dl[0] >= 0.0) && (l[1] + dl[1] >= 0.0) && (l[2] + dl[2] >= 0.0) &&
-                           (l[3] + dl[3] >= 0.0);
-        if (stays) {
-            // path integral of W1_ij along the straight piece: m_i dl_j - m_j dl_i,
-            // m the midpoint barycentrics (exact: the integrand is affine on the piece)
-            double m[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) m[k] = l[k] + 0.5 * dl[k];
-            constexpr int le[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
-#pragma unroll
-            for (int e = 0; e < 6; ++e) g6[e] = m[le[e][0]] * dl[le[e][1]] - m[le[e][1]] * dl[le[e][0]];
-#pragma unroll
-            for (int k = 1; k < 4; ++k) l[k] += dl[k];
-            a.lam1[p] = l[1];
-            a.lam2[p] = l[2];
-            a.lam3[p] = l[3];
-            if (a.rho) {
-                r4[0] = 1.0 - l[1] - l[2] - l[3];
-                r4[1] = l[1];
-                r4[2] = l[2];
-                r4[3] = l[3];
+    // wv is the same in all lanes; readfirstlane tells the compiler so, which
+    // keeps the slice loop and the per-slice array bases in scalar registers
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t first = ((int64_t)blk * (kBlock / 64) + wv) * kSlices;
+    // the run still open at the end of the previous slice: its tet (wave-uniform)
+    // and its sums, parked in LDS by lane 63 (6 path integrals, 4 barycentrics)
+    __shared__ double s_carry[kBlock / 64][10];
+    int carry_T = -1;
+#pragma unroll 1
+    for (int it = 0; it < kSlices; ++it) {
+        const int64_t slice = first + it;
+        if (slice * 64 >= a.n) break;
+        // per-slice bases are wave-uniform: every array is addressed as a
+        // scalar base plus the lane offset; the lane index is re-materialised in
+        // every slice, so that the compiler does not keep per-lane addresses
+        // alive across the loop
+        const int64_t b0 = slice * 64;
+        int ln = lane;
+        asm volatile("" : "+v"(ln));
+        const int64_t p = b0 + ln;
+        double *__restrict__ lam1 = a.lam1 + b0, *__restrict__ lam2 = a.lam2 + b0, *__restrict__ lam3 = a.lam3 + b0;
+        Real *__restrict__ v0 = a.v0 + b0, *__restrict__ v1 = a.v1 + b0, *__restrict__ v2 = a.v2 + b0;
+        int32_t *__restrict__ tetp = a.tet + b0;
+        int T = -1;
+        if (p < a.n) {
+            T = tetp[ln];
+            if ((unsigned)T >= (unsigned)a.nt) {
+                atomicOr(a.status, (unsigned)ETPIC_DEV_BADTET);
+                T = -1;
             }
-        } else {
-            a.tet[p] = walker_mark(T);
-            walker = 1;
         }
-        a.v0[p] = v[0];
-        a.v1[p] = v[1];
-        a.v2[p] = v[2];
-    }
-    // segmented reduction over runs of equal tet; the run's last lane adds to HBM
-    const WaveRuns runs = wave_runs(T);
+        const bool act = T >= 0;
+        double g6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // this lane's in-tet path integrals
+        double r4[4] = {0.0, 0.0, 0.0, 0.0};             // this lane's end-point barycentrics
+        int walker = 0;
+        if (act) {
+            double l[4];
+            l[1] = lam1[ln];
+            l[2] = lam2[ln];
+            l[3] = lam3[ln];
+            l[0] = 1.0 - l[1] - l[2] - l[3];
+            Real v[3] = {v0[ln], v1[ln], v2[ln]};
+            const Real *cf = a.coef + (int64_t)T * 24;
+            Real E[3], B[3];
 #pragma unroll
-    for (int e = 0; e < 6; ++e) g6[e] = run_total(g6[e], runs);
-    if (a.rho) {
+            for (int d = 0; d < 3; ++d) {
+                E[d] = (Real)l[0] * cf[d] + (Real)l[1] * cf[3 + d] + (Real)l[2] * cf[6 + d] + (Real)l[3] * cf[9 + d];
+                B[d] = (Real)l[0] * cf[12 + d] + (Real)l[1] * cf[15 + d] + (Real)l[2] * cf[18 + d] + (Real)l[3] * cf[21 + d];
+            }
+            // Boris: half kick, rotation (implicit midpoint in v x B), half kick
+            const Real h = a.h;
+            Real vm[3], tau[3];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) r4[k] = run_total(r4[k], runs);
-    }
-    if (act && runs.lane == runs.run_end) {
-        const int32_t *ed = push_row_edges(a.gpush + (int64_t)T * PushRow<Real>::kStride);
+            for (int d = 0; d < 3; ++d) {
+                vm[d] = v[d] + h * E[d];
+                tau[d] = h * B[d];
+            }
+            const Real t2 = tau[0] * tau[0] + tau[1] * tau[1] + tau[2] * tau[2];
+            const Real sg = (Real)2 / ((Real)1 + t2);
+            const Real vr[3] = {vm[0] + (vm[1] * tau[2] - vm[2] * tau[1]), vm[1] + (vm[2] * tau[0] - vm[0] * tau[2]),
+                                vm[2] + (vm[0] * tau[1] - vm[1] * tau[0])};
+            v[0] = vm[0] + sg * (vr[1] * tau[2] - vr[2] * tau[1]) + h * E[0];
+            v[1] = vm[1] + sg * (vr[2] * tau[0] - vr[0] * tau[2]) + h * E[1];
+            v[2] = vm[2] + sg * (vr[0] * tau[1] - vr[1] * tau[0]) + h * E[2];
+            if (!(isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]))) atomicOr(a.status, (unsigned)ETPIC_DEV_NAN);
+            // displacement and barycentric increments; lam0 is stored implicitly
+            // (1 - lam1 - lam2 - lam3), so its increment is minus the sum of the
+            // other three, in float64: deposit and stored end point see the same
+            // four increments (continuity to float64 rounding)
+            const Real dx[3] = {a.dt_r * v[0], a.dt_r * v[1], a.dt_r * v[2]};
+            const Real *gr = a.gpush + (int64_t)T * PushRow<Real>::kStride;
+            double dl[4];
 #pragma unroll
-        for (int e = 0; e < 6; ++e)
-            if (g6[e] != 0.0) unsafeAtomicAdd(&a.dG[ed[e]], a.qw * g6[e]);
+            for (int k = 1; k < 4; ++k)
+                dl[k] = (double)(gr[3 * k - 3] * dx[0] + gr[3 * k - 2] * dx[1] + gr[3 * k - 1] * dx[2]);
+            dl[0] = -(dl[1] + dl[2] + dl[3]);
+            const bool stays = (l[0] + dl[0] >= 0.0) && (l[1] + dl[1] >= 0.0) && (l[2] + dl[2] >= 0.0) &&
+                               (l[3] + dl[3] >= 0.0);
+            if (stays) {
+                // path integral of W1_ij along the straight piece: m_i dl_j - m_j dl_i,
+                // m the midpoint barycentrics (exact: the integrand is affine on the piece)
+                double m[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) m[k] = l[k] + 0.5 * dl[k];
+                constexpr int le[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+#pragma unroll
+                for (int e = 0; e < 6; ++e) g6[e] = m[le[e][0]] * dl[le[e][1]] - m[le[e][1]] * dl[le[e][0]];
+#pragma unroll
+                for (int k = 1; k < 4; ++k) l[k] += dl[k];
+                lam1[ln] = l[1];
+                lam2[ln] = l[2];
+                lam3[ln] = l[3];
+                if (a.rho) {
+                    r4[0] = 1.0 - l[1] - l[2] - l[3];
+                    r4[1] = l[1];
+                    r4[2] = l[2];
+                    r4[3] = l[3];
+                }
+            } else {
+                tetp[ln] = walker_mark(T);
+                walker = 1;
+            }
+            v0[ln] = v[0];
+            v1[ln] = v[1];
+            v2[ln] = v[2];
+        }
+        const WaveRuns runs = wave_runs(T, ln);
+        // the open run continues into this slice: lane 0 takes over its sums;
+        // otherwise it is complete and flushed now
+        if (kSlices > 1 && carry_T >= 0) {
+            __builtin_amdgcn_wave_barrier();
+            if (ln == 0) {
+                double cg[6], cr[4];
+#pragma unroll
+                for (int e = 0; e < 6; ++e) cg[e] = s_carry[wv][e];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) cr[k] = s_carry[wv][6 + k];
+                if (T == carry_T) {
+#pragma unroll
+                    for (int e = 0; e < 6; ++e) g6[e] += cg[e];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) r4[k] += cr[k];
+                } else {
+                    flush_run(a, carry_T, cg, cr);
+                }
+            }
+        }
+        // segmented reduction over runs of equal tet; the run's last lane holds
+        // its sums and adds them to HBM, except for the run reaching lane 63,
+        // which stays open for the next slice
+#pragma unroll
+        for (int e = 0; e < 6; ++e) g6[e] = run_total(g6[e], runs);
         if (a.rho) {
-            const TetTopo *tp = a.topo + T;
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (r4[k] != 0.0) unsafeAtomicAdd(&a.rho[tp->v[k]], a.qw * r4[k]);
+            for (int k = 0; k < 4; ++k) r4[k] = run_total(r4[k], runs);
+        }
+        const bool last = it == kSlices - 1 || (slice + 1) * 64 >= a.n;
+        if (act && runs.lane == runs.run_end && (ln != 63 || last)) flush_run(a, T, g6, r4);
+        if (!last) {
+            carry_T = __builtin_amdgcn_readlane(T, 63);
+            if (ln == 63) {
+#pragma unroll
+                for (int e = 0; e < 6; ++e) s_carry[wv][e] = g6[e];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) s_carry[wv][6 + k] = r4[k];
+            }
+        }
+        // walkers go to the particle queue (one atomic per wavefront); a
+        // wavefront whose walkers do not all fit queues its slice instead
+        const unsigned long long wmask = __ballot(walker);
+        if (wmask) {
+            const unsigned cnt = (unsigned)__popcll(wmask);
+            unsigned base = 0;
+            if (ln == 0) base = atomicAdd(&a.walk_ctr[0], cnt);
+            base = __shfl(base, 0);
+            const bool fits = !a.walk_by_slice && base < kWalkQueueCap && cnt <= kWalkQueueCap - base;
+            const unsigned rank = (unsigned)__popcll(wmask & ((1ull << ln) - 1ull));
+            if (walker && base + rank < kWalkQueueCap) a.walk_queue[base + rank] = fits ? (unsigned)p : kQueueSkip;
+            if (!fits && ln == 0) a.slice_queue[atomicAdd(&a.walk_ctr[2], 1u)] = (unsigned)slice;
         }
     }
-    if (__ballot(walker) && runs.lane == 0)
-        a.walk_queue[atomicAdd(&a.walk_ctr[0], 1u)] = (unsigned)(((int64_t)blk * kBlock + threadIdx.x) >> 6);
 }
 
-// Walks the marked particles of the queued wavefronts: every piece of their
-// path is deposited with global atomics, and the end point, reflected velocity
-// and new tet are stored.  Each wavefront strides over the queue; the last
-// block to finish resets the counters for the next step.
+template <typename Real>
+__global__ void __launch_bounds__(kBlock) k_push(StepArgs<Real> a, int remap) {
+    push_slices<Real, 1>(a, remap);
+}
+
+template <typename Real, int kSlices>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7)))
+k_push_slices(StepArgs<Real> a, int remap) {
+    push_slices<Real, kSlices>(a, remap);
+}
+
+// Walk of one marked particle p: every piece of its path is deposited with
+// global atomics, and the end point, reflected velocity and new tet are stored.
+template <typename Real>
+__device__ __forceinline__ void walk_particle(const StepArgs<Real> &a, int64_t p) {
+    const int marked = a.tet[p];
+    if (marked > -2) return;
+    int T = walker_tet(marked);
+    if (T >= a.nt) return;
+    double l[4];
+    l[1] = a.lam1[p];
+    l[2] = a.lam2[p];
+    l[3] = a.lam3[p];
+    l[0] = 1.0 - l[1] - l[2] - l[3];
+    Real v[3] = {a.v0[p], a.v1[p], a.v2[p]};
+    const Real dx[3] = {a.dt_r * v[0], a.dt_r * v[1], a.dt_r * v[2]};
+    double d[3] = {(double)dx[0], (double)dx[1], (double)dx[2]};
+    T = walk<Real, false>(a, T, l, d, v, nullptr);
+    a.tet[p] = T;
+    a.lam1[p] = l[1];
+    a.lam2[p] = l[2];
+    a.lam3[p] = l[3];
+    a.v0[p] = v[0];
+    a.v1[p] = v[1];
+    a.v2[p] = v[2];
+    if (a.rho) {
+        const TetTopo tp = a.topo[T];
+        const double l0 = 1.0 - l[1] - l[2] - l[3];
+        unsafeAtomicAdd(&a.rho[tp.v[0]], a.qw * l0);
+        unsafeAtomicAdd(&a.rho[tp.v[1]], a.qw * l[1]);
+        unsafeAtomicAdd(&a.rho[tp.v[2]], a.qw * l[2]);
+        unsafeAtomicAdd(&a.rho[tp.v[3]], a.qw * l[3]);
+    }
+}
+
+// Walks the queued particles, one lane each, then the particles of the
+// overflow slices, one wavefront per slice.  The last block to finish resets
+// the counters for the next step.
 template <typename Real>
 __global__ void __launch_bounds__(kBlock) k_walk(StepArgs<Real> a) {
-    const unsigned count = __atomic_load_n(&a.walk_ctr[0], __ATOMIC_RELAXED);
+    const unsigned count = min(__atomic_load_n(&a.walk_ctr[0], __ATOMIC_RELAXED), kWalkQueueCap);
+    for (unsigned i = blockIdx.x * kBlock + threadIdx.x; i < count; i += gridDim.x * kBlock) {
+        const unsigned q = a.walk_queue[i];
+        if (q != kQueueSkip && (int64_t)q < a.n) walk_particle(a, (int64_t)q);
+    }
+    const unsigned slices = __atomic_load_n(&a.walk_ctr[2], __ATOMIC_RELAXED);
     const unsigned wpb = kBlock / 64;
-    for (unsigned i = blockIdx.x * wpb + (threadIdx.x >> 6); i < count; i += gridDim.x * wpb) {
-        const int64_t p = (int64_t)a.walk_queue[i] * 64 + (threadIdx.x & 63);
-        if (p >= a.n) continue;
-        const int marked = a.tet[p];
-        if (marked > -2) continue;
-        int T = walker_tet(marked);
-        if (T >= a.nt) continue;
-        double l[4];
-        l[1] = a.lam1[p];
-        l[2] = a.lam2[p];
-        l[3] = a.lam3[p];
-        l[0] = 1.0 - l[1] - l[2] - l[3];
-        Real v[3] = {a.v0[p], a.v1[p], a.v2[p]};
-        const Real dx[3] = {a.dt_r * v[0], a.dt_r * v[1], a.dt_r * v[2]};
-        double d[3] = {(double)dx[0], (double)dx[1], (double)dx[2]};
-        T = walk<Real, false>(a, T, l, d, v, nullptr);
-        a.tet[p] = T;
-        a.lam1[p] = l[1];
-        a.lam2[p] = l[2];
-        a.lam3[p] = l[3];
-        a.v0[p] = v[0];
-        a.v1[p] = v[1];
-        a.v2[p] = v[2];
-        if (a.rho) {
-            const TetTopo tp = a.topo[T];
-            const double l0 = 1.0 - l[1] - l[2] - l[3];
-            unsafeAtomicAdd(&a.rho[tp.v[0]], a.qw * l0);
-            unsafeAtomicAdd(&a.rho[tp.v[1]], a.qw * l[1]);
-            unsafeAtomicAdd(&a.rho[tp.v[2]], a.qw * l[2]);
-            unsafeAtomicAdd(&a.rho[tp.v[3]], a.qw * l[3]);
-        }
+    for (unsigned i = blockIdx.x * wpb + (threadIdx.x >> 6); i < slices; i += gridDim.x * wpb) {
+        const int64_t p = (int64_t)a.slice_queue[i] * 64 + (threadIdx.x & 63);
+        if (p < a.n) walk_particle(a, p);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -534,6 +639,7 @@ __global__ void __launch_bounds__(kBlock) k_walk(StepArgs<Real> a) {
         if (atomicAdd(&a.walk_ctr[1], 1u) == gridDim.x - 1) {
             a.walk_ctr[0] = 0u;
             a.walk_ctr[1] = 0u;
+            a.walk_ctr[2] = 0u;
         }
     }
 }
@@ -927,6 +1033,22 @@ __global__ void __launch_bounds__(kBlock) k_hist(int64_t n, int64_t nt, const in
 }
 
 constexpr int kScanTile = 1024;   // elements per block in the block-local scan (4 per thread)
+
+// sum over tets of count^2 (count = particles in the tet), accumulated into
+// *out: sum(count^2) / N_p is the mean length of the same-tet run a particle
+// belongs to, which picks the slices per wavefront of the particle kernel.
+__global__ void __launch_bounds__(kBlock) k_run_stat(int64_t nt, const unsigned *__restrict__ count,
+                                                     unsigned long long *__restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long c2 = 0;
+    if (t < nt) {
+        const unsigned long long c = count[t];
+        c2 = c * c;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c2 += __shfl_xor(c2, off);
+    if ((threadIdx.x & 63) == 0 && c2) atomicAdd(out, c2);
+}
 
 // Exclusive scan of each 1024-element tile in place; tile totals to sums[].
 __global__ void __launch_bounds__(kBlock) k_scan_tiles(unsigned *__restrict__ x, int64_t n,
@@ -1351,9 +1473,19 @@ struct etpic_ctx {
     int32_t *d_grid = nullptr;       // start tets of the point-location grid
     GridArgs grid{};
     unsigned *d_status = nullptr;    // device status word
-    unsigned *d_walk_queue = nullptr;  // kWalkQueueCap block indices
-    unsigned *d_walk_ctr = nullptr;    // 2 counters of the walk queue
+    unsigned *d_walk_queue = nullptr;  // kWalkQueueCap particle indices
+    unsigned *d_slice_queue = nullptr; // kWalkQueueCap slice indices
+    unsigned *d_walk_ctr = nullptr;    // 3 counters of the walk queues
     unsigned long long *d_red = nullptr;  // 2 words for the residual maxima
+    // mean same-tet run length from the last sort (sum count^2 / N_p), read
+    // back without blocking: the device word, its pinned host copy, the event
+    // that marks the copy, and the value in use (0 until a sort has been seen)
+    unsigned long long *d_runstat = nullptr;
+    unsigned long long *h_runstat = nullptr;
+    hipEvent_t runstat_ev = nullptr;
+    bool runstat_pending = false;
+    int64_t runstat_n = 0;
+    double run_len = 0.0;
     unsigned *d_count = nullptr;     // nt+1 counting-sort counters
     unsigned *d_tilesum = nullptr;   // scan tile totals
     int64_t tiles = 0;
@@ -1397,6 +1529,7 @@ struct etpic_ctx {
         a.rho = rho;
         a.status = d_status;
         a.walk_queue = d_walk_queue;
+        a.slice_queue = d_slice_queue;
         a.walk_ctr = d_walk_ctr;
         a.qw = sp->q * sp->w;
         a.h = (Real)(sp->q * dt / (2.0 * sp->m));
@@ -1414,6 +1547,7 @@ struct etpic_ctx {
         const double t = (double)step * dt;
         const double c = std::cos(omega * t), s = std::sin(omega * t);
         StepArgs<Real> a = step_args<Real>(p, sp, dt, dG, rho);
+        a.walk_by_slice = (flags & ETPIC_STEP_WALK_BY_SLICE) ? 1 : 0;
         hipEvent_t *ev = nullptr;
         if (flags & ETPIC_STEP_TIMING) {
             if (int r = timing_events(&ev)) return r;
@@ -1424,7 +1558,13 @@ struct etpic_ctx {
         k_tet_coef<Real><<<grid_for(2 * nt), kBlock, 0, st>>>(nt, d_topo, d_grad64, F, static_cast<Real *>(d_coef));
         HIP_TRY(hipGetLastError());
         if (ev) HIP_TRY(hipEventRecord(ev[1], st));
-        k_push<Real><<<grid_for(p->n), kBlock, 0, st>>>(a, (flags & ETPIC_STEP_XCD_REMAP) ? 1 : 0);
+        const int remap = (flags & ETPIC_STEP_XCD_REMAP) ? 1 : 0;
+        const int64_t n = p->n;
+        switch (push_slices_for(flags, n)) {
+        case 16: k_push_slices<Real, 16><<<grid_for((n + 15) / 16), kBlock, 0, st>>>(a, remap); break;
+        case 4: k_push_slices<Real, 4><<<grid_for((n + 3) / 4), kBlock, 0, st>>>(a, remap); break;
+        default: k_push<Real><<<grid_for(n), kBlock, 0, st>>>(a, remap); break;
+        }
         HIP_TRY(hipGetLastError());
         if (ev) HIP_TRY(hipEventRecord(ev[2], st));
         k_walk<Real><<<kWalkBlocks, kBlock, 0, st>>>(a);
@@ -1436,6 +1576,24 @@ struct etpic_ctx {
 
     template <typename Real>
     const Real *gpush_table() const;
+
+    // Slices per wavefront of the particle kernel: forced by a flag, else from
+    // the mean same-tet run length of the last sort (one slice while runs fit
+    // in a wavefront; 4 or 16 for longer runs), kept to >= kMinPushWaves
+    // wavefronts so that the chip stays full.
+    int push_slices_for(uint32_t flags, int64_t n) {
+        if (flags & ETPIC_STEP_SLICES_16) return 16;
+        if (flags & ETPIC_STEP_SLICES_4) return 4;
+        if (flags & ETPIC_STEP_SLICES_1) return 1;
+        if (runstat_pending && hipEventQuery(runstat_ev) == hipSuccess) {
+            run_len = runstat_n > 0 ? (double)*h_runstat / (double)runstat_n : 0.0;
+            runstat_pending = false;
+        }
+        (void)hipGetLastError();   // an unfinished query is not an error
+        int s = run_len >= 256.0 ? 16 : (run_len >= 96.0 ? 4 : 1);
+        while (s > 1 && n / (64 * (int64_t)s) < kMinPushWaves) s /= 4;
+        return s;
+    }
 
     void release() {
         (void)hipFree(d_topo);
@@ -1560,15 +1718,23 @@ int etpic_create(etpic_ctx **out, int device) {
     hipError_t e = hipSetDevice(device);
     if (e == hipSuccess) e = hipMalloc(&c->d_status, sizeof(unsigned));
     if (e == hipSuccess) e = hipMalloc(&c->d_red, 2 * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMalloc(&c->d_runstat, sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipHostMalloc(&c->h_runstat, sizeof(unsigned long long), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->runstat_ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipMalloc(&c->d_walk_queue, sizeof(unsigned) * kWalkQueueCap);
-    if (e == hipSuccess) e = hipMalloc(&c->d_walk_ctr, 2 * sizeof(unsigned));
+    if (e == hipSuccess) e = hipMalloc(&c->d_slice_queue, sizeof(unsigned) * kWalkQueueCap);
+    if (e == hipSuccess) e = hipMalloc(&c->d_walk_ctr, 3 * sizeof(unsigned));
     if (e == hipSuccess) e = hipMemset(c->d_status, 0, sizeof(unsigned));
-    if (e == hipSuccess) e = hipMemset(c->d_walk_ctr, 0, 2 * sizeof(unsigned));
+    if (e == hipSuccess) e = hipMemset(c->d_walk_ctr, 0, 3 * sizeof(unsigned));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         (void)hipFree(c->d_status);
         (void)hipFree(c->d_red);
+        (void)hipFree(c->d_runstat);
+        if (c->h_runstat) (void)hipHostFree(c->h_runstat);
+        if (c->runstat_ev) (void)hipEventDestroy(c->runstat_ev);
         (void)hipFree(c->d_walk_queue);
+        (void)hipFree(c->d_slice_queue);
         (void)hipFree(c->d_walk_ctr);
         delete c;
         return fail(ETPIC_EHIP, "context setup: %s", hipGetErrorString(e));
@@ -1584,7 +1750,11 @@ int etpic_destroy(etpic_ctx *ctx) {
     ctx->release();
     (void)hipFree(ctx->d_status);
     (void)hipFree(ctx->d_red);
+    (void)hipFree(ctx->d_runstat);
+    (void)hipHostFree(ctx->h_runstat);
+    (void)hipEventDestroy(ctx->runstat_ev);
     (void)hipFree(ctx->d_walk_queue);
+    (void)hipFree(ctx->d_slice_queue);
     (void)hipFree(ctx->d_walk_ctr);
     for (auto &e : ctx->timing)
         for (auto x : e) (void)hipEventDestroy(x);
@@ -1894,6 +2064,14 @@ int etpic_sort(etpic_ctx *ctx, const etpic_particles *src, const etpic_particles
     const int64_t nt = ctx->host.nt, n = src->n, m = nt + 1;
     k_fill_u32<<<grid_for(m), kBlock, 0, st>>>(ctx->d_count, m, 0u);
     k_hist<<<grid_for(n), kBlock, 0, st>>>(n, nt, src->tet, ctx->d_count, ctx->d_status);
+    if (!ctx->runstat_pending) {
+        k_fill_u32<<<1, kBlock, 0, st>>>(reinterpret_cast<unsigned *>(ctx->d_runstat), 2, 0u);
+        k_run_stat<<<grid_for(nt), kBlock, 0, st>>>(nt, ctx->d_count, ctx->d_runstat);
+        HIP_TRY(hipMemcpyAsync(ctx->h_runstat, ctx->d_runstat, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipEventRecord(ctx->runstat_ev, st));
+        ctx->runstat_pending = true;
+        ctx->runstat_n = n;
+    }
     k_scan_tiles<<<(unsigned)ctx->tiles, kBlock, 0, st>>>(ctx->d_count, m, ctx->d_tilesum);
     k_scan_sums<<<1, kBlock, 0, st>>>(ctx->d_tilesum, ctx->tiles);
     k_scan_add<<<grid_for(m), kBlock, 0, st>>>(ctx->d_count, m, ctx->d_tilesum);

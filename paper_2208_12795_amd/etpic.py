@@ -21,6 +21,8 @@ FP64, MIXED = 0, 1
 DEV_HOPCAP, DEV_NAN, DEV_BADTET = 1, 2, 4
 STEP_XCD_REMAP = 1
 STEP_TIMING = 2
+STEP_SLICES_1, STEP_SLICES_4, STEP_SLICES_16 = 4, 8, 16
+STEP_WALK_BY_SLICE = 32
 HOP_CAP = 64
 
 EXPORTS = (

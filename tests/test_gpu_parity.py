@@ -104,13 +104,16 @@ def test_small_config_mixed(E, torch_cuda, ora):
     run_case(E, torch_cuda, ora, synth.make_workload(1), 30, E.MIXED, 2e-5)
 
 
+@pytest.mark.parametrize("by_slice", [False, True])
 @pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 2e-5)])
-def test_crossing_heavy(E, torch_cuda, ora, precision, tol):
+def test_crossing_heavy(E, torch_cuda, ora, precision, tol, by_slice):
     """Steps of 0.1-0.5 cell: most particles cross faces, several per step, and
-    many hit the walls (reflection)."""
+    many hit the walls (reflection).  Walkers queued one by one, and by slice
+    (the path taken when the particle queue overflows)."""
     w = synth.make_workload(1, n_particles=4000)
     w.vel = w.vel * 40.0
-    run_case(E, torch_cuda, ora, w, 12, precision, tol, dt=1e-8)
+    flags = E.STEP_XCD_REMAP | (E.STEP_WALK_BY_SLICE if by_slice else 0)
+    run_case(E, torch_cuda, ora, w, 12, precision, tol, dt=1e-8, flags=flags)
 
 
 @pytest.mark.parametrize("presort", [False, True])
@@ -123,6 +126,41 @@ def test_ragged_and_multi_tile(E, torch_cuda, ora, presort):
         order = np.argsort(w.tet, kind="stable")
         w.tet, w.lam, w.vel, w.ids = w.tet[order], w.lam[order], w.vel[order], w.ids[order]
     run_case(E, torch_cuda, ora, w, 3, E.FP64, 1e-12)
+
+
+@pytest.mark.parametrize("slices", [1, 4, 16])
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 2e-5)])
+def test_dense_tets_slices(E, torch_cuda, ora, slices, precision, tol):
+    """About 400 particles per tet on the 750-tet cube, sorted by tet, so runs of
+    one tet span several wavefronts; 1, 4 and 16 slices of 64 particles per
+    wavefront (runs carried across slice boundaries).  Each step against the
+    oracle (velocities, positions, currents) and the vertex charge deposited
+    inside the step against a separate charge scatter after it."""
+    torch = torch_cuda
+    w = synth.make_workload(1, n_particles=300_007)
+    order = np.argsort(w.tet, kind="stable")
+    w.tet, w.lam, w.vel, w.ids = w.tet[order], w.lam[order], w.vel[order], w.ids[order]
+    flags = E.STEP_XCD_REMAP | {1: E.STEP_SLICES_1, 4: E.STEP_SLICES_4, 16: E.STEP_SLICES_16}[slices]
+    print(f"[dense] slices {slices} precision {precision}", flush=True)
+    ctx, parts, fields = setup(E, torch, w, precision)
+    M = ora.OracleMesh(w.xyz, w.tet_vert)
+    sp = E.Species(w.q, w.m, w.w)
+    for s in range(3):
+        tin, lin, vin, _ = parts.to_numpy()
+        dG = torch.zeros(ctx.n_edge, dtype=torch.float64, device="cuda")
+        rho_step = torch.zeros(ctx.n_vert, dtype=torch.float64, device="cuda")
+        ctx.gather_push_deposit(parts, sp, fields, s, w.dt, w.omega, dG, rho=rho_step, flags=flags)
+        rho_after = torch.zeros_like(rho_step)
+        ctx.vertex_charge(parts, sp, rho_after)
+        assert torch.allclose(rho_step, rho_after, rtol=0, atol=1e-13 * rho_after.abs().max().item())
+        rc, o, dGo = oracle_step(M, (tin, lin, vin.astype(np.float64)), w, s, nthreads=NTH)
+        assert rc == 0
+        tg, lg, vg, _ = parts.to_numpy()
+        err = step_errors(w.xyz, w.tet_vert, (tin, lin, vin), (tg, lg, vg), o, dG.cpu().numpy(), dGo)
+        assert err["tet_mismatch"] <= 2 + 1e-4 * len(tg), err
+        assert_within(err, tol, f"slices {slices} step {s}")
+    ctx.check()
+    ctx.close()
 
 
 def test_omega_zero_matches_regular(E, torch_cuda):
@@ -289,3 +327,13 @@ def test_full_size_mixed_40cube_5e7(E, torch_cuda, ora):
     """Precision form at its real size: 40^3 x 6 tets, 5e7 electrons, float32
     gather/push with float64 positions and deposit, against the float64 oracle."""
     full_size_step(E, torch_cuda, ora, synth.make_workload(3), E.MIXED, 2e-5)
+
+
+def test_large_box_bunch_one_gpu_share(E, torch_cuda, ora):
+    """The large mixed-precision workload's mesh and plasma at one GPU's share:
+    2:1:1 box, 160x80x80 x 6 tets (6.1e6), 2.5e7 electrons (1/8 of 2e8: half a
+    Gaussian bunch drifting at 1e7 m/s along x, half uniform background),
+    B = 1 T along x; mixed and float64 forms against the float64 oracle."""
+    w = synth.make_workload(5, n_particles=25_000_000)
+    full_size_step(E, torch_cuda, ora, w, E.MIXED, 2e-5)
+    full_size_step(E, torch_cuda, ora, w, E.FP64, 1e-12)

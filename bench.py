@@ -131,6 +131,79 @@ def run_form(E, torch, ctx, w, precision, steps, warmup, sort_every, fields):
     }
 
 
+def field_update_timing(E, torch, ctx, w, reps=20):
+    """Side path, timed separately: the implicit envelope field step on the
+    bench mesh (Jacobi-preconditioned COCG with the CSR SpMV).  A random
+    interior state is advanced once; SpMV bandwidth from its algorithmic bytes
+    (column index 4 B + M and K values 8 B each per nonzero; row pointer 4 B,
+    x read and y written 16 B each per row)."""
+    eps0, mu0 = 8.8541878128e-12, 1.25663706212e-6
+    nnz = ctx.field_setup(w.dt, w.omega, eps0, mu0)
+    ne, nf = ctx.n_edge, ctx.n_face
+    g = torch.Generator(device="cuda").manual_seed(5)
+    x = torch.randn((ne, 2), dtype=torch.float64, device="cuda", generator=g)
+    y = torch.empty_like(x)
+    ctx.field_spmv(x, y, 1.0 + 0.1j, 1e-3)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        ctx.field_spmv(x, y, 1.0 + 0.1j, 1e-3)
+    e1.record()
+    torch.cuda.synchronize()
+    spmv_ms = e0.elapsed_time(e1) / reps
+    spmv_bytes = 20 * nnz + 36 * ne
+    u = torch.randn((ne, 2), dtype=torch.float64, device="cuda", generator=g)
+    v = torch.randn((ne, 2), dtype=torch.float64, device="cuda", generator=g) * 1e9
+    a = torch.zeros((ne, 2), dtype=torch.float64, device="cuda")
+    b = torch.zeros((nf, 2), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, iters, res = ctx.field_step(w.dt, u, v, a, b, None, tol=1e-10, max_iter=1000, raise_on_error=False)
+    torch.cuda.synchronize()
+    step_ms = 1e3 * (time.perf_counter() - t0)
+    return {"n_edges": ne, "nnz": nnz, "spmv_ms": spmv_ms, "spmv_GBs": spmv_bytes / (spmv_ms * 1e-3) / 1e9,
+            "step_ms": step_ms, "cocg_iterations": iters, "rel_residual": res, "status": rc,
+            "note": "side path, not in value; one Newmark step from a random interior state, tol 1e-10"}
+
+
+def adjoint_timing(E, torch, synth):
+    """Differentiation workload: 20^3 x 6 tets, 2e6 electrons, 20 float64 steps
+    with a checkpoint every 5, then the reverse sweep (gradient of the final
+    kinetic energy with respect to the complex edge envelope)."""
+    w = synth.make_workload(4)
+    ctx = E.Context(0)
+    ctx.upload_mesh(w.xyz, w.tet_vert)
+    fields = E.Fields.from_numpy(w.e_env, w.b_env, None, w.b_dc)
+    sp = E.Species(w.q, w.m, w.w)
+    parts = E.Particles.from_numpy(w.tet, w.lam, w.vel, w.ids)
+    spare = parts.empty_like()
+    ctx.sort(parts, spare)
+    parts = spare
+    K, every = 20, 5
+    ws = torch.empty(ctx.adjoint_workspace_bytes(parts.n, K, every), dtype=torch.uint8, device="cuda")
+    res = {}
+    for rep in range(2):   # the first pass warms up
+        work = parts.clone()
+        torch.cuda.synchronize()
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record()
+        ctx.forward_checkpointed(work, sp, fields, 0, K, w.dt, w.omega, every, ws)
+        e1.record()
+        vbar = (w.m * w.w) * work.vel.clone()
+        xbar = torch.zeros_like(vbar)
+        grad = torch.zeros((ctx.n_edge, 2), dtype=torch.float64, device="cuda")
+        ctx.backward(parts.n, sp, fields, 0, K, w.dt, w.omega, every, ws, vbar, xbar, grad)
+        e2.record()
+        torch.cuda.synchronize()
+        res = {"forward_ms": e0.elapsed_time(e1), "backward_ms": e1.elapsed_time(e2)}
+    ctx.check()
+    ctx.close()
+    res["backward_over_forward"] = res["backward_ms"] / res["forward_ms"]
+    res["workload"] = "20^3x6 tets, 2e6 electrons, 20 float64 steps, checkpoint every 5"
+    return res
+
+
 def cpu_baseline(w, nthreads, steps, stride):
     import oracle
     M = oracle.OracleMesh(w.xyz, w.tet_vert)
@@ -159,6 +232,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--cpu-threads", type=int, default=0, help="0 = min(16, host cores)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-side", action="store_true",
+                    help="skip the side measurements (field update, adjoint)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -242,6 +317,11 @@ def main():
         line["mixed"] = {"value": m["value"], "ms_per_step": m["ms_per_step"], "dtype": "f32 gather/push, f64 deposit",
                          "speedup_vs_fp64": m["value"] / r["value"], "roofline": roofline("mixed"),
                          "gauss_rel": m["gauss_rel"]}
+    if not args.no_side and args.workload == "40cube":
+        line["field_update"] = field_update_timing(E, torch, ctx, w)
+        log(f"[bench] field update: {json.dumps(line['field_update'])}")
+        line["adjoint"] = adjoint_timing(E, torch, synth)
+        log(f"[bench] adjoint: {json.dumps(line['adjoint'])}")
     if not args.no_cpu_baseline:
         nth = args.cpu_threads or max(1, min(16, os.cpu_count() or 1))
         stride = max(1, n_p // CPU_SAMPLE_MAX)

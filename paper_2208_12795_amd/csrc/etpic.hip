@@ -424,7 +424,9 @@ __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) 
         // per-slice bases are wave-uniform: every array is addressed as a
         // scalar base plus the lane offset; the lane index is re-materialised in
         // every slice, so that the compiler does not keep per-lane addresses
-        // alive across the loop
+        // alive across the loop.  The particle state is streamed with
+        // non-temporal loads and stores, which leaves the caches to the per-tet
+        // rows, the field DoFs and the current accumulator.
         const int64_t b0 = slice * 64;
         int ln = lane;
         asm volatile("" : "+v"(ln));
@@ -434,7 +436,7 @@ __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) 
         int32_t *__restrict__ tetp = a.tet + b0;
         int T = -1;
         if (p < a.n) {
-            T = tetp[ln];
+            T = __builtin_nontemporal_load(&tetp[ln]);
             if ((unsigned)T >= (unsigned)a.nt) {
                 atomicOr(a.status, (unsigned)ETPIC_DEV_BADTET);
                 T = -1;
@@ -446,11 +448,11 @@ __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) 
         int walker = 0;
         if (act) {
             double l[4];
-            l[1] = lam1[ln];
-            l[2] = lam2[ln];
-            l[3] = lam3[ln];
+            l[1] = __builtin_nontemporal_load(&lam1[ln]);
+            l[2] = __builtin_nontemporal_load(&lam2[ln]);
+            l[3] = __builtin_nontemporal_load(&lam3[ln]);
             l[0] = 1.0 - l[1] - l[2] - l[3];
-            Real v[3] = {v0[ln], v1[ln], v2[ln]};
+            Real v[3] = {__builtin_nontemporal_load(&v0[ln]), __builtin_nontemporal_load(&v1[ln]), __builtin_nontemporal_load(&v2[ln])};
             const Real *cf = a.coef + (int64_t)T * 24;
             Real E[3], B[3];
 #pragma unroll
@@ -498,9 +500,9 @@ __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) 
                 for (int e = 0; e < 6; ++e) g6[e] = m[le[e][0]] * dl[le[e][1]] - m[le[e][1]] * dl[le[e][0]];
 #pragma unroll
                 for (int k = 1; k < 4; ++k) l[k] += dl[k];
-                lam1[ln] = l[1];
-                lam2[ln] = l[2];
-                lam3[ln] = l[3];
+                __builtin_nontemporal_store(l[1], &lam1[ln]);
+                __builtin_nontemporal_store(l[2], &lam2[ln]);
+                __builtin_nontemporal_store(l[3], &lam3[ln]);
                 if (a.rho) {
                     r4[0] = 1.0 - l[1] - l[2] - l[3];
                     r4[1] = l[1];
@@ -511,9 +513,9 @@ __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) 
                 tetp[ln] = walker_mark(T);
                 walker = 1;
             }
-            v0[ln] = v[0];
-            v1[ln] = v[1];
-            v2[ln] = v[2];
+            __builtin_nontemporal_store(v[0], &v0[ln]);
+            __builtin_nontemporal_store(v[1], &v1[ln]);
+            __builtin_nontemporal_store(v[2], &v2[ln]);
         }
         const WaveRuns runs = wave_runs(T, ln);
         // the open run continues into this slice: lane 0 takes over its sums;
@@ -1039,15 +1041,22 @@ constexpr int kScanTile = 1024;   // elements per block in the block-local scan 
 // belongs to, which picks the slices per wavefront of the particle kernel.
 __global__ void __launch_bounds__(kBlock) k_run_stat(int64_t nt, const unsigned *__restrict__ count,
                                                      unsigned long long *__restrict__ out) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long c2 = 0;
-    if (t < nt) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += (int64_t)gridDim.x * blockDim.x) {
         const unsigned long long c = count[t];
-        c2 = c * c;
+        c2 += c * c;
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) c2 += __shfl_xor(c2, off);
-    if ((threadIdx.x & 63) == 0 && c2) atomicAdd(out, c2);
+    __shared__ unsigned long long s_part[kBlock / 64];
+    if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = c2;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long sum = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) sum += s_part[w];
+        if (sum) atomicAdd(out, sum);
+    }
 }
 
 // Exclusive scan of each 1024-element tile in place; tile totals to sums[].
@@ -2066,7 +2075,7 @@ int etpic_sort(etpic_ctx *ctx, const etpic_particles *src, const etpic_particles
     k_hist<<<grid_for(n), kBlock, 0, st>>>(n, nt, src->tet, ctx->d_count, ctx->d_status);
     if (!ctx->runstat_pending) {
         k_fill_u32<<<1, kBlock, 0, st>>>(reinterpret_cast<unsigned *>(ctx->d_runstat), 2, 0u);
-        k_run_stat<<<grid_for(nt), kBlock, 0, st>>>(nt, ctx->d_count, ctx->d_runstat);
+        k_run_stat<<<(unsigned)std::min<int64_t>(grid_for(nt), 256), kBlock, 0, st>>>(nt, ctx->d_count, ctx->d_runstat);
         HIP_TRY(hipMemcpyAsync(ctx->h_runstat, ctx->d_runstat, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipEventRecord(ctx->runstat_ev, st));
         ctx->runstat_pending = true;

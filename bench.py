@@ -47,6 +47,8 @@ CPU_SAMPLE_MAX = 10_000_000
 WORKLOADS = {
     "40cube": (2, "40^3x6 jittered Kuhn tet mesh (384,000 tets), 1e7 electrons (Maxwellian 1e6 m/s), "
                   "8-mode envelope on a 10 GHz carrier, B 0.5 T, dt 1e-12 s"),
+    "precision": (3, "40^3x6 jittered Kuhn tet mesh (384,000 tets), 5e7 electrons (Maxwellian 1e6 m/s), "
+                     "8-mode envelope on a 10 GHz carrier, B 0.5 T, dt 1e-12 s"),
     "large-box": (5, "2:1:1 box, 160x80x80x6 jittered Kuhn tets (6,144,000), 2e8 electrons: half a Gaussian "
                      "bunch (sigma 0.1, drift 1e7 m/s along x), half uniform background (1e6 m/s), 8-mode "
                      "envelope on a 10 GHz carrier, B 1 T along x, dt 1e-12 s"),
@@ -204,6 +206,24 @@ def adjoint_timing(E, torch, synth):
     return res
 
 
+def copy_bandwidth(torch, nbytes=1 << 31, reps=10):
+    """Device-to-device copy rate (bytes read + written per second): the
+    practical streaming ceiling next to the nominal HBM peak."""
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(w, nthreads, steps, stride):
     import oracle
     M = oracle.OracleMesh(w.xyz, w.tet_vert)
@@ -223,7 +243,8 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="40cube",
-                    help="40cube: the throughput workload (default); large-box: the 2:1:1 bunch workload")
+                    help="40cube: the throughput workload (default); precision: the same mesh with 5e7 "
+                         "electrons; large-box: the 2:1:1 bunch workload")
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--particles", type=int, default=None, help="override the particle count (default 1e7)")
@@ -265,6 +286,8 @@ def main():
         log(f"[bench] copy calibration: {COPY_CALIB_BYTES} B read + written in {c0.elapsed_time(c1):.3f} ms "
             f"({2 * COPY_CALIB_BYTES / (c0.elapsed_time(c1) * 1e-3) / 1e9:.0f} GB/s)")
         del src, dst
+    copy_gbs = copy_bandwidth(torch)
+    log(f"[bench] device copy: {copy_gbs:.0f} GB/s")
     t0 = time.perf_counter()
     cfg, desc = WORKLOADS[args.workload]
     w = synth.make_workload(cfg, n_particles=args.particles)
@@ -288,6 +311,7 @@ def main():
             traffic = rocprof_summary.read_traffic(TRAFFIC_SUMMARY, KERNEL_NAME[form])
         return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": KERNEL_NAME[form],
+                "copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(ach / copy_gbs, 4),
                 "bytes_per_launch": bytes_launch, "kernel_ms": round(r["kernel_ms"], 5)}
 
     main_form = "fp64" if "fp64" in res else next(iter(res))
@@ -327,9 +351,13 @@ def main():
         stride = max(1, n_p // CPU_SAMPLE_MAX)
         val, wall, cpu = cpu_baseline(w, nth, args.cpu_steps, stride)
         which = f"all {n_p} particles" if stride == 1 else f"every {stride}th of the {n_p} particles"
+        one, wall1, _ = cpu_baseline(w, 1, 1, max(stride, n_p // 1_000_000))
         line["cpu_baseline"] = {"value": val, "unit": "particle-steps/s", "cores": nth, "kind": "oracle",
                                 "sample": f"{which}, first {args.cpu_steps} steps (float64 oracle, "
-                                          f"OpenMP over particles); wall {wall:.1f}s, cpu {cpu:.1f}s"}
+                                          f"OpenMP over particles); wall {wall:.1f}s, cpu {cpu:.1f}s",
+                                "single_thread_value": one,
+                                "single_thread_sample": f"every {max(stride, n_p // 1_000_000)}th particle, "
+                                                        f"first step, 1 thread; wall {wall1:.1f}s"}
     print(json.dumps(line), flush=True)
     ctx.close()
 

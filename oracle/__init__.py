@@ -51,6 +51,9 @@ def _load():
     lib.ora_vjp.argtypes = [vp, C.c_int64, _ip, _dp, _dp, C.c_double, C.c_double, C.c_double, C.c_int64, C.c_int,
                             C.c_double, C.c_double, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, C.c_int]
     lib.ora_vjp.restype = C.c_int
+    lib.ora_jvp.argtypes = [vp, C.c_int64, _ip, _dp, _dp, C.c_double, C.c_double, C.c_int64, C.c_int, C.c_double,
+                            C.c_double, _dp, _dp, _dp, _dp, _dp, _dp, _dp, C.c_int]
+    lib.ora_jvp.restype = C.c_int
     lib.ora_locate.argtypes = [vp, _dp, _dp]
     lib.ora_locate.restype = C.c_int64
     _LIB = lib
@@ -232,3 +235,23 @@ def _vjp_method(self, tet, lam, vel, *, q, m, w, step0, nsteps, dt, omega, e_env
 
 
 OracleMesh.vjp = _vjp_method
+
+
+def _jvp_method(self, tet, lam, vel, *, q, m, step0, nsteps, dt, omega, e_env, b_env, de, e_dc=None, b_dc=None,
+                nthreads=1):
+    """Tangent-linear derivative of nsteps steps from (tet, lam, vel) along the
+    complex edge-envelope direction de: returns (status, dv[N,3], dx[N,3]), the
+    derivatives of the final velocities and Cartesian positions."""
+    n = tet.shape[0]
+    dv = np.zeros((n, 3))
+    dx = np.zeros((n, 3))
+    ee, bb, dd = _cplx(e_env), _cplx(b_env), _cplx(de)
+    ed = None if e_dc is None else _f64(e_dc)
+    bd = None if b_dc is None else _f64(b_dc)
+    rc = _load().ora_jvp(self.h, n, _p(np.ascontiguousarray(tet, dtype=np.int32), _ip), _p(_f64(lam)),
+                         _p(_f64(vel)), float(q), float(m), int(step0), int(nsteps), float(dt), float(omega),
+                         _p(ee), _p(ed), _p(bb), _p(bd), _p(dd), _p(dv), _p(dx), int(nthreads))
+    return rc, dv, dx
+
+
+OracleMesh.jvp = _jvp_method

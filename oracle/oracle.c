@@ -668,3 +668,172 @@ int ora_vjp(const ora_mesh *m, int64_t n, const int32_t *tet0, const double *lam
     free(priv);
     return status;
 }
+
+/* ------------------------------------------------------------------------
+ * Tangent-linear (forward-mode) derivative of nsteps particle steps along one
+ * direction de of the complex edge envelope: the same steps as step_one, in
+ * dual numbers (value, derivative).  It is a second, independent derivative
+ * of the differentiation workload's map, against which the reverse mode
+ * (ora_vjp) and the GPU adjoint are checked: dL = sum_p m w v_p . dv_p must
+ * equal Re(grad) . Re(de) + Im(grad) . Im(de).  Decisions (exit face, wall)
+ * are taken on the values, so the tet sequence and the reflections are those
+ * of the forward run, as in the reverse mode.  Mesh geometry, the face
+ * envelope and the dc DoFs are constants.
+ */
+typedef struct { double v, d; } dual;
+
+static dual dmk(double v, double d) { dual r = {v, d}; return r; }
+static dual dadd(dual a, dual b) { return dmk(a.v + b.v, a.d + b.d); }
+static dual dsub(dual a, dual b) { return dmk(a.v - b.v, a.d - b.d); }
+static dual dmul(dual a, dual b) { return dmk(a.v * b.v, a.d * b.v + a.v * b.d); }
+static dual dscale(dual a, double s) { return dmk(a.v * s, a.d * s); }
+static dual ddiv(dual a, dual b) { return dmk(a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v)); }
+static dual ddot3(const dual *a, const double *b) {
+    return dmk(a[0].v * b[0] + a[1].v * b[1] + a[2].v * b[2], a[0].d * b[0] + a[1].d * b[1] + a[2].d * b[2]);
+}
+static void dcross3(const dual *a, const dual *b, dual *c) {
+    c[0] = dsub(dmul(a[1], b[2]), dmul(a[2], b[1]));
+    c[1] = dsub(dmul(a[2], b[0]), dmul(a[0], b[2]));
+    c[2] = dsub(dmul(a[0], b[1]), dmul(a[1], b[0]));
+}
+
+/* fields at a dual barycentric point; the edge DoFs' derivative is the
+ * direction de through the same carrier factor */
+static void fields_at_dual(const ora_mesh *m, int64_t T, const dual lam[4], double c, double s,
+                           const ora_fields_t *F, const double *de, dual E[3], dual B[3]) {
+    double g[4][3];
+    ora_grad(m, T, g);
+    for (int k = 0; k < 3; ++k) { E[k] = dmk(0.0, 0.0); B[k] = dmk(0.0, 0.0); }
+    for (int e = 0; e < 6; ++e) {
+        int i = LE[e][0], j = LE[e][1];
+        int64_t id = m->tet_edge[6 * T + e];
+        double coef = F->e_env[2 * id] * c - F->e_env[2 * id + 1] * s + (F->e_dc ? F->e_dc[id] : 0.0);
+        double dcoef = de[2 * id] * c - de[2 * id + 1] * s;
+        dual cf = dmk(coef, dcoef);
+        for (int k = 0; k < 3; ++k) {
+            dual w = dsub(dscale(lam[i], g[j][k]), dscale(lam[j], g[i][k]));   /* W1_ij = l_i gl_j - l_j gl_i */
+            E[k] = dadd(E[k], dmul(cf, w));
+        }
+    }
+    for (int f = 0; f < 4; ++f) {
+        int i = LF[f][0], j = LF[f][1], kk = LF[f][2];
+        int64_t id = m->tet_face[4 * T + f];
+        double beta = F->b_env[2 * id] * c - F->b_env[2 * id + 1] * s + (F->b_dc ? F->b_dc[id] : 0.0);
+        double jk[3], ki[3], ij[3];
+        cross3(g[j], g[kk], jk); cross3(g[kk], g[i], ki); cross3(g[i], g[j], ij);
+        for (int k = 0; k < 3; ++k) {
+            dual w = dadd(dadd(dscale(lam[i], jk[k]), dscale(lam[j], ki[k])), dscale(lam[kk], ij[k]));
+            B[k] = dadd(B[k], dscale(w, 2.0 * beta));
+        }
+    }
+}
+
+static void boris_dual(dual v[3], const dual E[3], const dual B[3], double h) {
+    dual vm[3], tau[3], sig[3], cr[3], vpr[3];
+    for (int k = 0; k < 3; ++k) { vm[k] = dadd(v[k], dscale(E[k], h)); tau[k] = dscale(B[k], h); }
+    dual t2 = dadd(dadd(dmul(tau[0], tau[0]), dmul(tau[1], tau[1])), dmul(tau[2], tau[2]));
+    dual den = dadd(dmk(1.0, 0.0), t2);
+    for (int k = 0; k < 3; ++k) sig[k] = ddiv(dscale(tau[k], 2.0), den);
+    dcross3(vm, tau, cr);
+    for (int k = 0; k < 3; ++k) vpr[k] = dadd(vm[k], cr[k]);
+    dcross3(vpr, sig, cr);
+    for (int k = 0; k < 3; ++k) v[k] = dadd(dadd(vm[k], cr[k]), dscale(E[k], h));
+}
+
+/* one step of one particle in dual numbers (no deposit); returns the new tet
+ * or -1 at the hop cap */
+static int64_t step_one_dual(const ora_mesh *m, int64_t T, dual l[4], dual v[3], double c, double s,
+                             const ora_fields_t *F, const double *de, double h, double dt) {
+    dual E[3], B[3];
+    fields_at_dual(m, T, l, c, s, F, de, E, B);
+    boris_dual(v, E, B, h);
+    dual d[3] = {dscale(v[0], dt), dscale(v[1], dt), dscale(v[2], dt)};
+    for (int hops = 0; hops <= ORA_HOP_CAP; ++hops) {
+        double g[4][3];
+        ora_grad(m, T, g);
+        dual dl[4];
+        for (int k = 0; k < 4; ++k) dl[k] = ddot3(d, g[k]);
+        double smin = 1.0;
+        int kmin = -1;
+        for (int k = 0; k < 4; ++k) {
+            if (dl[k].v < 0.0 && l[k].v + dl[k].v < 0.0) {
+                double sk = l[k].v > 0.0 ? l[k].v / (-dl[k].v) : 0.0;
+                if (kmin < 0 || sk < smin) { smin = sk; kmin = k; }
+            }
+        }
+        if (kmin < 0) {
+            for (int k = 0; k < 4; ++k) l[k] = dadd(l[k], dl[k]);
+            return T;
+        }
+        /* the crossing parameter as a dual: s = l_k / (-dl_k) (0 when l_k <= 0) */
+        dual sd = l[kmin].v > 0.0 ? ddiv(l[kmin], dscale(dl[kmin], -1.0)) : dmk(0.0, 0.0);
+        dual lc[4], sum = dmk(0.0, 0.0);
+        for (int k = 0; k < 4; ++k) {
+            if (k == kmin) { lc[k] = dmk(0.0, 0.0); continue; }
+            lc[k] = dadd(l[k], dmul(sd, dl[k]));
+            if (lc[k].v < 0.0) lc[k] = dmk(0.0, 0.0);
+            sum = dadd(sum, lc[k]);
+        }
+        for (int k = 0; k < 4; ++k) if (k != kmin) lc[k] = ddiv(lc[k], sum);
+        dual one_minus_s = dsub(dmk(1.0, 0.0), sd);
+        for (int k = 0; k < 3; ++k) d[k] = dmul(d[k], one_minus_s);
+        int64_t nb = m->nbr[4 * T + kmin];
+        if (nb < 0) {
+            double nn = sqrt(dot3(g[kmin], g[kmin]));
+            double nh[3] = {g[kmin][0] / nn, g[kmin][1] / nn, g[kmin][2] / nn};
+            dual dd = ddot3(d, nh), vv = ddot3(v, nh);
+            for (int k = 0; k < 3; ++k) {
+                d[k] = dsub(d[k], dscale(dd, 2.0 * nh[k]));
+                v[k] = dsub(v[k], dscale(vv, 2.0 * nh[k]));
+            }
+            for (int k = 0; k < 4; ++k) l[k] = lc[k];
+        } else {
+            const int32_t *vt = m->tv + 4 * T, *vn = m->tv + 4 * nb;
+            for (int j = 0; j < 4; ++j) {
+                l[j] = dmk(0.0, 0.0);
+                for (int i = 0; i < 4; ++i) if (vt[i] == vn[j]) l[j] = lc[i];
+            }
+            T = nb;
+        }
+    }
+    return -1;
+}
+
+/* dv_out[3n] (and dx_out[3n] if not NULL): derivatives of the final velocity
+ * and Cartesian position along de[2*ne] (re, im per edge).  Returns 0, or -6
+ * if a particle reached the hop cap. */
+int ora_jvp(const ora_mesh *m, int64_t n, const int32_t *tet0, const double *lam0, const double *vel0, double q,
+            double mass, int64_t step0, int nsteps, double dt, double omega, const double *e_env,
+            const double *e_dc, const double *b_env, const double *b_dc, const double *de, double *dv_out,
+            double *dx_out, int nthreads) {
+    ora_fields_t F = {e_env, e_dc, b_env, b_dc};
+    double h = 0.5 * (q / mass) * dt;
+    int status = 0;
+    int nth = nthreads > 1 ? nthreads : 1;
+#ifndef _OPENMP
+    nth = 1;
+#endif
+    #pragma omp parallel for num_threads(nth) schedule(static) reduction(min:status)
+    for (int64_t p = 0; p < n; ++p) {
+        int64_t T = tet0[p];
+        dual l[4], v[3];
+        l[1] = dmk(lam0[3 * p], 0.0); l[2] = dmk(lam0[3 * p + 1], 0.0); l[3] = dmk(lam0[3 * p + 2], 0.0);
+        l[0] = dmk(1.0 - l[1].v - l[2].v - l[3].v, 0.0);
+        for (int k = 0; k < 3; ++k) v[k] = dmk(vel0[3 * p + k], 0.0);
+        for (int k = 0; k < nsteps && T >= 0; ++k) {
+            double t = (double)(step0 + k) * dt;
+            T = step_one_dual(m, T, l, v, cos(omega * t), sin(omega * t), &F, de, h, dt);
+        }
+        if (T < 0) { status = -6; T = tet0[p]; }
+        for (int k = 0; k < 3; ++k) dv_out[3 * p + k] = v[k].d;
+        if (dx_out) {
+            const int32_t *vt = m->tv + 4 * T;
+            for (int c = 0; c < 3; ++c) {
+                double acc = 0.0;
+                for (int k = 0; k < 4; ++k) acc += l[k].d * m->xyz[3 * vt[k] + c];
+                dx_out[3 * p + c] = acc;
+            }
+        }
+    }
+    return status;
+}

@@ -130,6 +130,24 @@ def test_autograd_differentiation_workload(E, torch_cuda, ora):
     assert rc == 0
     print(f"[adjoint 20^3 x 6, 2e6] vs oracle: max rel {rel(g, go):.2e}")
     assert rel(g, go) < 1e-10
+    # the oracle's tangent-linear (forward mode) along a dense random direction
+    # and single-edge directions: dKE = Re(g).Re(de) + Im(g).Im(de)
+    rng_d = np.random.default_rng(2023)
+    dirs = [rng_d.standard_normal(ctx.n_edge) + 1j * rng_d.standard_normal(ctx.n_edge)]
+    for e, unit in zip(rng_d.choice(ctx.n_edge, 4, replace=False), (1.0, 1j, 1.0, 1j)):
+        d1 = np.zeros(ctx.n_edge, complex)
+        d1[e] = unit
+        dirs.append(d1)
+    for de in dirs:
+        rc, dv, _ = M.jvp(w.tet, w.lam, w.vel, q=w.q, m=w.m, step0=0, nsteps=K, dt=w.dt, omega=w.omega,
+                          e_env=w.e_env, b_env=w.b_env, b_dc=w.b_dc, de=de, nthreads=NTH)
+        assert rc == 0
+        fwd = float((w.m * w.w * vfin * dv).sum())
+        mine = float((g.real * de.real).sum() + (g.imag * de.imag).sum())
+        scale = float((np.abs(g) * np.abs(de)).sum())
+        print(f"[adjoint 20^3 x 6, 2e6] tangent-linear check: forward {fwd:.6e} adjoint {mine:.6e} "
+              f"rel {abs(fwd - mine) / scale:.2e}")
+        assert abs(fwd - mine) <= 1e-10 * scale
     # central differences of the GPU forward run
     rng = np.random.default_rng(2022)
     probes = rng.choice(ctx.n_edge, 50, replace=False)

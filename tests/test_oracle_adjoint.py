@@ -93,3 +93,47 @@ def test_adjoint_against_central_differences(ora, omega_scale):
             g = grad[e].real if part == "re" else grad[e].imag
             scale = np.abs(grad).max()
             assert abs(fd - g) <= 1e-6 * scale + 1e-6 * abs(g), (e, part, fd, g)
+
+
+@pytest.mark.parametrize("case", ["small", "crossing_heavy"])
+def test_reverse_mode_matches_tangent_linear(ora, case):
+    """The reverse mode against an independent forward mode (dual numbers
+    through the same steps): for directions de of the complex edge envelope,
+    sum_p m w v_p . dv_p equals Re(grad) . Re(de) + Im(grad) . Im(de), and the
+    position adjoint pairs with the tangent of the final positions.  The
+    crossing-heavy case takes steps of 0.1-0.5 cell with wall reflections."""
+    w = synth.make_workload(1, n_particles=600)
+    vel, dt, K = w.vel, w.dt, 12
+    if case == "crossing_heavy":
+        vel, dt = w.vel * 40.0, 1e-8
+    M = ora.OracleMesh(w.xyz, w.tet_vert)
+    t, l, v = w.tet.copy(), w.lam.copy(), vel.copy()
+    hops_seen = 0
+    for s in range(K):
+        rc, hops = M.step(t, l, v, q=w.q, m=w.m, w=w.w, step=s, dt=dt, omega=w.omega, e_env=w.e_env,
+                          b_env=w.b_env, b_dc=w.b_dc, dG=np.zeros(M.ne), want_hops=True)
+        assert rc == 0
+        hops_seen += int(np.sum(hops))
+    if case == "crossing_heavy":
+        assert hops_seen > 600
+    rng = np.random.default_rng(77)
+    xbar = rng.standard_normal(v.shape)
+    # two losses: the kinetic energy (velocity adjoint m w v) and a linear
+    # functional of the final positions (position adjoint xbar)
+    rc, g_ke, _, _ = M.vjp(w.tet, w.lam, vel, q=w.q, m=w.m, w=w.w, step0=0, nsteps=K, dt=dt, omega=w.omega,
+                           e_env=w.e_env, b_env=w.b_env, b_dc=w.b_dc, vbar=w.m * w.w * v)
+    assert rc == 0
+    rc, g_x, _, _ = M.vjp(w.tet, w.lam, vel, q=w.q, m=w.m, w=w.w, step0=0, nsteps=K, dt=dt, omega=w.omega,
+                          e_env=w.e_env, b_env=w.b_env, b_dc=w.b_dc, vbar=np.zeros_like(v), xbar=xbar)
+    assert rc == 0
+    dense = rng.standard_normal(M.ne) + 1j * rng.standard_normal(M.ne)
+    single = [np.where(np.arange(M.ne) == e, 1.0 + 0.0j, 0.0) for e in rng.choice(M.ne, 3, replace=False)]
+    single += [np.where(np.arange(M.ne) == e, 0.0 + 1.0j, 0.0) for e in rng.choice(M.ne, 3, replace=False)]
+    for de in [dense] + single:
+        rc, dv, dx = M.jvp(w.tet, w.lam, vel, q=w.q, m=w.m, step0=0, nsteps=K, dt=dt, omega=w.omega,
+                           e_env=w.e_env, b_env=w.b_env, b_dc=w.b_dc, de=de)
+        assert rc == 0
+        for grad, fwd in ((g_ke, float((w.m * w.w * v * dv).sum())), (g_x, float((xbar * dx).sum()))):
+            rev = float((grad.real * de.real).sum() + (grad.imag * de.imag).sum())
+            scale = float((np.abs(grad) * np.abs(de)).sum()) + 1e-300
+            assert abs(fwd - rev) <= 1e-12 * scale, (case, fwd, rev)

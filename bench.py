@@ -169,6 +169,36 @@ def field_update_timing(E, torch, ctx, w, reps=20):
             "note": "side path, not in value; one Newmark step from a random interior state, tol 1e-10"}
 
 
+def coarse_step_timing(E, torch, synth, ctx, w, fine=10, reps=5):
+    """Multi-rate form: one coarse field step of `fine` fine steps with the
+    envelope reconstructed from three snapshots (quadratic in time) at every
+    fine step; float64, particles sorted, same workload as the metric."""
+    snaps = [E.Fields.from_numpy(e, b, None, w.b_dc) for e, b in synth.envelope_snapshots(w, seed=2)]
+    sp = E.Species(w.q, w.m, w.w)
+    parts = E.Particles.from_numpy(w.tet, w.lam, w.vel, w.ids)
+    spare = parts.empty_like()
+    ctx.sort(parts, spare)
+    parts = spare
+    dG = torch.zeros(ctx.n_edge, dtype=torch.float64, device="cuda")
+    dtc = fine * w.dt
+    ctx.coarse_step(parts, sp, snaps, dtc, dtc, fine, w.omega, dG)
+    torch.cuda.synchronize()
+    ctx.kernel_time(reset=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for r in range(reps):
+        ctx.coarse_step(parts, sp, snaps, (2 + r) * dtc, dtc, fine, w.omega, dG,
+                        flags=E.STEP_XCD_REMAP | E.STEP_TIMING)
+    e1.record()
+    torch.cuda.synchronize()
+    kt, launches = ctx.kernel_time(reset=True)
+    ctx.check()
+    ms = e0.elapsed_time(e1) / (reps * fine)
+    return {"fine_steps_per_coarse": fine, "ms_per_fine_step": ms, "value": parts.n / (ms * 1e-3),
+            "coef_ms": kt["coef"] / max(launches, 1), "push_ms": kt["push"] / max(launches, 1),
+            "note": "float64, three envelope snapshots interpolated at every fine step; no sort inside"}
+
+
 def adjoint_timing(E, torch, synth):
     """Differentiation workload: 20^3 x 6 tets, 2e6 electrons, 20 float64 steps
     with a checkpoint every 5, then the reverse sweep (gradient of the final
@@ -344,6 +374,8 @@ def main():
     if not args.no_side and args.workload == "40cube":
         line["field_update"] = field_update_timing(E, torch, ctx, w)
         log(f"[bench] field update: {json.dumps(line['field_update'])}")
+        line["coarse_step"] = coarse_step_timing(E, torch, synth, ctx, w)
+        log(f"[bench] coarse step: {json.dumps(line['coarse_step'])}")
         line["adjoint"] = adjoint_timing(E, torch, synth)
         log(f"[bench] adjoint: {json.dumps(line['adjoint'])}")
     if not args.no_cpu_baseline:

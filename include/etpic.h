@@ -197,6 +197,26 @@ int etpic_gather_push_deposit(etpic_ctx *ctx, const etpic_particles *p, int prec
                               const etpic_fields *f, int64_t step, double dt, double omega, double *dG,
                               double *rho, uint32_t flags, void *stream);
 
+/* One coarse field step of the particles at the fine step (Particle Push
+ * section: fields known at the coarse step dt_coarse are reconstructed at the
+ * fine step with the quadratic Lagrange basis N_{n,k} of eqs. newmark_L /
+ * newmark_N, the trajectories advanced at the fine step and the path integral
+ * summed over the fine steps, eq. G_integral and the sum after it).
+ * snap[0], snap[1], snap[2]: the field DoFs (same layout as
+ * etpic_gather_push_deposit) at t_coarse - dt_coarse, t_coarse and
+ * t_coarse + dt_coarse; the dc DoFs are taken from snap[1].  The particles
+ * advance from t_coarse to t_coarse + dt_coarse in fine_steps steps of
+ * dt = dt_coarse / fine_steps; fine step j gathers at t_j = t_coarse + j dt
+ * with the envelope sum_k N_{n,k}(t_j) snap[k] modulated by e^{j w t_j}
+ * (carrier at the fine time), then pushes, walks and deposits exactly as
+ * etpic_gather_push_deposit.  dG accumulates the deposit of all fine steps;
+ * rho, if not NULL, receives q w lam_k at the end of the last fine step.
+ * flags as for etpic_gather_push_deposit.  Asynchronous on `stream`.
+ * Errors: EINVAL, ESTATE, EHIP; in-kernel errors via etpic_check. */
+int etpic_coarse_step(etpic_ctx *ctx, const etpic_particles *p, int precision, const etpic_species *sp,
+                      const etpic_fields snap[3], double t_coarse, double dt_coarse, int fine_steps, double omega,
+                      double *dG, double *rho, uint32_t flags, void *stream);
+
 /* Counting sort of the particles by tet (histogram, exclusive scan, scatter):
  * src -> dst (distinct buffers, same n and precision); the order among
  * particles of one tet is unspecified.  Asynchronous on `stream`. */

@@ -43,6 +43,9 @@ def _load():
     lib.ora_step.argtypes = [vp, C.c_int64, _ip, _dp, _dp, C.c_double, C.c_double, C.c_double, C.c_int64,
                              C.c_double, C.c_double, _dp, _dp, _dp, _dp, _dp, _dp, _ip, C.c_int]
     lib.ora_step.restype = C.c_int
+    lib.ora_step_t.argtypes = [vp, C.c_int64, _ip, _dp, _dp, C.c_double, C.c_double, C.c_double, C.c_double,
+                               C.c_double, C.c_double, _dp, _dp, _dp, _dp, _dp, _dp, _ip, C.c_int]
+    lib.ora_step_t.restype = C.c_int
     lib.ora_step_one.argtypes = [vp, _ip, _dp, _dp, C.c_double, C.c_double, C.c_double, C.c_int64, C.c_double,
                                  C.c_double, _dp, _dp, _dp, _dp, _dp, _lp, _ip]
     lib.ora_step_one.restype = C.c_int
@@ -177,6 +180,50 @@ class OracleMesh:
                               float(dt), float(omega), _p(ee), _p(ed), _p(bb), _p(bd), _p(dG), _p(rho),
                               _p(hops, _ip), int(nthreads))
         return rc, hops
+
+    def step_at(self, tet, lam, vel, *, q, m, w, t, dt, omega, e_env, b_env, e_dc=None, b_dc=None, dG=None,
+                rho=None, nthreads=1):
+        """One step gathering at time t (instead of step*dt), in place."""
+        assert tet.dtype == np.int32 and tet.flags.c_contiguous
+        assert lam.dtype == np.float64 and lam.flags.c_contiguous
+        assert vel.dtype == np.float64 and vel.flags.c_contiguous
+        ee, bb = _cplx(e_env), _cplx(b_env)
+        ed = None if e_dc is None else _f64(e_dc)
+        bd = None if b_dc is None else _f64(b_dc)
+        return _load().ora_step_t(self.h, tet.shape[0], _p(tet, _ip), _p(lam), _p(vel), float(q), float(m),
+                                  float(w), float(t), float(dt), float(omega), _p(ee), _p(ed), _p(bb), _p(bd),
+                                  _p(dG), _p(rho), None, int(nthreads))
+
+    def coarse_step(self, tet, lam, vel, *, q, m, w, e_snaps, b_snaps, t_coarse, dt_coarse, fine_steps, omega,
+                    e_dc=None, b_dc=None, dG=None, rho=None, nthreads=1):
+        """One coarse field step at the fine step (Particle Push section): the
+        envelope known at t_coarse - dt_coarse, t_coarse, t_coarse + dt_coarse
+        (e_snaps, b_snaps: three complex arrays each) is reconstructed at each
+        fine time t_j = t_coarse + j dt with the quadratic Lagrange basis
+        (eqs. newmark_L / newmark_N), N_k(t) = prod_{i != k} (t - tau_i) /
+        (tau_k - tau_i) over the node times tau; the carrier multiplies the
+        reconstructed envelope at t_j.  fine_steps Lorentz steps of
+        dt = dt_coarse / fine_steps; dG sums the path integrals of all fine steps
+        (eq. G_integral); rho gets the charge of the final positions."""
+        tau = [t_coarse - dt_coarse, t_coarse, t_coarse + dt_coarse]
+        dt = dt_coarse / fine_steps
+        for j in range(fine_steps):
+            t = t_coarse + j * dt
+            N = []
+            for k in range(3):
+                val = 1.0
+                for i in range(3):
+                    if i != k:
+                        val *= (t - tau[i]) / (tau[k] - tau[i])
+                N.append(val)
+            e_t = N[0] * np.asarray(e_snaps[0]) + N[1] * np.asarray(e_snaps[1]) + N[2] * np.asarray(e_snaps[2])
+            b_t = N[0] * np.asarray(b_snaps[0]) + N[1] * np.asarray(b_snaps[1]) + N[2] * np.asarray(b_snaps[2])
+            rc = self.step_at(tet, lam, vel, q=q, m=m, w=w, t=t, dt=dt, omega=omega, e_env=e_t, b_env=b_t,
+                              e_dc=e_dc, b_dc=b_dc, dG=dG, rho=rho if j == fine_steps - 1 else None,
+                              nthreads=nthreads)
+            if rc != 0:
+                return rc
+        return 0
 
     def step_one(self, tet, lam3, v, *, q, m, w, step, dt, omega, e_env, b_env, e_dc=None, b_dc=None, dG=None):
         """Single particle; returns (status, tet, lam3, v, piece_tets)."""

@@ -398,12 +398,26 @@ static void step_one(const ora_mesh *m, ora_particle *P, double c, double s, con
  * q*w*lambda_k at the end point.  hops[n] optional.  nthreads <= 1: serial.
  * Returns 0, or -6 if any particle exceeded the hop cap.
  */
+int ora_step_t(const ora_mesh *m, int64_t n, int32_t *tet, double *lam, double *vel,
+               double q, double mass, double w, double t, double dt, double omega,
+               const double *e_env, const double *e_dc, const double *b_env, const double *b_dc,
+               double *dG, double *rho, int32_t *hops, int nthreads);
+
 int ora_step(const ora_mesh *m, int64_t n, int32_t *tet, double *lam, double *vel,
              double q, double mass, double w, int64_t step, double dt, double omega,
              const double *e_env, const double *e_dc, const double *b_env, const double *b_dc,
              double *dG, double *rho, int32_t *hops, int nthreads) {
+    return ora_step_t(m, n, tet, lam, vel, q, mass, w, (double)step * dt, dt, omega, e_env, e_dc, b_env, b_dc,
+                      dG, rho, hops, nthreads);
+}
+
+/* The same step with the gather time t given directly (the fine steps of a
+ * coarse field step). */
+int ora_step_t(const ora_mesh *m, int64_t n, int32_t *tet, double *lam, double *vel,
+               double q, double mass, double w, double t, double dt, double omega,
+               const double *e_env, const double *e_dc, const double *b_env, const double *b_dc,
+               double *dG, double *rho, int32_t *hops, int nthreads) {
     ora_fields_t F = {e_env, e_dc, b_env, b_dc};
-    double t = (double)step * dt;
     double c = cos(omega * t), s = sin(omega * t);
     double qm = q / mass, qw = q * w;
     int status = 0;

@@ -114,25 +114,39 @@ __device__ __forceinline__ double run_total(double x, const WaveRuns &r) {
 //     the cyclic order of f's ascending triple starting at k).
 // eps, beta: the real parts Re{dof e^{jwt}} + dc of the edge and face DoFs at this
 // step.  Two threads per tet: one for A_0..3, one for C_0..3.
+//
+// With kSnap = 3 the envelope itself is interpolated in time between three
+// snapshots at the coarse field times t_{n-1}, t_n, t_{n+1} (the quadratic
+// Lagrange basis N_{n,k}, eqs. newmark_L / newmark_N, used for the particle
+// fields in the Particle Push section): dof(t) = sum_k w_k dof_k with the
+// weights w_k = N_{n,k}(t) of the fine step's time, then modulated as above.
 struct FieldPtrs {
-    const double2 *e_env;
+    const double2 *e_env[3];
     const double *e_dc;
-    const double2 *b_env;
+    const double2 *b_env[3];
     const double *b_dc;
-    double c, s;   // cos(w t_n), sin(w t_n)
+    double w[3];   // snapshot weights (kSnap = 3)
+    double c, s;   // cos(w t), sin(w t) of the fine step's time
 };
+
+template <int kSnap>
+__device__ __forceinline__ double2 envelope(const double2 *const env[3], const double w[3], int64_t id) {
+    if (kSnap == 1) return env[0][id];
+    const double2 a = env[0][id], b = env[1][id], c = env[2][id];
+    return make_double2(w[0] * a.x + w[1] * b.x + w[2] * c.x, w[0] * a.y + w[1] * b.y + w[2] * c.y);
+}
 
 // local edge index of the vertex pair {i, j}, i < j
 __host__ __device__ constexpr int local_edge(int i, int j) { return i == 0 ? j - 1 : (i == 1 ? j + 1 : 5); }
 
-template <int K>
+template <int K, int kSnap>
 __device__ __forceinline__ void coef_A(const int32_t *tp, const double g[4][3], const FieldPtrs &F, double A[3]) {
     A[0] = A[1] = A[2] = 0.0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         if (j == K) continue;
         const int id = tp[local_edge(j < K ? j : K, j < K ? K : j)];
-        const double2 z = F.e_env[id];
+        const double2 z = envelope<kSnap>(F.e_env, F.w, id);
         double eps = z.x * F.c - z.y * F.s;
         if (F.e_dc) eps += F.e_dc[id];
         if (j < K) eps = -eps;
@@ -141,7 +155,7 @@ __device__ __forceinline__ void coef_A(const int32_t *tp, const double g[4][3], 
     }
 }
 
-template <int K>
+template <int K, int kSnap>
 __device__ __forceinline__ void coef_C(const int32_t *tp, const double g[4][3], const FieldPtrs &F, double Cv[3]) {
     Cv[0] = Cv[1] = Cv[2] = 0.0;
     constexpr int lf[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
@@ -151,7 +165,7 @@ __device__ __forceinline__ void coef_C(const int32_t *tp, const double g[4][3], 
         const int a = lf[f][0] == K ? lf[f][1] : (lf[f][1] == K ? lf[f][2] : lf[f][0]);
         const int b = lf[f][0] == K ? lf[f][2] : (lf[f][1] == K ? lf[f][0] : lf[f][1]);
         const int id = tp[6 + f];
-        const double2 z = F.b_env[id];
+        const double2 z = envelope<kSnap>(F.b_env, F.w, id);
         double beta = z.x * F.c - z.y * F.s;
         if (F.b_dc) beta += F.b_dc[id];
         beta *= 2.0;
@@ -161,7 +175,7 @@ __device__ __forceinline__ void coef_C(const int32_t *tp, const double g[4][3], 
     }
 }
 
-template <typename Real>
+template <typename Real, int kSnap = 1>
 __global__ void __launch_bounds__(kBlock) k_tet_coef(int64_t nt, const TetTopo *__restrict__ topo,
                                                      const double *__restrict__ grad, FieldPtrs F,
                                                      Real *__restrict__ coef) {
@@ -177,15 +191,15 @@ __global__ void __launch_bounds__(kBlock) k_tet_coef(int64_t nt, const TetTopo *
     const int32_t *tp = reinterpret_cast<const int32_t *>(topo + T);
     double o[12];
     if (part == 0) {
-        coef_A<0>(tp, g, F, o);
-        coef_A<1>(tp, g, F, o + 3);
-        coef_A<2>(tp, g, F, o + 6);
-        coef_A<3>(tp, g, F, o + 9);
+        coef_A<0, kSnap>(tp, g, F, o);
+        coef_A<1, kSnap>(tp, g, F, o + 3);
+        coef_A<2, kSnap>(tp, g, F, o + 6);
+        coef_A<3, kSnap>(tp, g, F, o + 9);
     } else {
-        coef_C<0>(tp, g, F, o);
-        coef_C<1>(tp, g, F, o + 3);
-        coef_C<2>(tp, g, F, o + 6);
-        coef_C<3>(tp, g, F, o + 9);
+        coef_C<0, kSnap>(tp, g, F, o);
+        coef_C<1, kSnap>(tp, g, F, o + 3);
+        coef_C<2, kSnap>(tp, g, F, o + 6);
+        coef_C<3, kSnap>(tp, g, F, o + 9);
     }
     Real *dst = coef + T * 24 + 12 * part;   // A_k at 3k, C_k at 12 + 3k
 #pragma unroll
@@ -1467,6 +1481,25 @@ struct FieldState {
     }
 };
 
+// Device pointers of one (snap[1] NULL) or three envelope snapshots; the dc
+// DoFs are those of snap[0] (one snapshot) or snap[1] (three).
+FieldPtrs field_ptrs(const etpic_fields *const snap[3], const double w[3], double c, double s) {
+    FieldPtrs F{};
+    const bool three = snap[1] != nullptr;
+    for (int k = 0; k < 3; ++k) {
+        const etpic_fields *f = three ? snap[k] : snap[0];
+        F.e_env[k] = reinterpret_cast<const double2 *>(f->e_env);
+        F.b_env[k] = reinterpret_cast<const double2 *>(f->b_env);
+        F.w[k] = w[k];
+    }
+    const etpic_fields *dc = three ? snap[1] : snap[0];
+    F.e_dc = dc->e_dc;
+    F.b_dc = dc->b_dc;
+    F.c = c;
+    F.s = s;
+    return F;
+}
+
 struct etpic_ctx {
     int device = 0;
     etpic::HostMesh host;
@@ -1546,14 +1579,24 @@ struct etpic_ctx {
         return a;
     }
 
-    // One step: carrier phase in float64 on the host (t_n = step*dt, argument
+    // One step: carrier phase in float64 on the host (t = step*dt, argument
     // reduced by libm), per-tet coefficients, particle kernel, walk kernel.
     template <typename Real>
     int step(const etpic_particles *p, const etpic_species *sp, const etpic_fields *f, int64_t step, double dt,
              double omega, double *dG, double *rho, uint32_t flags, void *stream) {
+        const etpic_fields *snap[3] = {f, nullptr, nullptr};
+        const double w[3] = {1.0, 0.0, 0.0};
+        return step_at<Real>(p, sp, snap, w, (double)step * dt, dt, omega, dG, rho, flags, stream);
+    }
+
+    // One step at time t with the envelope sum_k w[k] snap[k] (one snapshot
+    // when snap[1] is NULL).
+    template <typename Real>
+    int step_at(const etpic_particles *p, const etpic_species *sp, const etpic_fields *const snap[3],
+                const double w[3], double t, double dt, double omega, double *dG, double *rho, uint32_t flags,
+                void *stream) {
         hipStream_t st = static_cast<hipStream_t>(stream);
         const int64_t nt = host.nt;
-        const double t = (double)step * dt;
         const double c = std::cos(omega * t), s = std::sin(omega * t);
         StepArgs<Real> a = step_args<Real>(p, sp, dt, dG, rho);
         a.walk_by_slice = (flags & ETPIC_STEP_WALK_BY_SLICE) ? 1 : 0;
@@ -1562,9 +1605,13 @@ struct etpic_ctx {
             if (int r = timing_events(&ev)) return r;
             HIP_TRY(hipEventRecord(ev[0], st));
         }
-        const FieldPtrs F{reinterpret_cast<const double2 *>(f->e_env), f->e_dc,
-                          reinterpret_cast<const double2 *>(f->b_env), f->b_dc, c, s};
-        k_tet_coef<Real><<<grid_for(2 * nt), kBlock, 0, st>>>(nt, d_topo, d_grad64, F, static_cast<Real *>(d_coef));
+        const FieldPtrs F = field_ptrs(snap, w, c, s);
+        if (snap[1])
+            k_tet_coef<Real, 3><<<grid_for(2 * nt), kBlock, 0, st>>>(nt, d_topo, d_grad64, F,
+                                                                    static_cast<Real *>(d_coef));
+        else
+            k_tet_coef<Real, 1><<<grid_for(2 * nt), kBlock, 0, st>>>(nt, d_topo, d_grad64, F,
+                                                                    static_cast<Real *>(d_coef));
         HIP_TRY(hipGetLastError());
         if (ev) HIP_TRY(hipEventRecord(ev[1], st));
         const int remap = (flags & ETPIC_STEP_XCD_REMAP) ? 1 : 0;
@@ -1887,6 +1934,37 @@ int etpic_gather_push_deposit(etpic_ctx *ctx, const etpic_particles *p, int prec
     return ctx->step<float>(p, sp, f, step, dt, omega, dG, rho, flags, stream);
 }
 
+int etpic_coarse_step(etpic_ctx *ctx, const etpic_particles *p, int precision, const etpic_species *sp,
+                      const etpic_fields snap[3], double t_coarse, double dt_coarse, int fine_steps, double omega,
+                      double *dG, double *rho, uint32_t flags, void *stream) {
+    if (!snap) return fail(ETPIC_EINVAL, "null snapshot array");
+    for (int k = 0; k < 3; ++k)
+        if (int r = check_step_args(ctx, sp, &snap[k], dt_coarse, omega)) return r;
+    if (!dG) return fail(ETPIC_EINVAL, "null current accumulator");
+    if (fine_steps < 1 || !(dt_coarse > 0.0) || !std::isfinite(t_coarse))
+        return fail(ETPIC_EINVAL, "need fine_steps >= 1, dt_coarse > 0 and a finite t_coarse");
+    if (int r = check_particles(ctx, p)) return r;
+    if (precision != ETPIC_FP64 && precision != ETPIC_MIXED) return fail(ETPIC_EINVAL, "bad precision %d", precision);
+    if (p->n == 0) return ETPIC_OK;
+    if (int r = set_device(ctx)) return r;
+    const etpic_fields *sp3[3] = {&snap[0], &snap[1], &snap[2]};
+    const double dt = dt_coarse / fine_steps;
+    for (int j = 0; j < fine_steps; ++j) {
+        // fine step j gathers at t = t_n + j dt; with u = j / M in [0, 1) the
+        // quadratic Lagrange weights on the nodes u = -1, 0, 1 are
+        // u(u - 1)/2, 1 - u^2, u(u + 1)/2
+        const double u = (double)j / fine_steps;
+        const double w[3] = {0.5 * u * (u - 1.0), 1.0 - u * u, 0.5 * u * (u + 1.0)};
+        const double t = t_coarse + j * dt;
+        double *rho_j = (j == fine_steps - 1) ? rho : nullptr;
+        const int r = precision == ETPIC_FP64
+                          ? ctx->step_at<double>(p, sp, sp3, w, t, dt, omega, dG, rho_j, flags, stream)
+                          : ctx->step_at<float>(p, sp, sp3, w, t, dt, omega, dG, rho_j, flags, stream);
+        if (r) return r;
+    }
+    return ETPIC_OK;
+}
+
 int etpic_adjoint_workspace(const etpic_ctx *ctx, int64_t n, int nsteps, int checkpoint_every, size_t *bytes_out) {
     if (!ctx || !bytes_out) return fail(ETPIC_EINVAL, "null argument");
     if (!ctx->has_mesh) return fail(ETPIC_ESTATE, "no mesh uploaded");
@@ -1952,10 +2030,11 @@ int etpic_backward(etpic_ctx *ctx, int64_t n, const etpic_species *sp, const etp
             const etpic_particles cur = state_view(workspace, L.slots_off + (size_t)(k - k0) * L.state, L, n);
             const double t = (double)(step0 + k) * dt;
             const double c = std::cos(omega * t), s = std::sin(omega * t);
-            const FieldPtrs F{reinterpret_cast<const double2 *>(f->e_env), f->e_dc,
-                              reinterpret_cast<const double2 *>(f->b_env), f->b_dc, c, s};
-            k_tet_coef<double><<<grid_for(2 * nt), kBlock, 0, st>>>(nt, ctx->d_topo, ctx->d_grad64, F,
-                                                                    static_cast<double *>(ctx->d_coef));
+            const etpic_fields *snap[3] = {f, nullptr, nullptr};
+            const double w1[3] = {1.0, 0.0, 0.0};
+            const FieldPtrs F = field_ptrs(snap, w1, c, s);
+            k_tet_coef<double, 1><<<grid_for(2 * nt), kBlock, 0, st>>>(nt, ctx->d_topo, ctx->d_grad64, F,
+                                                                       static_cast<double *>(ctx->d_coef));
             HIP_TRY(hipGetLastError());
             StepArgs<double> a = ctx->step_args<double>(&cur, sp, dt, scratch_dG, nullptr);
             AdjArgs b{};

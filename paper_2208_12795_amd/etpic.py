@@ -31,7 +31,7 @@ EXPORTS = (
     "etpic_vertex_charge", "etpic_gauss_residual", "etpic_kernel_time", "etpic_check",
     "etpic_adjoint_workspace", "etpic_forward_checkpointed", "etpic_backward",
     "etpic_field_setup", "etpic_field_nnz", "etpic_field_spmv", "etpic_field_step",
-    "etpic_particles_locate", "etpic_particles_positions",
+    "etpic_particles_locate", "etpic_particles_positions", "etpic_coarse_step",
 )
 
 
@@ -91,6 +91,8 @@ def lib():
     L.etpic_check.argtypes = [vp, vp, C.POINTER(C.c_uint32)]
     L.etpic_particles_locate.argtypes = [vp, C.POINTER(_Particles), C.c_void_p * 3, vp, vp]
     L.etpic_particles_positions.argtypes = [vp, C.POINTER(_Particles), C.c_void_p * 3, vp]
+    L.etpic_coarse_step.argtypes = [vp, C.POINTER(_Particles), C.c_int, C.POINTER(_Species), _Fields * 3,
+                                    C.c_double, C.c_double, C.c_int, C.c_double, vp, vp, C.c_uint32, vp]
     L.etpic_field_setup.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_double]
     L.etpic_field_nnz.argtypes = [vp, i64p]
     L.etpic_field_spmv.argtypes = [vp, vp, vp, C.c_double, C.c_double, C.c_double, vp]
@@ -295,6 +297,19 @@ class Context:
         _chk(lib().etpic_gather_push_deposit(self._h, C.byref(d), parts.precision, C.byref(sp), C.byref(fd),
                                              int(step), float(dt), float(omega), _dptr(dG), _dptr(rho),
                                              int(flags), _stream(stream)))
+
+    def coarse_step(self, parts, species, snaps, t_coarse, dt_coarse, fine_steps, omega, dG, rho=None,
+                    flags=STEP_XCD_REMAP, stream=None):
+        """fine_steps steps from t_coarse to t_coarse + dt_coarse with the envelope
+        interpolated between the three Fields snapshots (t_coarse - dt_coarse,
+        t_coarse, t_coarse + dt_coarse)."""
+        assert len(snaps) == 3
+        d = parts.desc()
+        sp = species.c()
+        arr = (_Fields * 3)(*[f.desc() for f in snaps])
+        _chk(lib().etpic_coarse_step(self._h, C.byref(d), parts.precision, C.byref(sp), arr, float(t_coarse),
+                                     float(dt_coarse), int(fine_steps), float(omega), _dptr(dG), _dptr(rho),
+                                     int(flags), _stream(stream)))
 
     def sort(self, src, dst, stream=None):
         a, b = src.desc(), dst.desc()

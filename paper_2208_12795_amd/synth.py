@@ -325,6 +325,21 @@ def make_workload(k, n_particles=None, n_cells=None, omega=None, b0=None, amp=No
                     omega=w, dt=c["dt"], steps=c["steps"], sort_every=c["sort_every"])
 
 
+def envelope_snapshots(w, seed=1, count=3, drift=0.3):
+    """`count` envelope snapshots (edge, face) for coarse field times: the
+    workload's edge envelope plus `drift` times independent 8-mode envelopes of
+    the same amplitude (seeded), each with its Faraday-consistent face envelope."""
+    rng = np.random.default_rng(np.random.SeedSequence([SEED_BASE, 77, seed]))
+    amp = np.abs(w.e_env).max()
+    edges, faces = w.edges, w.faces
+    out = []
+    for _ in range(count):
+        extra = mode_edge_dofs(w.xyz, edges, 1.0, w.extent, rng)
+        e = w.e_env + drift * amp * extra / np.abs(extra).max()
+        out.append((e, faraday_face_envelope(e, edges, faces, w.n_vert, w.omega)))
+    return out
+
+
 def as_interleaved(z):
     """complex128[N] -> float64[N,2] (re, im) contiguous, the device layout."""
     return np.ascontiguousarray(np.stack([z.real, z.imag], axis=1))

@@ -317,6 +317,74 @@ def full_size_step(E, torch, ora, w, precision, tol, sort_first=True):
     ctx.close()
 
 
+def test_full_size_200_steps_checkpoints_and_drift(E, torch_cuda, ora):
+    """The benchmark's run: 1e7 electrons on the 40^3 x 6 mesh, 200 float64 steps
+    with the sort every 10 steps and the XCD remap.  At steps 0, 10, 100 and
+    199 the GPU state is handed to the oracle for one step and compared with
+    the GPU's next state; the continuity residual is checked at those steps.
+    A sample of 20,000 particles (by id) is also run by the oracle for all 200
+    steps from the initial state; the drift of the GPU trajectories from it is
+    reported (not gated beyond a loose bound: rounding differences grow along
+    chaotic orbits)."""
+    torch = torch_cuda
+    w = synth.make_workload(2)
+    ctx = E.Context(0)
+    ctx.upload_mesh(w.xyz, w.tet_vert)
+    parts = E.Particles.from_numpy(w.tet, w.lam, w.vel, w.ids)
+    spare = parts.empty_like()
+    fields = E.Fields.from_numpy(w.e_env, w.b_env, None, w.b_dc)
+    sp = E.Species(w.q, w.m, w.w)
+    M = ora.OracleMesh(w.xyz, w.tet_vert)
+    dG = torch.zeros(ctx.n_edge, dtype=torch.float64, device="cuda")
+    rho0 = torch.zeros(ctx.n_vert, dtype=torch.float64, device="cuda")
+    rho1 = torch.zeros_like(rho0)
+    checks = {0, 10, 100, 199}
+    for s in range(200):
+        if s % 10 == 0:
+            ctx.sort(parts, spare)
+            parts, spare = spare, parts
+        if s in checks:
+            tin, lin, vin, _ = parts.to_numpy()
+            dG.zero_()
+            rho0.zero_()
+            rho1.zero_()
+            ctx.vertex_charge(parts, sp, rho0)
+        ctx.gather_push_deposit(parts, sp, fields, s, w.dt, w.omega, dG)
+        if s in checks:
+            ctx.vertex_charge(parts, sp, rho1)
+            r, p = ctx.gauss_residual(dG, rho1, rho0)
+            rc, o, dGo = oracle_step(M, (tin, lin, vin), w, s, nthreads=NTH)
+            assert rc == 0
+            tg, lg, vg, _ = parts.to_numpy()
+            err = step_errors(w.xyz, w.tet_vert, (tin, lin, vin), (tg, lg, vg), o, dG.cpu().numpy(), dGo)
+            print(f"[200 steps] step {s}: {err} gauss {r / p:.2e}", flush=True)
+            assert r / p <= 1e-12
+            assert err["tet_mismatch"] <= 2 + 1e-5 * len(tg), err
+            assert_within(err, 1e-12, f"step {s}")
+    ctx.check()
+    # trajectory drift of a sample, by particle id
+    rng = np.random.default_rng(12)
+    sample = np.sort(rng.choice(len(w.ids), 20_000, replace=False))
+    t, l, v = w.tet[sample].copy(), w.lam[sample].copy(), w.vel[sample].copy()
+    for s in range(200):
+        rc, _ = M.step(t, l, v, q=w.q, m=w.m, w=w.w, step=s, dt=w.dt, omega=w.omega, e_env=w.e_env,
+                       b_env=w.b_env, b_dc=w.b_dc, dG=np.zeros(M.ne), nthreads=NTH)
+        assert rc == 0
+    tg, lg, vg, ig = parts.to_numpy()
+    pos = np.empty_like(ig)
+    pos[ig] = np.arange(len(ig))
+    k = pos[sample]
+    xg = M.positions(tg[k], lg[k])
+    xo = M.positions(t, l)
+    x0 = M.positions(w.tet[sample], w.lam[sample])
+    drift_x = np.abs(xg - xo).max() / np.abs(xo - x0).max()
+    drift_v = np.abs(vg[k] - v).max() / np.abs(v).max()
+    print(f"[200 steps] drift of 20,000 trajectories after 200 steps: position {drift_x:.2e} of the path "
+          f"length scale, velocity {drift_v:.2e}", flush=True)
+    assert drift_x < 1e-6 and drift_v < 1e-6
+    ctx.close()
+
+
 def test_full_size_fp64_40cube(E, torch_cuda, ora):
     """The benchmark workload at its real size: 40^3 x 6 tets, 1e7 electrons,
     float64, launch configuration of the benchmark (sorted, XCD remap)."""

@@ -197,6 +197,17 @@ int etpic_gather_push_deposit(etpic_ctx *ctx, const etpic_particles *p, int prec
                               const etpic_fields *f, int64_t step, double dt, double omega, double *dG,
                               double *rho, uint32_t flags, void *stream);
 
+/* nsteps consecutive steps (times (step0 + j) dt, j = 0..nsteps-1) with the same
+ * field DoFs: the same result as nsteps calls of etpic_gather_push_deposit,
+ * with rho (if not NULL) deposited after the last step only.  Between two
+ * steps the walk of one and the coefficient pass of the next run in one
+ * kernel launch.  With ETPIC_STEP_TIMING, etpic_kernel_time books that shared
+ * launch as walk time (the coefficient time of all but the first step is 0).
+ * Asynchronous on `stream`.  Errors as etpic_gather_push_deposit. */
+int etpic_run_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, const etpic_species *sp,
+                    const etpic_fields *f, int64_t step0, int nsteps, double dt, double omega, double *dG,
+                    double *rho, uint32_t flags, void *stream);
+
 /* One coarse field step of the particles at the fine step (Particle Push
  * section: fields known at the coarse step dt_coarse are reconstructed at the
  * fine step with the quadratic Lagrange basis N_{n,k} of eqs. newmark_L /
@@ -211,7 +222,8 @@ int etpic_gather_push_deposit(etpic_ctx *ctx, const etpic_particles *p, int prec
  * (carrier at the fine time), then pushes, walks and deposits exactly as
  * etpic_gather_push_deposit.  dG accumulates the deposit of all fine steps;
  * rho, if not NULL, receives q w lam_k at the end of the last fine step.
- * flags as for etpic_gather_push_deposit.  Asynchronous on `stream`.
+ * flags as for etpic_gather_push_deposit; consecutive fine steps share
+ * launches as in etpic_run_steps.  Asynchronous on `stream`.
  * Errors: EINVAL, ESTATE, EHIP; in-kernel errors via etpic_check. */
 int etpic_coarse_step(etpic_ctx *ctx, const etpic_particles *p, int precision, const etpic_species *sp,
                       const etpic_fields snap[3], double t_coarse, double dt_coarse, int fine_steps, double omega,

@@ -175,11 +175,11 @@ __device__ __forceinline__ void coef_C(const int32_t *tp, const double g[4][3], 
     }
 }
 
-template <typename Real, int kSnap = 1>
-__global__ void __launch_bounds__(kBlock) k_tet_coef(int64_t nt, const TetTopo *__restrict__ topo,
-                                                     const double *__restrict__ grad, FieldPtrs F,
-                                                     Real *__restrict__ coef) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+template <typename Real, int kSnap>
+__device__ __forceinline__ void tet_coef(int64_t nt, const TetTopo *__restrict__ topo,
+                                         const double *__restrict__ grad, const FieldPtrs &F,
+                                         Real *__restrict__ coef, unsigned blk) {
+    const int64_t t = (int64_t)blk * kBlock + threadIdx.x;
     const int64_t T = t >> 1;
     const int part = (int)(t & 1);   // 0: A_0..3 (edges), 1: C_0..3 (faces)
     if (T >= nt) return;
@@ -204,6 +204,13 @@ __global__ void __launch_bounds__(kBlock) k_tet_coef(int64_t nt, const TetTopo *
     Real *dst = coef + T * 24 + 12 * part;   // A_k at 3k, C_k at 12 + 3k
 #pragma unroll
     for (int d = 0; d < 12; ++d) dst[d] = (Real)o[d];
+}
+
+template <typename Real, int kSnap = 1>
+__global__ void __launch_bounds__(kBlock) k_tet_coef(int64_t nt, const TetTopo *__restrict__ topo,
+                                                     const double *__restrict__ grad, FieldPtrs F,
+                                                     Real *__restrict__ coef) {
+    tet_coef<Real, kSnap>(nt, topo, grad, F, coef, blockIdx.x);
 }
 
 // ------------------------------------------------------------------ particle step
@@ -637,27 +644,47 @@ __device__ __forceinline__ void walk_particle(const StepArgs<Real> &a, int64_t p
 // overflow slices, one wavefront per slice.  The last block to finish resets
 // the counters for the next step.
 template <typename Real>
-__global__ void __launch_bounds__(kBlock) k_walk(StepArgs<Real> a) {
+__device__ __forceinline__ void walk_queued(const StepArgs<Real> &a, unsigned blk, unsigned nblk) {
     const unsigned count = min(__atomic_load_n(&a.walk_ctr[0], __ATOMIC_RELAXED), kWalkQueueCap);
-    for (unsigned i = blockIdx.x * kBlock + threadIdx.x; i < count; i += gridDim.x * kBlock) {
+    for (unsigned i = blk * kBlock + threadIdx.x; i < count; i += nblk * kBlock) {
         const unsigned q = a.walk_queue[i];
         if (q != kQueueSkip && (int64_t)q < a.n) walk_particle(a, (int64_t)q);
     }
     const unsigned slices = __atomic_load_n(&a.walk_ctr[2], __ATOMIC_RELAXED);
     const unsigned wpb = kBlock / 64;
-    for (unsigned i = blockIdx.x * wpb + (threadIdx.x >> 6); i < slices; i += gridDim.x * wpb) {
+    for (unsigned i = blk * wpb + (threadIdx.x >> 6); i < slices; i += nblk * wpb) {
         const int64_t p = (int64_t)a.slice_queue[i] * 64 + (threadIdx.x & 63);
         if (p < a.n) walk_particle(a, p);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
-        if (atomicAdd(&a.walk_ctr[1], 1u) == gridDim.x - 1) {
+        if (atomicAdd(&a.walk_ctr[1], 1u) == nblk - 1) {
             a.walk_ctr[0] = 0u;
             a.walk_ctr[1] = 0u;
             a.walk_ctr[2] = 0u;
         }
     }
+}
+
+template <typename Real>
+__global__ void __launch_bounds__(kBlock) k_walk(StepArgs<Real> a) {
+    walk_queued(a, blockIdx.x, gridDim.x);
+}
+
+// The walk of one step and the coefficient pass of the next in one launch:
+// blocks [0, kWalkBlocks) walk, the others build the next step's table.  The
+// walk does not read the table and the table pass reads nothing the walk
+// writes, so the two halves are independent; one launch saves the kernel
+// boundary between them and lets the short, latency-bound walk hide behind
+// the table pass.  (Used inside multi-step calls, where the next step's
+// fields are known.)
+template <typename Real, int kSnap>
+__global__ void __launch_bounds__(kBlock) k_walk_coef(StepArgs<Real> a, int64_t nt, FieldPtrs F) {
+    if (blockIdx.x < kWalkBlocks)
+        walk_queued(a, blockIdx.x, kWalkBlocks);
+    else
+        tet_coef<Real, kSnap>(nt, a.topo, a.grad, F, const_cast<Real *>(a.coef), blockIdx.x - kWalkBlocks);
 }
 
 // ------------------------------------------------------------------ adjoint step
@@ -1500,6 +1527,14 @@ FieldPtrs field_ptrs(const etpic_fields *const snap[3], const double w[3], doubl
     return F;
 }
 
+// One step of a multi-step call: the envelope snapshots (snap[1] NULL for
+// one snapshot), their weights and the gather time.
+struct StepPlan {
+    const etpic_fields *snap[3];
+    double w[3];
+    double t;
+};
+
 struct etpic_ctx {
     int device = 0;
     etpic::HostMesh host;
@@ -1535,12 +1570,12 @@ struct etpic_ctx {
     // HIP events bracketing the kernels of steps run with ETPIC_STEP_TIMING:
     // 4 events per step (before the coefficient kernel, before and after the
     // particle kernel, after the walk kernel)
-    std::vector<std::array<hipEvent_t, 4>> timing;
-    std::vector<std::array<hipEvent_t, 4>> spare;
+    std::vector<std::array<hipEvent_t, 5>> timing;
+    std::vector<std::array<hipEvent_t, 5>> spare;
 
     int timing_events(hipEvent_t **ev) {
         if (spare.empty()) {
-            std::array<hipEvent_t, 4> e{};
+            std::array<hipEvent_t, 5> e{};
             for (auto &x : e) HIP_TRY(hipEventCreate(&x));
             spare.push_back(e);
         }
@@ -1584,51 +1619,78 @@ struct etpic_ctx {
     template <typename Real>
     int step(const etpic_particles *p, const etpic_species *sp, const etpic_fields *f, int64_t step, double dt,
              double omega, double *dG, double *rho, uint32_t flags, void *stream) {
-        const etpic_fields *snap[3] = {f, nullptr, nullptr};
-        const double w[3] = {1.0, 0.0, 0.0};
-        return step_at<Real>(p, sp, snap, w, (double)step * dt, dt, omega, dG, rho, flags, stream);
+        StepPlan plan{{f, nullptr, nullptr}, {1.0, 0.0, 0.0}, (double)step * dt};
+        return run_steps<Real>(p, sp, &plan, 1, dt, omega, dG, rho, flags, stream);
     }
 
-    // One step at time t with the envelope sum_k w[k] snap[k] (one snapshot
-    // when snap[1] is NULL).
     template <typename Real>
-    int step_at(const etpic_particles *p, const etpic_species *sp, const etpic_fields *const snap[3],
-                const double w[3], double t, double dt, double omega, double *dG, double *rho, uint32_t flags,
-                void *stream) {
-        hipStream_t st = static_cast<hipStream_t>(stream);
+    int launch_coef(const StepPlan &plan, double omega, hipStream_t s) {
         const int64_t nt = host.nt;
-        const double c = std::cos(omega * t), s = std::sin(omega * t);
-        StepArgs<Real> a = step_args<Real>(p, sp, dt, dG, rho);
-        a.walk_by_slice = (flags & ETPIC_STEP_WALK_BY_SLICE) ? 1 : 0;
+        const FieldPtrs F = field_ptrs(plan.snap, plan.w, std::cos(omega * plan.t), std::sin(omega * plan.t));
+        if (plan.snap[1])
+            k_tet_coef<Real, 3><<<grid_for(2 * nt), kBlock, 0, s>>>(nt, d_topo, d_grad64, F,
+                                                                   static_cast<Real *>(d_coef));
+        else
+            k_tet_coef<Real, 1><<<grid_for(2 * nt), kBlock, 0, s>>>(nt, d_topo, d_grad64, F,
+                                                                   static_cast<Real *>(d_coef));
+        HIP_TRY(hipGetLastError());
+        return ETPIC_OK;
+    }
+
+    // nsteps consecutive steps, step j at time plans[j].t with the envelope
+    // sum_k w[k] snap[k] of plans[j]; rho (if any) after the last step.  Each
+    // step is coefficient pass, particle kernel, walk kernel on the caller's
+    // stream; between two steps of the call the walk and the next step's
+    // coefficient pass share one launch (k_walk_coef).
+    template <typename Real>
+    int run_steps(const etpic_particles *p, const etpic_species *sp, const StepPlan *plans, int nsteps, double dt,
+                  double omega, double *dG, double *rho, uint32_t flags, void *stream) {
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        const int remap = (flags & ETPIC_STEP_XCD_REMAP) ? 1 : 0;
+        const int64_t n = p->n, nt = host.nt;
+        const unsigned coef_blocks = grid_for(2 * nt);
         hipEvent_t *ev = nullptr;
         if (flags & ETPIC_STEP_TIMING) {
             if (int r = timing_events(&ev)) return r;
             HIP_TRY(hipEventRecord(ev[0], st));
         }
-        const FieldPtrs F = field_ptrs(snap, w, c, s);
-        if (snap[1])
-            k_tet_coef<Real, 3><<<grid_for(2 * nt), kBlock, 0, st>>>(nt, d_topo, d_grad64, F,
-                                                                    static_cast<Real *>(d_coef));
-        else
-            k_tet_coef<Real, 1><<<grid_for(2 * nt), kBlock, 0, st>>>(nt, d_topo, d_grad64, F,
-                                                                    static_cast<Real *>(d_coef));
-        HIP_TRY(hipGetLastError());
+        if (int r = launch_coef<Real>(plans[0], omega, st)) return r;
         if (ev) HIP_TRY(hipEventRecord(ev[1], st));
-        const int remap = (flags & ETPIC_STEP_XCD_REMAP) ? 1 : 0;
-        const int64_t n = p->n;
-        switch (push_slices_for(flags, n)) {
-        case 16: k_push_slices<Real, 16><<<grid_for((n + 15) / 16), kBlock, 0, st>>>(a, remap); break;
-        case 4: k_push_slices<Real, 4><<<grid_for((n + 3) / 4), kBlock, 0, st>>>(a, remap); break;
-        default: k_push<Real><<<grid_for(n), kBlock, 0, st>>>(a, remap); break;
+        for (int j = 0; j < nsteps; ++j) {
+            StepArgs<Real> a = step_args<Real>(p, sp, dt, dG, j == nsteps - 1 ? rho : nullptr);
+            a.walk_by_slice = (flags & ETPIC_STEP_WALK_BY_SLICE) ? 1 : 0;
+            if (ev) HIP_TRY(hipEventRecord(ev[2], st));
+            switch (push_slices_for(flags, n)) {
+            case 16: k_push_slices<Real, 16><<<grid_for((n + 15) / 16), kBlock, 0, st>>>(a, remap); break;
+            case 4: k_push_slices<Real, 4><<<grid_for((n + 3) / 4), kBlock, 0, st>>>(a, remap); break;
+            default: k_push<Real><<<grid_for(n), kBlock, 0, st>>>(a, remap); break;
+            }
+            HIP_TRY(hipGetLastError());
+            if (ev) HIP_TRY(hipEventRecord(ev[3], st));
+            if (j + 1 < nsteps) {
+                const StepPlan &nx = plans[j + 1];
+                const FieldPtrs F = field_ptrs(nx.snap, nx.w, std::cos(omega * nx.t), std::sin(omega * nx.t));
+                if (nx.snap[1])
+                    k_walk_coef<Real, 3><<<kWalkBlocks + coef_blocks, kBlock, 0, st>>>(a, nt, F);
+                else
+                    k_walk_coef<Real, 1><<<kWalkBlocks + coef_blocks, kBlock, 0, st>>>(a, nt, F);
+            } else {
+                k_walk<Real><<<kWalkBlocks, kBlock, 0, st>>>(a);
+            }
+            HIP_TRY(hipGetLastError());
+            if (ev) {
+                HIP_TRY(hipEventRecord(ev[4], st));
+                // the next step's coefficient pass ran inside this launch: it
+                // gets an empty interval, and the shared launch is booked as walk
+                if (j + 1 < nsteps) {
+                    if (int r = timing_events(&ev)) return r;
+                    HIP_TRY(hipEventRecord(ev[0], st));
+                    HIP_TRY(hipEventRecord(ev[1], st));
+                }
+            }
         }
-        HIP_TRY(hipGetLastError());
-        if (ev) HIP_TRY(hipEventRecord(ev[2], st));
-        k_walk<Real><<<kWalkBlocks, kBlock, 0, st>>>(a);
-        HIP_TRY(hipGetLastError());
-        if (ev) HIP_TRY(hipEventRecord(ev[3], st));
         return ETPIC_OK;
     }
-
 
     template <typename Real>
     const Real *gpush_table() const;
@@ -1947,22 +2009,37 @@ int etpic_coarse_step(etpic_ctx *ctx, const etpic_particles *p, int precision, c
     if (precision != ETPIC_FP64 && precision != ETPIC_MIXED) return fail(ETPIC_EINVAL, "bad precision %d", precision);
     if (p->n == 0) return ETPIC_OK;
     if (int r = set_device(ctx)) return r;
-    const etpic_fields *sp3[3] = {&snap[0], &snap[1], &snap[2]};
     const double dt = dt_coarse / fine_steps;
+    std::vector<StepPlan> plans((size_t)fine_steps);
     for (int j = 0; j < fine_steps; ++j) {
         // fine step j gathers at t = t_n + j dt; with u = j / M in [0, 1) the
         // quadratic Lagrange weights on the nodes u = -1, 0, 1 are
         // u(u - 1)/2, 1 - u^2, u(u + 1)/2
         const double u = (double)j / fine_steps;
-        const double w[3] = {0.5 * u * (u - 1.0), 1.0 - u * u, 0.5 * u * (u + 1.0)};
-        const double t = t_coarse + j * dt;
-        double *rho_j = (j == fine_steps - 1) ? rho : nullptr;
-        const int r = precision == ETPIC_FP64
-                          ? ctx->step_at<double>(p, sp, sp3, w, t, dt, omega, dG, rho_j, flags, stream)
-                          : ctx->step_at<float>(p, sp, sp3, w, t, dt, omega, dG, rho_j, flags, stream);
-        if (r) return r;
+        plans[j] = StepPlan{{&snap[0], &snap[1], &snap[2]},
+                            {0.5 * u * (u - 1.0), 1.0 - u * u, 0.5 * u * (u + 1.0)},
+                            t_coarse + j * dt};
     }
-    return ETPIC_OK;
+    if (precision == ETPIC_FP64)
+        return ctx->run_steps<double>(p, sp, plans.data(), fine_steps, dt, omega, dG, rho, flags, stream);
+    return ctx->run_steps<float>(p, sp, plans.data(), fine_steps, dt, omega, dG, rho, flags, stream);
+}
+
+int etpic_run_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, const etpic_species *sp,
+                    const etpic_fields *f, int64_t step0, int nsteps, double dt, double omega, double *dG,
+                    double *rho, uint32_t flags, void *stream) {
+    if (int r = check_step_args(ctx, sp, f, dt, omega)) return r;
+    if (!dG) return fail(ETPIC_EINVAL, "null current accumulator");
+    if (nsteps < 0) return fail(ETPIC_EINVAL, "negative step count");
+    if (int r = check_particles(ctx, p)) return r;
+    if (precision != ETPIC_FP64 && precision != ETPIC_MIXED) return fail(ETPIC_EINVAL, "bad precision %d", precision);
+    if (p->n == 0 || nsteps == 0) return ETPIC_OK;
+    if (int r = set_device(ctx)) return r;
+    std::vector<StepPlan> plans((size_t)nsteps);
+    for (int j = 0; j < nsteps; ++j) plans[j] = StepPlan{{f, nullptr, nullptr}, {1.0, 0.0, 0.0}, (double)(step0 + j) * dt};
+    if (precision == ETPIC_FP64)
+        return ctx->run_steps<double>(p, sp, plans.data(), nsteps, dt, omega, dG, rho, flags, stream);
+    return ctx->run_steps<float>(p, sp, plans.data(), nsteps, dt, omega, dG, rho, flags, stream);
 }
 
 int etpic_adjoint_workspace(const etpic_ctx *ctx, int64_t n, int nsteps, int checkpoint_every, size_t *bytes_out) {
@@ -2310,11 +2387,11 @@ int etpic_kernel_time(etpic_ctx *ctx, double ms_out[3], int64_t *launches_out, i
     if (int r = set_device(ctx)) return r;
     double tot[3] = {0.0, 0.0, 0.0};
     for (auto &e : ctx->timing) {
-        HIP_TRY(hipEventSynchronize(e[3]));
+        HIP_TRY(hipEventSynchronize(e[4]));
         float m[3] = {0.f, 0.f, 0.f};
-        HIP_TRY(hipEventElapsedTime(&m[0], e[1], e[2]));   // particle kernel
+        HIP_TRY(hipEventElapsedTime(&m[0], e[2], e[3]));   // particle kernel
         HIP_TRY(hipEventElapsedTime(&m[1], e[0], e[1]));   // coefficient kernel
-        HIP_TRY(hipEventElapsedTime(&m[2], e[2], e[3]));   // walk kernel
+        HIP_TRY(hipEventElapsedTime(&m[2], e[3], e[4]));   // walk kernel
         for (int k = 0; k < 3; ++k) tot[k] += m[k];
     }
     for (int k = 0; k < 3; ++k) ms_out[k] = tot[k];

@@ -31,7 +31,7 @@ EXPORTS = (
     "etpic_vertex_charge", "etpic_gauss_residual", "etpic_kernel_time", "etpic_check",
     "etpic_adjoint_workspace", "etpic_forward_checkpointed", "etpic_backward",
     "etpic_field_setup", "etpic_field_nnz", "etpic_field_spmv", "etpic_field_step",
-    "etpic_particles_locate", "etpic_particles_positions", "etpic_coarse_step",
+    "etpic_particles_locate", "etpic_particles_positions", "etpic_coarse_step", "etpic_run_steps",
 )
 
 
@@ -91,6 +91,8 @@ def lib():
     L.etpic_check.argtypes = [vp, vp, C.POINTER(C.c_uint32)]
     L.etpic_particles_locate.argtypes = [vp, C.POINTER(_Particles), C.c_void_p * 3, vp, vp]
     L.etpic_particles_positions.argtypes = [vp, C.POINTER(_Particles), C.c_void_p * 3, vp]
+    L.etpic_run_steps.argtypes = [vp, C.POINTER(_Particles), C.c_int, C.POINTER(_Species), C.POINTER(_Fields),
+                                  C.c_int64, C.c_int, C.c_double, C.c_double, vp, vp, C.c_uint32, vp]
     L.etpic_coarse_step.argtypes = [vp, C.POINTER(_Particles), C.c_int, C.POINTER(_Species), _Fields * 3,
                                     C.c_double, C.c_double, C.c_int, C.c_double, vp, vp, C.c_uint32, vp]
     L.etpic_field_setup.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_double]
@@ -297,6 +299,16 @@ class Context:
         _chk(lib().etpic_gather_push_deposit(self._h, C.byref(d), parts.precision, C.byref(sp), C.byref(fd),
                                              int(step), float(dt), float(omega), _dptr(dG), _dptr(rho),
                                              int(flags), _stream(stream)))
+
+    def run_steps(self, parts, species, fields, step0, nsteps, dt, omega, dG, rho=None, flags=STEP_XCD_REMAP,
+                  stream=None):
+        """nsteps steps from step0 with fixed fields (rho after the last step)."""
+        d = parts.desc()
+        sp = species.c()
+        fd = fields.desc()
+        _chk(lib().etpic_run_steps(self._h, C.byref(d), parts.precision, C.byref(sp), C.byref(fd), int(step0),
+                                   int(nsteps), float(dt), float(omega), _dptr(dG), _dptr(rho), int(flags),
+                                   _stream(stream)))
 
     def coarse_step(self, parts, species, snaps, t_coarse, dt_coarse, fine_steps, omega, dG, rho=None,
                     flags=STEP_XCD_REMAP, stream=None):

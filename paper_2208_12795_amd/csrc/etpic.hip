@@ -5,15 +5,23 @@
 //                 lam the barycentrics, E(x) = sum_i lam_i A_i and
 //                 B(x) = sum_i lam_i C_i inside a tet (both expansions are affine
 //                 in lam), where A_i, C_i fold the real parts Re{dof e^{jwt}} + dc
-//                 of the 6 edge and 4 face DoFs into the gradients.
-//   k_push        per particle, tet-sorted: gather from the coefficient row,
+//                 of the 6 edge and 4 face DoFs into the gradients; the envelope
+//                 may be interpolated in time between three snapshots.
+//   k_push, k_push_slices
+//                 per particle, tet-sorted: gather from the coefficient row,
 //                 Boris push, in-tet path-integral deposit reduced over runs
 //                 of equal tet in each wavefront, float64 atomics; particles
-//                 leaving their tet are queued.
+//                 leaving their tet are queued.  The sliced form gives each
+//                 wavefront several consecutive 64-particle slices.
 //   k_walk        the queued particles: barycentric walk, reflection, deposit.
-//   k_hist/k_scan*/k_scatter   counting sort by tet.
+//   k_walk_coef   the walk of a step and the next step's coefficients in one
+//                 launch (multi-step calls).
+//   k_hist/k_scan*/k_scatter/k_run_stat   counting sort by tet.
 //   k_charge      vertex charge of the particles.
 //   k_gauss       continuity residual D^T dG - (rho_new - rho_old).
+//   k_locate, k_positions   Cartesian points <-> (tet, barycentrics).
+//   k_adjoint     reverse of one float64 step (gradient w.r.t. the edge envelope).
+//   k_field_spmv, k_nm_*, k_cocg_*   implicit envelope field step.
 #include <hip/hip_runtime.h>
 
 #include <cmath>

@@ -168,14 +168,16 @@ def field_update_timing(E, torch, ctx, w, reps=20):
     v = torch.randn((ne, 2), dtype=torch.float64, device="cuda", generator=g) * 1e9
     a = torch.zeros((ne, 2), dtype=torch.float64, device="cuda")
     b = torch.zeros((nf, 2), dtype=torch.float64, device="cuda")
+    # one untimed step, then the timed one (from the state the first left)
+    ctx.field_step(w.dt, u, v, a, b, None, tol=1e-10, max_iter=1000, raise_on_error=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    rc, iters, res = ctx.field_step(w.dt, u, v, a, b, None, tol=1e-10, max_iter=1000, raise_on_error=False)
+    rc, iters, res = ctx.field_step(2 * w.dt, u, v, a, b, None, tol=1e-10, max_iter=1000, raise_on_error=False)
     torch.cuda.synchronize()
     step_ms = 1e3 * (time.perf_counter() - t0)
     return {"n_edges": ne, "nnz": nnz, "spmv_ms": spmv_ms, "spmv_GBs": spmv_bytes / (spmv_ms * 1e-3) / 1e9,
             "step_ms": step_ms, "cocg_iterations": iters, "rel_residual": res, "status": rc,
-            "note": "side path, not in value; one Newmark step from a random interior state, tol 1e-10"}
+            "note": "side path, not in value; the second Newmark step from a random interior state, tol 1e-10"}
 
 
 def coarse_step_timing(E, torch, synth, ctx, w, fine=10, reps=5):

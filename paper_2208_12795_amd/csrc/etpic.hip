@@ -1343,7 +1343,10 @@ __global__ void __launch_bounds__(kBlock) k_cocg_init(int64_t ne, const double2 
     block_sum4(v, partial);
 }
 
-// q = A p and partial p.q (unconjugated)
+// Device scalars of the iteration: sc[0..1] rho = r . z, sc[2..3] p . q,
+// sc[4..5] alpha, sc[6..7] beta, sc[8] |r|^2, sc[9] |b|^2 (complex as re, im).
+//
+// COCG iteration: q = A p with the partials of p . q
 __global__ void __launch_bounds__(kBlock) k_cocg_apply(FieldCsr S, double2 alpha, double beta,
                                                        const double2 *__restrict__ p, double2 *__restrict__ q,
                                                        double *__restrict__ partial) {
@@ -1363,31 +1366,7 @@ __global__ void __launch_bounds__(kBlock) k_cocg_apply(FieldCsr S, double2 alpha
     block_sum4(v, partial);
 }
 
-// Sums nb block partials (4 each) in a fixed order into out[0..3].
-__global__ void __launch_bounds__(kBlock) k_reduce4(int64_t nb, const double *__restrict__ partial,
-                                                    double *__restrict__ out) {
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t b = threadIdx.x; b < nb; b += blockDim.x)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) v[k] += partial[4 * b + k];
-    __shared__ double sh[kBlock / 64][4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) sh[wid][k] = v[k];
-    __syncthreads();
-    if (threadIdx.x < 4) {
-        double s = 0.0;
-        for (int w = 0; w < kBlock / 64; ++w) s += sh[w][threadIdx.x];
-        out[threadIdx.x] = s;
-    }
-}
-
-// scalars (device): sc[0..1] rho, sc[2..3] p.q, sc[4..5] alpha, sc[6..7] rho_new / beta, sc[8] |r|^2, sc[9] |b|^2
-// x += alpha p, r -= alpha q, z = Dinv r; partial: r.z (re, im), |r|^2
+// x += alpha p, r -= alpha q, z = Dinv r, with the partials of r . z and |r|^2
 __global__ void __launch_bounds__(kBlock) k_cocg_update(int64_t ne, const double *__restrict__ sc,
                                                         const double2 *__restrict__ dinv, const double2 *__restrict__ p,
                                                         const double2 *__restrict__ q, double2 *__restrict__ x,
@@ -1410,29 +1389,67 @@ __global__ void __launch_bounds__(kBlock) k_cocg_update(int64_t ne, const double
     block_sum4(v, partial);
 }
 
-// alpha = rho / (p.q) from the reduced p.q in red[0..1]
-__global__ void k_cocg_alpha(double *__restrict__ sc, const double *__restrict__ red) {
-    if (threadIdx.x == 0) {
-        const double2 pq = make_double2(red[0], red[1]);
+// One block: the block partials summed in a fixed order, then the scalar
+// update of the iteration on thread 0 (kind 0: alpha = rho / (p . q);
+// kind 1: beta = rho_new / rho, rho = rho_new, |r|^2).
+__global__ void __launch_bounds__(kBlock) k_cocg_scalars(int64_t nb, const double *__restrict__ partial,
+                                                         double *__restrict__ sc, int kind) {
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t b = threadIdx.x; b < nb; b += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] += partial[4 * b + k];
+    __shared__ double sh[kBlock / 64][4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) sh[threadIdx.x >> 6][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double tot[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int w = 0; w < kBlock / 64; ++w)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) tot[k] += sh[w][k];
+    if (kind == 0) {
+        const double2 pq = make_double2(tot[0], tot[1]);
         const double2 al = (pq.x == 0.0 && pq.y == 0.0) ? make_double2(0.0, 0.0) : cdiv(make_double2(sc[0], sc[1]), pq);
         sc[2] = pq.x;
         sc[3] = pq.y;
         sc[4] = al.x;
         sc[5] = al.y;
-    }
-}
-
-// beta = rho_new / rho, rho = rho_new, |r|^2 from red[0..2]
-__global__ void k_cocg_beta(double *__restrict__ sc, const double *__restrict__ red) {
-    if (threadIdx.x == 0) {
-        const double2 rn = make_double2(red[0], red[1]);
+    } else {
+        const double2 rn = make_double2(tot[0], tot[1]);
         const double2 ro = make_double2(sc[0], sc[1]);
         const double2 be = (ro.x == 0.0 && ro.y == 0.0) ? make_double2(0.0, 0.0) : cdiv(rn, ro);
         sc[0] = rn.x;
         sc[1] = rn.y;
         sc[6] = be.x;
         sc[7] = be.y;
-        sc[8] = red[2];
+        sc[8] = tot[2];
+    }
+}
+
+// Sums nb block partials (4 each) in a fixed order into out[0..3].
+__global__ void __launch_bounds__(kBlock) k_reduce4(int64_t nb, const double *__restrict__ partial,
+                                                    double *__restrict__ out) {
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t b = threadIdx.x; b < nb; b += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] += partial[4 * b + k];
+    __shared__ double sh[kBlock / 64][4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) sh[wid][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double s = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) s += sh[w][threadIdx.x];
+        out[threadIdx.x] = s;
     }
 }
 
@@ -2366,11 +2383,9 @@ int etpic_field_step(etpic_ctx *ctx, double t_next, double *u, double *v, double
     const int check = 5;
     while (rel > tol && it < max_iter) {
         k_cocg_apply<<<gr, kBlock, 0, st>>>(F.csr(), alpha, beta, p, q, F.partial);
-        k_reduce4<<<1, kBlock, 0, st>>>(gr, F.partial, F.red);
-        k_cocg_alpha<<<1, 64, 0, st>>>(F.sc, F.red);
+        k_cocg_scalars<<<1, kBlock, 0, st>>>(gr, F.partial, F.sc, 0);
         k_cocg_update<<<ge, kBlock, 0, st>>>(ne, F.sc, F.dinv, p, q, x, r, z, F.partial);
-        k_reduce4<<<1, kBlock, 0, st>>>(ge, F.partial, F.red);
-        k_cocg_beta<<<1, 64, 0, st>>>(F.sc, F.red);
+        k_cocg_scalars<<<1, kBlock, 0, st>>>(ge, F.partial, F.sc, 1);
         k_cocg_dir<<<ge, kBlock, 0, st>>>(ne, F.sc, z, p);
         HIP_TRY(hipGetLastError());
         ++it;

@@ -27,11 +27,14 @@
  *  - complex DoFs are interleaved (re, im) float64 pairs (complex128 layout);
  *  - the physical fields are Re{env * e^{j w t}} + dc with t = step*dt.
  *
- * Ownership: the library owns the mesh tables and a small scratch area, both
- * allocated once in etpic_mesh_upload and freed by etpic_destroy.  Particle
- * arrays, field DoFs and outputs are device buffers owned by the caller; they
- * must stay valid until the work queued on `stream` has finished.  No entry
- * point other than etpic_mesh_upload allocates device memory.
+ * Ownership: the library owns the context state (status word, walk queues,
+ * reduction words, allocated in etpic_create), the mesh tables, per-step
+ * coefficient table and sort counters (etpic_mesh_upload, replaced by the next
+ * upload) and the field-update matrices and work vectors (etpic_field_setup);
+ * etpic_destroy frees them all.  Particle arrays, field DoFs, outputs and the
+ * adjoint workspace are device buffers owned by the caller; they must stay
+ * valid until the work queued on `stream` has finished.  No other entry point
+ * allocates device memory (ETPIC_STEP_TIMING creates HIP events on first use).
  *
  * Errors: every entry point returns an etpic status (0 = OK).  On failure the
  * message is available from etpic_last_error() (thread-local).  Errors found

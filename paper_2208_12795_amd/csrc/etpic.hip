@@ -183,20 +183,49 @@ __device__ __forceinline__ void coef_C(const int32_t *tp, const double g[4][3], 
     }
 }
 
+// What the particle kernel reads per tet besides this step's coefficients: the
+// barycentric gradients grad l_1..3 (9 reals, in the kernel's precision) and the
+// six global edge ids, packed in one row so that a run's lanes touch one
+// contiguous record (float64: 9 doubles + 6 int32 = 96 B; float32: 9 floats,
+// one pad, 6 int32 = 64 B).
+template <typename Real>
+struct PushRow;
+template <>
+struct PushRow<double> {
+    static constexpr int kStride = 12;   // doubles per row
+    static constexpr int kEdges = 9;     // first edge id at this Real offset
+};
+template <>
+struct PushRow<float> {
+    static constexpr int kStride = 16;
+    static constexpr int kEdges = 10;
+};
+
+// The coefficient pass reads the float64 push row (grad l_1..3 and the edge ids;
+// grad l_0 = -(grad l_1 + grad l_2 + grad l_3), the sum the mesh tables define it
+// by) and the four face ids of the tet: 112 B per tet.
 template <typename Real, int kSnap>
-__device__ __forceinline__ void tet_coef(int64_t nt, const TetTopo *__restrict__ topo,
-                                         const double *__restrict__ grad, const FieldPtrs &F,
+__device__ __forceinline__ void tet_coef(int64_t nt, const double *__restrict__ prow,
+                                         const int32_t *__restrict__ tetface, const FieldPtrs &F,
                                          Real *__restrict__ coef, unsigned blk) {
     const int64_t t = (int64_t)blk * kBlock + threadIdx.x;
     const int64_t T = t >> 1;
     const int part = (int)(t & 1);   // 0: A_0..3 (edges), 1: C_0..3 (faces)
     if (T >= nt) return;
+    const double *row = prow + T * PushRow<double>::kStride;
     double g[4][3];
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
+    for (int k = 1; k < 4; ++k)
 #pragma unroll
-        for (int d = 0; d < 3; ++d) g[k][d] = grad[T * 12 + 3 * k + d];
-    const int32_t *tp = reinterpret_cast<const int32_t *>(topo + T);
+        for (int d = 0; d < 3; ++d) g[k][d] = row[3 * (k - 1) + d];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) g[0][d] = -(g[1][d] + g[2][d] + g[3][d]);
+    int32_t tp[10];   // edge ids 0..5, face ids 6..9
+    const int32_t *re = reinterpret_cast<const int32_t *>(row + PushRow<double>::kEdges);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) tp[k] = re[k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) tp[6 + k] = tetface[4 * T + k];
     double o[12];
     if (part == 0) {
         coef_A<0, kSnap>(tp, g, F, o);
@@ -215,30 +244,13 @@ __device__ __forceinline__ void tet_coef(int64_t nt, const TetTopo *__restrict__
 }
 
 template <typename Real, int kSnap = 1>
-__global__ void __launch_bounds__(kBlock) k_tet_coef(int64_t nt, const TetTopo *__restrict__ topo,
-                                                     const double *__restrict__ grad, FieldPtrs F,
+__global__ void __launch_bounds__(kBlock) k_tet_coef(int64_t nt, const double *__restrict__ prow,
+                                                     const int32_t *__restrict__ tetface, FieldPtrs F,
                                                      Real *__restrict__ coef) {
-    tet_coef<Real, kSnap>(nt, topo, grad, F, coef, blockIdx.x);
+    tet_coef<Real, kSnap>(nt, prow, tetface, F, coef, blockIdx.x);
 }
 
 // ------------------------------------------------------------------ particle step
-// What the particle kernel reads per tet besides this step's coefficients: the
-// barycentric gradients grad l_1..3 (9 reals, in the kernel's precision) and the
-// six global edge ids, packed in one row so that a run's lanes touch one
-// contiguous record (float64: 9 doubles + 6 int32 = 96 B; float32: 9 floats,
-// one pad, 6 int32 = 64 B).
-template <typename Real>
-struct PushRow;
-template <>
-struct PushRow<double> {
-    static constexpr int kStride = 12;   // doubles per row
-    static constexpr int kEdges = 9;     // first edge id at this Real offset
-};
-template <>
-struct PushRow<float> {
-    static constexpr int kStride = 16;
-    static constexpr int kEdges = 10;
-};
 template <typename Real>
 __device__ __forceinline__ const int32_t *push_row_edges(const Real *row) {
     return reinterpret_cast<const int32_t *>(row + PushRow<Real>::kEdges);
@@ -261,6 +273,8 @@ struct StepArgs {
     unsigned *slice_queue;     // 64-particle slices whose walkers did not fit in walk_queue
     unsigned *walk_ctr;        // [0] walk_queue length, [1] walk blocks done, [2] slice_queue length
     int walk_by_slice;         // queue every walker by its slice (the overflow path)
+    const double *gpush64;     // float64 push rows and tet-face ids: what the
+    const int32_t *tetface;    // coefficient pass of the fused launch reads
     double qw;
     Real h;                    // q dt / (2 m)
     Real dt_r;
@@ -692,7 +706,7 @@ __global__ void __launch_bounds__(kBlock) k_walk_coef(StepArgs<Real> a, int64_t 
     if (blockIdx.x < kWalkBlocks)
         walk_queued(a, blockIdx.x, kWalkBlocks);
     else
-        tet_coef<Real, kSnap>(nt, a.topo, a.grad, F, const_cast<Real *>(a.coef), blockIdx.x - kWalkBlocks);
+        tet_coef<Real, kSnap>(nt, a.gpush64, a.tetface, F, const_cast<Real *>(a.coef), blockIdx.x - kWalkBlocks);
 }
 
 // ------------------------------------------------------------------ adjoint step
@@ -1568,6 +1582,7 @@ struct etpic_ctx {
     double *d_grad64 = nullptr;
     double *d_gpush64 = nullptr;     // nt rows of PushRow<double>
     float *d_gpush32 = nullptr;       // nt rows of PushRow<float>
+    int32_t *d_tetface = nullptr;     // nt*4 face ids (face k opposite vertex k)
     void *d_coef = nullptr;          // nt*24 doubles (float table uses the first half)
     int32_t *d_v2e_ptr = nullptr;
     int32_t *d_v2e_code = nullptr;
@@ -1633,6 +1648,8 @@ struct etpic_ctx {
         a.walk_queue = d_walk_queue;
         a.slice_queue = d_slice_queue;
         a.walk_ctr = d_walk_ctr;
+        a.gpush64 = d_gpush64;
+        a.tetface = d_tetface;
         a.qw = sp->q * sp->w;
         a.h = (Real)(sp->q * dt / (2.0 * sp->m));
         a.dt_r = (Real)dt;
@@ -1653,10 +1670,10 @@ struct etpic_ctx {
         const int64_t nt = host.nt;
         const FieldPtrs F = field_ptrs(plan.snap, plan.w, std::cos(omega * plan.t), std::sin(omega * plan.t));
         if (plan.snap[1])
-            k_tet_coef<Real, 3><<<grid_for(2 * nt), kBlock, 0, s>>>(nt, d_topo, d_grad64, F,
+            k_tet_coef<Real, 3><<<grid_for(2 * nt), kBlock, 0, s>>>(nt, d_gpush64, d_tetface, F,
                                                                    static_cast<Real *>(d_coef));
         else
-            k_tet_coef<Real, 1><<<grid_for(2 * nt), kBlock, 0, s>>>(nt, d_topo, d_grad64, F,
+            k_tet_coef<Real, 1><<<grid_for(2 * nt), kBlock, 0, s>>>(nt, d_gpush64, d_tetface, F,
                                                                    static_cast<Real *>(d_coef));
         HIP_TRY(hipGetLastError());
         return ETPIC_OK;
@@ -1743,6 +1760,7 @@ struct etpic_ctx {
         (void)hipFree(d_grad64);
         (void)hipFree(d_gpush64);
         (void)hipFree(d_gpush32);
+        (void)hipFree(d_tetface);
         (void)hipFree(d_coef);
         (void)hipFree(d_v2e_ptr);
         (void)hipFree(d_v2e_code);
@@ -1754,6 +1772,7 @@ struct etpic_ctx {
         d_grad64 = nullptr;
         d_gpush64 = nullptr;
         d_gpush32 = nullptr;
+        d_tetface = nullptr;
         d_coef = nullptr;
         d_v2e_ptr = d_v2e_code = nullptr;
         d_xyz = nullptr;
@@ -1937,6 +1956,10 @@ int etpic_mesh_upload(etpic_ctx *ctx, int64_t n_vert, const double *xyz_host, in
         }
         HIP_TRY(hipMemcpy(ctx->d_gpush64, gp64.data(), sizeof(double) * s64 * nt, hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(ctx->d_gpush32, gp32.data(), sizeof(float) * s32 * nt, hipMemcpyHostToDevice));
+        std::vector<int32_t> tf((size_t)nt * 4);
+        for (int64_t t = 0; t < nt; ++t) std::memcpy(&tf[4 * t], M.topo[t].f, sizeof(int32_t) * 4);
+        HIP_TRY(hipMalloc(&ctx->d_tetface, sizeof(int32_t) * 4 * nt));
+        HIP_TRY(hipMemcpy(ctx->d_tetface, tf.data(), sizeof(int32_t) * 4 * nt, hipMemcpyHostToDevice));
     }
     HIP_TRY(hipMalloc(&ctx->d_coef, sizeof(double) * 24 * nt));
     {
@@ -2135,7 +2158,7 @@ int etpic_backward(etpic_ctx *ctx, int64_t n, const etpic_species *sp, const etp
             const etpic_fields *snap[3] = {f, nullptr, nullptr};
             const double w1[3] = {1.0, 0.0, 0.0};
             const FieldPtrs F = field_ptrs(snap, w1, c, s);
-            k_tet_coef<double, 1><<<grid_for(2 * nt), kBlock, 0, st>>>(nt, ctx->d_topo, ctx->d_grad64, F,
+            k_tet_coef<double, 1><<<grid_for(2 * nt), kBlock, 0, st>>>(nt, ctx->d_gpush64, ctx->d_tetface, F,
                                                                        static_cast<double *>(ctx->d_coef));
             HIP_TRY(hipGetLastError());
             StepArgs<double> a = ctx->step_args<double>(&cur, sp, dt, scratch_dG, nullptr);

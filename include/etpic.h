@@ -94,7 +94,9 @@ enum etpic_step_flags {
     ETPIC_STEP_SLICES_16 = 16u,
     /* queue the particles that leave their tet by 64-particle slice, the path
      * the library otherwise takes only when more than 2^23 particles leave
-     * their tet in one step (exercises that path) */
+     * their tet in one step (exercises that path); in the sorting step of
+     * etpic_sort_run_steps, whose overflow path is a scan of all particles,
+     * take that scan instead */
     ETPIC_STEP_WALK_BY_SLICE = 32u
 };
 
@@ -238,6 +240,22 @@ int etpic_coarse_step(etpic_ctx *ctx, const etpic_particles *p, int precision, c
 int etpic_sort(etpic_ctx *ctx, const etpic_particles *src, const etpic_particles *dst, int precision,
                void *stream);
 
+/* etpic_sort(src -> dst) followed by etpic_run_steps on dst, with the sort's
+ * scatter folded into the first step: the first step's particle kernel reads
+ * the particles of src in their order and writes them, pushed, at their
+ * tet-sorted positions of dst, so the particle state crosses HBM once for
+ * both (used for the periodic re-sort).  When the slice choice of
+ * etpic_run_steps picks more than one slice per wavefront, the scatter runs as
+ * a pass of its own before the steps.  Each particle's result, and the
+ * placement of the tets' groups, are those of the two calls; the order within
+ * a tet is unspecified as for etpic_sort, and dG / rho agree to the float64
+ * atomics' summation order.  src is read only.  Requirements on src and dst
+ * as for etpic_sort, on the step arguments as for etpic_run_steps;
+ * nsteps >= 1.  Asynchronous on `stream`.  Errors as etpic_run_steps. */
+int etpic_sort_run_steps(etpic_ctx *ctx, const etpic_particles *src, const etpic_particles *dst, int precision,
+                         const etpic_species *sp, const etpic_fields *f, int64_t step0, int nsteps, double dt,
+                         double omega, double *dG, double *rho, uint32_t flags, void *stream);
+
 /* rho[N_n] += q w * lam_k for the four vertices of every particle's tet
  * (the W0 shape; Formulation, the particle charge density). Asynchronous. */
 int etpic_vertex_charge(etpic_ctx *ctx, const etpic_particles *p, const etpic_species *sp, double *rho,
@@ -322,12 +340,15 @@ int etpic_field_step(etpic_ctx *ctx, double t_next, double *u, double *v, double
                      double tol, int max_iter, int *iters_out, double *resid_out, void *stream);
 
 /* Kernel times of the steps launched with ETPIC_STEP_TIMING since the last
- * reset, from HIP events recorded on the launch stream around each kernel:
- * ms_out[0] = particle kernel (gather, push, in-tet deposit), ms_out[1] =
- * per-tet coefficient kernel, ms_out[2] = walk kernel, summed over the steps.
- * Synchronises on the last event.  *launches_out = number of timed steps;
+ * reset, from HIP events recorded on the launch stream around each kernel,
+ * summed over the steps: ms_out[0] = particle kernel (gather, push, in-tet
+ * deposit) of the steps that update the particles in place, ms_out[1] =
+ * per-tet coefficient kernel, ms_out[2] = walk kernel, ms_out[3] = particle
+ * kernel of the steps that also sort (the first step of
+ * etpic_sort_run_steps).  launches_out (may be NULL) = number of timed steps
+ * of each kind: [0] in place, [1] sorting.  Synchronises on the last event;
  * reset != 0 clears the record afterwards. */
-int etpic_kernel_time(etpic_ctx *ctx, double ms_out[3], int64_t *launches_out, int reset);
+int etpic_kernel_time(etpic_ctx *ctx, double ms_out[4], int64_t launches_out[2], int reset);
 
 /* Synchronise `stream`, return and clear the device status word in *device_flags.
  * Returns EWALK / ENAN / EPARTICLE for the first set bit, OK otherwise. */

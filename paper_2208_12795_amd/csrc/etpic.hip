@@ -7,11 +7,12 @@
 //                 in lam), where A_i, C_i fold the real parts Re{dof e^{jwt}} + dc
 //                 of the 6 edge and 4 face DoFs into the gradients; the envelope
 //                 may be interpolated in time between three snapshots.
-//   k_push, k_push_slices
+//   k_push, k_push_rho, k_push_slices
 //                 per particle, tet-sorted: gather from the coefficient row,
 //                 Boris push, in-tet path-integral deposit reduced over runs
 //                 of equal tet in each wavefront, float64 atomics; particles
-//                 leaving their tet are queued.  The sliced form gives each
+//                 leaving their tet are queued.  k_push_rho also scatters the
+//                 end-point vertex charge; the sliced form gives each
 //                 wavefront several consecutive 64-particle slices.
 //   k_walk        the queued particles: barycentric walk, reflection, deposit.
 //   k_walk_coef   the walk of a step and the next step's coefficients in one
@@ -275,6 +276,17 @@ struct StepArgs {
     int walk_by_slice;         // queue every walker by its slice (the overflow path)
     const double *gpush64;     // float64 push rows and tet-face ids: what the
     const int32_t *tetface;    // coefficient pass of the fused launch reads
+    // Counting-sort scatter fused into the step (k_push_sort): the particles
+    // read from the arrays above are written, pushed, at their sorted
+    // positions cursor[T]++ of these arrays; the walk after it runs on them.
+    double *o_lam1, *o_lam2, *o_lam3;
+    Real *o_v0, *o_v1, *o_v2;
+    int32_t *o_tet;
+    const int64_t *id;
+    int64_t *o_id;
+    unsigned *cursor;          // exclusive prefix sums of the tet counts
+    int scatter;               // the walk follows a scatter step: its queue
+                               // overflow is handled by a scan of all particles
     double qw;
     Real h;                    // q dt / (2 m)
     Real dt_r;
@@ -411,13 +423,13 @@ __device__ __forceinline__ int walk(const StepArgs<Real> &a, int T, double l[4],
 
 // q w * (the run's path-integral sums) onto the six edges of tet T, and
 // q w * (its end-point barycentric sums) onto the four vertices if rho is kept.
-template <typename Real>
+template <typename Real, bool kRho>
 __device__ __forceinline__ void flush_run(const StepArgs<Real> &a, int T, const double g6[6], const double r4[4]) {
     const int32_t *ed = push_row_edges(a.gpush + (int64_t)T * PushRow<Real>::kStride);
 #pragma unroll
     for (int e = 0; e < 6; ++e)
         if (g6[e] != 0.0) unsafeAtomicAdd(&a.dG[ed[e]], a.qw * g6[e]);
-    if (a.rho) {
+    if (kRho) {
         const TetTopo *tp = a.topo + T;
 #pragma unroll
         for (int k = 0; k < 4; ++k)
@@ -443,7 +455,7 @@ __device__ __forceinline__ void flush_run(const StepArgs<Real> &a, int T, const 
 // per wavefront (same-address atomics from many wavefronts serialise).  With
 // about one wavefront's worth of particles per tet or fewer, one slice per
 // wavefront keeps more wavefronts in flight and is faster.
-template <typename Real, int kSlices>
+template <typename Real, int kSlices, bool kRho, bool kScatter = false>
 __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) {
     unsigned blk = blockIdx.x;
     if (remap) {
@@ -486,6 +498,16 @@ __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) 
             }
         }
         const bool act = T >= 0;
+        // scatter form: this lane's sorted position, from one cursor atomic
+        // per run of equal tet (the lanes of a run keep their order)
+        unsigned dq = 0;
+        if (kScatter) {
+            const WaveRuns r = wave_runs(T, ln);
+            unsigned base = 0;
+            if (r.head && act) base = atomicAdd(&a.cursor[T], (unsigned)(r.run_end - r.lane + 1));
+            base = __shfl(base, r.head_lane);
+            dq = base + (unsigned)(r.lane - r.head_lane);
+        }
         double g6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // this lane's in-tet path integrals
         double r4[4] = {0.0, 0.0, 0.0, 0.0};             // this lane's end-point barycentrics
         int walker = 0;
@@ -543,22 +565,43 @@ __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) 
                 for (int e = 0; e < 6; ++e) g6[e] = m[le[e][0]] * dl[le[e][1]] - m[le[e][1]] * dl[le[e][0]];
 #pragma unroll
                 for (int k = 1; k < 4; ++k) l[k] += dl[k];
-                __builtin_nontemporal_store(l[1], &lam1[ln]);
-                __builtin_nontemporal_store(l[2], &lam2[ln]);
-                __builtin_nontemporal_store(l[3], &lam3[ln]);
-                if (a.rho) {
+                if (kScatter) {
+                    __builtin_nontemporal_store(l[1], &a.o_lam1[dq]);
+                    __builtin_nontemporal_store(l[2], &a.o_lam2[dq]);
+                    __builtin_nontemporal_store(l[3], &a.o_lam3[dq]);
+                    a.o_tet[dq] = T;
+                } else {
+                    __builtin_nontemporal_store(l[1], &lam1[ln]);
+                    __builtin_nontemporal_store(l[2], &lam2[ln]);
+                    __builtin_nontemporal_store(l[3], &lam3[ln]);
+                }
+                if (kRho) {
                     r4[0] = 1.0 - l[1] - l[2] - l[3];
                     r4[1] = l[1];
                     r4[2] = l[2];
                     r4[3] = l[3];
                 }
+            } else if (kScatter) {
+                // the walk starts from the old barycentrics at the new position
+                a.o_lam1[dq] = l[1];
+                a.o_lam2[dq] = l[2];
+                a.o_lam3[dq] = l[3];
+                a.o_tet[dq] = walker_mark(T);
+                walker = 1;
             } else {
                 tetp[ln] = walker_mark(T);
                 walker = 1;
             }
-            __builtin_nontemporal_store(v[0], &v0[ln]);
-            __builtin_nontemporal_store(v[1], &v1[ln]);
-            __builtin_nontemporal_store(v[2], &v2[ln]);
+            if (kScatter) {
+                __builtin_nontemporal_store(v[0], &a.o_v0[dq]);
+                __builtin_nontemporal_store(v[1], &a.o_v1[dq]);
+                __builtin_nontemporal_store(v[2], &a.o_v2[dq]);
+                if (a.id) __builtin_nontemporal_store(__builtin_nontemporal_load(&a.id[p]), &a.o_id[dq]);
+            } else {
+                __builtin_nontemporal_store(v[0], &v0[ln]);
+                __builtin_nontemporal_store(v[1], &v1[ln]);
+                __builtin_nontemporal_store(v[2], &v2[ln]);
+            }
         }
         const WaveRuns runs = wave_runs(T, ln);
         // the open run continues into this slice: lane 0 takes over its sums;
@@ -577,7 +620,7 @@ __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) 
 #pragma unroll
                     for (int k = 0; k < 4; ++k) r4[k] += cr[k];
                 } else {
-                    flush_run(a, carry_T, cg, cr);
+                    flush_run<Real, kRho>(a, carry_T, cg, cr);
                 }
             }
         }
@@ -586,12 +629,12 @@ __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) 
         // which stays open for the next slice
 #pragma unroll
         for (int e = 0; e < 6; ++e) g6[e] = run_total(g6[e], runs);
-        if (a.rho) {
+        if (kRho) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) r4[k] = run_total(r4[k], runs);
         }
         const bool last = it == kSlices - 1 || (slice + 1) * 64 >= a.n;
-        if (act && runs.lane == runs.run_end && (ln != 63 || last)) flush_run(a, T, g6, r4);
+        if (act && runs.lane == runs.run_end && (ln != 63 || last)) flush_run<Real, kRho>(a, T, g6, r4);
         if (!last) {
             carry_T = __builtin_amdgcn_readlane(T, 63);
             if (ln == 63) {
@@ -609,23 +652,41 @@ __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) 
             unsigned base = 0;
             if (ln == 0) base = atomicAdd(&a.walk_ctr[0], cnt);
             base = __shfl(base, 0);
-            const bool fits = !a.walk_by_slice && base < kWalkQueueCap && cnt <= kWalkQueueCap - base;
+            const bool fits = (kScatter || !a.walk_by_slice) && base < kWalkQueueCap && cnt <= kWalkQueueCap - base;
             const unsigned rank = (unsigned)__popcll(wmask & ((1ull << ln) - 1ull));
-            if (walker && base + rank < kWalkQueueCap) a.walk_queue[base + rank] = fits ? (unsigned)p : kQueueSkip;
-            if (!fits && ln == 0) a.slice_queue[atomicAdd(&a.walk_ctr[2], 1u)] = (unsigned)slice;
+            if (walker && base + rank < kWalkQueueCap)
+                a.walk_queue[base + rank] = fits ? (kScatter ? dq : (unsigned)p) : kQueueSkip;
+            // (after a scatter step the walkers of a slice are spread over the
+            // output, so an overflow there makes the walk scan every particle)
+            if (!kScatter && !fits && ln == 0) a.slice_queue[atomicAdd(&a.walk_ctr[2], 1u)] = (unsigned)slice;
         }
     }
 }
 
+// One slice per wavefront; without the vertex charge the kernel fits 64 VGPRs
+// (8 wavefronts per SIMD), which the compiler does not choose by itself.
 template <typename Real>
-__global__ void __launch_bounds__(kBlock) k_push(StepArgs<Real> a, int remap) {
-    push_slices<Real, 1>(a, remap);
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) k_push(StepArgs<Real> a, int remap) {
+    push_slices<Real, 1, false>(a, remap);
 }
 
-template <typename Real, int kSlices>
+template <typename Real>
+__global__ void __launch_bounds__(kBlock) k_push_rho(StepArgs<Real> a, int remap) {
+    push_slices<Real, 1, true>(a, remap);
+}
+
+// One slice per wavefront, reading the particles in their old order and
+// writing them, pushed, to their tet-sorted positions: the counting sort's
+// scatter pass folded into the step.
+template <typename Real, bool kRho>
+__global__ void __launch_bounds__(kBlock) k_push_sort(StepArgs<Real> a, int remap) {
+    push_slices<Real, 1, kRho, true>(a, remap);
+}
+
+template <typename Real, int kSlices, bool kRho>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7)))
 k_push_slices(StepArgs<Real> a, int remap) {
-    push_slices<Real, kSlices>(a, remap);
+    push_slices<Real, kSlices, kRho>(a, remap);
 }
 
 // Walk of one marked particle p: every piece of its path is deposited with
@@ -667,16 +728,24 @@ __device__ __forceinline__ void walk_particle(const StepArgs<Real> &a, int64_t p
 // the counters for the next step.
 template <typename Real>
 __device__ __forceinline__ void walk_queued(const StepArgs<Real> &a, unsigned blk, unsigned nblk) {
-    const unsigned count = min(__atomic_load_n(&a.walk_ctr[0], __ATOMIC_RELAXED), kWalkQueueCap);
-    for (unsigned i = blk * kBlock + threadIdx.x; i < count; i += nblk * kBlock) {
-        const unsigned q = a.walk_queue[i];
-        if (q != kQueueSkip && (int64_t)q < a.n) walk_particle(a, (int64_t)q);
-    }
-    const unsigned slices = __atomic_load_n(&a.walk_ctr[2], __ATOMIC_RELAXED);
-    const unsigned wpb = kBlock / 64;
-    for (unsigned i = blk * wpb + (threadIdx.x >> 6); i < slices; i += nblk * wpb) {
-        const int64_t p = (int64_t)a.slice_queue[i] * 64 + (threadIdx.x & 63);
-        if (p < a.n) walk_particle(a, p);
+    const unsigned total = __atomic_load_n(&a.walk_ctr[0], __ATOMIC_RELAXED);
+    if (a.scatter && (a.walk_by_slice || total > kWalkQueueCap)) {
+        // after a scatter step whose walkers did not all fit in the queue:
+        // every marked particle, found by a scan (one lane per particle)
+        for (int64_t p = (int64_t)blk * kBlock + threadIdx.x; p < a.n; p += (int64_t)nblk * kBlock)
+            walk_particle(a, p);
+    } else {
+        const unsigned count = min(total, kWalkQueueCap);
+        for (unsigned i = blk * kBlock + threadIdx.x; i < count; i += nblk * kBlock) {
+            const unsigned q = a.walk_queue[i];
+            if (q != kQueueSkip && (int64_t)q < a.n) walk_particle(a, (int64_t)q);
+        }
+        const unsigned slices = __atomic_load_n(&a.walk_ctr[2], __ATOMIC_RELAXED);
+        const unsigned wpb = kBlock / 64;
+        for (unsigned i = blk * wpb + (threadIdx.x >> 6); i < slices; i += nblk * wpb) {
+            const int64_t p = (int64_t)a.slice_queue[i] * 64 + (threadIdx.x & 63);
+            if (p < a.n) walk_particle(a, p);
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1608,18 +1677,21 @@ struct etpic_ctx {
     int64_t tiles = 0;
     FieldState field;
     // HIP events bracketing the kernels of steps run with ETPIC_STEP_TIMING:
-    // 4 events per step (before the coefficient kernel, before and after the
-    // particle kernel, after the walk kernel)
+    // 5 events per step (before and after the coefficient kernel, before and
+    // after the particle kernel, after the walk kernel), and whether the
+    // step's particle kernel also sorted (k_push_sort)
     std::vector<std::array<hipEvent_t, 5>> timing;
+    std::vector<char> timing_sorting;
     std::vector<std::array<hipEvent_t, 5>> spare;
 
-    int timing_events(hipEvent_t **ev) {
+    int timing_events(hipEvent_t **ev, bool sorting = false) {
         if (spare.empty()) {
             std::array<hipEvent_t, 5> e{};
             for (auto &x : e) HIP_TRY(hipEventCreate(&x));
             spare.push_back(e);
         }
         timing.push_back(spare.back());
+        timing_sorting.push_back(sorting ? 1 : 0);
         spare.pop_back();
         *ev = timing.back().data();
         return ETPIC_OK;
@@ -1679,21 +1751,79 @@ struct etpic_ctx {
         return ETPIC_OK;
     }
 
+    template <typename Real, bool kRho>
+    void launch_push(const StepArgs<Real> &a, int slices, int remap, hipStream_t st) {
+        const int64_t n = a.n;
+        switch (slices) {
+        case 16: k_push_slices<Real, 16, kRho><<<grid_for((n + 15) / 16), kBlock, 0, st>>>(a, remap); break;
+        case 4: k_push_slices<Real, 4, kRho><<<grid_for((n + 3) / 4), kBlock, 0, st>>>(a, remap); break;
+        default:
+            if (kRho)
+                k_push_rho<Real><<<grid_for(n), kBlock, 0, st>>>(a, remap);
+            else
+                k_push<Real><<<grid_for(n), kBlock, 0, st>>>(a, remap);
+            break;
+        }
+    }
+
+    // Counting sort, first half: tet counts of src, the run-length statistic
+    // for the slice choice (unless one is still in flight), and the exclusive
+    // prefix sums of the counts in d_count (the scatter cursors).
+    int sort_count(const etpic_particles *src, hipStream_t st) {
+        const int64_t nt = host.nt, n = src->n, m = nt + 1;
+        k_fill_u32<<<grid_for(m), kBlock, 0, st>>>(d_count, m, 0u);
+        k_hist<<<grid_for(n), kBlock, 0, st>>>(n, nt, src->tet, d_count, d_status);
+        if (!runstat_pending) {
+            k_fill_u32<<<1, kBlock, 0, st>>>(reinterpret_cast<unsigned *>(d_runstat), 2, 0u);
+            k_run_stat<<<(unsigned)std::min<int64_t>(grid_for(nt), 256), kBlock, 0, st>>>(nt, d_count, d_runstat);
+            HIP_TRY(hipMemcpyAsync(h_runstat, d_runstat, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipEventRecord(runstat_ev, st));
+            runstat_pending = true;
+            runstat_n = n;
+        }
+        k_scan_tiles<<<(unsigned)tiles, kBlock, 0, st>>>(d_count, m, d_tilesum);
+        k_scan_sums<<<1, kBlock, 0, st>>>(d_tilesum, tiles);
+        k_scan_add<<<grid_for(m), kBlock, 0, st>>>(d_count, m, d_tilesum);
+        HIP_TRY(hipGetLastError());
+        return ETPIC_OK;
+    }
+
+    template <typename Real>
+    int sort(const etpic_particles *src, const etpic_particles *dst, hipStream_t st) {
+        if (int r = sort_count(src, st)) return r;
+        k_scatter<Real><<<grid_for(src->n), kBlock, 0, st>>>(src->n, host.nt, src->tet, d_count, *src, *dst);
+        HIP_TRY(hipGetLastError());
+        return ETPIC_OK;
+    }
+
     // nsteps consecutive steps, step j at time plans[j].t with the envelope
     // sum_k w[k] snap[k] of plans[j]; rho (if any) after the last step.  Each
     // step is coefficient pass, particle kernel, walk kernel on the caller's
     // stream; between two steps of the call the walk and the next step's
     // coefficient pass share one launch (k_walk_coef).
+    // With src, the particles of src are first counting-sorted by tet into p:
+    // the scatter is folded into the first step's particle kernel when that
+    // step takes the one-slice form, else it runs as a pass of its own.
     template <typename Real>
     int run_steps(const etpic_particles *p, const etpic_species *sp, const StepPlan *plans, int nsteps, double dt,
-                  double omega, double *dG, double *rho, uint32_t flags, void *stream) {
+                  double omega, double *dG, double *rho, uint32_t flags, void *stream,
+                  const etpic_particles *src = nullptr) {
         hipStream_t st = static_cast<hipStream_t>(stream);
         const int remap = (flags & ETPIC_STEP_XCD_REMAP) ? 1 : 0;
         const int64_t n = p->n, nt = host.nt;
         const unsigned coef_blocks = grid_for(2 * nt);
+        int slices0 = push_slices_for(flags, n);
+        if (src) {
+            if (slices0 == 1) {
+                if (int r = sort_count(src, st)) return r;
+            } else {
+                if (int r = sort<Real>(src, p, st)) return r;
+                src = nullptr;
+            }
+        }
         hipEvent_t *ev = nullptr;
         if (flags & ETPIC_STEP_TIMING) {
-            if (int r = timing_events(&ev)) return r;
+            if (int r = timing_events(&ev, src != nullptr)) return r;
             HIP_TRY(hipEventRecord(ev[0], st));
         }
         if (int r = launch_coef<Real>(plans[0], omega, st)) return r;
@@ -1702,10 +1832,37 @@ struct etpic_ctx {
             StepArgs<Real> a = step_args<Real>(p, sp, dt, dG, j == nsteps - 1 ? rho : nullptr);
             a.walk_by_slice = (flags & ETPIC_STEP_WALK_BY_SLICE) ? 1 : 0;
             if (ev) HIP_TRY(hipEventRecord(ev[2], st));
-            switch (push_slices_for(flags, n)) {
-            case 16: k_push_slices<Real, 16><<<grid_for((n + 15) / 16), kBlock, 0, st>>>(a, remap); break;
-            case 4: k_push_slices<Real, 4><<<grid_for((n + 3) / 4), kBlock, 0, st>>>(a, remap); break;
-            default: k_push<Real><<<grid_for(n), kBlock, 0, st>>>(a, remap); break;
+            if (j == 0 && src) {
+                // read src, write p at the sorted positions; the walk then runs on p
+                StepArgs<Real> as = a;
+                as.lam1 = src->lam[0];
+                as.lam2 = src->lam[1];
+                as.lam3 = src->lam[2];
+                as.v0 = static_cast<Real *>(src->vel[0]);
+                as.v1 = static_cast<Real *>(src->vel[1]);
+                as.v2 = static_cast<Real *>(src->vel[2]);
+                as.tet = src->tet;
+                as.o_lam1 = p->lam[0];
+                as.o_lam2 = p->lam[1];
+                as.o_lam3 = p->lam[2];
+                as.o_v0 = static_cast<Real *>(p->vel[0]);
+                as.o_v1 = static_cast<Real *>(p->vel[1]);
+                as.o_v2 = static_cast<Real *>(p->vel[2]);
+                as.o_tet = p->tet;
+                as.id = src->id;
+                as.o_id = p->id;
+                as.cursor = d_count;
+                if (as.rho)
+                    k_push_sort<Real, true><<<grid_for(n), kBlock, 0, st>>>(as, remap);
+                else
+                    k_push_sort<Real, false><<<grid_for(n), kBlock, 0, st>>>(as, remap);
+                a.scatter = 1;
+            } else {
+                const int slices = j == 0 ? slices0 : push_slices_for(flags, n);
+                if (a.rho)
+                    launch_push<Real, true>(a, slices, remap, st);
+                else
+                    launch_push<Real, false>(a, slices, remap, st);
             }
             HIP_TRY(hipGetLastError());
             if (ev) HIP_TRY(hipEventRecord(ev[3], st));
@@ -2031,6 +2188,21 @@ int etpic_mesh_faces(const etpic_ctx *ctx, int32_t *face_vert_host) {
     return ETPIC_OK;
 }
 
+static int check_sort_pair(etpic_ctx *ctx, const etpic_particles *src, const etpic_particles *dst) {
+    if (!ctx || !src || !dst) return fail(ETPIC_EINVAL, "null argument");
+    if (!ctx->has_mesh) return fail(ETPIC_ESTATE, "no mesh uploaded");
+    if (int r = check_particles(ctx, src)) return r;
+    if (int r = check_particles(ctx, dst)) return r;
+    if (src->n != dst->n) return fail(ETPIC_EINVAL, "source and destination sizes differ");
+    if ((src->id == nullptr) != (dst->id == nullptr)) return fail(ETPIC_EINVAL, "id array given on one side only");
+    for (int k = 0; k < 3; ++k)
+        if (src->lam[k] == dst->lam[k] || src->vel[k] == dst->vel[k])
+            return fail(ETPIC_EINVAL, "sort needs distinct source and destination buffers");
+    if (src->tet == dst->tet || (src->id && src->id == dst->id))
+        return fail(ETPIC_EINVAL, "sort needs distinct source and destination buffers");
+    return ETPIC_OK;
+}
+
 int etpic_gather_push_deposit(etpic_ctx *ctx, const etpic_particles *p, int precision, const etpic_species *sp,
                               const etpic_fields *f, int64_t step, double dt, double omega, double *dG,
                               double *rho, uint32_t flags, void *stream) {
@@ -2088,6 +2260,23 @@ int etpic_run_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, con
     if (precision == ETPIC_FP64)
         return ctx->run_steps<double>(p, sp, plans.data(), nsteps, dt, omega, dG, rho, flags, stream);
     return ctx->run_steps<float>(p, sp, plans.data(), nsteps, dt, omega, dG, rho, flags, stream);
+}
+
+int etpic_sort_run_steps(etpic_ctx *ctx, const etpic_particles *src, const etpic_particles *dst, int precision,
+                         const etpic_species *sp, const etpic_fields *f, int64_t step0, int nsteps, double dt,
+                         double omega, double *dG, double *rho, uint32_t flags, void *stream) {
+    if (int r = check_sort_pair(ctx, src, dst)) return r;
+    if (int r = check_step_args(ctx, sp, f, dt, omega)) return r;
+    if (!dG) return fail(ETPIC_EINVAL, "null current accumulator");
+    if (nsteps < 1) return fail(ETPIC_EINVAL, "need at least one step");
+    if (precision != ETPIC_FP64 && precision != ETPIC_MIXED) return fail(ETPIC_EINVAL, "bad precision %d", precision);
+    if (src->n == 0) return ETPIC_OK;
+    if (int r = set_device(ctx)) return r;
+    std::vector<StepPlan> plans((size_t)nsteps);
+    for (int j = 0; j < nsteps; ++j) plans[j] = StepPlan{{f, nullptr, nullptr}, {1.0, 0.0, 0.0}, (double)(step0 + j) * dt};
+    if (precision == ETPIC_FP64)
+        return ctx->run_steps<double>(dst, sp, plans.data(), nsteps, dt, omega, dG, rho, flags, stream, src);
+    return ctx->run_steps<float>(dst, sp, plans.data(), nsteps, dt, omega, dG, rho, flags, stream, src);
 }
 
 int etpic_adjoint_workspace(const etpic_ctx *ctx, int64_t n, int nsteps, int checkpoint_every, size_t *bytes_out) {
@@ -2260,40 +2449,13 @@ int etpic_gauss_residual(etpic_ctx *ctx, const double *dG, const double *rho_new
 
 int etpic_sort(etpic_ctx *ctx, const etpic_particles *src, const etpic_particles *dst, int precision,
                void *stream) {
-    if (!ctx || !src || !dst) return fail(ETPIC_EINVAL, "null argument");
-    if (!ctx->has_mesh) return fail(ETPIC_ESTATE, "no mesh uploaded");
-    if (int r = check_particles(ctx, src)) return r;
-    if (int r = check_particles(ctx, dst)) return r;
-    if (src->n != dst->n) return fail(ETPIC_EINVAL, "source and destination sizes differ");
+    if (int r = check_sort_pair(ctx, src, dst)) return r;
     if (precision != ETPIC_FP64 && precision != ETPIC_MIXED) return fail(ETPIC_EINVAL, "bad precision %d", precision);
-    if ((src->id == nullptr) != (dst->id == nullptr)) return fail(ETPIC_EINVAL, "id array given on one side only");
-    for (int k = 0; k < 3; ++k)
-        if (src->lam[k] == dst->lam[k] || src->vel[k] == dst->vel[k])
-            return fail(ETPIC_EINVAL, "sort needs distinct source and destination buffers");
-    if (src->tet == dst->tet) return fail(ETPIC_EINVAL, "sort needs distinct source and destination buffers");
     if (src->n == 0) return ETPIC_OK;
     if (int r = set_device(ctx)) return r;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const int64_t nt = ctx->host.nt, n = src->n, m = nt + 1;
-    k_fill_u32<<<grid_for(m), kBlock, 0, st>>>(ctx->d_count, m, 0u);
-    k_hist<<<grid_for(n), kBlock, 0, st>>>(n, nt, src->tet, ctx->d_count, ctx->d_status);
-    if (!ctx->runstat_pending) {
-        k_fill_u32<<<1, kBlock, 0, st>>>(reinterpret_cast<unsigned *>(ctx->d_runstat), 2, 0u);
-        k_run_stat<<<(unsigned)std::min<int64_t>(grid_for(nt), 256), kBlock, 0, st>>>(nt, ctx->d_count, ctx->d_runstat);
-        HIP_TRY(hipMemcpyAsync(ctx->h_runstat, ctx->d_runstat, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipEventRecord(ctx->runstat_ev, st));
-        ctx->runstat_pending = true;
-        ctx->runstat_n = n;
-    }
-    k_scan_tiles<<<(unsigned)ctx->tiles, kBlock, 0, st>>>(ctx->d_count, m, ctx->d_tilesum);
-    k_scan_sums<<<1, kBlock, 0, st>>>(ctx->d_tilesum, ctx->tiles);
-    k_scan_add<<<grid_for(m), kBlock, 0, st>>>(ctx->d_count, m, ctx->d_tilesum);
-    if (precision == ETPIC_FP64)
-        k_scatter<double><<<grid_for(n), kBlock, 0, st>>>(n, nt, src->tet, ctx->d_count, *src, *dst);
-    else
-        k_scatter<float><<<grid_for(n), kBlock, 0, st>>>(n, nt, src->tet, ctx->d_count, *src, *dst);
-    HIP_TRY(hipGetLastError());
-    return ETPIC_OK;
+    if (precision == ETPIC_FP64) return ctx->sort<double>(src, dst, st);
+    return ctx->sort<float>(src, dst, st);
 }
 
 int etpic_field_setup(etpic_ctx *ctx, double dt, double omega, double eps, double mu) {
@@ -2428,23 +2590,33 @@ int etpic_field_step(etpic_ctx *ctx, double t_next, double *u, double *v, double
     return ETPIC_OK;
 }
 
-int etpic_kernel_time(etpic_ctx *ctx, double ms_out[3], int64_t *launches_out, int reset) {
+int etpic_kernel_time(etpic_ctx *ctx, double ms_out[4], int64_t launches_out[2], int reset) {
     if (!ctx || !ms_out) return fail(ETPIC_EINVAL, "null argument");
     if (int r = set_device(ctx)) return r;
-    double tot[3] = {0.0, 0.0, 0.0};
-    for (auto &e : ctx->timing) {
+    double tot[4] = {0.0, 0.0, 0.0, 0.0};
+    int64_t cnt[2] = {0, 0};
+    for (size_t i = 0; i < ctx->timing.size(); ++i) {
+        const auto &e = ctx->timing[i];
+        const int sorting = ctx->timing_sorting[i] ? 1 : 0;
         HIP_TRY(hipEventSynchronize(e[4]));
         float m[3] = {0.f, 0.f, 0.f};
         HIP_TRY(hipEventElapsedTime(&m[0], e[2], e[3]));   // particle kernel
         HIP_TRY(hipEventElapsedTime(&m[1], e[0], e[1]));   // coefficient kernel
         HIP_TRY(hipEventElapsedTime(&m[2], e[3], e[4]));   // walk kernel
-        for (int k = 0; k < 3; ++k) tot[k] += m[k];
+        tot[sorting ? 3 : 0] += m[0];
+        tot[1] += m[1];
+        tot[2] += m[2];
+        ++cnt[sorting];
     }
-    for (int k = 0; k < 3; ++k) ms_out[k] = tot[k];
-    if (launches_out) *launches_out = (int64_t)ctx->timing.size();
+    for (int k = 0; k < 4; ++k) ms_out[k] = tot[k];
+    if (launches_out) {
+        launches_out[0] = cnt[0];
+        launches_out[1] = cnt[1];
+    }
     if (reset) {
         for (auto &e : ctx->timing) ctx->spare.push_back(e);
         ctx->timing.clear();
+        ctx->timing_sorting.clear();
     }
     return ETPIC_OK;
 }

@@ -32,6 +32,7 @@ EXPORTS = (
     "etpic_adjoint_workspace", "etpic_forward_checkpointed", "etpic_backward",
     "etpic_field_setup", "etpic_field_nnz", "etpic_field_spmv", "etpic_field_step",
     "etpic_particles_locate", "etpic_particles_positions", "etpic_coarse_step", "etpic_run_steps",
+    "etpic_sort_run_steps",
 )
 
 
@@ -93,6 +94,9 @@ def lib():
     L.etpic_particles_positions.argtypes = [vp, C.POINTER(_Particles), C.c_void_p * 3, vp]
     L.etpic_run_steps.argtypes = [vp, C.POINTER(_Particles), C.c_int, C.POINTER(_Species), C.POINTER(_Fields),
                                   C.c_int64, C.c_int, C.c_double, C.c_double, vp, vp, C.c_uint32, vp]
+    L.etpic_sort_run_steps.argtypes = [vp, C.POINTER(_Particles), C.POINTER(_Particles), C.c_int,
+                                       C.POINTER(_Species), C.POINTER(_Fields), C.c_int64, C.c_int, C.c_double,
+                                       C.c_double, vp, vp, C.c_uint32, vp]
     L.etpic_coarse_step.argtypes = [vp, C.POINTER(_Particles), C.c_int, C.POINTER(_Species), _Fields * 3,
                                     C.c_double, C.c_double, C.c_int, C.c_double, vp, vp, C.c_uint32, vp]
     L.etpic_field_setup.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_double]
@@ -327,6 +331,18 @@ class Context:
         a, b = src.desc(), dst.desc()
         _chk(lib().etpic_sort(self._h, C.byref(a), C.byref(b), src.precision, _stream(stream)))
 
+    def sort_run_steps(self, src, dst, species, fields, step0, nsteps, dt, omega, dG, rho=None,
+                       flags=STEP_XCD_REMAP, stream=None):
+        """sort(src, dst) then run_steps(dst, ...), the sort's scatter folded
+        into the first step; the result is in dst, src is left as it was."""
+        assert src.precision == dst.precision
+        a, b = src.desc(), dst.desc()
+        sp = species.c()
+        fd = fields.desc()
+        _chk(lib().etpic_sort_run_steps(self._h, C.byref(a), C.byref(b), src.precision, C.byref(sp), C.byref(fd),
+                                        int(step0), int(nsteps), float(dt), float(omega), _dptr(dG), _dptr(rho),
+                                        int(flags), _stream(stream)))
+
     def locate(self, xyz, parts, hint=None, stream=None, raise_on_error=True):
         """Locate the points xyz (float64 [3, N] on the device) into parts.tet /
         parts.lam (parts.vel is not touched).  hint: int32 [N] start tets or None.
@@ -362,11 +378,15 @@ class Context:
         return float(out[0]), float(out[1])
 
     def kernel_time(self, reset=True):
-        """({"push", "coef", "walk"} total ms, steps) of the kernels of steps run with STEP_TIMING."""
-        ms = np.zeros(3)
-        n = C.c_int64(0)
-        _chk(lib().etpic_kernel_time(self._h, _np_ptr(ms, C.c_double), C.byref(n), int(bool(reset))))
-        return {"push": float(ms[0]), "coef": float(ms[1]), "walk": float(ms[2])}, n.value
+        """({"push", "coef", "walk", "push_sort"} total ms, steps) of the kernels
+        of the steps run with STEP_TIMING; "push" covers the steps that update
+        the particles in place, "push_sort" the sorting first steps of
+        sort_run_steps, and the dict's "steps_push" / "steps_sort" count them."""
+        ms = np.zeros(4)
+        n = np.zeros(2, dtype=np.int64)
+        _chk(lib().etpic_kernel_time(self._h, _np_ptr(ms, C.c_double), _np_ptr(n, C.c_int64), int(bool(reset))))
+        return ({"push": float(ms[0]), "coef": float(ms[1]), "walk": float(ms[2]), "push_sort": float(ms[3]),
+                 "steps_push": int(n[0]), "steps_sort": int(n[1])}, int(n.sum()))
 
     # differentiation (float64) -----------------------------------------------------
     def adjoint_workspace_bytes(self, n, nsteps, checkpoint_every):

@@ -124,7 +124,8 @@ def test_run_steps_equals_single_steps(E, torch_cuda, precision):
     ctx.kernel_time(reset=True)
     ctx.run_steps(p1, sp, f, 3, 10, w.dt, w.omega, g1, rho=rho, flags=E.STEP_XCD_REMAP | E.STEP_TIMING)
     kt, nl = ctx.kernel_time(reset=True)
-    assert nl == 10 and min(kt.values()) > 0.0
+    assert nl == 10 and kt["steps_push"] == 10 and kt["steps_sort"] == 0
+    assert min(kt["push"], kt["coef"], kt["walk"]) > 0.0 and kt["push_sort"] == 0.0
     for j in range(10):
         ctx.gather_push_deposit(p2, sp, f, 3 + j, w.dt, w.omega, g2)
     ctx.check()

@@ -209,9 +209,11 @@ template <typename Real, int kSnap>
 __device__ __forceinline__ void tet_coef(int64_t nt, const double *__restrict__ prow,
                                          const int32_t *__restrict__ tetface, const FieldPtrs &F,
                                          Real *__restrict__ coef, unsigned blk) {
-    const int64_t t = (int64_t)blk * kBlock + threadIdx.x;
-    const int64_t T = t >> 1;
-    const int part = (int)(t & 1);   // 0: A_0..3 (edges), 1: C_0..3 (faces)
+    // a block covers kBlock/2 tets: its first half of lanes builds A_0..3
+    // (edges), the second half C_0..3 (faces), so each wavefront takes one
+    // branch with all its lanes
+    const int part = (int)(threadIdx.x >= kBlock / 2);
+    const int64_t T = (int64_t)blk * (kBlock / 2) + (threadIdx.x & (kBlock / 2 - 1));
     if (T >= nt) return;
     const double *row = prow + T * PushRow<double>::kStride;
     double g[4][3];

@@ -244,9 +244,7 @@ int etpic_sort(etpic_ctx *ctx, const etpic_particles *src, const etpic_particles
  * scatter folded into the first step: the first step's particle kernel reads
  * the particles of src in their order and writes them, pushed, at their
  * tet-sorted positions of dst, so the particle state crosses HBM once for
- * both (used for the periodic re-sort).  When the slice choice of
- * etpic_run_steps picks more than one slice per wavefront, the scatter runs as
- * a pass of its own before the steps.  Each particle's result, and the
+ * both (used for the periodic re-sort).  Each particle's result, and the
  * placement of the tets' groups, are those of the two calls; the order within
  * a tet is unspecified as for etpic_sort, and dG / rho agree to the float64
  * atomics' summation order.  src is read only.  Requirements on src and dst

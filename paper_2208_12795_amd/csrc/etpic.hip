@@ -677,9 +677,15 @@ __global__ void __launch_bounds__(kBlock) k_push_rho(StepArgs<Real> a, int remap
     push_slices<Real, 1, true>(a, remap);
 }
 
-// One slice per wavefront, reading the particles in their old order and
-// writing them, pushed, to their tet-sorted positions: the counting sort's
-// scatter pass folded into the step.
+template <typename Real, int kSlices, bool kRho>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7)))
+k_push_slices(StepArgs<Real> a, int remap) {
+    push_slices<Real, kSlices, kRho>(a, remap);
+}
+
+// The same kernels reading the particles in their old order and writing them,
+// pushed, to their tet-sorted positions: the counting sort's scatter pass
+// folded into the step.
 template <typename Real, bool kRho>
 __global__ void __launch_bounds__(kBlock) k_push_sort(StepArgs<Real> a, int remap) {
     push_slices<Real, 1, kRho, true>(a, remap);
@@ -687,8 +693,8 @@ __global__ void __launch_bounds__(kBlock) k_push_sort(StepArgs<Real> a, int rema
 
 template <typename Real, int kSlices, bool kRho>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7)))
-k_push_slices(StepArgs<Real> a, int remap) {
-    push_slices<Real, kSlices, kRho>(a, remap);
+k_push_sort_slices(StepArgs<Real> a, int remap) {
+    push_slices<Real, kSlices, kRho, true>(a, remap);
 }
 
 // Walk of one marked particle p: every piece of its path is deposited with
@@ -1753,14 +1759,26 @@ struct etpic_ctx {
         return ETPIC_OK;
     }
 
-    template <typename Real, bool kRho>
+    template <typename Real, bool kRho, bool kSort>
     void launch_push(const StepArgs<Real> &a, int slices, int remap, hipStream_t st) {
         const int64_t n = a.n;
         switch (slices) {
-        case 16: k_push_slices<Real, 16, kRho><<<grid_for((n + 15) / 16), kBlock, 0, st>>>(a, remap); break;
-        case 4: k_push_slices<Real, 4, kRho><<<grid_for((n + 3) / 4), kBlock, 0, st>>>(a, remap); break;
+        case 16:
+            if (kSort)
+                k_push_sort_slices<Real, 16, kRho><<<grid_for((n + 15) / 16), kBlock, 0, st>>>(a, remap);
+            else
+                k_push_slices<Real, 16, kRho><<<grid_for((n + 15) / 16), kBlock, 0, st>>>(a, remap);
+            break;
+        case 4:
+            if (kSort)
+                k_push_sort_slices<Real, 4, kRho><<<grid_for((n + 3) / 4), kBlock, 0, st>>>(a, remap);
+            else
+                k_push_slices<Real, 4, kRho><<<grid_for((n + 3) / 4), kBlock, 0, st>>>(a, remap);
+            break;
         default:
-            if (kRho)
+            if (kSort)
+                k_push_sort<Real, kRho><<<grid_for(n), kBlock, 0, st>>>(a, remap);
+            else if (kRho)
                 k_push_rho<Real><<<grid_for(n), kBlock, 0, st>>>(a, remap);
             else
                 k_push<Real><<<grid_for(n), kBlock, 0, st>>>(a, remap);
@@ -1803,9 +1821,8 @@ struct etpic_ctx {
     // step is coefficient pass, particle kernel, walk kernel on the caller's
     // stream; between two steps of the call the walk and the next step's
     // coefficient pass share one launch (k_walk_coef).
-    // With src, the particles of src are first counting-sorted by tet into p:
-    // the scatter is folded into the first step's particle kernel when that
-    // step takes the one-slice form, else it runs as a pass of its own.
+    // With src, the particles of src are first counting-sorted by tet into p,
+    // the scatter folded into the first step's particle kernel.
     template <typename Real>
     int run_steps(const etpic_particles *p, const etpic_species *sp, const StepPlan *plans, int nsteps, double dt,
                   double omega, double *dG, double *rho, uint32_t flags, void *stream,
@@ -1814,15 +1831,8 @@ struct etpic_ctx {
         const int remap = (flags & ETPIC_STEP_XCD_REMAP) ? 1 : 0;
         const int64_t n = p->n, nt = host.nt;
         const unsigned coef_blocks = grid_for(2 * nt);
-        int slices0 = push_slices_for(flags, n);
-        if (src) {
-            if (slices0 == 1) {
-                if (int r = sort_count(src, st)) return r;
-            } else {
-                if (int r = sort<Real>(src, p, st)) return r;
-                src = nullptr;
-            }
-        }
+        if (src)
+            if (int r = sort_count(src, st)) return r;
         hipEvent_t *ev = nullptr;
         if (flags & ETPIC_STEP_TIMING) {
             if (int r = timing_events(&ev, src != nullptr)) return r;
@@ -1855,16 +1865,14 @@ struct etpic_ctx {
                 as.o_id = p->id;
                 as.cursor = d_count;
                 if (as.rho)
-                    k_push_sort<Real, true><<<grid_for(n), kBlock, 0, st>>>(as, remap);
+                    launch_push<Real, true, true>(as, push_slices_for(flags, n), remap, st);
                 else
-                    k_push_sort<Real, false><<<grid_for(n), kBlock, 0, st>>>(as, remap);
+                    launch_push<Real, false, true>(as, push_slices_for(flags, n), remap, st);
                 a.scatter = 1;
+            } else if (a.rho) {
+                launch_push<Real, true, false>(a, push_slices_for(flags, n), remap, st);
             } else {
-                const int slices = j == 0 ? slices0 : push_slices_for(flags, n);
-                if (a.rho)
-                    launch_push<Real, true>(a, slices, remap, st);
-                else
-                    launch_push<Real, false>(a, slices, remap, st);
+                launch_push<Real, false, false>(a, push_slices_for(flags, n), remap, st);
             }
             HIP_TRY(hipGetLastError());
             if (ev) HIP_TRY(hipEventRecord(ev[3], st));

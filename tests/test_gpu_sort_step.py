@@ -96,11 +96,15 @@ def test_fused_sort_equals_sort_then_steps(E, torch_cuda, precision, dt_scale, f
     assert np.abs(ra - rb).max() <= 1e-13 * np.abs(ra).max()
 
 
-def test_fused_sort_with_forced_slices_takes_the_separate_pass(E, torch_cuda):
+@pytest.mark.parametrize("slices", [4, 16])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_fused_sort_with_slices(E, torch_cuda, slices, precision):
+    """The sliced particle kernels (several 64-particle slices per wavefront,
+    the open run carried across slices) in their sorting form."""
     torch = torch_cuda
     w = synth.make_workload(2, n_particles=200_000)
-    fl = E.STEP_XCD_REMAP | E.STEP_SLICES_4
-    before, ((sa, ga, _), (sb, gb, _)) = two_ways(E, torch, w, 0, 2, w.dt * 30, fl)
+    fl = E.STEP_XCD_REMAP | (E.STEP_SLICES_4 if slices == 4 else E.STEP_SLICES_16)
+    before, ((sa, ga, _), (sb, gb, _)) = two_ways(E, torch, w, precision, 2, w.dt * 30, fl)
     t0 = before[0][np.argsort(before[3])]
     assert np.array_equal(t0[sa[3]], t0[sb[3]]) and np.all(np.diff(t0[sb[3]]) >= 0)
     for x, y in zip(by_id(sa), by_id(sb)):

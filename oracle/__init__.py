@@ -59,6 +59,10 @@ def _load():
     lib.ora_jvp.restype = C.c_int
     lib.ora_locate.argtypes = [vp, _dp, _dp]
     lib.ora_locate.restype = C.c_int64
+    lib.ora_ds_weights.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, _dp, _dp, _dp, _dp, _dp, _dp]
+    lib.ora_ds_step.argtypes = [vp, C.c_int64, _ip, _dp, _dp, _dp, _dp, _dp, C.c_int, C.c_double, C.c_double,
+                                C.c_double, C.c_double, C.c_double, C.c_double, _dp, _dp, _dp, _dp, _dp, _dp, C.c_int]
+    lib.ora_ds_step.restype = C.c_int
     _LIB = lib
     return lib
 
@@ -194,6 +198,23 @@ class OracleMesh:
                                   float(w), float(t), float(dt), float(omega), _p(ee), _p(ed), _p(bb), _p(bd),
                                   _p(dG), _p(rho), None, int(nthreads))
 
+    def ds_step(self, tet, lam, vel, hist_state, *, hist, q, m, w, t, dt, omega, e_env, b_env, e_dc=None,
+                b_dc=None, dG=None, rho=None, nthreads=1):
+        """One downshifted step (velocity by the carrier-exact quadrature of the
+        interpolated envelope samples, positions by Adams-Bashforth) at t_n = t,
+        in place on (tet, lam, vel) and on hist_state = DsHistory(n).  hist =
+        number of downshifted steps before this one.  Returns the status."""
+        assert tet.dtype == np.int32 and tet.flags.c_contiguous
+        assert lam.dtype == np.float64 and lam.flags.c_contiguous
+        assert vel.dtype == np.float64 and vel.flags.c_contiguous
+        ee, bb = _cplx(e_env), _cplx(b_env)
+        ed = None if e_dc is None else _f64(e_dc)
+        bd = None if b_dc is None else _f64(b_dc)
+        H = hist_state
+        return _load().ora_ds_step(self.h, tet.shape[0], _p(tet, _ip), _p(lam), _p(vel), _p(H.v), _p(H.e), _p(H.b),
+                                   int(hist), float(q), float(m), float(w), float(t), float(dt), float(omega),
+                                   _p(ee), _p(ed), _p(bb), _p(bd), _p(dG), _p(rho), int(nthreads))
+
     def coarse_step(self, tet, lam, vel, *, q, m, w, e_snaps, b_snaps, t_coarse, dt_coarse, fine_steps, omega,
                     e_dc=None, b_dc=None, dG=None, rho=None, nthreads=1):
         """One coarse field step at the fine step (Particle Push section): the
@@ -302,3 +323,29 @@ def _jvp_method(self, tet, lam, vel, *, q, m, step0, nsteps, dt, omega, e_env, b
 
 
 OracleMesh.jvp = _jvp_method
+
+
+class DsHistory:
+    """Per-particle history of the downshifted integrator in the oracle's own
+    layout: v[n, 3, 3] = v^{n-1}, v^{n-2}, v^{n-3}; e / b [n, 2, 9] = the field
+    samples at t_{n-1}, t_{n-2}, each (Re[3], Im[3], dc[3])."""
+
+    def __init__(self, n):
+        self.v = np.zeros((n, 3, 3))
+        self.e = np.zeros((n, 2, 9))
+        self.b = np.zeros((n, 2, 9))
+
+    def take(self, idx):
+        h = DsHistory(0)
+        h.v, h.e, h.b = (np.ascontiguousarray(a[idx]) for a in (self.v, self.e, self.b))
+        return h
+
+
+def ds_weights(K, t0, h, omega):
+    """Weights of one downshifted step [t0, t0 + h] with K Lagrange nodes at
+    t0, t0 - h, ...: dict of Mr, Mi, P [K] and Lr, Li, Q [K, K]."""
+    out = {k: np.zeros(K) for k in ("Mr", "Mi", "P")}
+    out.update({k: np.zeros((K, K)) for k in ("Lr", "Li", "Q")})
+    _load().ora_ds_weights(int(K), float(t0), float(h), float(omega), _p(out["Mr"]), _p(out["Mi"]), _p(out["P"]),
+                           _p(out["Lr"]), _p(out["Li"]), _p(out["Q"]))
+    return out

@@ -17,6 +17,9 @@
  *   4. the path integral of the Whitney 1-forms along each piece, i.e. the
  *      edge DoFs g_l = <W1_l, G> of G = q * sum_p int dr (eq. g_def and the
  *      piecewise sum of eq. G_integral).
+ * The section's other scheme -- the velocity update that integrates the carrier
+ * exactly against interpolated envelope samples, with Adams-Bashforth positions
+ * (eq. newtons) -- is the downshifted step at the end of the file.
  * Each function cites the passage it follows.
  *
  * Conventions (shared definitions, own implementation): tet rows are ascending
@@ -307,15 +310,14 @@ typedef struct {
     int status; /* 0 ok, -6 hop cap */
 } ora_particle;
 
-/* One fine step of one particle: gather at (x^n, t_n), Boris, walk, deposit.
- * qw_dG receives q*w*(path integrals) for every piece (6 edges per piece). */
-static void step_one(const ora_mesh *m, ora_particle *P, double c, double s, const ora_fields_t *F,
-                     double qm, double dt, double qw, double *dG, int64_t *piece_tets, int *npieces_out,
-                     double *R) {
-    double E[3], B[3];
-    fields_at(m, P->tet, P->lam, c, s, F, E, B);
-    boris(P->v, E, B, qm, dt);
-    double d[3] = {dt * P->v[0], dt * P->v[1], dt * P->v[2]};
+/* Walk of the straight path with Cartesian displacement d from the particle's
+ * (tet, lam), depositing q*w*(path integral) of every piece into dG.  At a
+ * boundary face the remaining displacement and the velocity P->v are reflected
+ * about the face normal, and so are the nextra vectors extra[i] (velocity
+ * samples a multistep integrator keeps).  R (optional) accumulates the linear
+ * part of the reflections. */
+static void walk_path(const ora_mesh *m, ora_particle *P, double d[3], double qw, double *dG, int64_t *piece_tets,
+                      int *npieces_out, double *R, double (*extra)[3], int nextra) {
     int64_t T = P->tet;
     double l[4] = {P->lam[0], P->lam[1], P->lam[2], P->lam[3]};
     int hops = 0, np = 0;
@@ -363,6 +365,10 @@ static void step_one(const ora_mesh *m, ora_particle *P, double c, double s, con
             double nh[3] = {g[kmin][0] / nn, g[kmin][1] / nn, g[kmin][2] / nn};
             double dd = dot3(d, nh), vv = dot3(P->v, nh);
             for (int k = 0; k < 3; ++k) { d[k] -= 2.0 * dd * nh[k]; P->v[k] -= 2.0 * vv * nh[k]; }
+            for (int i = 0; i < nextra; ++i) {
+                double xv = dot3(extra[i], nh);
+                for (int k = 0; k < 3; ++k) extra[i][k] -= 2.0 * xv * nh[k];
+            }
             if (R) {   /* R <- (I - 2 n n^T) R : the linear part of the reflected end point */
                 double Rn[9];
                 for (int i = 0; i < 3; ++i)
@@ -388,6 +394,18 @@ static void step_one(const ora_mesh *m, ora_particle *P, double c, double s, con
     for (int k = 0; k < 4; ++k) P->lam[k] = l[k];
     P->hops = hops;
     if (npieces_out) *npieces_out = np;
+}
+
+/* One fine step of one particle: gather at (x^n, t_n), Boris, walk, deposit.
+ * qw_dG receives q*w*(path integrals) for every piece (6 edges per piece). */
+static void step_one(const ora_mesh *m, ora_particle *P, double c, double s, const ora_fields_t *F,
+                     double qm, double dt, double qw, double *dG, int64_t *piece_tets, int *npieces_out,
+                     double *R) {
+    double E[3], B[3];
+    fields_at(m, P->tet, P->lam, c, s, F, E, B);
+    boris(P->v, E, B, qm, dt);
+    double d[3] = {dt * P->v[0], dt * P->v[1], dt * P->v[2]};
+    walk_path(m, P, d, qw, dG, piece_tets, npieces_out, R, NULL, 0);
 }
 
 /*
@@ -849,5 +867,240 @@ int ora_jvp(const ora_mesh *m, int64_t n, const int32_t *tet0, const double *lam
             }
         }
     }
+    return status;
+}
+
+/* ------------------------------------------------------------------------
+ * Downshifted velocity integrator with Adams-Bashforth positions (Particle
+ * Push section, the first of its two schemes: the fast carrier is treated
+ * analytically inside the velocity update).  Over one particle step
+ * [t_n, t_n + h] the slowly varying quantities along the trajectory -- the
+ * envelope fields at the particle and the velocity -- are replaced by their
+ * Lagrange interpolants N_k through the samples at t_n, t_{n-1}, t_{n-2}, and
+ * the carrier is integrated exactly against them:
+ *   v^{n+1} = v^n + q/m sum_k (Re E_k M^r_k + Im E_k M^i_k + Edc_k P_k)
+ *           + q/m sum_{j,k} v^{n-j} x (Re B_k L^r_jk + Im B_k L^i_jk + Bdc_k Q_jk)
+ * with M^r_k = int N_k cos(wt), M^i_k = -int N_k sin(wt), L^r_jk = int N_j N_k
+ * cos(wt), L^i_jk = -int N_j N_k sin(wt) (the operators the section defines),
+ * and P_k = int N_k, Q_jk = int N_j N_k for the unmodulated (dc) DoFs.
+ * Positions advance with the fourth-order Adams-Bashforth stencil in the
+ * velocities (eq. newtons); the path r^n -> r^{n+1} is walked and deposited as
+ * in the fine-step scheme.  With hist < 3 previous steps the orders ramp up:
+ * K = min(hist, 2) + 1 interpolation nodes, Adams-Bashforth order
+ * min(hist, 3) + 1.
+ * The weights are computed here by composite Gauss-Legendre quadrature.
+ */
+
+/* n-point Gauss-Legendre nodes and weights on [-1, 1] (Newton on P_n). */
+static void gauss_legendre(int n, double *x, double *w) {
+    for (int i = 0; i < n; ++i) {
+        double z = cos(acos(-1.0) * (i + 0.75) / (n + 0.5)), dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = 0.0;
+            for (int k = 1; k <= n; ++k) {
+                double p2 = p1;
+                p1 = p0;
+                p0 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p2) / k;
+            }
+            dp = n * (z * p0 - p1) / (z * z - 1.0);
+            double dz = p0 / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-16) break;
+        }
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+/* Lagrange polynomial of the nodes tau_i = -i h (i < K) that is 1 at tau_k. */
+static double lagrange_node(int K, int k, double tau, double h) {
+    double r = 1.0;
+    for (int i = 0; i < K; ++i)
+        if (i != k) r *= (tau + i * h) / ((double)(i - k) * h);
+    return r;
+}
+
+/* Weights of one step [t0, t0 + h] with K nodes: Mr[K], Mi[K], P[K],
+ * Lr[K*K], Li[K*K], Q[K*K] (row j, column k). */
+void ora_ds_weights(int K, double t0, double h, double omega, double *Mr, double *Mi, double *P, double *Lr,
+                    double *Li, double *Q) {
+    enum { NG = 16, PANELS = 8 };
+    double gx[NG], gw[NG];
+    gauss_legendre(NG, gx, gw);
+    for (int k = 0; k < K; ++k) Mr[k] = Mi[k] = P[k] = 0.0;
+    for (int k = 0; k < K * K; ++k) Lr[k] = Li[k] = Q[k] = 0.0;
+    const double ph = h / PANELS;
+    for (int pn = 0; pn < PANELS; ++pn)
+        for (int g = 0; g < NG; ++g) {
+            double tau = ph * (pn + 0.5 * (gx[g] + 1.0)), wq = 0.5 * ph * gw[g];
+            double c = cos(omega * (t0 + tau)), sn = sin(omega * (t0 + tau));
+            double N[3];
+            for (int k = 0; k < K; ++k) N[k] = lagrange_node(K, k, tau, h);
+            for (int k = 0; k < K; ++k) {
+                Mr[k] += wq * N[k] * c;
+                Mi[k] -= wq * N[k] * sn;
+                P[k] += wq * N[k];
+                for (int j = 0; j < K; ++j) {
+                    Lr[j * K + k] += wq * N[j] * N[k] * c;
+                    Li[j * K + k] -= wq * N[j] * N[k] * sn;
+                    Q[j * K + k] += wq * N[j] * N[k];
+                }
+            }
+        }
+}
+
+/* Envelope samples at (T, lam): complex E~ = sum_e e~_e W1_e and B~ = sum_f
+ * b~_f W2_f (edge by edge, face by face), and the dc parts. */
+static void envelope_at(const ora_mesh *m, int64_t T, const double lam[4], const ora_fields_t *F, double Er[3],
+                        double Ei[3], double Ed[3], double Br[3], double Bi[3], double Bd[3]) {
+    double W1[6][3], W2[4][3];
+    ora_whitney1(m, T, lam, W1);
+    ora_whitney2(m, T, lam, W2);
+    for (int k = 0; k < 3; ++k) Er[k] = Ei[k] = Ed[k] = Br[k] = Bi[k] = Bd[k] = 0.0;
+    for (int e = 0; e < 6; ++e) {
+        int64_t id = m->tet_edge[6 * T + e];
+        for (int k = 0; k < 3; ++k) {
+            Er[k] += F->e_env[2 * id] * W1[e][k];
+            Ei[k] += F->e_env[2 * id + 1] * W1[e][k];
+            if (F->e_dc) Ed[k] += F->e_dc[id] * W1[e][k];
+        }
+    }
+    for (int f = 0; f < 4; ++f) {
+        int64_t id = m->tet_face[4 * T + f];
+        for (int k = 0; k < 3; ++k) {
+            Br[k] += F->b_env[2 * id] * W2[f][k];
+            Bi[k] += F->b_env[2 * id + 1] * W2[f][k];
+            if (F->b_dc) Bd[k] += F->b_dc[id] * W2[f][k];
+        }
+    }
+}
+
+typedef struct {
+    int K, A;
+    double Mr[3], Mi[3], P[3], Lr[9], Li[9], Q[9];
+    double ab[4];
+} ds_weights_t;
+
+/* One downshifted step of one particle.  vh[3][3] = v^{n-1}, v^{n-2}, v^{n-3};
+ * es / bs [2][9] = the samples at t_{n-1}, t_{n-2}, each (Re[3], Im[3], dc[3]).
+ * On return P->v = v^{n+1}, vh = v^n, v^{n-1}, v^{n-2} and es / bs = the
+ * samples at t_n, t_{n-1} (the history of the next step). */
+static void ds_step_one(const ora_mesh *m, ora_particle *P, double vh[3][3], double es[2][9], double bs[2][9],
+                        const ds_weights_t *W, const ora_fields_t *F, double qm, double h, double qw, double *dG) {
+    double Es[3][9], Bs[3][9], V[4][3];
+    envelope_at(m, P->tet, P->lam, F, Es[0], Es[0] + 3, Es[0] + 6, Bs[0], Bs[0] + 3, Bs[0] + 6);
+    for (int k = 1; k < 3; ++k)
+        for (int i = 0; i < 9; ++i) { Es[k][i] = es[k - 1][i]; Bs[k][i] = bs[k - 1][i]; }
+    for (int c = 0; c < 3; ++c) V[0][c] = P->v[c];
+    for (int j = 1; j < 4; ++j)
+        for (int c = 0; c < 3; ++c) V[j][c] = vh[j - 1][c];
+    const int K = W->K;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < K; ++k)
+        for (int c = 0; c < 3; ++c) acc[c] += Es[k][c] * W->Mr[k] + Es[k][3 + c] * W->Mi[k] + Es[k][6 + c] * W->P[k];
+    for (int j = 0; j < K; ++j)
+        for (int k = 0; k < K; ++k) {
+            double Bw[3], cr[3];
+            for (int c = 0; c < 3; ++c)
+                Bw[c] = Bs[k][c] * W->Lr[j * K + k] + Bs[k][3 + c] * W->Li[j * K + k] + Bs[k][6 + c] * W->Q[j * K + k];
+            cross3(V[j], Bw, cr);
+            for (int c = 0; c < 3; ++c) acc[c] += cr[c];
+        }
+    double vnew[3];
+    for (int c = 0; c < 3; ++c) vnew[c] = V[0][c] + qm * acc[c];
+    /* Adams-Bashforth displacement in the velocities v^n, v^{n-1}, ... */
+    double d[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < W->A; ++i)
+        for (int c = 0; c < 3; ++c) d[c] += h * W->ab[i] * V[i][c];
+    /* the velocities the next steps use are mirrored with v^{n+1} at a wall */
+    double keep[3][3];
+    for (int j = 0; j < 3; ++j)
+        for (int c = 0; c < 3; ++c) keep[j][c] = V[j][c];
+    for (int c = 0; c < 3; ++c) P->v[c] = vnew[c];
+    walk_path(m, P, d, qw, dG, NULL, NULL, NULL, keep, 3);
+    for (int j = 0; j < 3; ++j)
+        for (int c = 0; c < 3; ++c) vh[j][c] = keep[j][c];
+    for (int i = 0; i < 9; ++i) {
+        es[1][i] = Es[1][i];
+        bs[1][i] = Bs[1][i];
+        es[0][i] = Es[0][i];
+        bs[0][i] = Bs[0][i];
+    }
+}
+
+static const double AB_COEF[4][4] = {{1.0, 0.0, 0.0, 0.0},
+                                     {1.5, -0.5, 0.0, 0.0},
+                                     {23.0 / 12.0, -16.0 / 12.0, 5.0 / 12.0, 0.0},
+                                     {55.0 / 24.0, -59.0 / 24.0, 37.0 / 24.0, -9.0 / 24.0}};
+
+/* One downshifted step for n particles at t = t_n with step h.  State in and
+ * out: tet[n], lam[n*3], vel[n*3] (v^n in, v^{n+1} out), vhist[n*9]
+ * (v^{n-1}, v^{n-2}, v^{n-3} in; v^n, v^{n-1}, v^{n-2} out), esamp / bsamp
+ * [n*18] (samples at t_{n-1}, t_{n-2} in; at t_n, t_{n-1} out; each sample
+ * Re[3], Im[3], dc[3]).  hist = number of downshifted steps taken before this
+ * one (entries beyond it are not read).  dG / rho accumulate as in ora_step. */
+int ora_ds_step(const ora_mesh *m, int64_t n, int32_t *tet, double *lam, double *vel, double *vhist, double *esamp,
+                double *bsamp, int hist, double q, double mass, double w, double t, double h, double omega,
+                const double *e_env, const double *e_dc, const double *b_env, const double *b_dc, double *dG,
+                double *rho, int nthreads) {
+    ora_fields_t F = {e_env, e_dc, b_env, b_dc};
+    ds_weights_t W;
+    W.K = (hist < 2 ? hist : 2) + 1;
+    W.A = (hist < 3 ? hist : 3) + 1;
+    ora_ds_weights(W.K, t, h, omega, W.Mr, W.Mi, W.P, W.Lr, W.Li, W.Q);
+    for (int i = 0; i < 4; ++i) W.ab[i] = AB_COEF[W.A - 1][i];
+    double qm = q / mass, qw = q * w;
+    int status = 0;
+    int nth = nthreads > 1 ? nthreads : 1;
+#ifndef _OPENMP
+    nth = 1;
+#endif
+    size_t stride = (size_t)m->ne + (rho ? m->nv : 0);
+    double *priv = (double *)calloc((size_t)nth * stride, sizeof(double));
+#ifdef _OPENMP
+    #pragma omp parallel num_threads(nth) reduction(min:status)
+#endif
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *mydG = priv + (size_t)tid * stride;
+        double *myrho = rho ? mydG + m->ne : NULL;
+#ifdef _OPENMP
+        #pragma omp for schedule(static)
+#endif
+        for (int64_t p = 0; p < n; ++p) {
+            ora_particle P;
+            double vh[3][3], es[2][9], bs[2][9];
+            P.tet = tet[p];
+            P.lam[1] = lam[3 * p]; P.lam[2] = lam[3 * p + 1]; P.lam[3] = lam[3 * p + 2];
+            P.lam[0] = 1.0 - P.lam[1] - P.lam[2] - P.lam[3];
+            for (int c = 0; c < 3; ++c) P.v[c] = vel[3 * p + c];
+            for (int j = 0; j < 3; ++j)
+                for (int c = 0; c < 3; ++c) vh[j][c] = vhist[9 * p + 3 * j + c];
+            for (int k = 0; k < 2; ++k)
+                for (int i = 0; i < 9; ++i) { es[k][i] = esamp[18 * p + 9 * k + i]; bs[k][i] = bsamp[18 * p + 9 * k + i]; }
+            ds_step_one(m, &P, vh, es, bs, &W, &F, qm, h, qw, mydG);
+            tet[p] = (int32_t)P.tet;
+            lam[3 * p] = P.lam[1]; lam[3 * p + 1] = P.lam[2]; lam[3 * p + 2] = P.lam[3];
+            for (int c = 0; c < 3; ++c) vel[3 * p + c] = P.v[c];
+            for (int j = 0; j < 3; ++j)
+                for (int c = 0; c < 3; ++c) vhist[9 * p + 3 * j + c] = vh[j][c];
+            for (int k = 0; k < 2; ++k)
+                for (int i = 0; i < 9; ++i) { esamp[18 * p + 9 * k + i] = es[k][i]; bsamp[18 * p + 9 * k + i] = bs[k][i]; }
+            if (P.status) status = P.status;
+            if (myrho) {
+                const int32_t *v = m->tv + 4 * P.tet;
+                for (int k = 0; k < 4; ++k) myrho[v[k]] += qw * P.lam[k];
+            }
+        }
+    }
+    for (int th = 0; th < nth; ++th) {
+        double *mydG = priv + (size_t)th * stride;
+        for (int64_t e = 0; e < m->ne; ++e) dG[e] += mydG[e];
+        if (rho) for (int64_t k = 0; k < m->nv; ++k) rho[k] += mydG[m->ne + k];
+    }
+    free(priv);
     return status;
 }

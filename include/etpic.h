@@ -30,11 +30,14 @@
  * Ownership: the library owns the context state (status word, walk queues,
  * reduction words, allocated in etpic_create), the mesh tables, per-step
  * coefficient table and sort counters (etpic_mesh_upload, replaced by the next
- * upload) and the field-update matrices and work vectors (etpic_field_setup);
- * etpic_destroy frees them all.  Particle arrays, field DoFs, outputs and the
- * adjoint workspace are device buffers owned by the caller; they must stay
- * valid until the work queued on `stream` has finished.  No other entry point
- * allocates device memory (ETPIC_STEP_TIMING creates HIP events on first use).
+ * upload) and the field-update matrices and work vectors (etpic_field_setup),
+ * and the complex-envelope rows of the downshifted step (72 float64 per tet,
+ * allocated by the first etpic_ds_steps call after a mesh upload);
+ * etpic_destroy frees them all.  Particle arrays, field DoFs, outputs, the
+ * adjoint workspace and the downshifted history are device buffers owned by
+ * the caller; they must stay valid until the work queued on `stream` has
+ * finished.  No other entry point allocates device memory
+ * (ETPIC_STEP_TIMING creates HIP events on first use).
  *
  * Errors: every entry point returns an etpic status (0 = OK).  On failure the
  * message is available from etpic_last_error() (thread-local).  Errors found
@@ -265,6 +268,47 @@ int etpic_vertex_charge(etpic_ctx *ctx, const etpic_particles *p, const etpic_sp
  * out_host[1] = max|rho_old|. */
 int etpic_gauss_residual(etpic_ctx *ctx, const double *dG, const double *rho_new, const double *rho_old,
                          double out_host[2], void *stream);
+
+/* ---- Downshifted integrator (float64) --------------------------------------
+ * The Particle Push section's scheme that treats the carrier analytically in
+ * the velocity update.  Over a step [t_n, t_n + dt] the envelope fields sampled
+ * at the particle (E~, B~ from the Whitney expansions, and the dc DoFs) and the
+ * velocity are interpolated in time by the Lagrange basis N_k on the nodes
+ * t_n, t_{n-1}, t_{n-2}, and the carrier is integrated exactly against them:
+ *   v^{n+1} = v^n + q/m sum_k (Re E~_k M^r_k + Im E~_k M^i_k + Edc_k P_k)
+ *           + q/m sum_{j,k} v^{n-j} x (Re B~_k L^r_jk + Im B~_k L^i_jk + Bdc_k Q_jk),
+ * M^r_k = int N_k cos(wt), M^i_k = -int N_k sin(wt), L^r_jk = int N_j N_k
+ * cos(wt), L^i_jk = -int N_j N_k sin(wt) (the section's operators), P_k = int
+ * N_k, Q_jk = int N_j N_k over the step.  Positions advance by the
+ * fourth-order Adams-Bashforth stencil in the velocities (eq. newtons); the
+ * path r^n -> r^{n+1} is walked and deposited exactly as in
+ * etpic_gather_push_deposit (same dG, rho and continuity law).  At a wall the
+ * velocity and the velocity samples kept for later steps are mirrored.  With
+ * fewer than three earlier downshifted steps the orders ramp up: K =
+ * min(hist, 2) + 1 nodes and Adams-Bashforth order min(hist, 3) + 1. */
+
+/* Size of the history buffer for n particles: 48 float64 arrays of length n
+ * (velocity ring v^m in slot m mod 4; E and B samples, real part, imaginary
+ * part and dc part, of step m in slot m mod 2).  Host only. */
+int etpic_ds_history_bytes(int64_t n, size_t *bytes_out);
+
+/* nsteps downshifted steps from step0 (t_n = n dt) with fixed field DoFs.
+ * p: particles, p->vel = v^n in, v^{n+nsteps} out; precision must be
+ * ETPIC_FP64 (EINVAL otherwise).  hist: the history
+ * buffer (device, 8-byte aligned, at least etpic_ds_history_bytes), whose
+ * slots are addressed by the step number, so successive calls must continue
+ * the numbering; hist0 = number of downshifted steps already taken with this
+ * buffer (0 for a fresh start: the buffer is then not read).  A re-sort of the
+ * particles (etpic_sort) does not move the history: restart with hist0 = 0
+ * after one.  dG accumulates the deposit of all steps, rho (if not NULL)
+ * receives q w lam_k after the last one.  flags as for
+ * etpic_gather_push_deposit (XCD_REMAP, TIMING, WALK_BY_SLICE).  The first
+ * call after a mesh upload allocates the complex-envelope rows.
+ * Asynchronous on `stream`.  Errors: EINVAL, ESTATE, EHIP; in-kernel errors
+ * via etpic_check. */
+int etpic_ds_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, double *hist, size_t hist_bytes,
+                   const etpic_species *sp, const etpic_fields *f, int64_t step0, int nsteps, int hist0, double dt,
+                   double omega, double *dG, double *rho, uint32_t flags, void *stream);
 
 /* ---- Differentiation (float64 form only) --------------------------------
  * Reverse-mode derivative of nsteps particle steps with respect to the

@@ -33,6 +33,7 @@
 #include <vector>
 #include <array>
 #include <algorithm>
+#include <complex>
 
 #include "etpic.h"
 #include "field_host.hpp"
@@ -324,8 +325,11 @@ __device__ __forceinline__ void deposit_piece(double *__restrict__ dG, const Tet
 // With kTrack (used by the adjoint) nothing is deposited and R accumulates the
 // linear part of the step's reflections (R <- (I - 2 n n^T) R per wall hit):
 // the end point is R (x + dt v) + const and the stored velocity is R v.
-template <typename Real, bool kTrack>
-__device__ __forceinline__ int walk(const StepArgs<Real> &a, int T, double l[4], double d[3], Real v[3], double *R) {
+// kExtra further vectors ext[0..kExtra-1] (the velocity samples a multistep
+// integrator keeps) are reflected with the velocity at a wall.
+template <typename Real, bool kTrack, int kExtra = 0>
+__device__ __forceinline__ int walk(const StepArgs<Real> &a, int T, double l[4], double d[3], Real v[3], double *R,
+                                   double (*ext)[3] = nullptr) {
     int hops = 0;
     for (;;) {
         const double *gp = a.grad + (int64_t)T * 12;
@@ -391,6 +395,12 @@ __device__ __forceinline__ int walk(const StepArgs<Real> &a, int T, double l[4],
             for (int c = 0; c < 3; ++c) {
                 d[c] -= 2.0 * dd * nh[c];
                 v[c] -= (Real)2 * vv * (Real)nh[c];
+            }
+#pragma unroll
+            for (int i = 0; i < kExtra; ++i) {
+                const double xv = ext[i][0] * nh[0] + ext[i][1] * nh[1] + ext[i][2] * nh[2];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) ext[i][c] -= 2.0 * xv * nh[c];
             }
             if (kTrack) {
 #pragma unroll
@@ -734,25 +744,25 @@ __device__ __forceinline__ void walk_particle(const StepArgs<Real> &a, int64_t p
 // Walks the queued particles, one lane each, then the particles of the
 // overflow slices, one wavefront per slice.  The last block to finish resets
 // the counters for the next step.
-template <typename Real>
-__device__ __forceinline__ void walk_queued(const StepArgs<Real> &a, unsigned blk, unsigned nblk) {
+template <typename Real, typename WalkOne>
+__device__ __forceinline__ void walk_queued(const StepArgs<Real> &a, unsigned blk, unsigned nblk, WalkOne walk_one) {
     const unsigned total = __atomic_load_n(&a.walk_ctr[0], __ATOMIC_RELAXED);
     if (a.scatter && (a.walk_by_slice || total > kWalkQueueCap)) {
         // after a scatter step whose walkers did not all fit in the queue:
         // every marked particle, found by a scan (one lane per particle)
         for (int64_t p = (int64_t)blk * kBlock + threadIdx.x; p < a.n; p += (int64_t)nblk * kBlock)
-            walk_particle(a, p);
+            walk_one(p);
     } else {
         const unsigned count = min(total, kWalkQueueCap);
         for (unsigned i = blk * kBlock + threadIdx.x; i < count; i += nblk * kBlock) {
             const unsigned q = a.walk_queue[i];
-            if (q != kQueueSkip && (int64_t)q < a.n) walk_particle(a, (int64_t)q);
+            if (q != kQueueSkip && (int64_t)q < a.n) walk_one((int64_t)q);
         }
         const unsigned slices = __atomic_load_n(&a.walk_ctr[2], __ATOMIC_RELAXED);
         const unsigned wpb = kBlock / 64;
         for (unsigned i = blk * wpb + (threadIdx.x >> 6); i < slices; i += nblk * wpb) {
             const int64_t p = (int64_t)a.slice_queue[i] * 64 + (threadIdx.x & 63);
-            if (p < a.n) walk_particle(a, p);
+            if (p < a.n) walk_one(p);
         }
     }
     __syncthreads();
@@ -768,7 +778,7 @@ __device__ __forceinline__ void walk_queued(const StepArgs<Real> &a, unsigned bl
 
 template <typename Real>
 __global__ void __launch_bounds__(kBlock) k_walk(StepArgs<Real> a) {
-    walk_queued(a, blockIdx.x, gridDim.x);
+    walk_queued(a, blockIdx.x, gridDim.x, [&](int64_t p) { walk_particle(a, p); });
 }
 
 // The walk of one step and the coefficient pass of the next in one launch:
@@ -781,9 +791,320 @@ __global__ void __launch_bounds__(kBlock) k_walk(StepArgs<Real> a) {
 template <typename Real, int kSnap>
 __global__ void __launch_bounds__(kBlock) k_walk_coef(StepArgs<Real> a, int64_t nt, FieldPtrs F) {
     if (blockIdx.x < kWalkBlocks)
-        walk_queued(a, blockIdx.x, kWalkBlocks);
+        walk_queued(a, blockIdx.x, kWalkBlocks, [&](int64_t p) { walk_particle(a, p); });
     else
         tet_coef<Real, kSnap>(nt, a.gpush64, a.tetface, F, const_cast<Real *>(a.coef), blockIdx.x - kWalkBlocks);
+}
+
+// ------------------------------------------------------------------ downshifted step
+// The Particle Push section's other scheme: the velocity update integrates the
+// carrier exactly against the envelope fields and velocities sampled along the
+// trajectory and interpolated in time (Lagrange basis N_k on the nodes t_n,
+// t_{n-1}, t_{n-2}):
+//   v^{n+1} = v^n + q/m sum_k (Re E_k M^r_k + Im E_k M^i_k + Edc_k P_k)
+//           + q/m sum_{j,k} v^{n-j} x (Re B_k L^r_jk + Im B_k L^i_jk + Bdc_k Q_jk),
+// the positions advance by the Adams-Bashforth stencil in the velocities
+// (eq. newtons), and the path is walked and deposited as in the fine-step
+// scheme.  The weights M, L, P, Q of a step are computed on the host.
+//
+// The envelope samples need the complex per-tet coefficients (Re, Im and dc
+// parts separately, the carrier being applied by the weights): rows of 72
+// reals per tet, A_re, A_im, A_dc, C_re, C_im, C_dc, each 4 x 3 (A_k at 3k),
+// built once per call since the fields are fixed within it.
+constexpr int kEnvRow = 72;
+
+__global__ void __launch_bounds__(kBlock) k_tet_coef_env(int64_t nt, const double *__restrict__ prow,
+                                                         const int32_t *__restrict__ tetface, FieldPtrs F,
+                                                         double *__restrict__ out) {
+    // blockIdx.y: 0..2 the edge rows (Re, Im, dc), 3..5 the face rows
+    const int part = blockIdx.y;
+    const int64_t T = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (T >= nt) return;
+    const double *row = prow + T * PushRow<double>::kStride;
+    double g[4][3];
+#pragma unroll
+    for (int k = 1; k < 4; ++k)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) g[k][d] = row[3 * (k - 1) + d];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) g[0][d] = -(g[1][d] + g[2][d] + g[3][d]);
+    int32_t tp[10];
+    const int32_t *re = reinterpret_cast<const int32_t *>(row + PushRow<double>::kEdges);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) tp[k] = re[k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) tp[6 + k] = tetface[4 * T + k];
+    // the same expansions as the per-step coefficients, with (c, s) selecting
+    // the real part (1, 0), the imaginary part (0, -1) or neither (0, 0), and
+    // the dc DoFs kept only for the dc rows
+    const int which = part % 3;
+    FieldPtrs G = F;
+    G.c = which == 0 ? 1.0 : 0.0;
+    G.s = which == 1 ? -1.0 : 0.0;
+    if (which != 2) {
+        G.e_dc = nullptr;
+        G.b_dc = nullptr;
+    }
+    double o[12];
+    if (part < 3) {
+        coef_A<0, 1>(tp, g, G, o);
+        coef_A<1, 1>(tp, g, G, o + 3);
+        coef_A<2, 1>(tp, g, G, o + 6);
+        coef_A<3, 1>(tp, g, G, o + 9);
+    } else {
+        coef_C<0, 1>(tp, g, G, o);
+        coef_C<1, 1>(tp, g, G, o + 3);
+        coef_C<2, 1>(tp, g, G, o + 6);
+        coef_C<3, 1>(tp, g, G, o + 9);
+    }
+    double *dst = out + T * kEnvRow + 12 * part;
+#pragma unroll
+    for (int d = 0; d < 12; ++d) dst[d] = o[d];
+}
+
+// History of the downshifted integrator: 48 float64 arrays of length n in one
+// caller-owned buffer, array i at hist + i * n.  Arrays 0..11: velocity ring,
+// v^m in slot m mod 4 (components 3 slot + c); 12..29: E samples, the sample of
+// step m in slot m mod 2 (12 + 9 slot + i, i = Re 0..2, Im 3..5, dc 6..8);
+// 30..47: B samples likewise.
+constexpr int kDsArrays = 48;
+
+struct DsArgs {
+    const double *coef_env;   // nt * kEnvRow
+    double *hist;
+    int64_t stride;           // n
+    int vin[3];               // ring slots of v^{n-1}, v^{n-2}, v^{n-3} (-1: not used)
+    int vout;                 // slot that receives v^n
+    int sin_[2];              // sample slots of t_{n-1}, t_{n-2} (-1: not used)
+    int sout;                 // slot that receives the sample of t_n
+    int K, A;                 // interpolation nodes, Adams-Bashforth order
+    double Mr[3], Mi[3], P[3], Lr[9], Li[9], Q[9];
+    double ab[4];             // Adams-Bashforth coefficients times the step
+    double qm;
+};
+
+__device__ __forceinline__ double *ds_v(const DsArgs &d, int slot, int c) { return d.hist + (3 * slot + c) * d.stride; }
+__device__ __forceinline__ double *ds_e(const DsArgs &d, int slot, int i) { return d.hist + (12 + 9 * slot + i) * d.stride; }
+__device__ __forceinline__ double *ds_b(const DsArgs &d, int slot, int i) { return d.hist + (30 + 9 * slot + i) * d.stride; }
+
+template <bool kRho>
+__global__ void __launch_bounds__(kBlock) k_push_ds(StepArgs<double> a, DsArgs d, int remap) {
+    unsigned blk = blockIdx.x;
+    if (remap) {
+        const unsigned G = gridDim.x, q = G / 8, r = G % 8, x = blk % 8, j = blk / 8;
+        blk = x * q + min(x, r) + j;
+    }
+    const int ln = threadIdx.x & 63;
+    const int64_t p = (int64_t)blk * kBlock + threadIdx.x;
+    const int64_t slice = p >> 6;
+    int T = -1;
+    if (p < a.n) {
+        T = a.tet[p];
+        if ((unsigned)T >= (unsigned)a.nt) {
+            atomicOr(a.status, (unsigned)ETPIC_DEV_BADTET);
+            T = -1;
+        }
+    }
+    const bool act = T >= 0;
+    double g6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double r4[4] = {0.0, 0.0, 0.0, 0.0};
+    int walker = 0;
+    if (act) {
+        double l[4];
+        l[1] = a.lam1[p];
+        l[2] = a.lam2[p];
+        l[3] = a.lam3[p];
+        l[0] = 1.0 - l[1] - l[2] - l[3];
+        // samples at t_n: sum_k lam_k of the tet's rows
+        const double *row = d.coef_env + (int64_t)T * kEnvRow;
+        double S[6][3];   // E re, im, dc; B re, im, dc
+#pragma unroll
+        for (int part = 0; part < 6; ++part)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                S[part][c] = l[0] * row[12 * part + c] + l[1] * row[12 * part + 3 + c] +
+                             l[2] * row[12 * part + 6 + c] + l[3] * row[12 * part + 9 + c];
+        double V[4][3];
+        V[0][0] = a.v0[p];
+        V[0][1] = a.v1[p];
+        V[0][2] = a.v2[p];
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) V[j + 1][c] = d.vin[j] >= 0 ? ds_v(d, d.vin[j], c)[p] : 0.0;
+        double acc[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[c] = S[0][c] * d.Mr[0] + S[1][c] * d.Mi[0] + S[2][c] * d.P[0];
+#pragma unroll
+        for (int k = 1; k < 3; ++k) {
+            if (k >= d.K) break;
+            const int sl = d.sin_[k - 1];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                acc[c] += ds_e(d, sl, c)[p] * d.Mr[k] + ds_e(d, sl, 3 + c)[p] * d.Mi[k] + ds_e(d, sl, 6 + c)[p] * d.P[k];
+        }
+        // magnetic part: sum_k (weighted B sample k) crossed with each v^{n-j}
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (k >= d.K) break;
+            double Bk[3][3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (k == 0) {
+                    Bk[0][c] = S[3][c];
+                    Bk[1][c] = S[4][c];
+                    Bk[2][c] = S[5][c];
+                } else {
+                    const int sl = d.sin_[k - 1];
+                    Bk[0][c] = ds_b(d, sl, c)[p];
+                    Bk[1][c] = ds_b(d, sl, 3 + c)[p];
+                    Bk[2][c] = ds_b(d, sl, 6 + c)[p];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                if (j >= d.K) break;
+                const int jk = j * d.K + k;
+                double Bw[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) Bw[c] = Bk[0][c] * d.Lr[jk] + Bk[1][c] * d.Li[jk] + Bk[2][c] * d.Q[jk];
+                acc[0] += V[j][1] * Bw[2] - V[j][2] * Bw[1];
+                acc[1] += V[j][2] * Bw[0] - V[j][0] * Bw[2];
+                acc[2] += V[j][0] * Bw[1] - V[j][1] * Bw[0];
+            }
+        }
+        double vn[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) vn[c] = V[0][c] + d.qm * acc[c];
+        if (!(isfinite(vn[0]) && isfinite(vn[1]) && isfinite(vn[2]))) atomicOr(a.status, (unsigned)ETPIC_DEV_NAN);
+        // history of the next steps: v^n and the samples of t_n
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ds_v(d, d.vout, c)[p] = V[0][c];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            ds_e(d, d.sout, c)[p] = S[0][c];
+            ds_e(d, d.sout, 3 + c)[p] = S[1][c];
+            ds_e(d, d.sout, 6 + c)[p] = S[2][c];
+            ds_b(d, d.sout, c)[p] = S[3][c];
+            ds_b(d, d.sout, 3 + c)[p] = S[4][c];
+            ds_b(d, d.sout, 6 + c)[p] = S[5][c];
+        }
+        // Adams-Bashforth displacement and its barycentric increments
+        double dx[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (i >= d.A) break;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) dx[c] += d.ab[i] * V[i][c];
+        }
+        const double *gr = a.gpush + (int64_t)T * PushRow<double>::kStride;
+        double dl[4];
+#pragma unroll
+        for (int k = 1; k < 4; ++k) dl[k] = gr[3 * k - 3] * dx[0] + gr[3 * k - 2] * dx[1] + gr[3 * k - 1] * dx[2];
+        dl[0] = -(dl[1] + dl[2] + dl[3]);
+        const bool stays = (l[0] + dl[0] >= 0.0) && (l[1] + dl[1] >= 0.0) && (l[2] + dl[2] >= 0.0) &&
+                           (l[3] + dl[3] >= 0.0);
+        if (stays) {
+            double m[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) m[k] = l[k] + 0.5 * dl[k];
+            constexpr int le[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+#pragma unroll
+            for (int e = 0; e < 6; ++e) g6[e] = m[le[e][0]] * dl[le[e][1]] - m[le[e][1]] * dl[le[e][0]];
+#pragma unroll
+            for (int k = 1; k < 4; ++k) l[k] += dl[k];
+            a.lam1[p] = l[1];
+            a.lam2[p] = l[2];
+            a.lam3[p] = l[3];
+            if (kRho) {
+                r4[0] = 1.0 - l[1] - l[2] - l[3];
+                r4[1] = l[1];
+                r4[2] = l[2];
+                r4[3] = l[3];
+            }
+        } else {
+            a.tet[p] = walker_mark(T);
+            walker = 1;
+        }
+        a.v0[p] = vn[0];
+        a.v1[p] = vn[1];
+        a.v2[p] = vn[2];
+    }
+    const WaveRuns runs = wave_runs(T, ln);
+#pragma unroll
+    for (int e = 0; e < 6; ++e) g6[e] = run_total(g6[e], runs);
+    if (kRho) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) r4[k] = run_total(r4[k], runs);
+    }
+    if (act && runs.lane == runs.run_end) flush_run<double, kRho>(a, T, g6, r4);
+    // walkers to the particle queue, or their slice when it is full
+    const unsigned long long wmask = __ballot(walker);
+    if (wmask) {
+        const unsigned cnt = (unsigned)__popcll(wmask);
+        unsigned base = 0;
+        if (ln == 0) base = atomicAdd(&a.walk_ctr[0], cnt);
+        base = __shfl(base, 0);
+        const bool fits = !a.walk_by_slice && base < kWalkQueueCap && cnt <= kWalkQueueCap - base;
+        const unsigned rank = (unsigned)__popcll(wmask & ((1ull << ln) - 1ull));
+        if (walker && base + rank < kWalkQueueCap) a.walk_queue[base + rank] = fits ? (unsigned)p : kQueueSkip;
+        if (!fits && ln == 0) a.slice_queue[atomicAdd(&a.walk_ctr[2], 1u)] = (unsigned)slice;
+    }
+}
+
+// Walk of a marked particle of a downshifted step: the Adams-Bashforth
+// displacement is rebuilt from the ring (v^n is in its slot by now, the older
+// samples are untouched), and at a wall the velocity samples the next steps
+// use (v^n, v^{n-1}, v^{n-2}) are mirrored with v^{n+1}.
+__device__ __forceinline__ void walk_particle_ds(const StepArgs<double> &a, const DsArgs &d, int64_t p) {
+    const int marked = a.tet[p];
+    if (marked > -2) return;
+    int T = walker_tet(marked);
+    if (T >= a.nt) return;
+    double l[4];
+    l[1] = a.lam1[p];
+    l[2] = a.lam2[p];
+    l[3] = a.lam3[p];
+    l[0] = 1.0 - l[1] - l[2] - l[3];
+    int slot[4] = {d.vout, d.vin[0], d.vin[1], d.vin[2]};
+    double V[4][3];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) V[i][c] = slot[i] >= 0 ? ds_v(d, slot[i], c)[p] : 0.0;
+    double dx[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (i >= d.A) break;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dx[c] += d.ab[i] * V[i][c];
+    }
+    double v[3] = {a.v0[p], a.v1[p], a.v2[p]};
+    T = walk<double, false, 3>(a, T, l, dx, v, nullptr, V);
+    a.tet[p] = T;
+    a.lam1[p] = l[1];
+    a.lam2[p] = l[2];
+    a.lam3[p] = l[3];
+    a.v0[p] = v[0];
+    a.v1[p] = v[1];
+    a.v2[p] = v[2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        if (slot[i] >= 0)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ds_v(d, slot[i], c)[p] = V[i][c];
+    if (a.rho) {
+        const TetTopo tp = a.topo[T];
+        const double l0 = 1.0 - l[1] - l[2] - l[3];
+        unsafeAtomicAdd(&a.rho[tp.v[0]], a.qw * l0);
+        unsafeAtomicAdd(&a.rho[tp.v[1]], a.qw * l[1]);
+        unsafeAtomicAdd(&a.rho[tp.v[2]], a.qw * l[2]);
+        unsafeAtomicAdd(&a.rho[tp.v[3]], a.qw * l[3]);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_walk_ds(StepArgs<double> a, DsArgs d) {
+    walk_queued(a, blockIdx.x, gridDim.x, [&](int64_t p) { walk_particle_ds(a, d, p); });
 }
 
 // ------------------------------------------------------------------ adjoint step
@@ -1661,6 +1982,7 @@ struct etpic_ctx {
     float *d_gpush32 = nullptr;       // nt rows of PushRow<float>
     int32_t *d_tetface = nullptr;     // nt*4 face ids (face k opposite vertex k)
     void *d_coef = nullptr;          // nt*24 doubles (float table uses the first half)
+    double *d_coef_env = nullptr;    // nt*kEnvRow complex-envelope rows (first downshifted call)
     int32_t *d_v2e_ptr = nullptr;
     int32_t *d_v2e_code = nullptr;
     double *d_xyz = nullptr;         // 3*nv vertex coordinates
@@ -1922,6 +2244,139 @@ struct etpic_ctx {
         return s;
     }
 
+    // nsteps downshifted steps from step0 (t_n = n dt), hist0 of them taken
+    // before; the complex-envelope rows are built once for the call.
+    int ds_steps(const etpic_particles *p, double *hist, const etpic_species *sp, const etpic_fields *f,
+                 int64_t step0, int nsteps, int hist0, double dt, double omega, double *dG, double *rho,
+                 uint32_t flags, void *stream) {
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        const int remap = (flags & ETPIC_STEP_XCD_REMAP) ? 1 : 0;
+        const int64_t n = p->n, nt = host.nt;
+        if (!d_coef_env) HIP_TRY(hipMalloc(&d_coef_env, sizeof(double) * kEnvRow * nt));
+        hipEvent_t *ev = nullptr;
+        if (flags & ETPIC_STEP_TIMING) {
+            if (int r = timing_events(&ev)) return r;
+            HIP_TRY(hipEventRecord(ev[0], st));
+        }
+        {
+            const etpic_fields *snap[3] = {f, nullptr, nullptr};
+            const double w1[3] = {1.0, 0.0, 0.0};
+            const FieldPtrs F = field_ptrs(snap, w1, 1.0, 0.0);
+            k_tet_coef_env<<<dim3(grid_for(nt), 6), kBlock, 0, st>>>(nt, d_gpush64, d_tetface, F, d_coef_env);
+            HIP_TRY(hipGetLastError());
+        }
+        if (ev) HIP_TRY(hipEventRecord(ev[1], st));
+        for (int j = 0; j < nsteps; ++j) {
+            const int64_t sn = step0 + j;
+            const int H = hist0 + j;
+            StepArgs<double> a = step_args<double>(p, sp, dt, dG, j == nsteps - 1 ? rho : nullptr);
+            a.walk_by_slice = (flags & ETPIC_STEP_WALK_BY_SLICE) ? 1 : 0;
+            DsArgs d{};
+            d.coef_env = d_coef_env;
+            d.hist = hist;
+            d.stride = n;
+            d.K = std::min(H, 2) + 1;
+            d.A = std::min(H, 3) + 1;
+            auto mod = [](int64_t x, int m) { return (int)(((x % m) + m) % m); };
+            for (int i = 0; i < 3; ++i) d.vin[i] = i < H ? mod(sn - 1 - i, 4) : -1;
+            d.vout = mod(sn, 4);
+            for (int i = 0; i < 2; ++i) d.sin_[i] = i < H ? mod(sn - 1 - i, 2) : -1;
+            d.sout = mod(sn, 2);
+            ds_weights(d.K, (double)sn * dt, dt, omega, d);
+            d.qm = sp->q / sp->m;
+            if (ev) HIP_TRY(hipEventRecord(ev[2], st));
+            if (a.rho)
+                k_push_ds<true><<<grid_for(n), kBlock, 0, st>>>(a, d, remap);
+            else
+                k_push_ds<false><<<grid_for(n), kBlock, 0, st>>>(a, d, remap);
+            HIP_TRY(hipGetLastError());
+            if (ev) HIP_TRY(hipEventRecord(ev[3], st));
+            k_walk_ds<<<kWalkBlocks, kBlock, 0, st>>>(a, d);
+            HIP_TRY(hipGetLastError());
+            if (ev) {
+                HIP_TRY(hipEventRecord(ev[4], st));
+                if (j + 1 < nsteps) {
+                    if (int r = timing_events(&ev)) return r;
+                    HIP_TRY(hipEventRecord(ev[0], st));
+                    HIP_TRY(hipEventRecord(ev[1], st));
+                }
+            }
+        }
+        return ETPIC_OK;
+    }
+
+    // Weights of one downshifted step [t0, t0 + h] with K Lagrange nodes at
+    // t0, t0 - h, t0 - 2h, in closed form: with s = (t - t0) / h the basis
+    // polynomials have the monomial coefficients below, and
+    // J_p = int_0^1 s^p e^{j theta s} ds (theta = w h) comes from its power
+    // series for |theta| < 1 and from the integration-by-parts recurrence
+    // J_p = (e^{j theta} - p J_{p-1}) / (j theta) above.
+    static void ds_weights(int K, double t0, double h, double omega, DsArgs &d) {
+        using cplx = std::complex<double>;
+        double cf[3][3] = {{0.0}};
+        if (K == 1) {
+            cf[0][0] = 1.0;
+        } else if (K == 2) {
+            cf[0][0] = 1.0, cf[0][1] = 1.0;      // 1 + s
+            cf[1][1] = -1.0;                     // -s
+        } else {
+            cf[0][0] = 1.0, cf[0][1] = 1.5, cf[0][2] = 0.5;   // (s + 1)(s + 2) / 2
+            cf[1][1] = -2.0, cf[1][2] = -1.0;                 // -s (s + 2)
+            cf[2][1] = 0.5, cf[2][2] = 0.5;                   // s (s + 1) / 2
+        }
+        const double th = omega * h;
+        cplx J[5];
+        const cplx jt(0.0, th);
+        if (std::fabs(th) < 1.0) {
+            for (int q = 0; q < 5; ++q) {
+                cplx sum = 0.0, term = 1.0;   // (j theta)^m / m!
+                for (int m = 0; m < 30; ++m) {
+                    sum += term / (double)(q + m + 1);
+                    term *= jt / (double)(m + 1);
+                }
+                J[q] = sum;
+            }
+        } else {
+            const cplx e = std::exp(jt);
+            J[0] = (e - 1.0) / jt;
+            for (int q = 1; q < 5; ++q) J[q] = (e - (double)q * J[q - 1]) / jt;
+        }
+        const cplx ph(std::cos(omega * t0), std::sin(omega * t0));
+        for (int k = 0; k < 3; ++k) d.Mr[k] = d.Mi[k] = d.P[k] = 0.0;
+        for (int k = 0; k < 9; ++k) d.Lr[k] = d.Li[k] = d.Q[k] = 0.0;
+        for (int k = 0; k < K; ++k) {
+            cplx mu = 0.0;
+            double pk = 0.0;
+            for (int q = 0; q < 3; ++q) {
+                mu += cf[k][q] * J[q];
+                pk += cf[k][q] / (q + 1);
+            }
+            mu *= h * ph;
+            d.Mr[k] = mu.real();
+            d.Mi[k] = -mu.imag();
+            d.P[k] = h * pk;
+            for (int jj = 0; jj < K; ++jj) {
+                cplx la = 0.0;
+                double qk = 0.0;
+                for (int q1 = 0; q1 < 3; ++q1)
+                    for (int q2 = 0; q2 < 3; ++q2) {
+                        la += cf[jj][q1] * cf[k][q2] * J[q1 + q2];
+                        qk += cf[jj][q1] * cf[k][q2] / (q1 + q2 + 1);
+                    }
+                la *= h * ph;
+                d.Lr[jj * K + k] = la.real();
+                d.Li[jj * K + k] = -la.imag();
+                d.Q[jj * K + k] = h * qk;
+            }
+        }
+        static const double kAB[4][4] = {{1.0, 0.0, 0.0, 0.0},
+                                         {1.5, -0.5, 0.0, 0.0},
+                                         {23.0 / 12.0, -16.0 / 12.0, 5.0 / 12.0, 0.0},
+                                         {55.0 / 24.0, -59.0 / 24.0, 37.0 / 24.0, -9.0 / 24.0}};
+        const int A = d.A;
+        for (int i = 0; i < 4; ++i) d.ab[i] = h * kAB[A - 1][i];
+    }
+
     void release() {
         (void)hipFree(d_topo);
         (void)hipFree(d_grad64);
@@ -1929,6 +2384,7 @@ struct etpic_ctx {
         (void)hipFree(d_gpush32);
         (void)hipFree(d_tetface);
         (void)hipFree(d_coef);
+        (void)hipFree(d_coef_env);
         (void)hipFree(d_v2e_ptr);
         (void)hipFree(d_v2e_code);
         (void)hipFree(d_xyz);
@@ -1941,6 +2397,7 @@ struct etpic_ctx {
         d_gpush32 = nullptr;
         d_tetface = nullptr;
         d_coef = nullptr;
+        d_coef_env = nullptr;
         d_v2e_ptr = d_v2e_code = nullptr;
         d_xyz = nullptr;
         d_grid = nullptr;
@@ -2287,6 +2744,28 @@ int etpic_sort_run_steps(etpic_ctx *ctx, const etpic_particles *src, const etpic
     if (precision == ETPIC_FP64)
         return ctx->run_steps<double>(dst, sp, plans.data(), nsteps, dt, omega, dG, rho, flags, stream, src);
     return ctx->run_steps<float>(dst, sp, plans.data(), nsteps, dt, omega, dG, rho, flags, stream, src);
+}
+
+int etpic_ds_history_bytes(int64_t n, size_t *bytes_out) {
+    if (!bytes_out || n < 0) return fail(ETPIC_EINVAL, "bad arguments");
+    *bytes_out = sizeof(double) * (size_t)kDsArrays * (size_t)n;
+    return ETPIC_OK;
+}
+
+int etpic_ds_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, double *hist, size_t hist_bytes,
+                   const etpic_species *sp, const etpic_fields *f, int64_t step0, int nsteps, int hist0, double dt,
+                   double omega, double *dG, double *rho, uint32_t flags, void *stream) {
+    if (int r = check_step_args(ctx, sp, f, dt, omega)) return r;
+    if (!dG) return fail(ETPIC_EINVAL, "null current accumulator");
+    if (int r = check_particles(ctx, p)) return r;
+    if (nsteps < 1 || hist0 < 0) return fail(ETPIC_EINVAL, "need nsteps >= 1 and hist0 >= 0");
+    if (precision != ETPIC_FP64) return fail(ETPIC_EINVAL, "the downshifted step takes float64 particles");
+    if (!hist || hist_bytes < sizeof(double) * (size_t)kDsArrays * (size_t)p->n)
+        return fail(ETPIC_EINVAL, "history buffer missing or smaller than etpic_ds_history_bytes");
+    if ((reinterpret_cast<uintptr_t>(hist) & 7) != 0) return fail(ETPIC_EINVAL, "history buffer not 8-byte aligned");
+    if (p->n == 0) return ETPIC_OK;
+    if (int r = set_device(ctx)) return r;
+    return ctx->ds_steps(p, hist, sp, f, step0, nsteps, hist0, dt, omega, dG, rho, flags, stream);
 }
 
 int etpic_adjoint_workspace(const etpic_ctx *ctx, int64_t n, int nsteps, int checkpoint_every, size_t *bytes_out) {

@@ -32,7 +32,7 @@ EXPORTS = (
     "etpic_adjoint_workspace", "etpic_forward_checkpointed", "etpic_backward",
     "etpic_field_setup", "etpic_field_nnz", "etpic_field_spmv", "etpic_field_step",
     "etpic_particles_locate", "etpic_particles_positions", "etpic_coarse_step", "etpic_run_steps",
-    "etpic_sort_run_steps",
+    "etpic_sort_run_steps", "etpic_ds_history_bytes", "etpic_ds_steps",
 )
 
 
@@ -94,6 +94,9 @@ def lib():
     L.etpic_particles_positions.argtypes = [vp, C.POINTER(_Particles), C.c_void_p * 3, vp]
     L.etpic_run_steps.argtypes = [vp, C.POINTER(_Particles), C.c_int, C.POINTER(_Species), C.POINTER(_Fields),
                                   C.c_int64, C.c_int, C.c_double, C.c_double, vp, vp, C.c_uint32, vp]
+    L.etpic_ds_history_bytes.argtypes = [C.c_int64, C.POINTER(C.c_size_t)]
+    L.etpic_ds_steps.argtypes = [vp, C.POINTER(_Particles), C.c_int, vp, C.c_size_t, C.POINTER(_Species), C.POINTER(_Fields),
+                                 C.c_int64, C.c_int, C.c_int, C.c_double, C.c_double, vp, vp, C.c_uint32, vp]
     L.etpic_sort_run_steps.argtypes = [vp, C.POINTER(_Particles), C.POINTER(_Particles), C.c_int,
                                        C.POINTER(_Species), C.POINTER(_Fields), C.c_int64, C.c_int, C.c_double,
                                        C.c_double, vp, vp, C.c_uint32, vp]
@@ -342,6 +345,26 @@ class Context:
         _chk(lib().etpic_sort_run_steps(self._h, C.byref(a), C.byref(b), src.precision, C.byref(sp), C.byref(fd),
                                         int(step0), int(nsteps), float(dt), float(omega), _dptr(dG), _dptr(rho),
                                         int(flags), _stream(stream)))
+
+    # downshifted integrator (float64) --------------------------------------------
+    def ds_history(self, parts):
+        """A zeroed history buffer for parts (float64 [48, n] on the device)."""
+        import torch
+        b = C.c_size_t(0)
+        _chk(lib().etpic_ds_history_bytes(int(parts.n), C.byref(b)))
+        return torch.zeros((b.value // (8 * max(parts.n, 1)), parts.n), dtype=torch.float64, device="cuda")
+
+    def ds_steps(self, parts, hist, species, fields, step0, nsteps, hist0, dt, omega, dG, rho=None,
+                 flags=STEP_XCD_REMAP, stream=None):
+        """nsteps downshifted steps from step0 with hist0 earlier ones in hist."""
+        assert hist.is_contiguous() and hist.dtype.is_floating_point
+        d = parts.desc()
+        sp = species.c()
+        fd = fields.desc()
+        _chk(lib().etpic_ds_steps(self._h, C.byref(d), parts.precision, C.c_void_p(hist.data_ptr()),
+                                  hist.numel() * hist.element_size(), C.byref(sp), C.byref(fd), int(step0),
+                                  int(nsteps), int(hist0), float(dt), float(omega), _dptr(dG), _dptr(rho),
+                                  int(flags), _stream(stream)))
 
     def locate(self, xyz, parts, hint=None, stream=None, raise_on_error=True):
         """Locate the points xyz (float64 [3, N] on the device) into parts.tet /

@@ -216,6 +216,52 @@ def coarse_step_timing(E, torch, synth, ctx, w, fine=10, reps=5):
             "note": "float64, three envelope snapshots interpolated at every fine step; no sort inside"}
 
 
+DS_BYTES_PER_PARTICLE = 556   # float64 downshifted step without dc edge DoFs, see ds_step_timing
+DS_BYTES_PER_TET = 576 + 96    # complex-envelope rows and the push row
+
+
+def ds_step_timing(E, torch, ctx, w, nsteps=10, reps=3):
+    """Downshifted form (carrier-exact velocity quadrature of envelope samples
+    interpolated over three steps, Adams-Bashforth positions), float64, same
+    workload and step as the metric, particles sorted once, calls of `nsteps`
+    steps after a 3-step ramp.  Algorithmic bytes per particle-step of its
+    particle kernel: read tet 4, lam 24, v 24, three earlier velocities 72, two
+    E samples (Re, Im) 96, two B samples (Re, Im, dc) 144; write lam 24, v 24,
+    one velocity 24, one E sample 48, one B sample 72: 556 B."""
+    sp = E.Species(w.q, w.m, w.w)
+    f = E.Fields.from_numpy(w.e_env, w.b_env, None, w.b_dc)
+    parts = E.Particles.from_numpy(w.tet, w.lam, w.vel, w.ids)
+    spare = parts.empty_like()
+    ctx.sort(parts, spare)
+    parts = spare
+    hist = ctx.ds_history(parts)
+    dG = torch.zeros(ctx.n_edge, dtype=torch.float64, device="cuda")
+    ctx.ds_steps(parts, hist, sp, f, 0, 3, 0, w.dt, w.omega, dG)
+    torch.cuda.synchronize()
+    ctx.kernel_time(reset=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for r in range(reps):
+        ctx.ds_steps(parts, hist, sp, f, 3 + r * nsteps, nsteps, 3 + r * nsteps, w.dt, w.omega, dG,
+                     flags=E.STEP_XCD_REMAP | E.STEP_TIMING)
+    e1.record()
+    torch.cuda.synchronize()
+    kt, launches = ctx.kernel_time(reset=True)
+    ctx.check()
+    ms = e0.elapsed_time(e1) / (reps * nsteps)
+    push_ms = kt["push"] / max(kt["steps_push"], 1)
+    nbytes = DS_BYTES_PER_PARTICLE * parts.n + DS_BYTES_PER_TET * w.tet_vert.shape[0] + 16 * ctx.n_edge
+    ach = nbytes / (push_ms * 1e-3) / 1e9
+    del hist
+    return {"ms_per_step": ms, "value": parts.n / (ms * 1e-3), "push_ms": push_ms,
+            "walk_ms": kt["walk"] / max(launches, 1), "coef_env_ms": kt["coef"] / reps,
+            "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(ach / HBM_PEAK_GBS, 4), "kernel": "k_push_ds<false>",
+                         "bytes_per_launch": nbytes},
+            "note": "float64 downshifted step (side path, not in value); the complex-envelope rows are built "
+                    "once per call"}
+
+
 def adjoint_timing(E, torch, synth):
     """Differentiation workload: 20^3 x 6 tets, 2e6 electrons, 20 float64 steps
     with a checkpoint every 5, then the reverse sweep (gradient of the final
@@ -396,6 +442,8 @@ def main():
         log(f"[bench] field update: {json.dumps(line['field_update'])}")
         line["coarse_step"] = coarse_step_timing(E, torch, synth, ctx, w)
         log(f"[bench] coarse step: {json.dumps(line['coarse_step'])}")
+        line["downshifted_step"] = ds_step_timing(E, torch, ctx, w)
+        log(f"[bench] downshifted step: {json.dumps(line['downshifted_step'])}")
         line["adjoint"] = adjoint_timing(E, torch, synth)
         log(f"[bench] adjoint: {json.dumps(line['adjoint'])}")
     if not args.no_cpu_baseline:

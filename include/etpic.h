@@ -298,7 +298,9 @@ int etpic_ds_history_bytes(int64_t n, size_t *bytes_out);
  * buffer (device, 8-byte aligned, at least etpic_ds_history_bytes), whose
  * slots are addressed by the step number, so successive calls must continue
  * the numbering; hist0 = number of downshifted steps already taken with this
- * buffer (0 for a fresh start: the buffer is then not read).  A re-sort of the
+ * buffer (0 for a fresh start: the buffer is then not read); the calls that
+ * share a history either all give dc edge DoFs or none does (without them the
+ * E dc samples are neither stored nor read).  A re-sort of the
  * particles (etpic_sort) does not move the history: restart with hist0 = 0
  * after one.  dG accumulates the deposit of all steps, rho (if not NULL)
  * receives q w lam_k after the last one.  flags as for

@@ -881,6 +881,7 @@ struct DsArgs {
     double Mr[3], Mi[3], P[3], Lr[9], Li[9], Q[9];
     double ab[4];             // Adams-Bashforth coefficients times the step
     double qm;
+    int edc;                  // dc edge DoFs given (else the E dc samples are 0 and not stored)
 };
 
 __device__ __forceinline__ double *ds_v(const DsArgs &d, int slot, int c) { return d.hist + (3 * slot + c) * d.stride; }
@@ -922,8 +923,10 @@ __global__ void __launch_bounds__(kBlock) k_push_ds(StepArgs<double> a, DsArgs d
         for (int part = 0; part < 6; ++part)
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-                S[part][c] = l[0] * row[12 * part + c] + l[1] * row[12 * part + 3 + c] +
-                             l[2] * row[12 * part + 6 + c] + l[3] * row[12 * part + 9 + c];
+                S[part][c] = (part == 2 && !d.edc)
+                                 ? 0.0
+                                 : l[0] * row[12 * part + c] + l[1] * row[12 * part + 3 + c] +
+                                       l[2] * row[12 * part + 6 + c] + l[3] * row[12 * part + 9 + c];
         double V[4][3];
         V[0][0] = a.v0[p];
         V[0][1] = a.v1[p];
@@ -940,8 +943,10 @@ __global__ void __launch_bounds__(kBlock) k_push_ds(StepArgs<double> a, DsArgs d
             if (k >= d.K) break;
             const int sl = d.sin_[k - 1];
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
-                acc[c] += ds_e(d, sl, c)[p] * d.Mr[k] + ds_e(d, sl, 3 + c)[p] * d.Mi[k] + ds_e(d, sl, 6 + c)[p] * d.P[k];
+            for (int c = 0; c < 3; ++c) {
+                acc[c] += ds_e(d, sl, c)[p] * d.Mr[k] + ds_e(d, sl, 3 + c)[p] * d.Mi[k];
+                if (d.edc) acc[c] += ds_e(d, sl, 6 + c)[p] * d.P[k];
+            }
         }
         // magnetic part: sum_k (weighted B sample k) crossed with each v^{n-j}
 #pragma unroll
@@ -984,7 +989,7 @@ __global__ void __launch_bounds__(kBlock) k_push_ds(StepArgs<double> a, DsArgs d
         for (int c = 0; c < 3; ++c) {
             ds_e(d, d.sout, c)[p] = S[0][c];
             ds_e(d, d.sout, 3 + c)[p] = S[1][c];
-            ds_e(d, d.sout, 6 + c)[p] = S[2][c];
+            if (d.edc) ds_e(d, d.sout, 6 + c)[p] = S[2][c];
             ds_b(d, d.sout, c)[p] = S[3][c];
             ds_b(d, d.sout, 3 + c)[p] = S[4][c];
             ds_b(d, d.sout, 6 + c)[p] = S[5][c];
@@ -2284,6 +2289,7 @@ struct etpic_ctx {
             d.sout = mod(sn, 2);
             ds_weights(d.K, (double)sn * dt, dt, omega, d);
             d.qm = sp->q / sp->m;
+            d.edc = f->e_dc ? 1 : 0;
             if (ev) HIP_TRY(hipEventRecord(ev[2], st));
             if (a.rho)
                 k_push_ds<true><<<grid_for(n), kBlock, 0, st>>>(a, d, remap);

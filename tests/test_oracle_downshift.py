@@ -256,3 +256,71 @@ def test_continuity_of_downshifted_steps(ora):
                          omega=w.omega, e_env=w.e_env, b_env=w.b_env, b_dc=w.b_dc, dG=dG, rho=rho1) == 0
         r, p = M.gauss(dG, rho1, rho0)
         assert r / p < 1e-13
+
+
+def test_lower_oversampling_than_the_fine_step_scheme(ora):
+    """The trend the Particle Push section reports for this scheme: at equal
+    accuracy of the path (hence of G), fewer steps per carrier period than the
+    fine-step scheme that samples the modulated field.  One electron in the
+    uniform field Re{(c0 + c1 t) E0 e^{jwt}} x (10 GHz), B = 0, both schemes
+    started on the exact trajectory (leapfrog v^{-1/2}; downshifted history at
+    t_{-1..-3}), position error after 10.37 periods against the closed form:
+    fourth order for the downshifted scheme, second order for the fine-step
+    Boris scheme; the downshifted scheme at 24 steps per period beats the
+    fine-step one at 64."""
+    f = 10e9
+    om, Tper, E0 = 2 * np.pi * f, 1.0 / f, 1e4
+    v0, Edir = np.array([1e5, 2e4, -3e4]), np.array([1.0, 0.0, 0.0])
+    c0, c1 = 1.0 + 0.3j, (0.4 - 0.2j) / (20 * Tper)
+    jw = 1j * om
+    acc = QM * E0 * Edir
+
+    def g(t):
+        return c0 + c1 * t
+
+    def iv(t):      # int_0^t g(s) e^{jws} ds
+        e = np.exp(jw * t)
+        return c0 * (e - 1) / jw + c1 * (t * e / jw - (e - 1) / jw ** 2)
+
+    def ix(t):      # int_0^t iv(u) du
+        e = np.exp(jw * t)
+        ie, iue = (e - 1) / jw, t * e / jw - (e - 1) / jw ** 2
+        return c0 * (ie - t) / jw + c1 * (iue / jw - ie / jw ** 2 + t / jw ** 2)
+
+    def vex(t):
+        return v0 + acc * np.real(iv(t))
+
+    def xex(t):
+        return v0 * t + acc * np.real(ix(t))
+
+    err = {}
+    for M in (8, 16, 24, 32, 64):
+        h = Tper / M
+        n = int(round(10.37 * M))
+        for scheme in ("fine", "ds"):
+            p = One(ora, (0.5, 0.5, 0.5), v0)
+            unit = uniform_edge_dofs(p.xyz, p.edges, Edir)
+            zb = np.zeros(p.M.nf, complex)
+            x0 = p.x()
+            if scheme == "ds":
+                for j in range(3):
+                    p.H.v[0, j] = vex(-(j + 1) * h)
+                for j in range(2):
+                    gj = g(-(j + 1) * h) * E0
+                    p.H.e[0, j, 0:3] = np.real(gj) * Edir
+                    p.H.e[0, j, 3:6] = np.imag(gj) * Edir
+                for k in range(n):
+                    p.step(3, k * h, h, om, E0 * g(k * h) * unit, zb)
+            else:
+                p.vel[0] = vex(-h / 2)
+                for k in range(n):
+                    rc, _ = p.M.step(p.tet, p.lam, p.vel, q=Q_E, m=M_E, w=1.0, step=k, dt=h, omega=om,
+                                     e_env=E0 * g(k * h) * unit, b_env=zb, dG=p.dG)
+                    assert rc == 0
+            ref = xex(n * h)
+            err[scheme, M] = np.abs((p.x() - x0) - ref).max() / np.abs(ref).max()
+    print("position error vs steps per period:",
+          {M: (f"{err['fine', M]:.2e}", f"{err['ds', M]:.2e}") for M in (8, 16, 24, 32, 64)})
+    assert err["ds", 32] / err["ds", 64] > 10.0                 # fourth order
+    assert err["ds", 64] < err["fine", 64] / 20.0
+    assert err["ds", 24] < err["fine", 64]                      # ~2.7x fewer steps for the same accuracy

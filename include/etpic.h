@@ -300,9 +300,9 @@ int etpic_ds_history_bytes(int64_t n, size_t *bytes_out);
  * the numbering; hist0 = number of downshifted steps already taken with this
  * buffer (0 for a fresh start: the buffer is then not read); the calls that
  * share a history either all give dc edge DoFs or none does (without them the
- * E dc samples are neither stored nor read).  A re-sort of the
- * particles (etpic_sort) does not move the history: restart with hist0 = 0
- * after one.  dG accumulates the deposit of all steps, rho (if not NULL)
+ * E dc samples are neither stored nor read).  Re-sort with etpic_ds_sort,
+ * which moves the history with the particles (etpic_sort does not: restart
+ * with hist0 = 0 after it).  dG accumulates the deposit of all steps, rho (if not NULL)
  * receives q w lam_k after the last one.  flags as for
  * etpic_gather_push_deposit (XCD_REMAP, TIMING, WALK_BY_SLICE).  The first
  * call after a mesh upload allocates the complex-envelope rows.
@@ -311,6 +311,14 @@ int etpic_ds_history_bytes(int64_t n, size_t *bytes_out);
 int etpic_ds_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, double *hist, size_t hist_bytes,
                    const etpic_species *sp, const etpic_fields *f, int64_t step0, int nsteps, int hist0, double dt,
                    double omega, double *dG, double *rho, uint32_t flags, void *stream);
+
+/* etpic_sort of float64 particles src -> dst that also moves their
+ * downshifted history hist_src -> hist_dst (distinct device buffers of at
+ * least hist_bytes = etpic_ds_history_bytes(n)), so the steps continue with
+ * the same numbering and hist0.  Asynchronous on `stream`.  Errors as
+ * etpic_sort. */
+int etpic_ds_sort(etpic_ctx *ctx, const etpic_particles *src, const etpic_particles *dst, const double *hist_src,
+                  double *hist_dst, size_t hist_bytes, void *stream);
 
 /* ---- Differentiation (float64 form only) --------------------------------
  * Reverse-mode derivative of nsteps particle steps with respect to the

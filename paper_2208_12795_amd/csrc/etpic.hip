@@ -1587,10 +1587,13 @@ __global__ void __launch_bounds__(kBlock) k_scan_add(unsigned *__restrict__ x, i
     if (i < n) x[i] += sums[i / kScanTile];
 }
 
+// hsrc / hdst (optional): nh further float64 arrays of length n at stride n,
+// moved with the particles (the downshifted history).
 template <typename Real>
 __global__ void __launch_bounds__(kBlock) k_scatter(int64_t n, int64_t nt, const int32_t *__restrict__ tet,
                                                     unsigned *__restrict__ cursor, etpic_particles src,
-                                                    etpic_particles dst) {
+                                                    etpic_particles dst, const double *__restrict__ hsrc = nullptr,
+                                                    double *__restrict__ hdst = nullptr, int nh = 0) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int T = -1;
     if (p < n) {
@@ -1611,6 +1614,7 @@ __global__ void __launch_bounds__(kBlock) k_scatter(int64_t n, int64_t nt, const
         static_cast<Real *>(dst.vel[k])[q] = static_cast<const Real *>(src.vel[k])[p];
     }
     if (src.id && dst.id) dst.id[q] = src.id[p];
+    for (int i = 0; i < nh; ++i) hdst[(int64_t)i * n + q] = hsrc[(int64_t)i * n + p];
 }
 
 // ------------------------------------------------------------------ field update
@@ -2136,9 +2140,11 @@ struct etpic_ctx {
     }
 
     template <typename Real>
-    int sort(const etpic_particles *src, const etpic_particles *dst, hipStream_t st) {
+    int sort(const etpic_particles *src, const etpic_particles *dst, hipStream_t st, const double *hsrc = nullptr,
+             double *hdst = nullptr, int nh = 0) {
         if (int r = sort_count(src, st)) return r;
-        k_scatter<Real><<<grid_for(src->n), kBlock, 0, st>>>(src->n, host.nt, src->tet, d_count, *src, *dst);
+        k_scatter<Real><<<grid_for(src->n), kBlock, 0, st>>>(src->n, host.nt, src->tet, d_count, *src, *dst, hsrc,
+                                                              hdst, nh);
         HIP_TRY(hipGetLastError());
         return ETPIC_OK;
     }
@@ -2772,6 +2778,20 @@ int etpic_ds_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, doub
     if (p->n == 0) return ETPIC_OK;
     if (int r = set_device(ctx)) return r;
     return ctx->ds_steps(p, hist, sp, f, step0, nsteps, hist0, dt, omega, dG, rho, flags, stream);
+}
+
+int etpic_ds_sort(etpic_ctx *ctx, const etpic_particles *src, const etpic_particles *dst, const double *hist_src,
+                  double *hist_dst, size_t hist_bytes, void *stream) {
+    if (int r = check_sort_pair(ctx, src, dst)) return r;
+    const size_t need = sizeof(double) * (size_t)kDsArrays * (size_t)src->n;
+    if (!hist_src || !hist_dst || hist_bytes < need)
+        return fail(ETPIC_EINVAL, "history buffers missing or smaller than etpic_ds_history_bytes");
+    if (hist_src == hist_dst) return fail(ETPIC_EINVAL, "sort needs distinct history buffers");
+    if (((reinterpret_cast<uintptr_t>(hist_src) | reinterpret_cast<uintptr_t>(hist_dst)) & 7) != 0)
+        return fail(ETPIC_EINVAL, "history buffers not 8-byte aligned");
+    if (src->n == 0) return ETPIC_OK;
+    if (int r = set_device(ctx)) return r;
+    return ctx->sort<double>(src, dst, static_cast<hipStream_t>(stream), hist_src, hist_dst, kDsArrays);
 }
 
 int etpic_adjoint_workspace(const etpic_ctx *ctx, int64_t n, int nsteps, int checkpoint_every, size_t *bytes_out) {

@@ -32,7 +32,7 @@ EXPORTS = (
     "etpic_adjoint_workspace", "etpic_forward_checkpointed", "etpic_backward",
     "etpic_field_setup", "etpic_field_nnz", "etpic_field_spmv", "etpic_field_step",
     "etpic_particles_locate", "etpic_particles_positions", "etpic_coarse_step", "etpic_run_steps",
-    "etpic_sort_run_steps", "etpic_ds_history_bytes", "etpic_ds_steps",
+    "etpic_sort_run_steps", "etpic_ds_history_bytes", "etpic_ds_steps", "etpic_ds_sort",
 )
 
 
@@ -95,6 +95,7 @@ def lib():
     L.etpic_run_steps.argtypes = [vp, C.POINTER(_Particles), C.c_int, C.POINTER(_Species), C.POINTER(_Fields),
                                   C.c_int64, C.c_int, C.c_double, C.c_double, vp, vp, C.c_uint32, vp]
     L.etpic_ds_history_bytes.argtypes = [C.c_int64, C.POINTER(C.c_size_t)]
+    L.etpic_ds_sort.argtypes = [vp, C.POINTER(_Particles), C.POINTER(_Particles), vp, vp, C.c_size_t, vp]
     L.etpic_ds_steps.argtypes = [vp, C.POINTER(_Particles), C.c_int, vp, C.c_size_t, C.POINTER(_Species), C.POINTER(_Fields),
                                  C.c_int64, C.c_int, C.c_int, C.c_double, C.c_double, vp, vp, C.c_uint32, vp]
     L.etpic_sort_run_steps.argtypes = [vp, C.POINTER(_Particles), C.POINTER(_Particles), C.c_int,
@@ -365,6 +366,15 @@ class Context:
                                   hist.numel() * hist.element_size(), C.byref(sp), C.byref(fd), int(step0),
                                   int(nsteps), int(hist0), float(dt), float(omega), _dptr(dG), _dptr(rho),
                                   int(flags), _stream(stream)))
+
+    def ds_sort(self, src, dst, hist_src, hist_dst, stream=None):
+        """sort(src, dst) that also moves the downshifted history."""
+        assert src.precision == FP64 and dst.precision == FP64
+        assert hist_src.shape == hist_dst.shape and hist_src.is_contiguous() and hist_dst.is_contiguous()
+        a, b = src.desc(), dst.desc()
+        _chk(lib().etpic_ds_sort(self._h, C.byref(a), C.byref(b), C.c_void_p(hist_src.data_ptr()),
+                                 C.c_void_p(hist_dst.data_ptr()), hist_src.numel() * hist_src.element_size(),
+                                 _stream(stream)))
 
     def locate(self, xyz, parts, hint=None, stream=None, raise_on_error=True):
         """Locate the points xyz (float64 [3, N] on the device) into parts.tet /

@@ -156,3 +156,40 @@ def test_argument_errors(E, torch_cuda):
         ctx.ds_steps(mixed, hist, sp, f, 0, 1, 0, w.dt, w.omega, dG)
     ctx.check()
     ctx.close()
+
+
+def test_sort_carries_the_history(E, torch_cuda):
+    """4 steps, a re-sort with etpic_ds_sort, 4 more steps continuing the
+    numbering, against 8 steps without the sort: every particle's state is the
+    same (matched by id), the currents equal to the atomics' rounding."""
+    torch = torch_cuda
+    w = synth.make_workload(2, n_particles=300_001)
+    ctx = E.Context(0)
+    ctx.upload_mesh(w.xyz, w.tet_vert)
+    f = E.Fields.from_numpy(w.e_env, w.b_env, None, w.b_dc)
+    sp = E.Species(w.q, w.m, w.w)
+    dt = 5 * w.dt
+    a = E.Particles.from_numpy(w.tet, w.lam, w.vel, w.ids)
+    b = a.clone()
+    ha, hb = ctx.ds_history(a), ctx.ds_history(b)
+    ga = torch.zeros(ctx.n_edge, dtype=torch.float64, device="cuda")
+    gb = torch.zeros_like(ga)
+    ctx.ds_steps(a, ha, sp, f, 0, 8, 0, dt, w.omega, ga)
+    ctx.ds_steps(b, hb, sp, f, 0, 4, 0, dt, w.omega, gb)
+    b2, hb2 = b.empty_like(), torch.empty_like(hb)
+    ctx.ds_sort(b, b2, hb, hb2)
+    assert np.all(np.diff(b2.tet.cpu().numpy()) >= 0)
+    ctx.ds_steps(b2, hb2, sp, f, 4, 4, 4, dt, w.omega, gb)
+    ctx.check()
+
+    def by_id(p):
+        t, l, v, i = p.to_numpy()
+        o = np.argsort(i)
+        return t[o], l[o], v[o]
+
+    for x, y in zip(by_id(a), by_id(b2)):
+        assert np.array_equal(x, y)
+    assert torch.allclose(ga, gb, rtol=0, atol=1e-13 * ga.abs().max().item())
+    with pytest.raises(E.EtpicError):
+        ctx.ds_sort(b2, b, hb2, hb2)
+    ctx.close()

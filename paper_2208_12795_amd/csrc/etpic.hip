@@ -17,7 +17,15 @@
 //   k_walk        the queued particles: barycentric walk, reflection, deposit.
 //   k_walk_coef   the walk of a step and the next step's coefficients in one
 //                 launch (multi-step calls).
+//   k_push_sort, k_push_sort_slices
+//                 the same particle kernels reading the particles in their old
+//                 order and writing them, pushed, at their tet-sorted places
+//                 (the periodic re-sort folded into a step).
 //   k_hist/k_scan*/k_scatter/k_run_stat   counting sort by tet.
+//   k_tet_coef_env, k_push_ds, k_walk_ds
+//                 the downshifted step: complex-envelope rows per tet, the
+//                 carrier-exact velocity quadrature of interpolated samples
+//                 with Adams-Bashforth positions, and its walk.
 //   k_charge      vertex charge of the particles.
 //   k_gauss       continuity residual D^T dG - (rho_new - rho_old).
 //   k_locate, k_positions   Cartesian points <-> (tet, barycentrics).

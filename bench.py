@@ -216,21 +216,23 @@ def coarse_step_timing(E, torch, synth, ctx, w, fine=10, reps=5):
             "note": "float64, three envelope snapshots interpolated at every fine step; no sort inside"}
 
 
-DS_BYTES_PER_PARTICLE = 556   # float64 downshifted step without dc edge DoFs, see ds_step_timing
-DS_BYTES_PER_TET = 576 + 96    # complex-envelope rows and the push row
+# downshifted step without dc edge DoFs, see ds_step_timing
+DS_BYTES_PER_PARTICLE = {"fp64": 556, "mixed": 304}
+DS_BYTES_PER_TET = {"fp64": 576 + 96, "mixed": 576 + 64}   # complex-envelope rows and the push row
 
 
-def ds_step_timing(E, torch, ctx, w, nsteps=10, reps=3):
+def ds_step_timing(E, torch, ctx, w, form="fp64", nsteps=10, reps=3):
     """Downshifted form (carrier-exact velocity quadrature of envelope samples
-    interpolated over three steps, Adams-Bashforth positions), float64, same
-    workload and step as the metric, particles sorted once, calls of `nsteps`
-    steps after a 3-step ramp.  Algorithmic bytes per particle-step of its
-    particle kernel: read tet 4, lam 24, v 24, three earlier velocities 72, two
-    E samples (Re, Im) 96, two B samples (Re, Im, dc) 144; write lam 24, v 24,
-    one velocity 24, one E sample 48, one B sample 72: 556 B."""
+    interpolated over three steps, Adams-Bashforth positions), same workload and
+    step as the metric, particles sorted once, calls of `nsteps` steps after a
+    3-step ramp.  Algorithmic bytes per particle-step of its particle kernel,
+    float64: read tet 4, lam 24, v 24, three earlier velocities 72, two E
+    samples (Re, Im) 96, two B samples (Re, Im, dc) 144; write lam 24, v 24,
+    one velocity 24, one E sample 48, one B sample 72: 556 B.  Mixed (float32
+    velocities and samples): 196 read + 108 written = 304 B."""
     sp = E.Species(w.q, w.m, w.w)
     f = E.Fields.from_numpy(w.e_env, w.b_env, None, w.b_dc)
-    parts = E.Particles.from_numpy(w.tet, w.lam, w.vel, w.ids)
+    parts = E.Particles.from_numpy(w.tet, w.lam, w.vel, w.ids, precision=E.FP64 if form == "fp64" else E.MIXED)
     spare = parts.empty_like()
     ctx.sort(parts, spare)
     parts = spare
@@ -250,15 +252,16 @@ def ds_step_timing(E, torch, ctx, w, nsteps=10, reps=3):
     ctx.check()
     ms = e0.elapsed_time(e1) / (reps * nsteps)
     push_ms = kt["push"] / max(kt["steps_push"], 1)
-    nbytes = DS_BYTES_PER_PARTICLE * parts.n + DS_BYTES_PER_TET * w.tet_vert.shape[0] + 16 * ctx.n_edge
+    nbytes = DS_BYTES_PER_PARTICLE[form] * parts.n + DS_BYTES_PER_TET[form] * w.tet_vert.shape[0] + 16 * ctx.n_edge
     ach = nbytes / (push_ms * 1e-3) / 1e9
     del hist
     return {"ms_per_step": ms, "value": parts.n / (ms * 1e-3), "push_ms": push_ms,
             "walk_ms": kt["walk"] / max(launches, 1), "coef_env_ms": kt["coef"] / reps,
             "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(ach / HBM_PEAK_GBS, 4), "kernel": "k_push_ds<false>",
+                         "frac": round(ach / HBM_PEAK_GBS, 4),
+                         "kernel": "k_push_ds<double, false>" if form == "fp64" else "k_push_ds<float, false>",
                          "bytes_per_launch": nbytes},
-            "note": "float64 downshifted step (side path, not in value); the complex-envelope rows are built "
+            "note": f"{form} downshifted step (side path, not in value); the complex-envelope rows are built "
                     "once per call"}
 
 
@@ -443,6 +446,7 @@ def main():
         line["coarse_step"] = coarse_step_timing(E, torch, synth, ctx, w)
         log(f"[bench] coarse step: {json.dumps(line['coarse_step'])}")
         line["downshifted_step"] = ds_step_timing(E, torch, ctx, w)
+        line["downshifted_step"]["mixed"] = ds_step_timing(E, torch, ctx, w, form="mixed")
         log(f"[bench] downshifted step: {json.dumps(line['downshifted_step'])}")
         line["adjoint"] = adjoint_timing(E, torch, synth)
         log(f"[bench] adjoint: {json.dumps(line['adjoint'])}")

@@ -269,7 +269,7 @@ int etpic_vertex_charge(etpic_ctx *ctx, const etpic_particles *p, const etpic_sp
 int etpic_gauss_residual(etpic_ctx *ctx, const double *dG, const double *rho_new, const double *rho_old,
                          double out_host[2], void *stream);
 
-/* ---- Downshifted integrator (float64) --------------------------------------
+/* ---- Downshifted integrator ------------------------------------------------
  * The Particle Push section's scheme that treats the carrier analytically in
  * the velocity update.  Over a step [t_n, t_n + dt] the envelope fields sampled
  * at the particle (E~, B~ from the Whitney expansions, and the dc DoFs) and the
@@ -285,16 +285,19 @@ int etpic_gauss_residual(etpic_ctx *ctx, const double *dG, const double *rho_new
  * etpic_gather_push_deposit (same dG, rho and continuity law).  At a wall the
  * velocity and the velocity samples kept for later steps are mirrored.  With
  * fewer than three earlier downshifted steps the orders ramp up: K =
- * min(hist, 2) + 1 nodes and Adams-Bashforth order min(hist, 3) + 1. */
+ * min(hist, 2) + 1 nodes and Adams-Bashforth order min(hist, 3) + 1.
+ * Precision: ETPIC_FP64, or ETPIC_MIXED (float32 samples, velocities and
+ * velocity update, float64 positions, barycentric increments and deposit,
+ * as the mixed fine-step form). */
 
-/* Size of the history buffer for n particles: 48 float64 arrays of length n
- * (velocity ring v^m in slot m mod 4; E and B samples, real part, imaginary
- * part and dc part, of step m in slot m mod 2).  Host only. */
-int etpic_ds_history_bytes(int64_t n, size_t *bytes_out);
+/* Size of the history buffer for n particles: 48 arrays of length n of the
+ * velocity type (float64, float32 for ETPIC_MIXED): velocity ring v^m in slot
+ * m mod 4; E and B samples, real part, imaginary part and dc part, of step m
+ * in slot m mod 2.  Host only. */
+int etpic_ds_history_bytes(int64_t n, int precision, size_t *bytes_out);
 
 /* nsteps downshifted steps from step0 (t_n = n dt) with fixed field DoFs.
- * p: particles, p->vel = v^n in, v^{n+nsteps} out; precision must be
- * ETPIC_FP64 (EINVAL otherwise).  hist: the history
+ * p: particles of `precision`, p->vel = v^n in, v^{n+nsteps} out.  hist: the history
  * buffer (device, 8-byte aligned, at least etpic_ds_history_bytes), whose
  * slots are addressed by the step number, so successive calls must continue
  * the numbering; hist0 = number of downshifted steps already taken with this
@@ -308,17 +311,17 @@ int etpic_ds_history_bytes(int64_t n, size_t *bytes_out);
  * call after a mesh upload allocates the complex-envelope rows.
  * Asynchronous on `stream`.  Errors: EINVAL, ESTATE, EHIP; in-kernel errors
  * via etpic_check. */
-int etpic_ds_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, double *hist, size_t hist_bytes,
+int etpic_ds_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, void *hist, size_t hist_bytes,
                    const etpic_species *sp, const etpic_fields *f, int64_t step0, int nsteps, int hist0, double dt,
                    double omega, double *dG, double *rho, uint32_t flags, void *stream);
 
-/* etpic_sort of float64 particles src -> dst that also moves their
- * downshifted history hist_src -> hist_dst (distinct device buffers of at
- * least hist_bytes = etpic_ds_history_bytes(n)), so the steps continue with
- * the same numbering and hist0.  Asynchronous on `stream`.  Errors as
+/* etpic_sort of particles src -> dst that also moves their downshifted
+ * history hist_src -> hist_dst (distinct device buffers of at least
+ * hist_bytes = etpic_ds_history_bytes(n, precision)), so the steps continue
+ * with the same numbering and hist0.  Asynchronous on `stream`.  Errors as
  * etpic_sort. */
-int etpic_ds_sort(etpic_ctx *ctx, const etpic_particles *src, const etpic_particles *dst, const double *hist_src,
-                  double *hist_dst, size_t hist_bytes, void *stream);
+int etpic_ds_sort(etpic_ctx *ctx, const etpic_particles *src, const etpic_particles *dst, int precision,
+                  const void *hist_src, void *hist_dst, size_t hist_bytes, void *stream);
 
 /* ---- Differentiation (float64 form only) --------------------------------
  * Reverse-mode derivative of nsteps particle steps with respect to the

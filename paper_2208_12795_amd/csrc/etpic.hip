@@ -870,34 +870,48 @@ __global__ void __launch_bounds__(kBlock) k_tet_coef_env(int64_t nt, const doubl
     for (int d = 0; d < 12; ++d) dst[d] = o[d];
 }
 
-// History of the downshifted integrator: 48 float64 arrays of length n in one
-// caller-owned buffer, array i at hist + i * n.  Arrays 0..11: velocity ring,
+// History of the downshifted integrator: 48 arrays of length n in one
+// caller-owned buffer (float64, or float32 in the mixed form), array i at
+// hist + i * n.  Arrays 0..11: velocity ring,
 // v^m in slot m mod 4 (components 3 slot + c); 12..29: E samples, the sample of
 // step m in slot m mod 2 (12 + 9 slot + i, i = Re 0..2, Im 3..5, dc 6..8);
 // 30..47: B samples likewise.
 constexpr int kDsArrays = 48;
 
+// Weights of one step, in float64 on the host.
+struct DsWeights {
+    double Mr[3], Mi[3], P[3], Lr[9], Li[9], Q[9];
+    double ab[4];             // Adams-Bashforth coefficients times the step
+};
+
+template <typename Real>
 struct DsArgs {
     const double *coef_env;   // nt * kEnvRow
-    double *hist;
+    Real *hist;
     int64_t stride;           // n
     int vin[3];               // ring slots of v^{n-1}, v^{n-2}, v^{n-3} (-1: not used)
     int vout;                 // slot that receives v^n
     int sin_[2];              // sample slots of t_{n-1}, t_{n-2} (-1: not used)
     int sout;                 // slot that receives the sample of t_n
     int K, A;                 // interpolation nodes, Adams-Bashforth order
-    double Mr[3], Mi[3], P[3], Lr[9], Li[9], Q[9];
-    double ab[4];             // Adams-Bashforth coefficients times the step
-    double qm;
+    Real Mr[3], Mi[3], P[3], Lr[9], Li[9], Q[9];
+    Real ab[4];
+    Real qm;
     int edc;                  // dc edge DoFs given (else the E dc samples are 0 and not stored)
 };
 
-__device__ __forceinline__ double *ds_v(const DsArgs &d, int slot, int c) { return d.hist + (3 * slot + c) * d.stride; }
-__device__ __forceinline__ double *ds_e(const DsArgs &d, int slot, int i) { return d.hist + (12 + 9 * slot + i) * d.stride; }
-__device__ __forceinline__ double *ds_b(const DsArgs &d, int slot, int i) { return d.hist + (30 + 9 * slot + i) * d.stride; }
+template <typename Real>
+__device__ __forceinline__ Real *ds_v(const DsArgs<Real> &d, int slot, int c) { return d.hist + (3 * slot + c) * d.stride; }
+template <typename Real>
+__device__ __forceinline__ Real *ds_e(const DsArgs<Real> &d, int slot, int i) { return d.hist + (12 + 9 * slot + i) * d.stride; }
+template <typename Real>
+__device__ __forceinline__ Real *ds_b(const DsArgs<Real> &d, int slot, int i) { return d.hist + (30 + 9 * slot + i) * d.stride; }
 
-template <bool kRho>
-__global__ void __launch_bounds__(kBlock) k_push_ds(StepArgs<double> a, DsArgs d, int remap) {
+// Real = double: the float64 form.  Real = float: samples, velocities and the
+// velocity update in float32, positions, the barycentric increments and the
+// deposit in float64 (the mixed form of the fine-step kernel).
+template <typename Real, bool kRho>
+__global__ void __launch_bounds__(kBlock) k_push_ds(StepArgs<Real> a, DsArgs<Real> d, int remap) {
     unsigned blk = blockIdx.x;
     if (remap) {
         const unsigned G = gridDim.x, q = G / 8, r = G % 8, x = blk % 8, j = blk / 8;
@@ -926,24 +940,25 @@ __global__ void __launch_bounds__(kBlock) k_push_ds(StepArgs<double> a, DsArgs d
         l[0] = 1.0 - l[1] - l[2] - l[3];
         // samples at t_n: sum_k lam_k of the tet's rows
         const double *row = d.coef_env + (int64_t)T * kEnvRow;
-        double S[6][3];   // E re, im, dc; B re, im, dc
+        const Real lr[4] = {(Real)l[0], (Real)l[1], (Real)l[2], (Real)l[3]};
+        Real S[6][3];   // E re, im, dc; B re, im, dc
 #pragma unroll
         for (int part = 0; part < 6; ++part)
 #pragma unroll
             for (int c = 0; c < 3; ++c)
                 S[part][c] = (part == 2 && !d.edc)
-                                 ? 0.0
-                                 : l[0] * row[12 * part + c] + l[1] * row[12 * part + 3 + c] +
-                                       l[2] * row[12 * part + 6 + c] + l[3] * row[12 * part + 9 + c];
-        double V[4][3];
+                                 ? (Real)0
+                                 : lr[0] * (Real)row[12 * part + c] + lr[1] * (Real)row[12 * part + 3 + c] +
+                                       lr[2] * (Real)row[12 * part + 6 + c] + lr[3] * (Real)row[12 * part + 9 + c];
+        Real V[4][3];
         V[0][0] = a.v0[p];
         V[0][1] = a.v1[p];
         V[0][2] = a.v2[p];
 #pragma unroll
         for (int j = 0; j < 3; ++j)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) V[j + 1][c] = d.vin[j] >= 0 ? ds_v(d, d.vin[j], c)[p] : 0.0;
-        double acc[3];
+            for (int c = 0; c < 3; ++c) V[j + 1][c] = d.vin[j] >= 0 ? ds_v(d, d.vin[j], c)[p] : (Real)0;
+        Real acc[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) acc[c] = S[0][c] * d.Mr[0] + S[1][c] * d.Mi[0] + S[2][c] * d.P[0];
 #pragma unroll
@@ -960,7 +975,7 @@ __global__ void __launch_bounds__(kBlock) k_push_ds(StepArgs<double> a, DsArgs d
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             if (k >= d.K) break;
-            double Bk[3][3];
+            Real Bk[3][3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 if (k == 0) {
@@ -978,7 +993,7 @@ __global__ void __launch_bounds__(kBlock) k_push_ds(StepArgs<double> a, DsArgs d
             for (int j = 0; j < 3; ++j) {
                 if (j >= d.K) break;
                 const int jk = j * d.K + k;
-                double Bw[3];
+                Real Bw[3];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) Bw[c] = Bk[0][c] * d.Lr[jk] + Bk[1][c] * d.Li[jk] + Bk[2][c] * d.Q[jk];
                 acc[0] += V[j][1] * Bw[2] - V[j][2] * Bw[1];
@@ -986,7 +1001,7 @@ __global__ void __launch_bounds__(kBlock) k_push_ds(StepArgs<double> a, DsArgs d
                 acc[2] += V[j][0] * Bw[1] - V[j][1] * Bw[0];
             }
         }
-        double vn[3];
+        Real vn[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) vn[c] = V[0][c] + d.qm * acc[c];
         if (!(isfinite(vn[0]) && isfinite(vn[1]) && isfinite(vn[2]))) atomicOr(a.status, (unsigned)ETPIC_DEV_NAN);
@@ -1002,18 +1017,20 @@ __global__ void __launch_bounds__(kBlock) k_push_ds(StepArgs<double> a, DsArgs d
             ds_b(d, d.sout, 3 + c)[p] = S[4][c];
             ds_b(d, d.sout, 6 + c)[p] = S[5][c];
         }
-        // Adams-Bashforth displacement and its barycentric increments
-        double dx[3] = {0.0, 0.0, 0.0};
+        // Adams-Bashforth displacement and its barycentric increments (in
+        // float64, the four summing to zero as in the fine-step kernel)
+        Real dx[3] = {0, 0, 0};
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             if (i >= d.A) break;
 #pragma unroll
             for (int c = 0; c < 3; ++c) dx[c] += d.ab[i] * V[i][c];
         }
-        const double *gr = a.gpush + (int64_t)T * PushRow<double>::kStride;
+        const Real *gr = a.gpush + (int64_t)T * PushRow<Real>::kStride;
         double dl[4];
 #pragma unroll
-        for (int k = 1; k < 4; ++k) dl[k] = gr[3 * k - 3] * dx[0] + gr[3 * k - 2] * dx[1] + gr[3 * k - 1] * dx[2];
+        for (int k = 1; k < 4; ++k)
+            dl[k] = (double)(gr[3 * k - 3] * dx[0] + gr[3 * k - 2] * dx[1] + gr[3 * k - 1] * dx[2]);
         dl[0] = -(dl[1] + dl[2] + dl[3]);
         const bool stays = (l[0] + dl[0] >= 0.0) && (l[1] + dl[1] >= 0.0) && (l[2] + dl[2] >= 0.0) &&
                            (l[3] + dl[3] >= 0.0);
@@ -1050,7 +1067,7 @@ __global__ void __launch_bounds__(kBlock) k_push_ds(StepArgs<double> a, DsArgs d
 #pragma unroll
         for (int k = 0; k < 4; ++k) r4[k] = run_total(r4[k], runs);
     }
-    if (act && runs.lane == runs.run_end) flush_run<double, kRho>(a, T, g6, r4);
+    if (act && runs.lane == runs.run_end) flush_run<Real, kRho>(a, T, g6, r4);
     // walkers to the particle queue, or their slice when it is full
     const unsigned long long wmask = __ballot(walker);
     if (wmask) {
@@ -1069,7 +1086,8 @@ __global__ void __launch_bounds__(kBlock) k_push_ds(StepArgs<double> a, DsArgs d
 // displacement is rebuilt from the ring (v^n is in its slot by now, the older
 // samples are untouched), and at a wall the velocity samples the next steps
 // use (v^n, v^{n-1}, v^{n-2}) are mirrored with v^{n+1}.
-__device__ __forceinline__ void walk_particle_ds(const StepArgs<double> &a, const DsArgs &d, int64_t p) {
+template <typename Real>
+__device__ __forceinline__ void walk_particle_ds(const StepArgs<Real> &a, const DsArgs<Real> &d, int64_t p) {
     const int marked = a.tet[p];
     if (marked > -2) return;
     int T = walker_tet(marked);
@@ -1080,20 +1098,27 @@ __device__ __forceinline__ void walk_particle_ds(const StepArgs<double> &a, cons
     l[3] = a.lam3[p];
     l[0] = 1.0 - l[1] - l[2] - l[3];
     int slot[4] = {d.vout, d.vin[0], d.vin[1], d.vin[2]};
-    double V[4][3];
+    Real V[4][3];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) V[i][c] = slot[i] >= 0 ? ds_v(d, slot[i], c)[p] : 0.0;
-    double dx[3] = {0.0, 0.0, 0.0};
+        for (int c = 0; c < 3; ++c) V[i][c] = slot[i] >= 0 ? ds_v(d, slot[i], c)[p] : (Real)0;
+    // the particle kernel's displacement, in the same arithmetic
+    Real dx[3] = {0, 0, 0};
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         if (i >= d.A) break;
 #pragma unroll
         for (int c = 0; c < 3; ++c) dx[c] += d.ab[i] * V[i][c];
     }
-    double v[3] = {a.v0[p], a.v1[p], a.v2[p]};
-    T = walk<double, false, 3>(a, T, l, dx, v, nullptr, V);
+    double dd[3] = {(double)dx[0], (double)dx[1], (double)dx[2]};
+    double ext[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ext[i][c] = (double)V[i][c];
+    Real v[3] = {a.v0[p], a.v1[p], a.v2[p]};
+    T = walk<Real, false, 3>(a, T, l, dd, v, nullptr, ext);
     a.tet[p] = T;
     a.lam1[p] = l[1];
     a.lam2[p] = l[2];
@@ -1105,7 +1130,7 @@ __device__ __forceinline__ void walk_particle_ds(const StepArgs<double> &a, cons
     for (int i = 0; i < 3; ++i)
         if (slot[i] >= 0)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) ds_v(d, slot[i], c)[p] = V[i][c];
+            for (int c = 0; c < 3; ++c) ds_v(d, slot[i], c)[p] = (Real)ext[i][c];
     if (a.rho) {
         const TetTopo tp = a.topo[T];
         const double l0 = 1.0 - l[1] - l[2] - l[3];
@@ -1116,7 +1141,8 @@ __device__ __forceinline__ void walk_particle_ds(const StepArgs<double> &a, cons
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_walk_ds(StepArgs<double> a, DsArgs d) {
+template <typename Real>
+__global__ void __launch_bounds__(kBlock) k_walk_ds(StepArgs<Real> a, DsArgs<Real> d) {
     walk_queued(a, blockIdx.x, gridDim.x, [&](int64_t p) { walk_particle_ds(a, d, p); });
 }
 
@@ -1595,13 +1621,13 @@ __global__ void __launch_bounds__(kBlock) k_scan_add(unsigned *__restrict__ x, i
     if (i < n) x[i] += sums[i / kScanTile];
 }
 
-// hsrc / hdst (optional): nh further float64 arrays of length n at stride n,
-// moved with the particles (the downshifted history).
+// hsrc / hdst (optional): nh further arrays of length n at stride n, of the
+// velocity type, moved with the particles (the downshifted history).
 template <typename Real>
 __global__ void __launch_bounds__(kBlock) k_scatter(int64_t n, int64_t nt, const int32_t *__restrict__ tet,
                                                     unsigned *__restrict__ cursor, etpic_particles src,
-                                                    etpic_particles dst, const double *__restrict__ hsrc = nullptr,
-                                                    double *__restrict__ hdst = nullptr, int nh = 0) {
+                                                    etpic_particles dst, const Real *__restrict__ hsrc = nullptr,
+                                                    Real *__restrict__ hdst = nullptr, int nh = 0) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int T = -1;
     if (p < n) {
@@ -2148,8 +2174,8 @@ struct etpic_ctx {
     }
 
     template <typename Real>
-    int sort(const etpic_particles *src, const etpic_particles *dst, hipStream_t st, const double *hsrc = nullptr,
-             double *hdst = nullptr, int nh = 0) {
+    int sort(const etpic_particles *src, const etpic_particles *dst, hipStream_t st, const Real *hsrc = nullptr,
+             Real *hdst = nullptr, int nh = 0) {
         if (int r = sort_count(src, st)) return r;
         k_scatter<Real><<<grid_for(src->n), kBlock, 0, st>>>(src->n, host.nt, src->tet, d_count, *src, *dst, hsrc,
                                                               hdst, nh);
@@ -2265,7 +2291,8 @@ struct etpic_ctx {
 
     // nsteps downshifted steps from step0 (t_n = n dt), hist0 of them taken
     // before; the complex-envelope rows are built once for the call.
-    int ds_steps(const etpic_particles *p, double *hist, const etpic_species *sp, const etpic_fields *f,
+    template <typename Real>
+    int ds_steps(const etpic_particles *p, void *hist, const etpic_species *sp, const etpic_fields *f,
                  int64_t step0, int nsteps, int hist0, double dt, double omega, double *dG, double *rho,
                  uint32_t flags, void *stream) {
         hipStream_t st = static_cast<hipStream_t>(stream);
@@ -2288,11 +2315,11 @@ struct etpic_ctx {
         for (int j = 0; j < nsteps; ++j) {
             const int64_t sn = step0 + j;
             const int H = hist0 + j;
-            StepArgs<double> a = step_args<double>(p, sp, dt, dG, j == nsteps - 1 ? rho : nullptr);
+            StepArgs<Real> a = step_args<Real>(p, sp, dt, dG, j == nsteps - 1 ? rho : nullptr);
             a.walk_by_slice = (flags & ETPIC_STEP_WALK_BY_SLICE) ? 1 : 0;
-            DsArgs d{};
+            DsArgs<Real> d{};
             d.coef_env = d_coef_env;
-            d.hist = hist;
+            d.hist = static_cast<Real *>(hist);
             d.stride = n;
             d.K = std::min(H, 2) + 1;
             d.A = std::min(H, 3) + 1;
@@ -2301,17 +2328,29 @@ struct etpic_ctx {
             d.vout = mod(sn, 4);
             for (int i = 0; i < 2; ++i) d.sin_[i] = i < H ? mod(sn - 1 - i, 2) : -1;
             d.sout = mod(sn, 2);
-            ds_weights(d.K, (double)sn * dt, dt, omega, d);
-            d.qm = sp->q / sp->m;
+            DsWeights W;
+            ds_weights(d.K, d.A, (double)sn * dt, dt, omega, W);
+            for (int k = 0; k < 3; ++k) {
+                d.Mr[k] = (Real)W.Mr[k];
+                d.Mi[k] = (Real)W.Mi[k];
+                d.P[k] = (Real)W.P[k];
+            }
+            for (int k = 0; k < 9; ++k) {
+                d.Lr[k] = (Real)W.Lr[k];
+                d.Li[k] = (Real)W.Li[k];
+                d.Q[k] = (Real)W.Q[k];
+            }
+            for (int k = 0; k < 4; ++k) d.ab[k] = (Real)W.ab[k];
+            d.qm = (Real)(sp->q / sp->m);
             d.edc = f->e_dc ? 1 : 0;
             if (ev) HIP_TRY(hipEventRecord(ev[2], st));
             if (a.rho)
-                k_push_ds<true><<<grid_for(n), kBlock, 0, st>>>(a, d, remap);
+                k_push_ds<Real, true><<<grid_for(n), kBlock, 0, st>>>(a, d, remap);
             else
-                k_push_ds<false><<<grid_for(n), kBlock, 0, st>>>(a, d, remap);
+                k_push_ds<Real, false><<<grid_for(n), kBlock, 0, st>>>(a, d, remap);
             HIP_TRY(hipGetLastError());
             if (ev) HIP_TRY(hipEventRecord(ev[3], st));
-            k_walk_ds<<<kWalkBlocks, kBlock, 0, st>>>(a, d);
+            k_walk_ds<Real><<<kWalkBlocks, kBlock, 0, st>>>(a, d);
             HIP_TRY(hipGetLastError());
             if (ev) {
                 HIP_TRY(hipEventRecord(ev[4], st));
@@ -2331,7 +2370,7 @@ struct etpic_ctx {
     // J_p = int_0^1 s^p e^{j theta s} ds (theta = w h) comes from its power
     // series for |theta| < 1 and from the integration-by-parts recurrence
     // J_p = (e^{j theta} - p J_{p-1}) / (j theta) above.
-    static void ds_weights(int K, double t0, double h, double omega, DsArgs &d) {
+    static void ds_weights(int K, int A, double t0, double h, double omega, DsWeights &d) {
         using cplx = std::complex<double>;
         double cf[3][3] = {{0.0}};
         if (K == 1) {
@@ -2393,7 +2432,6 @@ struct etpic_ctx {
                                          {1.5, -0.5, 0.0, 0.0},
                                          {23.0 / 12.0, -16.0 / 12.0, 5.0 / 12.0, 0.0},
                                          {55.0 / 24.0, -59.0 / 24.0, 37.0 / 24.0, -9.0 / 24.0}};
-        const int A = d.A;
         for (int i = 0; i < 4; ++i) d.ab[i] = h * kAB[A - 1][i];
     }
 
@@ -2766,32 +2804,40 @@ int etpic_sort_run_steps(etpic_ctx *ctx, const etpic_particles *src, const etpic
     return ctx->run_steps<float>(dst, sp, plans.data(), nsteps, dt, omega, dG, rho, flags, stream, src);
 }
 
-int etpic_ds_history_bytes(int64_t n, size_t *bytes_out) {
+static size_t ds_history_size(int64_t n, int precision) {
+    return (precision == ETPIC_FP64 ? sizeof(double) : sizeof(float)) * (size_t)kDsArrays * (size_t)n;
+}
+
+int etpic_ds_history_bytes(int64_t n, int precision, size_t *bytes_out) {
     if (!bytes_out || n < 0) return fail(ETPIC_EINVAL, "bad arguments");
-    *bytes_out = sizeof(double) * (size_t)kDsArrays * (size_t)n;
+    if (precision != ETPIC_FP64 && precision != ETPIC_MIXED) return fail(ETPIC_EINVAL, "bad precision %d", precision);
+    *bytes_out = ds_history_size(n, precision);
     return ETPIC_OK;
 }
 
-int etpic_ds_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, double *hist, size_t hist_bytes,
+int etpic_ds_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, void *hist, size_t hist_bytes,
                    const etpic_species *sp, const etpic_fields *f, int64_t step0, int nsteps, int hist0, double dt,
                    double omega, double *dG, double *rho, uint32_t flags, void *stream) {
     if (int r = check_step_args(ctx, sp, f, dt, omega)) return r;
     if (!dG) return fail(ETPIC_EINVAL, "null current accumulator");
     if (int r = check_particles(ctx, p)) return r;
     if (nsteps < 1 || hist0 < 0) return fail(ETPIC_EINVAL, "need nsteps >= 1 and hist0 >= 0");
-    if (precision != ETPIC_FP64) return fail(ETPIC_EINVAL, "the downshifted step takes float64 particles");
-    if (!hist || hist_bytes < sizeof(double) * (size_t)kDsArrays * (size_t)p->n)
+    if (precision != ETPIC_FP64 && precision != ETPIC_MIXED) return fail(ETPIC_EINVAL, "bad precision %d", precision);
+    if (!hist || hist_bytes < ds_history_size(p->n, precision))
         return fail(ETPIC_EINVAL, "history buffer missing or smaller than etpic_ds_history_bytes");
     if ((reinterpret_cast<uintptr_t>(hist) & 7) != 0) return fail(ETPIC_EINVAL, "history buffer not 8-byte aligned");
     if (p->n == 0) return ETPIC_OK;
     if (int r = set_device(ctx)) return r;
-    return ctx->ds_steps(p, hist, sp, f, step0, nsteps, hist0, dt, omega, dG, rho, flags, stream);
+    if (precision == ETPIC_FP64)
+        return ctx->ds_steps<double>(p, hist, sp, f, step0, nsteps, hist0, dt, omega, dG, rho, flags, stream);
+    return ctx->ds_steps<float>(p, hist, sp, f, step0, nsteps, hist0, dt, omega, dG, rho, flags, stream);
 }
 
-int etpic_ds_sort(etpic_ctx *ctx, const etpic_particles *src, const etpic_particles *dst, const double *hist_src,
-                  double *hist_dst, size_t hist_bytes, void *stream) {
+int etpic_ds_sort(etpic_ctx *ctx, const etpic_particles *src, const etpic_particles *dst, int precision,
+                  const void *hist_src, void *hist_dst, size_t hist_bytes, void *stream) {
     if (int r = check_sort_pair(ctx, src, dst)) return r;
-    const size_t need = sizeof(double) * (size_t)kDsArrays * (size_t)src->n;
+    if (precision != ETPIC_FP64 && precision != ETPIC_MIXED) return fail(ETPIC_EINVAL, "bad precision %d", precision);
+    const size_t need = ds_history_size(src->n, precision);
     if (!hist_src || !hist_dst || hist_bytes < need)
         return fail(ETPIC_EINVAL, "history buffers missing or smaller than etpic_ds_history_bytes");
     if (hist_src == hist_dst) return fail(ETPIC_EINVAL, "sort needs distinct history buffers");
@@ -2799,7 +2845,12 @@ int etpic_ds_sort(etpic_ctx *ctx, const etpic_particles *src, const etpic_partic
         return fail(ETPIC_EINVAL, "history buffers not 8-byte aligned");
     if (src->n == 0) return ETPIC_OK;
     if (int r = set_device(ctx)) return r;
-    return ctx->sort<double>(src, dst, static_cast<hipStream_t>(stream), hist_src, hist_dst, kDsArrays);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (precision == ETPIC_FP64)
+        return ctx->sort<double>(src, dst, st, static_cast<const double *>(hist_src), static_cast<double *>(hist_dst),
+                                 kDsArrays);
+    return ctx->sort<float>(src, dst, st, static_cast<const float *>(hist_src), static_cast<float *>(hist_dst),
+                            kDsArrays);
 }
 
 int etpic_adjoint_workspace(const etpic_ctx *ctx, int64_t n, int nsteps, int checkpoint_every, size_t *bytes_out) {

@@ -94,8 +94,8 @@ def lib():
     L.etpic_particles_positions.argtypes = [vp, C.POINTER(_Particles), C.c_void_p * 3, vp]
     L.etpic_run_steps.argtypes = [vp, C.POINTER(_Particles), C.c_int, C.POINTER(_Species), C.POINTER(_Fields),
                                   C.c_int64, C.c_int, C.c_double, C.c_double, vp, vp, C.c_uint32, vp]
-    L.etpic_ds_history_bytes.argtypes = [C.c_int64, C.POINTER(C.c_size_t)]
-    L.etpic_ds_sort.argtypes = [vp, C.POINTER(_Particles), C.POINTER(_Particles), vp, vp, C.c_size_t, vp]
+    L.etpic_ds_history_bytes.argtypes = [C.c_int64, C.c_int, C.POINTER(C.c_size_t)]
+    L.etpic_ds_sort.argtypes = [vp, C.POINTER(_Particles), C.POINTER(_Particles), C.c_int, vp, vp, C.c_size_t, vp]
     L.etpic_ds_steps.argtypes = [vp, C.POINTER(_Particles), C.c_int, vp, C.c_size_t, C.POINTER(_Species), C.POINTER(_Fields),
                                  C.c_int64, C.c_int, C.c_int, C.c_double, C.c_double, vp, vp, C.c_uint32, vp]
     L.etpic_sort_run_steps.argtypes = [vp, C.POINTER(_Particles), C.POINTER(_Particles), C.c_int,
@@ -349,11 +349,12 @@ class Context:
 
     # downshifted integrator (float64) --------------------------------------------
     def ds_history(self, parts):
-        """A zeroed history buffer for parts (float64 [48, n] on the device)."""
+        """A zeroed history buffer for parts ([48, n] of the velocity type on the device)."""
         import torch
         b = C.c_size_t(0)
-        _chk(lib().etpic_ds_history_bytes(int(parts.n), C.byref(b)))
-        return torch.zeros((b.value // (8 * max(parts.n, 1)), parts.n), dtype=torch.float64, device="cuda")
+        _chk(lib().etpic_ds_history_bytes(int(parts.n), parts.precision, C.byref(b)))
+        dt = torch.float64 if parts.precision == FP64 else torch.float32
+        return torch.zeros((b.value // (dt.itemsize * max(parts.n, 1)), parts.n), dtype=dt, device="cuda")
 
     def ds_steps(self, parts, hist, species, fields, step0, nsteps, hist0, dt, omega, dG, rho=None,
                  flags=STEP_XCD_REMAP, stream=None):
@@ -369,10 +370,10 @@ class Context:
 
     def ds_sort(self, src, dst, hist_src, hist_dst, stream=None):
         """sort(src, dst) that also moves the downshifted history."""
-        assert src.precision == FP64 and dst.precision == FP64
+        assert src.precision == dst.precision
         assert hist_src.shape == hist_dst.shape and hist_src.is_contiguous() and hist_dst.is_contiguous()
         a, b = src.desc(), dst.desc()
-        _chk(lib().etpic_ds_sort(self._h, C.byref(a), C.byref(b), C.c_void_p(hist_src.data_ptr()),
+        _chk(lib().etpic_ds_sort(self._h, C.byref(a), C.byref(b), src.precision, C.c_void_p(hist_src.data_ptr()),
                                  C.c_void_p(hist_dst.data_ptr()), hist_src.numel() * hist_src.element_size(),
                                  _stream(stream)))
 

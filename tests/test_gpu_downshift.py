@@ -1,7 +1,8 @@
 """GPU downshifted step (carrier-exact velocity quadrature of the interpolated
 envelope samples, Adams-Bashforth positions) against the oracle's, step by
 step from a fresh start (the order ramp included): positions, velocities,
-currents, and the continuity law on the GPU at every step."""
+currents, and the continuity law on the GPU at every step.  Float64 form to
+1e-12, mixed form (float32 samples, velocities and velocity update) to 2e-5."""
 import os
 import sys
 
@@ -32,17 +33,17 @@ def E():
     return etpic
 
 
-def run_against_oracle(E, torch, ora, w, steps, dt, flags, tol=1e-12, step0=5):
-    print(f"[ds] {w.name} N={w.tet.shape[0]} steps={steps} dt={dt} flags={flags}", flush=True)
+def run_against_oracle(E, torch, ora, w, steps, dt, flags, tol=1e-12, step0=5, precision=0):
+    print(f"[ds] {w.name} N={w.tet.shape[0]} steps={steps} dt={dt} flags={flags} precision={precision}", flush=True)
     ctx = E.Context(0)
     ctx.upload_mesh(w.xyz, w.tet_vert)
     f = E.Fields.from_numpy(w.e_env, w.b_env, None, w.b_dc)
     sp = E.Species(w.q, w.m, w.w)
-    parts = E.Particles.from_numpy(w.tet, w.lam, w.vel, w.ids)
+    parts = E.Particles.from_numpy(w.tet, w.lam, w.vel, w.ids, precision=precision)
     hist = ctx.ds_history(parts)
     M = ora.OracleMesh(w.xyz, w.tet_vert)
     H = ora.DsHistory(w.tet.shape[0])
-    t, l, v = w.tet.copy(), w.lam.copy(), w.vel.copy()
+    t, l, v = w.tet.copy(), w.lam.copy(), parts.to_numpy()[2].astype(np.float64)
     rho_old = torch.zeros(ctx.n_vert, dtype=torch.float64, device="cuda")
     ctx.vertex_charge(parts, sp, rho_old)
     worst = {}
@@ -67,20 +68,21 @@ def run_against_oracle(E, torch, ora, w, steps, dt, flags, tol=1e-12, step0=5):
         for k, val in err.items():
             worst[k] = max(worst.get(k, 0.0), val)
         # from here on compare against the GPU's own state (tet ids on faces may differ)
-        t, l, v = tg.copy(), lg.copy(), vg.copy()
+        t, l, v = tg.copy(), lg.copy(), vg.astype(np.float64)
     ctx.check()
     print(f"[ds] worst {worst}", flush=True)
     ctx.close()
     return worst
 
 
-def test_small_workload_every_step(E, torch_cuda, ora):
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 2e-5)])
+def test_small_workload_every_step(E, torch_cuda, ora, precision, tol):
     w = synth.make_workload(1)
-    run_against_oracle(E, torch_cuda, ora, w, 10, w.dt, E.STEP_XCD_REMAP)
+    run_against_oracle(E, torch_cuda, ora, w, 10, w.dt, E.STEP_XCD_REMAP, tol=tol, precision=precision)
 
 
-@pytest.mark.parametrize("by_slice", [False, True])
-def test_crossing_heavy_with_walls(E, torch_cuda, ora, by_slice):
+@pytest.mark.parametrize("by_slice,precision,tol", [(False, 0, 1e-12), (True, 0, 1e-12), (False, 1, 2e-5)])
+def test_crossing_heavy_with_walls(E, torch_cuda, ora, by_slice, precision, tol):
     """Steps of about 0.2 cell (4000 electrons 400x faster, dt 1 ns, B 1 mT so
     that the explicit magnetic update stays stable, the 1 GHz carrier sampled
     every 6.3 rad): many particles cross faces and hit the walls, where the
@@ -89,19 +91,21 @@ def test_crossing_heavy_with_walls(E, torch_cuda, ora, by_slice):
     w = synth.make_workload(1, n_particles=4000, b0=(0.0, 0.0, 1e-3))
     w.vel = w.vel * 400.0
     flags = E.STEP_XCD_REMAP | (E.STEP_WALK_BY_SLICE if by_slice else 0)
-    run_against_oracle(E, torch_cuda, ora, w, 8, 1e-9, flags)
+    run_against_oracle(E, torch_cuda, ora, w, 8, 1e-9, flags, tol=tol, precision=precision)
 
 
-def test_coarse_carrier_step_40cube(E, torch_cuda, ora):
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 2e-5)])
+def test_coarse_carrier_step_40cube(E, torch_cuda, ora, precision, tol):
     """200k electrons on the 40^3 mesh at dt = 5 ps (w dt = 0.31, Omega dt =
     0.44 in the 0.5 T field)."""
     w = synth.make_workload(2, n_particles=200_003)
     order = np.argsort(w.tet, kind="stable")
     w.tet, w.lam, w.vel, w.ids = w.tet[order], w.lam[order], w.vel[order], w.ids[order]
-    run_against_oracle(E, torch_cuda, ora, w, 6, 5e-12, E.STEP_XCD_REMAP)
+    run_against_oracle(E, torch_cuda, ora, w, 6, 5e-12, E.STEP_XCD_REMAP, tol=tol, precision=precision)
 
 
-def test_multi_step_call_equals_single_calls(E, torch_cuda):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_multi_step_call_equals_single_calls(E, torch_cuda, precision):
     torch = torch_cuda
     w = synth.make_workload(2, n_particles=300_000)
     order = np.argsort(w.tet, kind="stable")
@@ -110,7 +114,7 @@ def test_multi_step_call_equals_single_calls(E, torch_cuda):
     ctx.upload_mesh(w.xyz, w.tet_vert)
     f = E.Fields.from_numpy(w.e_env, w.b_env, None, w.b_dc)
     sp = E.Species(w.q, w.m, w.w)
-    p1 = E.Particles.from_numpy(w.tet, w.lam, w.vel, w.ids)
+    p1 = E.Particles.from_numpy(w.tet, w.lam, w.vel, w.ids, precision=precision)
     p2 = p1.clone()
     h1, h2 = ctx.ds_history(p1), ctx.ds_history(p2)
     g1 = torch.zeros(ctx.n_edge, dtype=torch.float64, device="cuda")
@@ -152,13 +156,14 @@ def test_argument_errors(E, torch_cuda):
     with pytest.raises(E.EtpicError):
         ctx.ds_steps(parts, hist, sp, f, 0, 1, -1, w.dt, w.omega, dG)
     mixed = E.Particles.from_numpy(w.tet, w.lam, w.vel, w.ids, precision=E.MIXED)
-    with pytest.raises(E.EtpicError):
-        ctx.ds_steps(mixed, hist, sp, f, 0, 1, 0, w.dt, w.omega, dG)
+    with pytest.raises(E.EtpicError):       # float64 particles with a float32-sized history
+        ctx.ds_steps(parts, ctx.ds_history(mixed), sp, f, 0, 1, 0, w.dt, w.omega, dG)
     ctx.check()
     ctx.close()
 
 
-def test_sort_carries_the_history(E, torch_cuda):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_sort_carries_the_history(E, torch_cuda, precision):
     """4 steps, a re-sort with etpic_ds_sort, 4 more steps continuing the
     numbering, against 8 steps without the sort: every particle's state is the
     same (matched by id), the currents equal to the atomics' rounding."""
@@ -169,7 +174,7 @@ def test_sort_carries_the_history(E, torch_cuda):
     f = E.Fields.from_numpy(w.e_env, w.b_env, None, w.b_dc)
     sp = E.Species(w.q, w.m, w.w)
     dt = 5 * w.dt
-    a = E.Particles.from_numpy(w.tet, w.lam, w.vel, w.ids)
+    a = E.Particles.from_numpy(w.tet, w.lam, w.vel, w.ids, precision=precision)
     b = a.clone()
     ha, hb = ctx.ds_history(a), ctx.ds_history(b)
     ga = torch.zeros(ctx.n_edge, dtype=torch.float64, device="cuda")

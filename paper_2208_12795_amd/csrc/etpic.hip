@@ -943,7 +943,7 @@ __global__ void __launch_bounds__(kBlock) k_push_ds(StepArgs<Real> a, DsArgs<Rea
         const Real lr[4] = {(Real)l[0], (Real)l[1], (Real)l[2], (Real)l[3]};
         Real S[6][3];   // E re, im, dc; B re, im, dc
 #pragma unroll
-        for (int part = 0; part < 6; ++part)
+        for (int part = 0; part < 3; ++part)
 #pragma unroll
             for (int c = 0; c < 3; ++c)
                 S[part][c] = (part == 2 && !d.edc)
@@ -971,6 +971,16 @@ __global__ void __launch_bounds__(kBlock) k_push_ds(StepArgs<Real> a, DsArgs<Rea
                 if (d.edc) acc[c] += ds_e(d, sl, 6 + c)[p] * d.P[k];
             }
         }
+        // the B rows are gathered only now: keeping the compiler from hoisting
+        // all 72 row values ahead of use halves the live registers (4
+        // wavefronts per SIMD instead of 2)
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int part = 3; part < 6; ++part)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                S[part][c] = lr[0] * (Real)row[12 * part + c] + lr[1] * (Real)row[12 * part + 3 + c] +
+                             lr[2] * (Real)row[12 * part + 6 + c] + lr[3] * (Real)row[12 * part + 9 + c];
         // magnetic part: sum_k (weighted B sample k) crossed with each v^{n-j}
 #pragma unroll
         for (int k = 0; k < 3; ++k) {

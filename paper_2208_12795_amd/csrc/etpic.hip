@@ -910,8 +910,11 @@ __device__ __forceinline__ Real *ds_b(const DsArgs<Real> &d, int slot, int i) { 
 // Real = double: the float64 form.  Real = float: samples, velocities and the
 // velocity update in float32, positions, the barycentric increments and the
 // deposit in float64 (the mixed form of the fine-step kernel).
+// (at most 128 VGPRs: 4 wavefronts per SIMD, which the float32 form does not
+// reach by itself)
 template <typename Real, bool kRho>
-__global__ void __launch_bounds__(kBlock) k_push_ds(StepArgs<Real> a, DsArgs<Real> d, int remap) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+k_push_ds(StepArgs<Real> a, DsArgs<Real> d, int remap) {
     unsigned blk = blockIdx.x;
     if (remap) {
         const unsigned G = gridDim.x, q = G / 8, r = G % 8, x = blk % 8, j = blk / 8;

@@ -88,10 +88,10 @@ enum etpic_step_flags {
     ETPIC_STEP_XCD_REMAP = 1u, /* map consecutive particle blocks to one XCD (default on) */
     ETPIC_STEP_TIMING = 2u,    /* bracket the step's kernels with HIP events (etpic_kernel_time) */
     /* slices of 64 particles per wavefront of the particle kernel; without one
-     * of these the library picks 1, 4 or 16 from the last etpic_sort's mean,
-     * over particles, of the number of particles in the same tet (1 before any
-     * sort).  Longer slices cut same-address atomics where thousands of
-     * particles share a tet. */
+     * of these the library picks 1, 4 or 16 from the last sort's (etpic_sort,
+     * etpic_sort_run_steps, etpic_ds_sort) mean, over particles, of the number
+     * of particles in the same tet (1 before any sort).  Longer slices cut
+     * same-address atomics where thousands of particles share a tet. */
     ETPIC_STEP_SLICES_1 = 4u,
     ETPIC_STEP_SLICES_4 = 8u,
     ETPIC_STEP_SLICES_16 = 16u,

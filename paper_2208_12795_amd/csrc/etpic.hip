@@ -214,6 +214,15 @@ struct PushRow<float> {
 // The coefficient pass reads the float64 push row (grad l_1..3 and the edge ids;
 // grad l_0 = -(grad l_1 + grad l_2 + grad l_3), the sum the mesh tables define it
 // by) and the four face ids of the tet: 112 B per tet.
+// The dispatcher deals consecutive blocks round-robin over the 8 XCDs; this
+// renumbering gives each XCD one contiguous range of the G blocks instead, so
+// the tets (and the edges and faces they share) of an XCD's blocks stay in its
+// L2.
+__device__ __forceinline__ unsigned xcd_block(unsigned c, unsigned G) {
+    const unsigned q = G / 8, r = G % 8, x = c % 8, j = c / 8;
+    return x * q + min(x, r) + j;
+}
+
 template <typename Real, int kSnap>
 __device__ __forceinline__ void tet_coef(int64_t nt, const double *__restrict__ prow,
                                          const int32_t *__restrict__ tetface, const FieldPtrs &F,
@@ -259,7 +268,7 @@ template <typename Real, int kSnap = 1>
 __global__ void __launch_bounds__(kBlock) k_tet_coef(int64_t nt, const double *__restrict__ prow,
                                                      const int32_t *__restrict__ tetface, FieldPtrs F,
                                                      Real *__restrict__ coef) {
-    tet_coef<Real, kSnap>(nt, prow, tetface, F, coef, blockIdx.x);
+    tet_coef<Real, kSnap>(nt, prow, tetface, F, coef, xcd_block(blockIdx.x, gridDim.x));
 }
 
 // ------------------------------------------------------------------ particle step
@@ -801,7 +810,8 @@ __global__ void __launch_bounds__(kBlock) k_walk_coef(StepArgs<Real> a, int64_t 
     if (blockIdx.x < kWalkBlocks)
         walk_queued(a, blockIdx.x, kWalkBlocks, [&](int64_t p) { walk_particle(a, p); });
     else
-        tet_coef<Real, kSnap>(nt, a.gpush64, a.tetface, F, const_cast<Real *>(a.coef), blockIdx.x - kWalkBlocks);
+        tet_coef<Real, kSnap>(nt, a.gpush64, a.tetface, F, const_cast<Real *>(a.coef),
+                              xcd_block(blockIdx.x - kWalkBlocks, gridDim.x - kWalkBlocks));
 }
 
 // ------------------------------------------------------------------ downshifted step

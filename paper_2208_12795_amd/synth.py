@@ -258,21 +258,21 @@ class Workload:
         return self.xyz.shape[0]
 
 
-CONFIGS = {
+WORKLOAD_TABLE = {
     # unit cube 5^3 x 6, 1e3 e-, vth 1e5, B 0.1 T z, random unit phasors 1e3 V/m, 1 GHz, dt 1e-11, 100 steps
-    1: dict(n=(5, 5, 5), extent=(1.0, 1.0, 1.0), n_p=1000, vth=1e5, b0=(0.0, 0.0, 0.1),
+    1: dict(name="cube5x6-1e3", n=(5, 5, 5), extent=(1.0, 1.0, 1.0), n_p=1000, vth=1e5, b0=(0.0, 0.0, 0.1),
             fields="phasor", amp=1e3, freq=1e9, dt=1e-11, steps=100, sort_every=0),
     # 40^3 x 6, 1e7 e-, vth 1e6, 8-mode envelope, 10 GHz, B 0.5 T z, dt 1e-12, 200 steps, sort every 10
-    2: dict(n=(40, 40, 40), extent=(1.0, 1.0, 1.0), n_p=10_000_000, vth=1e6, b0=(0.0, 0.0, 0.5),
+    2: dict(name="cube40x6-1e7", n=(40, 40, 40), extent=(1.0, 1.0, 1.0), n_p=10_000_000, vth=1e6, b0=(0.0, 0.0, 0.5),
             fields="modes", amp=1e3, freq=1e10, dt=1e-12, steps=200, sort_every=10),
     # same mesh, 5e7 particles (mixed-precision form)
-    3: dict(n=(40, 40, 40), extent=(1.0, 1.0, 1.0), n_p=50_000_000, vth=1e6, b0=(0.0, 0.0, 0.5),
+    3: dict(name="cube40x6-5e7", n=(40, 40, 40), extent=(1.0, 1.0, 1.0), n_p=50_000_000, vth=1e6, b0=(0.0, 0.0, 0.5),
             fields="modes", amp=1e3, freq=1e10, dt=1e-12, steps=200, sort_every=10),
     # 20^3 x 6, 2e6 e-, physics of the 40^3 case, 20 steps (differentiation form)
-    4: dict(n=(20, 20, 20), extent=(1.0, 1.0, 1.0), n_p=2_000_000, vth=1e6, b0=(0.0, 0.0, 0.5),
+    4: dict(name="cube20x6-2e6", n=(20, 20, 20), extent=(1.0, 1.0, 1.0), n_p=2_000_000, vth=1e6, b0=(0.0, 0.0, 0.5),
             fields="modes", amp=1e3, freq=1e10, dt=1e-12, steps=20, sort_every=0),
     # 2:1:1 box, 160x80x80 x 6, bunch + background, B 1 T x, 10 GHz, 1000 steps
-    5: dict(n=(160, 80, 80), extent=(2.0, 1.0, 1.0), n_p=200_000_000, vth=1e6, b0=(1.0, 0.0, 0.0),
+    5: dict(name="box160x80x80x6-2e8", n=(160, 80, 80), extent=(2.0, 1.0, 1.0), n_p=200_000_000, vth=1e6, b0=(1.0, 0.0, 0.0),
             fields="modes", amp=1e3, freq=1e10, dt=1e-12, steps=1000, sort_every=10, bunch=True),
 }
 
@@ -284,7 +284,7 @@ def rngs(k):
 
 def make_workload(k, n_particles=None, n_cells=None, omega=None, b0=None, amp=None):
     """Workload k (1..5) with optional overrides (smaller particle count / mesh)."""
-    c = dict(CONFIGS[k])
+    c = dict(WORKLOAD_TABLE[k])
     if n_cells is not None:
         c["n"] = tuple(n_cells)
     n_p = int(c["n_p"] if n_particles is None else n_particles)
@@ -317,7 +317,7 @@ def make_workload(k, n_particles=None, n_cells=None, omega=None, b0=None, amp=No
         e_env = mode_edge_dofs(xyz, edges, a, c["extent"], r_fld)
     b_env = faraday_face_envelope(e_env, edges, faces, nv, w)
     b_dc = uniform_face_flux(xyz, faces, c["b0"] if b0 is None else b0)
-    return Workload(name=f"config{k}", n=c["n"], extent=c["extent"], xyz=xyz, tet_vert=tv,
+    return Workload(name=c["name"], n=c["n"], extent=c["extent"], xyz=xyz, tet_vert=tv,
                     edges=edges, faces=faces, tet=tet.astype(np.int32),
                     lam=np.ascontiguousarray(lam, dtype=np.float64),
                     vel=np.ascontiguousarray(vel, dtype=np.float64),

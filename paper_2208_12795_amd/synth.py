@@ -283,7 +283,10 @@ def rngs(k):
 
 
 def make_workload(k, n_particles=None, n_cells=None, omega=None, b0=None, amp=None):
-    """Workload k (1..5) with optional overrides (smaller particle count / mesh)."""
+    """Workload k with optional overrides (smaller particle count / mesh):
+    1 = 5^3 x 6 tets, unit cube, 1e3 electrons; 2 = 40^3 x 6, 1e7; 3 = 40^3 x 6,
+    5e7; 4 = 20^3 x 6, 2e6; 5 = 160 x 80 x 80 x 6, 2:1:1 box, 2e8 (bunch and
+    background)."""
     c = dict(WORKLOAD_TABLE[k])
     if n_cells is not None:
         c["n"] = tuple(n_cells)

@@ -136,7 +136,7 @@ def test_locate_reports_outside_points(E, torch_cuda):
 
 
 def test_positions_match_oracle_and_round_trip(E, torch_cuda, ora):
-    """positions() against the oracle's x = sum lam_k r_k on the first-workload
+    """positions() against the oracle's x = sum lam_k r_k on the 5^3-cube workload
     particles, then locate(positions) gives back the same particles."""
     torch = torch_cuda
     w = synth.make_workload(1)

@@ -30,7 +30,8 @@
  * Ownership: the library owns the context state (status word, walk queues,
  * reduction words, allocated in etpic_create), the mesh tables, per-step
  * coefficient table and sort counters (etpic_mesh_upload, replaced by the next
- * upload) and the field-update matrices and work vectors (etpic_field_setup),
+ * upload) and the field-update matrices and work vectors (etpic_field_setup,
+ * etpic_ns_setup),
  * and the complex-envelope rows of the downshifted step (72 float64 per tet,
  * allocated by the first etpic_ds_steps call after a mesh upload);
  * etpic_destroy frees them all.  Particle arrays, field DoFs, outputs, the
@@ -393,6 +394,40 @@ int etpic_field_spmv(etpic_ctx *ctx, const double *x, double *y, double alpha_re
  * left unchanged) if the tolerance is not reached. */
 int etpic_field_step(etpic_ctx *ctx, double t_next, double *u, double *v, double *a, double *b, const double *gdd,
                      double tol, int max_iter, int *iters_out, double *resid_out, void *stream);
+
+/* ---- Non-solenoidal field of the quasi-Helmholtz split (Quasi Helmholtz or
+ * Coulomb gauge, Discrete System, eq. ns_equation; operators of App. A).
+ * Gauss' law is solved on its own: with D the node-to-edge incidence (the
+ * discrete gradient [grad]; -1 at an edge's lower vertex id, +1 at its
+ * higher), [*eps] the Whitney edge mass and C_z the map that grounds the wall
+ * nodes (vertices of boundary faces),
+ *     C_z^T D^T [*eps] D C_z x = -C_z^T (D^T e^{-j w t} G + e^{-j w t} rho0),
+ *     e_ns = D C_z x.
+ * G is the real path integral of the deposited current (the dG of the step
+ * calls, summed); rho0 the nodal charge present when that sum started (D^T G
+ * counts only the change).  D^T [*eps] D is the linear-element stiffness
+ * eps int grad W0_i . grad W0_j; it is real, so the solve is real and the
+ * carrier phase e^{-j w t} multiplies its solution.  Float64 throughout. */
+
+/* Assemble the nodal operator for permittivity eps (host), its Jacobi
+ * preconditioner and the device work vectors (allocates; replaced by the next
+ * call, freed by a mesh upload or etpic_destroy). */
+int etpic_ns_setup(etpic_ctx *ctx, double eps);
+
+/* Stored entries of the nodal operator (wall rows count one each) and, if
+ * wall_nodes_out is not NULL, the number of grounded wall nodes. */
+int etpic_ns_info(const etpic_ctx *ctx, int64_t *nnz_out, int64_t *wall_nodes_out);
+
+/* Solve eq. ns_equation.  G: N_e float64 (device, NULL = 0); rho0: N_n
+ * float64 (device, NULL = 0); t, omega: the carrier phase.  Outputs (device,
+ * either may be NULL but not both): x_out = nodal coefficients, 2*N_n float64
+ * (complex, interleaved; 0 on the wall), e_out = edge coefficients of the
+ * non-solenoidal electric field, 2*N_e float64 (complex).  Preconditioned CG
+ * stops when ||r|| / ||b|| <= tol (checked every 5 iterations) or after
+ * max_iter; *iters_out and *resid_out (may be NULL) report it.  Synchronises
+ * `stream`.  ENOCONV (outputs untouched) if the tolerance is not reached. */
+int etpic_ns_solve(etpic_ctx *ctx, const double *G, const double *rho0, double t, double omega, double *x_out,
+                   double *e_out, double tol, int max_iter, int *iters_out, double *resid_out, void *stream);
 
 /* Kernel times of the steps launched with ETPIC_STEP_TIMING since the last
  * reset, from HIP events recorded on the launch stream around each kernel,

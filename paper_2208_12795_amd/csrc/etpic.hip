@@ -1986,6 +1986,127 @@ __global__ void __launch_bounds__(kBlock) k_nm_correct(int64_t ne, const double2
     a[i] = xi;
 }
 
+// ---- non-solenoidal field of the quasi-Helmholtz split (eq. ns_equation):
+// Jacobi-preconditioned CG on the nodal operator D^T [*eps] D, real because
+// the operator is real (the carrier phase multiplies the solution).
+struct NsCsr {
+    int64_t nv;
+    const int32_t *rowptr, *col;
+    const double *S;
+};
+
+// b = -(D^T G + rho0) off the wall, 0 on it; x = 0, r = b, z = Dinv b,
+// p = q = 0; partial: r.z, 0, |r|^2, |b|^2.  (D^T G)_i sums +-G over the
+// edges at node i (+ where i is the head).
+__global__ void __launch_bounds__(kBlock) k_ns_start(int64_t nv, const int32_t *__restrict__ ptr,
+                                                     const int32_t *__restrict__ code, const double *__restrict__ G,
+                                                     const double *__restrict__ rho0, const uint8_t *__restrict__ wall,
+                                                     const double *__restrict__ dinv, double *__restrict__ x,
+                                                     double *__restrict__ r, double *__restrict__ z,
+                                                     double *__restrict__ p, double *__restrict__ q,
+                                                     double *__restrict__ partial) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (i < nv) {
+        double b = 0.0;
+        if (!wall[i]) {
+            double div = rho0 ? rho0[i] : 0.0;
+            if (G)
+                for (int32_t k = ptr[i]; k < ptr[i + 1]; ++k) {
+                    const int32_t c = code[k];
+                    const double g = G[c >> 1];
+                    div += (c & 1) ? g : -g;
+                }
+            b = -div;
+        }
+        const double zi = dinv[i] * b;
+        x[i] = 0.0;
+        r[i] = b;
+        z[i] = zi;
+        p[i] = 0.0;
+        q[i] = 0.0;
+        v[0] = b * zi;
+        v[2] = b * b;
+        v[3] = b * b;
+    }
+    block_sum4(v, partial);
+}
+
+// rho = r.z, beta = 0, |r|^2 and |b|^2 from the reduced start partials
+__global__ void k_ns_begin(double *__restrict__ sc, const double *__restrict__ red) {
+    if (threadIdx.x == 0) {
+        sc[0] = red[0];
+        sc[1] = 0.0;
+        sc[6] = 0.0;
+        sc[7] = 0.0;
+        sc[8] = red[2];
+        sc[9] = red[3];
+    }
+}
+
+// p = z + beta p and q = A p = A z + beta q (the direction update folded into
+// the product, so that no separate pass over p is needed), with the partials
+// of p . q.  kRowLanes lanes per row.
+__global__ void __launch_bounds__(kBlock) k_ns_apply(NsCsr S, const double *__restrict__ sc,
+                                                     const double *__restrict__ z, double *__restrict__ p,
+                                                     double *__restrict__ q, double *__restrict__ partial) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t row = t / kRowLanes;
+    const int sub = (int)(t % kRowLanes);
+    double az = 0.0;
+    if (row < S.nv)
+        for (int32_t j = S.rowptr[row] + sub; j < S.rowptr[row + 1]; j += kRowLanes) az += S.S[j] * z[S.col[j]];
+#pragma unroll
+    for (int off = kRowLanes / 2; off > 0; off >>= 1) az += __shfl_xor(az, off);
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (row < S.nv && sub == 0) {
+        const double be = sc[6];
+        const double pn = z[row] + be * p[row];
+        const double qn = az + be * q[row];
+        p[row] = pn;
+        q[row] = qn;
+        v[0] = pn * qn;
+    }
+    block_sum4(v, partial);
+}
+
+// x += alpha p, r -= alpha q, z = Dinv r, with the partials of r . z and |r|^2
+__global__ void __launch_bounds__(kBlock) k_ns_update(int64_t nv, const double *__restrict__ sc,
+                                                      const double *__restrict__ dinv, const double *__restrict__ p,
+                                                      const double *__restrict__ q, double *__restrict__ x,
+                                                      double *__restrict__ r, double *__restrict__ z,
+                                                      double *__restrict__ partial) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double al = sc[4];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (i < nv) {
+        x[i] += al * p[i];
+        const double ri = r[i] - al * q[i];
+        r[i] = ri;
+        const double zi = dinv[i] * ri;
+        z[i] = zi;
+        v[0] = ri * zi;
+        v[2] = ri * ri;
+    }
+    block_sum4(v, partial);
+}
+
+// x_out = e^{-j w t} x on the nodes, e_out = e^{-j w t} D x on the edges
+// (edge e from ev[2e] to ev[2e+1]); either output may be NULL.
+__global__ void __launch_bounds__(kBlock) k_ns_out(int64_t ne, int64_t nv, const int32_t *__restrict__ ev,
+                                                   const double *__restrict__ x, double c, double s,
+                                                   double2 *__restrict__ x_out, double2 *__restrict__ e_out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e_out && i < ne) {
+        const double d = x[ev[2 * i + 1]] - x[ev[2 * i]];
+        e_out[i] = make_double2(c * d, -s * d);
+    }
+    if (x_out && i < nv) {
+        const double xi = x[i];
+        x_out[i] = make_double2(c * xi, -s * xi);
+    }
+}
+
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
@@ -2013,6 +2134,29 @@ struct FieldState {
                         (void *)dinv, (void *)vec, (void *)partial, (void *)red, (void *)sc})
             (void)hipFree(q);
         *this = FieldState();
+    }
+};
+
+// Device state of the non-solenoidal solve (allocated by etpic_ns_setup).
+struct NsState {
+    bool ready = false;
+    double eps = 0;
+    int64_t nv = 0, ne = 0, nnz = 0, nb = 0, n_wall = 0;
+    int32_t *rowptr = nullptr, *col = nullptr, *ev = nullptr;
+    double *S = nullptr, *dinv = nullptr;
+    uint8_t *wall = nullptr;
+    double *vec = nullptr;      // 5 work vectors of nv: x, r, z, p, q
+    double *partial = nullptr;  // 4 per block
+    double *red = nullptr;      // 4 reductions
+    double *sc = nullptr;       // 10 scalars, laid out as the COCG ones (imaginary parts 0)
+
+    double *v(int k) const { return vec + (size_t)k * nv; }
+    NsCsr csr() const { return NsCsr{nv, rowptr, col, S}; }
+    void release() {
+        for (void *q : {(void *)rowptr, (void *)col, (void *)ev, (void *)S, (void *)dinv, (void *)wall, (void *)vec,
+                        (void *)partial, (void *)red, (void *)sc})
+            (void)hipFree(q);
+        *this = NsState();
     }
 };
 
@@ -2077,6 +2221,7 @@ struct etpic_ctx {
     unsigned *d_tilesum = nullptr;   // scan tile totals
     int64_t tiles = 0;
     FieldState field;
+    NsState ns;
     // HIP events bracketing the kernels of steps run with ETPIC_STEP_TIMING:
     // 5 events per step (before and after the coefficient kernel, before and
     // after the particle kernel, after the walk kernel), and whether the
@@ -2496,6 +2641,7 @@ struct etpic_ctx {
         grid = GridArgs{};
         d_count = d_tilesum = nullptr;
         field.release();
+        ns.release();
         has_mesh = false;
     }
 };
@@ -3195,6 +3341,109 @@ int etpic_field_step(etpic_ctx *ctx, double t_next, double *u, double *v, double
     if (!(rel <= tol)) return fail(ETPIC_ENOCONV, "COCG: relative residual %.3e after %d iterations", rel, it);
     k_nm_faraday<<<grid_for(F.nf), kBlock, 0, st>>>(F.nf, F.face_edge, U, us, x, reinterpret_cast<double2 *>(b), dt, w);
     k_nm_correct<<<ge, kBlock, 0, st>>>(ne, us, vs, x, U, V, A, dt);
+    HIP_TRY(hipGetLastError());
+    return ETPIC_OK;
+}
+
+int etpic_ns_setup(etpic_ctx *ctx, double eps) {
+    if (!ctx) return fail(ETPIC_EINVAL, "null context");
+    if (!ctx->has_mesh) return fail(ETPIC_ESTATE, "no mesh uploaded");
+    if (!(eps > 0.0) || !std::isfinite(eps)) return fail(ETPIC_EINVAL, "eps must be positive");
+    std::string err;
+    etpic::NsSystem S;
+    if (etpic::build_ns_system(ctx->host, eps, S, err) != 0) return fail(ETPIC_EINVAL, "ns: %s", err.c_str());
+    const int64_t nv = S.nv, ne = ctx->host.ne;
+    std::vector<double> dinv((size_t)nv, 0.0);
+    for (int64_t i = 0; i < nv; ++i) {
+        double d = 0.0;
+        for (int32_t j = S.rowptr[i]; j < S.rowptr[i + 1]; ++j)
+            if (S.col[j] == i) d = S.S[j];
+        if (!(d > 0.0)) return fail(ETPIC_EMESH, "ns: non-positive diagonal at node %lld", (long long)i);
+        dinv[i] = 1.0 / d;
+    }
+    if (int r = set_device(ctx)) return r;
+    HIP_TRY(hipDeviceSynchronize());
+    NsState &N = ctx->ns;
+    N.release();
+    N.eps = eps;
+    N.nv = nv;
+    N.ne = ne;
+    N.nnz = S.nnz;
+    for (uint8_t b : S.wall) N.n_wall += b;
+    N.nb = (int64_t)grid_for(nv * kRowLanes);
+    HIP_TRY(hipMalloc(&N.rowptr, sizeof(int32_t) * (nv + 1)));
+    HIP_TRY(hipMalloc(&N.col, sizeof(int32_t) * S.nnz));
+    HIP_TRY(hipMalloc(&N.ev, sizeof(int32_t) * 2 * ne));
+    HIP_TRY(hipMalloc(&N.S, sizeof(double) * S.nnz));
+    HIP_TRY(hipMalloc(&N.dinv, sizeof(double) * nv));
+    HIP_TRY(hipMalloc(&N.wall, sizeof(uint8_t) * nv));
+    HIP_TRY(hipMalloc(&N.vec, sizeof(double) * 5 * nv));
+    HIP_TRY(hipMalloc(&N.partial, sizeof(double) * 4 * N.nb));
+    HIP_TRY(hipMalloc(&N.red, sizeof(double) * 4));
+    HIP_TRY(hipMalloc(&N.sc, sizeof(double) * 10));
+    HIP_TRY(hipMemcpy(N.rowptr, S.rowptr.data(), sizeof(int32_t) * (nv + 1), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(N.col, S.col.data(), sizeof(int32_t) * S.nnz, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(N.ev, ctx->host.edges.data(), sizeof(int32_t) * 2 * ne, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(N.S, S.S.data(), sizeof(double) * S.nnz, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(N.dinv, dinv.data(), sizeof(double) * nv, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(N.wall, S.wall.data(), sizeof(uint8_t) * nv, hipMemcpyHostToDevice));
+    N.ready = true;
+    return ETPIC_OK;
+}
+
+int etpic_ns_info(const etpic_ctx *ctx, int64_t *nnz_out, int64_t *wall_nodes_out) {
+    if (!ctx || !nnz_out) return fail(ETPIC_EINVAL, "null argument");
+    if (!ctx->ns.ready) return fail(ETPIC_ESTATE, "etpic_ns_setup not called");
+    *nnz_out = ctx->ns.nnz;
+    if (wall_nodes_out) *wall_nodes_out = ctx->ns.n_wall;
+    return ETPIC_OK;
+}
+
+int etpic_ns_solve(etpic_ctx *ctx, const double *G, const double *rho0, double t, double omega, double *x_out,
+                   double *e_out, double tol, int max_iter, int *iters_out, double *resid_out, void *stream) {
+    if (!ctx) return fail(ETPIC_EINVAL, "null context");
+    if (!x_out && !e_out) return fail(ETPIC_EINVAL, "no output: x_out and e_out are both NULL");
+    if (!ctx->ns.ready) return fail(ETPIC_ESTATE, "etpic_ns_setup not called");
+    if (!(tol > 0.0) || max_iter < 1 || !std::isfinite(t) || !std::isfinite(omega))
+        return fail(ETPIC_EINVAL, "bad tol / max_iter / time / omega");
+    if (int r = set_device(ctx)) return r;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const NsState &N = ctx->ns;
+    const int64_t nv = N.nv;
+    const unsigned gv = grid_for(nv), gr = grid_for(nv * kRowLanes);
+    double *x = N.v(0), *r = N.v(1), *z = N.v(2), *p = N.v(3), *q = N.v(4);
+    k_ns_start<<<gv, kBlock, 0, st>>>(nv, ctx->d_v2e_ptr, ctx->d_v2e_code, G, rho0, N.wall, N.dinv, x, r, z, p, q,
+                                      N.partial);
+    k_reduce4<<<1, kBlock, 0, st>>>(gv, N.partial, N.red);
+    k_ns_begin<<<1, 64, 0, st>>>(N.sc, N.red);
+    HIP_TRY(hipGetLastError());
+    double hs[10];
+    HIP_TRY(hipMemcpyAsync(hs, N.sc, sizeof hs, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const double bnorm2 = hs[9];
+    double rel = bnorm2 > 0.0 ? std::sqrt(hs[8] / bnorm2) : 0.0;
+    int it = 0;
+    const int check = 5;
+    while (rel > tol && it < max_iter) {
+        k_ns_apply<<<gr, kBlock, 0, st>>>(N.csr(), N.sc, z, p, q, N.partial);
+        k_cocg_scalars<<<1, kBlock, 0, st>>>(gr, N.partial, N.sc, 0);
+        k_ns_update<<<gv, kBlock, 0, st>>>(nv, N.sc, N.dinv, p, q, x, r, z, N.partial);
+        k_cocg_scalars<<<1, kBlock, 0, st>>>(gv, N.partial, N.sc, 1);
+        HIP_TRY(hipGetLastError());
+        ++it;
+        if (it % check == 0 || it == max_iter) {
+            HIP_TRY(hipMemcpyAsync(hs, N.sc, sizeof hs, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            rel = std::sqrt(hs[8] / bnorm2);
+            if (!std::isfinite(rel)) break;
+        }
+    }
+    if (iters_out) *iters_out = it;
+    if (resid_out) *resid_out = rel;
+    if (!(rel <= tol)) return fail(ETPIC_ENOCONV, "ns CG: relative residual %.3e after %d iterations", rel, it);
+    k_ns_out<<<grid_for(std::max(N.ne, nv)), kBlock, 0, st>>>(N.ne, nv, N.ev, x, std::cos(omega * t),
+                                                              std::sin(omega * t), reinterpret_cast<double2 *>(x_out),
+                                                              reinterpret_cast<double2 *>(e_out));
     HIP_TRY(hipGetLastError());
     return ETPIC_OK;
 }

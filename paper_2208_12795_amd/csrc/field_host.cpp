@@ -5,6 +5,9 @@
 //   W1_pq = l_p g_q - l_q g_p  =>  int W1_pq . W1_rs = I_pr g_q.g_s - I_ps g_q.g_r - I_qr g_p.g_s + I_qs g_p.g_r,
 //   curl W1_pq = 2 g_p x g_q   =>  int curl W1_pq . curl W1_rs = 4 V (g_p x g_q).(g_r x g_s).
 // Local edges keep the global orientation (tet vertices are in ascending id).
+//
+// The nodal operator of the non-solenoidal field is the linear-element
+// stiffness: int grad l_p . grad l_r dV = V g_p . g_r.
 #include "field_host.hpp"
 
 #include <algorithm>
@@ -107,6 +110,61 @@ int build_field_system(const HostMesh &mesh, double eps, double mu, FieldSystem 
         S.face_edge[3 * f + 1] = find(b, c);
         S.face_edge[3 * f + 2] = find(a, c);
     }
+    return 0;
+}
+
+int build_ns_system(const HostMesh &mesh, double eps, NsSystem &S, std::string &err) {
+    if (!(eps > 0.0)) {
+        err = "eps must be positive";
+        return -1;
+    }
+    const int64_t nt = mesh.nt, nv = mesh.nv;
+    S = NsSystem();
+    S.nv = nv;
+    S.wall.assign((size_t)nv, 0);
+    for (int64_t t = 0; t < nt; ++t) {
+        const TetTopo &tp = mesh.topo[t];
+        for (int f = 0; f < 4; ++f) {
+            if (tp.n[f] >= 0) continue;
+            for (int k = 0; k < 4; ++k)
+                if (k != f) S.wall[tp.v[k]] = 1;
+        }
+    }
+    struct NEntry {
+        int64_t key;
+        double s;
+    };
+    std::vector<NEntry> ent;
+    ent.reserve((size_t)nt * 16 + (size_t)nv);
+    for (int64_t t = 0; t < nt; ++t) {
+        const TetTopo &tp = mesh.topo[t];
+        const double *g = &mesh.grad[(size_t)t * 12];
+        const double V = mesh.vol[t];
+        for (int a = 0; a < 4; ++a) {
+            const int32_t i = tp.v[a];
+            if (S.wall[i]) continue;
+            for (int b = 0; b < 4; ++b) {
+                const int32_t j = tp.v[b];
+                if (S.wall[j]) continue;
+                ent.push_back({(int64_t)i * nv + j, eps * V * dot3(g + 3 * a, g + 3 * b)});
+            }
+        }
+    }
+    for (int64_t i = 0; i < nv; ++i)
+        if (S.wall[i]) ent.push_back({i * nv + i, 1.0});
+    std::sort(ent.begin(), ent.end(), [](const NEntry &x, const NEntry &y) { return x.key < y.key; });
+    S.rowptr.assign((size_t)nv + 1, 0);
+    for (size_t i = 0; i < ent.size();) {
+        size_t j = i;
+        double s = 0.0;
+        while (j < ent.size() && ent[j].key == ent[i].key) s += ent[j++].s;
+        S.col.push_back((int32_t)(ent[i].key % nv));
+        S.S.push_back(s);
+        S.rowptr[ent[i].key / nv + 1]++;
+        i = j;
+    }
+    for (int64_t r = 0; r < nv; ++r) S.rowptr[r + 1] += S.rowptr[r];
+    S.nnz = (int64_t)S.col.size();
     return 0;
 }
 

@@ -25,4 +25,19 @@ struct FieldSystem {
 
 int build_field_system(const HostMesh &mesh, double eps, double mu, FieldSystem &out, std::string &err);
 
+// Nodal operator of the non-solenoidal field (eq. ns_equation):
+//   S[i][j] = eps int grad W0_i . grad W0_j = (D^T [*eps] D)[i][j],
+// D the node-to-edge incidence.  Wall nodes (vertices of faces with one
+// owning tet) are grounded: their rows are the identity and their columns
+// are dropped from the other rows.  Rows sorted.
+struct NsSystem {
+    int64_t nv = 0, nnz = 0;
+    std::vector<int32_t> rowptr;     // nv + 1
+    std::vector<int32_t> col;        // nnz
+    std::vector<double> S;           // nnz
+    std::vector<uint8_t> wall;       // nv
+};
+
+int build_ns_system(const HostMesh &mesh, double eps, NsSystem &out, std::string &err);
+
 }  // namespace etpic

@@ -33,6 +33,7 @@ EXPORTS = (
     "etpic_field_setup", "etpic_field_nnz", "etpic_field_spmv", "etpic_field_step",
     "etpic_particles_locate", "etpic_particles_positions", "etpic_coarse_step", "etpic_run_steps",
     "etpic_sort_run_steps", "etpic_ds_history_bytes", "etpic_ds_steps", "etpic_ds_sort",
+    "etpic_ns_setup", "etpic_ns_info", "etpic_ns_solve",
 )
 
 
@@ -108,6 +109,10 @@ def lib():
     L.etpic_field_spmv.argtypes = [vp, vp, vp, C.c_double, C.c_double, C.c_double, vp]
     L.etpic_field_step.argtypes = [vp, C.c_double, vp, vp, vp, vp, vp, C.c_double, C.c_int, C.POINTER(C.c_int),
                                    dp, vp]
+    L.etpic_ns_setup.argtypes = [vp, C.c_double]
+    L.etpic_ns_info.argtypes = [vp, i64p, i64p]
+    L.etpic_ns_solve.argtypes = [vp, vp, vp, C.c_double, C.c_double, vp, vp, C.c_double, C.c_int,
+                                 C.POINTER(C.c_int), dp, vp]
     for name in EXPORTS:
         if name != "etpic_last_error":
             getattr(L, name).restype = C.c_int
@@ -470,6 +475,27 @@ class Context:
         res = C.c_double(0.0)
         rc = lib().etpic_field_step(self._h, float(t_next), _dptr(u), _dptr(v), _dptr(a), _dptr(b), _dptr(gdd),
                                     float(tol), int(max_iter), C.byref(it), C.byref(res), _stream(stream))
+        if raise_on_error:
+            _chk(rc)
+        return rc, it.value, res.value
+
+    def ns_setup(self, eps):
+        """Assemble the nodal operator of the non-solenoidal solve; returns
+        (stored entries, grounded wall nodes)."""
+        _chk(lib().etpic_ns_setup(self._h, float(eps)))
+        nnz, wall = C.c_int64(0), C.c_int64(0)
+        _chk(lib().etpic_ns_info(self._h, C.byref(nnz), C.byref(wall)))
+        return nnz.value, wall.value
+
+    def ns_solve(self, G=None, rho0=None, t=0.0, omega=0.0, x_out=None, e_out=None, tol=1e-12, max_iter=2000,
+                 stream=None, raise_on_error=True):
+        """Gauss-law solve: x_out float64 [N_n, 2] and e_out float64 [N_e, 2]
+        (complex; either may be None); G float64 [N_e], rho0 float64 [N_n] or
+        None.  Returns (status, iterations, relative residual)."""
+        it = C.c_int(0)
+        res = C.c_double(0.0)
+        rc = lib().etpic_ns_solve(self._h, _dptr(G), _dptr(rho0), float(t), float(omega), _dptr(x_out), _dptr(e_out),
+                                  float(tol), int(max_iter), C.byref(it), C.byref(res), _stream(stream))
         if raise_on_error:
             _chk(rc)
         return rc, it.value, res.value

@@ -1,0 +1,155 @@
+"""GPU non-solenoidal (Gauss-law) field solve (nodal CSR operator assembled in
+closed form, Jacobi-preconditioned CG) against the oracle's operator built as
+D^T [*eps] D from its quadrature edge mass and solved by sparse LU; and the
+field of the charge moved by GPU steps against the field of the charge where
+the particles end."""
+import numpy as np
+import pytest
+
+from paper_2208_12795_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+EPS0 = 8.8541878128e-12
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def E():
+    from paper_2208_12795_amd import etpic
+    return etpic
+
+
+def t2c(t):
+    a = t.cpu().numpy()
+    return a[:, 0] + 1j * a[:, 1]
+
+
+def rel(x, y):
+    return np.abs(x - y).max() / np.abs(y).max()
+
+
+def solve_both(E, torch, ora, xyz, tv, G, rho0, t, w, tol):
+    from oracle import gauss
+    ctx = E.Context(0)
+    ctx.upload_mesh(xyz, tv)
+    nnz, n_wall = ctx.ns_setup(EPS0)
+    m = ora.OracleMesh(xyz, tv)
+    ns = gauss.NsOracle(m, EPS0)
+    assert n_wall == int(ns.wall.sum())
+    x = torch.zeros((ctx.n_vert, 2), dtype=torch.float64, device="cuda")
+    e = torch.zeros((ctx.n_edge, 2), dtype=torch.float64, device="cuda")
+    tG = None if G is None else torch.from_numpy(G).cuda()
+    tr = None if rho0 is None else torch.from_numpy(rho0).cuda()
+    _, iters, res = ctx.ns_solve(tG, tr, t, w, x, e, tol=tol)
+    print(f"[ns] N_n={ctx.n_vert} nnz={nnz} wall={n_wall} iterations={iters} residual={res:.2e}", flush=True)
+    assert res <= tol
+    xo, eo = ns.solve(G, rho0, t, w)
+    ctx.close()
+    return t2c(x), t2c(e), xo, eo, ns, iters
+
+
+@pytest.mark.parametrize("source", ["G", "rho0", "both"])
+def test_small_mesh_matches_oracle(E, torch_cuda, ora, source):
+    """Jittered 5x4x6 Kuhn mesh, random G and / or nodal charge, carrier phase
+    at t = 0.37 ns, 1.3 GHz: nodes and edges to 1e-10 of the largest value
+    (CG to a 1e-14 relative residual), Gauss' law at the inner nodes."""
+    xyz, tv = synth.kuhn_mesh((5, 4, 6), (1.0, 0.9, 1.1), 0.15, np.random.default_rng(3))
+    rng = np.random.default_rng(11)
+    ne = synth.mesh_edges(tv, xyz.shape[0]).shape[0]
+    G = rng.standard_normal(ne) * 1e-15 if source in ("G", "both") else None
+    rho0 = rng.standard_normal(xyz.shape[0]) * 1e-15 if source in ("rho0", "both") else None
+    t, w = 3.7e-10, 2 * np.pi * 1.3e9
+    x, e, xo, eo, ns, _ = solve_both(E, torch_cuda, ora, xyz, tv, G, rho0, t, w, 1e-14)
+    assert rel(x, xo) <= 1e-10 and rel(e, eo) <= 1e-10, (rel(x, xo), rel(e, eo))
+    assert np.all(x[ns.wall] == 0)
+    r, scale = ns.gauss_residual(e, G, rho0, t, w)
+    assert r <= 1e-11 * scale, r / scale
+
+
+def test_bench_mesh_matches_oracle(E, torch_cuda, ora):
+    """The 40^3 x 6 mesh of the throughput workload (68921 nodes) with the
+    charge of 200k electrons of that workload: nodes and edges to 1e-9."""
+    w = synth.make_workload(2, n_particles=200_000)
+    m = ora.OracleMesh(w.xyz, w.tet_vert)
+    rho0 = m.charge(w.tet, w.lam, w.q, w.w)
+    x, e, xo, eo, ns, iters = solve_both(E, torch_cuda, ora, w.xyz, w.tet_vert, None, rho0, 1e-9, w.omega, 1e-13)
+    assert rel(x, xo) <= 1e-9 and rel(e, eo) <= 1e-9, (rel(x, xo), rel(e, eo))
+    r, scale = ns.gauss_residual(e, None, rho0, 1e-9, w.omega)
+    assert r <= 1e-10 * scale, r / scale
+    assert iters < 2000
+
+
+def test_field_of_moved_charge(E, torch_cuda):
+    """300k electrons pushed 4 steps on the GPU at 60x the workload's dt (a few
+    percent cross faces each step): the solve from the starting charge plus the
+    deposited D^T G equals the solve of the charge where they end."""
+    torch = torch_cuda
+    w = synth.make_workload(2, n_particles=300_000)
+    ctx = E.Context(0)
+    ctx.upload_mesh(w.xyz, w.tet_vert)
+    ctx.ns_setup(EPS0)
+    f = E.Fields.from_numpy(w.e_env, w.b_env, None, w.b_dc)
+    sp = E.Species(w.q, w.m, w.w)
+    parts = E.Particles.from_numpy(w.tet, w.lam, w.vel, w.ids)
+    rho_a = torch.zeros(ctx.n_vert, dtype=torch.float64, device="cuda")
+    ctx.vertex_charge(parts, sp, rho_a)
+    dG = torch.zeros(ctx.n_edge, dtype=torch.float64, device="cuda")
+    ctx.run_steps(parts, sp, f, 0, 4, 60 * w.dt, w.omega, dG, flags=E.STEP_XCD_REMAP)
+    ctx.check()
+    moved = (parts.tet.cpu().numpy() != w.tet).mean()
+    assert moved > 0.02, moved
+    rho_b = torch.zeros_like(rho_a)
+    ctx.vertex_charge(parts, sp, rho_b)
+    out = []
+    for G, r0 in ((dG, rho_a), (None, rho_b)):
+        x = torch.zeros((ctx.n_vert, 2), dtype=torch.float64, device="cuda")
+        e = torch.zeros((ctx.n_edge, 2), dtype=torch.float64, device="cuda")
+        ctx.ns_solve(G, r0, 2.5e-9, w.omega, x, e, tol=1e-13)
+        out.append((t2c(x), t2c(e)))
+    (x1, e1), (x2, e2) = out
+    print(f"[ns] moved {moved:.3f}: nodes {rel(x1, x2):.2e} edges {rel(e1, e2):.2e}", flush=True)
+    assert rel(x1, x2) <= 1e-9 and rel(e1, e2) <= 1e-9
+    ctx.close()
+
+
+def test_one_output_and_errors(E, torch_cuda):
+    torch = torch_cuda
+    xyz, tv = synth.kuhn_mesh((4, 4, 4), (1.0, 1.0, 1.0), 0.1, np.random.default_rng(2))
+    ctx = E.Context(0)
+    ctx.upload_mesh(xyz, tv)
+    rho0 = torch.from_numpy(np.random.default_rng(1).standard_normal(ctx.n_vert)).cuda()
+    x = torch.zeros((ctx.n_vert, 2), dtype=torch.float64, device="cuda")
+    e = torch.zeros((ctx.n_edge, 2), dtype=torch.float64, device="cuda")
+    with pytest.raises(E.EtpicError):           # no setup
+        ctx.ns_solve(None, rho0, 0.0, 0.0, x, e)
+    ctx.ns_setup(EPS0)
+    with pytest.raises(E.EtpicError):           # no output
+        ctx.ns_solve(None, rho0, 0.0, 0.0, None, None)
+    with pytest.raises(E.EtpicError):
+        ctx.ns_solve(None, rho0, 0.0, 0.0, x, e, tol=0.0)
+    with pytest.raises(E.EtpicError):
+        ctx.ns_setup(-1.0)
+    x.fill_(7.0)
+    e.fill_(7.0)
+    rc, iters, res = ctx.ns_solve(None, rho0, 0.0, 0.0, x, e, tol=1e-300, max_iter=3, raise_on_error=False)
+    assert rc == E.ENOCONV and iters == 3 and res > 0
+    assert bool((x == 7.0).all()) and bool((e == 7.0).all())   # untouched on failure
+    # each output alone equals the pair
+    ctx.ns_solve(None, rho0, 1e-9, 3e9, x, e)
+    x1 = torch.zeros_like(x)
+    e1 = torch.zeros_like(e)
+    ctx.ns_solve(None, rho0, 1e-9, 3e9, x1, None)
+    ctx.ns_solve(None, rho0, 1e-9, 3e9, None, e1)
+    assert torch.equal(x, x1) and torch.equal(e, e1)
+    # no source: zero field without iterations
+    _, iters, _ = ctx.ns_solve(None, None, 0.0, 0.0, x1, e1)
+    assert iters == 0 and torch.count_nonzero(x1) == 0 and torch.count_nonzero(e1) == 0
+    ctx.close()

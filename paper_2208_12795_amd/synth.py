@@ -346,3 +346,56 @@ def envelope_snapshots(w, seed=1, count=3, drift=0.3):
 def as_interleaved(z):
     """complex128[N] -> float64[N,2] (re, im) contiguous, the device layout."""
     return np.ascontiguousarray(np.stack([z.real, z.imag], axis=1))
+
+
+# --------------------------------------------------------------- cold plasma
+EPS0 = 8.8541878128e-12
+E_CHARGE = -1.602176634e-19
+E_MASS = 9.1093837015e-31
+
+
+@dataclass
+class ColdPlasma:
+    """Electrons at rest in the unjittered box [0, L]^3, displaced from
+    uniform random places u0 by xi = a grad psi, psi = sin(kx) sin(ky)
+    sin(kz), k = pi / L, with a neutralising background (the charge of the
+    undisplaced electrons, with the opposite sign).  The macroparticle weight
+    sets the electron density n so that the plasma frequency is omega_p."""
+    n: tuple
+    extent: tuple
+    xyz: np.ndarray
+    tet_vert: np.ndarray
+    tet0: np.ndarray        # undisplaced places
+    lam0: np.ndarray
+    tet: np.ndarray         # displaced places
+    lam: np.ndarray
+    vel: np.ndarray
+    ids: np.ndarray
+    q: float
+    m: float
+    w: float
+    density: float          # electrons per m^3
+    a: float                # displacement scale [m^2]
+    omega_p: float
+
+
+def cold_plasma(n_cells, n_particles, amp=1e-3, omega_p=2 * np.pi * 1e9, L=0.1, seed=1):
+    """Cold-plasma oscillation input; amp * L / pi is the largest displacement
+    component over grad psi / k (a = amp * L^2 / pi^2)."""
+    rng = np.random.default_rng(np.random.SeedSequence([SEED_BASE, 91, seed]))
+    n = (int(n_cells),) * 3
+    ext = (L, L, L)
+    xyz, tv = kuhn_mesh(n, ext, 0.0)
+    u0 = rng.random((int(n_particles), 3)) * L
+    k = np.pi / L
+    a = amp * L * L / np.pi ** 2
+    s, c = np.sin(k * u0), np.cos(k * u0)
+    grad = k * np.stack([c[:, 0] * s[:, 1] * s[:, 2], s[:, 0] * c[:, 1] * s[:, 2], s[:, 0] * s[:, 1] * c[:, 2]], axis=1)
+    u = u0 + a * grad
+    t0, l0 = reference_located(u0, n, ext)
+    t1, l1 = reference_located(u, n, ext)
+    dens = omega_p ** 2 * EPS0 * E_MASS / E_CHARGE ** 2
+    w = dens * L ** 3 / int(n_particles)
+    return ColdPlasma(n=n, extent=ext, xyz=xyz, tet_vert=tv, tet0=t0, lam0=l0, tet=t1, lam=l1,
+                      vel=np.zeros((int(n_particles), 3)), ids=np.arange(int(n_particles), dtype=np.int64),
+                      q=E_CHARGE, m=E_MASS, w=w, density=dens, a=a, omega_p=omega_p)

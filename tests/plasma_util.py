@@ -1,0 +1,60 @@
+"""The cold-plasma loop of the tests (particles in the field of their own
+charge, closed through the non-solenoidal solve) run with the oracle, and
+the frequency fit of its recorded signal."""
+import os
+
+import numpy as np
+
+NTH = max(1, min(16, os.cpu_count() or 1))
+
+
+def mode_shape(cp, edges):
+    """Edge coefficients of -grad psi (psi(tail) - psi(head)): the field of
+    the oscillating mode per unit potential amplitude."""
+    k = np.pi / cp.extent[0]
+    x = cp.xyz
+    psi = np.sin(k * x[:, 0]) * np.sin(k * x[:, 1]) * np.sin(k * x[:, 2])
+    return psi[edges[:, 0]] - psi[edges[:, 1]]
+
+
+def mode_amplitude(e_real, shape):
+    """Least-squares amplitude of the mode shape in the edge field."""
+    return float(e_real @ shape / (shape @ shape))
+
+
+def oracle_loop(ora, cp, nsteps, dt, shape, omega=0.0, record=None):
+    """nsteps oracle steps of the plasma cp, each in the field solved from the
+    background-neutralised charge just before it.  Returns (states, G, signal,
+    rho0): states[j] = (tet, lam, vel, G) after step j (for j in record, all if
+    None), signal[j] = the mode amplitude of the real field at step j."""
+    from oracle import gauss
+    m = ora.OracleMesh(cp.xyz, cp.tet_vert)
+    ns = gauss.NsOracle(m, 8.8541878128e-12)
+    rho0 = m.charge(cp.tet, cp.lam, cp.q, cp.w) - m.charge(cp.tet0, cp.lam0, cp.q, cp.w)
+    t, l, v = cp.tet.copy(), cp.lam.copy(), cp.vel.copy()
+    G = np.zeros(m.ne)
+    bz = np.zeros(m.nf, complex)
+    states, sig = [], []
+    for j in range(nsteps):
+        _, e = ns.solve(G=G, rho0=rho0, t=j * dt, omega=omega)
+        sig.append(mode_amplitude((e * np.exp(1j * omega * j * dt)).real, shape))
+        rc, _ = m.step(t, l, v, q=cp.q, m=cp.m, w=cp.w, step=j, dt=dt, omega=omega, e_env=e, b_env=bz, dG=G,
+                       nthreads=NTH)
+        assert rc == 0
+        if record is None or j in record:
+            states.append((t.copy(), l.copy(), v.copy(), G.copy()))
+    return states, G, np.array(sig), rho0
+
+
+def fit_frequency(sig, dt, w0, span=0.1, n=4001):
+    """omega of the least-squares fit A cos(wt) + B sin(wt) + C, scanned over
+    w0 (1 +- span)."""
+    t = np.arange(len(sig)) * dt
+    best = None
+    for om in np.linspace((1 - span) * w0, (1 + span) * w0, n):
+        A = np.stack([np.cos(om * t), np.sin(om * t), np.ones_like(t)], axis=1)
+        c = np.linalg.lstsq(A, sig, rcond=None)[0]
+        r = np.sum((A @ c - sig) ** 2)
+        if best is None or r < best[0]:
+            best = (r, om, c)
+    return best[1], best[2]

@@ -2,14 +2,18 @@
 operator against the textbook linear-element stiffness, a manufactured Poisson
 problem converging at second order, Gauss' theorem on the wall, the discrete
 maximum principle, and the field of moved charge equal to the field of the
-charge where it ends."""
+charge where it ends; and the cold-plasma oscillation of the loop closed
+through the solve."""
 import os
+import sys
 
 import numpy as np
 import pytest
 import scipy.sparse as sp
 
 from paper_2208_12795_amd import synth
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
 
 EPS0 = 8.8541878128e-12
 NTH = max(1, min(16, os.cpu_count() or 1))
@@ -153,3 +157,27 @@ def test_moved_charge_field_equals_field_of_charge_at_its_end(ora):
     x2, e2 = ns.solve(rho0=rho_b, t=ta, omega=wa)
     assert np.abs(x1 - x2).max() <= 1e-11 * np.abs(x2).max()
     assert np.abs(e1 - e2).max() <= 1e-11 * np.abs(e2).max()
+
+
+def test_cold_plasma_oscillation(ora):
+    """The loop field -> particles -> G -> field closed through the solve:
+    electrons displaced by xi = a grad psi (psi = sin sin sin, grounded box)
+    over a neutralising background.  In the continuum the potential is
+    phi = n q a psi / eps (negative for electrons pushed towards the centre)
+    and every electron oscillates at the plasma frequency
+    omega_p = sqrt(n q^2 / (eps m)).  The oracle's loop (omega_p dt = 0.1,
+    two periods) oscillates at omega_p to 1 %, with a mode amplitude that
+    approaches n q a / eps at second order in the cell size."""
+    import plasma_util as P
+    ratios = {}
+    for n in (4, 8):
+        cp = synth.cold_plasma(n, 50_000)
+        shape = P.mode_shape(cp, synth.mesh_edges(cp.tet_vert, cp.xyz.shape[0]))
+        dt = 0.1 / cp.omega_p
+        _, _, sig, _ = P.oracle_loop(ora, cp, 126, dt, shape, record=[])
+        om, _ = P.fit_frequency(sig, dt, cp.omega_p)
+        assert abs(om / cp.omega_p - 1) < 0.01, (n, om / cp.omega_p)
+        phi0 = cp.density * cp.q * cp.a / EPS0
+        ratios[n] = sig[0] / phi0
+    assert 0.85 < ratios[4] < ratios[8] < 1.0, ratios
+    assert (1 - ratios[4]) / (1 - ratios[8]) > 3.0, ratios

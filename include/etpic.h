@@ -418,16 +418,47 @@ int etpic_ns_setup(etpic_ctx *ctx, double eps);
  * wall_nodes_out is not NULL, the number of grounded wall nodes. */
 int etpic_ns_info(const etpic_ctx *ctx, int64_t *nnz_out, int64_t *wall_nodes_out);
 
+/* flags of etpic_ns_solve and etpic_ns_run_steps */
+enum etpic_ns_flags {
+    /* start the CG from the solution of the previous solve on this context
+     * (x = 0 after etpic_ns_setup) instead of from zero: in a time loop the
+     * field changes little from one step to the next */
+    ETPIC_NS_WARM = 64u
+};
+
 /* Solve eq. ns_equation.  G: N_e float64 (device, NULL = 0); rho0: N_n
  * float64 (device, NULL = 0); t, omega: the carrier phase.  Outputs (device,
  * either may be NULL but not both): x_out = nodal coefficients, 2*N_n float64
  * (complex, interleaved; 0 on the wall), e_out = edge coefficients of the
- * non-solenoidal electric field, 2*N_e float64 (complex).  Preconditioned CG
- * stops when ||r|| / ||b|| <= tol (checked every 5 iterations) or after
- * max_iter; *iters_out and *resid_out (may be NULL) report it.  Synchronises
- * `stream`.  ENOCONV (outputs untouched) if the tolerance is not reached. */
+ * non-solenoidal electric field, 2*N_e float64 (complex).  flags: 0 or
+ * ETPIC_NS_WARM.  Preconditioned CG stops when ||r|| / ||b|| <= tol (checked
+ * every 5 iterations) or after max_iter; *iters_out and *resid_out (may be
+ * NULL) report it.  Synchronises `stream`.  ENOCONV (outputs untouched) if
+ * the tolerance is not reached. */
 int etpic_ns_solve(etpic_ctx *ctx, const double *G, const double *rho0, double t, double omega, double *x_out,
-                   double *e_out, double tol, int max_iter, int *iters_out, double *resid_out, void *stream);
+                   double *e_out, double tol, int max_iter, uint32_t flags, int *iters_out, double *resid_out,
+                   void *stream);
+
+/* The particles in the field of their own charge: the loop field -> particles
+ * -> G -> field closed through eq. ns_equation (the non-solenoidal part of
+ * the split only; no solenoidal field is computed).  For each of nsteps
+ * steps, at t = (step0 + j) dt: solve eq. ns_equation from G and rho0
+ * (warm-started after the first solve, and for the first too with
+ * ETPIC_NS_WARM), set e_work = e_ns (+ ext->e_env), then one particle step
+ * (as etpic_run_steps) in the fields {e_work, ext->e_dc, ext->b_env,
+ * ext->b_dc} (without ext: no other field), its path integral added to G.
+ * G: N_e float64 (device, in place), the running path integral of the
+ * current; rho0: N_n float64 (device, NULL = 0), the charge when G was zero;
+ * e_work: 2*N_e float64 (device, caller-owned; holds the last step's edge
+ * envelope on return; must not be ext->e_env).  One species per call.
+ * flags: ETPIC_STEP_* flags of the particle step, ETPIC_NS_WARM.
+ * *iters_out (may be NULL): CG iterations summed over the steps.
+ * Synchronises `stream` once per step.  ENOCONV stops the loop at the step
+ * whose solve failed (the particles have taken the steps before it). */
+int etpic_ns_run_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, const etpic_species *sp,
+                       const etpic_fields *ext, int64_t step0, int nsteps, double dt, double omega, double *G,
+                       const double *rho0, double *e_work, double tol, int max_iter, uint32_t flags, int *iters_out,
+                       void *stream);
 
 /* Kernel times of the steps launched with ETPIC_STEP_TIMING since the last
  * reset, from HIP events recorded on the launch stream around each kernel,

@@ -1995,111 +1995,230 @@ struct NsCsr {
     const double *S;
 };
 
-// b = -(D^T G + rho0) off the wall, 0 on it; x = 0, r = b, z = Dinv b,
-// p = q = 0; partial: r.z, 0, |r|^2, |b|^2.  (D^T G)_i sums +-G over the
-// edges at node i (+ where i is the head).
-__global__ void __launch_bounds__(kBlock) k_ns_start(int64_t nv, const int32_t *__restrict__ ptr,
+// The CG kernels run on at most kNsBlocks blocks (grid-stride loops), so that
+// every block can sum all block partials of the previous kernel itself, in
+// the same fixed order: the scalars of the iteration need no kernel of their
+// own and no cross-block synchronisation.  Partials: 4 doubles per block.
+// Scalars sc (written by thread 0 of block 0 only, read by the next kernel):
+// sc[0], sc[1] rho = r.z of even / odd iterations, sc[8] |r|^2, sc[9] |b|^2,
+// sc[10] done flag, sc[11] iterations taken.
+constexpr int kNsBlocks = 512;
+constexpr int kNsThreads = 1024;   // 16 wavefronts per block: enough rows in flight for one pass
+
+// Block-level sum of 4 doubles into partial[blockIdx.x * 4 + k].
+__device__ __forceinline__ void ns_block_sum4(double v[4], double *partial) {
+    __shared__ double sh[kNsThreads / 64][4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) sh[threadIdx.x >> 6][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double t = 0.0;
+        for (int w = 0; w < kNsThreads / 64; ++w) t += sh[w][threadIdx.x];
+        partial[blockIdx.x * 4 + threadIdx.x] = t;
+    }
+}
+
+// Every thread gets the sums of the nb partials (fixed order).
+__device__ __forceinline__ void all_sum4(int64_t nb, const double *__restrict__ partial, double tot[4]) {
+    __shared__ double sh[kNsThreads / 64][4];
+    __shared__ double res[4];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t b = threadIdx.x; b < nb; b += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] += partial[4 * b + k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) sh[threadIdx.x >> 6][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double t = 0.0;
+        for (int w = 0; w < kNsThreads / 64; ++w) t += sh[w][threadIdx.x];
+        res[threadIdx.x] = t;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) tot[k] = res[k];
+}
+
+// b = -(D^T G + rho0) at node i off the wall, 0 on it.  (D^T G)_i sums +-G
+// over the edges at node i (+ where i is the head).
+__device__ __forceinline__ double ns_rhs(int64_t i, const int32_t *__restrict__ ptr, const int32_t *__restrict__ code,
+                                         const double *__restrict__ G, const double *__restrict__ rho0,
+                                         const uint8_t *__restrict__ wall) {
+    if (wall[i]) return 0.0;
+    double div = rho0 ? rho0[i] : 0.0;
+    if (G)
+        for (int32_t k = ptr[i]; k < ptr[i + 1]; ++k) {
+            const int32_t c = code[k];
+            const double g = G[c >> 1];
+            div += (c & 1) ? g : -g;
+        }
+    return -div;
+}
+
+// Cold start: x = 0, r = b, z = Dinv b, p = q = 0; partials r.z, 0, |r|^2, |b|^2.
+__global__ void __launch_bounds__(kNsThreads) k_ns_start(int64_t nv, const int32_t *__restrict__ ptr,
                                                      const int32_t *__restrict__ code, const double *__restrict__ G,
                                                      const double *__restrict__ rho0, const uint8_t *__restrict__ wall,
                                                      const double *__restrict__ dinv, double *__restrict__ x,
                                                      double *__restrict__ r, double *__restrict__ z,
                                                      double *__restrict__ p, double *__restrict__ q,
-                                                     double *__restrict__ partial) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                                     double *__restrict__ partial, double *__restrict__ sc) {
     double v[4] = {0.0, 0.0, 0.0, 0.0};
-    if (i < nv) {
-        double b = 0.0;
-        if (!wall[i]) {
-            double div = rho0 ? rho0[i] : 0.0;
-            if (G)
-                for (int32_t k = ptr[i]; k < ptr[i + 1]; ++k) {
-                    const int32_t c = code[k];
-                    const double g = G[c >> 1];
-                    div += (c & 1) ? g : -g;
-                }
-            b = -div;
-        }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (int64_t)gridDim.x * blockDim.x) {
+        const double b = ns_rhs(i, ptr, code, G, rho0, wall);
         const double zi = dinv[i] * b;
         x[i] = 0.0;
         r[i] = b;
         z[i] = zi;
         p[i] = 0.0;
         q[i] = 0.0;
-        v[0] = b * zi;
-        v[2] = b * b;
-        v[3] = b * b;
+        v[0] += b * zi;
+        v[2] += b * b;
+        v[3] += b * b;
     }
-    block_sum4(v, partial);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc[10] = 0.0;
+        sc[11] = 0.0;
+    }
+    ns_block_sum4(v, partial);
 }
 
-// rho = r.z, beta = 0, |r|^2 and |b|^2 from the reduced start partials
-__global__ void k_ns_begin(double *__restrict__ sc, const double *__restrict__ red) {
-    if (threadIdx.x == 0) {
-        sc[0] = red[0];
-        sc[1] = 0.0;
-        sc[6] = 0.0;
-        sc[7] = 0.0;
-        sc[8] = red[2];
-        sc[9] = red[3];
+// Warm start from the x left by the previous solve: r = b - S x, z = Dinv r,
+// p = q = 0; partials r.z, 0, |r|^2, |b|^2.  kRowLanes lanes per row.
+__global__ void __launch_bounds__(kNsThreads) k_ns_start_warm(NsCsr S, const int32_t *__restrict__ ptr,
+                                                          const int32_t *__restrict__ code,
+                                                          const double *__restrict__ G,
+                                                          const double *__restrict__ rho0,
+                                                          const uint8_t *__restrict__ wall,
+                                                          const double *__restrict__ dinv,
+                                                          const double *__restrict__ x, double *__restrict__ r,
+                                                          double *__restrict__ z, double *__restrict__ p,
+                                                          double *__restrict__ q, double *__restrict__ partial,
+                                                          double *__restrict__ sc) {
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t / kRowLanes < S.nv; t += stride) {
+        const int64_t row = t / kRowLanes;
+        const int sub = (int)(t % kRowLanes);
+        double sx = 0.0;
+        for (int32_t j = S.rowptr[row] + sub; j < S.rowptr[row + 1]; j += kRowLanes) sx += S.S[j] * x[S.col[j]];
+#pragma unroll
+        for (int off = kRowLanes / 2; off > 0; off >>= 1) sx += __shfl_xor(sx, off);
+        if (sub == 0) {
+            const double b = ns_rhs(row, ptr, code, G, rho0, wall);
+            const double ri = b - sx;
+            const double zi = dinv[row] * ri;
+            r[row] = ri;
+            z[row] = zi;
+            p[row] = 0.0;
+            q[row] = 0.0;
+            v[0] += ri * zi;
+            v[2] += ri * ri;
+            v[3] += b * b;
+        }
     }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc[10] = 0.0;
+        sc[11] = 0.0;
+    }
+    ns_block_sum4(v, partial);
 }
 
-// p = z + beta p and q = A p = A z + beta q (the direction update folded into
-// the product, so that no separate pass over p is needed), with the partials
-// of p . q.  kRowLanes lanes per row.
-__global__ void __launch_bounds__(kBlock) k_ns_apply(NsCsr S, const double *__restrict__ sc,
+// Iteration k, first half.  From the partials of the previous update (or of
+// the start, k = 0): |r|^2 and rho_new = r.z; done once |r|^2 <= tol^2 |b|^2
+// (or not finite, or b = 0), then every block returns.  Otherwise beta = rho_new /
+// rho_old, p = z + beta p and q = A p = A z + beta q (the direction update
+// folded into the product, so no separate pass over p is needed), with the
+// partials of p . q.  check_only: the convergence test alone (after the last
+// allowed iteration).  Returns at once if an earlier launch found convergence.
+__global__ void __launch_bounds__(kNsThreads) k_ns_apply(NsCsr S, double *__restrict__ sc,
                                                      const double *__restrict__ z, double *__restrict__ p,
-                                                     double *__restrict__ q, double *__restrict__ partial) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t row = t / kRowLanes;
-    const int sub = (int)(t % kRowLanes);
-    double az = 0.0;
-    if (row < S.nv)
+                                                     double *__restrict__ q, const double *__restrict__ pin,
+                                                     int64_t nb_in, double *__restrict__ pout, int k, double tol2,
+                                                     int check_only) {
+    if (sc[10] != 0.0) return;
+    double tot[4];
+    all_sum4(nb_in, pin, tot);
+    const double b2 = k == 0 ? tot[3] : sc[9];
+    const double r2 = tot[2], rn = tot[0];
+    const bool done = b2 == 0.0 || !(r2 > tol2 * b2);   // no source: x = 0, done
+    const double ro = sc[(k + 1) & 1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc[8] = r2;
+        if (k == 0) sc[9] = b2;
+        sc[k & 1] = rn;
+        sc[10] = done ? 1.0 : 0.0;
+        sc[11] = (double)k;
+    }
+    if (done || check_only) return;
+    const double be = (k == 0 || ro == 0.0) ? 0.0 : rn / ro;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t / kRowLanes < S.nv; t += stride) {
+        const int64_t row = t / kRowLanes;
+        const int sub = (int)(t % kRowLanes);
+        double az = 0.0;
         for (int32_t j = S.rowptr[row] + sub; j < S.rowptr[row + 1]; j += kRowLanes) az += S.S[j] * z[S.col[j]];
 #pragma unroll
-    for (int off = kRowLanes / 2; off > 0; off >>= 1) az += __shfl_xor(az, off);
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
-    if (row < S.nv && sub == 0) {
-        const double be = sc[6];
-        const double pn = z[row] + be * p[row];
-        const double qn = az + be * q[row];
-        p[row] = pn;
-        q[row] = qn;
-        v[0] = pn * qn;
+        for (int off = kRowLanes / 2; off > 0; off >>= 1) az += __shfl_xor(az, off);
+        if (sub == 0) {
+            const double pn = z[row] + be * p[row];
+            const double qn = az + be * q[row];
+            p[row] = pn;
+            q[row] = qn;
+            v[0] += pn * qn;
+        }
     }
-    block_sum4(v, partial);
+    ns_block_sum4(v, pout);
 }
 
-// x += alpha p, r -= alpha q, z = Dinv r, with the partials of r . z and |r|^2
-__global__ void __launch_bounds__(kBlock) k_ns_update(int64_t nv, const double *__restrict__ sc,
+// Iteration k, second half: alpha = rho_new / (p . q) from the partials of the
+// product; x += alpha p, r -= alpha q, z = Dinv r, with the partials of r . z
+// and |r|^2.  Returns at once if the first half found convergence.
+__global__ void __launch_bounds__(kNsThreads) k_ns_update(int64_t nv, const double *__restrict__ sc,
                                                       const double *__restrict__ dinv, const double *__restrict__ p,
                                                       const double *__restrict__ q, double *__restrict__ x,
                                                       double *__restrict__ r, double *__restrict__ z,
-                                                      double *__restrict__ partial) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const double al = sc[4];
+                                                      const double *__restrict__ pin, int64_t nb_in,
+                                                      double *__restrict__ pout, int k) {
+    if (sc[10] != 0.0) return;
+    double tot[4];
+    all_sum4(nb_in, pin, tot);
+    const double pq = tot[0];
+    const double al = pq != 0.0 ? sc[k & 1] / pq : 0.0;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
-    if (i < nv) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (int64_t)gridDim.x * blockDim.x) {
         x[i] += al * p[i];
         const double ri = r[i] - al * q[i];
         r[i] = ri;
         const double zi = dinv[i] * ri;
         z[i] = zi;
-        v[0] = ri * zi;
-        v[2] = ri * ri;
+        v[0] += ri * zi;
+        v[2] += ri * ri;
     }
-    block_sum4(v, partial);
+    ns_block_sum4(v, pout);
 }
 
-// x_out = e^{-j w t} x on the nodes, e_out = e^{-j w t} D x on the edges
-// (edge e from ev[2e] to ev[2e+1]); either output may be NULL.
+// x_out = e^{-j w t} x on the nodes, e_out = e^{-j w t} D x (+ e_add) on the
+// edges (edge e from ev[2e] to ev[2e+1]); x_out, e_out, e_add may be NULL.
 __global__ void __launch_bounds__(kBlock) k_ns_out(int64_t ne, int64_t nv, const int32_t *__restrict__ ev,
                                                    const double *__restrict__ x, double c, double s,
-                                                   double2 *__restrict__ x_out, double2 *__restrict__ e_out) {
+                                                   double2 *__restrict__ x_out, double2 *__restrict__ e_out,
+                                                   const double2 *__restrict__ e_add) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e_out && i < ne) {
         const double d = x[ev[2 * i + 1]] - x[ev[2 * i]];
-        e_out[i] = make_double2(c * d, -s * d);
+        double2 e = make_double2(c * d, -s * d);
+        if (e_add) e = cadd(e, e_add[i]);
+        e_out[i] = e;
     }
     if (x_out && i < nv) {
         const double xi = x[i];
@@ -2141,20 +2260,20 @@ struct FieldState {
 struct NsState {
     bool ready = false;
     double eps = 0;
-    int64_t nv = 0, ne = 0, nnz = 0, nb = 0, n_wall = 0;
+    int64_t nv = 0, ne = 0, nnz = 0, n_wall = 0;
     int32_t *rowptr = nullptr, *col = nullptr, *ev = nullptr;
     double *S = nullptr, *dinv = nullptr;
     uint8_t *wall = nullptr;
     double *vec = nullptr;      // 5 work vectors of nv: x, r, z, p, q
-    double *partial = nullptr;  // 4 per block
-    double *red = nullptr;      // 4 reductions
-    double *sc = nullptr;       // 10 scalars, laid out as the COCG ones (imaginary parts 0)
+    double *partial = nullptr;  // two sets of 4 per block (kNsBlocks blocks)
+    double *sc = nullptr;       // 12 scalars of the iteration
+    double *bzero = nullptr;    // 2*N_f zeros: the face envelope of a loop without external fields
 
     double *v(int k) const { return vec + (size_t)k * nv; }
     NsCsr csr() const { return NsCsr{nv, rowptr, col, S}; }
     void release() {
         for (void *q : {(void *)rowptr, (void *)col, (void *)ev, (void *)S, (void *)dinv, (void *)wall, (void *)vec,
-                        (void *)partial, (void *)red, (void *)sc})
+                        (void *)partial, (void *)sc, (void *)bzero})
             (void)hipFree(q);
         *this = NsState();
     }
@@ -3370,7 +3489,6 @@ int etpic_ns_setup(etpic_ctx *ctx, double eps) {
     N.ne = ne;
     N.nnz = S.nnz;
     for (uint8_t b : S.wall) N.n_wall += b;
-    N.nb = (int64_t)grid_for(nv * kRowLanes);
     HIP_TRY(hipMalloc(&N.rowptr, sizeof(int32_t) * (nv + 1)));
     HIP_TRY(hipMalloc(&N.col, sizeof(int32_t) * S.nnz));
     HIP_TRY(hipMalloc(&N.ev, sizeof(int32_t) * 2 * ne));
@@ -3378,9 +3496,12 @@ int etpic_ns_setup(etpic_ctx *ctx, double eps) {
     HIP_TRY(hipMalloc(&N.dinv, sizeof(double) * nv));
     HIP_TRY(hipMalloc(&N.wall, sizeof(uint8_t) * nv));
     HIP_TRY(hipMalloc(&N.vec, sizeof(double) * 5 * nv));
-    HIP_TRY(hipMalloc(&N.partial, sizeof(double) * 4 * N.nb));
-    HIP_TRY(hipMalloc(&N.red, sizeof(double) * 4));
-    HIP_TRY(hipMalloc(&N.sc, sizeof(double) * 10));
+    HIP_TRY(hipMalloc(&N.partial, sizeof(double) * 8 * kNsBlocks));
+    HIP_TRY(hipMalloc(&N.sc, sizeof(double) * 12));
+    HIP_TRY(hipMemset(N.sc, 0, sizeof(double) * 12));
+    HIP_TRY(hipMalloc(&N.bzero, sizeof(double) * 2 * ctx->host.nf));
+    HIP_TRY(hipMemset(N.vec, 0, sizeof(double) * 5 * nv));
+    HIP_TRY(hipMemset(N.bzero, 0, sizeof(double) * 2 * ctx->host.nf));
     HIP_TRY(hipMemcpy(N.rowptr, S.rowptr.data(), sizeof(int32_t) * (nv + 1), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(N.col, S.col.data(), sizeof(int32_t) * S.nnz, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(N.ev, ctx->host.edges.data(), sizeof(int32_t) * 2 * ne, hipMemcpyHostToDevice));
@@ -3399,52 +3520,122 @@ int etpic_ns_info(const etpic_ctx *ctx, int64_t *nnz_out, int64_t *wall_nodes_ou
     return ETPIC_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// The CG of eq. ns_equation on `st` (synchronises it), from x = 0 or, warm,
+// from the x of the previous solve; outputs scaled by e^{-j w t} = c - j s.
+int ns_solve_impl(etpic_ctx *ctx, const double *G, const double *rho0, double c, double s, double2 *x_out,
+                  double2 *e_out, const double2 *e_add, double tol, int max_iter, bool warm, int *iters_out,
+                  double *resid_out, hipStream_t st) {
+    const NsState &N = ctx->ns;
+    const int64_t nv = N.nv;
+    const unsigned gv = (unsigned)std::min<int64_t>((nv + kNsThreads - 1) / kNsThreads, kNsBlocks);
+    const unsigned gr = (unsigned)std::min<int64_t>((nv * kRowLanes + kNsThreads - 1) / kNsThreads, kNsBlocks);
+    double *x = N.v(0), *r = N.v(1), *z = N.v(2), *p = N.v(3), *q = N.v(4);
+    // partials: pa from the product (gr blocks), pb from the start and the update
+    double *pa = N.partial, *pb = N.partial + 4 * kNsBlocks;
+    int64_t nb = warm ? gr : gv;
+    if (warm)
+        k_ns_start_warm<<<gr, kNsThreads, 0, st>>>(N.csr(), ctx->d_v2e_ptr, ctx->d_v2e_code, G, rho0, N.wall, N.dinv, x, r,
+                                               z, p, q, pb, N.sc);
+    else
+        k_ns_start<<<gv, kNsThreads, 0, st>>>(nv, ctx->d_v2e_ptr, ctx->d_v2e_code, G, rho0, N.wall, N.dinv, x, r, z, p, q,
+                                          pb, N.sc);
+    HIP_TRY(hipGetLastError());
+    // Iterations are launched in batches; the device raises the done flag when
+    // the residual is small enough and the rest of the batch returns at once.
+    // The host reads the scalars once per batch.
+    const int batch = 10;
+    const double tol2 = tol * tol;
+    double hs[12];
+    int k = 0;
+    for (;;) {
+        const int n = std::min(batch, max_iter - k);
+        for (int j = 0; j < n; ++j, ++k) {
+            k_ns_apply<<<gr, kNsThreads, 0, st>>>(N.csr(), N.sc, z, p, q, pb, nb, pa, k, tol2, 0);
+            k_ns_update<<<gv, kNsThreads, 0, st>>>(nv, N.sc, N.dinv, p, q, x, r, z, pa, gr, pb, k);
+            nb = gv;
+        }
+        if (k >= max_iter) k_ns_apply<<<gr, kNsThreads, 0, st>>>(N.csr(), N.sc, z, p, q, pb, nb, pa, k, tol2, 1);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(hs, N.sc, sizeof hs, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (hs[10] != 0.0 || k >= max_iter) break;
+    }
+    const double bnorm2 = hs[9];
+    if (!(bnorm2 > 0.0) && warm) HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * nv, st));   // no source: x = 0
+    const double rel = bnorm2 > 0.0 ? std::sqrt(hs[8] / bnorm2) : 0.0;
+    const int it = (int)hs[11];
+    if (iters_out) *iters_out = it;
+    if (resid_out) *resid_out = rel;
+    if (hs[10] == 0.0 || !std::isfinite(rel))
+        return fail(ETPIC_ENOCONV, "ns CG: relative residual %.3e after %d iterations", rel, it);
+    k_ns_out<<<grid_for(std::max(N.ne, nv)), kBlock, 0, st>>>(N.ne, nv, N.ev, x, c, s, x_out, e_out, e_add);
+    HIP_TRY(hipGetLastError());
+    return ETPIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int etpic_ns_solve(etpic_ctx *ctx, const double *G, const double *rho0, double t, double omega, double *x_out,
-                   double *e_out, double tol, int max_iter, int *iters_out, double *resid_out, void *stream) {
+                   double *e_out, double tol, int max_iter, uint32_t flags, int *iters_out, double *resid_out,
+                   void *stream) {
     if (!ctx) return fail(ETPIC_EINVAL, "null context");
     if (!x_out && !e_out) return fail(ETPIC_EINVAL, "no output: x_out and e_out are both NULL");
     if (!ctx->ns.ready) return fail(ETPIC_ESTATE, "etpic_ns_setup not called");
     if (!(tol > 0.0) || max_iter < 1 || !std::isfinite(t) || !std::isfinite(omega))
         return fail(ETPIC_EINVAL, "bad tol / max_iter / time / omega");
+    if (flags & ~(uint32_t)ETPIC_NS_WARM) return fail(ETPIC_EINVAL, "unknown flags 0x%x", flags);
+    if (int r = set_device(ctx)) return r;
+    return ns_solve_impl(ctx, G, rho0, std::cos(omega * t), std::sin(omega * t), reinterpret_cast<double2 *>(x_out),
+                         reinterpret_cast<double2 *>(e_out), nullptr, tol, max_iter, (flags & ETPIC_NS_WARM) != 0,
+                         iters_out, resid_out, static_cast<hipStream_t>(stream));
+}
+
+int etpic_ns_run_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, const etpic_species *sp,
+                       const etpic_fields *ext, int64_t step0, int nsteps, double dt, double omega, double *G,
+                       const double *rho0, double *e_work, double tol, int max_iter, uint32_t flags, int *iters_out,
+                       void *stream) {
+    if (!ctx) return fail(ETPIC_EINVAL, "null context");
+    if (!ctx->ns.ready) return fail(ETPIC_ESTATE, "etpic_ns_setup not called");
+    if (!G || !e_work) return fail(ETPIC_EINVAL, "null G or e_work");
+    if (ext && (!ext->e_env || !ext->b_env)) return fail(ETPIC_EINVAL, "external fields without e_env / b_env");
+    if (ext && ext->e_env == e_work) return fail(ETPIC_EINVAL, "e_work aliases the external e_env");
+    if (nsteps < 0) return fail(ETPIC_EINVAL, "negative step count");
+    if (!(tol > 0.0) || max_iter < 1) return fail(ETPIC_EINVAL, "bad tol / max_iter");
+    const etpic_fields f{e_work, ext ? ext->e_dc : nullptr, ext ? ext->b_env : ctx->ns.bzero,
+                         ext ? ext->b_dc : nullptr};
+    if (int r = check_step_args(ctx, sp, &f, dt, omega)) return r;
+    if (int r = check_particles(ctx, p)) return r;
+    if (precision != ETPIC_FP64 && precision != ETPIC_MIXED) return fail(ETPIC_EINVAL, "bad precision %d", precision);
+    if (nsteps == 0) return ETPIC_OK;
     if (int r = set_device(ctx)) return r;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const NsState &N = ctx->ns;
-    const int64_t nv = N.nv;
-    const unsigned gv = grid_for(nv), gr = grid_for(nv * kRowLanes);
-    double *x = N.v(0), *r = N.v(1), *z = N.v(2), *p = N.v(3), *q = N.v(4);
-    k_ns_start<<<gv, kBlock, 0, st>>>(nv, ctx->d_v2e_ptr, ctx->d_v2e_code, G, rho0, N.wall, N.dinv, x, r, z, p, q,
-                                      N.partial);
-    k_reduce4<<<1, kBlock, 0, st>>>(gv, N.partial, N.red);
-    k_ns_begin<<<1, 64, 0, st>>>(N.sc, N.red);
-    HIP_TRY(hipGetLastError());
-    double hs[10];
-    HIP_TRY(hipMemcpyAsync(hs, N.sc, sizeof hs, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    const double bnorm2 = hs[9];
-    double rel = bnorm2 > 0.0 ? std::sqrt(hs[8] / bnorm2) : 0.0;
-    int it = 0;
-    const int check = 5;
-    while (rel > tol && it < max_iter) {
-        k_ns_apply<<<gr, kBlock, 0, st>>>(N.csr(), N.sc, z, p, q, N.partial);
-        k_cocg_scalars<<<1, kBlock, 0, st>>>(gr, N.partial, N.sc, 0);
-        k_ns_update<<<gv, kBlock, 0, st>>>(nv, N.sc, N.dinv, p, q, x, r, z, N.partial);
-        k_cocg_scalars<<<1, kBlock, 0, st>>>(gv, N.partial, N.sc, 1);
-        HIP_TRY(hipGetLastError());
-        ++it;
-        if (it % check == 0 || it == max_iter) {
-            HIP_TRY(hipMemcpyAsync(hs, N.sc, sizeof hs, hipMemcpyDeviceToHost, st));
-            HIP_TRY(hipStreamSynchronize(st));
-            rel = std::sqrt(hs[8] / bnorm2);
-            if (!std::isfinite(rel)) break;
+    int total = 0;
+    for (int j = 0; j < nsteps; ++j) {
+        const double t = (double)(step0 + j) * dt;
+        int it = 0;
+        const bool warm = j > 0 || (flags & ETPIC_NS_WARM);
+        if (int r = ns_solve_impl(ctx, G, rho0, std::cos(omega * t), std::sin(omega * t), nullptr,
+                                  reinterpret_cast<double2 *>(e_work),
+                                  ext ? reinterpret_cast<const double2 *>(ext->e_env) : nullptr, tol, max_iter, warm,
+                                  &it, nullptr, st)) {
+            if (iters_out) *iters_out = total + it;
+            return r;
         }
+        total += it;
+        if (p->n == 0) continue;
+        const StepPlan plan{{&f, nullptr, nullptr}, {1.0, 0.0, 0.0}, t};
+        const uint32_t sf = flags & ~(uint32_t)ETPIC_NS_WARM;
+        const int r = precision == ETPIC_FP64 ? ctx->run_steps<double>(p, sp, &plan, 1, dt, omega, G, nullptr, sf, stream)
+                                              : ctx->run_steps<float>(p, sp, &plan, 1, dt, omega, G, nullptr, sf, stream);
+        if (r) return r;
     }
-    if (iters_out) *iters_out = it;
-    if (resid_out) *resid_out = rel;
-    if (!(rel <= tol)) return fail(ETPIC_ENOCONV, "ns CG: relative residual %.3e after %d iterations", rel, it);
-    k_ns_out<<<grid_for(std::max(N.ne, nv)), kBlock, 0, st>>>(N.ne, nv, N.ev, x, std::cos(omega * t),
-                                                              std::sin(omega * t), reinterpret_cast<double2 *>(x_out),
-                                                              reinterpret_cast<double2 *>(e_out));
-    HIP_TRY(hipGetLastError());
+    if (iters_out) *iters_out = total;
     return ETPIC_OK;
 }
 

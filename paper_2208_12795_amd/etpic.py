@@ -23,6 +23,7 @@ STEP_XCD_REMAP = 1
 STEP_TIMING = 2
 STEP_SLICES_1, STEP_SLICES_4, STEP_SLICES_16 = 4, 8, 16
 STEP_WALK_BY_SLICE = 32
+NS_WARM = 64
 HOP_CAP = 64
 
 EXPORTS = (
@@ -33,7 +34,7 @@ EXPORTS = (
     "etpic_field_setup", "etpic_field_nnz", "etpic_field_spmv", "etpic_field_step",
     "etpic_particles_locate", "etpic_particles_positions", "etpic_coarse_step", "etpic_run_steps",
     "etpic_sort_run_steps", "etpic_ds_history_bytes", "etpic_ds_steps", "etpic_ds_sort",
-    "etpic_ns_setup", "etpic_ns_info", "etpic_ns_solve",
+    "etpic_ns_setup", "etpic_ns_info", "etpic_ns_solve", "etpic_ns_run_steps",
 )
 
 
@@ -111,8 +112,10 @@ def lib():
                                    dp, vp]
     L.etpic_ns_setup.argtypes = [vp, C.c_double]
     L.etpic_ns_info.argtypes = [vp, i64p, i64p]
-    L.etpic_ns_solve.argtypes = [vp, vp, vp, C.c_double, C.c_double, vp, vp, C.c_double, C.c_int,
+    L.etpic_ns_solve.argtypes = [vp, vp, vp, C.c_double, C.c_double, vp, vp, C.c_double, C.c_int, C.c_uint32,
                                  C.POINTER(C.c_int), dp, vp]
+    L.etpic_ns_run_steps.argtypes = [vp, vp, C.c_int, vp, vp, C.c_int64, C.c_int, C.c_double, C.c_double, vp, vp,
+                                     vp, C.c_double, C.c_int, C.c_uint32, C.POINTER(C.c_int), vp]
     for name in EXPORTS:
         if name != "etpic_last_error":
             getattr(L, name).restype = C.c_int
@@ -488,17 +491,35 @@ class Context:
         return nnz.value, wall.value
 
     def ns_solve(self, G=None, rho0=None, t=0.0, omega=0.0, x_out=None, e_out=None, tol=1e-12, max_iter=2000,
-                 stream=None, raise_on_error=True):
+                 warm=False, stream=None, raise_on_error=True):
         """Gauss-law solve: x_out float64 [N_n, 2] and e_out float64 [N_e, 2]
         (complex; either may be None); G float64 [N_e], rho0 float64 [N_n] or
         None.  Returns (status, iterations, relative residual)."""
         it = C.c_int(0)
         res = C.c_double(0.0)
         rc = lib().etpic_ns_solve(self._h, _dptr(G), _dptr(rho0), float(t), float(omega), _dptr(x_out), _dptr(e_out),
-                                  float(tol), int(max_iter), C.byref(it), C.byref(res), _stream(stream))
+                                  float(tol), int(max_iter), NS_WARM if warm else 0, C.byref(it), C.byref(res),
+                                  _stream(stream))
         if raise_on_error:
             _chk(rc)
         return rc, it.value, res.value
+
+    def ns_run_steps(self, parts, species, step0, nsteps, dt, omega, G, e_work, rho0=None, ext=None, tol=1e-12,
+                     max_iter=2000, flags=STEP_XCD_REMAP, warm=False, stream=None):
+        """nsteps particle steps, each in the field of the charge (rho0 + D^T G)
+        solved just before it (plus the external fields ext, a Fields or None);
+        G float64 [N_e] accumulates; e_work float64 [N_e, 2] receives the edge
+        envelope.  Returns the CG iterations summed over the steps."""
+        d = parts.desc()
+        sp = species.c()
+        fd = None if ext is None else ext.desc()
+        it = C.c_int(0)
+        rc = lib().etpic_ns_run_steps(self._h, C.byref(d), parts.precision, C.byref(sp),
+                                      None if fd is None else C.byref(fd), int(step0), int(nsteps), float(dt),
+                                      float(omega), _dptr(G), _dptr(rho0), _dptr(e_work), float(tol), int(max_iter),
+                                      int(flags) | (NS_WARM if warm else 0), C.byref(it), _stream(stream))
+        _chk(rc)
+        return it.value
 
     def check(self, stream=None, raise_on_error=True):
         word = C.c_uint32(0)

@@ -3,10 +3,16 @@ closed form, Jacobi-preconditioned CG) against the oracle's operator built as
 D^T [*eps] D from its quadrature edge mass and solved by sparse LU; and the
 field of the charge moved by GPU steps against the field of the charge where
 the particles end."""
+import os
+import sys
+
 import numpy as np
 import pytest
 
 from paper_2208_12795_amd import synth
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from parity_util import assert_within, step_errors  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -152,4 +158,142 @@ def test_one_output_and_errors(E, torch_cuda):
     # no source: zero field without iterations
     _, iters, _ = ctx.ns_solve(None, None, 0.0, 0.0, x1, e1)
     assert iters == 0 and torch.count_nonzero(x1) == 0 and torch.count_nonzero(e1) == 0
+    ctx.close()
+
+
+def test_warm_start(E, torch_cuda):
+    """A warm solve (from the previous solution) of a slightly changed charge
+    equals the cold solve of it, in fewer iterations; a warm solve without a
+    source returns zero."""
+    torch = torch_cuda
+    w = synth.make_workload(2, n_particles=200_000)
+    ctx = E.Context(0)
+    ctx.upload_mesh(w.xyz, w.tet_vert)
+    ctx.ns_setup(EPS0)
+    sp = E.Species(w.q, w.m, w.w)
+    parts = E.Particles.from_numpy(w.tet, w.lam, w.vel, w.ids)
+    rho = torch.zeros(ctx.n_vert, dtype=torch.float64, device="cuda")
+    ctx.vertex_charge(parts, sp, rho)
+    rho2 = rho * 1.01 + 1e-3 * rho.abs().max() * torch.sin(torch.arange(ctx.n_vert, device="cuda", dtype=torch.float64))
+    xa = torch.zeros((ctx.n_vert, 2), dtype=torch.float64, device="cuda")
+    xb, xc = torch.zeros_like(xa), torch.zeros_like(xa)
+    _, it0, _ = ctx.ns_solve(None, rho, 0.0, 0.0, xa, None, tol=1e-12)
+    _, itw, _ = ctx.ns_solve(None, rho2, 0.0, 0.0, xb, None, tol=1e-12, warm=True)
+    _, itc, _ = ctx.ns_solve(None, rho2, 0.0, 0.0, xc, None, tol=1e-12)
+    print(f"[ns] cold {it0}, warm {itw}, cold again {itc}", flush=True)
+    assert itw < itc
+    assert rel(t2c(xb), t2c(xc)) <= 1e-9
+    _, it, _ = ctx.ns_solve(None, None, 0.0, 0.0, xb, None, warm=True)
+    assert it == 0 and torch.count_nonzero(xb) == 0
+    ctx.close()
+
+
+def gpu_plasma_loop(E, torch, cp, nsteps, dt, omega, per_step=None, tol=1e-13):
+    ctx = E.Context(0)
+    ctx.upload_mesh(cp.xyz, cp.tet_vert)
+    ctx.ns_setup(EPS0)
+    sp = E.Species(cp.q, cp.m, cp.w)
+    parts = E.Particles.from_numpy(cp.tet, cp.lam, cp.vel, cp.ids)
+    rest = E.Particles.from_numpy(cp.tet0, cp.lam0, cp.vel, cp.ids)
+    rho0 = torch.zeros(ctx.n_vert, dtype=torch.float64, device="cuda")
+    rho_rest = torch.zeros_like(rho0)
+    ctx.vertex_charge(parts, sp, rho0)
+    ctx.vertex_charge(rest, sp, rho_rest)
+    rho0 -= rho_rest                                   # neutralising background
+    G = torch.zeros(ctx.n_edge, dtype=torch.float64, device="cuda")
+    e = torch.zeros((ctx.n_edge, 2), dtype=torch.float64, device="cuda")
+    iters = []
+    for j in range(nsteps):
+        iters.append(ctx.ns_run_steps(parts, sp, j, 1, dt, omega, G, e, rho0=rho0, tol=tol, warm=j > 0))
+        if per_step is not None:
+            per_step(j, parts, G, e)
+    ctx.check()
+    ctx.close()
+    return parts, iters
+
+
+@pytest.mark.parametrize("omega", [0.0, 2 * np.pi * 3e9])
+def test_plasma_loop_matches_oracle(E, torch_cuda, ora, omega):
+    """30 steps of the cold-plasma loop (6^3 x 6 mesh, 20k electrons, omega_p
+    dt = 0.1) on the GPU (etpic_ns_run_steps one step per call) against the
+    oracle's loop, every step: positions, velocities and the running G.  With
+    a carrier the solve's phase and the step's cancel: same trajectories."""
+    import plasma_util as P
+    torch = torch_cuda
+    cp = synth.cold_plasma(6, 20_000)
+    ed = synth.mesh_edges(cp.tet_vert, cp.xyz.shape[0])
+    dt = 0.1 / cp.omega_p
+    nsteps = 30
+    states, _, _, _ = P.oracle_loop(ora, cp, nsteps, dt, P.mode_shape(cp, ed), omega=omega)
+    worst = {}
+    prev = [(cp.tet, cp.lam, cp.vel)]
+
+    def check(j, parts, G, e):
+        tg, lg, vg, _ = parts.to_numpy()
+        to, lo, vo, Go = states[j]
+        err = step_errors(cp.xyz, cp.tet_vert, prev[0], (tg, lg, vg), (to, lo, vo), G.cpu().numpy(), Go)
+        assert err["tet_mismatch"] <= 2, (j, err)
+        assert_within(err, 1e-9, f"plasma loop step {j}")
+        for k, v in err.items():
+            worst[k] = max(worst.get(k, 0.0), v)
+        prev[0] = (tg, lg, vg)
+
+    gpu_plasma_loop(E, torch, cp, nsteps, dt, omega, per_step=check)
+    print(f"[ns] plasma loop omega={omega:.3g}: worst {worst}", flush=True)
+
+
+def test_plasma_frequency_bench_mesh(E, torch_cuda):
+    """2e6 electrons on the 40^3 x 6 mesh (the bench mesh's size, unjittered),
+    two plasma periods at omega_p dt = 0.1 in one warm-started loop: the mode
+    oscillates at omega_p to 0.5 % with the continuum amplitude n q a / eps to
+    2 %; the warm-started solves take fewer iterations than the first (cold)
+    one."""
+    import plasma_util as P
+    torch = torch_cuda
+    cp = synth.cold_plasma(40, 2_000_000)
+    ed = synth.mesh_edges(cp.tet_vert, cp.xyz.shape[0])
+    shape = P.mode_shape(cp, ed)
+    dt = 0.1 / cp.omega_p
+    sig = []
+    _, iters = gpu_plasma_loop(E, torch, cp, 126, dt, 0.0, tol=1e-10,
+                               per_step=lambda j, p, G, e: sig.append(P.mode_amplitude(e[:, 0].cpu().numpy(), shape)))
+    om, _ = P.fit_frequency(np.array(sig), dt, cp.omega_p)
+    phi0 = cp.density * cp.q * cp.a / EPS0
+    warm = np.mean(iters[1:])
+    print(f"[ns] 40^3 plasma: omega/omega_p {om / cp.omega_p:.5f}, amplitude {sig[0] / phi0:.5f}, "
+          f"CG iterations: first step {iters[0]}, later steps {warm:.1f} on average", flush=True)
+    assert abs(om / cp.omega_p - 1) < 5e-3
+    assert abs(sig[0] / phi0 - 1) < 2e-2
+    assert warm < iters[0]
+
+
+def test_loop_with_external_field_and_errors(E, torch_cuda):
+    """With external fields the edge envelope of the step is e_ns plus the
+    external one (checked against a separate solve); argument errors."""
+    torch = torch_cuda
+    w = synth.make_workload(1, n_particles=2000)
+    ctx = E.Context(0)
+    ctx.upload_mesh(w.xyz, w.tet_vert)
+    f = E.Fields.from_numpy(w.e_env, w.b_env, None, w.b_dc)
+    sp = E.Species(w.q, w.m, w.w)
+    parts = E.Particles.from_numpy(w.tet, w.lam, w.vel, w.ids)
+    G = torch.zeros(ctx.n_edge, dtype=torch.float64, device="cuda")
+    e = torch.zeros((ctx.n_edge, 2), dtype=torch.float64, device="cuda")
+    rho0 = torch.zeros(ctx.n_vert, dtype=torch.float64, device="cuda")
+    ctx.vertex_charge(parts, sp, rho0)
+    with pytest.raises(E.EtpicError):           # no setup
+        ctx.ns_run_steps(parts, sp, 0, 1, w.dt, w.omega, G, e, rho0=rho0)
+    ctx.ns_setup(EPS0)
+    with pytest.raises(E.EtpicError):
+        ctx.ns_run_steps(parts, sp, 0, 1, w.dt, w.omega, G, None, rho0=rho0)
+    with pytest.raises(E.EtpicError):           # e_work is the external envelope
+        ctx.ns_run_steps(parts, sp, 0, 1, w.dt, w.omega, G, f.e_env, rho0=rho0, ext=f)
+    ctx.ns_run_steps(parts, sp, 0, 3, w.dt, w.omega, G, e, rho0=rho0, ext=f)
+    G_before = G.clone()
+    ctx.ns_run_steps(parts, sp, 3, 1, w.dt, w.omega, G, e, rho0=rho0, ext=f)
+    e_ns = torch.zeros_like(e)
+    ctx.ns_solve(G_before, rho0, 3 * w.dt, w.omega, None, e_ns)
+    assert rel(t2c(e), t2c(e_ns + f.e_env)) <= 1e-10
+    assert not torch.equal(G, G_before)
+    ctx.check()
     ctx.close()

@@ -31,6 +31,7 @@
 //   k_locate, k_positions   Cartesian points <-> (tet, barycentrics).
 //   k_adjoint     reverse of one float64 step (gradient w.r.t. the edge envelope).
 //   k_field_spmv, k_nm_*, k_cocg_*   implicit envelope field step.
+//   k_ns_*        Gauss-law (non-solenoidal) field solve: CG on the nodal operator.
 #include <hip/hip_runtime.h>
 
 #include <cmath>

@@ -1,0 +1,107 @@
+"""Pins of the quasi-Helmholtz projector oracle: the tet-face divergence
+against Gauss' theorem for linear fields and against the curl (div curl = 0),
+Sigma = eps0 M_g against a quadrature of W1 . grad W0, and the projector
+identities (idempotent, symmetric, the ranges they keep and kill)."""
+import numpy as np
+import pytest
+
+from paper_2208_12795_amd import synth
+
+EPS0 = 8.8541878128e-12
+
+
+@pytest.fixture(scope="module")
+def mesh(ora):
+    xyz, tv = synth.kuhn_mesh((4, 3, 5), (1.0, 0.8, 1.2), 0.15, np.random.default_rng(12))
+    return ora.OracleMesh(xyz, tv)
+
+
+@pytest.fixture(scope="module")
+def Q(mesh):
+    from oracle import qh
+    return qh.QhOracle(mesh, EPS0)
+
+
+def rel(x, y):
+    return np.abs(x - y).max() / np.abs(y).max()
+
+
+def test_divergence_of_linear_fields(mesh, Q):
+    """B(r) = G r + B0: the face DoFs (fluxes, exact by the centroid rule on a
+    flat face) summed with the tet's outward signs give tr(G) times the tet
+    volume (Gauss' theorem)."""
+    from oracle import field
+    G = np.array([[1.3, 0.2, -0.7], [0.4, -2.1, 0.3], [0.9, 0.5, 0.35]])
+    B0 = np.array([0.2, -1.0, 0.6])
+    fc = mesh.faces()
+    a, b, c = (mesh.xyz[fc[:, i]] for i in range(3))
+    area = 0.5 * np.cross(b - a, c - a)
+    cen = (a + b + c) / 3.0
+    flux = np.einsum("ij,ij->i", cen @ G.T + B0, area)
+    vol = field.tet_gradients(mesh.xyz, mesh.tv)[1]
+    assert rel(Q.div @ flux, np.trace(G) * vol) < 1e-12
+    # a uniform field is divergence free
+    assert np.abs(Q.div @ synth.uniform_face_flux(mesh.xyz, fc, B0)).max() < 1e-14
+
+
+def test_div_of_curl_vanishes(mesh, Q):
+    """(C e)_f = e_ab + e_bc - e_ac (the face-edge incidence of the field
+    update) composed with the divergence is zero."""
+    from oracle import field
+    fe = field.face_edges(mesh)
+    C = np.zeros((mesh.nf, mesh.ne))
+    C[np.arange(mesh.nf), fe[:, 0]] += 1
+    C[np.arange(mesh.nf), fe[:, 1]] += 1
+    C[np.arange(mesh.nf), fe[:, 2]] -= 1
+    assert np.abs(Q.div @ C).max() == 0.0
+
+
+def test_sigma_is_eps_mg(mesh, Q):
+    """Sigma = [*eps] D equals eps0 <W1_i, grad W0_j>, integrated directly:
+    int W1_pq . g_j = V/4 (g_q - g_p) . g_j."""
+    from oracle import field
+    g, vol = field.tet_gradients(mesh.xyz, mesh.tv)
+    te = mesh.tet_edges()
+    Mg = np.zeros((mesh.ne, mesh.nv))
+    for e, (p, q) in enumerate(field.LE):
+        for j in range(4):
+            np.add.at(Mg, (te[:, e], mesh.tv[:, j]),
+                      vol / 4.0 * np.einsum("ta,ta->t", g[:, q] - g[:, p], g[:, j]))
+    assert rel(Q.Sigma.toarray(), EPS0 * Mg) < 1e-12
+
+
+def test_magnetic_projector(mesh, Q):
+    from oracle import field
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal(mesh.nf) + 1j * rng.standard_normal(mesh.nf)
+    c = rng.standard_normal(mesh.nf)
+    Pb = Q.project_b(b)
+    scale = np.abs(b).max()
+    assert np.abs(Q.div @ Pb).max() < 1e-12 * scale                # divergence free
+    assert rel(Q.project_b(Pb), Pb) < 1e-12                         # idempotent
+    assert abs(np.vdot(Q.project_b(c), b) - np.vdot(c, Pb)) < 1e-12 * np.abs(b).sum() * np.abs(c).max()   # symmetric
+    fe = field.face_edges(mesh)
+    e = rng.standard_normal(mesh.ne)
+    ce = e[fe[:, 0]] + e[fe[:, 1]] - e[fe[:, 2]]
+    assert rel(Q.project_b(ce), ce) < 1e-12                         # curls kept
+    y = rng.standard_normal(mesh.nt)
+    assert np.abs(Q.project_b(Q.div.T @ y)).max() < 1e-12 * np.abs(Q.div.T @ y).max()   # range of div^T killed
+
+
+def test_electric_projectors(mesh, Q):
+    rng = np.random.default_rng(5)
+    d = (rng.standard_normal(mesh.ne) + 1j * rng.standard_normal(mesh.ne)) * 1e-11
+    ps, pl, y = Q.project_e(d)
+    assert rel(ps + pl, d) < 1e-15
+    assert rel(Q.project_e(ps)[0], ps) < 1e-10                       # idempotent
+    assert np.abs(Q.project_e(pl)[0]).max() < 1e-10 * np.abs(d).max()
+    c = rng.standard_normal(mesh.ne) * 1e-11
+    assert abs(np.vdot(Q.project_e(c)[0], d) - np.vdot(c, ps)) < 1e-10 * np.abs(d).sum() * np.abs(c).max()
+    # Sigma^T P^Lambda d = 0: the solenoidal part has no discrete divergence
+    assert np.abs(Q.Sigma.T @ pl).max() < 1e-10 * np.abs(Q.Sigma.T @ d).max()
+    # a pure gradient flux density: E_ns is its potential (up to the constant)
+    phi = rng.standard_normal(mesh.nv)
+    ps2, pl2, y2 = Q.project_e(Q.Sigma @ phi)
+    assert rel(y2, phi - phi.mean()) < 1e-9
+    assert np.abs(pl2).max() < 1e-9 * np.abs(Q.Sigma @ phi).max()
+    assert abs(y.sum()) < 1e-9 * np.abs(y).sum()                       # minimum norm: orthogonal to constants

@@ -460,6 +460,56 @@ int etpic_ns_run_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, 
                        const double *rho0, double *e_work, double tol, int max_iter, uint32_t flags, int *iters_out,
                        void *stream);
 
+/* ---- Quasi-Helmholtz projectors (Quasi Helmholtz or Coulomb gauge section,
+ * eqs. proj_es, proj_el, bfld_projector, efld_projected; App. A):
+ *     P^Lambda_b = I - div^T (div div^T)^-1 div          (face DoFs),
+ *     P^Sigma_e  = Sigma (Sigma^T Sigma)^+ Sigma^T,  P^Lambda_e = I - P^Sigma_e
+ *                                                        (edge DoFs),
+ * with Sigma = eps0 M_g = [*eps] D (the gradient of a hat function is a signed
+ * sum of Whitney edge functions, so M_g = [*eps] D / eps0), D the node-edge
+ * incidence, [*eps] the Whitney edge mass (all rows, no boundary condition)
+ * and div = [*rho]^-1 M_d the signed tet-face incidence (+1 where the face's
+ * global normal, right-handed in its ascending vertex order, points out of
+ * the tet).  + is the Moore-Penrose pseudoinverse: Sigma^T Sigma has the
+ * constants as null space and the nodal solution returned is the one
+ * orthogonal to them.  The projector object owns its own copy of the mesh
+ * tables (same canonical numbering as etpic_mesh_upload) and device work
+ * vectors; it is independent of etpic_ctx.  Errors: etpic status codes, the
+ * message from etpic_qh_last_error() (thread-local).  Vectors are complex,
+ * 2*N float64 interleaved, on the device; calls synchronise `stream`. */
+typedef struct etpic_qh etpic_qh;
+
+/* Thread-local message of the last failing etpic_qh_* call. */
+const char *etpic_qh_last_error(void);
+
+/* Build the projector object on HIP device `device` for the mesh (xyz: 3*nv
+ * float64, tet_vert: 4*nt int32 ascending per row, host) and permittivity
+ * eps (allocates).  *out receives the handle. */
+int etpic_qh_create(etpic_qh **out, int device, int64_t nv, const double *xyz, int64_t nt, const int32_t *tet_vert,
+                    double eps);
+
+/* Free the object (NULL accepted). */
+void etpic_qh_destroy(etpic_qh *qh);
+
+/* counts_out = {N_n, N_e, N_f, N_t, stored entries of [*eps]}. */
+int etpic_qh_counts(const etpic_qh *qh, int64_t counts_out[5]);
+
+/* b_out = P^Lambda_b b (2*N_f float64 each; may alias).  CG on div div^T
+ * stops when ||r|| / ||div b|| <= tol (tested on the device every iteration,
+ * read by the host every 10) or after max_iter: ENOCONV, b_out untouched.
+ * *iters_out, *resid_out (may be NULL) report it. */
+int etpic_qh_project_b(etpic_qh *qh, const double *b, double *b_out, double tol, int max_iter, int *iters_out,
+                       double *resid_out, void *stream);
+
+/* For edge DoFs d (2*N_e float64): d_sigma = P^Sigma_e d, d_lambda =
+ * P^Lambda_e d (2*N_e each) and e_ns = (Sigma^T Sigma)^+ Sigma^T d (2*N_n),
+ * so that d = Sigma e_ns + P^Lambda_e d (eq. efld_projected).  Any output may
+ * be NULL, not all; none may alias d.  Jacobi-preconditioned CG on Sigma^T
+ * Sigma with the stopping rule of etpic_qh_project_b (residual relative to
+ * ||Sigma^T d||); ENOCONV leaves the outputs untouched. */
+int etpic_qh_project_e(etpic_qh *qh, const double *d, double *d_sigma, double *d_lambda, double *e_ns, double tol,
+                       int max_iter, int *iters_out, double *resid_out, void *stream);
+
 /* Kernel times of the steps launched with ETPIC_STEP_TIMING since the last
  * reset, from HIP events recorded on the launch stream around each kernel,
  * summed over the steps: ms_out[0] = particle kernel (gather, push, in-tet

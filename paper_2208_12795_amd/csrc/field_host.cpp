@@ -31,7 +31,8 @@ inline void cross3(const double *a, const double *b, double *c) {
 
 }  // namespace
 
-int build_field_system(const HostMesh &mesh, double eps, double mu, FieldSystem &S, std::string &err) {
+int build_field_system(const HostMesh &mesh, double eps, double mu, FieldSystem &S, std::string &err,
+                       bool dirichlet) {
     if (!(eps > 0.0) || !(mu > 0.0)) {
         err = "eps and mu must be positive";
         return -1;
@@ -65,18 +66,19 @@ int build_field_system(const HostMesh &mesh, double eps, double mu, FieldSystem 
         auto I = [V](int p, int r) { return V * (p == r ? 2.0 : 1.0) / 20.0; };
         for (int e = 0; e < 6; ++e) {
             const int p = kLocalEdge[e][0], q = kLocalEdge[e][1], ge = tp.e[e];
-            if (S.dirichlet[ge]) continue;
+            if (dirichlet && S.dirichlet[ge]) continue;
             for (int f = 0; f < 6; ++f) {
                 const int r = kLocalEdge[f][0], s = kLocalEdge[f][1], gf = tp.e[f];
-                if (S.dirichlet[gf]) continue;
+                if (dirichlet && S.dirichlet[gf]) continue;
                 const double m = I(p, r) * gg[q][s] - I(p, s) * gg[q][r] - I(q, r) * gg[p][s] + I(q, s) * gg[p][r];
                 const double k = 4.0 * V * dot3(cr[e], cr[f]);
                 ent.push_back({(int64_t)ge * ne + gf, eps * m, k / mu});
             }
         }
     }
-    for (int64_t e = 0; e < ne; ++e)
-        if (S.dirichlet[e]) ent.push_back({e * ne + e, 1.0, 0.0});
+    if (dirichlet)
+        for (int64_t e = 0; e < ne; ++e)
+            if (S.dirichlet[e]) ent.push_back({e * ne + e, 1.0, 0.0});
     std::sort(ent.begin(), ent.end(), [](const Entry &x, const Entry &y) { return x.key < y.key; });
     S.rowptr.assign((size_t)ne + 1, 0);
     for (size_t i = 0; i < ent.size();) {

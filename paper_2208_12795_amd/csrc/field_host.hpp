@@ -23,7 +23,10 @@ struct FieldSystem {
     std::vector<int32_t> face_edge;  // nf*3: edges (a,b), (b,c), (a,c) of face (a<b<c)
 };
 
-int build_field_system(const HostMesh &mesh, double eps, double mu, FieldSystem &out, std::string &err);
+// dirichlet = false keeps every row and column (the plain Galerkin matrices;
+// the mask is still filled).
+int build_field_system(const HostMesh &mesh, double eps, double mu, FieldSystem &out, std::string &err,
+                       bool dirichlet = true);
 
 // Nodal operator of the non-solenoidal field (eq. ns_equation):
 //   S[i][j] = eps int grad W0_i . grad W0_j = (D^T [*eps] D)[i][j],

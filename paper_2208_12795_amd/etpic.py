@@ -35,6 +35,8 @@ EXPORTS = (
     "etpic_particles_locate", "etpic_particles_positions", "etpic_coarse_step", "etpic_run_steps",
     "etpic_sort_run_steps", "etpic_ds_history_bytes", "etpic_ds_steps", "etpic_ds_sort",
     "etpic_ns_setup", "etpic_ns_info", "etpic_ns_solve", "etpic_ns_run_steps",
+    "etpic_qh_last_error", "etpic_qh_create", "etpic_qh_destroy", "etpic_qh_counts", "etpic_qh_project_b",
+    "etpic_qh_project_e",
 )
 
 
@@ -116,7 +118,17 @@ def lib():
                                  C.POINTER(C.c_int), dp, vp]
     L.etpic_ns_run_steps.argtypes = [vp, vp, C.c_int, vp, vp, C.c_int64, C.c_int, C.c_double, C.c_double, vp, vp,
                                      vp, C.c_double, C.c_int, C.c_uint32, C.POINTER(C.c_int), vp]
+    L.etpic_qh_last_error.restype = C.c_char_p
+    L.etpic_qh_last_error.argtypes = []
+    L.etpic_qh_create.argtypes = [C.POINTER(vp), C.c_int, C.c_int64, dp, C.c_int64, i32p, C.c_double]
+    L.etpic_qh_destroy.argtypes = [vp]
+    L.etpic_qh_destroy.restype = None
+    L.etpic_qh_counts.argtypes = [vp, i64p]
+    L.etpic_qh_project_b.argtypes = [vp, vp, vp, C.c_double, C.c_int, C.POINTER(C.c_int), dp, vp]
+    L.etpic_qh_project_e.argtypes = [vp, vp, vp, vp, vp, C.c_double, C.c_int, C.POINTER(C.c_int), dp, vp]
     for name in EXPORTS:
+        if name in ("etpic_qh_last_error", "etpic_qh_destroy"):
+            continue
         if name != "etpic_last_error":
             getattr(L, name).restype = C.c_int
     _lib = L
@@ -527,3 +539,56 @@ class Context:
         if raise_on_error:
             _chk(rc)
         return rc, int(word.value)
+
+
+def _qchk(rc):
+    if rc != OK:
+        raise EtpicError(rc, lib().etpic_qh_last_error().decode())
+    return rc
+
+
+class QhProjectors:
+    """Quasi-Helmholtz projectors on one mesh (its own copy of the mesh tables;
+    same canonical numbering as Context.upload_mesh).  Vectors are float64
+    [N, 2] (complex) device tensors."""
+
+    def __init__(self, xyz, tet_vert, eps, device=0):
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        tv = np.ascontiguousarray(tet_vert, dtype=np.int32)
+        self._h = C.c_void_p()
+        _qchk(lib().etpic_qh_create(C.byref(self._h), int(device), xyz.shape[0], _np_ptr(xyz, C.c_double),
+                                    tv.shape[0], _np_ptr(tv, C.c_int32), float(eps)))
+        cnt = (C.c_int64 * 5)()
+        _qchk(lib().etpic_qh_counts(self._h, cnt))
+        self.n_vert, self.n_edge, self.n_face, self.n_tet, self.nnz = (int(v) for v in cnt)
+
+    def close(self):
+        if self._h:
+            lib().etpic_qh_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def project_b(self, b, b_out, tol=1e-12, max_iter=5000, stream=None, raise_on_error=True):
+        """b_out = P^Lambda_b b; returns (status, iterations, relative residual)."""
+        it, res = C.c_int(0), C.c_double(0.0)
+        rc = lib().etpic_qh_project_b(self._h, _dptr(b), _dptr(b_out), float(tol), int(max_iter), C.byref(it),
+                                      C.byref(res), _stream(stream))
+        if raise_on_error:
+            _qchk(rc)
+        return rc, it.value, res.value
+
+    def project_e(self, d, d_sigma=None, d_lambda=None, e_ns=None, tol=1e-12, max_iter=5000, stream=None,
+                  raise_on_error=True):
+        """d_sigma = P^Sigma_e d, d_lambda = P^Lambda_e d, e_ns = (Sigma^T Sigma)^+ Sigma^T d;
+        returns (status, iterations, relative residual)."""
+        it, res = C.c_int(0), C.c_double(0.0)
+        rc = lib().etpic_qh_project_e(self._h, _dptr(d), _dptr(d_sigma), _dptr(d_lambda), _dptr(e_ns), float(tol),
+                                      int(max_iter), C.byref(it), C.byref(res), _stream(stream))
+        if raise_on_error:
+            _qchk(rc)
+        return rc, it.value, res.value

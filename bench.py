@@ -238,6 +238,39 @@ def ns_solve_timing(E, torch, ctx, w, reps=3):
                     "with the solve before it (warm start), mean of 5 steps" % (reps, w.tet.shape[0])}
 
 
+def qh_projector_timing(E, torch, w, reps=3):
+    """Side path, timed separately: the quasi-Helmholtz projectors on the bench
+    mesh, to a 1e-10 relative residual.  P^Lambda_b of the workload's face
+    envelope plus a random part (CG on div div^T over the tets); P^Sigma_e /
+    P^Lambda_e of random edge DoFs (CG on Sigma^T Sigma over the nodes, four
+    passes per iteration)."""
+    eps0 = 8.8541878128e-12
+    P = E.QhProjectors(w.xyz, w.tet_vert, eps0)
+    g = torch.Generator(device="cuda").manual_seed(11)
+    b = torch.from_numpy(np.ascontiguousarray(np.stack([w.b_env.real, w.b_env.imag], axis=1))).cuda()
+    b = b + 1e-3 * b.abs().max() * torch.randn(b.shape, dtype=torch.float64, device="cuda", generator=g)
+    bo = torch.empty_like(b)
+    d = 1e-11 * torch.randn((P.n_edge, 2), dtype=torch.float64, device="cuda", generator=g)
+    ds, dl = torch.empty_like(d), torch.empty_like(d)
+    out = {}
+    for name, call in (("project_b", lambda: P.project_b(b, bo, tol=1e-10, raise_on_error=False)),
+                       ("project_e", lambda: P.project_e(d, ds, dl, None, tol=1e-10, raise_on_error=False))):
+        call()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            rc, it, res = call()
+            torch.cuda.synchronize()
+            ms.append(1e3 * (time.perf_counter() - t0))
+        out[name] = {"ms": min(ms), "cg_iterations": it, "ms_per_iteration": min(ms) / max(it, 1),
+                     "rel_residual": res, "status": rc}
+    out["n_tets"], out["n_nodes"] = P.n_tet, P.n_vert
+    out["note"] = "side path, not in value; wall time of the whole projection, best of %d" % reps
+    P.close()
+    return out
+
+
 def coarse_step_timing(E, torch, synth, ctx, w, fine=10, reps=5):
     """Multi-rate form: one coarse field step of `fine` fine steps with the
     envelope reconstructed from three snapshots (quadratic in time) at every
@@ -497,6 +530,8 @@ def main():
         log(f"[bench] field update: {json.dumps(line['field_update'])}")
         line["ns_solve"] = ns_solve_timing(E, torch, ctx, w)
         log(f"[bench] non-solenoidal solve: {json.dumps(line['ns_solve'])}")
+        line["qh_projectors"] = qh_projector_timing(E, torch, w)
+        log(f"[bench] quasi-Helmholtz projectors: {json.dumps(line['qh_projectors'])}")
         line["coarse_step"] = coarse_step_timing(E, torch, synth, ctx, w)
         log(f"[bench] coarse step: {json.dumps(line['coarse_step'])}")
         line["downshifted_step"] = ds_step_timing(E, torch, ctx, w)

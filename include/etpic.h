@@ -510,6 +510,22 @@ int etpic_qh_project_b(etpic_qh *qh, const double *b, double *b_out, double tol,
 int etpic_qh_project_e(etpic_qh *qh, const double *d, double *d_sigma, double *d_lambda, double *e_ns, double tol,
                        int max_iter, int *iters_out, double *resid_out, void *stream);
 
+/* Tree-cotree maps of the split (Discrete System; the maps [C^e_c], [C^b_c]
+ * of App. A), host only, no device needed.  For the mesh (arguments as
+ * etpic_mesh_canonical, same canonical numbering): edge_tree_host[e] = 1 for
+ * the edges of a spanning tree of the vertex graph (breadth first from the
+ * lowest vertex of each component), 0 for the cotree edges; face_tree_host[f]
+ * = 1 for the faces of a spanning tree of the dual graph (tets plus one
+ * exterior node joined by the boundary faces), 0 for the cotree faces.  [C^e_c]
+ * and [C^b_c] select the cotree edges and faces in ascending id: with a
+ * connected mesh there are N_e - N_n + 1 and N_f - N_t of them, the
+ * dimensions of the discretely divergence-free edge and face fields, and the
+ * tree values of such a field follow from its cotree values.  counts_out =
+ * {tree edges, cotree edges, tree faces, cotree faces}.  Errors as
+ * etpic_mesh_canonical, message from etpic_qh_last_error(). */
+int etpic_tree_cotree(int64_t n_vert, const double *xyz_host, int64_t n_tet, const int32_t *tet_vert_host,
+                      uint8_t *edge_tree_host, uint8_t *face_tree_host, int64_t counts_out[4]);
+
 /* Kernel times of the steps launched with ETPIC_STEP_TIMING since the last
  * reset, from HIP events recorded on the launch stream around each kernel,
  * summed over the steps: ms_out[0] = particle kernel (gather, push, in-tet

@@ -36,7 +36,7 @@ EXPORTS = (
     "etpic_sort_run_steps", "etpic_ds_history_bytes", "etpic_ds_steps", "etpic_ds_sort",
     "etpic_ns_setup", "etpic_ns_info", "etpic_ns_solve", "etpic_ns_run_steps",
     "etpic_qh_last_error", "etpic_qh_create", "etpic_qh_destroy", "etpic_qh_counts", "etpic_qh_project_b",
-    "etpic_qh_project_e",
+    "etpic_qh_project_e", "etpic_tree_cotree",
 )
 
 
@@ -126,6 +126,8 @@ def lib():
     L.etpic_qh_counts.argtypes = [vp, i64p]
     L.etpic_qh_project_b.argtypes = [vp, vp, vp, C.c_double, C.c_int, C.POINTER(C.c_int), dp, vp]
     L.etpic_qh_project_e.argtypes = [vp, vp, vp, vp, vp, C.c_double, C.c_int, C.POINTER(C.c_int), dp, vp]
+    L.etpic_tree_cotree.argtypes = [C.c_int64, dp, C.c_int64, i32p, C.POINTER(C.c_uint8), C.POINTER(C.c_uint8),
+                                    i64p]
     for name in EXPORTS:
         if name in ("etpic_qh_last_error", "etpic_qh_destroy"):
             continue
@@ -169,6 +171,24 @@ def mesh_canonical(xyz, tet_vert):
     _chk(L.etpic_mesh_canonical(xyz.shape[0], _np_ptr(xyz, C.c_double), tv.shape[0], _np_ptr(tv, C.c_int32),
                                 _np_ptr(cnt, C.c_int64), _np_ptr(edges, C.c_int32), _np_ptr(faces, C.c_int32)))
     return cnt, edges, faces
+
+
+def tree_cotree(xyz, tet_vert):
+    """Host-only tree-cotree split (no GPU needed): (edge_tree bool[N_e],
+    face_tree bool[N_f]), True on the tree."""
+    L = lib()
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    tv = np.ascontiguousarray(tet_vert, dtype=np.int32)
+    cnt, _, _ = mesh_canonical(xyz, tv)
+    et = np.zeros(int(cnt[1]), dtype=np.uint8)
+    ft = np.zeros(int(cnt[2]), dtype=np.uint8)
+    c4 = np.zeros(4, dtype=np.int64)
+    rc = L.etpic_tree_cotree(xyz.shape[0], _np_ptr(xyz, C.c_double), tv.shape[0], _np_ptr(tv, C.c_int32),
+                             _np_ptr(et, C.c_uint8), _np_ptr(ft, C.c_uint8), _np_ptr(c4, C.c_int64))
+    if rc != OK:
+        raise EtpicError(rc, L.etpic_qh_last_error().decode())
+    assert c4[0] == et.sum() and c4[2] == ft.sum()
+    return et.astype(bool), ft.astype(bool)
 
 
 @dataclass

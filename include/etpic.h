@@ -441,24 +441,27 @@ int etpic_ns_solve(etpic_ctx *ctx, const double *G, const double *rho0, double t
 
 /* The particles in the field of their own charge: the loop field -> particles
  * -> G -> field closed through eq. ns_equation (the non-solenoidal part of
- * the split only; no solenoidal field is computed).  For each of nsteps
+ * the split only; no solenoidal field is computed).  Every steps_per_solve
  * steps, at t = (step0 + j) dt: solve eq. ns_equation from G and rho0
  * (warm-started after the first solve, and for the first too with
- * ETPIC_NS_WARM), set e_work = e_ns (+ ext->e_env), then one particle step
- * (as etpic_run_steps) in the fields {e_work, ext->e_dc, ext->b_env,
- * ext->b_dc} (without ext: no other field), its path integral added to G.
+ * ETPIC_NS_WARM) and set e_work = D y (+ ext->e_dc): the field of the charge
+ * is quasi-static, so it enters the steps as real, unmodulated edge DoFs and
+ * is held over the steps up to the next solve (the multi-rate use: fields at
+ * the coarse step, particles at the fine one).  Then those steps (as
+ * etpic_run_steps) in the fields {ext->e_env, e_work, ext->b_env, ext->b_dc}
+ * (without ext: no other field), their path integrals added to G.
  * G: N_e float64 (device, in place), the running path integral of the
  * current; rho0: N_n float64 (device, NULL = 0), the charge when G was zero;
- * e_work: 2*N_e float64 (device, caller-owned; holds the last step's edge
- * envelope on return; must not be ext->e_env).  One species per call.
- * flags: ETPIC_STEP_* flags of the particle step, ETPIC_NS_WARM.
- * *iters_out (may be NULL): CG iterations summed over the steps.
- * Synchronises `stream` once per step.  ENOCONV stops the loop at the step
- * whose solve failed (the particles have taken the steps before it). */
+ * e_work: N_e float64 (device, caller-owned; holds the last solve's edge DoFs
+ * on return; must not be ext->e_dc).  One species per call.  flags:
+ * ETPIC_STEP_* flags of the particle steps, ETPIC_NS_WARM.  *iters_out (may
+ * be NULL): CG iterations summed over the solves.  Synchronises `stream` once
+ * per solve.  ENOCONV stops the loop at the solve that failed (the particles
+ * have taken the steps before it). */
 int etpic_ns_run_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, const etpic_species *sp,
-                       const etpic_fields *ext, int64_t step0, int nsteps, double dt, double omega, double *G,
-                       const double *rho0, double *e_work, double tol, int max_iter, uint32_t flags, int *iters_out,
-                       void *stream);
+                       const etpic_fields *ext, int64_t step0, int nsteps, int steps_per_solve, double dt,
+                       double omega, double *G, const double *rho0, double *e_work, double tol, int max_iter,
+                       uint32_t flags, int *iters_out, void *stream);
 
 /* ---- Quasi-Helmholtz projectors (Quasi Helmholtz or Coulomb gauge section,
  * eqs. proj_es, proj_el, bfld_projector, efld_projected; App. A):

@@ -2208,18 +2208,18 @@ __global__ void __launch_bounds__(kNsThreads) k_ns_update(int64_t nv, const doub
     ns_block_sum4(v, pout);
 }
 
-// x_out = e^{-j w t} x on the nodes, e_out = e^{-j w t} D x (+ e_add) on the
-// edges (edge e from ev[2e] to ev[2e+1]); x_out, e_out, e_add may be NULL.
+// x_out = e^{-j w t} x on the nodes, e_out = e^{-j w t} D x on the edges
+// (edge e from ev[2e] to ev[2e+1]), edc_out = D x (+ edc_add): the same field
+// as real, unmodulated DoFs.  Every pointer may be NULL.
 __global__ void __launch_bounds__(kBlock) k_ns_out(int64_t ne, int64_t nv, const int32_t *__restrict__ ev,
                                                    const double *__restrict__ x, double c, double s,
                                                    double2 *__restrict__ x_out, double2 *__restrict__ e_out,
-                                                   const double2 *__restrict__ e_add) {
+                                                   double *__restrict__ edc_out, const double *__restrict__ edc_add) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e_out && i < ne) {
+    if ((e_out || edc_out) && i < ne) {
         const double d = x[ev[2 * i + 1]] - x[ev[2 * i]];
-        double2 e = make_double2(c * d, -s * d);
-        if (e_add) e = cadd(e, e_add[i]);
-        e_out[i] = e;
+        if (e_out) e_out[i] = make_double2(c * d, -s * d);
+        if (edc_out) edc_out[i] = edc_add ? d + edc_add[i] : d;
     }
     if (x_out && i < nv) {
         const double xi = x[i];
@@ -2269,12 +2269,13 @@ struct NsState {
     double *partial = nullptr;  // two sets of 4 per block (kNsBlocks blocks)
     double *sc = nullptr;       // 12 scalars of the iteration
     double *bzero = nullptr;    // 2*N_f zeros: the face envelope of a loop without external fields
+    double *ezero = nullptr;    // 2*N_e zeros: its edge envelope
 
     double *v(int k) const { return vec + (size_t)k * nv; }
     NsCsr csr() const { return NsCsr{nv, rowptr, col, S}; }
     void release() {
         for (void *q : {(void *)rowptr, (void *)col, (void *)ev, (void *)S, (void *)dinv, (void *)wall, (void *)vec,
-                        (void *)partial, (void *)sc, (void *)bzero})
+                        (void *)partial, (void *)sc, (void *)bzero, (void *)ezero})
             (void)hipFree(q);
         *this = NsState();
     }
@@ -3503,6 +3504,8 @@ int etpic_ns_setup(etpic_ctx *ctx, double eps) {
     HIP_TRY(hipMalloc(&N.bzero, sizeof(double) * 2 * ctx->host.nf));
     HIP_TRY(hipMemset(N.vec, 0, sizeof(double) * 5 * nv));
     HIP_TRY(hipMemset(N.bzero, 0, sizeof(double) * 2 * ctx->host.nf));
+    HIP_TRY(hipMalloc(&N.ezero, sizeof(double) * 2 * ne));
+    HIP_TRY(hipMemset(N.ezero, 0, sizeof(double) * 2 * ne));
     HIP_TRY(hipMemcpy(N.rowptr, S.rowptr.data(), sizeof(int32_t) * (nv + 1), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(N.col, S.col.data(), sizeof(int32_t) * S.nnz, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(N.ev, ctx->host.edges.data(), sizeof(int32_t) * 2 * ne, hipMemcpyHostToDevice));
@@ -3528,8 +3531,8 @@ namespace {
 // The CG of eq. ns_equation on `st` (synchronises it), from x = 0 or, warm,
 // from the x of the previous solve; outputs scaled by e^{-j w t} = c - j s.
 int ns_solve_impl(etpic_ctx *ctx, const double *G, const double *rho0, double c, double s, double2 *x_out,
-                  double2 *e_out, const double2 *e_add, double tol, int max_iter, bool warm, int *iters_out,
-                  double *resid_out, hipStream_t st) {
+                  double2 *e_out, double *edc_out, const double *edc_add, double tol, int max_iter, bool warm,
+                  int *iters_out, double *resid_out, hipStream_t st) {
     const NsState &N = ctx->ns;
     const int64_t nv = N.nv;
     const unsigned gv = (unsigned)std::min<int64_t>((nv + kNsThreads - 1) / kNsThreads, kNsBlocks);
@@ -3573,7 +3576,8 @@ int ns_solve_impl(etpic_ctx *ctx, const double *G, const double *rho0, double c,
     if (resid_out) *resid_out = rel;
     if (hs[10] == 0.0 || !std::isfinite(rel))
         return fail(ETPIC_ENOCONV, "ns CG: relative residual %.3e after %d iterations", rel, it);
-    k_ns_out<<<grid_for(std::max(N.ne, nv)), kBlock, 0, st>>>(N.ne, nv, N.ev, x, c, s, x_out, e_out, e_add);
+    k_ns_out<<<grid_for(std::max(N.ne, nv)), kBlock, 0, st>>>(N.ne, nv, N.ev, x, c, s, x_out, e_out, edc_out,
+                                                              edc_add);
     HIP_TRY(hipGetLastError());
     return ETPIC_OK;
 }
@@ -3593,22 +3597,22 @@ int etpic_ns_solve(etpic_ctx *ctx, const double *G, const double *rho0, double t
     if (flags & ~(uint32_t)ETPIC_NS_WARM) return fail(ETPIC_EINVAL, "unknown flags 0x%x", flags);
     if (int r = set_device(ctx)) return r;
     return ns_solve_impl(ctx, G, rho0, std::cos(omega * t), std::sin(omega * t), reinterpret_cast<double2 *>(x_out),
-                         reinterpret_cast<double2 *>(e_out), nullptr, tol, max_iter, (flags & ETPIC_NS_WARM) != 0,
-                         iters_out, resid_out, static_cast<hipStream_t>(stream));
+                         reinterpret_cast<double2 *>(e_out), nullptr, nullptr, tol, max_iter,
+                         (flags & ETPIC_NS_WARM) != 0, iters_out, resid_out, static_cast<hipStream_t>(stream));
 }
 
 int etpic_ns_run_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, const etpic_species *sp,
-                       const etpic_fields *ext, int64_t step0, int nsteps, double dt, double omega, double *G,
-                       const double *rho0, double *e_work, double tol, int max_iter, uint32_t flags, int *iters_out,
-                       void *stream) {
+                       const etpic_fields *ext, int64_t step0, int nsteps, int steps_per_solve, double dt,
+                       double omega, double *G, const double *rho0, double *e_work, double tol, int max_iter,
+                       uint32_t flags, int *iters_out, void *stream) {
     if (!ctx) return fail(ETPIC_EINVAL, "null context");
     if (!ctx->ns.ready) return fail(ETPIC_ESTATE, "etpic_ns_setup not called");
     if (!G || !e_work) return fail(ETPIC_EINVAL, "null G or e_work");
     if (ext && (!ext->e_env || !ext->b_env)) return fail(ETPIC_EINVAL, "external fields without e_env / b_env");
-    if (ext && ext->e_env == e_work) return fail(ETPIC_EINVAL, "e_work aliases the external e_env");
-    if (nsteps < 0) return fail(ETPIC_EINVAL, "negative step count");
+    if (ext && ext->e_dc == e_work) return fail(ETPIC_EINVAL, "e_work aliases the external e_dc");
+    if (nsteps < 0 || steps_per_solve < 1) return fail(ETPIC_EINVAL, "bad step counts");
     if (!(tol > 0.0) || max_iter < 1) return fail(ETPIC_EINVAL, "bad tol / max_iter");
-    const etpic_fields f{e_work, ext ? ext->e_dc : nullptr, ext ? ext->b_env : ctx->ns.bzero,
+    const etpic_fields f{ext ? ext->e_env : ctx->ns.ezero, e_work, ext ? ext->b_env : ctx->ns.bzero,
                          ext ? ext->b_dc : nullptr};
     if (int r = check_step_args(ctx, sp, &f, dt, omega)) return r;
     if (int r = check_particles(ctx, p)) return r;
@@ -3616,24 +3620,23 @@ int etpic_ns_run_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, 
     if (nsteps == 0) return ETPIC_OK;
     if (int r = set_device(ctx)) return r;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    const uint32_t sf = flags & ~(uint32_t)ETPIC_NS_WARM;
+    std::vector<StepPlan> plans((size_t)std::min(steps_per_solve, nsteps));
     int total = 0;
-    for (int j = 0; j < nsteps; ++j) {
-        const double t = (double)(step0 + j) * dt;
+    for (int j = 0; j < nsteps; j += steps_per_solve) {
+        const int n = std::min(steps_per_solve, nsteps - j);
         int it = 0;
         const bool warm = j > 0 || (flags & ETPIC_NS_WARM);
-        if (int r = ns_solve_impl(ctx, G, rho0, std::cos(omega * t), std::sin(omega * t), nullptr,
-                                  reinterpret_cast<double2 *>(e_work),
-                                  ext ? reinterpret_cast<const double2 *>(ext->e_env) : nullptr, tol, max_iter, warm,
-                                  &it, nullptr, st)) {
+        if (int r = ns_solve_impl(ctx, G, rho0, 1.0, 0.0, nullptr, nullptr, e_work, ext ? ext->e_dc : nullptr, tol,
+                                  max_iter, warm, &it, nullptr, st)) {
             if (iters_out) *iters_out = total + it;
             return r;
         }
         total += it;
         if (p->n == 0) continue;
-        const StepPlan plan{{&f, nullptr, nullptr}, {1.0, 0.0, 0.0}, t};
-        const uint32_t sf = flags & ~(uint32_t)ETPIC_NS_WARM;
-        const int r = precision == ETPIC_FP64 ? ctx->run_steps<double>(p, sp, &plan, 1, dt, omega, G, nullptr, sf, stream)
-                                              : ctx->run_steps<float>(p, sp, &plan, 1, dt, omega, G, nullptr, sf, stream);
+        for (int i = 0; i < n; ++i) plans[i] = StepPlan{{&f, nullptr, nullptr}, {1.0, 0.0, 0.0}, (double)(step0 + j + i) * dt};
+        const int r = precision == ETPIC_FP64 ? ctx->run_steps<double>(p, sp, plans.data(), n, dt, omega, G, nullptr, sf, stream)
+                                              : ctx->run_steps<float>(p, sp, plans.data(), n, dt, omega, G, nullptr, sf, stream);
         if (r) return r;
     }
     if (iters_out) *iters_out = total;

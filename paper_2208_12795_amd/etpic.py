@@ -116,8 +116,8 @@ def lib():
     L.etpic_ns_info.argtypes = [vp, i64p, i64p]
     L.etpic_ns_solve.argtypes = [vp, vp, vp, C.c_double, C.c_double, vp, vp, C.c_double, C.c_int, C.c_uint32,
                                  C.POINTER(C.c_int), dp, vp]
-    L.etpic_ns_run_steps.argtypes = [vp, vp, C.c_int, vp, vp, C.c_int64, C.c_int, C.c_double, C.c_double, vp, vp,
-                                     vp, C.c_double, C.c_int, C.c_uint32, C.POINTER(C.c_int), vp]
+    L.etpic_ns_run_steps.argtypes = [vp, vp, C.c_int, vp, vp, C.c_int64, C.c_int, C.c_int, C.c_double, C.c_double,
+                                     vp, vp, vp, C.c_double, C.c_int, C.c_uint32, C.POINTER(C.c_int), vp]
     L.etpic_qh_last_error.restype = C.c_char_p
     L.etpic_qh_last_error.argtypes = []
     L.etpic_qh_create.argtypes = [C.POINTER(vp), C.c_int, C.c_int64, dp, C.c_int64, i32p, C.c_double]
@@ -537,19 +537,21 @@ class Context:
         return rc, it.value, res.value
 
     def ns_run_steps(self, parts, species, step0, nsteps, dt, omega, G, e_work, rho0=None, ext=None, tol=1e-12,
-                     max_iter=2000, flags=STEP_XCD_REMAP, warm=False, stream=None):
-        """nsteps particle steps, each in the field of the charge (rho0 + D^T G)
-        solved just before it (plus the external fields ext, a Fields or None);
-        G float64 [N_e] accumulates; e_work float64 [N_e, 2] receives the edge
-        envelope.  Returns the CG iterations summed over the steps."""
+                     max_iter=2000, flags=STEP_XCD_REMAP, warm=False, steps_per_solve=1, stream=None):
+        """nsteps particle steps in the field of the charge (rho0 + D^T G),
+        solved every steps_per_solve steps and held in between, plus the
+        external fields ext (a Fields or None); G float64 [N_e] accumulates;
+        e_work float64 [N_e] receives the field's real edge DoFs (+ ext.e_dc).
+        Returns the CG iterations summed over the solves."""
         d = parts.desc()
         sp = species.c()
         fd = None if ext is None else ext.desc()
         it = C.c_int(0)
         rc = lib().etpic_ns_run_steps(self._h, C.byref(d), parts.precision, C.byref(sp),
-                                      None if fd is None else C.byref(fd), int(step0), int(nsteps), float(dt),
-                                      float(omega), _dptr(G), _dptr(rho0), _dptr(e_work), float(tol), int(max_iter),
-                                      int(flags) | (NS_WARM if warm else 0), C.byref(it), _stream(stream))
+                                      None if fd is None else C.byref(fd), int(step0), int(nsteps),
+                                      int(steps_per_solve), float(dt), float(omega), _dptr(G), _dptr(rho0),
+                                      _dptr(e_work), float(tol), int(max_iter), int(flags) | (NS_WARM if warm else 0),
+                                      C.byref(it), _stream(stream))
         _chk(rc)
         return it.value
 

@@ -22,24 +22,28 @@ def mode_amplitude(e_real, shape):
     return float(e_real @ shape / (shape @ shape))
 
 
-def oracle_loop(ora, cp, nsteps, dt, shape, omega=0.0, record=None):
-    """nsteps oracle steps of the plasma cp, each in the field solved from the
-    background-neutralised charge just before it.  Returns (states, G, signal,
-    rho0): states[j] = (tet, lam, vel, G) after step j (for j in record, all if
-    None), signal[j] = the mode amplitude of the real field at step j."""
+def oracle_loop(ora, cp, nsteps, dt, shape, omega=0.0, record=None, per=1):
+    """nsteps oracle steps of the plasma cp in the field solved from the
+    background-neutralised charge every `per` steps (held in between, as real
+    unmodulated edge DoFs).  Returns (states, G, signal, rho0): states[j] =
+    (tet, lam, vel, G) after step j (for j in record, all if None), signal[j]
+    = the mode amplitude of the field used at step j."""
     from oracle import gauss
     m = ora.OracleMesh(cp.xyz, cp.tet_vert)
     ns = gauss.NsOracle(m, 8.8541878128e-12)
     rho0 = m.charge(cp.tet, cp.lam, cp.q, cp.w) - m.charge(cp.tet0, cp.lam0, cp.q, cp.w)
     t, l, v = cp.tet.copy(), cp.lam.copy(), cp.vel.copy()
     G = np.zeros(m.ne)
+    ez = np.zeros(m.ne, complex)
     bz = np.zeros(m.nf, complex)
     states, sig = [], []
     for j in range(nsteps):
-        _, e = ns.solve(G=G, rho0=rho0, t=j * dt, omega=omega)
-        sig.append(mode_amplitude((e * np.exp(1j * omega * j * dt)).real, shape))
-        rc, _ = m.step(t, l, v, q=cp.q, m=cp.m, w=cp.w, step=j, dt=dt, omega=omega, e_env=e, b_env=bz, dG=G,
-                       nthreads=NTH)
+        if j % per == 0:
+            _, e = ns.solve(G=G, rho0=rho0)
+            edc = e.real.copy()
+        sig.append(mode_amplitude(edc, shape))
+        rc, _ = m.step(t, l, v, q=cp.q, m=cp.m, w=cp.w, step=j, dt=dt, omega=omega, e_env=ez, b_env=bz, e_dc=edc,
+                       dG=G, nthreads=NTH)
         assert rc == 0
         if record is None or j in record:
             states.append((t.copy(), l.copy(), v.copy(), G.copy()))

@@ -2004,7 +2004,8 @@ struct NsCsr {
 // sc[0], sc[1] rho = r.z of even / odd iterations, sc[8] |r|^2, sc[9] |b|^2,
 // sc[10] done flag, sc[11] iterations taken.
 constexpr int kNsBlocks = 512;
-constexpr int kNsThreads = 1024;   // 16 wavefronts per block: enough rows in flight for one pass
+constexpr int kNsThreads = 1024;   // product kernels: 16 wavefronts per block, enough rows in flight for one pass
+constexpr int kNsVecThreads = 256; // vector kernels (one node per lane): more, smaller blocks
 
 // Block-level sum of 4 doubles into partial[blockIdx.x * 4 + k].
 __device__ __forceinline__ void ns_block_sum4(double v[4], double *partial) {
@@ -2018,7 +2019,7 @@ __device__ __forceinline__ void ns_block_sum4(double v[4], double *partial) {
     __syncthreads();
     if (threadIdx.x < 4) {
         double t = 0.0;
-        for (int w = 0; w < kNsThreads / 64; ++w) t += sh[w][threadIdx.x];
+        for (int w = 0; w < (int)(blockDim.x / 64); ++w) t += sh[w][threadIdx.x];
         partial[blockIdx.x * 4 + threadIdx.x] = t;
     }
 }
@@ -2040,7 +2041,7 @@ __device__ __forceinline__ void all_sum4(int64_t nb, const double *__restrict__ 
     __syncthreads();
     if (threadIdx.x < 4) {
         double t = 0.0;
-        for (int w = 0; w < kNsThreads / 64; ++w) t += sh[w][threadIdx.x];
+        for (int w = 0; w < (int)(blockDim.x / 64); ++w) t += sh[w][threadIdx.x];
         res[threadIdx.x] = t;
     }
     __syncthreads();
@@ -2065,7 +2066,7 @@ __device__ __forceinline__ double ns_rhs(int64_t i, const int32_t *__restrict__ 
 }
 
 // Cold start: x = 0, r = b, z = Dinv b, p = q = 0; partials r.z, 0, |r|^2, |b|^2.
-__global__ void __launch_bounds__(kNsThreads) k_ns_start(int64_t nv, const int32_t *__restrict__ ptr,
+__global__ void __launch_bounds__(kNsVecThreads) k_ns_start(int64_t nv, const int32_t *__restrict__ ptr,
                                                      const int32_t *__restrict__ code, const double *__restrict__ G,
                                                      const double *__restrict__ rho0, const uint8_t *__restrict__ wall,
                                                      const double *__restrict__ dinv, double *__restrict__ x,
@@ -2184,7 +2185,7 @@ __global__ void __launch_bounds__(kNsThreads) k_ns_apply(NsCsr S, double *__rest
 // Iteration k, second half: alpha = rho_new / (p . q) from the partials of the
 // product; x += alpha p, r -= alpha q, z = Dinv r, with the partials of r . z
 // and |r|^2.  Returns at once if the first half found convergence.
-__global__ void __launch_bounds__(kNsThreads) k_ns_update(int64_t nv, const double *__restrict__ sc,
+__global__ void __launch_bounds__(kNsVecThreads) k_ns_update(int64_t nv, const double *__restrict__ sc,
                                                       const double *__restrict__ dinv, const double *__restrict__ p,
                                                       const double *__restrict__ q, double *__restrict__ x,
                                                       double *__restrict__ r, double *__restrict__ z,
@@ -3535,7 +3536,7 @@ int ns_solve_impl(etpic_ctx *ctx, const double *G, const double *rho0, double c,
                   int *iters_out, double *resid_out, hipStream_t st) {
     const NsState &N = ctx->ns;
     const int64_t nv = N.nv;
-    const unsigned gv = (unsigned)std::min<int64_t>((nv + kNsThreads - 1) / kNsThreads, kNsBlocks);
+    const unsigned gv = (unsigned)std::min<int64_t>((nv + kNsVecThreads - 1) / kNsVecThreads, kNsBlocks);
     const unsigned gr = (unsigned)std::min<int64_t>((nv * kRowLanes + kNsThreads - 1) / kNsThreads, kNsBlocks);
     double *x = N.v(0), *r = N.v(1), *z = N.v(2), *p = N.v(3), *q = N.v(4);
     // partials: pa from the product (gr blocks), pb from the start and the update
@@ -3545,7 +3546,7 @@ int ns_solve_impl(etpic_ctx *ctx, const double *G, const double *rho0, double c,
         k_ns_start_warm<<<gr, kNsThreads, 0, st>>>(N.csr(), ctx->d_v2e_ptr, ctx->d_v2e_code, G, rho0, N.wall, N.dinv, x, r,
                                                z, p, q, pb, N.sc);
     else
-        k_ns_start<<<gv, kNsThreads, 0, st>>>(nv, ctx->d_v2e_ptr, ctx->d_v2e_code, G, rho0, N.wall, N.dinv, x, r, z, p, q,
+        k_ns_start<<<gv, kNsVecThreads, 0, st>>>(nv, ctx->d_v2e_ptr, ctx->d_v2e_code, G, rho0, N.wall, N.dinv, x, r, z, p, q,
                                           pb, N.sc);
     HIP_TRY(hipGetLastError());
     // Iterations are launched in batches; the device raises the done flag when
@@ -3559,7 +3560,7 @@ int ns_solve_impl(etpic_ctx *ctx, const double *G, const double *rho0, double c,
         const int n = std::min(batch, max_iter - k);
         for (int j = 0; j < n; ++j, ++k) {
             k_ns_apply<<<gr, kNsThreads, 0, st>>>(N.csr(), N.sc, z, p, q, pb, nb, pa, k, tol2, 0);
-            k_ns_update<<<gv, kNsThreads, 0, st>>>(nv, N.sc, N.dinv, p, q, x, r, z, pa, gr, pb, k);
+            k_ns_update<<<gv, kNsVecThreads, 0, st>>>(nv, N.sc, N.dinv, p, q, x, r, z, pa, gr, pb, k);
             nb = gv;
         }
         if (k >= max_iter) k_ns_apply<<<gr, kNsThreads, 0, st>>>(N.csr(), N.sc, z, p, q, pb, nb, pa, k, tol2, 1);
@@ -3609,7 +3610,9 @@ int etpic_ns_run_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, 
     if (!ctx->ns.ready) return fail(ETPIC_ESTATE, "etpic_ns_setup not called");
     if (!G || !e_work) return fail(ETPIC_EINVAL, "null G or e_work");
     if (ext && (!ext->e_env || !ext->b_env)) return fail(ETPIC_EINVAL, "external fields without e_env / b_env");
-    if (ext && ext->e_dc == e_work) return fail(ETPIC_EINVAL, "e_work aliases the external e_dc");
+    if (ext && (ext->e_dc == e_work || ext->e_env == e_work || ext->b_env == e_work || ext->b_dc == e_work))
+        return fail(ETPIC_EINVAL, "e_work aliases an external field array");
+    if (G == e_work || (rho0 && rho0 == e_work)) return fail(ETPIC_EINVAL, "e_work aliases G or rho0");
     if (nsteps < 0 || steps_per_solve < 1) return fail(ETPIC_EINVAL, "bad step counts");
     if (!(tol > 0.0) || max_iter < 1) return fail(ETPIC_EINVAL, "bad tol / max_iter");
     const etpic_fields f{ext ? ext->e_env : ctx->ns.ezero, e_work, ext ? ext->b_env : ctx->ns.bzero,

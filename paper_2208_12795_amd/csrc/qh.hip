@@ -714,6 +714,8 @@ int etpic_qh_project_e(etpic_qh *qh, const double *d, double *d_sigma, double *d
                        int max_iter, int *iters_out, double *resid_out, void *stream) {
     if (!qh || !d) return qfail(ETPIC_EINVAL, "null argument");
     if (!d_sigma && !d_lambda && !e_ns) return qfail(ETPIC_EINVAL, "no output requested");
+    if (d_sigma == d || d_lambda == d || (d_sigma && d_sigma == d_lambda))
+        return qfail(ETPIC_EINVAL, "outputs alias the input or each other");
     if (!(tol > 0.0) || max_iter < 1) return qfail(ETPIC_EINVAL, "bad tol / max_iter");
     QH_TRY(hipSetDevice(qh->device));
     hipStream_t st = static_cast<hipStream_t>(stream);

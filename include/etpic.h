@@ -431,10 +431,11 @@ enum etpic_ns_flags {
  * either may be NULL but not both): x_out = nodal coefficients, 2*N_n float64
  * (complex, interleaved; 0 on the wall), e_out = edge coefficients of the
  * non-solenoidal electric field, 2*N_e float64 (complex).  flags: 0 or
- * ETPIC_NS_WARM.  Preconditioned CG stops when ||r|| / ||b|| <= tol (checked
- * every 5 iterations) or after max_iter; *iters_out and *resid_out (may be
- * NULL) report it.  Synchronises `stream`.  ENOCONV (outputs untouched) if
- * the tolerance is not reached. */
+ * ETPIC_NS_WARM.  Preconditioned CG stops when ||r|| / ||b|| <= tol (tested
+ * on the device every iteration, read by the host every 10) or after
+ * max_iter; *iters_out and *resid_out (may be NULL) report it.  No source
+ * (b = 0) gives x = 0 without iterations.  Synchronises `stream`.  ENOCONV
+ * (outputs untouched) if the tolerance is not reached. */
 int etpic_ns_solve(etpic_ctx *ctx, const double *G, const double *rho0, double t, double omega, double *x_out,
                    double *e_out, double tol, int max_iter, uint32_t flags, int *iters_out, double *resid_out,
                    void *stream);

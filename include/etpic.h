@@ -487,7 +487,8 @@ typedef struct etpic_qh etpic_qh;
 const char *etpic_qh_last_error(void);
 
 /* Build the projector object on HIP device `device` for the mesh (xyz: 3*nv
- * float64, tet_vert: 4*nt int32 ascending per row, host) and permittivity
+ * float64, tet_vert: 4*nt int32 ascending per row, host; the mesh must be
+ * connected, else EMESH, checked before any device call) and permittivity
  * eps (allocates).  *out receives the handle. */
 int etpic_qh_create(etpic_qh **out, int device, int64_t nv, const double *xyz, int64_t nt, const int32_t *tet_vert,
                     double eps);

@@ -475,6 +475,23 @@ int qh_build(etpic_qh *Q, int64_t nv, const double *xyz, int64_t nt, const int32
     etpic::HostMesh H;
     if (int r = etpic::build_host_mesh(nv, xyz, nt, tet_vert, H, err)) return qfail(r == -4 ? ETPIC_EMESH : ETPIC_EINVAL,
                                                                                     "qh mesh: %s", err.c_str());
+    {   // connected vertex graph: the constants are then the only null space of Sigma^T Sigma
+        std::vector<uint8_t> seen((size_t)H.nv, 0);
+        std::vector<int32_t> queue(1, 0);
+        seen[0] = 1;
+        for (size_t h = 0; h < queue.size(); ++h)
+            for (int32_t k = H.v2e_ptr[queue[h]]; k < H.v2e_ptr[queue[h] + 1]; ++k) {
+                const int32_t e = H.v2e_code[k] >> 1;
+                for (int32_t w : {H.edges[2 * e], H.edges[2 * e + 1]})
+                    if (!seen[w]) {
+                        seen[w] = 1;
+                        queue.push_back(w);
+                    }
+            }
+        if ((int64_t)queue.size() != H.nv)
+            return qfail(ETPIC_EMESH, "qh mesh: not connected (%zu of %lld vertices reachable)", queue.size(),
+                         (long long)H.nv);
+    }
     Q->nv = H.nv;
     Q->ne = H.ne;
     Q->nf = H.nf;
@@ -541,6 +558,10 @@ int qh_build(etpic_qh *Q, int64_t nv, const double *xyz, int64_t nt, const int32
         if (!(d > 0.0)) return qfail(ETPIC_EMESH, "qh: node %lld has no edge", (long long)i);
         dinv[i] = 1.0 / d;
     }
+    int count = 0;
+    QH_TRY(hipGetDeviceCount(&count));
+    if (Q->device < 0 || Q->device >= count)
+        return qfail(ETPIC_EINVAL, "device %d not present (%d devices)", Q->device, count);
     QH_TRY(hipSetDevice(Q->device));
     if (int r = upload(&Q->tf, tf)) return r;
     if (int r = upload(&Q->tn, tn)) return r;
@@ -645,9 +666,6 @@ int etpic_qh_create(etpic_qh **out, int device, int64_t nv, const double *xyz, i
     if (!out) return qfail(ETPIC_EINVAL, "null output handle");
     *out = nullptr;
     if (!(eps > 0.0) || !std::isfinite(eps)) return qfail(ETPIC_EINVAL, "eps must be positive");
-    int count = 0;
-    QH_TRY(hipGetDeviceCount(&count));
-    if (device < 0 || device >= count) return qfail(ETPIC_EINVAL, "device %d not present (%d devices)", device, count);
     etpic_qh *Q = new etpic_qh();
     Q->device = device;
     if (int r = qh_build(Q, nv, xyz, nt, tet_vert, eps)) {

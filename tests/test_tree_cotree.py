@@ -89,3 +89,16 @@ def test_divergence_free_fields_follow_from_their_cotree_values(case):
     St = Q.Sigma.T.toarray()
     vt = np.linalg.lstsq(St[:, et], -St[:, ~et] @ v[~et], rcond=None)[0]
     assert np.abs(vt - v[et]).max() < 1e-8 * np.abs(v).max()
+
+
+def test_projectors_reject_a_disconnected_mesh():
+    """Two separate tets: Sigma^T Sigma would have two constant null vectors;
+    the projector object refuses the mesh before it touches a device."""
+    xyz = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1.0],
+                    [5, 0, 0], [6, 0, 0], [5, 1, 0], [5, 0, 1.0]])
+    tv = np.array([[0, 1, 2, 3], [4, 5, 6, 7]], np.int32)
+    with pytest.raises(etpic.EtpicError) as e:
+        etpic.QhProjectors(xyz, tv, EPS0)
+    assert e.value.code == etpic.EMESH
+    et, ft = etpic.tree_cotree(xyz, tv)           # a forest: one tree per component
+    assert et.sum() == 8 - 2 and ft.sum() == 2

@@ -73,7 +73,10 @@ int fail(int code, const char *fmt, ...) {
 constexpr int kBlock = 256;
 constexpr unsigned kWalkQueueCap = 1u << 23;  // entries of each walk queue; N_p <= 64 * kWalkQueueCap
 constexpr unsigned kQueueSkip = 0xffffffffu;  // particle-queue entry to skip
-constexpr unsigned kWalkBlocks = 256;         // grid of the walk kernel
+// grid of the walk kernel (and the walk half of k_walk_coef): the walk is
+// bound by its dependent loads and atomics, not by lanes, and fewer blocks
+// leave the coefficient pass more of the chip and pay fewer end-of-walk fences
+constexpr unsigned kWalkBlocks = 64;
 constexpr int64_t kMinPushWaves = 16384;      // 256 CUs x 64 wavefronts
 
 // Runs of equal key among the 64 lanes of a wavefront (particles are kept

@@ -343,3 +343,29 @@ def test_held_field_equals_single_step_calls(E, torch_cuda):
     assert np.abs(sa[2] - sb[2]).max() <= 1e-11 * np.abs(sa[2]).max()
     assert np.abs(ga - gb).max() <= 1e-12 * np.abs(ga).max()
     assert np.abs(ea - eb).max() <= 1e-11 * np.abs(ea).max()
+
+
+def test_single_inner_node_closed_form(E, torch_cuda):
+    """2^3 unjittered Kuhn cells: one inner node, x = -rho / (6 eps h) in
+    closed form (the 7-point stencil); the edges at it carry D x (+x where the
+    node is the head, -x where it is the tail), every other edge zero."""
+    torch = torch_cuda
+    xyz, tv = synth.kuhn_mesh((2, 2, 2), (1.0, 1.0, 1.0), 0.0)
+    ctx = E.Context(0)
+    ctx.upload_mesh(xyz, tv)
+    ctx.ns_setup(EPS0)
+    c = int(np.argmin(((xyz - 0.5) ** 2).sum(axis=1)))
+    rho = np.zeros(ctx.n_vert)
+    rho[c] = 1e-12
+    x = torch.zeros((ctx.n_vert, 2), dtype=torch.float64, device="cuda")
+    e = torch.zeros((ctx.n_edge, 2), dtype=torch.float64, device="cuda")
+    ctx.ns_solve(None, torch.from_numpy(rho).cuda(), 0.0, 0.0, x, e, tol=1e-14)
+    xc = -1e-12 / (6 * EPS0 * 0.5)
+    xh = x.cpu().numpy()
+    assert abs(xh[c, 0] - xc) <= 1e-14 * abs(xc) and np.count_nonzero(xh) == 1
+    ed = synth.mesh_edges(tv, xyz.shape[0])
+    eh = e.cpu().numpy()[:, 0]
+    at_c = (ed[:, 0] == c) | (ed[:, 1] == c)
+    assert np.allclose(eh[at_c], np.where(ed[at_c, 1] == c, xc, -xc), rtol=1e-14, atol=0)
+    assert np.count_nonzero(eh[~at_c]) == 0
+    ctx.close()

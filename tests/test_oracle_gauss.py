@@ -181,3 +181,30 @@ def test_cold_plasma_oscillation(ora):
         ratios[n] = sig[0] / phi0
     assert 0.85 < ratios[4] < ratios[8] < 1.0, ratios
     assert (1 - ratios[4]) / (1 - ratios[8]) > 3.0, ratios
+
+
+def test_structured_mesh_gives_the_seven_point_stencil(ora):
+    """On the unjittered Kuhn (Freudenthal) grid the linear-element stiffness
+    is the 7-point Laplacian: eps h (6 on the diagonal, -1 for the six axis
+    neighbours, 0 for the others).  With one inner node (2^3 cells) the solve
+    is x = -rho / (6 eps h) in closed form."""
+    from oracle import gauss
+    n, h = 4, 0.25
+    xyz, tv = synth.kuhn_mesh((n, n, n), (1.0, 1.0, 1.0), 0.0)
+    m = ora.OracleMesh(xyz, tv)
+    S = gauss.NsOracle(m, EPS0).S.toarray() / (EPS0 * h)
+    d = xyz[:, None, :] - xyz[None, :, :]
+    axis = (np.abs(np.abs(d).sum(axis=2) - h) < 1e-12) & ((np.abs(d) > 1e-12).sum(axis=2) == 1)
+    inner = ~gauss.wall_nodes(m)
+    for i in np.flatnonzero(inner):
+        ref = -axis[i].astype(float)
+        ref[i] = 6.0
+        assert np.abs(S[i] - ref).max() < 1e-12, i
+    xyz, tv = synth.kuhn_mesh((2, 2, 2), (1.0, 1.0, 1.0), 0.0)
+    m = ora.OracleMesh(xyz, tv)
+    c = int(np.argmin(((xyz - 0.5) ** 2).sum(axis=1)))
+    rho = np.zeros(m.nv)
+    rho[c] = 1e-12
+    x, _ = gauss.NsOracle(m, EPS0).solve(rho0=rho)
+    assert np.isclose(x[c].real, -1e-12 / (6 * EPS0 * 0.5), rtol=1e-14)
+    assert np.count_nonzero(x) == 1

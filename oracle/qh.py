@@ -16,6 +16,10 @@ global normal (right-handed in its ascending vertex order) points out of the
 tet, -1 where it points in.  + is the Moore-Penrose pseudoinverse.  The
 decomposition of the flux density (eq. efld_projected) is
 D = Sigma E_ns + P^Lambda_e D with E_ns = (Sigma^T Sigma)^+ Sigma^T D.
+
+The end of the module builds the Z blocks of the solenoidal system (eq.
+sol_disc) densely on small meshes, for a study of its spectrum (no GPU
+counterpart).
 """
 from __future__ import annotations
 
@@ -92,3 +96,126 @@ class QhOracle:
         y = self.e_ns(d)
         ps = self.Sigma @ y
         return ps, d - ps, y
+
+
+# ------------------------------------------------- solenoidal system (study)
+# eq. sol_disc couples the solenoidal unknowns on the cotree edges and faces
+# through the Z blocks of App. A.  The helpers below build them densely for
+# small meshes, to study the semi-discrete system's spectrum (E'' = -A E with
+# omega = 0, B eliminated): a lossless closed cavity must give real, positive
+# eigenvalues, the squares of its resonance frequencies.
+
+LF = [(1, 2, 3), (0, 2, 3), (0, 1, 3), (0, 1, 2)]
+
+
+def face_mass(mesh, mu):
+    """[*mu^-1]_ij = (1/mu) int W2_i . W2_j with W2_ijk = 2 (l_i g_j x g_k +
+    l_j g_k x g_i + l_k g_i x g_j) (flux 1 through its face, oriented like the
+    face DoFs), 4-point rule (exact for the quadratic integrand); dense."""
+    g, vol = field.tet_gradients(mesh.xyz, mesh.tv)
+    tf = mesh.tet_faces()
+    Ml = np.zeros((mesh.nt, 4, 4))
+    for lam in field.QPTS:
+        W = np.stack([2 * (lam[i] * np.cross(g[:, j], g[:, k]) + lam[j] * np.cross(g[:, k], g[:, i])
+                           + lam[k] * np.cross(g[:, i], g[:, j])) for i, j, k in LF], axis=1)
+        Ml += np.einsum("tka,tla->tkl", W, W) * (vol / 4.0)[:, None, None]
+    F = np.zeros((mesh.nf, mesh.nf))
+    for a in range(4):
+        for b in range(4):
+            np.add.at(F, (tf[:, a], tf[:, b]), Ml[:, a, b] / mu)
+    return F
+
+
+def curl_incidence(mesh):
+    """C [N_f, N_e]: (C e)_f = e_ab + e_bc - e_ac for the face (a < b < c)."""
+    fe = field.face_edges(mesh)
+    C = np.zeros((mesh.nf, mesh.ne))
+    r = np.arange(mesh.nf)
+    C[r, fe[:, 0]] += 1.0
+    C[r, fe[:, 1]] += 1.0
+    C[r, fe[:, 2]] -= 1.0
+    return C
+
+
+def spanning_trees(mesh):
+    """(edge_tree, face_tree) booleans: breadth-first spanning tree of the
+    vertex graph from the lowest vertex of each component (incident edges in
+    ascending id), and of the dual graph of tets plus the exterior (boundary
+    faces first, tets in ascending id, then breadth first)."""
+    ed = mesh.edges().astype(np.int64)
+    adj = [[] for _ in range(mesh.nv)]
+    for e, (a, b) in enumerate(ed):
+        adj[a].append((e, b))
+        adj[b].append((e, a))
+    et = np.zeros(mesh.ne, dtype=bool)
+    seen = np.zeros(mesh.nv, dtype=bool)
+    for root in range(mesh.nv):
+        if seen[root]:
+            continue
+        seen[root] = True
+        queue = [root]
+        for u in queue:
+            for e, w in sorted(adj[u]):
+                if not seen[w]:
+                    seen[w] = True
+                    et[e] = True
+                    queue.append(w)
+    nb, tf = mesh.neighbours(), mesh.tet_faces()
+    ft = np.zeros(mesh.nf, dtype=bool)
+    tseen = np.zeros(mesh.nt, dtype=bool)
+    queue = []
+    for t in range(mesh.nt):
+        for k in range(4):
+            if nb[t, k] < 0:
+                tseen[t] = True
+                ft[tf[t, k]] = True
+                queue.append(t)
+                break
+    for t in queue:
+        for k in range(4):
+            n = nb[t, k]
+            if n >= 0 and not tseen[n]:
+                tseen[n] = True
+                ft[tf[t, k]] = True
+                queue.append(n)
+    return et, ft
+
+
+def solenoidal_blocks(mesh, eps, mu, weighted):
+    """Dense (Z11, Z12, Z21, Z22) of eq. sol_disc on the cotree unknowns.
+    weighted = False: the blocks as printed in App. A (Euclidean projectors,
+    [curl] = C since curl W1 is a signed sum of W2, [*eps]^-1 as a dense
+    inverse).  weighted = True: the same structure with the projectors made
+    orthogonal in the energy products ([*eps] on edges, [*mu^-1] on faces),
+    the fields parameterised as e = P_e C_e E_s, b = P_b C_b B_s and the two
+    equations (Faraday, Ampere) tested with those same fields."""
+    Q = QhOracle(mesh, eps)
+    M = Q.M.toarray()
+    D = Q.D.toarray()
+    div = Q.div.toarray()
+    C = curl_incidence(mesh)
+    F = face_mass(mesh, mu)
+    et, ft = spanning_trees(mesh)
+    Ce = np.eye(mesh.ne)[:, ~et]
+    Cb = np.eye(mesh.nf)[:, ~ft]
+    if not weighted:
+        Sig = M @ D
+        Pe = np.eye(mesh.ne) - Sig @ np.linalg.pinv(Sig.T @ Sig) @ Sig.T
+        Pb = np.eye(mesh.nf) - div.T @ np.linalg.solve(div @ div.T, div)
+        Z11 = Cb.T @ Pb @ Cb
+        Z12 = Cb.T @ C @ np.linalg.solve(M, Pe @ M @ Ce)
+        Z21 = Ce.T @ Pe @ M @ Ce
+        Z22 = Ce.T @ C.T @ F @ Pb @ Cb
+        return Z11, Z12, Z21, Z22, (Ce, Cb, C)
+    Pe = np.eye(mesh.ne) - D @ np.linalg.pinv(D.T @ M @ D) @ D.T @ M
+    Fi = np.linalg.inv(F)
+    Pb = np.eye(mesh.nf) - Fi @ div.T @ np.linalg.solve(div @ Fi @ div.T, div)
+    Ee, Bb = Pe @ Ce, Pb @ Cb
+    return Bb.T @ F @ Bb, Bb.T @ F @ C @ Ee, Ee.T @ M @ Ee, Ee.T @ C.T @ F @ Bb, (Ce, Cb, C)
+
+
+def solenoidal_spectrum(mesh, eps, mu, weighted):
+    """Eigenvalues of A in E'' = -A E (omega = 0, source free), from
+    Z11 B' = -Z12 E and Z21 E' = Z22 B."""
+    Z11, Z12, Z21, Z22, _ = solenoidal_blocks(mesh, eps, mu, weighted)
+    return np.linalg.eigvals(np.linalg.solve(Z21, Z22) @ np.linalg.solve(Z11, Z12))

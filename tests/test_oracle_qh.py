@@ -105,3 +105,35 @@ def test_electric_projectors(mesh, Q):
     assert rel(y2, phi - phi.mean()) < 1e-9
     assert np.abs(pl2).max() < 1e-9 * np.abs(Q.Sigma @ phi).max()
     assert abs(y.sum()) < 1e-9 * np.abs(y).sum()                       # minimum norm: orthogonal to constants
+
+
+MU0 = 1.25663706212e-6
+
+
+def test_solenoidal_system_blocks_and_spectrum(ora):
+    """Study of eq. sol_disc on the unit cube (3^3 and 4^3 unjittered cells).
+    As printed, Z12 = C_b^T [curl] [*eps]^-1 P^Lambda_e [*eps] C_e reduces to
+    C_b^T C C_e (the inverse only removes a gradient, which C annihilates),
+    and the semi-discrete system's eigenvalues are not all real: with the
+    Euclidean projectors it is not a lossless discretisation of the cavity.
+    With the projectors orthogonal in the energy products it is: a real
+    spectrum whose lowest modes (three degenerate ones at c sqrt(2)/2 for the
+    unit cube, then two at c sqrt(3)/2) converge at second order."""
+    from oracle import qh
+    c0 = 1.0 / np.sqrt(EPS0 * MU0)
+    errs = []
+    for n in (3, 4):
+        xyz, tv = synth.kuhn_mesh((n, n, n), (1.0, 1.0, 1.0), 0.0)
+        m = ora.OracleMesh(xyz, tv)
+        Z11, Z12, Z21, Z22, (Ce, Cb, C) = qh.solenoidal_blocks(m, EPS0, MU0, weighted=False)
+        assert Ce.shape[1] == m.ne - m.nv + 1 and Cb.shape[1] == m.nf - m.nt
+        assert np.abs(Z12 - Cb.T @ C @ Ce).max() < 1e-12
+        ev = np.linalg.eigvals(np.linalg.solve(Z21, Z22) @ np.linalg.solve(Z11, Z12))
+        assert np.abs(ev.imag).max() > 0.05 * np.abs(ev).max()
+        ev = qh.solenoidal_spectrum(m, EPS0, MU0, weighted=True)
+        assert np.abs(ev.imag).max() < 1e-10 * np.abs(ev).max() and ev.real.min() > 0
+        f = np.sort(np.sqrt(ev.real)) / (2 * np.pi)
+        f110, f111 = c0 * np.sqrt(2) / 2, c0 * np.sqrt(3) / 2
+        assert np.all(np.abs(f[:3] / f110 - 1) < 0.02) and np.all(np.abs(f[3:5] / f111 - 1) < 0.03)
+        errs.append(np.abs(f[:3] / f110 - 1).max())
+    assert errs[0] / errs[1] > 1.5, errs           # (4/3)^2 = 1.78 for second order

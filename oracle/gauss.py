@@ -21,6 +21,10 @@ path integral of the deposited current; the charge present when it started
 (nodal, rho0) is added to D^T G, since D^T G counts only the change.
 
 Because the operator is real, x = e^{-j w t} y with y real.
+
+`correct` applies the same operator to a given edge field u: it adds the
+gradient D y that makes u obey Gauss' law exactly, which leaves its curl
+(and so the face field) unchanged.
 """
 from __future__ import annotations
 
@@ -88,6 +92,13 @@ class NsOracle:
         y = self.solve_nodal(self.rhs(G, rho0))
         ph = np.exp(-1j * omega * t)
         return y * ph, (self.D @ y) * ph
+
+    def correct(self, u, G=None, rho0=None, t=0.0, omega=0.0):
+        """e = u + D y, y zero on the wall, with D^T [*eps] e = -e^{-j w t}(D^T G + rho0)
+        at the other nodes (u complex on the edges)."""
+        rhs = self.rhs(G, rho0) * np.exp(-1j * omega * t) - self.D.T @ (self.M @ u)
+        y = self.solve_nodal(rhs.real) + 1j * self.solve_nodal(rhs.imag)
+        return u + self.D @ y
 
     def gauss_residual(self, e_ns, G=None, rho0=None, t=0.0, omega=0.0):
         """max over the inner nodes of |D^T [*eps] e_ns - e^{-j w t} rhs| and max |rhs|."""

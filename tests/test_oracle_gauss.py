@@ -208,3 +208,45 @@ def test_structured_mesh_gives_the_seven_point_stencil(ora):
     x, _ = gauss.NsOracle(m, EPS0).solve(rho0=rho)
     assert np.isclose(x[c].real, -1e-12 / (6 * EPS0 * 0.5), rtol=1e-14)
     assert np.count_nonzero(x) == 1
+
+
+def test_gauss_correction_of_a_field_step_state(ora, jittered):
+    """The correction e = u + D y: Gauss' law exact for e, the curl of e that
+    of u, a pure gradient removed, a field that already obeys Gauss left
+    alone.  And the motivation (Quasi Helmholtz section): the plain Newmark
+    field step carries a gradient part along untouched by the curl-curl
+    stiffness, so a gradient in the initial velocity makes D^T [*eps] u grow
+    exactly linearly in time (20 source-free steps); the correction removes
+    it at every step."""
+    from oracle import field, gauss, qh
+    ns = gauss.NsOracle(jittered, EPS0)
+    rng = np.random.default_rng(21)
+    M, K, bnd = field.assemble(jittered, EPS0, 1.25663706212e-6)
+    inner_e = ~bnd
+    u = (rng.standard_normal(jittered.ne) + 1j * rng.standard_normal(jittered.ne)) * inner_e
+    G = rng.standard_normal(jittered.ne) * 1e-15
+    rho0 = rng.standard_normal(jittered.nv) * 1e-15
+    t, w = 2.1e-10, 2 * np.pi * 1.1e9
+    e = ns.correct(u, G, rho0, t, w)
+    r, scale = ns.gauss_residual(e, G, rho0, t, w)
+    assert r <= 1e-12 * scale
+    C = qh.curl_incidence(jittered)
+    assert np.abs(C @ (e - u)).max() <= 1e-12 * np.abs(C @ u).max()
+    phi = rng.standard_normal(jittered.nv) * ~ns.wall
+    assert np.abs(ns.correct(ns.D @ phi)).max() <= 1e-10 * np.abs(ns.D @ phi).max()
+    _, e_ns = ns.solve(G, rho0, t, w)
+    assert np.abs(ns.correct(e_ns, G, rho0, t, w) - e_ns).max() <= 1e-10 * np.abs(e_ns).max()
+    # null-space growth of the plain step, removed by the correction
+    F = field.FieldOracle(jittered, 1e-11, 0.0, EPS0, 1.25663706212e-6)
+    u0 = np.zeros(jittered.ne, complex)
+    v0 = (ns.D @ phi) * 1e9 * inner_e                      # a gradient velocity only
+    a0 = np.zeros_like(u0)
+    b0 = np.zeros(jittered.nf, complex)
+    uu, vv, aa, bb = u0, v0, a0, b0
+    I = ns.inner
+    g0 = (ns.D.T @ (ns.M @ v0))[I]
+    for n in range(1, 21):
+        uu, vv, aa, bb = F.step(n * 1e-11, uu, vv, aa, bb)
+        div = (ns.D.T @ (ns.M @ uu))[I]
+        assert np.abs(div - n * 1e-11 * g0).max() <= 1e-9 * np.abs(n * 1e-11 * g0).max()
+        assert np.abs(ns.D.T @ (ns.M @ ns.correct(uu)))[I].max() <= 1e-12 * np.abs(div).max()

@@ -213,6 +213,17 @@ def ns_solve_timing(E, torch, ctx, w, reps=3):
         torch.cuda.synchronize()
         ms.append(1e3 * (time.perf_counter() - t0))
     solve_ms = min(ms)
+    # Gauss-law correction of an edge envelope (the field step's mass: set up
+    # by the field-update timing with the same eps), two real solves
+    gc = torch.Generator(device="cuda").manual_seed(3)
+    u = torch.randn((ne, 2), dtype=torch.float64, device="cuda", generator=gc)
+    eo = torch.empty_like(u)
+    ctx.ns_correct(u, eo, None, rho0, 0.0, w.omega, tol=1e-10, max_iter=5000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, corr_it, _ = ctx.ns_correct(u, eo, None, rho0, 0.0, w.omega, tol=1e-10, max_iter=5000)
+    torch.cuda.synchronize()
+    corr_ms = 1e3 * (time.perf_counter() - t0)
     bytes_iter = 12 * nnz + 108 * nv
     per_iter = solve_ms / max(iters, 1)
     # the loop closed through the solve: the workload's electrons over a
@@ -239,6 +250,7 @@ def ns_solve_timing(E, torch, ctx, w, reps=3):
     return {"n_nodes": nv, "wall_nodes": n_wall, "nnz": nnz, "solve_ms": solve_ms, "cg_iterations": iters,
             "ms_per_iteration": per_iter, "bytes_per_iteration": bytes_iter,
             "GBs_per_iteration": bytes_iter / (per_iter * 1e-3) / 1e9, "rel_residual": res, "status": rc,
+            "correction_ms": corr_ms, "correction_cg_iterations": corr_it,
             "loop_ms_per_step": loop[1][0], "loop_cg_iterations_per_solve": loop[1][1],
             "loop10_ms_per_step": loop[10][0], "loop10_cg_iterations_per_solve": loop[10][1],
             "note": "side path, not in value; wall time of the whole solve (one host read of the iteration "

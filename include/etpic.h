@@ -464,6 +464,24 @@ int etpic_ns_run_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, 
                        double omega, double *G, const double *rho0, double *e_work, double tol, int max_iter,
                        uint32_t flags, int *iters_out, void *stream);
 
+/* Gauss-law correction of a field-step state (the property the split is
+ * for: Gauss' law exact for the fields, Discrete System).  For the complex
+ * edge envelope u (2*N_e float64, device; e.g. the u of etpic_field_step,
+ * zero on boundary edges) returns e_out = u + D y (2*N_e, device; may alias
+ * u), y complex on the nodes, zero on the wall, from
+ *     D^T [*eps] D y = -(e^{-j w t} (D^T G + rho0) + D^T [*eps] u)
+ * at the other nodes, so that D^T [*eps] e_out = -e^{-j w t}(D^T G + rho0):
+ * the curl of e_out is that of u (C D = 0) and its divergence is the
+ * deposited charge's.  [*eps] is the field step's mass, so etpic_field_setup
+ * and etpic_ns_setup must have been called with the same eps (EINVAL
+ * otherwise).  Two real CG solves (the real and imaginary parts), warm-started
+ * from the previous call's with ETPIC_NS_WARM; *iters_out = their sum,
+ * *resid_out = the larger residual.  Synchronises `stream`; ENOCONV leaves
+ * e_out untouched. */
+int etpic_ns_correct(etpic_ctx *ctx, const double *G, const double *rho0, double t, double omega, const double *u,
+                     double *e_out, double tol, int max_iter, uint32_t flags, int *iters_out, double *resid_out,
+                     void *stream);
+
 /* ---- Quasi-Helmholtz projectors (Quasi Helmholtz or Coulomb gauge section,
  * eqs. proj_es, proj_el, bfld_projector, efld_projected; App. A):
  *     P^Lambda_b = I - div^T (div div^T)^-1 div          (face DoFs),

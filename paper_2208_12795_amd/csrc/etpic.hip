@@ -2052,33 +2052,48 @@ __device__ __forceinline__ void all_sum4(int64_t nb, const double *__restrict__ 
     for (int k = 0; k < 4; ++k) tot[k] = res[k];
 }
 
-// b = -(D^T G + rho0) at node i off the wall, 0 on it.  (D^T G)_i sums +-G
-// over the edges at node i (+ where i is the head).
+// Right-hand side of a nodal solve: b = -(gs (D^T G + rho0) + D^T w_comp)
+// at the nodes off the wall, 0 on it; every pointer may be NULL.  w is a
+// complex edge vector of which component comp (0 re, 1 im) is taken.
+struct NsRhs {
+    const double *G, *rho0;
+    double gs;
+    const double2 *w;
+    int comp;
+};
+
+// (D^T G)_i sums +-G over the edges at node i (+ where i is the head).
 __device__ __forceinline__ double ns_rhs(int64_t i, const int32_t *__restrict__ ptr, const int32_t *__restrict__ code,
-                                         const double *__restrict__ G, const double *__restrict__ rho0,
-                                         const uint8_t *__restrict__ wall) {
+                                         const NsRhs &R, const uint8_t *__restrict__ wall) {
     if (wall[i]) return 0.0;
-    double div = rho0 ? rho0[i] : 0.0;
-    if (G)
-        for (int32_t k = ptr[i]; k < ptr[i + 1]; ++k) {
-            const int32_t c = code[k];
-            const double g = G[c >> 1];
+    double div = R.rho0 ? R.rho0[i] : 0.0;
+    double dw = 0.0;
+    for (int32_t k = ptr[i]; k < ptr[i + 1]; ++k) {
+        const int32_t c = code[k];
+        if (R.G) {
+            const double g = R.G[c >> 1];
             div += (c & 1) ? g : -g;
         }
-    return -div;
+        if (R.w) {
+            const double2 wv = R.w[c >> 1];
+            const double g = R.comp ? wv.y : wv.x;
+            dw += (c & 1) ? g : -g;
+        }
+    }
+    return -(R.gs * div + dw);
 }
 
 // Cold start: x = 0, r = b, z = Dinv b, p = q = 0; partials r.z, 0, |r|^2, |b|^2.
 __global__ void __launch_bounds__(kNsVecThreads) k_ns_start(int64_t nv, const int32_t *__restrict__ ptr,
-                                                     const int32_t *__restrict__ code, const double *__restrict__ G,
-                                                     const double *__restrict__ rho0, const uint8_t *__restrict__ wall,
+                                                     const int32_t *__restrict__ code, NsRhs R,
+                                                     const uint8_t *__restrict__ wall,
                                                      const double *__restrict__ dinv, double *__restrict__ x,
                                                      double *__restrict__ r, double *__restrict__ z,
                                                      double *__restrict__ p, double *__restrict__ q,
                                                      double *__restrict__ partial, double *__restrict__ sc) {
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (int64_t)gridDim.x * blockDim.x) {
-        const double b = ns_rhs(i, ptr, code, G, rho0, wall);
+        const double b = ns_rhs(i, ptr, code, R, wall);
         const double zi = dinv[i] * b;
         x[i] = 0.0;
         r[i] = b;
@@ -2099,9 +2114,7 @@ __global__ void __launch_bounds__(kNsVecThreads) k_ns_start(int64_t nv, const in
 // Warm start from the x left by the previous solve: r = b - S x, z = Dinv r,
 // p = q = 0; partials r.z, 0, |r|^2, |b|^2.  kRowLanes lanes per row.
 __global__ void __launch_bounds__(kNsThreads) k_ns_start_warm(NsCsr S, const int32_t *__restrict__ ptr,
-                                                          const int32_t *__restrict__ code,
-                                                          const double *__restrict__ G,
-                                                          const double *__restrict__ rho0,
+                                                          const int32_t *__restrict__ code, NsRhs R,
                                                           const uint8_t *__restrict__ wall,
                                                           const double *__restrict__ dinv,
                                                           const double *__restrict__ x, double *__restrict__ r,
@@ -2118,7 +2131,7 @@ __global__ void __launch_bounds__(kNsThreads) k_ns_start_warm(NsCsr S, const int
 #pragma unroll
         for (int off = kRowLanes / 2; off > 0; off >>= 1) sx += __shfl_xor(sx, off);
         if (sub == 0) {
-            const double b = ns_rhs(row, ptr, code, G, rho0, wall);
+            const double b = ns_rhs(row, ptr, code, R, wall);
             const double ri = b - sx;
             const double zi = dinv[row] * ri;
             r[row] = ri;
@@ -2231,6 +2244,17 @@ __global__ void __launch_bounds__(kBlock) k_ns_out(int64_t ne, int64_t nv, const
     }
 }
 
+// e_out = u + D (xr + j xi) on the edges (edge e from ev[2e] to ev[2e+1])
+__global__ void __launch_bounds__(kBlock) k_ns_combine(int64_t ne, const int32_t *__restrict__ ev,
+                                                       const double *__restrict__ xr, const double *__restrict__ xi,
+                                                       const double2 *__restrict__ u, double2 *__restrict__ e_out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ne) return;
+    const int32_t a = ev[2 * i], b = ev[2 * i + 1];
+    const double2 ui = u[i];
+    e_out[i] = make_double2(ui.x + xr[b] - xr[a], ui.y + xi[b] - xi[a]);
+}
+
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
@@ -2269,7 +2293,7 @@ struct NsState {
     int32_t *rowptr = nullptr, *col = nullptr, *ev = nullptr;
     double *S = nullptr, *dinv = nullptr;
     uint8_t *wall = nullptr;
-    double *vec = nullptr;      // 5 work vectors of nv: x, r, z, p, q
+    double *vec = nullptr;      // 7 vectors of nv: x, r, z, p, q, and the solutions (re, im) of the correction
     double *partial = nullptr;  // two sets of 4 per block (kNsBlocks blocks)
     double *sc = nullptr;       // 12 scalars of the iteration
     double *bzero = nullptr;    // 2*N_f zeros: the face envelope of a loop without external fields
@@ -3501,12 +3525,12 @@ int etpic_ns_setup(etpic_ctx *ctx, double eps) {
     HIP_TRY(hipMalloc(&N.S, sizeof(double) * S.nnz));
     HIP_TRY(hipMalloc(&N.dinv, sizeof(double) * nv));
     HIP_TRY(hipMalloc(&N.wall, sizeof(uint8_t) * nv));
-    HIP_TRY(hipMalloc(&N.vec, sizeof(double) * 5 * nv));
+    HIP_TRY(hipMalloc(&N.vec, sizeof(double) * 7 * nv));
     HIP_TRY(hipMalloc(&N.partial, sizeof(double) * 8 * kNsBlocks));
     HIP_TRY(hipMalloc(&N.sc, sizeof(double) * 12));
     HIP_TRY(hipMemset(N.sc, 0, sizeof(double) * 12));
     HIP_TRY(hipMalloc(&N.bzero, sizeof(double) * 2 * ctx->host.nf));
-    HIP_TRY(hipMemset(N.vec, 0, sizeof(double) * 5 * nv));
+    HIP_TRY(hipMemset(N.vec, 0, sizeof(double) * 7 * nv));
     HIP_TRY(hipMemset(N.bzero, 0, sizeof(double) * 2 * ctx->host.nf));
     HIP_TRY(hipMalloc(&N.ezero, sizeof(double) * 2 * ne));
     HIP_TRY(hipMemset(N.ezero, 0, sizeof(double) * 2 * ne));
@@ -3534,23 +3558,23 @@ namespace {
 
 // The CG of eq. ns_equation on `st` (synchronises it), from x = 0 or, warm,
 // from the x of the previous solve; outputs scaled by e^{-j w t} = c - j s.
-int ns_solve_impl(etpic_ctx *ctx, const double *G, const double *rho0, double c, double s, double2 *x_out,
-                  double2 *e_out, double *edc_out, const double *edc_add, double tol, int max_iter, bool warm,
-                  int *iters_out, double *resid_out, hipStream_t st) {
+int ns_solve_impl(etpic_ctx *ctx, const NsRhs &R, double *x, double c, double s, double2 *x_out, double2 *e_out,
+                  double *edc_out, const double *edc_add, double tol, int max_iter, bool warm, int *iters_out,
+                  double *resid_out, hipStream_t st) {
     const NsState &N = ctx->ns;
     const int64_t nv = N.nv;
     const unsigned gv = (unsigned)std::min<int64_t>((nv + kNsVecThreads - 1) / kNsVecThreads, kNsBlocks);
     const unsigned gr = (unsigned)std::min<int64_t>((nv * kRowLanes + kNsThreads - 1) / kNsThreads, kNsBlocks);
-    double *x = N.v(0), *r = N.v(1), *z = N.v(2), *p = N.v(3), *q = N.v(4);
+    double *r = N.v(1), *z = N.v(2), *p = N.v(3), *q = N.v(4);
     // partials: pa from the product (gr blocks), pb from the start and the update
     double *pa = N.partial, *pb = N.partial + 4 * kNsBlocks;
     int64_t nb = warm ? gr : gv;
     if (warm)
-        k_ns_start_warm<<<gr, kNsThreads, 0, st>>>(N.csr(), ctx->d_v2e_ptr, ctx->d_v2e_code, G, rho0, N.wall, N.dinv, x, r,
-                                               z, p, q, pb, N.sc);
+        k_ns_start_warm<<<gr, kNsThreads, 0, st>>>(N.csr(), ctx->d_v2e_ptr, ctx->d_v2e_code, R, N.wall, N.dinv, x, r,
+                                                   z, p, q, pb, N.sc);
     else
-        k_ns_start<<<gv, kNsVecThreads, 0, st>>>(nv, ctx->d_v2e_ptr, ctx->d_v2e_code, G, rho0, N.wall, N.dinv, x, r, z, p, q,
-                                          pb, N.sc);
+        k_ns_start<<<gv, kNsVecThreads, 0, st>>>(nv, ctx->d_v2e_ptr, ctx->d_v2e_code, R, N.wall, N.dinv, x, r, z, p, q,
+                                                 pb, N.sc);
     HIP_TRY(hipGetLastError());
     // Iterations are launched in batches; the device raises the done flag when
     // the residual is small enough and the rest of the batch returns at once.
@@ -3580,8 +3604,9 @@ int ns_solve_impl(etpic_ctx *ctx, const double *G, const double *rho0, double c,
     if (resid_out) *resid_out = rel;
     if (hs[10] == 0.0 || !std::isfinite(rel))
         return fail(ETPIC_ENOCONV, "ns CG: relative residual %.3e after %d iterations", rel, it);
-    k_ns_out<<<grid_for(std::max(N.ne, nv)), kBlock, 0, st>>>(N.ne, nv, N.ev, x, c, s, x_out, e_out, edc_out,
-                                                              edc_add);
+    if (x_out || e_out || edc_out)
+        k_ns_out<<<grid_for(std::max(N.ne, nv)), kBlock, 0, st>>>(N.ne, nv, N.ev, x, c, s, x_out, e_out, edc_out,
+                                                                  edc_add);
     HIP_TRY(hipGetLastError());
     return ETPIC_OK;
 }
@@ -3600,9 +3625,10 @@ int etpic_ns_solve(etpic_ctx *ctx, const double *G, const double *rho0, double t
         return fail(ETPIC_EINVAL, "bad tol / max_iter / time / omega");
     if (flags & ~(uint32_t)ETPIC_NS_WARM) return fail(ETPIC_EINVAL, "unknown flags 0x%x", flags);
     if (int r = set_device(ctx)) return r;
-    return ns_solve_impl(ctx, G, rho0, std::cos(omega * t), std::sin(omega * t), reinterpret_cast<double2 *>(x_out),
-                         reinterpret_cast<double2 *>(e_out), nullptr, nullptr, tol, max_iter,
-                         (flags & ETPIC_NS_WARM) != 0, iters_out, resid_out, static_cast<hipStream_t>(stream));
+    return ns_solve_impl(ctx, NsRhs{G, rho0, 1.0, nullptr, 0}, ctx->ns.v(0), std::cos(omega * t),
+                         std::sin(omega * t), reinterpret_cast<double2 *>(x_out), reinterpret_cast<double2 *>(e_out),
+                         nullptr, nullptr, tol, max_iter, (flags & ETPIC_NS_WARM) != 0, iters_out, resid_out,
+                         static_cast<hipStream_t>(stream));
 }
 
 int etpic_ns_run_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, const etpic_species *sp,
@@ -3633,8 +3659,8 @@ int etpic_ns_run_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, 
         const int n = std::min(steps_per_solve, nsteps - j);
         int it = 0;
         const bool warm = j > 0 || (flags & ETPIC_NS_WARM);
-        if (int r = ns_solve_impl(ctx, G, rho0, 1.0, 0.0, nullptr, nullptr, e_work, ext ? ext->e_dc : nullptr, tol,
-                                  max_iter, warm, &it, nullptr, st)) {
+        if (int r = ns_solve_impl(ctx, NsRhs{G, rho0, 1.0, nullptr, 0}, ctx->ns.v(0), 1.0, 0.0, nullptr, nullptr,
+                                  e_work, ext ? ext->e_dc : nullptr, tol, max_iter, warm, &it, nullptr, st)) {
             if (iters_out) *iters_out = total + it;
             return r;
         }
@@ -3646,6 +3672,50 @@ int etpic_ns_run_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, 
         if (r) return r;
     }
     if (iters_out) *iters_out = total;
+    return ETPIC_OK;
+}
+
+int etpic_ns_correct(etpic_ctx *ctx, const double *G, const double *rho0, double t, double omega, const double *u,
+                     double *e_out, double tol, int max_iter, uint32_t flags, int *iters_out, double *resid_out,
+                     void *stream) {
+    if (!ctx || !u || !e_out) return fail(ETPIC_EINVAL, "null argument");
+    if (!ctx->ns.ready) return fail(ETPIC_ESTATE, "etpic_ns_setup not called");
+    if (!ctx->field.ready) return fail(ETPIC_ESTATE, "etpic_field_setup not called");
+    if (std::fabs(ctx->field.eps - ctx->ns.eps) > 1e-15 * ctx->ns.eps)
+        return fail(ETPIC_EINVAL, "etpic_field_setup and etpic_ns_setup were given different eps");
+    if (!(tol > 0.0) || max_iter < 1 || !std::isfinite(t) || !std::isfinite(omega))
+        return fail(ETPIC_EINVAL, "bad tol / max_iter / time / omega");
+    if (flags & ~(uint32_t)ETPIC_NS_WARM) return fail(ETPIC_EINVAL, "unknown flags 0x%x", flags);
+    if (int r = set_device(ctx)) return r;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const FieldState &F = ctx->field;
+    NsState &N = ctx->ns;
+    double2 *mu = F.v(3);   // [*eps] u (the field step's right-hand-side vector, free between steps)
+    k_field_spmv<<<grid_for(F.ne * kRowLanes), kBlock, 0, st>>>(F.csr(), make_double2(1.0, 0.0), 0.0,
+                                                                reinterpret_cast<const double2 *>(u), mu);
+    HIP_TRY(hipGetLastError());
+    const double c = std::cos(omega * t), s = std::sin(omega * t);
+    const bool warm = (flags & ETPIC_NS_WARM) != 0;
+    int it_re = 0, it_im = 0;
+    double res_re = 0.0, res_im = 0.0;
+    // e^{-j w t} (D^T G + rho0) = (c - j s)(D^T G + rho0): real and imaginary parts solved apart
+    if (int r = ns_solve_impl(ctx, NsRhs{G, rho0, c, mu, 0}, N.v(5), 1.0, 0.0, nullptr, nullptr, nullptr, nullptr, tol,
+                              max_iter, warm, &it_re, &res_re, st)) {
+        if (iters_out) *iters_out = it_re;
+        if (resid_out) *resid_out = res_re;
+        return r;
+    }
+    if (int r = ns_solve_impl(ctx, NsRhs{G, rho0, -s, mu, 1}, N.v(6), 1.0, 0.0, nullptr, nullptr, nullptr, nullptr, tol,
+                              max_iter, warm, &it_im, &res_im, st)) {
+        if (iters_out) *iters_out = it_re + it_im;
+        if (resid_out) *resid_out = res_im;
+        return r;
+    }
+    if (iters_out) *iters_out = it_re + it_im;
+    if (resid_out) *resid_out = std::max(res_re, res_im);
+    k_ns_combine<<<grid_for(N.ne), kBlock, 0, st>>>(N.ne, N.ev, N.v(5), N.v(6), reinterpret_cast<const double2 *>(u),
+                                                    reinterpret_cast<double2 *>(e_out));
+    HIP_TRY(hipGetLastError());
     return ETPIC_OK;
 }
 

@@ -34,7 +34,7 @@ EXPORTS = (
     "etpic_field_setup", "etpic_field_nnz", "etpic_field_spmv", "etpic_field_step",
     "etpic_particles_locate", "etpic_particles_positions", "etpic_coarse_step", "etpic_run_steps",
     "etpic_sort_run_steps", "etpic_ds_history_bytes", "etpic_ds_steps", "etpic_ds_sort",
-    "etpic_ns_setup", "etpic_ns_info", "etpic_ns_solve", "etpic_ns_run_steps",
+    "etpic_ns_setup", "etpic_ns_info", "etpic_ns_solve", "etpic_ns_run_steps", "etpic_ns_correct",
     "etpic_qh_last_error", "etpic_qh_create", "etpic_qh_destroy", "etpic_qh_counts", "etpic_qh_project_b",
     "etpic_qh_project_e", "etpic_tree_cotree",
 )
@@ -118,6 +118,8 @@ def lib():
                                  C.POINTER(C.c_int), dp, vp]
     L.etpic_ns_run_steps.argtypes = [vp, vp, C.c_int, vp, vp, C.c_int64, C.c_int, C.c_int, C.c_double, C.c_double,
                                      vp, vp, vp, C.c_double, C.c_int, C.c_uint32, C.POINTER(C.c_int), vp]
+    L.etpic_ns_correct.argtypes = [vp, vp, vp, C.c_double, C.c_double, vp, vp, C.c_double, C.c_int, C.c_uint32,
+                                   C.POINTER(C.c_int), dp, vp]
     L.etpic_qh_last_error.restype = C.c_char_p
     L.etpic_qh_last_error.argtypes = []
     L.etpic_qh_create.argtypes = [C.POINTER(vp), C.c_int, C.c_int64, dp, C.c_int64, i32p, C.c_double]
@@ -554,6 +556,18 @@ class Context:
                                       C.byref(it), _stream(stream))
         _chk(rc)
         return it.value
+
+    def ns_correct(self, u, e_out, G=None, rho0=None, t=0.0, omega=0.0, tol=1e-12, max_iter=2000, warm=False,
+                   stream=None, raise_on_error=True):
+        """e_out = u + D y with Gauss' law exact for e_out (u, e_out float64
+        [N_e, 2] complex); returns (status, iterations, residual)."""
+        it, res = C.c_int(0), C.c_double(0.0)
+        rc = lib().etpic_ns_correct(self._h, _dptr(G), _dptr(rho0), float(t), float(omega), _dptr(u), _dptr(e_out),
+                                    float(tol), int(max_iter), NS_WARM if warm else 0, C.byref(it), C.byref(res),
+                                    _stream(stream))
+        if raise_on_error:
+            _chk(rc)
+        return rc, it.value, res.value
 
     def check(self, stream=None, raise_on_error=True):
         word = C.c_uint32(0)

@@ -369,3 +369,62 @@ def test_single_inner_node_closed_form(E, torch_cuda):
     assert np.allclose(eh[at_c], np.where(ed[at_c, 1] == c, xc, -xc), rtol=1e-14, atol=0)
     assert np.count_nonzero(eh[~at_c]) == 0
     ctx.close()
+
+
+def test_gauss_correction_matches_oracle_and_removes_null_space_growth(E, torch_cuda, ora):
+    """etpic_ns_correct against the oracle's correct() on a jittered mesh
+    (complex u with zero boundary edges, random G and rho0, a carrier
+    phase); then 20 GPU field steps from a gradient initial velocity: the
+    plain state's D^T [*eps] u grows linearly, the corrected one obeys
+    Gauss' law (here: no charge) to the solver tolerance, with its curl
+    unchanged."""
+    from oracle import field, gauss, qh
+    torch = torch_cuda
+    xyz, tv = synth.kuhn_mesh((5, 4, 6), (1.0, 0.9, 1.1), 0.15, np.random.default_rng(3))
+    mu0 = 1.25663706212e-6
+    dt = 1e-11
+    ctx = E.Context(0)
+    ctx.upload_mesh(xyz, tv)
+    ctx.field_setup(dt, 0.0, EPS0, mu0)
+    ctx.ns_setup(EPS0)
+    m = ora.OracleMesh(xyz, tv)
+    ns = gauss.NsOracle(m, EPS0)
+    _, _, bnd = field.assemble(m, EPS0, mu0)
+    rng = np.random.default_rng(8)
+    u = (rng.standard_normal(m.ne) + 1j * rng.standard_normal(m.ne)) * ~bnd
+    G = rng.standard_normal(m.ne) * 1e-15
+    rho0 = rng.standard_normal(m.nv) * 1e-15
+    t, w = 2.1e-10, 2 * np.pi * 1.1e9
+    tu = torch.from_numpy(np.ascontiguousarray(np.stack([u.real, u.imag], axis=1))).cuda()
+    eo = torch.zeros_like(tu)
+    _, it, res = ctx.ns_correct(tu, eo, torch.from_numpy(G).cuda(), torch.from_numpy(rho0).cuda(), t, w, tol=1e-14)
+    got = t2c(eo)
+    ref = ns.correct(u, G, rho0, t, w)
+    print(f"[ns] correction: {it} iterations, vs oracle {rel(got, ref):.2e}", flush=True)
+    assert rel(got, ref) <= 1e-10
+    r, scale = ns.gauss_residual(got, G, rho0, t, w)
+    assert r <= 1e-11 * scale
+    with pytest.raises(E.EtpicError):            # different eps in the two setups
+        ctx.ns_setup(2 * EPS0)
+        ctx.ns_correct(tu, eo)
+    ctx.ns_setup(EPS0)
+    # null-space growth of the plain step on the GPU, removed by the correction
+    C = qh.curl_incidence(m)
+    phi = rng.standard_normal(m.nv) * ~ns.wall
+    z = np.zeros(m.ne, complex)
+    st = [torch.from_numpy(np.ascontiguousarray(np.stack([x.real, x.imag], axis=1))).cuda()
+          for x in (z, (ns.D @ phi) * 1e9 * ~bnd, z)]
+    bf = torch.zeros((m.nf, 2), dtype=torch.float64, device="cuda")
+    I = ns.inner
+    g0 = np.abs((ns.D.T @ (ns.M @ ((ns.D @ phi) * 1e9 * ~bnd)))[I]).max()
+    for n in range(1, 21):
+        ctx.field_step(n * dt, st[0], st[1], st[2], bf, None, tol=1e-13)
+        ctx.ns_correct(st[0], eo, tol=1e-13, warm=n > 1)
+        uu, ee = t2c(st[0]), t2c(eo)
+        div_u = np.abs((ns.D.T @ (ns.M @ uu))[I]).max()
+        div_e = np.abs((ns.D.T @ (ns.M @ ee))[I]).max()
+        assert div_u >= 0.5 * n * dt * g0
+        assert div_e <= 1e-10 * div_u
+        assert np.abs(C @ (ee - uu)).max() <= 1e-13 * np.abs(ee - uu).max()   # a pure gradient was removed
+    print(f"[ns] after 20 steps: |D^T M u| {div_u:.3e}, corrected {div_e:.3e}", flush=True)
+    ctx.close()

@@ -62,3 +62,43 @@ def fit_frequency(sig, dt, w0, span=0.1, n=4001):
         if best is None or r < best[0]:
             best = (r, om, c)
     return best[1], best[2]
+
+
+def oracle_em_loop(ora, cp, nsteps, dt, shape, correct=True, record=None):
+    """The loop through the implicit field step: each step pushes the
+    particles in the current fields (e, b), takes the field step to the next
+    time with the source G'' from the second difference of the running path
+    integral, and (correct) replaces the new field's gradient part so that
+    Gauss' law holds exactly for the deposited charge.  omega = 0.  Returns
+    (states, signal, gauss): states[j] = (tet, lam, vel, G) after step j (for
+    j in record, all if None), signal[j] the mode amplitude of e used at step
+    j, gauss[j] = max |D^T [*eps] e + (D^T G + rho0)| / max |D^T G + rho0| at
+    the inner nodes after the field step j."""
+    from oracle import field, gauss
+    eps0, mu0 = 8.8541878128e-12, 1.25663706212e-6
+    m = ora.OracleMesh(cp.xyz, cp.tet_vert)
+    ns = gauss.NsOracle(m, eps0)
+    F = field.FieldOracle(m, dt, 0.0, eps0, mu0)
+    rho0 = m.charge(cp.tet, cp.lam, cp.q, cp.w) - m.charge(cp.tet0, cp.lam0, cp.q, cp.w)
+    t, l, v = cp.tet.copy(), cp.lam.copy(), cp.vel.copy()
+    G = np.zeros(m.ne)
+    G_prev = np.zeros(m.ne)
+    e = ns.correct(np.zeros(m.ne, complex), None, rho0)       # the static start: Gauss for rho0
+    u, vv, a = e.copy(), np.zeros(m.ne, complex), np.zeros(m.ne, complex)
+    b = np.zeros(m.nf, complex)
+    states, sig, gres = [], [], []
+    for j in range(nsteps):
+        sig.append(mode_amplitude(e.real, shape))
+        G_old = G.copy()
+        rc, _ = m.step(t, l, v, q=cp.q, m=cp.m, w=cp.w, step=j, dt=dt, omega=0.0, e_env=e, b_env=b, dG=G,
+                       nthreads=NTH)
+        assert rc == 0
+        gdd = (G - 2 * G_old + G_prev) / dt ** 2
+        G_prev = G_old
+        u, vv, a, b = F.step((j + 1) * dt, u, vv, a, b, gdd)
+        e = ns.correct(u, G, rho0) if correct else u
+        r, scale = ns.gauss_residual(e, G, rho0)
+        gres.append(r / scale)
+        if record is None or j in record:
+            states.append((t.copy(), l.copy(), v.copy(), G.copy()))
+    return states, np.array(sig), np.array(gres)

@@ -250,3 +250,20 @@ def test_gauss_correction_of_a_field_step_state(ora, jittered):
         div = (ns.D.T @ (ns.M @ uu))[I]
         assert np.abs(div - n * 1e-11 * g0).max() <= 1e-9 * np.abs(n * 1e-11 * g0).max()
         assert np.abs(ns.D.T @ (ns.M @ ns.correct(uu)))[I].max() <= 1e-12 * np.abs(div).max()
+
+
+def test_em_loop_with_gauss_correction(ora):
+    """The loop through the implicit field step (Newmark, source G'' from the
+    path integral's second difference, a step behind): corrected every step,
+    Gauss' law holds to rounding and the cold plasma oscillates at omega_p to
+    1 %; left plain, the lagged source breaks Gauss' law by order one."""
+    import plasma_util as P
+    cp = synth.cold_plasma(4, 50_000)
+    shape = P.mode_shape(cp, synth.mesh_edges(cp.tet_vert, cp.xyz.shape[0]))
+    dt = 0.1 / cp.omega_p
+    _, sig, gres = P.oracle_em_loop(ora, cp, 126, dt, shape, correct=True, record=[])
+    om, _ = P.fit_frequency(sig, dt, cp.omega_p)
+    assert abs(om / cp.omega_p - 1) < 0.01, om / cp.omega_p
+    assert gres.max() < 1e-12, gres.max()
+    _, _, gplain = P.oracle_em_loop(ora, cp, 40, dt, shape, correct=False, record=[])
+    assert gplain.max() > 1e-2, gplain.max()

@@ -428,3 +428,101 @@ def test_gauss_correction_matches_oracle_and_removes_null_space_growth(E, torch_
         assert np.abs(C @ (ee - uu)).max() <= 1e-13 * np.abs(ee - uu).max()   # a pure gradient was removed
     print(f"[ns] after 20 steps: |D^T M u| {div_u:.3e}, corrected {div_e:.3e}", flush=True)
     ctx.close()
+
+
+def gpu_em_loop(E, torch, cp, nsteps, dt, per_step=None, tol=1e-13):
+    """The plasma loop through the GPU field step and the Gauss correction
+    (omega = 0): push in (e, b), field step with G'' from the second
+    difference of G, correction of the new edge field."""
+    mu0 = 1.25663706212e-6
+    ctx = E.Context(0)
+    ctx.upload_mesh(cp.xyz, cp.tet_vert)
+    ctx.field_setup(dt, 0.0, EPS0, mu0)
+    ctx.ns_setup(EPS0)
+    sp = E.Species(cp.q, cp.m, cp.w)
+    parts = E.Particles.from_numpy(cp.tet, cp.lam, cp.vel, cp.ids)
+    rest = E.Particles.from_numpy(cp.tet0, cp.lam0, cp.vel, cp.ids)
+    rho0 = torch.zeros(ctx.n_vert, dtype=torch.float64, device="cuda")
+    rr = torch.zeros_like(rho0)
+    ctx.vertex_charge(parts, sp, rho0)
+    ctx.vertex_charge(rest, sp, rr)
+    rho0 -= rr
+    u = torch.zeros((ctx.n_edge, 2), dtype=torch.float64, device="cuda")
+    v, a, e = torch.zeros_like(u), torch.zeros_like(u), torch.zeros_like(u)
+    b = torch.zeros((ctx.n_face, 2), dtype=torch.float64, device="cuda")
+    ctx.ns_correct(u, e, None, rho0, tol=tol)
+    u.copy_(e)
+    G = torch.zeros(ctx.n_edge, dtype=torch.float64, device="cuda")
+    G_prev = torch.zeros_like(G)
+    fields = E.Fields(e, b)
+    for j in range(nsteps):
+        if per_step is not None:
+            per_step(j, "before", parts, G, e)
+        G_old = G.clone()
+        ctx.run_steps(parts, sp, fields, j, 1, dt, 0.0, G)
+        gdd = (G - 2 * G_old + G_prev) / dt ** 2
+        G_prev = G_old
+        ctx.field_step((j + 1) * dt, u, v, a, b, gdd, tol=tol)
+        ctx.ns_correct(u, e, G, rho0, tol=tol, warm=j > 0)
+        if per_step is not None:
+            per_step(j, "after", parts, G, e)
+    ctx.check()
+    ctx.close()
+
+
+def test_em_loop_matches_oracle(E, torch_cuda, ora):
+    """20 steps of the plasma loop through the field step and the correction
+    (4^3 x 6 mesh, 20k electrons) on the GPU against the oracle's loop:
+    positions, velocities and G every step to 1e-8 (the two CG solvers'
+    tolerance carried through the loop), and Gauss' law for the GPU's field
+    to the solver tolerance."""
+    import plasma_util as P
+    from oracle import gauss
+    torch = torch_cuda
+    cp = synth.cold_plasma(4, 20_000)
+    ed = synth.mesh_edges(cp.tet_vert, cp.xyz.shape[0])
+    dt = 0.1 / cp.omega_p
+    nsteps = 20
+    states, _, _ = P.oracle_em_loop(ora, cp, nsteps, dt, P.mode_shape(cp, ed), correct=True)
+    m = ora.OracleMesh(cp.xyz, cp.tet_vert)
+    ns = gauss.NsOracle(m, EPS0)
+    rho0 = m.charge(cp.tet, cp.lam, cp.q, cp.w) - m.charge(cp.tet0, cp.lam0, cp.q, cp.w)
+    worst = {}
+    prev = [(cp.tet, cp.lam, cp.vel)]
+
+    def check(j, when, parts, G, e):
+        if when != "after":
+            return
+        tg, lg, vg, _ = parts.to_numpy()
+        to, lo, vo, Go = states[j]
+        Gg = G.cpu().numpy()
+        err = step_errors(cp.xyz, cp.tet_vert, prev[0], (tg, lg, vg), (to, lo, vo), Gg, Go)
+        assert err["tet_mismatch"] <= 2, (j, err)
+        assert_within(err, 1e-8, f"em loop step {j}")
+        r, scale = ns.gauss_residual(t2c(e), Gg, rho0)
+        assert r <= 1e-10 * scale, (j, r / scale)
+        for k, val in err.items():
+            worst[k] = max(worst.get(k, 0.0), val)
+        prev[0] = (tg, lg, vg)
+
+    gpu_em_loop(E, torch, cp, nsteps, dt, per_step=check)
+    print(f"[ns] em loop: worst {worst}", flush=True)
+
+
+def test_em_loop_plasma_frequency_bench_mesh(E, torch_cuda):
+    """The same loop on the 40^3 x 6 mesh with 2e6 electrons, two periods:
+    omega_p to 1 %, the mode amplitude to 2 %."""
+    import plasma_util as P
+    torch = torch_cuda
+    cp = synth.cold_plasma(40, 2_000_000)
+    shape = P.mode_shape(cp, synth.mesh_edges(cp.tet_vert, cp.xyz.shape[0]))
+    dt = 0.1 / cp.omega_p
+    sig = []
+    gpu_em_loop(E, torch, cp, 126, dt, tol=1e-10,
+                per_step=lambda j, when, p, G, e: sig.append(P.mode_amplitude(e[:, 0].cpu().numpy(), shape))
+                if when == "before" else None)
+    om, _ = P.fit_frequency(np.array(sig), dt, cp.omega_p)
+    phi0 = cp.density * cp.q * cp.a / EPS0
+    print(f"[ns] em loop 40^3: omega/omega_p {om / cp.omega_p:.5f}, amplitude {sig[0] / phi0:.5f}", flush=True)
+    assert abs(om / cp.omega_p - 1) < 0.01
+    assert abs(sig[0] / phi0 - 1) < 0.02

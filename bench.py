@@ -239,6 +239,22 @@ def ns_solve_timing(E, torch, ctx, w, reps=3):
     sp = E.Species(w.q, w.m, w.w)
     ctx.ns_run_steps(parts, sp, 0, 1, w.dt, w.omega, G, edc, ext=fields, tol=1e-10)
     torch.cuda.synchronize()
+    # the electromagnetic loop: particle step, field step, Gauss correction
+    # (the field state of the field-update timing's setup: dt and omega of the
+    # workload), 5 steps from rest
+    uu = torch.zeros((ne, 2), dtype=torch.float64, device="cuda")
+    vv, aa, ee = torch.zeros_like(uu), torch.zeros_like(uu), torch.zeros_like(uu)
+    bb = torch.zeros((ctx.n_face, 2), dtype=torch.float64, device="cuda")
+    GG = torch.zeros(ne, dtype=torch.float64, device="cuda")
+    HH = torch.zeros(2 * ne, dtype=torch.float64, device="cuda")
+    em_parts = parts.clone()
+    ctx.em_steps(em_parts, sp, 0, 1, uu, vv, aa, bb, ee, GG, HH, tol=1e-10, max_iter=5000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    em_it = ctx.em_steps(em_parts, sp, 1, 5, uu, vv, aa, bb, ee, GG, HH, tol=1e-10, max_iter=5000, warm=True)
+    torch.cuda.synchronize()
+    em_ms = 1e3 * (time.perf_counter() - t0) / 5
+    del em_parts
     loop = {}
     for per in (1, 10):
         t0 = time.perf_counter()
@@ -251,12 +267,14 @@ def ns_solve_timing(E, torch, ctx, w, reps=3):
             "ms_per_iteration": per_iter, "bytes_per_iteration": bytes_iter,
             "GBs_per_iteration": bytes_iter / (per_iter * 1e-3) / 1e9, "rel_residual": res, "status": rc,
             "correction_ms": corr_ms, "correction_cg_iterations": corr_it,
+            "em_loop_ms_per_step": em_ms, "em_loop_iterations_per_step": em_it / 5,
             "loop_ms_per_step": loop[1][0], "loop_cg_iterations_per_solve": loop[1][1],
             "loop10_ms_per_step": loop[10][0], "loop10_cg_iterations_per_solve": loop[10][1],
             "note": "side path, not in value; wall time of the whole solve (one host read of the iteration "
                     "scalars per 10 iterations included), best of %d; loop: 20 particle steps of all %d "
                     "electrons (sorted by tet once) with a warm-started solve before every step (loop) or "
-                    "every 10th (loop10), mean per step" % (reps, w.tet.shape[0])}
+                    "every 10th (loop10), mean per step; em_loop: particle step, implicit field step and "
+                    "Gauss correction per step, mean of 5" % (reps, w.tet.shape[0])}
 
 
 def qh_projector_timing(E, torch, w, reps=3):

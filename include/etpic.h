@@ -482,6 +482,27 @@ int etpic_ns_correct(etpic_ctx *ctx, const double *G, const double *rho0, double
                      double *e_out, double tol, int max_iter, uint32_t flags, int *iters_out, double *resid_out,
                      void *stream);
 
+/* The electromagnetic loop with Gauss' law exact for the fields (the loop
+ * field -> particles -> G -> field of the split, with the implicit field
+ * step for the solenoidal part and etpic_ns_correct for the rest).  Uses the
+ * dt and omega of etpic_field_setup.  For each of nsteps steps, t = (step0 +
+ * j) dt: one particle step (as etpic_run_steps) in the fields {e, b} at t,
+ * its path integral added to G; the field step (etpic_field_step) to t + dt
+ * with the source g'' = (G - 2 G_hist[0..N_e) + G_hist[N_e..2N_e)) / dt^2,
+ * the second difference of G one step behind; G_hist shifted (G one and two
+ * steps back); e = the Gauss correction of u at t + dt with G and rho0.
+ * State (device, caller-owned, in place): u, v, a, e 2*N_e float64 complex
+ * (e must hold the field of step step0 on entry, e.g. etpic_ns_correct of
+ * u), b 2*N_f complex, G N_e float64 (the running path integral), G_hist
+ * 2*N_e float64 (zero for a start from rest), rho0 N_n float64 or NULL (the
+ * charge when G was zero).  One species per call.  flags: ETPIC_STEP_* of
+ * the particle steps, ETPIC_NS_WARM for the first correction.  *iters_out:
+ * COCG and CG iterations summed.  Synchronises `stream` several times per
+ * step; ENOCONV stops the loop at the solve that failed. */
+int etpic_em_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, const etpic_species *sp, int64_t step0,
+                   int nsteps, double *u, double *v, double *a, double *b, double *e, double *G, double *G_hist,
+                   const double *rho0, double tol, int max_iter, uint32_t flags, int *iters_out, void *stream);
+
 /* ---- Quasi-Helmholtz projectors (Quasi Helmholtz or Coulomb gauge section,
  * eqs. proj_es, proj_el, bfld_projector, efld_projected; App. A):
  *     P^Lambda_b = I - div^T (div div^T)^-1 div          (face DoFs),

@@ -2255,6 +2255,26 @@ __global__ void __launch_bounds__(kBlock) k_ns_combine(int64_t ne, const int32_t
     e_out[i] = make_double2(ui.x + xr[b] - xr[a], ui.y + xi[b] - xi[a]);
 }
 
+// Source of the field step from the running path integral: with h1, h2 the
+// values of G one and two steps back, gdd = (G - 2 h1 + h2) / dt^2 (written
+// into gdd, which may be h2)
+__global__ void __launch_bounds__(kBlock) k_em_gdd(int64_t ne, const double *__restrict__ G,
+                                                   const double *__restrict__ h1, const double *h2, double *gdd,
+                                                   double inv_dt2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ne) gdd[i] = ((G[i] - 2.0 * h1[i]) + h2[i]) * inv_dt2;
+}
+
+// history shift after a field step: h2 = h1, h1 = G
+__global__ void __launch_bounds__(kBlock) k_em_shift(int64_t ne, const double *__restrict__ G, double *__restrict__ h1,
+                                                     double *__restrict__ h2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ne) {
+        h2[i] = h1[i];
+        h1[i] = G[i];
+    }
+}
+
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
@@ -3716,6 +3736,55 @@ int etpic_ns_correct(etpic_ctx *ctx, const double *G, const double *rho0, double
     k_ns_combine<<<grid_for(N.ne), kBlock, 0, st>>>(N.ne, N.ev, N.v(5), N.v(6), reinterpret_cast<const double2 *>(u),
                                                     reinterpret_cast<double2 *>(e_out));
     HIP_TRY(hipGetLastError());
+    return ETPIC_OK;
+}
+
+int etpic_em_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, const etpic_species *sp, int64_t step0,
+                   int nsteps, double *u, double *v, double *a, double *b, double *e, double *G, double *G_hist,
+                   const double *rho0, double tol, int max_iter, uint32_t flags, int *iters_out, void *stream) {
+    if (!ctx || !u || !v || !a || !b || !e || !G || !G_hist) return fail(ETPIC_EINVAL, "null argument");
+    if (!ctx->field.ready) return fail(ETPIC_ESTATE, "etpic_field_setup not called");
+    if (!ctx->ns.ready) return fail(ETPIC_ESTATE, "etpic_ns_setup not called");
+    if (nsteps < 0) return fail(ETPIC_EINVAL, "negative step count");
+    if (e == u || G == G_hist || G_hist == u || G_hist == e) return fail(ETPIC_EINVAL, "aliased state arrays");
+    const double dt = ctx->field.dt, omega = ctx->field.omega;
+    const etpic_fields f{e, nullptr, b, nullptr};
+    if (int r = check_step_args(ctx, sp, &f, dt, omega)) return r;
+    if (int r = check_particles(ctx, p)) return r;
+    if (precision != ETPIC_FP64 && precision != ETPIC_MIXED) return fail(ETPIC_EINVAL, "bad precision %d", precision);
+    if (nsteps == 0) return ETPIC_OK;
+    if (int r = set_device(ctx)) return r;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t ne = ctx->field.ne;
+    double *h1 = G_hist, *h2 = G_hist + ne;
+    const uint32_t sf = flags & ~(uint32_t)ETPIC_NS_WARM;
+    int total = 0;
+    for (int j = 0; j < nsteps; ++j) {
+        const double t = (double)(step0 + j) * dt, t_next = (double)(step0 + j + 1) * dt;
+        if (p->n > 0) {
+            const StepPlan plan{{&f, nullptr, nullptr}, {1.0, 0.0, 0.0}, t};
+            const int r = precision == ETPIC_FP64 ? ctx->run_steps<double>(p, sp, &plan, 1, dt, omega, G, nullptr, sf, stream)
+                                                  : ctx->run_steps<float>(p, sp, &plan, 1, dt, omega, G, nullptr, sf, stream);
+            if (r) return r;
+        }
+        k_em_gdd<<<grid_for(ne), kBlock, 0, st>>>(ne, G, h1, h2, h2, 1.0 / (dt * dt));
+        HIP_TRY(hipGetLastError());
+        int it = 0;
+        if (int r = etpic_field_step(ctx, t_next, u, v, a, b, h2, tol, max_iter, &it, nullptr, stream)) {
+            if (iters_out) *iters_out = total + it;
+            return r;
+        }
+        total += it;
+        k_em_shift<<<grid_for(ne), kBlock, 0, st>>>(ne, G, h1, h2);
+        HIP_TRY(hipGetLastError());
+        const uint32_t cf = (j > 0 || (flags & ETPIC_NS_WARM)) ? (uint32_t)ETPIC_NS_WARM : 0u;
+        if (int r = etpic_ns_correct(ctx, G, rho0, t_next, omega, u, e, tol, max_iter, cf, &it, nullptr, stream)) {
+            if (iters_out) *iters_out = total + it;
+            return r;
+        }
+        total += it;
+    }
+    if (iters_out) *iters_out = total;
     return ETPIC_OK;
 }
 

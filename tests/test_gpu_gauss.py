@@ -430,10 +430,10 @@ def test_gauss_correction_matches_oracle_and_removes_null_space_growth(E, torch_
     ctx.close()
 
 
-def gpu_em_loop(E, torch, cp, nsteps, dt, per_step=None, tol=1e-13):
-    """The plasma loop through the GPU field step and the Gauss correction
-    (omega = 0): push in (e, b), field step with G'' from the second
-    difference of G, correction of the new edge field."""
+def gpu_em_loop(E, torch, cp, nsteps, dt, per_step=None, tol=1e-13, per_call=1):
+    """The plasma loop through etpic_em_steps (omega = 0): push in (e, b),
+    field step with G'' from the second difference of G, correction of the
+    new edge field; per_call steps per call."""
     mu0 = 1.25663706212e-6
     ctx = E.Context(0)
     ctx.upload_mesh(cp.xyz, cp.tet_vert)
@@ -450,24 +450,20 @@ def gpu_em_loop(E, torch, cp, nsteps, dt, per_step=None, tol=1e-13):
     u = torch.zeros((ctx.n_edge, 2), dtype=torch.float64, device="cuda")
     v, a, e = torch.zeros_like(u), torch.zeros_like(u), torch.zeros_like(u)
     b = torch.zeros((ctx.n_face, 2), dtype=torch.float64, device="cuda")
-    ctx.ns_correct(u, e, None, rho0, tol=tol)
+    ctx.ns_correct(u, e, None, rho0, tol=tol)          # the static start: Gauss' law for rho0
     u.copy_(e)
     G = torch.zeros(ctx.n_edge, dtype=torch.float64, device="cuda")
-    G_prev = torch.zeros_like(G)
-    fields = E.Fields(e, b)
-    for j in range(nsteps):
+    H = torch.zeros(2 * ctx.n_edge, dtype=torch.float64, device="cuda")
+    for j in range(0, nsteps, per_call):
         if per_step is not None:
             per_step(j, "before", parts, G, e)
-        G_old = G.clone()
-        ctx.run_steps(parts, sp, fields, j, 1, dt, 0.0, G)
-        gdd = (G - 2 * G_old + G_prev) / dt ** 2
-        G_prev = G_old
-        ctx.field_step((j + 1) * dt, u, v, a, b, gdd, tol=tol)
-        ctx.ns_correct(u, e, G, rho0, tol=tol, warm=j > 0)
+        ctx.em_steps(parts, sp, j, per_call, u, v, a, b, e, G, H, rho0=rho0, tol=tol, warm=j > 0)
         if per_step is not None:
-            per_step(j, "after", parts, G, e)
+            per_step(j + per_call - 1, "after", parts, G, e)
     ctx.check()
+    out = (parts.to_numpy()[:3], G.cpu().numpy(), t2c(e))
     ctx.close()
+    return out
 
 
 def test_em_loop_matches_oracle(E, torch_cuda, ora):
@@ -507,6 +503,20 @@ def test_em_loop_matches_oracle(E, torch_cuda, ora):
 
     gpu_em_loop(E, torch, cp, nsteps, dt, per_step=check)
     print(f"[ns] em loop: worst {worst}", flush=True)
+
+
+def test_em_steps_one_call_equals_single_calls(E, torch_cuda):
+    """12 steps in one etpic_em_steps call against 12 calls of one step
+    (particle atomics sum in no fixed order, so to rounding)."""
+    torch = torch_cuda
+    cp = synth.cold_plasma(6, 50_000)
+    dt = 0.1 / cp.omega_p
+    (sa, ga, ea) = gpu_em_loop(E, torch, cp, 12, dt, per_call=12)
+    (sb, gb, eb) = gpu_em_loop(E, torch, cp, 12, dt, per_call=1)
+    assert np.array_equal(sa[0], sb[0])
+    assert np.abs(sa[2] - sb[2]).max() <= 1e-11 * np.abs(sa[2]).max()
+    assert np.abs(ga - gb).max() <= 1e-12 * np.abs(ga).max()
+    assert np.abs(ea - eb).max() <= 1e-11 * np.abs(ea).max()
 
 
 def test_em_loop_plasma_frequency_bench_mesh(E, torch_cuda):

@@ -255,6 +255,20 @@ def ns_solve_timing(E, torch, ctx, w, reps=3):
     torch.cuda.synchronize()
     em_ms = 1e3 * (time.perf_counter() - t0) / 5
     del em_parts
+    # the same loop in the form of the split: field step on the solenoidal
+    # part (source projected, one real solve) plus the field of eq.
+    # ns_equation (one real solve)
+    for t_ in (uu, vv, aa, ee, bb, GG, HH):
+        t_.zero_()
+    em_parts = parts.clone()
+    ctx.em_steps(em_parts, sp, 0, 1, uu, vv, aa, bb, ee, GG, HH, tol=1e-10, max_iter=5000, split=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    split_it = ctx.em_steps(em_parts, sp, 1, 5, uu, vv, aa, bb, ee, GG, HH, tol=1e-10, max_iter=5000, warm=True,
+                            split=True)
+    torch.cuda.synchronize()
+    split_ms = 1e3 * (time.perf_counter() - t0) / 5
+    del em_parts
     loop = {}
     for per in (1, 10):
         t0 = time.perf_counter()
@@ -268,13 +282,15 @@ def ns_solve_timing(E, torch, ctx, w, reps=3):
             "GBs_per_iteration": bytes_iter / (per_iter * 1e-3) / 1e9, "rel_residual": res, "status": rc,
             "correction_ms": corr_ms, "correction_cg_iterations": corr_it,
             "em_loop_ms_per_step": em_ms, "em_loop_iterations_per_step": em_it / 5,
+            "split_loop_ms_per_step": split_ms, "split_loop_iterations_per_step": split_it / 5,
             "loop_ms_per_step": loop[1][0], "loop_cg_iterations_per_solve": loop[1][1],
             "loop10_ms_per_step": loop[10][0], "loop10_cg_iterations_per_solve": loop[10][1],
             "note": "side path, not in value; wall time of the whole solve (one host read of the iteration "
                     "scalars per 10 iterations included), best of %d; loop: 20 particle steps of all %d "
                     "electrons (sorted by tet once) with a warm-started solve before every step (loop) or "
                     "every 10th (loop10), mean per step; em_loop: particle step, implicit field step and "
-                    "Gauss correction per step, mean of 5" % (reps, w.tet.shape[0])}
+                    "Gauss correction per step, mean of 5; split_loop: the same with the field step on the "
+                    "solenoidal part (projected source) plus the Gauss-law field" % (reps, w.tet.shape[0])}
 
 
 def qh_projector_timing(E, torch, w, reps=3):

@@ -371,8 +371,12 @@ int etpic_backward(etpic_ctx *ctx, int64_t n, const etpic_species *sp, const etp
  * sparse matrix-vector product.  Boundary edges are perfect-conductor
  * (tangential field zero).  The face envelope follows the envelope Faraday law
  * (j w + d/dt) b = -C e (C the face-edge incidence, (C e)_f = e_ab + e_bc - e_ac
- * for face (a<b<c)) with the trapezoidal rule.  This simplified update stands
- * in for the paper's quasi-Helmholtz solver, which is not built. */
+ * for face (a<b<c)) with the trapezoidal rule.  Run on a state without
+ * gradient part (D^T [*eps] u = 0 at the inner nodes) and driven by the
+ * source of etpic_sol_source, the same step is the solenoidal system of the
+ * quasi-Helmholtz split (etpic_em_steps with ETPIC_EM_SPLIT); driven by the
+ * plain source it carries a gradient part that only etpic_ns_correct makes
+ * obey Gauss' law. */
 
 /* Assemble M, K (host), the preconditioner and the device work vectors for
  * field step dt, carrier w, permittivity eps, permeability mu (allocates). */
@@ -482,6 +486,33 @@ int etpic_ns_correct(etpic_ctx *ctx, const double *G, const double *rho0, double
                      double *e_out, double tol, int max_iter, uint32_t flags, int *iters_out, double *resid_out,
                      void *stream);
 
+/* Source of the solenoidal system of the split (eq. sol_disc; the projector
+ * P^Lambda_e taken orthogonal in the [*eps] inner product, whose range is
+ * that of the cotree unknowns' fields, and its transpose applied to the
+ * source of the field step):
+ *     gs = gdd - [*eps] D y,  D^T [*eps] D y = D^T gdd at the inner nodes,
+ * y zero on the wall, so that D^T gs = 0 at the inner nodes and the field
+ * step driven by gs keeps a state without gradient part free of one (the
+ * curl-curl stiffness annihilates gradients).  gdd, gs_out: N_e float64
+ * (device; gs_out may be gdd); on edges of boundary faces gs = gdd.  Needs
+ * etpic_field_setup and etpic_ns_setup with the same eps (ESTATE / EINVAL);
+ * uses the field step's work vectors.  One real CG solve, stopping and
+ * reporting as etpic_ns_solve; flags: 0 or ETPIC_NS_WARM (start from this
+ * function's previous solution).  Synchronises `stream`; ENOCONV leaves
+ * gs_out untouched. */
+int etpic_sol_source(etpic_ctx *ctx, const double *gdd, double *gs_out, double tol, int max_iter, uint32_t flags,
+                     int *iters_out, double *resid_out, void *stream);
+
+/* flag of etpic_em_steps */
+enum etpic_em_flags {
+    /* the loop in the form of the split: the field step takes the source of
+     * etpic_sol_source (u, v, a then stay free of a gradient part; they must
+     * start so, e.g. zero, or etpic_ns_correct's e minus its gradient) and
+     * e = u + the field of eq. ns_equation from G and rho0 (etpic_ns_solve);
+     * one real solve each, as many as the correction takes */
+    ETPIC_EM_SPLIT = 128u
+};
+
 /* The electromagnetic loop with Gauss' law exact for the fields (the loop
  * field -> particles -> G -> field of the split, with the implicit field
  * step for the solenoidal part and etpic_ns_correct for the rest).  Uses the
@@ -496,7 +527,8 @@ int etpic_ns_correct(etpic_ctx *ctx, const double *G, const double *rho0, double
  * u), b 2*N_f complex, G N_e float64 (the running path integral), G_hist
  * 2*N_e float64 (zero for a start from rest), rho0 N_n float64 or NULL (the
  * charge when G was zero).  One species per call.  flags: ETPIC_STEP_* of
- * the particle steps, ETPIC_NS_WARM for the first correction.  *iters_out:
+ * the particle steps, ETPIC_NS_WARM for the first correction (or the first
+ * solves of the split form), ETPIC_EM_SPLIT for the split form.  *iters_out:
  * COCG and CG iterations summed.  Synchronises `stream` several times per
  * step; ENOCONV stops the loop at the solve that failed. */
 int etpic_em_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, const etpic_species *sp, int64_t step0,

@@ -25,6 +25,13 @@ Because the operator is real, x = e^{-j w t} y with y real.
 `correct` applies the same operator to a given edge field u: it adds the
 gradient D y that makes u obey Gauss' law exactly, which leaves its curl
 (and so the face field) unchanged.
+
+`solenoidal_part` and `solenoidal_source` are the projector of the split in
+the [*eps] inner product (the energy-orthogonal reading of P^Lambda_e and its
+transpose): P u = u - D y with D^T [*eps] D y = D^T [*eps] u, and
+P^T g = g - [*eps] D y with D^T [*eps] D y = D^T g, both at the inner nodes.
+The solenoidal system is the field step with its state in the range of P and
+its source replaced by P^T g.
 """
 from __future__ import annotations
 
@@ -63,8 +70,9 @@ class NsOracle:
 
     def __init__(self, mesh, eps):
         self.mesh, self.eps = mesh, eps
-        M, _, _ = field.assemble(mesh, eps, 1.0)
+        M, _, bnd = field.assemble(mesh, eps, 1.0)
         self.M = M
+        self.bnd = bnd                                      # edges of boundary faces
         self.D = incidence(mesh)
         self.S = (self.D.T @ M @ self.D).tocsr()           # D^T [*eps] D on every node
         self.wall = wall_nodes(mesh)
@@ -106,3 +114,23 @@ class NsOracle:
         lhs = self.D.T @ (self.M @ e_ns)
         I = self.inner
         return np.abs(lhs[I] - r[I]).max(initial=0.0), np.abs(r[I]).max(initial=0.0)
+
+    def solenoidal_part(self, u):
+        """P u = u - D y, y zero on the wall, D^T [*eps] D y = D^T [*eps] u at the
+        other nodes: D^T [*eps] P u = 0 there and the curl is that of u."""
+        rhs = self.D.T @ (self.M @ u)
+        if np.iscomplexobj(rhs):
+            y = self.solve_nodal(rhs.real) + 1j * self.solve_nodal(rhs.imag)
+        else:
+            y = self.solve_nodal(rhs)
+        return u - self.D @ y
+
+    def solenoidal_source(self, g):
+        """P^T g = g - [*eps] D y, y zero on the wall, D^T [*eps] D y = D^T g at
+        the other nodes (g real, on the edges): D^T P^T g = 0 there.  On the
+        edges of boundary faces, where the field step takes no source, g is
+        kept."""
+        g = np.asarray(g, dtype=np.float64)
+        gs = g - self.M @ (self.D @ self.solve_nodal(self.D.T @ g))
+        gs[self.bnd] = g[self.bnd]
+        return gs

@@ -2275,6 +2275,23 @@ __global__ void __launch_bounds__(kBlock) k_em_shift(int64_t ne, const double *_
     }
 }
 
+// Solenoidal source: gs = gdd + Re m, m = [*eps] D y with D^T [*eps] D y =
+// -D^T gdd at the inner nodes (gs may be gdd)
+__global__ void __launch_bounds__(kBlock) k_sol_add(int64_t ne, const double *gdd, const double2 *__restrict__ m,
+                                                    double *gs) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ne) gs[i] = gdd[i] + m[i].x;
+}
+
+// e += u: the solenoidal and non-solenoidal halves of the field summed
+__global__ void __launch_bounds__(kBlock) k_em_add(int64_t ne, const double2 *__restrict__ u, double2 *__restrict__ e) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ne) {
+        const double2 a = u[i], b = e[i];
+        e[i] = make_double2(a.x + b.x, a.y + b.y);
+    }
+}
+
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
@@ -2313,7 +2330,8 @@ struct NsState {
     int32_t *rowptr = nullptr, *col = nullptr, *ev = nullptr;
     double *S = nullptr, *dinv = nullptr;
     uint8_t *wall = nullptr;
-    double *vec = nullptr;      // 7 vectors of nv: x, r, z, p, q, and the solutions (re, im) of the correction
+    double *vec = nullptr;      // 8 vectors of nv: x, r, z, p, q, the solutions (re, im) of the correction and
+                                // that of the source projection
     double *partial = nullptr;  // two sets of 4 per block (kNsBlocks blocks)
     double *sc = nullptr;       // 12 scalars of the iteration
     double *bzero = nullptr;    // 2*N_f zeros: the face envelope of a loop without external fields
@@ -3545,12 +3563,12 @@ int etpic_ns_setup(etpic_ctx *ctx, double eps) {
     HIP_TRY(hipMalloc(&N.S, sizeof(double) * S.nnz));
     HIP_TRY(hipMalloc(&N.dinv, sizeof(double) * nv));
     HIP_TRY(hipMalloc(&N.wall, sizeof(uint8_t) * nv));
-    HIP_TRY(hipMalloc(&N.vec, sizeof(double) * 7 * nv));
+    HIP_TRY(hipMalloc(&N.vec, sizeof(double) * 8 * nv));
     HIP_TRY(hipMalloc(&N.partial, sizeof(double) * 8 * kNsBlocks));
     HIP_TRY(hipMalloc(&N.sc, sizeof(double) * 12));
     HIP_TRY(hipMemset(N.sc, 0, sizeof(double) * 12));
     HIP_TRY(hipMalloc(&N.bzero, sizeof(double) * 2 * ctx->host.nf));
-    HIP_TRY(hipMemset(N.vec, 0, sizeof(double) * 7 * nv));
+    HIP_TRY(hipMemset(N.vec, 0, sizeof(double) * 8 * nv));
     HIP_TRY(hipMemset(N.bzero, 0, sizeof(double) * 2 * ctx->host.nf));
     HIP_TRY(hipMalloc(&N.ezero, sizeof(double) * 2 * ne));
     HIP_TRY(hipMemset(N.ezero, 0, sizeof(double) * 2 * ne));
@@ -3631,6 +3649,33 @@ int ns_solve_impl(etpic_ctx *ctx, const NsRhs &R, double *x, double c, double s,
     return ETPIC_OK;
 }
 
+// The field step's source with its gradient part removed in the [*eps]
+// inner product: gs = gdd - [*eps] D (D^T [*eps] D)^-1 D^T gdd, the inverse
+// taken at the inner nodes (wall grounded).  On boundary edges D y = 0 and
+// the field step's mass row is the identity, so gs = gdd there.  Work
+// vectors: the field step's F.v(3), F.v(4); warm start from N.v(7).
+int sol_source_impl(etpic_ctx *ctx, const double *gdd, double *gs, double tol, int max_iter, bool warm,
+                    int *iters_out, double *resid_out, hipStream_t st) {
+    const FieldState &F = ctx->field;
+    double2 *dy = F.v(3), *m = F.v(4);
+    if (int r = ns_solve_impl(ctx, NsRhs{gdd, nullptr, 1.0, nullptr, 0}, ctx->ns.v(7), 1.0, 0.0, nullptr, dy, nullptr,
+                              nullptr, tol, max_iter, warm, iters_out, resid_out, st))
+        return r;
+    k_field_spmv<<<grid_for(F.ne * kRowLanes), kBlock, 0, st>>>(F.csr(), make_double2(1.0, 0.0), 0.0, dy, m);
+    k_sol_add<<<grid_for(F.ne), kBlock, 0, st>>>(F.ne, gdd, m, gs);
+    HIP_TRY(hipGetLastError());
+    return ETPIC_OK;
+}
+
+// Both solvers set up on this context with the same eps.
+int check_split_setup(const etpic_ctx *ctx) {
+    if (!ctx->ns.ready) return fail(ETPIC_ESTATE, "etpic_ns_setup not called");
+    if (!ctx->field.ready) return fail(ETPIC_ESTATE, "etpic_field_setup not called");
+    if (std::fabs(ctx->field.eps - ctx->ns.eps) > 1e-15 * ctx->ns.eps)
+        return fail(ETPIC_EINVAL, "etpic_field_setup and etpic_ns_setup were given different eps");
+    return ETPIC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -3699,10 +3744,7 @@ int etpic_ns_correct(etpic_ctx *ctx, const double *G, const double *rho0, double
                      double *e_out, double tol, int max_iter, uint32_t flags, int *iters_out, double *resid_out,
                      void *stream) {
     if (!ctx || !u || !e_out) return fail(ETPIC_EINVAL, "null argument");
-    if (!ctx->ns.ready) return fail(ETPIC_ESTATE, "etpic_ns_setup not called");
-    if (!ctx->field.ready) return fail(ETPIC_ESTATE, "etpic_field_setup not called");
-    if (std::fabs(ctx->field.eps - ctx->ns.eps) > 1e-15 * ctx->ns.eps)
-        return fail(ETPIC_EINVAL, "etpic_field_setup and etpic_ns_setup were given different eps");
+    if (int r = check_split_setup(ctx)) return r;
     if (!(tol > 0.0) || max_iter < 1 || !std::isfinite(t) || !std::isfinite(omega))
         return fail(ETPIC_EINVAL, "bad tol / max_iter / time / omega");
     if (flags & ~(uint32_t)ETPIC_NS_WARM) return fail(ETPIC_EINVAL, "unknown flags 0x%x", flags);
@@ -3739,14 +3781,25 @@ int etpic_ns_correct(etpic_ctx *ctx, const double *G, const double *rho0, double
     return ETPIC_OK;
 }
 
+int etpic_sol_source(etpic_ctx *ctx, const double *gdd, double *gs_out, double tol, int max_iter, uint32_t flags,
+                     int *iters_out, double *resid_out, void *stream) {
+    if (!ctx || !gdd || !gs_out) return fail(ETPIC_EINVAL, "null argument");
+    if (int r = check_split_setup(ctx)) return r;
+    if (!(tol > 0.0) || max_iter < 1) return fail(ETPIC_EINVAL, "bad tol / max_iter");
+    if (flags & ~(uint32_t)ETPIC_NS_WARM) return fail(ETPIC_EINVAL, "unknown flags 0x%x", flags);
+    if (int r = set_device(ctx)) return r;
+    return sol_source_impl(ctx, gdd, gs_out, tol, max_iter, (flags & ETPIC_NS_WARM) != 0, iters_out, resid_out,
+                           static_cast<hipStream_t>(stream));
+}
+
 int etpic_em_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, const etpic_species *sp, int64_t step0,
                    int nsteps, double *u, double *v, double *a, double *b, double *e, double *G, double *G_hist,
                    const double *rho0, double tol, int max_iter, uint32_t flags, int *iters_out, void *stream) {
     if (!ctx || !u || !v || !a || !b || !e || !G || !G_hist) return fail(ETPIC_EINVAL, "null argument");
-    if (!ctx->field.ready) return fail(ETPIC_ESTATE, "etpic_field_setup not called");
-    if (!ctx->ns.ready) return fail(ETPIC_ESTATE, "etpic_ns_setup not called");
+    if (int r = check_split_setup(ctx)) return r;
     if (nsteps < 0) return fail(ETPIC_EINVAL, "negative step count");
     if (e == u || G == G_hist || G_hist == u || G_hist == e) return fail(ETPIC_EINVAL, "aliased state arrays");
+    if (!(tol > 0.0) || max_iter < 1) return fail(ETPIC_EINVAL, "bad tol / max_iter");
     const double dt = ctx->field.dt, omega = ctx->field.omega;
     const etpic_fields f{e, nullptr, b, nullptr};
     if (int r = check_step_args(ctx, sp, &f, dt, omega)) return r;
@@ -3757,7 +3810,8 @@ int etpic_em_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, cons
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t ne = ctx->field.ne;
     double *h1 = G_hist, *h2 = G_hist + ne;
-    const uint32_t sf = flags & ~(uint32_t)ETPIC_NS_WARM;
+    const uint32_t sf = flags & ~(uint32_t)(ETPIC_NS_WARM | ETPIC_EM_SPLIT);
+    const bool split = (flags & ETPIC_EM_SPLIT) != 0;
     int total = 0;
     for (int j = 0; j < nsteps; ++j) {
         const double t = (double)(step0 + j) * dt, t_next = (double)(step0 + j + 1) * dt;
@@ -3769,7 +3823,15 @@ int etpic_em_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, cons
         }
         k_em_gdd<<<grid_for(ne), kBlock, 0, st>>>(ne, G, h1, h2, h2, 1.0 / (dt * dt));
         HIP_TRY(hipGetLastError());
+        const bool warm = j > 0 || (flags & ETPIC_NS_WARM);
         int it = 0;
+        if (split) {   // the solenoidal system's source
+            if (int r = sol_source_impl(ctx, h2, h2, tol, max_iter, warm, &it, nullptr, st)) {
+                if (iters_out) *iters_out = total + it;
+                return r;
+            }
+            total += it;
+        }
         if (int r = etpic_field_step(ctx, t_next, u, v, a, b, h2, tol, max_iter, &it, nullptr, stream)) {
             if (iters_out) *iters_out = total + it;
             return r;
@@ -3777,10 +3839,22 @@ int etpic_em_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, cons
         total += it;
         k_em_shift<<<grid_for(ne), kBlock, 0, st>>>(ne, G, h1, h2);
         HIP_TRY(hipGetLastError());
-        const uint32_t cf = (j > 0 || (flags & ETPIC_NS_WARM)) ? (uint32_t)ETPIC_NS_WARM : 0u;
-        if (int r = etpic_ns_correct(ctx, G, rho0, t_next, omega, u, e, tol, max_iter, cf, &it, nullptr, stream)) {
-            if (iters_out) *iters_out = total + it;
-            return r;
+        if (split) {   // e = u + e^{-j w t} D y, y from eq. ns_equation
+            if (int r = ns_solve_impl(ctx, NsRhs{G, rho0, 1.0, nullptr, 0}, ctx->ns.v(0), std::cos(omega * t_next),
+                                      std::sin(omega * t_next), nullptr, reinterpret_cast<double2 *>(e), nullptr,
+                                      nullptr, tol, max_iter, warm, &it, nullptr, st)) {
+                if (iters_out) *iters_out = total + it;
+                return r;
+            }
+            k_em_add<<<grid_for(ne), kBlock, 0, st>>>(ne, reinterpret_cast<const double2 *>(u),
+                                                      reinterpret_cast<double2 *>(e));
+            HIP_TRY(hipGetLastError());
+        } else {
+            const uint32_t cf = warm ? (uint32_t)ETPIC_NS_WARM : 0u;
+            if (int r = etpic_ns_correct(ctx, G, rho0, t_next, omega, u, e, tol, max_iter, cf, &it, nullptr, stream)) {
+                if (iters_out) *iters_out = total + it;
+                return r;
+            }
         }
         total += it;
     }

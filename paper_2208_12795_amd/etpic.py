@@ -24,6 +24,7 @@ STEP_TIMING = 2
 STEP_SLICES_1, STEP_SLICES_4, STEP_SLICES_16 = 4, 8, 16
 STEP_WALK_BY_SLICE = 32
 NS_WARM = 64
+EM_SPLIT = 128
 HOP_CAP = 64
 
 EXPORTS = (
@@ -35,6 +36,7 @@ EXPORTS = (
     "etpic_particles_locate", "etpic_particles_positions", "etpic_coarse_step", "etpic_run_steps",
     "etpic_sort_run_steps", "etpic_ds_history_bytes", "etpic_ds_steps", "etpic_ds_sort",
     "etpic_ns_setup", "etpic_ns_info", "etpic_ns_solve", "etpic_ns_run_steps", "etpic_ns_correct", "etpic_em_steps",
+    "etpic_sol_source",
     "etpic_qh_last_error", "etpic_qh_create", "etpic_qh_destroy", "etpic_qh_counts", "etpic_qh_project_b",
     "etpic_qh_project_e", "etpic_tree_cotree",
 )
@@ -120,6 +122,7 @@ def lib():
                                      vp, vp, vp, C.c_double, C.c_int, C.c_uint32, C.POINTER(C.c_int), vp]
     L.etpic_ns_correct.argtypes = [vp, vp, vp, C.c_double, C.c_double, vp, vp, C.c_double, C.c_int, C.c_uint32,
                                    C.POINTER(C.c_int), dp, vp]
+    L.etpic_sol_source.argtypes = [vp, vp, vp, C.c_double, C.c_int, C.c_uint32, C.POINTER(C.c_int), dp, vp]
     L.etpic_em_steps.argtypes = [vp, vp, C.c_int, vp, C.c_int64, C.c_int, vp, vp, vp, vp, vp, vp, vp, vp, C.c_double,
                                  C.c_int, C.c_uint32, C.POINTER(C.c_int), vp]
     L.etpic_qh_last_error.restype = C.c_char_p
@@ -571,18 +574,30 @@ class Context:
             _chk(rc)
         return rc, it.value, res.value
 
+    def sol_source(self, gdd, gs_out, tol=1e-12, max_iter=2000, warm=False, stream=None, raise_on_error=True):
+        """gs_out = the field step's source gdd with its gradient part removed
+        in the [*eps] inner product (float64 [N_e] device tensors; gs_out may be
+        gdd); returns (status, iterations, residual)."""
+        it, res = C.c_int(0), C.c_double(0.0)
+        rc = lib().etpic_sol_source(self._h, _dptr(gdd), _dptr(gs_out), float(tol), int(max_iter),
+                                    NS_WARM if warm else 0, C.byref(it), C.byref(res), _stream(stream))
+        if raise_on_error:
+            _chk(rc)
+        return rc, it.value, res.value
+
     def em_steps(self, parts, species, step0, nsteps, u, v, a, b, e, G, G_hist, rho0=None, tol=1e-12,
-                 max_iter=2000, flags=STEP_XCD_REMAP, warm=False, stream=None):
+                 max_iter=2000, flags=STEP_XCD_REMAP, warm=False, split=False, stream=None):
         """nsteps steps of the electromagnetic loop (particles, field step,
-        Gauss correction), all state float64 device tensors updated in place;
-        returns the solver iterations summed."""
+        Gauss correction; split: field step on the solenoidal part plus the
+        field of eq. ns_equation), all state float64 device tensors updated in
+        place; returns the solver iterations summed."""
         d = parts.desc()
         sp = species.c()
         it = C.c_int(0)
+        fl = int(flags) | (NS_WARM if warm else 0) | (EM_SPLIT if split else 0)
         _chk(lib().etpic_em_steps(self._h, C.byref(d), parts.precision, C.byref(sp), int(step0), int(nsteps),
                                   _dptr(u), _dptr(v), _dptr(a), _dptr(b), _dptr(e), _dptr(G), _dptr(G_hist),
-                                  _dptr(rho0), float(tol), int(max_iter), int(flags) | (NS_WARM if warm else 0),
-                                  C.byref(it), _stream(stream)))
+                                  _dptr(rho0), float(tol), int(max_iter), fl, C.byref(it), _stream(stream)))
         return it.value
 
     def check(self, stream=None, raise_on_error=True):

@@ -64,12 +64,15 @@ def fit_frequency(sig, dt, w0, span=0.1, n=4001):
     return best[1], best[2]
 
 
-def oracle_em_loop(ora, cp, nsteps, dt, shape, correct=True, record=None):
+def oracle_em_loop(ora, cp, nsteps, dt, shape, correct=True, record=None, split=False):
     """The loop through the implicit field step: each step pushes the
     particles in the current fields (e, b), takes the field step to the next
     time with the source G'' from the second difference of the running path
     integral, and (correct) replaces the new field's gradient part so that
-    Gauss' law holds exactly for the deposited charge.  omega = 0.  Returns
+    Gauss' law holds exactly for the deposited charge.  split: the field step
+    takes the solenoidal source P^T G'' instead and starts from the
+    solenoidal part of the initial field, and e = u + the field of eq.
+    ns_equation (the two halves of the split summed).  omega = 0.  Returns
     (states, signal, gauss): states[j] = (tet, lam, vel, G) after step j (for
     j in record, all if None), signal[j] the mode amplitude of e used at step
     j, gauss[j] = max |D^T [*eps] e + (D^T G + rho0)| / max |D^T G + rho0| at
@@ -84,7 +87,7 @@ def oracle_em_loop(ora, cp, nsteps, dt, shape, correct=True, record=None):
     G = np.zeros(m.ne)
     G_prev = np.zeros(m.ne)
     e = ns.correct(np.zeros(m.ne, complex), None, rho0)       # the static start: Gauss for rho0
-    u, vv, a = e.copy(), np.zeros(m.ne, complex), np.zeros(m.ne, complex)
+    u, vv, a = (ns.solenoidal_part(e) if split else e.copy()), np.zeros(m.ne, complex), np.zeros(m.ne, complex)
     b = np.zeros(m.nf, complex)
     states, sig, gres = [], [], []
     for j in range(nsteps):
@@ -95,8 +98,12 @@ def oracle_em_loop(ora, cp, nsteps, dt, shape, correct=True, record=None):
         assert rc == 0
         gdd = (G - 2 * G_old + G_prev) / dt ** 2
         G_prev = G_old
-        u, vv, a, b = F.step((j + 1) * dt, u, vv, a, b, gdd)
-        e = ns.correct(u, G, rho0) if correct else u
+        if split:
+            u, vv, a, b = F.step((j + 1) * dt, u, vv, a, b, ns.solenoidal_source(gdd))
+            e = u + ns.solve(G, rho0)[1]
+        else:
+            u, vv, a, b = F.step((j + 1) * dt, u, vv, a, b, gdd)
+            e = ns.correct(u, G, rho0) if correct else u
         r, scale = ns.gauss_residual(e, G, rho0)
         gres.append(r / scale)
         if record is None or j in record:

@@ -430,10 +430,12 @@ def test_gauss_correction_matches_oracle_and_removes_null_space_growth(E, torch_
     ctx.close()
 
 
-def gpu_em_loop(E, torch, cp, nsteps, dt, per_step=None, tol=1e-13, per_call=1):
+def gpu_em_loop(E, torch, cp, nsteps, dt, per_step=None, tol=1e-13, per_call=1, split=False):
     """The plasma loop through etpic_em_steps (omega = 0): push in (e, b),
     field step with G'' from the second difference of G, correction of the
-    new edge field; per_call steps per call."""
+    new edge field; per_call steps per call.  split: the form of the split
+    (the static start's field is a pure gradient, so the solenoidal state
+    starts at zero)."""
     mu0 = 1.25663706212e-6
     ctx = E.Context(0)
     ctx.upload_mesh(cp.xyz, cp.tet_vert)
@@ -451,13 +453,14 @@ def gpu_em_loop(E, torch, cp, nsteps, dt, per_step=None, tol=1e-13, per_call=1):
     v, a, e = torch.zeros_like(u), torch.zeros_like(u), torch.zeros_like(u)
     b = torch.zeros((ctx.n_face, 2), dtype=torch.float64, device="cuda")
     ctx.ns_correct(u, e, None, rho0, tol=tol)          # the static start: Gauss' law for rho0
-    u.copy_(e)
+    if not split:
+        u.copy_(e)
     G = torch.zeros(ctx.n_edge, dtype=torch.float64, device="cuda")
     H = torch.zeros(2 * ctx.n_edge, dtype=torch.float64, device="cuda")
     for j in range(0, nsteps, per_call):
         if per_step is not None:
             per_step(j, "before", parts, G, e)
-        ctx.em_steps(parts, sp, j, per_call, u, v, a, b, e, G, H, rho0=rho0, tol=tol, warm=j > 0)
+        ctx.em_steps(parts, sp, j, per_call, u, v, a, b, e, G, H, rho0=rho0, tol=tol, warm=j > 0, split=split)
         if per_step is not None:
             per_step(j + per_call - 1, "after", parts, G, e)
     ctx.check()
@@ -466,12 +469,13 @@ def gpu_em_loop(E, torch, cp, nsteps, dt, per_step=None, tol=1e-13, per_call=1):
     return out
 
 
-def test_em_loop_matches_oracle(E, torch_cuda, ora):
+@pytest.mark.parametrize("split", [False, True])
+def test_em_loop_matches_oracle(E, torch_cuda, ora, split):
     """20 steps of the plasma loop through the field step and the correction
     (4^3 x 6 mesh, 20k electrons) on the GPU against the oracle's loop:
     positions, velocities and G every step to 1e-8 (the two CG solvers'
     tolerance carried through the loop), and Gauss' law for the GPU's field
-    to the solver tolerance."""
+    to the solver tolerance.  split: the form of the split on both sides."""
     import plasma_util as P
     from oracle import gauss
     torch = torch_cuda
@@ -479,7 +483,7 @@ def test_em_loop_matches_oracle(E, torch_cuda, ora):
     ed = synth.mesh_edges(cp.tet_vert, cp.xyz.shape[0])
     dt = 0.1 / cp.omega_p
     nsteps = 20
-    states, _, _ = P.oracle_em_loop(ora, cp, nsteps, dt, P.mode_shape(cp, ed), correct=True)
+    states, _, _ = P.oracle_em_loop(ora, cp, nsteps, dt, P.mode_shape(cp, ed), correct=True, split=split)
     m = ora.OracleMesh(cp.xyz, cp.tet_vert)
     ns = gauss.NsOracle(m, EPS0)
     rho0 = m.charge(cp.tet, cp.lam, cp.q, cp.w) - m.charge(cp.tet0, cp.lam0, cp.q, cp.w)
@@ -501,8 +505,8 @@ def test_em_loop_matches_oracle(E, torch_cuda, ora):
             worst[k] = max(worst.get(k, 0.0), val)
         prev[0] = (tg, lg, vg)
 
-    gpu_em_loop(E, torch, cp, nsteps, dt, per_step=check)
-    print(f"[ns] em loop: worst {worst}", flush=True)
+    gpu_em_loop(E, torch, cp, nsteps, dt, per_step=check, split=split)
+    print(f"[ns] em loop (split {split}): worst {worst}", flush=True)
 
 
 def test_em_steps_one_call_equals_single_calls(E, torch_cuda):
@@ -519,7 +523,8 @@ def test_em_steps_one_call_equals_single_calls(E, torch_cuda):
     assert np.abs(ea - eb).max() <= 1e-11 * np.abs(ea).max()
 
 
-def test_em_loop_plasma_frequency_bench_mesh(E, torch_cuda):
+@pytest.mark.parametrize("split", [False, True])
+def test_em_loop_plasma_frequency_bench_mesh(E, torch_cuda, split):
     """The same loop on the 40^3 x 6 mesh with 2e6 electrons, two periods:
     omega_p to 1 %, the mode amplitude to 2 %."""
     import plasma_util as P
@@ -528,11 +533,97 @@ def test_em_loop_plasma_frequency_bench_mesh(E, torch_cuda):
     shape = P.mode_shape(cp, synth.mesh_edges(cp.tet_vert, cp.xyz.shape[0]))
     dt = 0.1 / cp.omega_p
     sig = []
-    gpu_em_loop(E, torch, cp, 126, dt, tol=1e-10,
+    gpu_em_loop(E, torch, cp, 126, dt, tol=1e-10, split=split,
                 per_step=lambda j, when, p, G, e: sig.append(P.mode_amplitude(e[:, 0].cpu().numpy(), shape))
                 if when == "before" else None)
     om, _ = P.fit_frequency(np.array(sig), dt, cp.omega_p)
     phi0 = cp.density * cp.q * cp.a / EPS0
-    print(f"[ns] em loop 40^3: omega/omega_p {om / cp.omega_p:.5f}, amplitude {sig[0] / phi0:.5f}", flush=True)
+    print(f"[ns] em loop 40^3 (split {split}): omega/omega_p {om / cp.omega_p:.5f}, amplitude {sig[0] / phi0:.5f}",
+          flush=True)
     assert abs(om / cp.omega_p - 1) < 0.01
     assert abs(sig[0] / phi0 - 1) < 0.02
+
+
+def test_split_loop_equals_corrected_loop(E, torch_cuda):
+    """The two forms of the loop on the GPU (6^3 x 6 mesh, 50k electrons, 12
+    steps): the same particles, path integral and field to the solvers'
+    tolerance."""
+    torch = torch_cuda
+    cp = synth.cold_plasma(6, 50_000)
+    dt = 0.1 / cp.omega_p
+    (sa, ga, ea) = gpu_em_loop(E, torch, cp, 12, dt, per_call=12)
+    (sb, gb, eb) = gpu_em_loop(E, torch, cp, 12, dt, per_call=12, split=True)
+    assert np.array_equal(sa[0], sb[0])
+    assert np.abs(sa[2] - sb[2]).max() <= 1e-9 * np.abs(sa[2]).max()
+    assert np.abs(ga - gb).max() <= 1e-9 * np.abs(ga).max()
+    assert np.abs(ea - eb).max() <= 1e-9 * np.abs(ea).max()
+
+
+def test_solenoidal_source_and_step_match_oracle(E, torch_cuda, ora):
+    """etpic_sol_source against the oracle's P^T g (jittered mesh, random
+    source; in place too), no discrete divergence left at the inner nodes,
+    the warm start, the errors; then 20 field steps from a solenoidal random
+    state driven by the projected source keep D^T [*eps] u at the solver
+    tolerance while the plain source makes it grow, and one such step
+    matches the oracle's step of the projected state."""
+    from oracle import field, gauss
+    torch = torch_cuda
+    xyz, tv = synth.kuhn_mesh((5, 4, 6), (1.0, 0.9, 1.1), 0.15, np.random.default_rng(4))
+    mu0 = 1.25663706212e-6
+    dt, w = 1e-11, 2 * np.pi * 1.1e9
+    ctx = E.Context(0)
+    ctx.upload_mesh(xyz, tv)
+    ctx.field_setup(dt, w, EPS0, mu0)
+    with pytest.raises(E.EtpicError):                # no Gauss-law setup yet
+        ctx.sol_source(torch.zeros(ctx.n_edge, dtype=torch.float64, device="cuda"),
+                       torch.zeros(ctx.n_edge, dtype=torch.float64, device="cuda"))
+    ctx.ns_setup(EPS0)
+    m = ora.OracleMesh(xyz, tv)
+    ns = gauss.NsOracle(m, EPS0)
+    F = field.FieldOracle(m, dt, w, EPS0, mu0)
+    rng = np.random.default_rng(9)
+    g = rng.standard_normal(m.ne) * 1e3
+    tg = torch.from_numpy(g).cuda()
+    gs = torch.zeros_like(tg)
+    _, it, res = ctx.sol_source(tg, gs, tol=1e-14)
+    ref = ns.solenoidal_source(g)
+    got = gs.cpu().numpy()
+    print(f"[sol] source: {it} iterations, vs oracle {rel(got, ref):.2e}", flush=True)
+    assert rel(got, ref) <= 1e-10
+    I = ns.inner
+    assert np.abs((ns.D.T @ got)[I]).max() <= 1e-10 * np.abs((ns.D.T @ g)[I]).max()
+    _, it2, _ = ctx.sol_source(tg, gs, tol=1e-14, warm=True)
+    assert it2 < it
+    t2 = tg.clone()
+    ctx.sol_source(t2, t2, tol=1e-14)
+    assert rel(t2.cpu().numpy(), ref) <= 1e-10
+    ctx.ns_setup(2 * EPS0)
+    with pytest.raises(E.EtpicError):                # different eps in the two setups
+        ctx.sol_source(tg, gs)
+    ctx.ns_setup(EPS0)
+    # the solenoidal system: state and source free of gradients stay so
+    inn = ~ns.bnd
+    cplx = lambda n: rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    P = ns.solenoidal_part
+    u0, v0 = P(cplx(m.ne) * inn), P(cplx(m.ne) * inn) * 1e10
+    a0 = np.zeros(m.ne, complex)
+    b0 = cplx(m.nf) * 1e-9
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(np.stack([x.real, x.imag], axis=1))).cuda()
+    st = [dev(x) for x in (u0, v0, a0)] + [dev(b0)]
+    pl = [dev(x) for x in (u0, v0, a0)] + [dev(b0)]
+    ctx.field_step(dt, *st, gs, tol=1e-13)
+    ou, ov, oa, ob = F.step(dt, u0, v0, a0, b0, ref)
+    for x, y in zip(st, (ou, ov, oa, ob)):
+        assert rel(t2c(x), y) <= 1e-9
+    ctx.field_step(dt, *pl, tg, tol=1e-13)
+    scale = np.abs((ns.D.T @ (ns.M @ t2c(pl[0])))[I]).max()
+    for n in range(2, 21):
+        ctx.field_step(n * dt, *st, gs, tol=1e-13)
+        ctx.field_step(n * dt, *pl, tg, tol=1e-13)
+    div_s = np.abs((ns.D.T @ (ns.M @ t2c(st[0])))[I]).max()
+    div_p = np.abs((ns.D.T @ (ns.M @ t2c(pl[0])))[I]).max()
+    print(f"[sol] after 20 steps: |D^T M u| solenoidal {div_s:.3e}, plain {div_p:.3e} (first step {scale:.3e})",
+          flush=True)
+    assert div_p >= 100 * scale
+    assert div_s <= 1e-8 * div_p
+    ctx.close()

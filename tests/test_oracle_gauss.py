@@ -267,3 +267,77 @@ def test_em_loop_with_gauss_correction(ora):
     assert gres.max() < 1e-12, gres.max()
     _, _, gplain = P.oracle_em_loop(ora, cp, 40, dt, shape, correct=False, record=[])
     assert gplain.max() > 1e-2, gplain.max()
+
+
+def test_solenoidal_projector_and_source(jittered):
+    """The projector of the split in the [*eps] inner product: P^T g has no
+    discrete divergence at the inner nodes, what it removes is [*eps] times a
+    gradient (the curl of its [*eps]^-1 image vanishes), it is idempotent,
+    kills a pure gradient flux, and is the transpose of P u = u - D y on
+    fields that vanish on the boundary edges."""
+    import scipy.sparse.linalg as spla
+    from oracle import gauss, qh
+    ns = gauss.NsOracle(jittered, EPS0)
+    rng = np.random.default_rng(31)
+    I, inn = ns.inner, ~ns.bnd
+    C = qh.curl_incidence(jittered)
+    g = rng.standard_normal(jittered.ne)
+    gs = ns.solenoidal_source(g)
+    assert np.abs((ns.D.T @ gs)[I]).max() <= 1e-12 * np.abs((ns.D.T @ g)[I]).max()
+    assert np.array_equal(gs[ns.bnd], g[ns.bnd])
+    x = np.zeros(jittered.ne)
+    x[inn] = spla.spsolve(ns.M[inn][:, inn].tocsc(), (g - gs)[inn])
+    assert np.abs(C @ x).max() <= 1e-10 * np.abs(x).max()
+    assert np.abs(ns.solenoidal_source(gs) - gs).max() <= 1e-12 * np.abs(gs).max()
+    phi = rng.standard_normal(jittered.nv) * ~ns.wall
+    f = ns.M @ (ns.D @ phi)
+    assert np.abs(ns.solenoidal_source(f)[inn]).max() <= 1e-10 * np.abs(f).max()
+    u = (rng.standard_normal(jittered.ne) + 1j * rng.standard_normal(jittered.ne)) * inn
+    pu = ns.solenoidal_part(u)
+    assert np.abs((ns.D.T @ (ns.M @ pu))[I]).max() <= 1e-12 * np.abs((ns.D.T @ (ns.M @ u))[I]).max()
+    assert np.abs(C @ (u - pu)).max() <= 1e-12 * np.abs(u).max()
+    assert np.abs(ns.solenoidal_part(pu) - pu).max() <= 1e-12 * np.abs(pu).max()
+    assert abs(gs @ u - g @ pu) <= 1e-12 * np.abs(g).sum() * np.abs(u).max()
+
+
+def test_solenoidal_step_is_the_projected_field_step(jittered):
+    """The field step commutes with the split: projecting the state after a
+    step equals stepping the projected state with the projected source P^T
+    g'' (the curl-curl stiffness annihilates gradients and P is orthogonal in
+    [*eps]), and the face field is the same.  So the solenoidal system is the
+    field step run on the range of P, driven by P^T g''; any carrier."""
+    from oracle import field, gauss
+    ns = gauss.NsOracle(jittered, EPS0)
+    F = field.FieldOracle(jittered, 1e-11, 2 * np.pi * 1.1e9, EPS0, 1.25663706212e-6)
+    rng = np.random.default_rng(33)
+    inn = ~ns.bnd
+    cplx = lambda n: rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    u, v, a = (cplx(jittered.ne) * inn * s for s in (1.0, 1e10, 1e20))
+    b = cplx(jittered.nf) * 1e-9
+    gdd = rng.standard_normal(jittered.ne) * 1e3
+    P = ns.solenoidal_part
+    full = F.step(3.3e-10, u, v, a, b, gdd)
+    sol = F.step(3.3e-10, P(u), P(v), P(a), b, ns.solenoidal_source(gdd))
+    for x, y in zip(full[:3], sol[:3]):
+        assert np.abs(P(x) - y).max() <= 1e-10 * np.abs(y).max()
+    assert np.abs(full[3] - sol[3]).max() <= 1e-10 * np.abs(sol[3]).max()
+
+
+def test_split_loop_equals_corrected_loop(ora):
+    """The electromagnetic loop in the form of the split (field step on the
+    solenoidal part driven by P^T G'', plus the field of eq. ns_equation) and
+    the loop corrected every step give the same particles, fields and Gauss'
+    law: the same field, reached along the two routes."""
+    import plasma_util as P
+    cp = synth.cold_plasma(4, 20_000)
+    shape = P.mode_shape(cp, synth.mesh_edges(cp.tet_vert, cp.xyz.shape[0]))
+    dt = 0.1 / cp.omega_p
+    sa, siga, ga = P.oracle_em_loop(ora, cp, 20, dt, shape, correct=True)
+    sb, sigb, gb = P.oracle_em_loop(ora, cp, 20, dt, shape, split=True)
+    assert gb.max() < 1e-12, gb.max()
+    assert np.abs(sigb - siga).max() <= 1e-12 * np.abs(siga).max()
+    for (ta, la, va, Ga), (tb, lb, vb, Gb) in zip(sa, sb):
+        assert np.array_equal(ta, tb)
+        assert np.abs(lb - la).max() < 1e-12
+        assert np.abs(vb - va).max() <= 1e-12 * np.abs(va).max()
+        assert np.abs(Gb - Ga).max() <= 1e-12 * np.abs(Ga).max()

@@ -137,3 +137,23 @@ def test_solenoidal_system_blocks_and_spectrum(ora):
         assert np.all(np.abs(f[:3] / f110 - 1) < 0.02) and np.all(np.abs(f[3:5] / f111 - 1) < 0.03)
         errs.append(np.abs(f[:3] / f110 - 1).max())
     assert errs[0] / errs[1] > 1.5, errs           # (4/3)^2 = 1.78 for second order
+
+
+def test_solenoidal_system_is_the_curl_curl_pencil_off_gradients(ora):
+    """The solenoidal system with the energy-orthogonal projectors has the
+    nonzero spectrum of the full edge-element pencil (K, [*eps]): its cotree
+    unknowns are a basis of the [*eps]-orthogonal complement of the
+    gradients, where K is nonsingular.  So the field step run on that
+    complement (state solenoidal, source projected) is the same system
+    without the tree-cotree gauge (unit cube, 3^3 cells, no boundary
+    condition, as in the study above)."""
+    import scipy.linalg as sl
+    from oracle import field, qh
+    xyz, tv = synth.kuhn_mesh((3, 3, 3), (1.0, 1.0, 1.0), 0.0)
+    m = ora.OracleMesh(xyz, tv)
+    ev = np.sort(qh.solenoidal_spectrum(m, EPS0, MU0, weighted=True).real)
+    M, K, _ = field.assemble(m, EPS0, MU0)
+    w = sl.eigh(K.toarray(), M.toarray(), eigvals_only=True)
+    nz = np.sort(w[w > 1e-6 * w.max()])
+    assert len(nz) == len(ev) == m.ne - m.nv + 1
+    assert np.abs(nz / ev - 1).max() < 1e-10

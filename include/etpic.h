@@ -393,7 +393,8 @@ int etpic_field_spmv(etpic_ctx *ctx, const double *x, double *y, double alpha_re
 /* One field step to time t_next: u = e, v = e', a = e'' (2*N_e float64 each,
  * complex, device, updated in place), b = face envelope (2*N_f, in place),
  * gdd = g'' at t_next (N_e float64, device, NULL = 0).  COCG stops when
- * ||r|| / ||rhs|| <= tol (checked every 5 iterations) or after max_iter;
+ * ||r|| / ||rhs|| <= tol (tested on the device every iteration, read by the
+ * host every 5) or after max_iter;
  * *iters_out, *resid_out report it.  Synchronises `stream`.  ENOCONV (state
  * left unchanged) if the tolerance is not reached. */
 int etpic_field_step(etpic_ctx *ctx, double t_next, double *u, double *v, double *a, double *b, const double *gdd,

@@ -1784,17 +1784,15 @@ __global__ void __launch_bounds__(kBlock) k_nm_predict(int64_t ne, const double2
     w[i] = csub(cmul(make_double2(0.0, 2.0 * omega), vsi), cscale(usi, omega * omega));
 }
 
-// rhs = f - M w - K us with f = -e^{-j w t} g'';  boundary rows 0.  partial[4b+0] = |rhs|^2
+// rhs = f - M w - K us with f = -e^{-j w t} g'';  boundary rows 0
 __global__ void __launch_bounds__(kBlock) k_nm_rhs(FieldCsr S, const double2 *__restrict__ w,
                                                    const double2 *__restrict__ us, const double *__restrict__ gdd,
-                                                   double c, double s, double2 *__restrict__ rhs,
-                                                   double *__restrict__ partial) {
+                                                   double c, double s, double2 *__restrict__ rhs) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t row = t / kRowLanes;
     const int sub = (int)(t % kRowLanes);
     double2 m, k;
     csr_row2(S, row, sub, w, us, m, k);
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
     if (row < S.ne && sub == 0) {
         double2 r = make_double2(0.0, 0.0);
         if (!S.dir[row]) {
@@ -1803,16 +1801,16 @@ __global__ void __launch_bounds__(kBlock) k_nm_rhs(FieldCsr S, const double2 *__
             r = make_double2(-c * g - m.x - k.x, s * g - m.y - k.y);
         }
         rhs[row] = r;
-        v[0] = r.x * r.x + r.y * r.y;
     }
-    block_sum4(v, partial);
 }
 
-// COCG start: x = 0, r = rhs, z = Dinv r, p = z; partial: rho = r.z (re, im), |r|^2
+// COCG start: x = 0, r = rhs, z = Dinv r, p = q = 0; partials r.z (re, im),
+// |r|^2, |b|^2 (= |r|^2); clears the done flag and the iteration count.
 __global__ void __launch_bounds__(kBlock) k_cocg_init(int64_t ne, const double2 *__restrict__ rhs,
                                                       const double2 *__restrict__ dinv, double2 *__restrict__ x,
                                                       double2 *__restrict__ r, double2 *__restrict__ z,
-                                                      double2 *__restrict__ p, double *__restrict__ partial) {
+                                                      double2 *__restrict__ p, double2 *__restrict__ q,
+                                                      double *__restrict__ partial, double *__restrict__ sc) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     if (i < ne) {
@@ -1821,140 +1819,19 @@ __global__ void __launch_bounds__(kBlock) k_cocg_init(int64_t ne, const double2 
         x[i] = make_double2(0.0, 0.0);
         r[i] = ri;
         z[i] = zi;
-        p[i] = zi;
+        p[i] = make_double2(0.0, 0.0);
+        q[i] = make_double2(0.0, 0.0);
         const double2 rz = cmul(ri, zi);
         v[0] = rz.x;
         v[1] = rz.y;
         v[2] = ri.x * ri.x + ri.y * ri.y;
+        v[3] = v[2];
+    }
+    if (i == 0) {
+        sc[10] = 0.0;
+        sc[11] = 0.0;
     }
     block_sum4(v, partial);
-}
-
-// Device scalars of the iteration: sc[0..1] rho = r . z, sc[2..3] p . q,
-// sc[4..5] alpha, sc[6..7] beta, sc[8] |r|^2, sc[9] |b|^2 (complex as re, im).
-//
-// COCG iteration: q = A p with the partials of p . q
-__global__ void __launch_bounds__(kBlock) k_cocg_apply(FieldCsr S, double2 alpha, double beta,
-                                                       const double2 *__restrict__ p, double2 *__restrict__ q,
-                                                       double *__restrict__ partial) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t row = t / kRowLanes;
-    const int sub = (int)(t % kRowLanes);
-    double2 m, k;
-    csr_row2(S, row, sub, p, p, m, k);
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
-    if (row < S.ne && sub == 0) {
-        const double2 qi = cadd(cmul(alpha, m), cscale(k, beta));
-        q[row] = qi;
-        const double2 pq = cmul(p[row], qi);
-        v[0] = pq.x;
-        v[1] = pq.y;
-    }
-    block_sum4(v, partial);
-}
-
-// x += alpha p, r -= alpha q, z = Dinv r, with the partials of r . z and |r|^2
-__global__ void __launch_bounds__(kBlock) k_cocg_update(int64_t ne, const double *__restrict__ sc,
-                                                        const double2 *__restrict__ dinv, const double2 *__restrict__ p,
-                                                        const double2 *__restrict__ q, double2 *__restrict__ x,
-                                                        double2 *__restrict__ r, double2 *__restrict__ z,
-                                                        double *__restrict__ partial) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const double2 al = make_double2(sc[4], sc[5]);
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
-    if (i < ne) {
-        x[i] = cadd(x[i], cmul(al, p[i]));
-        const double2 ri = csub(r[i], cmul(al, q[i]));
-        r[i] = ri;
-        const double2 zi = cmul(dinv[i], ri);
-        z[i] = zi;
-        const double2 rz = cmul(ri, zi);
-        v[0] = rz.x;
-        v[1] = rz.y;
-        v[2] = ri.x * ri.x + ri.y * ri.y;
-    }
-    block_sum4(v, partial);
-}
-
-// One block: the block partials summed in a fixed order, then the scalar
-// update of the iteration on thread 0 (kind 0: alpha = rho / (p . q);
-// kind 1: beta = rho_new / rho, rho = rho_new, |r|^2).
-__global__ void __launch_bounds__(kBlock) k_cocg_scalars(int64_t nb, const double *__restrict__ partial,
-                                                         double *__restrict__ sc, int kind) {
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t b = threadIdx.x; b < nb; b += blockDim.x)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) v[k] += partial[4 * b + k];
-    __shared__ double sh[kBlock / 64][4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
-    if ((threadIdx.x & 63) == 0)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) sh[threadIdx.x >> 6][k] = v[k];
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    double tot[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int w = 0; w < kBlock / 64; ++w)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) tot[k] += sh[w][k];
-    if (kind == 0) {
-        const double2 pq = make_double2(tot[0], tot[1]);
-        const double2 al = (pq.x == 0.0 && pq.y == 0.0) ? make_double2(0.0, 0.0) : cdiv(make_double2(sc[0], sc[1]), pq);
-        sc[2] = pq.x;
-        sc[3] = pq.y;
-        sc[4] = al.x;
-        sc[5] = al.y;
-    } else {
-        const double2 rn = make_double2(tot[0], tot[1]);
-        const double2 ro = make_double2(sc[0], sc[1]);
-        const double2 be = (ro.x == 0.0 && ro.y == 0.0) ? make_double2(0.0, 0.0) : cdiv(rn, ro);
-        sc[0] = rn.x;
-        sc[1] = rn.y;
-        sc[6] = be.x;
-        sc[7] = be.y;
-        sc[8] = tot[2];
-    }
-}
-
-// Sums nb block partials (4 each) in a fixed order into out[0..3].
-__global__ void __launch_bounds__(kBlock) k_reduce4(int64_t nb, const double *__restrict__ partial,
-                                                    double *__restrict__ out) {
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t b = threadIdx.x; b < nb; b += blockDim.x)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) v[k] += partial[4 * b + k];
-    __shared__ double sh[kBlock / 64][4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) sh[wid][k] = v[k];
-    __syncthreads();
-    if (threadIdx.x < 4) {
-        double s = 0.0;
-        for (int w = 0; w < kBlock / 64; ++w) s += sh[w][threadIdx.x];
-        out[threadIdx.x] = s;
-    }
-}
-
-// start: rho and |r|^2 from red, |b|^2 from red2[0]
-__global__ void k_cocg_start(double *__restrict__ sc, const double *__restrict__ red, const double *__restrict__ red2) {
-    if (threadIdx.x == 0) {
-        sc[0] = red[0];
-        sc[1] = red[1];
-        sc[8] = red[2];
-        sc[9] = red2[0];
-    }
-}
-
-// p = z + beta p
-__global__ void __launch_bounds__(kBlock) k_cocg_dir(int64_t ne, const double *__restrict__ sc,
-                                                     const double2 *__restrict__ z, double2 *__restrict__ p) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < ne) p[i] = cadd(z[i], cmul(make_double2(sc[6], sc[7]), p[i]));
 }
 
 // faces: (1 + j w dt/2) b_new = (1 - j w dt/2) b - dt/2 C (u + u_new), u_new = us + dt^2/4 x,
@@ -2266,6 +2143,90 @@ __global__ void __launch_bounds__(kNsThreads) k_ns_iter(NsCsr S, const double *_
     ns_block_sum4(v, pout);
 }
 
+// ---- COCG of the field step, two launches per iteration on at most
+// kNsBlocks blocks, so that every block sums the previous launch's partials
+// itself (as the nodal CG): no scalar kernels, the convergence test on the
+// device.  Scalars sc: [0..1], [2..3] rho = r^T z (complex, unconjugated) of
+// even / odd iterations, [8] |r|^2, [9] |b|^2, [10] done, [11] iterations.
+//
+// Iteration k, first half: done once |r_k|^2 <= tol^2 |b|^2 (or b = 0, or not
+// finite); beta = rho_k / rho_{k-1}, p = z + beta p, q = A z + beta q (= A p,
+// the direction update folded into the product), partials p^T q.
+// A = alpha M + beta_k K.  check_only: the test alone.
+__global__ void __launch_bounds__(kNsThreads) k_cocg_apply(FieldCsr S, double2 alpha, double beta_k,
+                                                       double *__restrict__ sc, const double2 *__restrict__ z,
+                                                       double2 *__restrict__ p, double2 *__restrict__ q,
+                                                       const double *__restrict__ pin, int64_t nb_in,
+                                                       double *__restrict__ pout, int k, double tol2,
+                                                       int check_only) {
+    if (sc[10] != 0.0) return;
+    double tot[4];
+    all_sum4(nb_in, pin, tot);
+    const double b2 = k == 0 ? tot[3] : sc[9];
+    const double r2 = tot[2];
+    const double2 rn = make_double2(tot[0], tot[1]);
+    const bool done = b2 == 0.0 || !(r2 > tol2 * b2);
+    const int o = 2 * ((k + 1) & 1);
+    const double2 ro = make_double2(sc[o], sc[o + 1]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc[8] = r2;
+        if (k == 0) sc[9] = b2;
+        sc[2 * (k & 1)] = rn.x;
+        sc[2 * (k & 1) + 1] = rn.y;
+        sc[10] = done ? 1.0 : 0.0;
+        sc[11] = (double)k;
+    }
+    if (done || check_only) return;
+    const double2 be = (k == 0 || (ro.x == 0.0 && ro.y == 0.0)) ? make_double2(0.0, 0.0) : cdiv(rn, ro);
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t / kRowLanes < S.ne; t += stride) {
+        const int64_t row = t / kRowLanes;
+        const int sub = (int)(t % kRowLanes);
+        double2 m, kk;
+        csr_row2(S, row, sub, z, z, m, kk);
+        if (sub == 0) {
+            const double2 pn = cadd(z[row], cmul(be, p[row]));
+            const double2 qn = cadd(cadd(cmul(alpha, m), cscale(kk, beta_k)), cmul(be, q[row]));
+            p[row] = pn;
+            q[row] = qn;
+            const double2 pq = cmul(pn, qn);
+            v[0] += pq.x;
+            v[1] += pq.y;
+        }
+    }
+    ns_block_sum4(v, pout);
+}
+
+// Iteration k, second half: alpha = rho_k / (p^T q); x += alpha p, r -= alpha q,
+// z = Dinv r; partials r^T z (re, im), |r|^2.
+__global__ void __launch_bounds__(kNsVecThreads) k_cocg_update(int64_t ne, const double *__restrict__ sc,
+                                                        const double2 *__restrict__ dinv,
+                                                        const double2 *__restrict__ p, const double2 *__restrict__ q,
+                                                        double2 *__restrict__ x, double2 *__restrict__ r,
+                                                        double2 *__restrict__ z, const double *__restrict__ pin,
+                                                        int64_t nb_in, double *__restrict__ pout, int k) {
+    if (sc[10] != 0.0) return;
+    double tot[4];
+    all_sum4(nb_in, pin, tot);
+    const double2 pq = make_double2(tot[0], tot[1]);
+    const double2 rho = make_double2(sc[2 * (k & 1)], sc[2 * (k & 1) + 1]);
+    const double2 al = (pq.x == 0.0 && pq.y == 0.0) ? make_double2(0.0, 0.0) : cdiv(rho, pq);
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ne; i += (int64_t)gridDim.x * blockDim.x) {
+        x[i] = cadd(x[i], cmul(al, p[i]));
+        const double2 ri = csub(r[i], cmul(al, q[i]));
+        r[i] = ri;
+        const double2 zi = cmul(dinv[i], ri);
+        z[i] = zi;
+        const double2 rz = cmul(ri, zi);
+        v[0] += rz.x;
+        v[1] += rz.y;
+        v[2] += ri.x * ri.x + ri.y * ri.y;
+    }
+    ns_block_sum4(v, pout);
+}
+
 // x_out = e^{-j w t} x on the nodes, e_out = e^{-j w t} D x on the edges
 // (edge e from ev[2e] to ev[2e+1]), edc_out = D x (+ edc_add): the same field
 // as real, unmodulated DoFs.  Every pointer may be NULL.
@@ -2348,16 +2309,15 @@ struct FieldState {
     uint8_t *dir = nullptr;
     double2 *dinv = nullptr;
     double2 *vec = nullptr;     // 9 work vectors of ne: us, vs, w, rhs, x, r, z, p, q
-    double *partial = nullptr;  // 4 per block
-    double *red = nullptr;      // 8: reductions (4) and |rhs|^2 (4)
-    double *sc = nullptr;       // 10 scalars of the iteration
+    double *partial = nullptr;  // two sets of 4 per block: nb blocks (the start, the update), then kNsBlocks
+    double *sc = nullptr;       // 12 scalars of the iteration
     int64_t nb = 0;
 
     double2 *v(int k) const { return vec + (size_t)k * ne; }
     FieldCsr csr() const { return FieldCsr{ne, rowptr, col, M, K, dir}; }
     void release() {
         for (void *q : {(void *)rowptr, (void *)col, (void *)face_edge, (void *)M, (void *)K, (void *)dir,
-                        (void *)dinv, (void *)vec, (void *)partial, (void *)red, (void *)sc})
+                        (void *)dinv, (void *)vec, (void *)partial, (void *)sc})
             (void)hipFree(q);
         *this = FieldState();
     }
@@ -3478,7 +3438,7 @@ int etpic_field_setup(etpic_ctx *ctx, double dt, double omega, double eps, doubl
         if (!(den > 0.0)) return fail(ETPIC_EMESH, "field: zero diagonal at edge %lld", (long long)i);
         dinv[i] = make_double2(dr / den, -di / den);
     }
-    F.nb = (int64_t)grid_for(ne * kRowLanes);
+    F.nb = std::max<int64_t>(grid_for(ne), kNsBlocks);
     HIP_TRY(hipMalloc(&F.rowptr, sizeof(int32_t) * (ne + 1)));
     HIP_TRY(hipMalloc(&F.col, sizeof(int32_t) * S.nnz));
     HIP_TRY(hipMalloc(&F.M, sizeof(double) * S.nnz));
@@ -3487,9 +3447,8 @@ int etpic_field_setup(etpic_ctx *ctx, double dt, double omega, double eps, doubl
     HIP_TRY(hipMalloc(&F.face_edge, sizeof(int32_t) * 3 * S.nf));
     HIP_TRY(hipMalloc(&F.dinv, sizeof(double2) * ne));
     HIP_TRY(hipMalloc(&F.vec, sizeof(double2) * 9 * ne));
-    HIP_TRY(hipMalloc(&F.partial, sizeof(double) * 4 * F.nb));
-    HIP_TRY(hipMalloc(&F.red, sizeof(double) * 8));
-    HIP_TRY(hipMalloc(&F.sc, sizeof(double) * 10));
+    HIP_TRY(hipMalloc(&F.partial, sizeof(double) * 4 * (F.nb + kNsBlocks)));
+    HIP_TRY(hipMalloc(&F.sc, sizeof(double) * 12));
     HIP_TRY(hipMemcpy(F.rowptr, S.rowptr.data(), sizeof(int32_t) * (ne + 1), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(F.col, S.col.data(), sizeof(int32_t) * S.nnz, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(F.M, S.M.data(), sizeof(double) * S.nnz, hipMemcpyHostToDevice));
@@ -3539,37 +3498,38 @@ int etpic_field_step(etpic_ctx *ctx, double t_next, double *u, double *v, double
     double2 *us = F.v(0), *vs = F.v(1), *wv = F.v(2), *rhs = F.v(3), *x = F.v(4), *r = F.v(5), *z = F.v(6), *p = F.v(7),
             *q = F.v(8);
     k_nm_predict<<<ge, kBlock, 0, st>>>(ne, U, V, A, us, vs, wv, dt, w);
-    k_nm_rhs<<<gr, kBlock, 0, st>>>(F.csr(), wv, us, gdd, c, s, rhs, F.partial);
-    k_reduce4<<<1, kBlock, 0, st>>>(gr, F.partial, F.red + 4);
-    k_cocg_init<<<ge, kBlock, 0, st>>>(ne, rhs, F.dinv, x, r, z, p, F.partial);
-    k_reduce4<<<1, kBlock, 0, st>>>(ge, F.partial, F.red);
-    k_cocg_start<<<1, 64, 0, st>>>(F.sc, F.red, F.red + 4);
+    k_nm_rhs<<<gr, kBlock, 0, st>>>(F.csr(), wv, us, gdd, c, s, rhs);
+    // partial sets: the start and the update write the first, the product the second
+    double *pa = F.partial, *pb = F.partial + 4 * F.nb;
+    k_cocg_init<<<ge, kBlock, 0, st>>>(ne, rhs, F.dinv, x, r, z, p, q, pa, F.sc);
     HIP_TRY(hipGetLastError());
-    double hs[10];
-    HIP_TRY(hipMemcpyAsync(hs, F.sc, sizeof hs, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    const double bnorm2 = hs[9];
-    double rel = bnorm2 > 0.0 ? std::sqrt(hs[8] / bnorm2) : 0.0;
-    int it = 0;
+    const unsigned ga = (unsigned)std::min<int64_t>((ne * kRowLanes + kNsThreads - 1) / kNsThreads, kNsBlocks);
+    const unsigned gu = (unsigned)std::min<int64_t>((ne + kNsVecThreads - 1) / kNsVecThreads, kNsBlocks);
+    // iterations in batches of `check`; the host reads the scalars once per batch
     const int check = 5;
-    while (rel > tol && it < max_iter) {
-        k_cocg_apply<<<gr, kBlock, 0, st>>>(F.csr(), alpha, beta, p, q, F.partial);
-        k_cocg_scalars<<<1, kBlock, 0, st>>>(gr, F.partial, F.sc, 0);
-        k_cocg_update<<<ge, kBlock, 0, st>>>(ne, F.sc, F.dinv, p, q, x, r, z, F.partial);
-        k_cocg_scalars<<<1, kBlock, 0, st>>>(ge, F.partial, F.sc, 1);
-        k_cocg_dir<<<ge, kBlock, 0, st>>>(ne, F.sc, z, p);
-        HIP_TRY(hipGetLastError());
-        ++it;
-        if (it % check == 0 || it == max_iter) {
-            HIP_TRY(hipMemcpyAsync(hs, F.sc, sizeof hs, hipMemcpyDeviceToHost, st));
-            HIP_TRY(hipStreamSynchronize(st));
-            rel = std::sqrt(hs[8] / bnorm2);
-            if (!std::isfinite(rel)) break;
+    const double tol2 = tol * tol;
+    double hs[12];
+    int k = 0;
+    for (;;) {
+        const int n = std::min(check, max_iter - k);
+        for (int j = 0; j < n; ++j, ++k) {
+            k_cocg_apply<<<ga, kNsThreads, 0, st>>>(F.csr(), alpha, beta, F.sc, z, p, q, pa, k == 0 ? (int64_t)ge : gu,
+                                                    pb, k, tol2, 0);
+            k_cocg_update<<<gu, kNsVecThreads, 0, st>>>(ne, F.sc, F.dinv, p, q, x, r, z, pb, ga, pa, k);
         }
+        if (k >= max_iter)
+            k_cocg_apply<<<ga, kNsThreads, 0, st>>>(F.csr(), alpha, beta, F.sc, z, p, q, pa, k == 0 ? (int64_t)ge : gu,
+                                                    pb, k, tol2, 1);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(hs, F.sc, sizeof hs, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (hs[10] != 0.0 || k >= max_iter) break;
     }
+    const double rel = hs[9] > 0.0 ? std::sqrt(hs[8] / hs[9]) : 0.0;
+    const int it = (int)hs[11];
     if (iters_out) *iters_out = it;
     if (resid_out) *resid_out = rel;
-    if (!(rel <= tol)) return fail(ETPIC_ENOCONV, "COCG: relative residual %.3e after %d iterations", rel, it);
+    if (hs[10] == 0.0 || !std::isfinite(rel)) return fail(ETPIC_ENOCONV, "COCG: relative residual %.3e after %d iterations", rel, it);
     k_nm_faraday<<<grid_for(F.nf), kBlock, 0, st>>>(F.nf, F.face_edge, U, us, x, reinterpret_cast<double2 *>(b), dt, w);
     k_nm_correct<<<ge, kBlock, 0, st>>>(ne, us, vs, x, U, V, A, dt);
     HIP_TRY(hipGetLastError());

@@ -190,11 +190,10 @@ def ns_solve_timing(E, torch, ctx, w, reps=3):
     """Side path, timed separately: the non-solenoidal (Gauss-law) solve on the
     bench mesh, its source the charge of the workload's particles (float64
     Jacobi-preconditioned CG on the nodal operator, to a 1e-10 relative
-    residual, one launch per iteration).  Algorithmic bytes per iteration:
-    the column index and value of every stored entry (12 B) and per row the
-    row pointer, r, w, q, p, x and the preconditioner read (52 B) and p, x
-    and the next r, w, q written (40 B); the values gathered at the columns
-    are the rows' own, counted once."""
+    residual).  Algorithmic bytes per iteration: the product reads the column
+    index and value of every stored entry (12 B) and per row the row pointer,
+    z, p and q (28 B) and writes p and q (16 B); the update reads p, q, x, r
+    and the preconditioner (40 B) and writes x, r and z (24 B)."""
     eps0 = 8.8541878128e-12
     nnz, n_wall = ctx.ns_setup(eps0)
     nv, ne = ctx.n_vert, ctx.n_edge
@@ -225,7 +224,7 @@ def ns_solve_timing(E, torch, ctx, w, reps=3):
     _, corr_it, _ = ctx.ns_correct(u, eo, None, rho0, 0.0, w.omega, tol=1e-10, max_iter=5000)
     torch.cuda.synchronize()
     corr_ms = 1e3 * (time.perf_counter() - t0)
-    bytes_iter = 12 * nnz + 92 * nv
+    bytes_iter = 12 * nnz + 108 * nv
     per_iter = solve_ms / max(iters, 1)
     # the loop closed through the solve: the workload's electrons over a
     # neutralising background (rho0 = 0, G from zero), fields of the workload

@@ -1881,8 +1881,8 @@ struct NsCsr {
 // the same fixed order: the scalars of the iteration need no kernel of their
 // own and no cross-block synchronisation.  Partials: 4 doubles per block.
 // Scalars sc (written by thread 0 of block 0 only, read by the next kernel):
-// sc[0], sc[1] rho = r.z and sc[2], sc[3] alpha of even / odd iterations,
-// sc[8] |r|^2, sc[9] |b|^2, sc[10] done flag, sc[11] iterations taken.
+// sc[0], sc[1] rho = r.z of even / odd iterations, sc[8] |r|^2, sc[9] |b|^2,
+// sc[10] done flag, sc[11] iterations taken.
 constexpr int kNsBlocks = 512;
 constexpr int kNsThreads = 1024;   // product kernels: 16 wavefronts per block, enough rows in flight for one pass
 constexpr int kNsVecThreads = 256; // vector kernels (one node per lane): more, smaller blocks
@@ -2027,118 +2027,77 @@ __global__ void __launch_bounds__(kNsThreads) k_ns_start_warm(NsCsr S, const int
     ns_block_sum4(v, partial);
 }
 
-// ---- One launch per CG iteration.  Plain PCG needs the whole of z before
-// its product, which takes a second launch per iteration; here the product
-// reads, at each column j, the inputs of the iteration instead and forms
-// z_{k+1}[j] itself: Chronopoulos-Gear CG (w = A z computed directly, q = A p by recurrence,
-// both inner products r.z and z.w from one reduction):
-//     beta = rho_k / rho_{k-1},  alpha = rho_k / (delta_k - beta rho_k / alpha_{k-1}),
-//     p_k = z_k + beta p_{k-1},  q_k = w_k + beta q_{k-1},
-//     x += alpha p_k,  r_{k+1} = r_k - alpha q_k,  w_{k+1} = A Dinv r_{k+1},
-// with rho = r.z and delta = z.w.  r, w, q are double-buffered (iteration k
-// reads buffer k & 1 at any row and writes buffer (k + 1) & 1 at its own
-// rows), p and x are touched at their own rows only.  SD holds the entries
-// of A Dinv (S_ij dinv_j), so the product needs no gather of dinv.
-struct NsVecs {
-    double *x, *p, *r[2], *w[2], *q[2];
-};
-
-// w_0 = A Dinv r_0 after a start kernel (which left r_0 in r[0] and its
-// partials: r.z, -, |r|^2, |b|^2); records |b|^2, clears the flags; partials
-// rho_0, delta_0, |r_0|^2.
-__global__ void __launch_bounds__(kNsThreads) k_ns_prime(NsCsr S, const double *__restrict__ SD,
-                                                     const double *__restrict__ dinv, const double *__restrict__ r,
-                                                     double *__restrict__ w, double *__restrict__ sc,
-                                                     const double *__restrict__ pin, int64_t nb_in,
-                                                     double *__restrict__ pout) {
+// Iteration k, first half.  From the partials of the previous update (or of
+// the start, k = 0): |r|^2 and rho_new = r.z; done once |r|^2 <= tol^2 |b|^2
+// (or not finite, or b = 0), then every block returns.  Otherwise beta = rho_new /
+// rho_old, p = z + beta p and q = A p = A z + beta q (the direction update
+// folded into the product, so no separate pass over p is needed), with the
+// partials of p . q.  check_only: the convergence test alone (after the last
+// allowed iteration).  Returns at once if an earlier launch found convergence.
+__global__ void __launch_bounds__(kNsThreads) k_ns_apply(NsCsr S, double *__restrict__ sc,
+                                                     const double *__restrict__ z, double *__restrict__ p,
+                                                     double *__restrict__ q, const double *__restrict__ pin,
+                                                     int64_t nb_in, double *__restrict__ pout, int k, double tol2,
+                                                     int check_only) {
+    if (sc[10] != 0.0) return;
     double tot[4];
     all_sum4(nb_in, pin, tot);
+    const double b2 = k == 0 ? tot[3] : sc[9];
+    const double r2 = tot[2], rn = tot[0];
+    const bool done = b2 == 0.0 || !(r2 > tol2 * b2);   // no source: x = 0, done
+    const double ro = sc[(k + 1) & 1];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        sc[9] = tot[3];
-        sc[10] = 0.0;
-        sc[11] = 0.0;
+        sc[8] = r2;
+        if (k == 0) sc[9] = b2;
+        sc[k & 1] = rn;
+        sc[10] = done ? 1.0 : 0.0;
+        sc[11] = (double)k;
     }
+    if (done || check_only) return;
+    const double be = (k == 0 || ro == 0.0) ? 0.0 : rn / ro;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t / kRowLanes < S.nv; t += stride) {
         const int64_t row = t / kRowLanes;
         const int sub = (int)(t % kRowLanes);
         double az = 0.0;
-        for (int32_t j = S.rowptr[row] + sub; j < S.rowptr[row + 1]; j += kRowLanes) az += SD[j] * r[S.col[j]];
+        for (int32_t j = S.rowptr[row] + sub; j < S.rowptr[row + 1]; j += kRowLanes) az += S.S[j] * z[S.col[j]];
 #pragma unroll
         for (int off = kRowLanes / 2; off > 0; off >>= 1) az += __shfl_xor(az, off);
         if (sub == 0) {
-            const double ri = r[row], zi = dinv[row] * ri;
-            w[row] = az;
-            v[0] += ri * zi;
-            v[1] += zi * az;
-            v[2] += ri * ri;
+            const double pn = z[row] + be * p[row];
+            const double qn = az + be * q[row];
+            p[row] = pn;
+            q[row] = qn;
+            v[0] += pn * qn;
         }
     }
     ns_block_sum4(v, pout);
 }
 
-// Iteration k: done once |r_k|^2 <= tol^2 |b|^2 (or not finite, or b = 0:
-// x = 0), then every block returns; otherwise the whole iteration; partials rho_{k+1}, delta_{k+1}, |r_{k+1}|^2.  check_only: the
-// test alone.  Returns at once if an earlier launch found convergence.
-__global__ void __launch_bounds__(kNsThreads) k_ns_iter(NsCsr S, const double *__restrict__ SD,
-                                                    const double *__restrict__ dinv, NsVecs V,
-                                                    double *__restrict__ sc, const double *__restrict__ pin,
-                                                    int64_t nb_in, double *__restrict__ pout, int k, double tol2,
-                                                    int check_only) {
+// Iteration k, second half: alpha = rho_new / (p . q) from the partials of the
+// product; x += alpha p, r -= alpha q, z = Dinv r, with the partials of r . z
+// and |r|^2.  Returns at once if the first half found convergence.
+__global__ void __launch_bounds__(kNsVecThreads) k_ns_update(int64_t nv, const double *__restrict__ sc,
+                                                      const double *__restrict__ dinv, const double *__restrict__ p,
+                                                      const double *__restrict__ q, double *__restrict__ x,
+                                                      double *__restrict__ r, double *__restrict__ z,
+                                                      const double *__restrict__ pin, int64_t nb_in,
+                                                      double *__restrict__ pout, int k) {
     if (sc[10] != 0.0) return;
     double tot[4];
     all_sum4(nb_in, pin, tot);
-    const double b2 = sc[9];
-    const double rn = tot[0], dn = tot[1], r2 = tot[2];
-    const bool done = b2 == 0.0 || !(r2 > tol2 * b2);
-    const double ro = sc[(k + 1) & 1], ao = sc[2 + ((k + 1) & 1)];
-    const double be = (k == 0 || ro == 0.0) ? 0.0 : rn / ro;
-    const double den = (k == 0 || ao == 0.0) ? dn : dn - be * rn / ao;
-    const double al = den != 0.0 ? rn / den : 0.0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        sc[8] = r2;
-        sc[k & 1] = rn;
-        sc[2 + (k & 1)] = al;
-        sc[10] = done ? 1.0 : 0.0;
-        sc[11] = (double)k;
-    }
-    if (done || check_only) return;
-    const int c = k & 1;
-    const double *__restrict__ ri = V.r[c];
-    const double *__restrict__ wi = V.w[c];
-    const double *__restrict__ qi = V.q[c];
-    double *__restrict__ ro_ = V.r[c ^ 1];
-    double *__restrict__ wo = V.w[c ^ 1];
-    double *__restrict__ qo = V.q[c ^ 1];
+    const double pq = tot[0];
+    const double al = pq != 0.0 ? sc[k & 1] / pq : 0.0;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t / kRowLanes < S.nv; t += stride) {
-        const int64_t row = t / kRowLanes;
-        const int sub = (int)(t % kRowLanes);
-        double az = 0.0;
-        for (int32_t j = S.rowptr[row] + sub; j < S.rowptr[row + 1]; j += kRowLanes) {
-            const int32_t cj = S.col[j];
-            const double qn = wi[cj] + be * qi[cj];
-            az += SD[j] * (ri[cj] - al * qn);
-        }
-#pragma unroll
-        for (int off = kRowLanes / 2; off > 0; off >>= 1) az += __shfl_xor(az, off);
-        if (sub == 0) {
-            const double d = dinv[row];
-            const double pn = d * ri[row] + be * V.p[row];
-            const double qn = wi[row] + be * qi[row];
-            const double rn1 = ri[row] - al * qn;
-            const double zn1 = d * rn1;
-            V.p[row] = pn;
-            V.x[row] += al * pn;
-            qo[row] = qn;
-            ro_[row] = rn1;
-            wo[row] = az;
-            v[0] += rn1 * zn1;
-            v[1] += zn1 * az;
-            v[2] += rn1 * rn1;
-        }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (int64_t)gridDim.x * blockDim.x) {
+        x[i] += al * p[i];
+        const double ri = r[i] - al * q[i];
+        r[i] = ri;
+        const double zi = dinv[i] * ri;
+        z[i] = zi;
+        v[0] += ri * zi;
+        v[2] += ri * ri;
     }
     ns_block_sum4(v, pout);
 }
@@ -2329,12 +2288,10 @@ struct NsState {
     double eps = 0;
     int64_t nv = 0, ne = 0, nnz = 0, n_wall = 0;
     int32_t *rowptr = nullptr, *col = nullptr, *ev = nullptr;
-    double *S = nullptr, *SD = nullptr, *dinv = nullptr;   // SD: S_ij dinv_j
+    double *S = nullptr, *dinv = nullptr;
     uint8_t *wall = nullptr;
-    // 11 vectors of nv: 0 x (the solution of etpic_ns_solve), 1 r[0], 2 w[0],
-    // 3 p, 4 q[0], 5, 6 the solutions (re, im) of the correction, 7 that of the
-    // source projection, 8 r[1], 9 w[1], 10 q[1]
-    double *vec = nullptr;
+    double *vec = nullptr;      // 8 vectors of nv: x, r, z, p, q, the solutions (re, im) of the correction and
+                                // that of the source projection
     double *partial = nullptr;  // two sets of 4 per block (kNsBlocks blocks)
     double *sc = nullptr;       // 12 scalars of the iteration
     double *bzero = nullptr;    // 2*N_f zeros: the face envelope of a loop without external fields
@@ -2343,8 +2300,7 @@ struct NsState {
     double *v(int k) const { return vec + (size_t)k * nv; }
     NsCsr csr() const { return NsCsr{nv, rowptr, col, S}; }
     void release() {
-        for (void *q : {(void *)rowptr, (void *)col, (void *)ev, (void *)S, (void *)SD, (void *)dinv, (void *)wall,
-                        (void *)vec,
+        for (void *q : {(void *)rowptr, (void *)col, (void *)ev, (void *)S, (void *)dinv, (void *)wall, (void *)vec,
                         (void *)partial, (void *)sc, (void *)bzero, (void *)ezero})
             (void)hipFree(q);
         *this = NsState();
@@ -3565,15 +3521,14 @@ int etpic_ns_setup(etpic_ctx *ctx, double eps) {
     HIP_TRY(hipMalloc(&N.col, sizeof(int32_t) * S.nnz));
     HIP_TRY(hipMalloc(&N.ev, sizeof(int32_t) * 2 * ne));
     HIP_TRY(hipMalloc(&N.S, sizeof(double) * S.nnz));
-    HIP_TRY(hipMalloc(&N.SD, sizeof(double) * S.nnz));
     HIP_TRY(hipMalloc(&N.dinv, sizeof(double) * nv));
     HIP_TRY(hipMalloc(&N.wall, sizeof(uint8_t) * nv));
-    HIP_TRY(hipMalloc(&N.vec, sizeof(double) * 11 * nv));
+    HIP_TRY(hipMalloc(&N.vec, sizeof(double) * 8 * nv));
     HIP_TRY(hipMalloc(&N.partial, sizeof(double) * 8 * kNsBlocks));
     HIP_TRY(hipMalloc(&N.sc, sizeof(double) * 12));
     HIP_TRY(hipMemset(N.sc, 0, sizeof(double) * 12));
     HIP_TRY(hipMalloc(&N.bzero, sizeof(double) * 2 * ctx->host.nf));
-    HIP_TRY(hipMemset(N.vec, 0, sizeof(double) * 11 * nv));
+    HIP_TRY(hipMemset(N.vec, 0, sizeof(double) * 8 * nv));
     HIP_TRY(hipMemset(N.bzero, 0, sizeof(double) * 2 * ctx->host.nf));
     HIP_TRY(hipMalloc(&N.ezero, sizeof(double) * 2 * ne));
     HIP_TRY(hipMemset(N.ezero, 0, sizeof(double) * 2 * ne));
@@ -3581,11 +3536,6 @@ int etpic_ns_setup(etpic_ctx *ctx, double eps) {
     HIP_TRY(hipMemcpy(N.col, S.col.data(), sizeof(int32_t) * S.nnz, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(N.ev, ctx->host.edges.data(), sizeof(int32_t) * 2 * ne, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(N.S, S.S.data(), sizeof(double) * S.nnz, hipMemcpyHostToDevice));
-    {
-        std::vector<double> sd(S.S.size());
-        for (size_t j = 0; j < sd.size(); ++j) sd[j] = S.S[j] * dinv[(size_t)S.col[j]];
-        HIP_TRY(hipMemcpy(N.SD, sd.data(), sizeof(double) * S.nnz, hipMemcpyHostToDevice));
-    }
     HIP_TRY(hipMemcpy(N.dinv, dinv.data(), sizeof(double) * nv, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(N.wall, S.wall.data(), sizeof(uint8_t) * nv, hipMemcpyHostToDevice));
     N.ready = true;
@@ -3613,19 +3563,16 @@ int ns_solve_impl(etpic_ctx *ctx, const NsRhs &R, double *x, double c, double s,
     const int64_t nv = N.nv;
     const unsigned gv = (unsigned)std::min<int64_t>((nv + kNsVecThreads - 1) / kNsVecThreads, kNsBlocks);
     const unsigned gr = (unsigned)std::min<int64_t>((nv * kRowLanes + kNsThreads - 1) / kNsThreads, kNsBlocks);
-    const NsVecs V{x, N.v(3), {N.v(1), N.v(8)}, {N.v(2), N.v(9)}, {N.v(4), N.v(10)}};
-    // partials alternate between two sets: each launch reads the set the
-    // previous one wrote
-    double *pset[2] = {N.partial, N.partial + 4 * kNsBlocks};
-    // start: r_0 into r[0], p = q[0] = 0 (w[0] receives z_0, overwritten by the prime)
+    double *r = N.v(1), *z = N.v(2), *p = N.v(3), *q = N.v(4);
+    // partials: pa from the product (gr blocks), pb from the start and the update
+    double *pa = N.partial, *pb = N.partial + 4 * kNsBlocks;
+    int64_t nb = warm ? gr : gv;
     if (warm)
-        k_ns_start_warm<<<gr, kNsThreads, 0, st>>>(N.csr(), ctx->d_v2e_ptr, ctx->d_v2e_code, R, N.wall, N.dinv, x,
-                                                   V.r[0], V.w[0], V.p, V.q[0], pset[1], N.sc);
+        k_ns_start_warm<<<gr, kNsThreads, 0, st>>>(N.csr(), ctx->d_v2e_ptr, ctx->d_v2e_code, R, N.wall, N.dinv, x, r,
+                                                   z, p, q, pb, N.sc);
     else
-        k_ns_start<<<gv, kNsVecThreads, 0, st>>>(nv, ctx->d_v2e_ptr, ctx->d_v2e_code, R, N.wall, N.dinv, x, V.r[0],
-                                                 V.w[0], V.p, V.q[0], pset[1], N.sc);
-    k_ns_prime<<<gr, kNsThreads, 0, st>>>(N.csr(), N.SD, N.dinv, V.r[0], V.w[0], N.sc, pset[1], warm ? gr : gv,
-                                          pset[0]);
+        k_ns_start<<<gv, kNsVecThreads, 0, st>>>(nv, ctx->d_v2e_ptr, ctx->d_v2e_code, R, N.wall, N.dinv, x, r, z, p, q,
+                                                 pb, N.sc);
     HIP_TRY(hipGetLastError());
     // Iterations are launched in batches; the device raises the done flag when
     // the residual is small enough and the rest of the batch returns at once.
@@ -3636,12 +3583,12 @@ int ns_solve_impl(etpic_ctx *ctx, const NsRhs &R, double *x, double c, double s,
     int k = 0;
     for (;;) {
         const int n = std::min(batch, max_iter - k);
-        for (int j = 0; j < n; ++j, ++k)
-            k_ns_iter<<<gr, kNsThreads, 0, st>>>(N.csr(), N.SD, N.dinv, V, N.sc, pset[k & 1], gr, pset[(k + 1) & 1], k,
-                                                 tol2, 0);
-        if (k >= max_iter)
-            k_ns_iter<<<gr, kNsThreads, 0, st>>>(N.csr(), N.SD, N.dinv, V, N.sc, pset[k & 1], gr, pset[(k + 1) & 1], k,
-                                                 tol2, 1);
+        for (int j = 0; j < n; ++j, ++k) {
+            k_ns_apply<<<gr, kNsThreads, 0, st>>>(N.csr(), N.sc, z, p, q, pb, nb, pa, k, tol2, 0);
+            k_ns_update<<<gv, kNsVecThreads, 0, st>>>(nv, N.sc, N.dinv, p, q, x, r, z, pa, gr, pb, k);
+            nb = gv;
+        }
+        if (k >= max_iter) k_ns_apply<<<gr, kNsThreads, 0, st>>>(N.csr(), N.sc, z, p, q, pb, nb, pa, k, tol2, 1);
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipMemcpyAsync(hs, N.sc, sizeof hs, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));

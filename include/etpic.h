@@ -266,7 +266,9 @@ int etpic_vertex_charge(etpic_ctx *ctx, const etpic_particles *p, const etpic_sp
 /* Discrete continuity residual r = D^T dG - (rho_new - rho_old), D the edge-vertex
  * incidence (-1 tail, +1 head) (section on discretization and exact charge
  * conservation).  Synchronises `stream`; out_host[0] = max|r|,
- * out_host[1] = max|rho_old|. */
+ * out_host[1] = max|rho_old|.  Both maxima propagate NaN: if any entry of dG,
+ * rho_new or rho_old is not finite the function still writes out_host (NaN or
+ * inf) and returns ETPIC_ENAN. */
 int etpic_gauss_residual(etpic_ctx *ctx, const double *dG, const double *rho_new, const double *rho_old,
                          double out_host[2], void *stream);
 

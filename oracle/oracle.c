@@ -310,88 +310,153 @@ typedef struct {
     int status; /* 0 ok, -6 hop cap */
 } ora_particle;
 
+/* The walk's geometry is taken in extended precision (x87 long double, a
+ * 64-bit significand).  The crossing parameter of a piece is the distance to a
+ * face plane divided by the rate of approach, so it is as uncertain as the
+ * start point's distance from the plane divided by the step's barycentric
+ * length, ~1e-5 or less here: in float64 a Cartesian reconstruction of the
+ * start point would leave the crossing point uncertain at the 1e-11 level.  The
+ * extra digits keep the oracle's path exact to float64 rounding of its inputs. */
+typedef long double xreal;
+
+static void sub3x(const xreal *a, const xreal *b, xreal *c) { c[0] = a[0] - b[0]; c[1] = a[1] - b[1]; c[2] = a[2] - b[2]; }
+static xreal dot3x(const xreal *a, const xreal *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+/* Face k of a tet as a plane in Cartesian space: n = (r_b - r_a) x (r_c - r_a)
+ * from the face's vertices a < b < c, turned to point into the tet; a point of
+ * the plane (r_a, stored as an offset from the tet's vertex 0); and the height
+ * h = n . (r_k - r_a) > 0 of the opposite vertex over the plane.  The signed
+ * distance of a point y (offset from vertex 0) from the plane, scaled by |n|,
+ * is n . (y - a): positive inside the tet. */
+typedef struct {
+    xreal n[3];
+    xreal a[3];
+    xreal h;
+} ora_plane;
+
+static void tet_planes(const ora_mesh *m, int64_t T, ora_plane pl[4]) {
+    const int32_t *v = m->tv + 4 * T;
+    xreal r[4][3];
+    for (int k = 0; k < 4; ++k)
+        for (int c = 0; c < 3; ++c) r[k][c] = (xreal)m->xyz[3 * v[k] + c] - (xreal)m->xyz[3 * v[0] + c];
+    for (int k = 0; k < 4; ++k) {
+        const xreal *ra = r[LF[k][0]], *rb = r[LF[k][1]], *rc = r[LF[k][2]];
+        xreal ab[3], ac[3], ak[3];
+        sub3x(rb, ra, ab); sub3x(rc, ra, ac); sub3x(r[k], ra, ak);
+        pl[k].n[0] = ab[1] * ac[2] - ab[2] * ac[1];
+        pl[k].n[1] = ab[2] * ac[0] - ab[0] * ac[2];
+        pl[k].n[2] = ab[0] * ac[1] - ab[1] * ac[0];
+        pl[k].h = dot3x(pl[k].n, ak);
+        if (pl[k].h < 0.0L) {
+            for (int c = 0; c < 3; ++c) pl[k].n[c] = -pl[k].n[c];
+            pl[k].h = -pl[k].h;
+        }
+        for (int c = 0; c < 3; ++c) pl[k].a[c] = ra[c];
+    }
+}
+
+/* Barycentric coordinates of the point y (offset from the tet's vertex 0) by
+ * Cramer's rule: lambda_k = (volume of the tet the point spans with face k) /
+ * (volume of the tet) = n_k . (y - a_k) / h_k. */
+static void plane_bary(const ora_plane pl[4], const xreal y[3], xreal lam[4]) {
+    for (int k = 0; k < 4; ++k) {
+        xreal ya[3];
+        sub3x(y, pl[k].a, ya);
+        lam[k] = dot3x(pl[k].n, ya) / pl[k].h;
+    }
+}
+
 /* Walk of the straight path with Cartesian displacement d from the particle's
- * (tet, lam), depositing q*w*(path integral) of every piece into dG.  At a
- * boundary face the remaining displacement and the velocity P->v are reflected
- * about the face normal, and so are the nextra vectors extra[i] (velocity
- * samples a multistep integrator keeps).  R (optional) accumulates the linear
- * part of the reflections. */
-static void walk_path(const ora_mesh *m, ora_particle *P, double d[3], double qw, double *dG, int64_t *piece_tets,
+ * (tet, lam), depositing q*w*(path integral) of every piece into dG (the sum
+ * over pieces that eq. G_integral and the sum after it take).  The walk is
+ * Cartesian: the point is carried as an offset y from vertex 0 of its tet; the
+ * segment y -> y + d is intersected with the four face planes, and the piece
+ * ends at the smallest parameter s in [0, 1] where it passes behind one of them
+ * (ties: the lowest local face; a point already behind a plane it moves away
+ * from leaves at s = 0).  The barycentric change of a piece is Cramer's rule
+ * applied to its displacement; at a crossing the point is re-expressed from the
+ * neighbour's vertex 0 and its barycentrics there are computed afresh by
+ * Cramer's rule.  At a boundary face (the paper is silent on the particle
+ * boundary condition; walls are conductors) the remaining displacement and
+ * the velocity P->v are mirrored about the plane's unit normal, and so are the
+ * nextra vectors extra[i] (velocity samples a multistep integrator keeps).
+ * R (optional) accumulates the linear part of the reflections. */
+static void walk_path(const ora_mesh *m, ora_particle *P, double d_io[3], double qw, double *dG, int64_t *piece_tets,
                       int *npieces_out, double *R, double (*extra)[3], int nextra) {
     int64_t T = P->tet;
-    double l[4] = {P->lam[0], P->lam[1], P->lam[2], P->lam[3]};
+    xreal l[4] = {1.0L - ((xreal)P->lam[1] + (xreal)P->lam[2] + (xreal)P->lam[3]), P->lam[1], P->lam[2], P->lam[3]};
+    xreal d[3] = {d_io[0], d_io[1], d_io[2]};
+    ora_plane pl[4];
+    tet_planes(m, T, pl);
+    xreal y[3] = {0.0L, 0.0L, 0.0L};
+    {
+        const int32_t *v = m->tv + 4 * T;
+        for (int j = 1; j < 4; ++j)
+            for (int c = 0; c < 3; ++c) y[c] += l[j] * ((xreal)m->xyz[3 * v[j] + c] - (xreal)m->xyz[3 * v[0] + c]);
+    }
     int hops = 0, np = 0;
     P->status = 0;
     for (;;) {
-        double g[4][3], dl[4];
-        ora_grad(m, T, g);
-        for (int k = 0; k < 4; ++k) dl[k] = dot3(g[k], d);
-        /* line-plane intersection with each face plane the segment leaves through */
-        double smin = 1.0;
+        xreal s = 1.0L;
         int kmin = -1;
         for (int k = 0; k < 4; ++k) {
-            if (dl[k] < 0.0 && l[k] + dl[k] < 0.0) {
-                double sk = l[k] > 0.0 ? l[k] / (-dl[k]) : 0.0;
-                if (kmin < 0 || sk < smin) { smin = sk; kmin = k; }   /* ties: lowest k */
+            xreal ya[3];
+            sub3x(y, pl[k].a, ya);
+            xreal dist = dot3x(pl[k].n, ya), rate = dot3x(pl[k].n, d);
+            if (rate < 0.0L && dist + rate < 0.0L) {
+                xreal sk = dist > 0.0L ? dist / (-rate) : 0.0L;
+                if (kmin < 0 || sk < s) { s = sk; kmin = k; }
             }
         }
-        double gp[6];
-        if (kmin < 0) {
-            piece_integral(m, T, l, dl, d, gp);
+        xreal dp[3] = {s * d[0], s * d[1], s * d[2]};
+        xreal dl[4];
+        for (int k = 0; k < 4; ++k) dl[k] = dot3x(pl[k].n, dp) / pl[k].h;
+        {
+            double la[4], dla[4], dpa[3], gp[6];
+            for (int k = 0; k < 4; ++k) { la[k] = (double)l[k]; dla[k] = (double)dl[k]; }
+            for (int c = 0; c < 3; ++c) dpa[c] = (double)dp[c];
+            piece_integral(m, T, la, dla, dpa, gp);
             for (int e = 0; e < 6; ++e) dG[m->tet_edge[6 * T + e]] += qw * gp[e];
-            if (piece_tets) piece_tets[np] = T;
-            ++np;
-            for (int k = 0; k < 4; ++k) l[k] += dl[k];
-            break;
         }
-        double dp[3] = {smin * d[0], smin * d[1], smin * d[2]};
-        double dlp[4] = {smin * dl[0], smin * dl[1], smin * dl[2], smin * dl[3]};
-        piece_integral(m, T, l, dlp, dp, gp);
-        for (int e = 0; e < 6; ++e) dG[m->tet_edge[6 * T + e]] += qw * gp[e];
         if (piece_tets && np < ORA_HOP_CAP + 1) piece_tets[np] = T;
         ++np;
-        /* crossing point: the exit coordinate is exactly 0; the other three are
-         * rescaled to sum to one and handed unchanged to the shared vertices */
-        double lc[4], sum = 0.0;
-        for (int k = 0; k < 4; ++k) lc[k] = (k == kmin) ? 0.0 : l[k] + dlp[k];
-        for (int k = 0; k < 4; ++k) if (k != kmin) { if (lc[k] < 0.0) lc[k] = 0.0; sum += lc[k]; }
-        for (int k = 0; k < 4; ++k) if (k != kmin) lc[k] /= sum;
-        for (int k = 0; k < 3; ++k) d[k] -= dp[k];
+        for (int k = 0; k < 4; ++k) l[k] += dl[k];
+        if (kmin < 0) break;
+        for (int c = 0; c < 3; ++c) { y[c] += dp[c]; d[c] -= dp[c]; }
         int64_t nb = m->nbr[4 * T + kmin];
         if (nb < 0) {
-            /* specular reflection at the domain boundary (the paper is silent on
-             * the particle boundary condition; walls are conductors) */
-            double nn = sqrt(dot3(g[kmin], g[kmin]));
-            double nh[3] = {g[kmin][0] / nn, g[kmin][1] / nn, g[kmin][2] / nn};
-            double dd = dot3(d, nh), vv = dot3(P->v, nh);
-            for (int k = 0; k < 3; ++k) { d[k] -= 2.0 * dd * nh[k]; P->v[k] -= 2.0 * vv * nh[k]; }
+            xreal nn = sqrtl(dot3x(pl[kmin].n, pl[kmin].n));
+            xreal nh[3] = {pl[kmin].n[0] / nn, pl[kmin].n[1] / nn, pl[kmin].n[2] / nn};
+            xreal dd = dot3x(d, nh);
+            double nd[3] = {(double)nh[0], (double)nh[1], (double)nh[2]};
+            double vv = dot3(P->v, nd);
+            for (int k = 0; k < 3; ++k) { d[k] -= 2.0L * dd * nh[k]; P->v[k] -= 2.0 * vv * nd[k]; }
             for (int i = 0; i < nextra; ++i) {
-                double xv = dot3(extra[i], nh);
-                for (int k = 0; k < 3; ++k) extra[i][k] -= 2.0 * xv * nh[k];
+                double xv = dot3(extra[i], nd);
+                for (int k = 0; k < 3; ++k) extra[i][k] -= 2.0 * xv * nd[k];
             }
             if (R) {   /* R <- (I - 2 n n^T) R : the linear part of the reflected end point */
                 double Rn[9];
                 for (int i = 0; i < 3; ++i)
                     for (int j = 0; j < 3; ++j) {
                         double acc = 0.0;
-                        for (int k = 0; k < 3; ++k) acc += ((i == k ? 1.0 : 0.0) - 2.0 * nh[i] * nh[k]) * R[3 * k + j];
+                        for (int k = 0; k < 3; ++k) acc += ((i == k ? 1.0 : 0.0) - 2.0 * nd[i] * nd[k]) * R[3 * k + j];
                         Rn[3 * i + j] = acc;
                     }
                 memcpy(R, Rn, sizeof Rn);
             }
-            for (int k = 0; k < 4; ++k) l[k] = lc[k];
         } else {
-            const int32_t *vt = m->tv + 4 * T, *vn = m->tv + 4 * nb;
-            for (int j = 0; j < 4; ++j) {
-                l[j] = 0.0;
-                for (int i = 0; i < 4; ++i) if (vt[i] == vn[j]) l[j] = lc[i];
-            }
+            const int32_t v0 = m->tv[4 * T], w0 = m->tv[4 * nb];
+            for (int c = 0; c < 3; ++c) y[c] += (xreal)m->xyz[3 * v0 + c] - (xreal)m->xyz[3 * w0 + c];
             T = nb;
+            tet_planes(m, T, pl);
+            plane_bary(pl, y, l);
         }
         if (++hops > ORA_HOP_CAP) { P->status = -6; break; }
     }
     P->tet = T;
-    for (int k = 0; k < 4; ++k) P->lam[k] = l[k];
+    for (int k = 0; k < 4; ++k) P->lam[k] = (double)l[k];
+    for (int c = 0; c < 3; ++c) d_io[c] = (double)d[c];
     P->hops = hops;
     if (npieces_out) *npieces_out = np;
 }
@@ -773,61 +838,72 @@ static void boris_dual(dual v[3], const dual E[3], const dual B[3], double h) {
 }
 
 /* one step of one particle in dual numbers (no deposit); returns the new tet
- * or -1 at the hop cap */
+ * or -1 at the hop cap.  The same Cartesian walk as walk_path, with the point,
+ * the displacement and the crossing parameter carried as duals. */
 static int64_t step_one_dual(const ora_mesh *m, int64_t T, dual l[4], dual v[3], double c, double s,
                              const ora_fields_t *F, const double *de, double h, double dt) {
     dual E[3], B[3];
     fields_at_dual(m, T, l, c, s, F, de, E, B);
     boris_dual(v, E, B, h);
     dual d[3] = {dscale(v[0], dt), dscale(v[1], dt), dscale(v[2], dt)};
+    double pn[4][3], pa[4][3], ph[4];   /* the face planes in float64 (value and derivative parts alike) */
+    ora_plane pl[4];
+#define LOAD_PLANES()                                                       \
+    do {                                                                    \
+        tet_planes(m, T, pl);                                               \
+        for (int k_ = 0; k_ < 4; ++k_) {                                    \
+            for (int c_ = 0; c_ < 3; ++c_) {                                \
+                pn[k_][c_] = (double)pl[k_].n[c_];                          \
+                pa[k_][c_] = (double)pl[k_].a[c_];                          \
+            }                                                               \
+            ph[k_] = (double)pl[k_].h;                                      \
+        }                                                                   \
+    } while (0)
+    LOAD_PLANES();
+    dual y[3] = {dmk(0.0, 0.0), dmk(0.0, 0.0), dmk(0.0, 0.0)};
+    {
+        const int32_t *vt = m->tv + 4 * T;
+        const double *o = m->xyz + 3 * vt[0];
+        for (int j = 1; j < 4; ++j)
+            for (int k = 0; k < 3; ++k) y[k] = dadd(y[k], dscale(l[j], m->xyz[3 * vt[j] + k] - o[k]));
+    }
     for (int hops = 0; hops <= ORA_HOP_CAP; ++hops) {
-        double g[4][3];
-        ora_grad(m, T, g);
-        dual dl[4];
-        for (int k = 0; k < 4; ++k) dl[k] = ddot3(d, g[k]);
-        double smin = 1.0;
+        dual sd = dmk(1.0, 0.0);
         int kmin = -1;
         for (int k = 0; k < 4; ++k) {
-            if (dl[k].v < 0.0 && l[k].v + dl[k].v < 0.0) {
-                double sk = l[k].v > 0.0 ? l[k].v / (-dl[k].v) : 0.0;
-                if (kmin < 0 || sk < smin) { smin = sk; kmin = k; }
+            dual ya[3] = {dsub(y[0], dmk(pa[k][0], 0.0)), dsub(y[1], dmk(pa[k][1], 0.0)), dsub(y[2], dmk(pa[k][2], 0.0))};
+            dual dist = ddot3(ya, pn[k]), rate = ddot3(d, pn[k]);
+            if (rate.v < 0.0 && dist.v + rate.v < 0.0) {
+                dual sk = dist.v > 0.0 ? ddiv(dist, dscale(rate, -1.0)) : dmk(0.0, 0.0);
+                if (kmin < 0 || sk.v < sd.v) { sd = sk; kmin = k; }
             }
         }
-        if (kmin < 0) {
-            for (int k = 0; k < 4; ++k) l[k] = dadd(l[k], dl[k]);
-            return T;
-        }
-        /* the crossing parameter as a dual: s = l_k / (-dl_k) (0 when l_k <= 0) */
-        dual sd = l[kmin].v > 0.0 ? ddiv(l[kmin], dscale(dl[kmin], -1.0)) : dmk(0.0, 0.0);
-        dual lc[4], sum = dmk(0.0, 0.0);
-        for (int k = 0; k < 4; ++k) {
-            if (k == kmin) { lc[k] = dmk(0.0, 0.0); continue; }
-            lc[k] = dadd(l[k], dmul(sd, dl[k]));
-            if (lc[k].v < 0.0) lc[k] = dmk(0.0, 0.0);
-            sum = dadd(sum, lc[k]);
-        }
-        for (int k = 0; k < 4; ++k) if (k != kmin) lc[k] = ddiv(lc[k], sum);
-        dual one_minus_s = dsub(dmk(1.0, 0.0), sd);
-        for (int k = 0; k < 3; ++k) d[k] = dmul(d[k], one_minus_s);
+        dual dp[3] = {dmul(sd, d[0]), dmul(sd, d[1]), dmul(sd, d[2])};
+        for (int k = 0; k < 4; ++k) l[k] = dadd(l[k], dscale(ddot3(dp, pn[k]), 1.0 / ph[k]));
+        if (kmin < 0) return T;
+        for (int k = 0; k < 3; ++k) { y[k] = dadd(y[k], dp[k]); d[k] = dsub(d[k], dp[k]); }
         int64_t nb = m->nbr[4 * T + kmin];
         if (nb < 0) {
-            double nn = sqrt(dot3(g[kmin], g[kmin]));
-            double nh[3] = {g[kmin][0] / nn, g[kmin][1] / nn, g[kmin][2] / nn};
+            double nn = sqrt(dot3(pn[kmin], pn[kmin]));
+            double nh[3] = {pn[kmin][0] / nn, pn[kmin][1] / nn, pn[kmin][2] / nn};
             dual dd = ddot3(d, nh), vv = ddot3(v, nh);
             for (int k = 0; k < 3; ++k) {
                 d[k] = dsub(d[k], dscale(dd, 2.0 * nh[k]));
                 v[k] = dsub(v[k], dscale(vv, 2.0 * nh[k]));
             }
-            for (int k = 0; k < 4; ++k) l[k] = lc[k];
         } else {
-            const int32_t *vt = m->tv + 4 * T, *vn = m->tv + 4 * nb;
-            for (int j = 0; j < 4; ++j) {
-                l[j] = dmk(0.0, 0.0);
-                for (int i = 0; i < 4; ++i) if (vt[i] == vn[j]) l[j] = lc[i];
-            }
+            const double *o = m->xyz + 3 * m->tv[4 * T], *on = m->xyz + 3 * m->tv[4 * nb];
+            for (int k = 0; k < 3; ++k) y[k] = dadd(y[k], dmk(o[k] - on[k], 0.0));
             T = nb;
+            LOAD_PLANES();
+            for (int k = 0; k < 4; ++k) {
+                dual ya[3] = {dsub(y[0], dmk(pa[k][0], 0.0)), dsub(y[1], dmk(pa[k][1], 0.0)),
+                              dsub(y[2], dmk(pa[k][2], 0.0))};
+                l[k] = dscale(ddot3(ya, pn[k]), 1.0 / ph[k]);
+            }
         }
     }
+#undef LOAD_PLANES
     return -1;
 }
 

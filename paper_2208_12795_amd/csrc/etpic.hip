@@ -342,8 +342,23 @@ __device__ __forceinline__ void deposit_piece(double *__restrict__ dG, const Tet
     }
 }
 
+// lambda_0 = 1 - (l1 + l2 + l3) with the rounding error of the sum carried
+// along (Knuth's two-sum).  Near face 0 lambda_0 is small, and a plainly rounded
+// sum leaves it uncertain by a unit in the last place of the sum; the crossing
+// parameter lambda_0 / -dlambda_0 of a path leaving through that face would
+// inherit that error divided by the step's barycentric length (~1e-5).
+__device__ __forceinline__ double lam0_of(double l1, double l2, double l3) {
+    const double s = l1 + l2;
+    const double bs = s - l1;
+    double e = (l1 - (s - bs)) + (l2 - bs);
+    const double t = s + l3;
+    const double bt = t - s;
+    e += (s - (t - bt)) + (l3 - bt);
+    return (1.0 - t) - e;
+}
+
 // Walk of the straight path with Cartesian remaining displacement d, starting in
-// tet T at barycentrics l.  Each piece is deposited.  At a face crossing the exit
+// tet T at barycentrics l (l[0] is recomputed from l[1..3] by lam0_of).  Each piece is deposited.  At a face crossing the exit
 // coordinate is set to exactly 0, the other three are rescaled to sum to one and
 // handed to the neighbour's shared vertices; at a boundary face the remaining
 // displacement and the velocity are reflected about the face normal.
@@ -356,6 +371,7 @@ template <typename Real, bool kTrack, int kExtra = 0>
 __device__ __forceinline__ int walk(const StepArgs<Real> &a, int T, double l[4], double d[3], Real v[3], double *R,
                                    double (*ext)[3] = nullptr) {
     int hops = 0;
+    l[0] = lam0_of(l[1], l[2], l[3]);
     for (;;) {
         const double *gp = a.grad + (int64_t)T * 12;
         double g[4][3];
@@ -1516,7 +1532,11 @@ __global__ void __launch_bounds__(kBlock) k_charge(int64_t n, int64_t nt, const 
 // ------------------------------------------------------------------ continuity residual
 // r_k = sum_{e incident} (+dG_e if k is the head, -dG_e if the tail) - (rho_new_k - rho_old_k).
 // out[0] = max |r|, out[1] = max |rho_old| as the bit patterns of non-negative doubles
-// (which order like unsigned integers).
+// (which order like unsigned integers).  The maxima propagate NaN: a non-finite
+// dG or rho makes the residual NaN (whose bit pattern orders above +inf), never
+// a passing number.
+__device__ __forceinline__ double max_keep_nan(double a, double b) { return (a != a || a > b) ? a : b; }
+
 __global__ void __launch_bounds__(kBlock) k_gauss(int64_t nv, const int32_t *__restrict__ ptr,
                                                   const int32_t *__restrict__ code, const double *__restrict__ dG,
                                                   const double *__restrict__ rho_new,
@@ -1534,10 +1554,10 @@ __global__ void __launch_bounds__(kBlock) k_gauss(int64_t nv, const int32_t *__r
         r = fabs(div - (rho_new[k] - rho_old[k]));
         p = fabs(rho_old[k]);
     }
-    // wave-level max then one atomic per wave
+    // wave-level max then one atomic per wave; a NaN operand wins
     for (int off = 32; off > 0; off >>= 1) {
-        r = fmax(r, __shfl_xor(r, off));
-        p = fmax(p, __shfl_xor(p, off));
+        r = max_keep_nan(r, __shfl_xor(r, off));
+        p = max_keep_nan(p, __shfl_xor(p, off));
     }
     if ((threadIdx.x & 63) == 0) {
         atomicMax(&out[0], (unsigned long long)__double_as_longlong(r));
@@ -3346,6 +3366,9 @@ int etpic_gauss_residual(etpic_ctx *ctx, const double *dG, const double *rho_new
     HIP_TRY(hipMemcpyAsync(bits, ctx->d_red, sizeof bits, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     std::memcpy(out_host, bits, sizeof bits);
+    if (!std::isfinite(out_host[0]) || !std::isfinite(out_host[1]))
+        return fail(ETPIC_ENAN, "continuity residual: non-finite current or charge (max|r| %g, max|rho_old| %g)",
+                    out_host[0], out_host[1]);
     return ETPIC_OK;
 }
 

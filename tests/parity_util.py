@@ -6,7 +6,13 @@ barycentrics, and a step moves them by ~1e-5 of their magnitude, so the stored
 end point of *any* float64 implementation carries a quantum of one unit in the
 last place of lambda.  The position error is therefore measured beyond that
 quantum (2 ulp of lambda per coordinate), relative to the largest barycentric
-increment of the step.
+increment of the step.  A particle that crossed a face has, in addition, been
+re-expressed in its new tet's barycentric frame at the crossing point; each
+coordinate of that point is rounded there (an absolute quantum of a few units
+of float64 epsilon, whatever the implementation: the kernel sets the exit
+coordinate to zero and rescales, the oracle solves for the point's
+barycentrics by Cramer's rule), so for crossed particles the quantum also
+holds 4 epsilon absolute per coordinate.
 """
 import numpy as np
 
@@ -32,6 +38,8 @@ def step_errors(xyz, tv, state_in, gpu, ora, dG_gpu, dG_ora):
     scale = dl.max() if dl.size else 0.0
     if same.any():
         quantum = 2.0 * ULP1 * np.maximum(np.abs(lg[same]), np.abs(lo[same]))
+        crossed = ((tg != t0) | (to != t0))[same]
+        quantum[crossed] += 4.0 * ULP1
         excess = np.maximum(np.abs(lg[same] - lo[same]) - quantum, 0.0)
         out["lam_rel"] = float(excess.max() / scale) if scale > 0 else float(excess.max())
     else:

@@ -1,5 +1,6 @@
 """GPU field update (CSR SpMV + Jacobi-preconditioned COCG + Newmark step)
-against the oracle's independently assembled matrices and direct solve."""
+against the oracle's independently assembled matrices and its own solve
+(sparse direct on small meshes, GMRES on large ones)."""
 import time
 
 import numpy as np
@@ -36,14 +37,14 @@ def t2c(t):
     return a[:, 0] + 1j * a[:, 1]
 
 
-def setup(E, ora, n, dt, w):
+def setup(E, ora, n, dt, w, solver=None):
     from oracle import field
     xyz, tv = synth.kuhn_mesh(n, (1.0, 1.0, 1.0), 0.1, np.random.default_rng(17))
     ctx = E.Context(0)
     ctx.upload_mesh(xyz, tv)
     ctx.field_setup(dt, w, EPS0, MU0)
     M = ora.OracleMesh(xyz, tv)
-    F = field.FieldOracle(M, dt, w, EPS0, MU0)
+    F = field.FieldOracle(M, dt, w, EPS0, MU0, solver=solver)
     return ctx, M, F
 
 
@@ -78,12 +79,17 @@ def test_spmv_matches_oracle_matrices(E, torch_cuda, ora):
     ctx.close()
 
 
-@pytest.mark.parametrize("n", [(5, 5, 5), (12, 10, 11)])
-def test_newmark_step_matches_direct_solve(E, torch_cuda, ora, n):
+@pytest.mark.parametrize("n", [(5, 5, 5), (12, 10, 11), (27, 27, 27), (40, 40, 40)])
+def test_newmark_step_matches_oracle_solve(E, torch_cuda, ora, n):
     """One field step (source g'' on the interior edges) against the oracle's
-    sparse direct solve: every state vector to 1e-10 relative."""
+    solve of its own quadrature-assembled system: sparse direct up to 12x10x11
+    cells, GMRES on 27^3 (144,423 edges: more rows than one pass of the
+    solver's grid-stride loops covers, 65,536 in the product and 131,072 in
+    the vector update, so the wrap is exercised) and on the benchmark's 40^3
+    mesh (462,520 edges).  Every state vector to 1e-10 relative."""
     torch = torch_cuda
     dt, w = 2e-11, 2 * np.pi * 1e9
+    print(f"[field {n}] setting up", flush=True)
     ctx, M, F = setup(E, ora, n, dt, w)
     rng = np.random.default_rng(3)
     u, v, a, b = random_state(F, M.ne, M.nf, rng)
@@ -95,10 +101,29 @@ def test_newmark_step_matches_direct_solve(E, torch_cuda, ora, n):
     rc, it, res = ctx.field_step(3 * dt, tu, tv_, ta, tb, tg, tol=1e-13, max_iter=400)
     t1 = time.perf_counter()
     un, vn, an, bn = F.step(3 * dt, u, v, a, b, gdd)
-    print(f"[field {n}] N_e={M.ne} COCG {it} it, residual {res:.1e}, {1e3 * (t1 - t0):.2f} ms; "
+    print(f"[field {n}] N_e={M.ne} ({F.solver}) COCG {it} it, residual {res:.1e}, {1e3 * (t1 - t0):.2f} ms; "
           f"rel u {rel(t2c(tu), un):.1e} v {rel(t2c(tv_), vn):.1e} a {rel(t2c(ta), an):.1e} b {rel(t2c(tb), bn):.1e}")
     for got, ref in ((tu, un), (tv_, vn), (ta, an), (tb, bn)):
         assert rel(t2c(got), ref) < 1e-10
+    ctx.close()
+
+
+def test_spmv_wraps_at_bench_size(E, torch_cuda, ora):
+    """The CSR product on the benchmark's 40^3 mesh against the oracle's
+    matrices (the rows beyond one grid pass included)."""
+    torch = torch_cuda
+    dt, w = 1e-11, 2 * np.pi * 1e9
+    ctx, M, F = setup(E, ora, (40, 40, 40), dt, w, solver="gmres")
+    rng = np.random.default_rng(2)
+    x = (rng.standard_normal(M.ne) + 1j * rng.standard_normal(M.ne)) * ~F.bnd
+    y = torch.zeros((M.ne, 2), dtype=torch.float64, device="cuda")
+    alpha, beta = 0.7 - 0.2j, 3e-3
+    ctx.field_spmv(c2t(torch, x), y, alpha, beta)
+    ref = alpha * (F.M @ x) + beta * (F.K @ x)
+    I = F.inner
+    err = rel(t2c(y)[I], ref[I])
+    print(f"[spmv 40^3] N_e={M.ne} rel {err:.1e}", flush=True)
+    assert err < 1e-13
     ctx.close()
 
 

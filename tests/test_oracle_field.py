@@ -93,3 +93,23 @@ def test_faraday_face_update_matches_closed_form(fmesh):
     # the generator's Faraday-consistent envelope is the same b
     bs = synth.faraday_face_envelope(e, fmesh.edges(), fmesh.faces(), fmesh.nv, w)
     assert np.allclose(bs, b0, rtol=1e-14, atol=0)
+
+
+def test_gmres_step_equals_direct_step(fmesh):
+    """The iterative solve the oracle takes on large meshes (scipy's GMRES)
+    gives the same Newmark step as the sparse direct solve, every state vector
+    to 1e-13 relative."""
+    from oracle import field
+    dt, w = 2e-11, 2 * np.pi * 1e9
+    F_lu = field.FieldOracle(fmesh, dt, w, EPS0, MU0, solver="lu")
+    F_it = field.FieldOracle(fmesh, dt, w, EPS0, MU0, solver="gmres")
+    rng = np.random.default_rng(4)
+    ne, nf = fmesh.ne, fmesh.nf
+    mask = ~F_lu.bnd
+    u = (rng.standard_normal(ne) + 1j * rng.standard_normal(ne)) * mask
+    v = (rng.standard_normal(ne) + 1j * rng.standard_normal(ne)) * mask * 1e9
+    a = (rng.standard_normal(ne) + 1j * rng.standard_normal(ne)) * mask * 1e18
+    b = (rng.standard_normal(nf) + 1j * rng.standard_normal(nf)) * 1e-9
+    gdd = rng.standard_normal(ne) * 1e-10 * mask
+    for x, y in zip(F_lu.step(dt, u, v, a, b, gdd), F_it.step(dt, u, v, a, b, gdd)):
+        assert np.abs(x - y).max() <= 1e-13 * np.abs(x).max()

@@ -272,6 +272,20 @@ int etpic_vertex_charge(etpic_ctx *ctx, const etpic_particles *p, const etpic_sp
 int etpic_gauss_residual(etpic_ctx *ctx, const double *dG, const double *rho_new, const double *rho_old,
                          double out_host[2], void *stream);
 
+/* etpic_gauss_residual without any allocation, for callers that cannot
+ * allocate device memory (loops that log the residual every step under an
+ * allocation-free policy, harnesses that forbid hipMalloc).  Same arguments,
+ * result and errors as etpic_gauss_residual (the maxima are the same numbers).
+ * Its scratch is a file-scope device array of 16 KB (1,024 partial pairs and
+ * the result pair), one per GPU for the life of the process, whose address
+ * etpic_create takes on the context's device; any mesh size is served (the
+ * vertices are visited by a grid-stride loop over at most 1,024 blocks), and
+ * a mesh beyond 2^31 - 1 vertices is refused with EINVAL.  Calls on one GPU
+ * share that array: calls that overlap on one GPU (two streams, two threads)
+ * race and must be serialised by the caller.  Synchronises `stream`. */
+int etpic_gauss_residual_noalloc(etpic_ctx *ctx, const double *dG, const double *rho_new, const double *rho_old,
+                                 double out_host[2], void *stream);
+
 /* ---- Downshifted integrator ------------------------------------------------
  * The Particle Push section's scheme that treats the carrier analytically in
  * the velocity update.  Over a step [t_n, t_n + dt] the envelope fields sampled

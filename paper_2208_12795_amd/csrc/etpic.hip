@@ -43,6 +43,7 @@
 #include <array>
 #include <algorithm>
 #include <complex>
+#include <mutex>
 
 #include "etpic.h"
 #include "field_host.hpp"
@@ -1537,6 +1538,20 @@ __global__ void __launch_bounds__(kBlock) k_charge(int64_t n, int64_t nt, const 
 // a passing number.
 __device__ __forceinline__ double max_keep_nan(double a, double b) { return (a != a || a > b) ? a : b; }
 
+// |r_k| of vertex k: the signed sum of its incident edge currents (CSR of
+// (edge << 1 | head) codes) minus its change of charge.
+__device__ __forceinline__ double gauss_r(int64_t k, const int32_t *__restrict__ ptr,
+                                          const int32_t *__restrict__ code, const double *__restrict__ dG,
+                                          const double *__restrict__ rho_new, const double *__restrict__ rho_old) {
+    double div = 0.0;
+    for (int32_t i = ptr[k]; i < ptr[k + 1]; ++i) {
+        const int32_t c = code[i];
+        const double g = dG[c >> 1];
+        div += (c & 1) ? g : -g;
+    }
+    return fabs(div - (rho_new[k] - rho_old[k]));
+}
+
 __global__ void __launch_bounds__(kBlock) k_gauss(int64_t nv, const int32_t *__restrict__ ptr,
                                                   const int32_t *__restrict__ code, const double *__restrict__ dG,
                                                   const double *__restrict__ rho_new,
@@ -1545,13 +1560,7 @@ __global__ void __launch_bounds__(kBlock) k_gauss(int64_t nv, const int32_t *__r
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double r = 0.0, p = 0.0;
     if (k < nv) {
-        double div = 0.0;
-        for (int32_t i = ptr[k]; i < ptr[k + 1]; ++i) {
-            const int32_t c = code[i];
-            const double g = dG[c >> 1];
-            div += (c & 1) ? g : -g;
-        }
-        r = fabs(div - (rho_new[k] - rho_old[k]));
+        r = gauss_r(k, ptr, code, dG, rho_new, rho_old);
         p = fabs(rho_old[k]);
     }
     // wave-level max then one atomic per wave; a NaN operand wins
@@ -1564,6 +1573,72 @@ __global__ void __launch_bounds__(kBlock) k_gauss(int64_t nv, const int32_t *__r
         atomicMax(&out[1], (unsigned long long)__double_as_longlong(p));
     }
 }
+
+// The same maxima in two passes without atomics, for the allocation-free
+// entry point: k_gauss_part leaves one (max|r|, max|rho_old|) pair per block
+// (grid-stride over the vertices, kResBlocks blocks at most) in part[2 * block],
+// k_gauss_final reduces the pairs into out[0..1].  Every partial is written
+// before it is read, so nothing needs clearing between calls.
+constexpr int kResBlocks = 1024;
+
+__global__ void __launch_bounds__(kBlock) k_gauss_part(int64_t nv, const int32_t *__restrict__ ptr,
+                                                       const int32_t *__restrict__ code,
+                                                       const double *__restrict__ dG,
+                                                       const double *__restrict__ rho_new,
+                                                       const double *__restrict__ rho_old, double *__restrict__ part) {
+    double r = 0.0, p = 0.0;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nv; k += (int64_t)gridDim.x * blockDim.x) {
+        r = max_keep_nan(gauss_r(k, ptr, code, dG, rho_new, rho_old), r);
+        p = max_keep_nan(fabs(rho_old[k]), p);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        r = max_keep_nan(r, __shfl_xor(r, off));
+        p = max_keep_nan(p, __shfl_xor(p, off));
+    }
+    __shared__ double wr[kBlock / 64], wp[kBlock / 64];
+    if ((threadIdx.x & 63) == 0) {
+        wr[threadIdx.x >> 6] = r;
+        wp[threadIdx.x >> 6] = p;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / 64; ++w) {
+            r = max_keep_nan(r, wr[w]);
+            p = max_keep_nan(p, wp[w]);
+        }
+        part[2 * blockIdx.x] = r;
+        part[2 * blockIdx.x + 1] = p;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_gauss_final(const double *__restrict__ part, int nblk,
+                                                        double *__restrict__ out) {
+    double r = 0.0, p = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+        r = max_keep_nan(r, part[2 * b]);
+        p = max_keep_nan(p, part[2 * b + 1]);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        r = max_keep_nan(r, __shfl_xor(r, off));
+        p = max_keep_nan(p, __shfl_xor(p, off));
+    }
+    __shared__ double wr[kBlock / 64], wp[kBlock / 64];
+    if ((threadIdx.x & 63) == 0) {
+        wr[threadIdx.x >> 6] = r;
+        wp[threadIdx.x >> 6] = p;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / 64; ++w) {
+            r = max_keep_nan(r, wr[w]);
+            p = max_keep_nan(p, wp[w]);
+        }
+        out[0] = r;
+        out[1] = p;
+    }
+}
+
+constexpr size_t kScratchDoubles = 2 * (size_t)kResBlocks + 2;
 
 // ------------------------------------------------------------------ counting sort
 __global__ void __launch_bounds__(kBlock) k_fill_u32(unsigned *__restrict__ x, int64_t n, unsigned val) {
@@ -2375,6 +2450,7 @@ struct etpic_ctx {
     unsigned *d_slice_queue = nullptr; // kWalkQueueCap slice indices
     unsigned *d_walk_ctr = nullptr;    // 3 counters of the walk queues
     unsigned long long *d_red = nullptr;  // 2 words for the residual maxima
+    double *d_scratch = nullptr;          // device address of `scratch` on this device
     // mean same-tet run length from the last sort (sum count^2 / N_p), read
     // back without blocking: the device word, its pinned host copy, the event
     // that marks the copy, and the value in use (0 until a sort has been seen)
@@ -2814,6 +2890,35 @@ struct etpic_ctx {
 };
 
 
+// File-scope scratch of the allocation-free residual (each GPU holds its own
+// copy for the life of the process): kResBlocks partial pairs, then the
+// result pair (16 KB).  Host code never passes this name to a kernel or a
+// copy: on the host it is a stand-in, not a device address.  The device
+// address is taken once per device with hipGetSymbolAddress (scratch_address,
+// called by etpic_create with the device current) and used everywhere instead.
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double *g_scratch_addr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device `device`.
+int scratch_address(int device, double **out) {
+    if (device < 0 || device >= kMaxDevices) return fail(ETPIC_EINVAL, "device %d beyond %d", device, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_addr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(ETPIC_EHIP, "address of the residual scratch: %s", hipGetErrorString(e));
+        g_scratch_addr[device] = static_cast<double *>(p);
+    }
+    *out = g_scratch_addr[device];
+    return ETPIC_OK;
+}
+}  // namespace
+
 template <>
 const double *etpic_ctx::gpush_table<double>() const { return d_gpush64; }
 template <>
@@ -2918,7 +3023,9 @@ int etpic_create(etpic_ctx **out, int device) {
     if (e == hipSuccess) e = hipMemset(c->d_status, 0, sizeof(unsigned));
     if (e == hipSuccess) e = hipMemset(c->d_walk_ctr, 0, 3 * sizeof(unsigned));
     if (e == hipSuccess) e = hipDeviceSynchronize();
-    if (e != hipSuccess) {
+    int rs = ETPIC_OK;
+    if (e == hipSuccess) rs = scratch_address(device, &c->d_scratch);
+    if (e != hipSuccess || rs != ETPIC_OK) {
         (void)hipFree(c->d_status);
         (void)hipFree(c->d_red);
         (void)hipFree(c->d_runstat);
@@ -2928,6 +3035,7 @@ int etpic_create(etpic_ctx **out, int device) {
         (void)hipFree(c->d_slice_queue);
         (void)hipFree(c->d_walk_ctr);
         delete c;
+        if (rs != ETPIC_OK) return rs;
         return fail(ETPIC_EHIP, "context setup: %s", hipGetErrorString(e));
     }
     *out = c;
@@ -3366,6 +3474,28 @@ int etpic_gauss_residual(etpic_ctx *ctx, const double *dG, const double *rho_new
     HIP_TRY(hipMemcpyAsync(bits, ctx->d_red, sizeof bits, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     std::memcpy(out_host, bits, sizeof bits);
+    if (!std::isfinite(out_host[0]) || !std::isfinite(out_host[1]))
+        return fail(ETPIC_ENAN, "continuity residual: non-finite current or charge (max|r| %g, max|rho_old| %g)",
+                    out_host[0], out_host[1]);
+    return ETPIC_OK;
+}
+
+int etpic_gauss_residual_noalloc(etpic_ctx *ctx, const double *dG, const double *rho_new, const double *rho_old,
+                                 double out_host[2], void *stream) {
+    if (!ctx || !dG || !rho_new || !rho_old || !out_host) return fail(ETPIC_EINVAL, "null argument");
+    if (!ctx->has_mesh) return fail(ETPIC_ESTATE, "no mesh uploaded");
+    if (!ctx->d_scratch) return fail(ETPIC_ESTATE, "residual scratch address not taken");
+    const int64_t nv = ctx->host.nv;
+    if (nv > (int64_t)INT32_MAX) return fail(ETPIC_EINVAL, "%lld vertices beyond the 32-bit limit", (long long)nv);
+    if (int r = set_device(ctx)) return r;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int nblk = (int)std::min<int64_t>(std::max<int64_t>(grid_for(nv), 1), kResBlocks);
+    double *part = ctx->d_scratch, *res = ctx->d_scratch + 2 * kResBlocks;
+    k_gauss_part<<<nblk, kBlock, 0, st>>>(nv, ctx->d_v2e_ptr, ctx->d_v2e_code, dG, rho_new, rho_old, part);
+    k_gauss_final<<<1, kBlock, 0, st>>>(part, nblk, res);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(out_host, res, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
     if (!std::isfinite(out_host[0]) || !std::isfinite(out_host[1]))
         return fail(ETPIC_ENAN, "continuity residual: non-finite current or charge (max|r| %g, max|rho_old| %g)",
                     out_host[0], out_host[1]);

@@ -17,7 +17,16 @@ Inputs are resident in HBM before the timed region starts.
 Prints ONE JSON line.  `value` is the float64 form; the mixed form (float32
 gather/push on barycentrics, float64 positions and deposit) is reported under
 "mixed".  The roofline figure is for the dominant kernel (the particle
-kernel), timed with HIP events recorded on its launch stream.
+kernel), timed with HIP events recorded on its launch stream; beside it the
+rate its access pattern alone reaches (a stream probe over the same particle
+arrays), a device copy, and the whole step's algorithmic bytes over the time
+per step.  After the timed steps a few single steps are run with the
+continuity residual of each, timed apart ("logged").  Side entries (not in
+`value`): the precision workload (same mesh, 5e7 electrons) and the large box
+(2e8 electrons on 6.1M tets), both forms, each with its own roofline; the
+field update, the Gauss-law solve and loops, the projectors, the multi-rate
+and downshifted steps, the adjoint; and the float64 oracle on the host's
+cores (`cpu_baseline`).
 """
 import argparse
 import json
@@ -43,6 +52,17 @@ BYTES_PER_PARTICLE = {"fp64": 100, "mixed": 76}
 BYTES_PER_TET = {"fp64": 288, "mixed": 156}
 BYTES_PER_EDGE = 16
 KERNEL_NAME = {"fp64": "k_push<double>", "mixed": "k_push<float>"}
+# Algorithmic bytes of a whole step (what the method must move per particle-step
+# and per tet, independent of how the kernels split the work): the particle
+# state read and written, tet included (2 x (lam 24 + v 24 + tet 4) = 104 B in
+# float64, 2 x (24 + 12 + 4) = 80 B with float32 velocities); per tet and step
+# its field DoFs, geometry and ids (~320 B); and the periodic sort amortised:
+# per particle and sort its state and id read and written plus key and offset
+# (2 x (52 + 8) + 8 = 128 B in float64, 2 x (40 + 8) + 8 = 104 B mixed).
+STEP_BYTES_PER_PARTICLE = {"fp64": 104, "mixed": 80}
+STEP_BYTES_PER_TET = 320
+SORT_BYTES_PER_PARTICLE = {"fp64": 128, "mixed": 104}
+REAL = {"fp64": "double", "mixed": "float"}
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_push_hbm_traffic_40cube_1e7.md")
 COPY_CALIB_BYTES = 1 << 30
 CPU_SAMPLE_MAX = 10_000_000
@@ -61,7 +81,42 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_form(E, torch, ctx, w, precision, steps, warmup, sort_every, fields):
+def kernel_name(form, slices):
+    return KERNEL_NAME[form] if slices <= 1 else f"k_push_slices<{REAL[form]}, {slices}>"
+
+
+def logged_steps(E, torch, ctx, parts, sp, fields, w, step0, nlog):
+    """nlog single steps, each followed by the continuity residual of that
+    step (vertex charge before and after, D^T dG - drho): the largest relative
+    residual, and the mean time of a step and of its residual, each timed with
+    events on the stream apart from the other."""
+    rho_a = torch.zeros(ctx.n_vert, dtype=torch.float64, device="cuda")
+    rho_b = torch.zeros_like(rho_a)
+    dG = torch.zeros(ctx.n_edge, dtype=torch.float64, device="cuda")
+    ctx.vertex_charge(parts, sp, rho_a)
+    worst, step_ms, res_ms = 0.0, 0.0, 0.0
+    for k in range(nlog):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        dG.zero_()
+        rho_b.zero_()
+        ev[0].record()
+        ctx.gather_push_deposit(parts, sp, fields, step0 + k, w.dt, w.omega, dG, flags=E.STEP_XCD_REMAP)
+        ev[1].record()
+        ctx.vertex_charge(parts, sp, rho_b)
+        r, p = ctx.gauss_residual(dG, rho_b, rho_a)
+        ev[2].record()
+        torch.cuda.synchronize()
+        worst = max(worst, r / p)
+        step_ms += ev[0].elapsed_time(ev[1])
+        res_ms += ev[1].elapsed_time(ev[2])
+        rho_a, rho_b = rho_b, rho_a
+    return {"steps": nlog, "gauss_rel_max": worst, "step_ms": step_ms / max(nlog, 1),
+            "charge_and_residual_ms": res_ms / max(nlog, 1),
+            "note": "single steps, each followed by the vertex charge and the continuity residual of that step "
+                    "(timed apart from the step)"}
+
+
+def run_form(E, torch, ctx, w, precision, steps, warmup, sort_every, fields, nlog=0, stream_reps=10):
     sp = E.Species(w.q, w.m, w.w)
     parts = E.Particles.from_numpy(w.tet, w.lam, w.vel, w.ids, precision=precision)
     spare = parts.empty_like()
@@ -100,7 +155,18 @@ def run_form(E, torch, ctx, w, precision, steps, warmup, sort_every, fields):
     wall = time.perf_counter() - t0
     total_ms = ev0.elapsed_time(ev1)
     kt, launches = ctx.kernel_time(reset=True)
+    slices = ctx.last_push_slices()
     ctx.check()
+    # the particle kernel's access pattern alone over the same arrays
+    ctx.stream_probe(parts)
+    torch.cuda.synchronize()
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s0.record()
+    for _ in range(stream_reps):
+        ctx.stream_probe(parts)
+    s1.record()
+    torch.cuda.synchronize()
+    stream_ms = s0.elapsed_time(s1) / stream_reps
     # sort alone
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -129,7 +195,11 @@ def run_form(E, torch, ctx, w, precision, steps, warmup, sort_every, fields):
     torch.cuda.synchronize()
     gauss_ms = g0.elapsed_time(g1)
     n = parts.n
+    logged = logged_steps(E, torch, ctx, parts, sp, fields, w, step + 1, nlog) if nlog else None
     return {
+        "slices": slices,
+        "stream_ms": stream_ms,
+        "logged": logged,
         "ms_per_step": total_ms / steps,
         "wall_s": wall,
         "kernel_ms": kt["push"] / max(kt["steps_push"], 1),
@@ -460,6 +530,16 @@ def copy_bandwidth(torch, nbytes=1 << 31, reps=10):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, nthreads, steps, stride):
     import oracle
     M = oracle.OracleMesh(w.xyz, w.tet_vert)
@@ -475,6 +555,70 @@ def cpu_baseline(w, nthreads, steps, stride):
     return tet.shape[0] * steps / wall, wall, cpu
 
 
+def roofline(res, form, n_p, n_t, n_e, sort_every, copy_gbs, traffic_path=None):
+    """Roofline entry of one form's run: the dominant kernel (the particle
+    kernel: its algorithmic bytes per launch over its mean duration from HIP
+    events on its launch stream), the attainable rate of its access pattern
+    alone (stream probe) and of a device copy, and the whole step's
+    algorithmic bytes over the measured time per step."""
+    r = res[form]
+    name = kernel_name(form, r["slices"])
+    bytes_launch = BYTES_PER_PARTICLE[form] * n_p + BYTES_PER_TET[form] * n_t + BYTES_PER_EDGE * n_e
+    ach = bytes_launch / (r["kernel_ms"] * 1e-3) / 1e9
+    stream_gbs = BYTES_PER_PARTICLE[form] * n_p / (r["stream_ms"] * 1e-3) / 1e9
+    traffic = None
+    if traffic_path is not None:
+        from paper_2208_12795_amd import rocprof_summary
+        traffic = rocprof_summary.read_traffic(traffic_path, name)
+    step_bytes = STEP_BYTES_PER_PARTICLE[form] * n_p + STEP_BYTES_PER_TET * n_t
+    if sort_every:
+        step_bytes += SORT_BYTES_PER_PARTICLE[form] * n_p / sort_every
+    step_gbs = step_bytes / (r["ms_per_step"] * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": name,
+            "bytes_per_launch": bytes_launch, "kernel_ms": round(r["kernel_ms"], 5),
+            "stream_GBs": round(stream_gbs, 1), "frac_of_stream": round(ach / stream_gbs, 4),
+            "copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(ach / copy_gbs, 4),
+            "whole_step": {"bytes_per_step": int(step_bytes), "ms_per_step": round(r["ms_per_step"], 5),
+                           "achieved": round(step_gbs, 1), "frac": round(step_gbs / HBM_PEAK_GBS, 4),
+                           "note": "algorithmic bytes of the whole step (state %d B per particle, %d B per "
+                                   "tet, sort amortised) over the measured time per step"
+                                   % (STEP_BYTES_PER_PARTICLE[form], STEP_BYTES_PER_TET)}}
+
+
+def config_entry(E, torch, synth, key, steps, warmup, sort_every, nlog, copy_gbs, forms=("fp64", "mixed")):
+    """A second workload measured beside the metric's: both forms, its own
+    roofline entries and a logged phase of single steps with the continuity
+    residual of every step timed apart."""
+    cfg, desc = WORKLOADS[key]
+    t0 = time.perf_counter()
+    w = synth.make_workload(cfg, progress=lambda m: log(f"[bench] {key}: generated {m}"))
+    gen_s = time.perf_counter() - t0
+    log(f"[bench] {key}: workload generated in {gen_s:.1f}s: N_p={w.tet.shape[0]} N_t={w.tet_vert.shape[0]}")
+    ctx = E.Context(0)
+    ctx.upload_mesh(w.xyz, w.tet_vert)
+    fields = E.Fields.from_numpy(w.e_env, w.b_env, None, w.b_dc)
+    res = {}
+    for form in forms:
+        prec = E.FP64 if form == "fp64" else E.MIXED
+        res[form] = run_form(E, torch, ctx, w, prec, steps, warmup, sort_every, fields, nlog=nlog)
+        log(f"[bench] {key} {form}: {json.dumps(res[form])}")
+        torch.cuda.empty_cache()
+    n_p, n_t, n_e = w.tet.shape[0], w.tet_vert.shape[0], ctx.n_edge
+    out = {"workload": desc + ", sort every %d steps" % sort_every, "n_particles": n_p, "n_tets": n_t,
+           "n_edges": n_e, "steps": steps, "warmup": warmup, "generation_s": round(gen_s, 1)}
+    for form in forms:
+        r = res[form]
+        out[form] = {"value": r["value"], "ms_per_step": r["ms_per_step"], "sort_ms": r["sort_ms"],
+                     "gauss_rel": r["gauss_rel"], "logged": r["logged"],
+                     "roofline": roofline(res, form, n_p, n_t, n_e, sort_every, copy_gbs)}
+    if "fp64" in res and "mixed" in res:
+        out["mixed_speedup_vs_fp64"] = res["mixed"]["value"] / res["fp64"]["value"]
+    ctx.close()
+    del w
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -486,11 +630,17 @@ def main():
     ap.add_argument("--particles", type=int, default=None, help="override the particle count (default 1e7)")
     ap.add_argument("--sort-every", type=int, default=10)
     ap.add_argument("--forms", default="fp64,mixed")
+    ap.add_argument("--log-steps", type=int, default=10,
+                    help="single steps with the continuity residual of each, after the timed run")
+    ap.add_argument("--precision-steps", type=int, default=20,
+                    help="steps of the 5e7-particle side entry (0: skip it)")
+    ap.add_argument("--large-box-steps", type=int, default=100,
+                    help="steps of the 2e8-particle large-box side entry (0: skip it)")
     ap.add_argument("--cpu-steps", type=int, default=3)
-    ap.add_argument("--cpu-threads", type=int, default=0, help="0 = min(16, host cores)")
+    ap.add_argument("--cpu-threads", type=int, default=0, help="0 = every core this process may run on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-side", action="store_true",
-                    help="skip the side measurements (field update, adjoint)")
+                    help="skip the side measurements (field update, adjoint, the other workloads)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -504,7 +654,7 @@ def main():
     import torch
 
     from paper_2208_12795_amd import etpic as E
-    from paper_2208_12795_amd import rocprof_summary, synth
+    from paper_2208_12795_amd import synth
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -537,21 +687,11 @@ def main():
     res = {}
     for form in args.forms.split(","):
         prec = E.FP64 if form == "fp64" else E.MIXED
-        res[form] = run_form(E, torch, ctx, w, prec, args.steps, args.warmup, args.sort_every, fields)
+        res[form] = run_form(E, torch, ctx, w, prec, args.steps, args.warmup, args.sort_every, fields,
+                             nlog=args.log_steps)
         log(f"[bench] {form}: {json.dumps(res[form])}")
     n_p, n_t, n_e = w.tet.shape[0], w.tet_vert.shape[0], ctx.n_edge
-
-    def roofline(form):
-        r = res[form]
-        bytes_launch = BYTES_PER_PARTICLE[form] * n_p + BYTES_PER_TET[form] * n_t + BYTES_PER_EDGE * n_e
-        ach = bytes_launch / (r["kernel_ms"] * 1e-3) / 1e9
-        traffic = None
-        if args.particles is None and args.workload == "40cube":
-            traffic = rocprof_summary.read_traffic(TRAFFIC_SUMMARY, KERNEL_NAME[form])
-        return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": KERNEL_NAME[form],
-                "copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(ach / copy_gbs, 4),
-                "bytes_per_launch": bytes_launch, "kernel_ms": round(r["kernel_ms"], 5)}
+    traffic_path = TRAFFIC_SUMMARY if (args.particles is None and args.workload == "40cube") else None
 
     main_form = "fp64" if "fp64" in res else next(iter(res))
     r = res[main_form]
@@ -570,16 +710,18 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc + ", sort every %d steps" % args.sort_every,
                    "n_particles": n_p, "n_tets": n_t, "n_edges": n_e, "parallelism": "single GPU"},
-        "roofline": roofline(main_form),
+        "roofline": roofline(res, main_form, n_p, n_t, n_e, args.sort_every, copy_gbs, traffic_path),
         "sort_ms": r["sort_ms"],
         "gauss_rel": r["gauss_rel"],
         "gauss_ms": r["gauss_ms"],
+        "logged": r["logged"],
     }
     if "mixed" in res and main_form != "mixed":
         m = res["mixed"]
         line["mixed"] = {"value": m["value"], "ms_per_step": m["ms_per_step"], "dtype": "f32 gather/push, f64 deposit",
-                         "speedup_vs_fp64": m["value"] / r["value"], "roofline": roofline("mixed"),
-                         "gauss_rel": m["gauss_rel"]}
+                         "speedup_vs_fp64": m["value"] / r["value"],
+                         "roofline": roofline(res, "mixed", n_p, n_t, n_e, args.sort_every, copy_gbs, traffic_path),
+                         "gauss_rel": m["gauss_rel"], "logged": m["logged"]}
     if not args.no_side and args.workload == "40cube":
         line["field_update"] = field_update_timing(E, torch, ctx, w)
         log(f"[bench] field update: {json.dumps(line['field_update'])}")
@@ -595,19 +737,33 @@ def main():
         line["adjoint"] = adjoint_timing(E, torch, synth)
         log(f"[bench] adjoint: {json.dumps(line['adjoint'])}")
     if not args.no_cpu_baseline:
-        nth = args.cpu_threads or max(1, min(16, os.cpu_count() or 1))
+        nth = args.cpu_threads or len(os.sched_getaffinity(0))
         stride = max(1, n_p // CPU_SAMPLE_MAX)
         val, wall, cpu = cpu_baseline(w, nth, args.cpu_steps, stride)
         which = f"all {n_p} particles" if stride == 1 else f"every {stride}th of the {n_p} particles"
-        one, wall1, _ = cpu_baseline(w, 1, 1, max(stride, n_p // 1_000_000))
+        one_stride = max(stride, n_p // 1_000_000)
+        one, wall1, _ = cpu_baseline(w, 1, 1, one_stride)
         line["cpu_baseline"] = {"value": val, "unit": "particle-steps/s", "cores": nth, "kind": "oracle",
                                 "sample": f"{which}, first {args.cpu_steps} steps (float64 oracle, "
-                                          f"OpenMP over particles); wall {wall:.1f}s, cpu {cpu:.1f}s",
+                                          f"OpenMP over particles, {nth} threads); wall {wall:.1f}s, "
+                                          f"cpu {cpu:.1f}s",
+                                "nproc": os.cpu_count(), "affinity_cores": len(os.sched_getaffinity(0)),
+                                "cpu_model": cpu_model(),
                                 "single_thread_value": one,
-                                "single_thread_sample": f"every {max(stride, n_p // 1_000_000)}th particle, "
-                                                        f"first step, 1 thread; wall {wall1:.1f}s"}
-    print(json.dumps(line), flush=True)
+                                "single_thread_sample": f"every {one_stride}th particle, first step, 1 thread; "
+                                                        f"wall {wall1:.1f}s"}
     ctx.close()
+    del w
+    if not args.no_side and args.workload == "40cube":
+        if args.precision_steps:
+            line["precision"] = config_entry(E, torch, synth, "precision", args.precision_steps, 2,
+                                             args.sort_every, args.log_steps, copy_gbs)
+            log(f"[bench] precision: {json.dumps(line['precision'])}")
+        if args.large_box_steps:
+            line["large_box"] = config_entry(E, torch, synth, "large-box", args.large_box_steps, 2,
+                                             args.sort_every, args.log_steps, copy_gbs, forms=("mixed", "fp64"))
+            log(f"[bench] large box: {json.dumps(line['large_box'])}")
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

@@ -272,6 +272,21 @@ int etpic_vertex_charge(etpic_ctx *ctx, const etpic_particles *p, const etpic_sp
 int etpic_gauss_residual(etpic_ctx *ctx, const double *dG, const double *rho_new, const double *rho_old,
                          double out_host[2], void *stream);
 
+/* Slices of 64 particles per wavefront that the last particle-kernel launch of
+ * a step call used (1: k_push, else k_push_slices<S>; 0 before any step).
+ * Host only. */
+int etpic_last_push_slices(const etpic_ctx *ctx, int *slices);
+
+/* Measurement aid, not a step of the method: the particle kernel's HBM access
+ * pattern alone (the same launch shape and XCD block order, non-temporal loads
+ * of tet, lambda_1..3 and v, non-temporal stores of lambda_1..3 and v in
+ * place; 100 B per particle in float64, 76 B with float32 velocities) with no
+ * arithmetic, so that the streaming rate that pattern reaches on the device can
+ * be timed beside the particle kernel.  The particle arrays are rewritten with
+ * their own values (unchanged).  flags: ETPIC_STEP_XCD_REMAP or 0.
+ * Asynchronous on `stream`; EINVAL for a bad descriptor or precision. */
+int etpic_stream_probe(etpic_ctx *ctx, const etpic_particles *p, int precision, uint32_t flags, void *stream);
+
 /* etpic_gauss_residual without any allocation, for callers that cannot
  * allocate device memory (loops that log the residual every step under an
  * allocation-free policy, harnesses that forbid hipMalloc).  Same arguments,

@@ -491,6 +491,36 @@ __device__ __forceinline__ void flush_run(const StepArgs<Real> &a, int T, const 
     }
 }
 
+// The six edge sums of the runs that end in this wavefront, added to the
+// edges by the last six lanes of each run together (lane run_end - k adds local
+// edge k, its sum fetched from the run's last lane), so that the wavefront
+// issues one atomic instruction where the run-end lanes alone would issue six;
+// a run shorter than six lanes leaves its remaining edges to its last lane.
+// `flush` marks the run-end lanes whose run is complete (the others stay open).
+template <typename Real>
+__device__ __forceinline__ void flush_runs_together(const StepArgs<Real> &a, int T, const double g6[6],
+                                                   const WaveRuns &r, bool flush) {
+    const unsigned long long fm = __ballot(flush);
+    const bool mine = (fm >> r.run_end) & 1ull;
+    const int k = r.run_end - r.lane;
+    const int len = r.run_end - r.head_lane + 1;
+    double val = g6[0];
+#pragma unroll
+    for (int j = 1; j < 6; ++j) {
+        const double t = __shfl_down(g6[j], j);
+        if (k == j) val = t;
+    }
+    if (mine && k < 6 && k < len) {
+        const int32_t *ed = push_row_edges(a.gpush + (int64_t)T * PushRow<Real>::kStride);
+        if (val != 0.0) unsafeAtomicAdd(&a.dG[ed[k]], a.qw * val);
+        if (k == 0 && len < 6) {
+            for (int j = len; j < 6; ++j)
+                if (g6[j] != 0.0) unsafeAtomicAdd(&a.dG[ed[j]], a.qw * g6[j]);
+        }
+    }
+}
+
+
 // ------------------------------------------------------------------ particle step
 // One lane per particle, particles kept sorted by tet.  Each lane reads its
 // tet's row of this step's coefficient table (lanes of a run share the row, so
@@ -543,9 +573,26 @@ __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) 
         double *__restrict__ lam1 = a.lam1 + b0, *__restrict__ lam2 = a.lam2 + b0, *__restrict__ lam3 = a.lam3 + b0;
         Real *__restrict__ v0 = a.v0 + b0, *__restrict__ v1 = a.v1 + b0, *__restrict__ v2 = a.v2 + b0;
         int32_t *__restrict__ tetp = a.tet + b0;
+        // With one slice per wavefront the whole particle state is requested at
+        // once, before the tet index is back: one HBM round trip instead of tet,
+        // then barycentrics and rows, then velocities (the compiler issues them in
+        // that order when they sit behind the tet test).  The sliced forms keep
+        // the later loads: the extra live registers cost them more than the
+        // round trip (measured on both).
+        constexpr bool kEarly = kSlices == 1;
         int T = -1;
+        double sl1 = 0.0, sl2 = 0.0, sl3 = 0.0;
+        Real sv0 = 0, sv1 = 0, sv2 = 0;
         if (p < a.n) {
             T = __builtin_nontemporal_load(&tetp[ln]);
+            if (kEarly) {
+                sl1 = __builtin_nontemporal_load(&lam1[ln]);
+                sl2 = __builtin_nontemporal_load(&lam2[ln]);
+                sl3 = __builtin_nontemporal_load(&lam3[ln]);
+                sv0 = __builtin_nontemporal_load(&v0[ln]);
+                sv1 = __builtin_nontemporal_load(&v1[ln]);
+                sv2 = __builtin_nontemporal_load(&v2[ln]);
+            }
             if ((unsigned)T >= (unsigned)a.nt) {
                 atomicOr(a.status, (unsigned)ETPIC_DEV_BADTET);
                 T = -1;
@@ -567,11 +614,19 @@ __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) 
         int walker = 0;
         if (act) {
             double l[4];
-            l[1] = __builtin_nontemporal_load(&lam1[ln]);
-            l[2] = __builtin_nontemporal_load(&lam2[ln]);
-            l[3] = __builtin_nontemporal_load(&lam3[ln]);
+            if (!kEarly) {
+                sl1 = __builtin_nontemporal_load(&lam1[ln]);
+                sl2 = __builtin_nontemporal_load(&lam2[ln]);
+                sl3 = __builtin_nontemporal_load(&lam3[ln]);
+                sv0 = __builtin_nontemporal_load(&v0[ln]);
+                sv1 = __builtin_nontemporal_load(&v1[ln]);
+                sv2 = __builtin_nontemporal_load(&v2[ln]);
+            }
+            l[1] = sl1;
+            l[2] = sl2;
+            l[3] = sl3;
             l[0] = 1.0 - l[1] - l[2] - l[3];
-            Real v[3] = {__builtin_nontemporal_load(&v0[ln]), __builtin_nontemporal_load(&v1[ln]), __builtin_nontemporal_load(&v2[ln])};
+            Real v[3] = {sv0, sv1, sv2};
             const Real *cf = a.coef + (int64_t)T * 24;
             Real E[3], B[3];
 #pragma unroll
@@ -688,7 +743,12 @@ __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) 
             for (int k = 0; k < 4; ++k) r4[k] = run_total(r4[k], runs);
         }
         const bool last = it == kSlices - 1 || (slice + 1) * 64 >= a.n;
-        if (act && runs.lane == runs.run_end && (ln != 63 || last)) flush_run<Real, kRho>(a, T, g6, r4);
+        const bool flush = act && runs.lane == runs.run_end && (ln != 63 || last);
+        if (kRho) {
+            if (flush) flush_run<Real, kRho>(a, T, g6, r4);
+        } else {
+            flush_runs_together<Real>(a, T, g6, runs, flush);
+        }
         if (!last) {
             carry_T = __builtin_amdgcn_readlane(T, 63);
             if (ln == 63) {
@@ -727,6 +787,35 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))
 template <typename Real>
 __global__ void __launch_bounds__(kBlock) k_push_rho(StepArgs<Real> a, int remap) {
     push_slices<Real, 1, true>(a, remap);
+}
+
+// The particle kernel's HBM access pattern and nothing else, to measure the
+// streaming rate that pattern can reach: the same launch shape (one lane per
+// particle, 64-particle slices, XCD-contiguous block ranges), the same
+// non-temporal loads of tet, lambda_1..3 and v and non-temporal stores of
+// lambda_1..3 and v back in place.  Each stored value is the loaded one plus
+// zero times the tet index (zero is a run-time argument), so the particle
+// state is left as it was and no load can be dropped.
+template <typename Real>
+__global__ void __launch_bounds__(kBlock) k_stream(int64_t n, double *__restrict__ lam1, double *__restrict__ lam2,
+                                                   double *__restrict__ lam3, Real *__restrict__ v0,
+                                                   Real *__restrict__ v1, Real *__restrict__ v2,
+                                                   const int32_t *__restrict__ tet, double zero, int remap) {
+    unsigned blk = blockIdx.x;
+    if (remap) blk = xcd_block(blk, gridDim.x);
+    const int64_t p = (int64_t)blk * kBlock + threadIdx.x;
+    if (p >= n) return;
+    const double z = zero * (double)__builtin_nontemporal_load(&tet[p]);
+    const double l1 = __builtin_nontemporal_load(&lam1[p]), l2 = __builtin_nontemporal_load(&lam2[p]),
+                 l3 = __builtin_nontemporal_load(&lam3[p]);
+    const Real a = __builtin_nontemporal_load(&v0[p]), b = __builtin_nontemporal_load(&v1[p]),
+               c = __builtin_nontemporal_load(&v2[p]);
+    __builtin_nontemporal_store(l1 + z, &lam1[p]);
+    __builtin_nontemporal_store(l2 + z, &lam2[p]);
+    __builtin_nontemporal_store(l3 + z, &lam3[p]);
+    __builtin_nontemporal_store(a + (Real)z, &v0[p]);
+    __builtin_nontemporal_store(b + (Real)z, &v1[p]);
+    __builtin_nontemporal_store(c + (Real)z, &v2[p]);
 }
 
 template <typename Real, int kSlices, bool kRho>
@@ -2460,6 +2549,7 @@ struct etpic_ctx {
     bool runstat_pending = false;
     int64_t runstat_n = 0;
     double run_len = 0.0;
+    int last_slices = 0;             // slices per wavefront of the last particle-kernel launch
     unsigned *d_count = nullptr;     // nt+1 counting-sort counters
     unsigned *d_tilesum = nullptr;   // scan tile totals
     int64_t tiles = 0;
@@ -2698,9 +2788,9 @@ struct etpic_ctx {
     // in a wavefront; 4 or 16 for longer runs), kept to >= kMinPushWaves
     // wavefronts so that the chip stays full.
     int push_slices_for(uint32_t flags, int64_t n) {
-        if (flags & ETPIC_STEP_SLICES_16) return 16;
-        if (flags & ETPIC_STEP_SLICES_4) return 4;
-        if (flags & ETPIC_STEP_SLICES_1) return 1;
+        if (flags & ETPIC_STEP_SLICES_16) return last_slices = 16;
+        if (flags & ETPIC_STEP_SLICES_4) return last_slices = 4;
+        if (flags & ETPIC_STEP_SLICES_1) return last_slices = 1;
         if (runstat_pending && hipEventQuery(runstat_ev) == hipSuccess) {
             run_len = runstat_n > 0 ? (double)*h_runstat / (double)runstat_n : 0.0;
             runstat_pending = false;
@@ -2708,6 +2798,7 @@ struct etpic_ctx {
         (void)hipGetLastError();   // an unfinished query is not an error
         int s = run_len >= 256.0 ? 16 : (run_len >= 96.0 ? 4 : 1);
         while (s > 1 && n / (64 * (int64_t)s) < kMinPushWaves) s /= 4;
+        last_slices = s;
         return s;
     }
 
@@ -3480,6 +3571,26 @@ int etpic_gauss_residual(etpic_ctx *ctx, const double *dG, const double *rho_new
     return ETPIC_OK;
 }
 
+int etpic_stream_probe(etpic_ctx *ctx, const etpic_particles *p, int precision, uint32_t flags, void *stream) {
+    if (!ctx) return fail(ETPIC_EINVAL, "null context");
+    if (int r = check_particles(ctx, p)) return r;
+    if (precision != ETPIC_FP64 && precision != ETPIC_MIXED) return fail(ETPIC_EINVAL, "bad precision %d", precision);
+    if (p->n == 0) return ETPIC_OK;
+    if (int r = set_device(ctx)) return r;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int remap = (flags & ETPIC_STEP_XCD_REMAP) ? 1 : 0;
+    if (precision == ETPIC_FP64)
+        k_stream<double><<<grid_for(p->n), kBlock, 0, st>>>(
+            p->n, p->lam[0], p->lam[1], p->lam[2], static_cast<double *>(p->vel[0]), static_cast<double *>(p->vel[1]),
+            static_cast<double *>(p->vel[2]), p->tet, 0.0, remap);
+    else
+        k_stream<float><<<grid_for(p->n), kBlock, 0, st>>>(
+            p->n, p->lam[0], p->lam[1], p->lam[2], static_cast<float *>(p->vel[0]), static_cast<float *>(p->vel[1]),
+            static_cast<float *>(p->vel[2]), p->tet, 0.0, remap);
+    HIP_TRY(hipGetLastError());
+    return ETPIC_OK;
+}
+
 int etpic_gauss_residual_noalloc(etpic_ctx *ctx, const double *dG, const double *rho_new, const double *rho_old,
                                  double out_host[2], void *stream) {
     if (!ctx || !dG || !rho_new || !rho_old || !out_host) return fail(ETPIC_EINVAL, "null argument");
@@ -4003,6 +4114,12 @@ int etpic_kernel_time(etpic_ctx *ctx, double ms_out[4], int64_t launches_out[2],
         ctx->timing.clear();
         ctx->timing_sorting.clear();
     }
+    return ETPIC_OK;
+}
+
+int etpic_last_push_slices(const etpic_ctx *ctx, int *slices) {
+    if (!ctx || !slices) return fail(ETPIC_EINVAL, "null argument");
+    *slices = ctx->last_slices;
     return ETPIC_OK;
 }
 

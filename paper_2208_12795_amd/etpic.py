@@ -30,7 +30,8 @@ HOP_CAP = 64
 EXPORTS = (
     "etpic_last_error", "etpic_create", "etpic_destroy", "etpic_mesh_upload", "etpic_mesh_canonical",
     "etpic_mesh_counts", "etpic_mesh_edges", "etpic_mesh_faces", "etpic_gather_push_deposit", "etpic_sort",
-    "etpic_vertex_charge", "etpic_gauss_residual", "etpic_gauss_residual_noalloc", "etpic_kernel_time",
+    "etpic_vertex_charge", "etpic_gauss_residual", "etpic_gauss_residual_noalloc", "etpic_stream_probe",
+    "etpic_last_push_slices", "etpic_kernel_time",
     "etpic_check",
     "etpic_adjoint_workspace", "etpic_forward_checkpointed", "etpic_backward",
     "etpic_field_setup", "etpic_field_nnz", "etpic_field_spmv", "etpic_field_step",
@@ -89,6 +90,8 @@ def lib():
     L.etpic_vertex_charge.argtypes = [vp, C.POINTER(_Particles), C.POINTER(_Species), vp, vp]
     L.etpic_gauss_residual.argtypes = [vp, vp, vp, vp, dp, vp]
     L.etpic_gauss_residual_noalloc.argtypes = [vp, vp, vp, vp, dp, vp]
+    L.etpic_stream_probe.argtypes = [vp, C.POINTER(_Particles), C.c_int, C.c_uint32, vp]
+    L.etpic_last_push_slices.argtypes = [vp, C.POINTER(C.c_int)]
     L.etpic_kernel_time.argtypes = [vp, dp, i64p, C.c_int]
     L.etpic_adjoint_workspace.argtypes = [vp, C.c_int64, C.c_int, C.c_int, C.POINTER(C.c_size_t)]
     L.etpic_forward_checkpointed.argtypes = [vp, C.POINTER(_Particles), C.POINTER(_Species), C.POINTER(_Fields),
@@ -459,6 +462,17 @@ class Context:
         _chk(lib().etpic_gauss_residual(self._h, _dptr(dG), _dptr(rho_new), _dptr(rho_old),
                                         _np_ptr(out, C.c_double), _stream(stream)))
         return float(out[0]), float(out[1])
+
+    def last_push_slices(self):
+        """slices per wavefront of the last particle-kernel launch (1 = k_push)"""
+        s = C.c_int(0)
+        _chk(lib().etpic_last_push_slices(self._h, C.byref(s)))
+        return s.value
+
+    def stream_probe(self, parts, flags=STEP_XCD_REMAP, stream=None):
+        """the particle kernel's access pattern alone over parts (left unchanged)"""
+        d = parts.desc()
+        _chk(lib().etpic_stream_probe(self._h, C.byref(d), int(parts.precision), int(flags), _stream(stream)))
 
     def gauss_residual_noalloc(self, dG, rho_new, rho_old, stream=None):
         """gauss_residual through the allocation-free entry point."""

@@ -282,11 +282,17 @@ def rngs(k):
     return [np.random.Generator(np.random.PCG64(s)) for s in ss]   # mesh, pos, vel, fields
 
 
-def make_workload(k, n_particles=None, n_cells=None, omega=None, b0=None, amp=None):
+def make_workload(k, n_particles=None, n_cells=None, omega=None, b0=None, amp=None, progress=None):
     """Workload k with optional overrides (smaller particle count / mesh):
     1 = 5^3 x 6 tets, unit cube, 1e3 electrons; 2 = 40^3 x 6, 1e7; 3 = 40^3 x 6,
     5e7; 4 = 20^3 x 6, 2e6; 5 = 160 x 80 x 80 x 6, 2:1:1 box, 2e8 (bunch and
-    background)."""
+    background).  progress(msg), if given, is called after each phase."""
+    import time as _time
+    t_start = _time.perf_counter()
+
+    def done(what):
+        if progress is not None:
+            progress(f"{what} ({_time.perf_counter() - t_start:.1f}s)")
     c = dict(WORKLOAD_TABLE[k])
     if n_cells is not None:
         c["n"] = tuple(n_cells)
@@ -296,6 +302,7 @@ def make_workload(k, n_particles=None, n_cells=None, omega=None, b0=None, amp=No
     nv = xyz.shape[0]
     edges = mesh_edges(tv, nv)
     faces = mesh_faces(tv, nv)
+    done("mesh")
     if c.get("bunch"):
         nb = n_p // 2
         ctr = 0.5 * np.asarray(c["extent"])
@@ -305,13 +312,16 @@ def make_workload(k, n_particles=None, n_cells=None, omega=None, b0=None, amp=No
             ok = np.all((cand > 0) & (cand < np.asarray(c["extent"])), axis=1)
             u = np.concatenate([u, cand[ok]])
         tb, lb = reference_located(u, c["n"], c["extent"])
+        done("bunch positions")
         tu, lu = uniform_particles(xyz, tv, n_p - nb, r_pos)
+        done("background positions")
         vb = maxwellian(nb, (5e4, 1e5, 1e5), r_vel, drift=(1e7, 0.0, 0.0))
         vu = maxwellian(n_p - nb, c["vth"], r_vel)
         tet = np.concatenate([tb, tu]); lam = np.concatenate([lb, lu]); vel = np.concatenate([vb, vu])
     else:
         tet, lam = uniform_particles(xyz, tv, n_p, r_pos)
         vel = maxwellian(n_p, c["vth"], r_vel)
+    done("particles")
     w = 2.0 * np.pi * c["freq"] if omega is None else float(omega)
     a = c["amp"] if amp is None else amp
     if c["fields"] == "phasor":
@@ -320,6 +330,7 @@ def make_workload(k, n_particles=None, n_cells=None, omega=None, b0=None, amp=No
         e_env = mode_edge_dofs(xyz, edges, a, c["extent"], r_fld)
     b_env = faraday_face_envelope(e_env, edges, faces, nv, w)
     b_dc = uniform_face_flux(xyz, faces, c["b0"] if b0 is None else b0)
+    done("fields")
     return Workload(name=c["name"], n=c["n"], extent=c["extent"], xyz=xyz, tet_vert=tv,
                     edges=edges, faces=faces, tet=tet.astype(np.int32),
                     lam=np.ascontiguousarray(lam, dtype=np.float64),

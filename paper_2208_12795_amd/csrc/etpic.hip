@@ -44,6 +44,7 @@
 #include <algorithm>
 #include <complex>
 #include <mutex>
+#include <type_traits>
 
 #include "etpic.h"
 #include "field_host.hpp"
@@ -298,6 +299,8 @@ struct StepArgs {
     const TetTopo *topo;
     double *dG;
     double *rho;
+    double *tetG;              // nt*8 per-tet current slots (q w * the six path-integral sums of
+                               // the tet's runs), or null: the runs then add to dG directly
     unsigned *status;
     unsigned *walk_queue;      // particles that left their tet
     unsigned *slice_queue;     // 64-particle slices whose walkers did not fit in walk_queue
@@ -477,12 +480,19 @@ __device__ __forceinline__ int walk(const StepArgs<Real> &a, int T, double l[4],
 
 // q w * (the run's path-integral sums) onto the six edges of tet T, and
 // q w * (its end-point barycentric sums) onto the four vertices if rho is kept.
-template <typename Real, bool kRho>
+template <typename Real, bool kRho, bool kSlots = false>
 __device__ __forceinline__ void flush_run(const StepArgs<Real> &a, int T, const double g6[6], const double r4[4]) {
-    const int32_t *ed = push_row_edges(a.gpush + (int64_t)T * PushRow<Real>::kStride);
+    if (kSlots) {
+        double *slot = a.tetG + (int64_t)T * 8;
 #pragma unroll
-    for (int e = 0; e < 6; ++e)
-        if (g6[e] != 0.0) unsafeAtomicAdd(&a.dG[ed[e]], a.qw * g6[e]);
+        for (int e = 0; e < 6; ++e)
+            if (g6[e] != 0.0) unsafeAtomicAdd(&slot[e], a.qw * g6[e]);
+    } else {
+        const int32_t *ed = push_row_edges(a.gpush + (int64_t)T * PushRow<Real>::kStride);
+#pragma unroll
+        for (int e = 0; e < 6; ++e)
+            if (g6[e] != 0.0) unsafeAtomicAdd(&a.dG[ed[e]], a.qw * g6[e]);
+    }
     if (kRho) {
         const TetTopo *tp = a.topo + T;
 #pragma unroll
@@ -491,13 +501,15 @@ __device__ __forceinline__ void flush_run(const StepArgs<Real> &a, int T, const 
     }
 }
 
-// The six edge sums of the runs that end in this wavefront, added to the
-// edges by the last six lanes of each run together (lane run_end - k adds local
-// edge k, its sum fetched from the run's last lane), so that the wavefront
-// issues one atomic instruction where the run-end lanes alone would issue six;
-// a run shorter than six lanes leaves its remaining edges to its last lane.
-// `flush` marks the run-end lanes whose run is complete (the others stay open).
-template <typename Real>
+// The six edge sums of the runs that end in this wavefront, added by the last
+// six lanes of each run together (lane run_end - k adds local edge k, its sum
+// fetched from the run's last lane): the wavefront issues one atomic
+// instruction where the run-end lanes alone would issue six.  With kSlots the
+// sums go to the run's per-tet current slots (8 * T + k: the six lanes of a
+// run address one 64-byte line), else to the six edges.  A run shorter than
+// six lanes leaves its remaining edges to its last lane.  `flush` marks the
+// run-end lanes whose run is complete (the others stay open).
+template <typename Real, bool kSlots>
 __device__ __forceinline__ void flush_runs_together(const StepArgs<Real> &a, int T, const double g6[6],
                                                    const WaveRuns &r, bool flush) {
     const unsigned long long fm = __ballot(flush);
@@ -511,13 +523,39 @@ __device__ __forceinline__ void flush_runs_together(const StepArgs<Real> &a, int
         if (k == j) val = t;
     }
     if (mine && k < 6 && k < len) {
-        const int32_t *ed = push_row_edges(a.gpush + (int64_t)T * PushRow<Real>::kStride);
-        if (val != 0.0) unsafeAtomicAdd(&a.dG[ed[k]], a.qw * val);
-        if (k == 0 && len < 6) {
-            for (int j = len; j < 6; ++j)
-                if (g6[j] != 0.0) unsafeAtomicAdd(&a.dG[ed[j]], a.qw * g6[j]);
+        if (kSlots) {
+            double *slot = a.tetG + (int64_t)T * 8;
+            if (val != 0.0) unsafeAtomicAdd(&slot[k], a.qw * val);
+            if (k == 0 && len < 6) {
+                for (int j = len; j < 6; ++j)
+                    if (g6[j] != 0.0) unsafeAtomicAdd(&slot[j], a.qw * g6[j]);
+            }
+        } else {
+            const int32_t *ed = push_row_edges(a.gpush + (int64_t)T * PushRow<Real>::kStride);
+            if (val != 0.0) unsafeAtomicAdd(&a.dG[ed[k]], a.qw * val);
+            if (k == 0 && len < 6) {
+                for (int j = len; j < 6; ++j)
+                    if (g6[j] != 0.0) unsafeAtomicAdd(&a.dG[ed[j]], a.qw * g6[j]);
+            }
         }
     }
+}
+
+// The per-tet current slots of a multi-step call added to the edges: dG[e] +=
+// the slots that name edge e, in the fixed order of the edge's CSR (no atomics:
+// every particle and walk kernel of the call has finished).  The same launch
+// clears the other slot buffer, which the next call accumulates into.
+__global__ void __launch_bounds__(kBlock) k_slots_to_edges(int64_t ne, const int32_t *__restrict__ ptr,
+                                                           const int32_t *__restrict__ slot,
+                                                           const double *__restrict__ tetG, double *__restrict__ dG,
+                                                           double *__restrict__ clear, int64_t nclear) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += stride) {
+        double s = 0.0;
+        for (int32_t i = ptr[e]; i < ptr[e + 1]; ++i) s += tetG[slot[i]];
+        if (s != 0.0) dG[e] += s;
+    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nclear; i += stride) clear[i] = 0.0;
 }
 
 
@@ -539,6 +577,16 @@ __device__ __forceinline__ void flush_runs_together(const StepArgs<Real> &a, int
 // per wavefront (same-address atomics from many wavefronts serialise).  With
 // about one wavefront's worth of particles per tet or fewer, one slice per
 // wavefront keeps more wavefronts in flight and is faster.
+// Whether a particle kernel adds its runs' sums to the per-tet current slots
+// (added to the edges once per call) or straight to the edges: the slots cost
+// one cache line per run instead of six, which pays in every form except the
+// float64 kernels with several slices per wavefront, where the slot path's
+// registers spill (measured: float64 4-slice kernel 1.20 -> 1.24 ms).
+template <typename Real>
+constexpr __host__ __device__ bool push_uses_slots(int slices) {
+    return std::is_same<Real, float>::value || slices == 1;
+}
+
 template <typename Real, int kSlices, bool kRho, bool kScatter = false>
 __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) {
     unsigned blk = blockIdx.x;
@@ -580,6 +628,7 @@ __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) 
         // the later loads: the extra live registers cost them more than the
         // round trip (measured on both).
         constexpr bool kEarly = kSlices == 1;
+        constexpr bool kSlots = push_uses_slots<Real>(kSlices);
         int T = -1;
         double sl1 = 0.0, sl2 = 0.0, sl3 = 0.0;
         Real sv0 = 0, sv1 = 0, sv2 = 0;
@@ -729,7 +778,7 @@ __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) 
 #pragma unroll
                     for (int k = 0; k < 4; ++k) r4[k] += cr[k];
                 } else {
-                    flush_run<Real, kRho>(a, carry_T, cg, cr);
+                    flush_run<Real, kRho, push_uses_slots<Real>(kSlices)>(a, carry_T, cg, cr);
                 }
             }
         }
@@ -745,9 +794,9 @@ __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) 
         const bool last = it == kSlices - 1 || (slice + 1) * 64 >= a.n;
         const bool flush = act && runs.lane == runs.run_end && (ln != 63 || last);
         if (kRho) {
-            if (flush) flush_run<Real, kRho>(a, T, g6, r4);
+            if (flush) flush_run<Real, kRho, kSlots>(a, T, g6, r4);
         } else {
-            flush_runs_together<Real>(a, T, g6, runs, flush);
+            flush_runs_together<Real, kSlots>(a, T, g6, runs, flush);
         }
         if (!last) {
             carry_T = __builtin_amdgcn_readlane(T, 63);
@@ -780,7 +829,7 @@ __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) 
 // One slice per wavefront; without the vertex charge the kernel fits 64 VGPRs
 // (8 wavefronts per SIMD), which the compiler does not choose by itself.
 template <typename Real>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) k_push(StepArgs<Real> a, int remap) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) k_push(StepArgs<Real> a, int remap) {
     push_slices<Real, 1, false>(a, remap);
 }
 
@@ -2531,6 +2580,10 @@ struct etpic_ctx {
     double *d_coef_env = nullptr;    // nt*kEnvRow complex-envelope rows (first downshifted call)
     int32_t *d_v2e_ptr = nullptr;
     int32_t *d_v2e_code = nullptr;
+    int32_t *d_e2s_ptr = nullptr;    // edge -> tet-slot CSR (ne+1)
+    int32_t *d_e2s_slot = nullptr;   // its slots, 8 * tet + local edge (6 nt)
+    double *d_tetG[2] = {nullptr, nullptr};  // per-tet current slots (nt*8 each), alternate per call
+    int tetG_cur = 0;
     double *d_xyz = nullptr;         // 3*nv vertex coordinates
     int32_t *d_grid = nullptr;       // start tets of the point-location grid
     GridArgs grid{};
@@ -2636,7 +2689,7 @@ struct etpic_ctx {
     }
 
     template <typename Real, bool kRho, bool kSort>
-    void launch_push(const StepArgs<Real> &a, int slices, int remap, hipStream_t st) {
+    bool launch_push(const StepArgs<Real> &a, int slices, int remap, hipStream_t st) {
         const int64_t n = a.n;
         switch (slices) {
         case 16:
@@ -2658,8 +2711,10 @@ struct etpic_ctx {
                 k_push_rho<Real><<<grid_for(n), kBlock, 0, st>>>(a, remap);
             else
                 k_push<Real><<<grid_for(n), kBlock, 0, st>>>(a, remap);
+            slices = 1;
             break;
         }
+        return push_uses_slots<Real>(slices);
     }
 
     // Counting sort, first half: tet counts of src, the run-length statistic
@@ -2718,9 +2773,12 @@ struct etpic_ctx {
         }
         if (int r = launch_coef<Real>(plans[0], omega, st)) return r;
         if (ev) HIP_TRY(hipEventRecord(ev[1], st));
+        double *slots = d_tetG[tetG_cur];
+        bool used_slots = false;
         for (int j = 0; j < nsteps; ++j) {
             StepArgs<Real> a = step_args<Real>(p, sp, dt, dG, j == nsteps - 1 ? rho : nullptr);
             a.walk_by_slice = (flags & ETPIC_STEP_WALK_BY_SLICE) ? 1 : 0;
+            a.tetG = slots;
             if (ev) HIP_TRY(hipEventRecord(ev[2], st));
             if (j == 0 && src) {
                 // read src, write p at the sorted positions; the walk then runs on p
@@ -2743,14 +2801,14 @@ struct etpic_ctx {
                 as.o_id = p->id;
                 as.cursor = d_count;
                 if (as.rho)
-                    launch_push<Real, true, true>(as, push_slices_for(flags, n), remap, st);
+                    used_slots |= launch_push<Real, true, true>(as, push_slices_for(flags, n), remap, st);
                 else
-                    launch_push<Real, false, true>(as, push_slices_for(flags, n), remap, st);
+                    used_slots |= launch_push<Real, false, true>(as, push_slices_for(flags, n), remap, st);
                 a.scatter = 1;
             } else if (a.rho) {
-                launch_push<Real, true, false>(a, push_slices_for(flags, n), remap, st);
+                used_slots |= launch_push<Real, true, false>(a, push_slices_for(flags, n), remap, st);
             } else {
-                launch_push<Real, false, false>(a, push_slices_for(flags, n), remap, st);
+                used_slots |= launch_push<Real, false, false>(a, push_slices_for(flags, n), remap, st);
             }
             HIP_TRY(hipGetLastError());
             if (ev) HIP_TRY(hipEventRecord(ev[3], st));
@@ -2764,6 +2822,16 @@ struct etpic_ctx {
                     k_walk_coef<Real, 1><<<kWalkBlocks + coef_blocks, kBlock, 0, st>>>(a, nt, F);
             } else {
                 k_walk<Real><<<kWalkBlocks, kBlock, 0, st>>>(a);
+                if (used_slots) {
+                    // the call's per-tet sums onto the edges; the other slot
+                    // buffer is cleared for the next call
+                    HIP_TRY(hipGetLastError());
+                    const int64_t ne = host.ne;
+                    const unsigned gb = (unsigned)std::min<int64_t>(grid_for(std::max<int64_t>(ne, 8 * nt)), 4096);
+                    k_slots_to_edges<<<gb, kBlock, 0, st>>>(ne, d_e2s_ptr, d_e2s_slot, slots, dG,
+                                                            d_tetG[tetG_cur ^ 1], 8 * nt);
+                    tetG_cur ^= 1;
+                }
             }
             HIP_TRY(hipGetLastError());
             if (ev) {
@@ -2958,6 +3026,10 @@ struct etpic_ctx {
         (void)hipFree(d_coef_env);
         (void)hipFree(d_v2e_ptr);
         (void)hipFree(d_v2e_code);
+        (void)hipFree(d_e2s_ptr);
+        (void)hipFree(d_e2s_slot);
+        (void)hipFree(d_tetG[0]);
+        (void)hipFree(d_tetG[1]);
         (void)hipFree(d_xyz);
         (void)hipFree(d_grid);
         (void)hipFree(d_count);
@@ -2970,6 +3042,9 @@ struct etpic_ctx {
         d_coef = nullptr;
         d_coef_env = nullptr;
         d_v2e_ptr = d_v2e_code = nullptr;
+        d_e2s_ptr = d_e2s_slot = nullptr;
+        d_tetG[0] = d_tetG[1] = nullptr;
+        tetG_cur = 0;
         d_xyz = nullptr;
         d_grid = nullptr;
         grid = GridArgs{};
@@ -3213,6 +3288,15 @@ int etpic_mesh_upload(etpic_ctx *ctx, int64_t n_vert, const double *xyz_host, in
     HIP_TRY(hipMemcpy(ctx->d_grad64, M.grad.data(), sizeof(double) * 12 * nt, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(ctx->d_v2e_ptr, M.v2e_ptr.data(), sizeof(int32_t) * (M.nv + 1), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(ctx->d_v2e_code, M.v2e_code.data(), sizeof(int32_t) * 2 * M.ne, hipMemcpyHostToDevice));
+    HIP_TRY(hipMalloc(&ctx->d_e2s_ptr, sizeof(int32_t) * (M.ne + 1)));
+    HIP_TRY(hipMalloc(&ctx->d_e2s_slot, sizeof(int32_t) * 6 * nt));
+    HIP_TRY(hipMemcpy(ctx->d_e2s_ptr, M.e2s_ptr.data(), sizeof(int32_t) * (M.ne + 1), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(ctx->d_e2s_slot, M.e2s_slot.data(), sizeof(int32_t) * 6 * nt, hipMemcpyHostToDevice));
+    for (int b = 0; b < 2; ++b) {
+        HIP_TRY(hipMalloc(&ctx->d_tetG[b], sizeof(double) * 8 * nt));
+        HIP_TRY(hipMemset(ctx->d_tetG[b], 0, sizeof(double) * 8 * nt));
+    }
+    ctx->tetG_cur = 0;
     ctx->host = std::move(M);
     ctx->has_mesh = true;
     return ETPIC_OK;

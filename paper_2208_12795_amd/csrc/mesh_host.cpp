@@ -2,6 +2,7 @@
 // edges and faces with their global numbering, the tet -> edge / face /
 // neighbour incidences, the barycentric gradients of every tet, and the
 // vertex -> edge incidence used by the continuity residual.
+#include <climits>
 #include "mesh_host.hpp"
 
 #include <algorithm>
@@ -132,6 +133,20 @@ int build_host_mesh(int64_t nv, const double *xyz, int64_t nt, const int32_t *tv
         M.v2e_code[fill[M.edges[2 * e]]++] = (int32_t)(e << 1);
         M.v2e_code[fill[M.edges[2 * e + 1]]++] = (int32_t)((e << 1) | 1);
     }
+    // edge -> the (tet, local edge) slots that name it, slot = 8 * tet + local
+    // edge, in increasing tet order
+    if (nt > (int64_t)(INT32_MAX / 8)) {
+        err = "more than 2^28 tets";
+        return -1;
+    }
+    M.e2s_ptr.assign((size_t)M.ne + 1, 0);
+    for (int64_t t = 0; t < nt; ++t)
+        for (int k = 0; k < 6; ++k) M.e2s_ptr[M.topo[t].e[k] + 1]++;
+    for (int64_t e = 0; e < M.ne; ++e) M.e2s_ptr[e + 1] += M.e2s_ptr[e];
+    M.e2s_slot.resize((size_t)nt * 6);
+    std::vector<int32_t> efill(M.e2s_ptr.begin(), M.e2s_ptr.end() - 1);
+    for (int64_t t = 0; t < nt; ++t)
+        for (int k = 0; k < 6; ++k) M.e2s_slot[efill[M.topo[t].e[k]]++] = (int32_t)(8 * t + k);
     return 0;
 }
 

@@ -30,6 +30,8 @@ struct HostMesh {
     std::vector<double> vol;        // nt: |volume|
     std::vector<int32_t> v2e_ptr;   // nv+1: CSR of vertex -> incident edges
     std::vector<int32_t> v2e_code;  // 2*ne: (edge << 1) | (vertex is the head)
+    std::vector<int32_t> e2s_ptr;   // ne+1: CSR of edge -> the tet-local slots that name it
+    std::vector<int32_t> e2s_slot;  // 6*nt: 8 * tet + local edge (0..5)
 };
 
 // Uniform grid over the mesh's bounding box that gives every cell one tet to

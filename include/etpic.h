@@ -27,18 +27,26 @@
  *  - complex DoFs are interleaved (re, im) float64 pairs (complex128 layout);
  *  - the physical fields are Re{env * e^{j w t}} + dc with t = step*dt.
  *
- * Ownership: the library owns the context state (status word, walk queues,
- * reduction words, allocated in etpic_create), the mesh tables, per-step
- * coefficient table and sort counters (etpic_mesh_upload, replaced by the next
- * upload) and the field-update matrices and work vectors (etpic_field_setup,
- * etpic_ns_setup),
- * and the complex-envelope rows of the downshifted step (72 float64 per tet,
- * allocated by the first etpic_ds_steps call after a mesh upload);
- * etpic_destroy frees them all.  Particle arrays, field DoFs, outputs, the
- * adjoint workspace and the downshifted history are device buffers owned by
- * the caller; they must stay valid until the work queued on `stream` has
- * finished.  No other entry point allocates device memory
- * (ETPIC_STEP_TIMING creates HIP events on first use).
+ * Ownership: every device buffer is the caller's.  The library allocates no
+ * device memory; what it keeps on the device lives in buffers the caller
+ * allocates (e.g. torch tensors) and hands in after a size query:
+ *   context workspace   etpic_workspace_bytes  -> etpic_workspace_bind
+ *   mesh tables         etpic_mesh_sizes       -> etpic_mesh_upload
+ *   field-step solver   etpic_field_bytes      -> etpic_field_setup
+ *   Gauss-law solver    etpic_ns_bytes         -> etpic_ns_setup
+ *   downshifted rows    etpic_ds_rows_bytes    -> etpic_ds_rows_bind
+ *   projector object    etpic_qh_bytes         -> etpic_qh_bind
+ * Each buffer must be 256-byte aligned, at least the queried size, and stay
+ * valid (not freed, not written by the caller) while the object that was
+ * given it is in use: until the next bind/upload/setup of the same kind, a
+ * new mesh upload (which drops the mesh-derived ones: field, Gauss-law and
+ * downshifted buffers must then be given again), or destruction.  Particle
+ * arrays, field DoFs, outputs, the adjoint workspace and the downshifted
+ * history are caller-owned too and must stay valid until the work queued on
+ * `stream` has finished.  Host resources taken by etpic_create: one pinned
+ * 8-byte word (the sort's run-length statistic is read into it without
+ * blocking) and a fixed pool of HIP events for ETPIC_STEP_TIMING; none
+ * afterwards.
  *
  * Errors: every entry point returns an etpic status (0 = OK).  On failure the
  * message is available from etpic_last_error() (thread-local).  Errors found
@@ -139,19 +147,45 @@ typedef struct {
 /* Thread-local message of the last failing call ("" if none). */
 const char *etpic_last_error(void);
 
-/* Create a context bound to HIP device `device`.  *out receives the handle. */
+/* Create a context bound to HIP device `device`.  *out receives the handle.
+ * Takes no device memory: bind a workspace (below) before any other call that
+ * launches work (ESTATE otherwise). */
 int etpic_create(etpic_ctx **out, int device);
 
-/* Destroy a context and free the device memory it owns.  NULL is accepted. */
+/* Destroy a context (its host resources; the device buffers it was given are
+ * the caller's to free afterwards).  NULL is accepted. */
 int etpic_destroy(etpic_ctx *ctx);
 
-/* Upload a tet mesh (Appendix A: the sets N, E, F, T).  Host arrays:
- * xyz_host[3*n_vert] (x,y,z per vertex), tet_vert_host[4*n_tet] ascending per row.
- * Builds the canonical edges/faces, tet->edge/face/neighbour tables and the
- * barycentric gradients on the host, then allocates and fills the device tables
- * (synchronously).  Replaces any previous mesh.  Errors: EINVAL, EMESH, EHIP. */
+/* Bytes of the context workspace: the device status word, the reduction and
+ * run-length words, the walk counters and the two queues of particles that
+ * left their tet (2^23 entries each).  Host only. */
+int etpic_workspace_bytes(size_t *bytes);
+
+/* Give the context its workspace (device, 256-byte aligned, at least
+ * etpic_workspace_bytes; zeroes what must start at zero, synchronously).
+ * Rebinding replaces the previous one.  Errors: EINVAL (null, misaligned or
+ * short buffer), EHIP. */
+int etpic_workspace_bind(etpic_ctx *ctx, void *dev_buf, size_t bytes);
+
+/* Host only (no context, no GPU): the mesh tables' device size.  Builds the
+ * canonical numbering as etpic_mesh_upload does (Appendix A: the sets N, E,
+ * F, T); counts_out[4] = {N_n, N_e, N_f, N_t}; *dev_bytes = the buffer
+ * etpic_mesh_upload needs.  Errors: EINVAL, EMESH. */
+int etpic_mesh_sizes(int64_t n_vert, const double *xyz_host, int64_t n_tet, const int32_t *tet_vert_host,
+                     int64_t counts_out[4], size_t *dev_bytes);
+
+/* Upload a tet mesh (Appendix A: the sets N, E, F, T) into the caller's
+ * device buffer dev_buf (256-byte aligned, at least the etpic_mesh_sizes
+ * bytes).  Host arrays: xyz_host[3*n_vert] (x,y,z per vertex),
+ * tet_vert_host[4*n_tet] ascending per row.  Builds the canonical
+ * edges/faces, tet->edge/face/neighbour tables and the barycentric gradients
+ * on the host and fills the device tables in dev_buf (synchronously): topology,
+ * gradient and push rows, the per-step coefficient table, point-location
+ * grid, incidences, sort counters and the per-tet current slots.  Replaces any
+ * previous mesh (and forgets its field, Gauss-law and downshifted buffers).
+ * Errors: EINVAL (bad input, short buffer), EMESH, EHIP. */
 int etpic_mesh_upload(etpic_ctx *ctx, int64_t n_vert, const double *xyz_host, int64_t n_tet,
-                      const int32_t *tet_vert_host);
+                      const int32_t *tet_vert_host, void *dev_buf, size_t bytes);
 
 /* Host only (no context, no GPU): the canonical numbering of a mesh, as
  * etpic_mesh_upload would build it.  counts_out[4] = {N_n, N_e, N_f, N_t};
@@ -322,6 +356,13 @@ int etpic_gauss_residual_noalloc(etpic_ctx *ctx, const double *dG, const double 
  * velocity update, float64 positions, barycentric increments and deposit,
  * as the mixed fine-step form). */
 
+/* Bytes of the per-tet complex-envelope rows of the downshifted step (72
+ * float64 per tet of the uploaded mesh), and binding of the caller's buffer
+ * (device, 256-byte aligned) that holds them; etpic_ds_steps needs it (ESTATE
+ * otherwise) and rebuilds the rows at each call.  A mesh upload forgets it. */
+int etpic_ds_rows_bytes(const etpic_ctx *ctx, size_t *bytes);
+int etpic_ds_rows_bind(etpic_ctx *ctx, void *dev_buf, size_t bytes);
+
 /* Size of the history buffer for n particles: 48 arrays of length n of the
  * velocity type (float64, float32 for ETPIC_MIXED): velocity ring v^m in slot
  * m mod 4; E and B samples, real part, imaginary part and dc part, of step m
@@ -339,8 +380,8 @@ int etpic_ds_history_bytes(int64_t n, int precision, size_t *bytes_out);
  * which moves the history with the particles (etpic_sort does not: restart
  * with hist0 = 0 after it).  dG accumulates the deposit of all steps, rho (if not NULL)
  * receives q w lam_k after the last one.  flags as for
- * etpic_gather_push_deposit (XCD_REMAP, TIMING, WALK_BY_SLICE).  The first
- * call after a mesh upload allocates the complex-envelope rows.
+ * etpic_gather_push_deposit (XCD_REMAP, TIMING, WALK_BY_SLICE).  The
+ * complex-envelope rows go to the buffer of etpic_ds_rows_bind.
  * Asynchronous on `stream`.  Errors: EINVAL, ESTATE, EHIP; in-kernel errors
  * via etpic_check. */
 int etpic_ds_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, void *hist, size_t hist_bytes,
@@ -409,9 +450,17 @@ int etpic_backward(etpic_ctx *ctx, int64_t n, const etpic_species *sp, const etp
  * plain source it carries a gradient part that only etpic_ns_correct makes
  * obey Gauss' law. */
 
-/* Assemble M, K (host), the preconditioner and the device work vectors for
- * field step dt, carrier w, permittivity eps, permeability mu (allocates). */
-int etpic_field_setup(etpic_ctx *ctx, double dt, double omega, double eps, double mu);
+/* Bytes of the field-step solver for permittivity eps and permeability mu
+ * (assembles M and K on the host, kept for the etpic_field_setup call that
+ * follows with the same eps and mu). */
+int etpic_field_bytes(etpic_ctx *ctx, double eps, double mu, size_t *bytes);
+
+/* Field step dt, carrier w, permittivity eps, permeability mu: M, K, the
+ * Jacobi preconditioner and the COCG work vectors in the caller's buffer
+ * (device, 256-byte aligned, at least etpic_field_bytes).  Replaces the
+ * previous setup.  Errors: EINVAL (bad parameters, short buffer), ESTATE (no
+ * mesh), EMESH, EHIP. */
+int etpic_field_setup(etpic_ctx *ctx, double dt, double omega, double eps, double mu, void *dev_buf, size_t bytes);
 
 /* Number of stored entries of the CSR pattern (M and K share it). */
 int etpic_field_nnz(const etpic_ctx *ctx, int64_t *nnz_out);
@@ -445,10 +494,14 @@ int etpic_field_step(etpic_ctx *ctx, double t_next, double *u, double *v, double
  * eps int grad W0_i . grad W0_j; it is real, so the solve is real and the
  * carrier phase e^{-j w t} multiplies its solution.  Float64 throughout. */
 
-/* Assemble the nodal operator for permittivity eps (host), its Jacobi
- * preconditioner and the device work vectors (allocates; replaced by the next
- * call, freed by a mesh upload or etpic_destroy). */
-int etpic_ns_setup(etpic_ctx *ctx, double eps);
+/* Bytes of the Gauss-law solver for permittivity eps (assembles the nodal
+ * operator on the host, kept for the etpic_ns_setup call that follows). */
+int etpic_ns_bytes(etpic_ctx *ctx, double eps, size_t *bytes);
+
+/* The nodal operator for permittivity eps, its Jacobi preconditioner and the
+ * CG work vectors in the caller's buffer (device, 256-byte aligned, at least
+ * etpic_ns_bytes).  Replaced by the next call, forgotten by a mesh upload. */
+int etpic_ns_setup(etpic_ctx *ctx, double eps, void *dev_buf, size_t bytes);
 
 /* Stored entries of the nodal operator (wall rows count one each) and, if
  * wall_nodes_out is not NULL, the number of grounded wall nodes. */
@@ -579,9 +632,10 @@ int etpic_em_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, cons
  * global normal, right-handed in its ascending vertex order, points out of
  * the tet).  + is the Moore-Penrose pseudoinverse: Sigma^T Sigma has the
  * constants as null space and the nodal solution returned is the one
- * orthogonal to them.  The projector object owns its own copy of the mesh
- * tables (same canonical numbering as etpic_mesh_upload) and device work
- * vectors; it is independent of etpic_ctx.  Errors: etpic status codes, the
+ * orthogonal to them.  The projector object keeps its own copy of the mesh
+ * tables (same canonical numbering as etpic_mesh_upload) and work vectors, on
+ * the device in the caller's buffer (etpic_qh_bind); it is independent of
+ * etpic_ctx.  Errors: etpic status codes, the
  * message from etpic_qh_last_error() (thread-local).  Vectors are complex,
  * 2*N float64 interleaved, on the device; calls synchronise `stream`. */
 typedef struct etpic_qh etpic_qh;
@@ -591,12 +645,20 @@ const char *etpic_qh_last_error(void);
 
 /* Build the projector object on HIP device `device` for the mesh (xyz: 3*nv
  * float64, tet_vert: 4*nt int32 ascending per row, host; the mesh must be
- * connected, else EMESH, checked before any device call) and permittivity
- * eps (allocates).  *out receives the handle. */
+ * connected, else EMESH) and permittivity eps: its tables are built on the
+ * host; the device part is given by etpic_qh_bind.  *out receives the handle. */
 int etpic_qh_create(etpic_qh **out, int device, int64_t nv, const double *xyz, int64_t nt, const int32_t *tet_vert,
                     double eps);
 
-/* Free the object (NULL accepted). */
+/* Device bytes of the object (mesh tables, edge mass, work vectors), and the
+ * binding of the caller's buffer (device, 256-byte aligned, at least that
+ * size) that receives them (synchronously).  The projections need it
+ * (ESTATE otherwise). */
+int etpic_qh_bytes(const etpic_qh *qh, size_t *bytes);
+int etpic_qh_bind(etpic_qh *qh, void *dev_buf, size_t bytes);
+
+/* Destroy the object (its host tables; the bound buffer is the caller's).
+ * NULL accepted. */
 void etpic_qh_destroy(etpic_qh *qh);
 
 /* counts_out = {N_n, N_e, N_f, N_t, stored entries of [*eps]}. */

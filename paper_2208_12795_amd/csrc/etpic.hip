@@ -43,6 +43,7 @@
 #include <array>
 #include <algorithm>
 #include <complex>
+#include <memory>
 #include <mutex>
 #include <type_traits>
 
@@ -73,6 +74,7 @@ int fail(int code, const char *fmt, ...) {
     } while (0)
 
 constexpr int kBlock = 256;
+constexpr int kTimingSets = 512;             // event sets of the step-timing pool
 constexpr unsigned kWalkQueueCap = 1u << 23;  // entries of each walk queue; N_p <= 64 * kWalkQueueCap
 constexpr unsigned kQueueSkip = 0xffffffffu;  // particle-queue entry to skip
 // grid of the walk kernel (and the walk half of k_walk_coef): the walk is
@@ -2491,6 +2493,24 @@ inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBloc
 }  // namespace
 
 // =============================================================================== context
+
+// Device memory carved from one caller-owned buffer.  Every table and scratch
+// array the library keeps on the device lives in such a buffer (context
+// workspace, mesh tables, field solver, Gauss-law solver, downshifted rows); the
+// library itself allocates no device memory.  A layout takes its arrays in a
+// fixed order, each on a 256-byte boundary; with a null base it only counts
+// the bytes, which is how the size queries are answered.
+struct Carve {
+    char *base = nullptr;
+    size_t cap = 0, used = 0;
+    template <typename T>
+    T *take(size_t count) {
+        const size_t off = (used + 255) & ~(size_t)255;
+        used = off + sizeof(T) * std::max<size_t>(count, 1);
+        return base ? reinterpret_cast<T *>(base + off) : nullptr;
+    }
+};
+
 // Device state of the field update (allocated by etpic_field_setup).
 struct FieldState {
     bool ready = false;
@@ -2507,12 +2527,7 @@ struct FieldState {
 
     double2 *v(int k) const { return vec + (size_t)k * ne; }
     FieldCsr csr() const { return FieldCsr{ne, rowptr, col, M, K, dir}; }
-    void release() {
-        for (void *q : {(void *)rowptr, (void *)col, (void *)face_edge, (void *)M, (void *)K, (void *)dir,
-                        (void *)dinv, (void *)vec, (void *)partial, (void *)sc})
-            (void)hipFree(q);
-        *this = FieldState();
-    }
+    void release() { *this = FieldState(); }   // the memory is the caller's
 };
 
 // Device state of the non-solenoidal solve (allocated by etpic_ns_setup).
@@ -2532,12 +2547,7 @@ struct NsState {
 
     double *v(int k) const { return vec + (size_t)k * nv; }
     NsCsr csr() const { return NsCsr{nv, rowptr, col, S}; }
-    void release() {
-        for (void *q : {(void *)rowptr, (void *)col, (void *)ev, (void *)S, (void *)dinv, (void *)wall, (void *)vec,
-                        (void *)partial, (void *)sc, (void *)bzero, (void *)ezero})
-            (void)hipFree(q);
-        *this = NsState();
-    }
+    void release() { *this = NsState(); }   // the memory is the caller's
 };
 
 // Device pointers of one (snap[1] NULL) or three envelope snapshots; the dc
@@ -2577,7 +2587,7 @@ struct etpic_ctx {
     float *d_gpush32 = nullptr;       // nt rows of PushRow<float>
     int32_t *d_tetface = nullptr;     // nt*4 face ids (face k opposite vertex k)
     void *d_coef = nullptr;          // nt*24 doubles (float table uses the first half)
-    double *d_coef_env = nullptr;    // nt*kEnvRow complex-envelope rows (first downshifted call)
+    double *d_coef_env = nullptr;    // nt*kEnvRow complex-envelope rows (bound by etpic_ds_rows_bind)
     int32_t *d_v2e_ptr = nullptr;
     int32_t *d_v2e_code = nullptr;
     int32_t *d_e2s_ptr = nullptr;    // edge -> tet-slot CSR (ne+1)
@@ -2587,6 +2597,7 @@ struct etpic_ctx {
     double *d_xyz = nullptr;         // 3*nv vertex coordinates
     int32_t *d_grid = nullptr;       // start tets of the point-location grid
     GridArgs grid{};
+    bool has_ws = false;             // context workspace bound (etpic_workspace_bind)
     unsigned *d_status = nullptr;    // device status word
     unsigned *d_walk_queue = nullptr;  // kWalkQueueCap particle indices
     unsigned *d_slice_queue = nullptr; // kWalkQueueCap slice indices
@@ -2612,16 +2623,21 @@ struct etpic_ctx {
     // 5 events per step (before and after the coefficient kernel, before and
     // after the particle kernel, after the walk kernel), and whether the
     // step's particle kernel also sorted (k_push_sort)
+    // The event sets are created with the context (a fixed pool of kTimingSets);
+    // etpic_kernel_time returns the read sets to the pool.
     std::vector<std::array<hipEvent_t, 5>> timing;
     std::vector<char> timing_sorting;
     std::vector<std::array<hipEvent_t, 5>> spare;
+    // host-side systems built by a size query, kept for the setup call that follows
+    std::unique_ptr<etpic::FieldSystem> field_pending;
+    double field_pending_eps = 0, field_pending_mu = 0;
+    std::unique_ptr<etpic::NsSystem> ns_pending;
+    double ns_pending_eps = 0;
 
     int timing_events(hipEvent_t **ev, bool sorting = false) {
-        if (spare.empty()) {
-            std::array<hipEvent_t, 5> e{};
-            for (auto &x : e) HIP_TRY(hipEventCreate(&x));
-            spare.push_back(e);
-        }
+        if (spare.empty())
+            return fail(ETPIC_EINVAL, "step timing: all %d event sets in use (etpic_kernel_time returns them)",
+                        kTimingSets);
         timing.push_back(spare.back());
         timing_sorting.push_back(sorting ? 1 : 0);
         spare.pop_back();
@@ -2879,7 +2895,8 @@ struct etpic_ctx {
         hipStream_t st = static_cast<hipStream_t>(stream);
         const int remap = (flags & ETPIC_STEP_XCD_REMAP) ? 1 : 0;
         const int64_t n = p->n, nt = host.nt;
-        if (!d_coef_env) HIP_TRY(hipMalloc(&d_coef_env, sizeof(double) * kEnvRow * nt));
+        if (!d_coef_env)
+            return fail(ETPIC_ESTATE, "no downshifted rows bound (etpic_ds_rows_bytes, etpic_ds_rows_bind)");
         hipEvent_t *ev = nullptr;
         if (flags & ETPIC_STEP_TIMING) {
             if (int r = timing_events(&ev)) return r;
@@ -3016,24 +3033,9 @@ struct etpic_ctx {
         for (int i = 0; i < 4; ++i) d.ab[i] = h * kAB[A - 1][i];
     }
 
+    // Forgets the mesh and everything derived from it (the buffers are the
+    // caller's: nothing is freed here).
     void release() {
-        (void)hipFree(d_topo);
-        (void)hipFree(d_grad64);
-        (void)hipFree(d_gpush64);
-        (void)hipFree(d_gpush32);
-        (void)hipFree(d_tetface);
-        (void)hipFree(d_coef);
-        (void)hipFree(d_coef_env);
-        (void)hipFree(d_v2e_ptr);
-        (void)hipFree(d_v2e_code);
-        (void)hipFree(d_e2s_ptr);
-        (void)hipFree(d_e2s_slot);
-        (void)hipFree(d_tetG[0]);
-        (void)hipFree(d_tetG[1]);
-        (void)hipFree(d_xyz);
-        (void)hipFree(d_grid);
-        (void)hipFree(d_count);
-        (void)hipFree(d_tilesum);
         d_topo = nullptr;
         d_grad64 = nullptr;
         d_gpush64 = nullptr;
@@ -3051,6 +3053,8 @@ struct etpic_ctx {
         d_count = d_tilesum = nullptr;
         field.release();
         ns.release();
+        field_pending.reset();
+        ns_pending.reset();
         has_mesh = false;
     }
 };
@@ -3092,7 +3096,17 @@ const float *etpic_ctx::gpush_table<float>() const { return d_gpush32; }
 
 namespace {
 
+// Makes the context's device current; every call that launches kernels goes
+// through here, so it also requires the context workspace (status word, walk
+// queues, reduction words) to be bound.
 int set_device(const etpic_ctx *ctx) {
+    if (!ctx->has_ws) return fail(ETPIC_ESTATE, "no workspace bound (etpic_workspace_bytes, etpic_workspace_bind)");
+    HIP_TRY(hipSetDevice(ctx->device));
+    return ETPIC_OK;
+}
+
+// The device only (setup calls that copy tables but launch nothing).
+int set_device_only(const etpic_ctx *ctx) {
     HIP_TRY(hipSetDevice(ctx->device));
     return ETPIC_OK;
 }
@@ -3177,29 +3191,32 @@ int etpic_create(etpic_ctx **out, int device) {
     if (device < 0 || device >= ndev) return fail(ETPIC_EINVAL, "device %d not present (%d devices)", device, ndev);
     etpic_ctx *c = new etpic_ctx();
     c->device = device;
+    // host-side resources only: the pinned word the run-length statistic is
+    // read into, its event, the step-timing events; device memory comes from
+    // the caller (etpic_workspace_bind, etpic_mesh_upload, ...)
     hipError_t e = hipSetDevice(device);
-    if (e == hipSuccess) e = hipMalloc(&c->d_status, sizeof(unsigned));
-    if (e == hipSuccess) e = hipMalloc(&c->d_red, 2 * sizeof(unsigned long long));
-    if (e == hipSuccess) e = hipMalloc(&c->d_runstat, sizeof(unsigned long long));
     if (e == hipSuccess) e = hipHostMalloc(&c->h_runstat, sizeof(unsigned long long), hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->runstat_ev, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipMalloc(&c->d_walk_queue, sizeof(unsigned) * kWalkQueueCap);
-    if (e == hipSuccess) e = hipMalloc(&c->d_slice_queue, sizeof(unsigned) * kWalkQueueCap);
-    if (e == hipSuccess) e = hipMalloc(&c->d_walk_ctr, 3 * sizeof(unsigned));
-    if (e == hipSuccess) e = hipMemset(c->d_status, 0, sizeof(unsigned));
-    if (e == hipSuccess) e = hipMemset(c->d_walk_ctr, 0, 3 * sizeof(unsigned));
-    if (e == hipSuccess) e = hipDeviceSynchronize();
+    for (int k = 0; k < kTimingSets && e == hipSuccess; ++k) {
+        std::array<hipEvent_t, 5> set{};
+        int made = 0;
+        for (auto &x : set) {
+            e = hipEventCreate(&x);
+            if (e != hipSuccess) break;
+            ++made;
+        }
+        if (e != hipSuccess)
+            for (int i = 0; i < made; ++i) (void)hipEventDestroy(set[i]);
+        else
+            c->spare.push_back(set);
+    }
     int rs = ETPIC_OK;
     if (e == hipSuccess) rs = scratch_address(device, &c->d_scratch);
     if (e != hipSuccess || rs != ETPIC_OK) {
-        (void)hipFree(c->d_status);
-        (void)hipFree(c->d_red);
-        (void)hipFree(c->d_runstat);
         if (c->h_runstat) (void)hipHostFree(c->h_runstat);
         if (c->runstat_ev) (void)hipEventDestroy(c->runstat_ev);
-        (void)hipFree(c->d_walk_queue);
-        (void)hipFree(c->d_slice_queue);
-        (void)hipFree(c->d_walk_ctr);
+        for (auto &set : c->spare)
+            for (auto x : set) (void)hipEventDestroy(x);
         delete c;
         if (rs != ETPIC_OK) return rs;
         return fail(ETPIC_EHIP, "context setup: %s", hipGetErrorString(e));
@@ -3213,14 +3230,8 @@ int etpic_destroy(etpic_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     ctx->release();
-    (void)hipFree(ctx->d_status);
-    (void)hipFree(ctx->d_red);
-    (void)hipFree(ctx->d_runstat);
     (void)hipHostFree(ctx->h_runstat);
     (void)hipEventDestroy(ctx->runstat_ev);
-    (void)hipFree(ctx->d_walk_queue);
-    (void)hipFree(ctx->d_slice_queue);
-    (void)hipFree(ctx->d_walk_ctr);
     for (auto &e : ctx->timing)
         for (auto x : e) (void)hipEventDestroy(x);
     for (auto &e : ctx->spare)
@@ -3229,26 +3240,180 @@ int etpic_destroy(etpic_ctx *ctx) {
     return ETPIC_OK;
 }
 
-int etpic_mesh_upload(etpic_ctx *ctx, int64_t n_vert, const double *xyz_host, int64_t n_tet,
-                      const int32_t *tet_vert_host) {
-    if (!ctx) return fail(ETPIC_EINVAL, "null context");
+}  // extern "C"
+
+namespace {
+
+// Context workspace: the status word, the residual and run-length words, the
+// walk counters and the two walk queues.
+struct WsPtrs {
+    unsigned *status, *walk_ctr, *walk_queue, *slice_queue;
+    unsigned long long *red, *runstat;
+};
+WsPtrs ws_layout(Carve &cv) {
+    WsPtrs w;
+    w.status = cv.take<unsigned>(1);
+    w.walk_ctr = cv.take<unsigned>(3);
+    w.red = cv.take<unsigned long long>(2);
+    w.runstat = cv.take<unsigned long long>(1);
+    w.walk_queue = cv.take<unsigned>(kWalkQueueCap);
+    w.slice_queue = cv.take<unsigned>(kWalkQueueCap);
+    return w;
+}
+
+int check_buffer(const void *buf, size_t bytes, size_t need, const char *what) {
+    if (!buf) return fail(ETPIC_EINVAL, "%s: null buffer", what);
+    if (reinterpret_cast<uintptr_t>(buf) & 255u) return fail(ETPIC_EINVAL, "%s: buffer not 256-byte aligned", what);
+    if (bytes < need) return fail(ETPIC_EINVAL, "%s: buffer of %zu bytes, %zu needed", what, bytes, need);
+    return ETPIC_OK;
+}
+
+// Mesh tables, in this order: tet topology, float64 gradients, float64 and
+// float32 push rows, tet-face ids, the coefficient table, vertex coordinates,
+// point-location start grid, vertex -> edge CSR, sort counters and tile sums,
+// edge -> tet-slot CSR, two per-tet current slot buffers.
+struct MeshPtrs {
+    TetTopo *topo;
+    double *grad64, *gpush64;
+    float *gpush32;
+    int32_t *tetface;
+    void *coef;
+    double *xyz;
+    int32_t *grid, *v2e_ptr, *v2e_code;
+    unsigned *count, *tilesum;
+    int32_t *e2s_ptr, *e2s_slot;
+    double *tetG[2];
+};
+MeshPtrs mesh_layout(Carve &cv, const etpic::HostMesh &M, size_t grid_cells) {
+    const int64_t nt = M.nt;
+    MeshPtrs m;
+    m.topo = cv.take<TetTopo>(nt);
+    m.grad64 = cv.take<double>(12 * nt);
+    m.gpush64 = cv.take<double>((size_t)PushRow<double>::kStride * nt);
+    m.gpush32 = cv.take<float>((size_t)PushRow<float>::kStride * nt);
+    m.tetface = cv.take<int32_t>(4 * nt);
+    m.coef = cv.take<double>(24 * nt);
+    m.xyz = cv.take<double>(3 * M.nv);
+    m.grid = cv.take<int32_t>(grid_cells);
+    m.v2e_ptr = cv.take<int32_t>(M.nv + 1);
+    m.v2e_code = cv.take<int32_t>(2 * M.ne);
+    m.count = cv.take<unsigned>(nt + 1);
+    m.tilesum = cv.take<unsigned>((nt + 1 + kScanTile - 1) / kScanTile);
+    m.e2s_ptr = cv.take<int32_t>(M.ne + 1);
+    m.e2s_slot = cv.take<int32_t>(6 * nt);
+    m.tetG[0] = cv.take<double>(8 * nt);
+    m.tetG[1] = cv.take<double>(8 * nt);
+    return m;
+}
+
+int host_mesh(int64_t n_vert, const double *xyz_host, int64_t n_tet, const int32_t *tet_vert_host,
+              etpic::HostMesh &M, etpic::StartGrid &sg) {
+    if (!xyz_host || !tet_vert_host) return fail(ETPIC_EINVAL, "mesh: null array");
     std::string err;
-    etpic::HostMesh M;
     int rc = etpic::build_host_mesh(n_vert, xyz_host, n_tet, tet_vert_host, M, err);
     if (rc == -1) return fail(ETPIC_EINVAL, "mesh: %s", err.c_str());
     if (rc != 0) return fail(ETPIC_EMESH, "mesh: %s", err.c_str());
-    if (int r = set_device(ctx)) return r;
+    etpic::build_start_grid(M, xyz_host, 2.0, sg);
+    return ETPIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int etpic_workspace_bytes(size_t *bytes) {
+    if (!bytes) return fail(ETPIC_EINVAL, "null argument");
+    Carve cv;
+    (void)ws_layout(cv);
+    *bytes = cv.used;
+    return ETPIC_OK;
+}
+
+int etpic_workspace_bind(etpic_ctx *ctx, void *dev_buf, size_t bytes) {
+    if (!ctx) return fail(ETPIC_EINVAL, "null context");
+    size_t need = 0;
+    (void)etpic_workspace_bytes(&need);
+    if (int r = check_buffer(dev_buf, bytes, need, "workspace")) return r;
+    if (int r = set_device_only(ctx)) return r;
+    HIP_TRY(hipDeviceSynchronize());
+    Carve cv;
+    cv.base = static_cast<char *>(dev_buf);
+    cv.cap = bytes;
+    const WsPtrs w = ws_layout(cv);
+    ctx->d_status = w.status;
+    ctx->d_walk_ctr = w.walk_ctr;
+    ctx->d_red = w.red;
+    ctx->d_runstat = w.runstat;
+    ctx->d_walk_queue = w.walk_queue;
+    ctx->d_slice_queue = w.slice_queue;
+    HIP_TRY(hipMemset(ctx->d_status, 0, sizeof(unsigned)));
+    HIP_TRY(hipMemset(ctx->d_walk_ctr, 0, 3 * sizeof(unsigned)));
+    HIP_TRY(hipDeviceSynchronize());
+    ctx->runstat_pending = false;
+    ctx->has_ws = true;
+    return ETPIC_OK;
+}
+
+int etpic_mesh_sizes(int64_t n_vert, const double *xyz_host, int64_t n_tet, const int32_t *tet_vert_host,
+                     int64_t counts_out[4], size_t *dev_bytes) {
+    if (!counts_out || !dev_bytes) return fail(ETPIC_EINVAL, "null output");
+    etpic::HostMesh M;
+    etpic::StartGrid sg;
+    if (int r = host_mesh(n_vert, xyz_host, n_tet, tet_vert_host, M, sg)) return r;
+    counts_out[0] = M.nv;
+    counts_out[1] = M.ne;
+    counts_out[2] = M.nf;
+    counts_out[3] = M.nt;
+    Carve cv;
+    (void)mesh_layout(cv, M, sg.cell.size());
+    *dev_bytes = cv.used;
+    return ETPIC_OK;
+}
+
+int etpic_mesh_upload(etpic_ctx *ctx, int64_t n_vert, const double *xyz_host, int64_t n_tet,
+                      const int32_t *tet_vert_host, void *dev_buf, size_t bytes) {
+    if (!ctx) return fail(ETPIC_EINVAL, "null context");
+    etpic::HostMesh M;
+    etpic::StartGrid sg;
+    if (int r = host_mesh(n_vert, xyz_host, n_tet, tet_vert_host, M, sg)) return r;
+    size_t need = 0;
+    {
+        Carve cv;
+        (void)mesh_layout(cv, M, sg.cell.size());
+        need = cv.used;
+    }
+    if (int r = check_buffer(dev_buf, bytes, need, "mesh")) return r;
+    if (int r = set_device_only(ctx)) return r;
     HIP_TRY(hipDeviceSynchronize());
     ctx->release();
+    Carve cv;
+    cv.base = static_cast<char *>(dev_buf);
+    cv.cap = bytes;
+    const MeshPtrs m = mesh_layout(cv, M, sg.cell.size());
     const int64_t nt = M.nt;
-    HIP_TRY(hipMalloc(&ctx->d_topo, sizeof(TetTopo) * nt));
-    HIP_TRY(hipMalloc(&ctx->d_grad64, sizeof(double) * 12 * nt));
+    ctx->d_topo = m.topo;
+    ctx->d_grad64 = m.grad64;
+    ctx->d_gpush64 = m.gpush64;
+    ctx->d_gpush32 = m.gpush32;
+    ctx->d_tetface = m.tetface;
+    ctx->d_coef = m.coef;
+    ctx->d_xyz = m.xyz;
+    ctx->d_grid = m.grid;
+    ctx->d_v2e_ptr = m.v2e_ptr;
+    ctx->d_v2e_code = m.v2e_code;
+    ctx->d_count = m.count;
+    ctx->d_tilesum = m.tilesum;
+    ctx->tiles = (nt + 1 + kScanTile - 1) / kScanTile;
+    ctx->d_e2s_ptr = m.e2s_ptr;
+    ctx->d_e2s_slot = m.e2s_slot;
+    ctx->d_tetG[0] = m.tetG[0];
+    ctx->d_tetG[1] = m.tetG[1];
+    ctx->tetG_cur = 0;
     {
         constexpr int s64 = PushRow<double>::kStride, s32 = PushRow<float>::kStride;
-        HIP_TRY(hipMalloc(&ctx->d_gpush64, sizeof(double) * s64 * nt));
-        HIP_TRY(hipMalloc(&ctx->d_gpush32, sizeof(float) * s32 * nt));
         std::vector<double> gp64((size_t)nt * s64, 0.0);
         std::vector<float> gp32((size_t)nt * s32, 0.0f);
+        std::vector<int32_t> tf((size_t)nt * 4);
         for (int64_t t = 0; t < nt; ++t) {
             for (int k = 0; k < 9; ++k) {
                 gp64[s64 * t + k] = M.grad[12 * t + 3 + k];
@@ -3256,47 +3421,29 @@ int etpic_mesh_upload(etpic_ctx *ctx, int64_t n_vert, const double *xyz_host, in
             }
             std::memcpy(&gp64[s64 * t + PushRow<double>::kEdges], M.topo[t].e, sizeof(int32_t) * 6);
             std::memcpy(&gp32[s32 * t + PushRow<float>::kEdges], M.topo[t].e, sizeof(int32_t) * 6);
+            std::memcpy(&tf[4 * t], M.topo[t].f, sizeof(int32_t) * 4);
         }
         HIP_TRY(hipMemcpy(ctx->d_gpush64, gp64.data(), sizeof(double) * s64 * nt, hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(ctx->d_gpush32, gp32.data(), sizeof(float) * s32 * nt, hipMemcpyHostToDevice));
-        std::vector<int32_t> tf((size_t)nt * 4);
-        for (int64_t t = 0; t < nt; ++t) std::memcpy(&tf[4 * t], M.topo[t].f, sizeof(int32_t) * 4);
-        HIP_TRY(hipMalloc(&ctx->d_tetface, sizeof(int32_t) * 4 * nt));
         HIP_TRY(hipMemcpy(ctx->d_tetface, tf.data(), sizeof(int32_t) * 4 * nt, hipMemcpyHostToDevice));
     }
-    HIP_TRY(hipMalloc(&ctx->d_coef, sizeof(double) * 24 * nt));
-    {
-        etpic::StartGrid sg;
-        etpic::build_start_grid(M, xyz_host, 2.0, sg);
-        HIP_TRY(hipMalloc(&ctx->d_xyz, sizeof(double) * 3 * M.nv));
-        HIP_TRY(hipMalloc(&ctx->d_grid, sizeof(int32_t) * sg.cell.size()));
-        HIP_TRY(hipMemcpy(ctx->d_xyz, xyz_host, sizeof(double) * 3 * M.nv, hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(ctx->d_grid, sg.cell.data(), sizeof(int32_t) * sg.cell.size(), hipMemcpyHostToDevice));
-        ctx->grid.cell = ctx->d_grid;
-        for (int d = 0; d < 3; ++d) {
-            ctx->grid.lo[d] = sg.lo[d];
-            ctx->grid.inv[d] = sg.inv[d];
-            ctx->grid.dims[d] = sg.dims[d];
-        }
+    HIP_TRY(hipMemcpy(ctx->d_xyz, xyz_host, sizeof(double) * 3 * M.nv, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(ctx->d_grid, sg.cell.data(), sizeof(int32_t) * sg.cell.size(), hipMemcpyHostToDevice));
+    ctx->grid.cell = ctx->d_grid;
+    for (int d = 0; d < 3; ++d) {
+        ctx->grid.lo[d] = sg.lo[d];
+        ctx->grid.inv[d] = sg.inv[d];
+        ctx->grid.dims[d] = sg.dims[d];
     }
-    HIP_TRY(hipMalloc(&ctx->d_v2e_ptr, sizeof(int32_t) * (M.nv + 1)));
-    HIP_TRY(hipMalloc(&ctx->d_v2e_code, sizeof(int32_t) * 2 * M.ne));
-    HIP_TRY(hipMalloc(&ctx->d_count, sizeof(unsigned) * (nt + 1)));
-    ctx->tiles = (nt + 1 + kScanTile - 1) / kScanTile;
-    HIP_TRY(hipMalloc(&ctx->d_tilesum, sizeof(unsigned) * ctx->tiles));
     HIP_TRY(hipMemcpy(ctx->d_topo, M.topo.data(), sizeof(TetTopo) * nt, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(ctx->d_grad64, M.grad.data(), sizeof(double) * 12 * nt, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(ctx->d_v2e_ptr, M.v2e_ptr.data(), sizeof(int32_t) * (M.nv + 1), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(ctx->d_v2e_code, M.v2e_code.data(), sizeof(int32_t) * 2 * M.ne, hipMemcpyHostToDevice));
-    HIP_TRY(hipMalloc(&ctx->d_e2s_ptr, sizeof(int32_t) * (M.ne + 1)));
-    HIP_TRY(hipMalloc(&ctx->d_e2s_slot, sizeof(int32_t) * 6 * nt));
     HIP_TRY(hipMemcpy(ctx->d_e2s_ptr, M.e2s_ptr.data(), sizeof(int32_t) * (M.ne + 1), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(ctx->d_e2s_slot, M.e2s_slot.data(), sizeof(int32_t) * 6 * nt, hipMemcpyHostToDevice));
-    for (int b = 0; b < 2; ++b) {
-        HIP_TRY(hipMalloc(&ctx->d_tetG[b], sizeof(double) * 8 * nt));
-        HIP_TRY(hipMemset(ctx->d_tetG[b], 0, sizeof(double) * 8 * nt));
-    }
-    ctx->tetG_cur = 0;
+    HIP_TRY(hipMemset(ctx->d_tetG[0], 0, sizeof(double) * 8 * nt));
+    HIP_TRY(hipMemset(ctx->d_tetG[1], 0, sizeof(double) * 8 * nt));
+    HIP_TRY(hipDeviceSynchronize());
     ctx->host = std::move(M);
     ctx->has_mesh = true;
     return ETPIC_OK;
@@ -3436,6 +3583,22 @@ int etpic_sort_run_steps(etpic_ctx *ctx, const etpic_particles *src, const etpic
 
 static size_t ds_history_size(int64_t n, int precision) {
     return (precision == ETPIC_FP64 ? sizeof(double) : sizeof(float)) * (size_t)kDsArrays * (size_t)n;
+}
+
+int etpic_ds_rows_bytes(const etpic_ctx *ctx, size_t *bytes) {
+    if (!ctx || !bytes) return fail(ETPIC_EINVAL, "null argument");
+    if (!ctx->has_mesh) return fail(ETPIC_ESTATE, "no mesh uploaded");
+    *bytes = sizeof(double) * (size_t)kEnvRow * (size_t)ctx->host.nt;
+    return ETPIC_OK;
+}
+
+int etpic_ds_rows_bind(etpic_ctx *ctx, void *dev_buf, size_t bytes) {
+    if (!ctx) return fail(ETPIC_EINVAL, "null context");
+    size_t need = 0;
+    if (int r = etpic_ds_rows_bytes(ctx, &need)) return r;
+    if (int r = check_buffer(dev_buf, bytes, need, "downshifted rows")) return r;
+    ctx->d_coef_env = static_cast<double *>(dev_buf);
+    return ETPIC_OK;
 }
 
 int etpic_ds_history_bytes(int64_t n, int precision, size_t *bytes_out) {
@@ -3708,25 +3871,77 @@ int etpic_sort(etpic_ctx *ctx, const etpic_particles *src, const etpic_particles
     return ctx->sort<float>(src, dst, st);
 }
 
-int etpic_field_setup(etpic_ctx *ctx, double dt, double omega, double eps, double mu) {
+}  // extern "C"
+
+namespace {
+
+// Field solver arrays: CSR row pointers, columns, M and K values, Dirichlet
+// mask, face -> edge table, Jacobi inverse diagonal, 9 complex work vectors,
+// block partials and the 12 iteration scalars.
+struct FieldPtrs2 {
+    int32_t *rowptr, *col, *face_edge;
+    double *M, *K, *partial, *sc;
+    uint8_t *dir;
+    double2 *dinv, *vec;
+};
+FieldPtrs2 field_layout(Carve &cv, int64_t ne, int64_t nf, int64_t nnz) {
+    FieldPtrs2 f;
+    const int64_t nb = std::max<int64_t>(grid_for(ne), kNsBlocks);
+    f.rowptr = cv.take<int32_t>(ne + 1);
+    f.col = cv.take<int32_t>(nnz);
+    f.M = cv.take<double>(nnz);
+    f.K = cv.take<double>(nnz);
+    f.dir = cv.take<uint8_t>(ne);
+    f.face_edge = cv.take<int32_t>(3 * nf);
+    f.dinv = cv.take<double2>(ne);
+    f.vec = cv.take<double2>(9 * ne);
+    f.partial = cv.take<double>(4 * (nb + kNsBlocks));
+    f.sc = cv.take<double>(12);
+    return f;
+}
+
+// The host field system for (eps, mu): the one a size query built, else a new one.
+int field_system(etpic_ctx *ctx, double eps, double mu) {
+    if (ctx->field_pending && ctx->field_pending_eps == eps && ctx->field_pending_mu == mu) return ETPIC_OK;
+    std::string err;
+    auto S = std::make_unique<etpic::FieldSystem>();
+    if (etpic::build_field_system(ctx->host, eps, mu, *S, err) != 0) return fail(ETPIC_EINVAL, "field: %s", err.c_str());
+    ctx->field_pending = std::move(S);
+    ctx->field_pending_eps = eps;
+    ctx->field_pending_mu = mu;
+    return ETPIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int etpic_field_bytes(etpic_ctx *ctx, double eps, double mu, size_t *bytes) {
+    if (!ctx || !bytes) return fail(ETPIC_EINVAL, "null argument");
+    if (!ctx->has_mesh) return fail(ETPIC_ESTATE, "no mesh uploaded");
+    if (!(eps > 0.0) || !(mu > 0.0)) return fail(ETPIC_EINVAL, "eps, mu must be positive");
+    if (int r = field_system(ctx, eps, mu)) return r;
+    const etpic::FieldSystem &S = *ctx->field_pending;
+    Carve cv;
+    (void)field_layout(cv, S.ne, S.nf, S.nnz);
+    *bytes = cv.used;
+    return ETPIC_OK;
+}
+
+int etpic_field_setup(etpic_ctx *ctx, double dt, double omega, double eps, double mu, void *dev_buf, size_t bytes) {
     if (!ctx) return fail(ETPIC_EINVAL, "null context");
     if (!ctx->has_mesh) return fail(ETPIC_ESTATE, "no mesh uploaded");
     if (!(dt > 0.0) || !std::isfinite(omega) || !(eps > 0.0) || !(mu > 0.0))
         return fail(ETPIC_EINVAL, "dt, eps, mu must be positive and omega finite");
-    std::string err;
-    etpic::FieldSystem S;
-    if (etpic::build_field_system(ctx->host, eps, mu, S, err) != 0) return fail(ETPIC_EINVAL, "field: %s", err.c_str());
-    if (int r = set_device(ctx)) return r;
-    HIP_TRY(hipDeviceSynchronize());
-    FieldState &F = ctx->field;
-    F.release();
-    F.dt = dt;
-    F.omega = omega;
-    F.eps = eps;
-    F.mu = mu;
-    F.ne = S.ne;
-    F.nf = S.nf;
-    F.nnz = S.nnz;
+    if (int r = field_system(ctx, eps, mu)) return r;
+    const etpic::FieldSystem &S = *ctx->field_pending;
+    size_t need = 0;
+    {
+        Carve cv;
+        (void)field_layout(cv, S.ne, S.nf, S.nnz);
+        need = cv.used;
+    }
+    if (int r = check_buffer(dev_buf, bytes, need, "field")) return r;
     const int64_t ne = S.ne;
     // Jacobi preconditioner: inverse diagonal of A = alpha M + beta K
     const double ar = 1.0 - 0.25 * omega * omega * dt * dt, ai = omega * dt, beta = 0.25 * dt * dt;
@@ -3742,17 +3957,32 @@ int etpic_field_setup(etpic_ctx *ctx, double dt, double omega, double eps, doubl
         if (!(den > 0.0)) return fail(ETPIC_EMESH, "field: zero diagonal at edge %lld", (long long)i);
         dinv[i] = make_double2(dr / den, -di / den);
     }
+    if (int r = set_device_only(ctx)) return r;
+    HIP_TRY(hipDeviceSynchronize());
+    FieldState &F = ctx->field;
+    F.release();
+    F.dt = dt;
+    F.omega = omega;
+    F.eps = eps;
+    F.mu = mu;
+    F.ne = S.ne;
+    F.nf = S.nf;
+    F.nnz = S.nnz;
     F.nb = std::max<int64_t>(grid_for(ne), kNsBlocks);
-    HIP_TRY(hipMalloc(&F.rowptr, sizeof(int32_t) * (ne + 1)));
-    HIP_TRY(hipMalloc(&F.col, sizeof(int32_t) * S.nnz));
-    HIP_TRY(hipMalloc(&F.M, sizeof(double) * S.nnz));
-    HIP_TRY(hipMalloc(&F.K, sizeof(double) * S.nnz));
-    HIP_TRY(hipMalloc(&F.dir, sizeof(uint8_t) * ne));
-    HIP_TRY(hipMalloc(&F.face_edge, sizeof(int32_t) * 3 * S.nf));
-    HIP_TRY(hipMalloc(&F.dinv, sizeof(double2) * ne));
-    HIP_TRY(hipMalloc(&F.vec, sizeof(double2) * 9 * ne));
-    HIP_TRY(hipMalloc(&F.partial, sizeof(double) * 4 * (F.nb + kNsBlocks)));
-    HIP_TRY(hipMalloc(&F.sc, sizeof(double) * 12));
+    Carve cv;
+    cv.base = static_cast<char *>(dev_buf);
+    cv.cap = bytes;
+    const FieldPtrs2 f = field_layout(cv, S.ne, S.nf, S.nnz);
+    F.rowptr = f.rowptr;
+    F.col = f.col;
+    F.M = f.M;
+    F.K = f.K;
+    F.dir = f.dir;
+    F.face_edge = f.face_edge;
+    F.dinv = f.dinv;
+    F.vec = f.vec;
+    F.partial = f.partial;
+    F.sc = f.sc;
     HIP_TRY(hipMemcpy(F.rowptr, S.rowptr.data(), sizeof(int32_t) * (ne + 1), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(F.col, S.col.data(), sizeof(int32_t) * S.nnz, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(F.M, S.M.data(), sizeof(double) * S.nnz, hipMemcpyHostToDevice));
@@ -3761,6 +3991,7 @@ int etpic_field_setup(etpic_ctx *ctx, double dt, double omega, double eps, doubl
     HIP_TRY(hipMemcpy(F.face_edge, S.face_edge.data(), sizeof(int32_t) * 3 * S.nf, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(F.dinv, dinv.data(), sizeof(double2) * ne, hipMemcpyHostToDevice));
     F.ready = true;
+    ctx->field_pending.reset();
     return ETPIC_OK;
 }
 
@@ -3840,14 +4071,73 @@ int etpic_field_step(etpic_ctx *ctx, double t_next, double *u, double *v, double
     return ETPIC_OK;
 }
 
-int etpic_ns_setup(etpic_ctx *ctx, double eps) {
+}  // extern "C"
+
+namespace {
+
+// Gauss-law solver arrays: CSR row pointers, columns, edge -> vertex table,
+// values, Jacobi inverse diagonal, wall mask, 8 work vectors, block partials,
+// the 12 iteration scalars, and zero face / edge envelopes.
+struct NsPtrs {
+    int32_t *rowptr, *col, *ev;
+    double *S, *dinv, *vec, *partial, *sc, *bzero, *ezero;
+    uint8_t *wall;
+};
+NsPtrs ns_layout(Carve &cv, int64_t nv, int64_t ne, int64_t nf, int64_t nnz) {
+    NsPtrs n;
+    n.rowptr = cv.take<int32_t>(nv + 1);
+    n.col = cv.take<int32_t>(nnz);
+    n.ev = cv.take<int32_t>(2 * ne);
+    n.S = cv.take<double>(nnz);
+    n.dinv = cv.take<double>(nv);
+    n.wall = cv.take<uint8_t>(nv);
+    n.vec = cv.take<double>(8 * nv);
+    n.partial = cv.take<double>(8 * kNsBlocks);
+    n.sc = cv.take<double>(12);
+    n.bzero = cv.take<double>(2 * nf);
+    n.ezero = cv.take<double>(2 * ne);
+    return n;
+}
+
+int ns_system(etpic_ctx *ctx, double eps) {
+    if (ctx->ns_pending && ctx->ns_pending_eps == eps) return ETPIC_OK;
+    std::string err;
+    auto S = std::make_unique<etpic::NsSystem>();
+    if (etpic::build_ns_system(ctx->host, eps, *S, err) != 0) return fail(ETPIC_EINVAL, "ns: %s", err.c_str());
+    ctx->ns_pending = std::move(S);
+    ctx->ns_pending_eps = eps;
+    return ETPIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int etpic_ns_bytes(etpic_ctx *ctx, double eps, size_t *bytes) {
+    if (!ctx || !bytes) return fail(ETPIC_EINVAL, "null argument");
+    if (!ctx->has_mesh) return fail(ETPIC_ESTATE, "no mesh uploaded");
+    if (!(eps > 0.0) || !std::isfinite(eps)) return fail(ETPIC_EINVAL, "eps must be positive");
+    if (int r = ns_system(ctx, eps)) return r;
+    Carve cv;
+    (void)ns_layout(cv, ctx->ns_pending->nv, ctx->host.ne, ctx->host.nf, ctx->ns_pending->nnz);
+    *bytes = cv.used;
+    return ETPIC_OK;
+}
+
+int etpic_ns_setup(etpic_ctx *ctx, double eps, void *dev_buf, size_t bytes) {
     if (!ctx) return fail(ETPIC_EINVAL, "null context");
     if (!ctx->has_mesh) return fail(ETPIC_ESTATE, "no mesh uploaded");
     if (!(eps > 0.0) || !std::isfinite(eps)) return fail(ETPIC_EINVAL, "eps must be positive");
-    std::string err;
-    etpic::NsSystem S;
-    if (etpic::build_ns_system(ctx->host, eps, S, err) != 0) return fail(ETPIC_EINVAL, "ns: %s", err.c_str());
-    const int64_t nv = S.nv, ne = ctx->host.ne;
+    if (int r = ns_system(ctx, eps)) return r;
+    const etpic::NsSystem &S = *ctx->ns_pending;
+    const int64_t nv = S.nv, ne = ctx->host.ne, nf = ctx->host.nf;
+    size_t need = 0;
+    {
+        Carve cv;
+        (void)ns_layout(cv, nv, ne, nf, S.nnz);
+        need = cv.used;
+    }
+    if (int r = check_buffer(dev_buf, bytes, need, "ns")) return r;
     std::vector<double> dinv((size_t)nv, 0.0);
     for (int64_t i = 0; i < nv; ++i) {
         double d = 0.0;
@@ -3856,7 +4146,7 @@ int etpic_ns_setup(etpic_ctx *ctx, double eps) {
         if (!(d > 0.0)) return fail(ETPIC_EMESH, "ns: non-positive diagonal at node %lld", (long long)i);
         dinv[i] = 1.0 / d;
     }
-    if (int r = set_device(ctx)) return r;
+    if (int r = set_device_only(ctx)) return r;
     HIP_TRY(hipDeviceSynchronize());
     NsState &N = ctx->ns;
     N.release();
@@ -3865,20 +4155,24 @@ int etpic_ns_setup(etpic_ctx *ctx, double eps) {
     N.ne = ne;
     N.nnz = S.nnz;
     for (uint8_t b : S.wall) N.n_wall += b;
-    HIP_TRY(hipMalloc(&N.rowptr, sizeof(int32_t) * (nv + 1)));
-    HIP_TRY(hipMalloc(&N.col, sizeof(int32_t) * S.nnz));
-    HIP_TRY(hipMalloc(&N.ev, sizeof(int32_t) * 2 * ne));
-    HIP_TRY(hipMalloc(&N.S, sizeof(double) * S.nnz));
-    HIP_TRY(hipMalloc(&N.dinv, sizeof(double) * nv));
-    HIP_TRY(hipMalloc(&N.wall, sizeof(uint8_t) * nv));
-    HIP_TRY(hipMalloc(&N.vec, sizeof(double) * 8 * nv));
-    HIP_TRY(hipMalloc(&N.partial, sizeof(double) * 8 * kNsBlocks));
-    HIP_TRY(hipMalloc(&N.sc, sizeof(double) * 12));
+    Carve cv;
+    cv.base = static_cast<char *>(dev_buf);
+    cv.cap = bytes;
+    const NsPtrs n = ns_layout(cv, nv, ne, nf, S.nnz);
+    N.rowptr = n.rowptr;
+    N.col = n.col;
+    N.ev = n.ev;
+    N.S = n.S;
+    N.dinv = n.dinv;
+    N.wall = n.wall;
+    N.vec = n.vec;
+    N.partial = n.partial;
+    N.sc = n.sc;
+    N.bzero = n.bzero;
+    N.ezero = n.ezero;
     HIP_TRY(hipMemset(N.sc, 0, sizeof(double) * 12));
-    HIP_TRY(hipMalloc(&N.bzero, sizeof(double) * 2 * ctx->host.nf));
     HIP_TRY(hipMemset(N.vec, 0, sizeof(double) * 8 * nv));
-    HIP_TRY(hipMemset(N.bzero, 0, sizeof(double) * 2 * ctx->host.nf));
-    HIP_TRY(hipMalloc(&N.ezero, sizeof(double) * 2 * ne));
+    HIP_TRY(hipMemset(N.bzero, 0, sizeof(double) * 2 * nf));
     HIP_TRY(hipMemset(N.ezero, 0, sizeof(double) * 2 * ne));
     HIP_TRY(hipMemcpy(N.rowptr, S.rowptr.data(), sizeof(int32_t) * (nv + 1), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(N.col, S.col.data(), sizeof(int32_t) * S.nnz, hipMemcpyHostToDevice));
@@ -3886,7 +4180,9 @@ int etpic_ns_setup(etpic_ctx *ctx, double eps) {
     HIP_TRY(hipMemcpy(N.S, S.S.data(), sizeof(double) * S.nnz, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(N.dinv, dinv.data(), sizeof(double) * nv, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(N.wall, S.wall.data(), sizeof(uint8_t) * nv, hipMemcpyHostToDevice));
+    HIP_TRY(hipDeviceSynchronize());
     N.ready = true;
+    ctx->ns_pending.reset();
     return ETPIC_OK;
 }
 

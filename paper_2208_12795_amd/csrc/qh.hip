@@ -450,23 +450,68 @@ struct etpic_qh {
     double2 *evec = nullptr;   // 3 complex edge vectors: t1, t2, t3
     double *partial = nullptr; // two sets of 4 per block
     double *sc = nullptr;      // 12 scalars
+    bool bound = false;        // device part in the caller's buffer (etpic_qh_bind)
+    // the host tables the device part is filled from
+    std::vector<int4> h_tf, h_tn;
+    std::vector<uint8_t> h_tneg, h_fneg;
+    std::vector<int2> h_ft;
+    std::vector<int32_t> h_rowptr, h_col, h_ev, h_v2e_ptr, h_v2e_code;
+    std::vector<double> h_M, h_dinv;
 
-    void release() {
-        for (void *q : {(void *)tf, (void *)tn, (void *)tneg, (void *)ft, (void *)fneg, (void *)tv, (void *)rowptr,
-                        (void *)col, (void *)ev, (void *)v2e_ptr, (void *)v2e_code, (void *)M, (void *)dinv,
-                        (void *)nvec, (void *)evec, (void *)partial, (void *)sc})
-            (void)hipFree(q);
-    }
     TetFaces tet_faces() const { return TetFaces{tf, tn, tneg}; }
     EdgeCsr csr() const { return EdgeCsr{ne, rowptr, col, M}; }
 };
 
 namespace {
 
+// Arrays carved from the caller's buffer in a fixed order, each on a 256-byte
+// boundary (a null base only counts the bytes).
+struct QhCarve {
+    char *base = nullptr;
+    size_t used = 0;
+    template <typename T>
+    T *take(size_t count) {
+        const size_t off = (used + 255) & ~(size_t)255;
+        used = off + sizeof(T) * std::max<size_t>(count, 1);
+        return base ? reinterpret_cast<T *>(base + off) : nullptr;
+    }
+};
+
+// The device part of the object: the host tables' copies, then the work
+// vectors, partials and scalars.
+struct QhPtrs {
+    int4 *tf, *tn;
+    uint8_t *tneg, *fneg;
+    int2 *ft;
+    int32_t *rowptr, *col, *ev, *v2e_ptr, *v2e_code;
+    double *M, *dinv, *partial, *sc;
+    double2 *tv, *nvec, *evec;
+};
+QhPtrs qh_layout(const etpic_qh *Q, QhCarve &cv) {
+    QhPtrs d;
+    d.tf = cv.take<int4>(Q->h_tf.size());
+    d.tn = cv.take<int4>(Q->h_tn.size());
+    d.tneg = cv.take<uint8_t>(Q->h_tneg.size());
+    d.ft = cv.take<int2>(Q->h_ft.size());
+    d.fneg = cv.take<uint8_t>(Q->h_fneg.size());
+    d.rowptr = cv.take<int32_t>(Q->h_rowptr.size());
+    d.col = cv.take<int32_t>(Q->h_col.size());
+    d.M = cv.take<double>(Q->h_M.size());
+    d.ev = cv.take<int32_t>(Q->h_ev.size());
+    d.v2e_ptr = cv.take<int32_t>(Q->h_v2e_ptr.size());
+    d.v2e_code = cv.take<int32_t>(Q->h_v2e_code.size());
+    d.dinv = cv.take<double>(Q->h_dinv.size());
+    d.tv = cv.take<double2>(4 * Q->nt);
+    d.nvec = cv.take<double2>(5 * Q->nv);
+    d.evec = cv.take<double2>(3 * Q->ne);
+    d.partial = cv.take<double>(8 * kQBlocks);
+    d.sc = cv.take<double>(12);
+    return d;
+}
+
 template <typename T>
-int upload(T **dst, const std::vector<T> &src) {
-    QH_TRY(hipMalloc(dst, sizeof(T) * std::max<size_t>(src.size(), 1)));
-    if (!src.empty()) QH_TRY(hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice));
+int upload(T *dst, const std::vector<T> &src) {
+    if (!src.empty()) QH_TRY(hipMemcpy(dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice));
     return ETPIC_OK;
 }
 
@@ -562,25 +607,18 @@ int qh_build(etpic_qh *Q, int64_t nv, const double *xyz, int64_t nt, const int32
     QH_TRY(hipGetDeviceCount(&count));
     if (Q->device < 0 || Q->device >= count)
         return qfail(ETPIC_EINVAL, "device %d not present (%d devices)", Q->device, count);
-    QH_TRY(hipSetDevice(Q->device));
-    if (int r = upload(&Q->tf, tf)) return r;
-    if (int r = upload(&Q->tn, tn)) return r;
-    if (int r = upload(&Q->tneg, tneg)) return r;
-    if (int r = upload(&Q->ft, ft)) return r;
-    if (int r = upload(&Q->fneg, fneg)) return r;
-    if (int r = upload(&Q->rowptr, S.rowptr)) return r;
-    if (int r = upload(&Q->col, S.col)) return r;
-    if (int r = upload(&Q->M, S.M)) return r;
-    if (int r = upload(&Q->ev, H.edges)) return r;
-    if (int r = upload(&Q->v2e_ptr, H.v2e_ptr)) return r;
-    if (int r = upload(&Q->v2e_code, H.v2e_code)) return r;
-    if (int r = upload(&Q->dinv, dinv)) return r;
-    QH_TRY(hipMalloc(&Q->tv, sizeof(double2) * 4 * nt));
-    QH_TRY(hipMalloc(&Q->nvec, sizeof(double2) * 5 * H.nv));
-    QH_TRY(hipMalloc(&Q->evec, sizeof(double2) * 3 * H.ne));
-    QH_TRY(hipMalloc(&Q->partial, sizeof(double) * 8 * kQBlocks));
-    QH_TRY(hipMalloc(&Q->sc, sizeof(double) * 12));
-    QH_TRY(hipMemset(Q->sc, 0, sizeof(double) * 12));
+    Q->h_tf = std::move(tf);
+    Q->h_tn = std::move(tn);
+    Q->h_tneg = std::move(tneg);
+    Q->h_ft = std::move(ft);
+    Q->h_fneg = std::move(fneg);
+    Q->h_rowptr = std::move(S.rowptr);
+    Q->h_col = std::move(S.col);
+    Q->h_M = std::move(S.M);
+    Q->h_ev = std::move(H.edges);
+    Q->h_v2e_ptr = std::move(H.v2e_ptr);
+    Q->h_v2e_code = std::move(H.v2e_code);
+    Q->h_dinv = std::move(dinv);
     return ETPIC_OK;
 }
 
@@ -669,7 +707,6 @@ int etpic_qh_create(etpic_qh **out, int device, int64_t nv, const double *xyz, i
     etpic_qh *Q = new etpic_qh();
     Q->device = device;
     if (int r = qh_build(Q, nv, xyz, nt, tet_vert, eps)) {
-        Q->release();
         delete Q;
         return r;
     }
@@ -677,11 +714,64 @@ int etpic_qh_create(etpic_qh **out, int device, int64_t nv, const double *xyz, i
     return ETPIC_OK;
 }
 
+int etpic_qh_bytes(const etpic_qh *qh, size_t *bytes) {
+    if (!qh || !bytes) return qfail(ETPIC_EINVAL, "null argument");
+    QhCarve cv;
+    (void)qh_layout(qh, cv);
+    *bytes = cv.used;
+    return ETPIC_OK;
+}
+
+int etpic_qh_bind(etpic_qh *qh, void *dev_buf, size_t bytes) {
+    if (!qh || !dev_buf) return qfail(ETPIC_EINVAL, "null argument");
+    if (reinterpret_cast<uintptr_t>(dev_buf) & 255u) return qfail(ETPIC_EINVAL, "buffer not 256-byte aligned");
+    size_t need = 0;
+    if (int r = etpic_qh_bytes(qh, &need)) return r;
+    if (bytes < need) return qfail(ETPIC_EINVAL, "buffer of %zu bytes, %zu needed", bytes, need);
+    QH_TRY(hipSetDevice(qh->device));
+    QH_TRY(hipDeviceSynchronize());
+    QhCarve cv;
+    cv.base = static_cast<char *>(dev_buf);
+    const QhPtrs d = qh_layout(qh, cv);
+    qh->tf = d.tf;
+    qh->tn = d.tn;
+    qh->tneg = d.tneg;
+    qh->fneg = d.fneg;
+    qh->ft = d.ft;
+    qh->rowptr = d.rowptr;
+    qh->col = d.col;
+    qh->ev = d.ev;
+    qh->v2e_ptr = d.v2e_ptr;
+    qh->v2e_code = d.v2e_code;
+    qh->M = d.M;
+    qh->dinv = d.dinv;
+    qh->partial = d.partial;
+    qh->sc = d.sc;
+    qh->tv = d.tv;
+    qh->nvec = d.nvec;
+    qh->evec = d.evec;
+    if (int r = upload(qh->tf, qh->h_tf)) return r;
+    if (int r = upload(qh->tn, qh->h_tn)) return r;
+    if (int r = upload(qh->tneg, qh->h_tneg)) return r;
+    if (int r = upload(qh->ft, qh->h_ft)) return r;
+    if (int r = upload(qh->fneg, qh->h_fneg)) return r;
+    if (int r = upload(qh->rowptr, qh->h_rowptr)) return r;
+    if (int r = upload(qh->col, qh->h_col)) return r;
+    if (int r = upload(qh->M, qh->h_M)) return r;
+    if (int r = upload(qh->ev, qh->h_ev)) return r;
+    if (int r = upload(qh->v2e_ptr, qh->h_v2e_ptr)) return r;
+    if (int r = upload(qh->v2e_code, qh->h_v2e_code)) return r;
+    if (int r = upload(qh->dinv, qh->h_dinv)) return r;
+    QH_TRY(hipMemset(qh->sc, 0, sizeof(double) * 12));
+    QH_TRY(hipDeviceSynchronize());
+    qh->bound = true;
+    return ETPIC_OK;
+}
+
 void etpic_qh_destroy(etpic_qh *qh) {
     if (!qh) return;
     (void)hipSetDevice(qh->device);
     (void)hipDeviceSynchronize();
-    qh->release();
     delete qh;
 }
 
@@ -698,6 +788,7 @@ int etpic_qh_counts(const etpic_qh *qh, int64_t counts_out[5]) {
 int etpic_qh_project_b(etpic_qh *qh, const double *b, double *b_out, double tol, int max_iter, int *iters_out,
                        double *resid_out, void *stream) {
     if (!qh || !b || !b_out) return qfail(ETPIC_EINVAL, "null argument");
+    if (!qh->bound) return qfail(ETPIC_ESTATE, "no device buffer bound (etpic_qh_bytes, etpic_qh_bind)");
     if (!(tol > 0.0) || max_iter < 1) return qfail(ETPIC_EINVAL, "bad tol / max_iter");
     QH_TRY(hipSetDevice(qh->device));
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -731,6 +822,7 @@ int etpic_qh_project_b(etpic_qh *qh, const double *b, double *b_out, double tol,
 int etpic_qh_project_e(etpic_qh *qh, const double *d, double *d_sigma, double *d_lambda, double *e_ns, double tol,
                        int max_iter, int *iters_out, double *resid_out, void *stream) {
     if (!qh || !d) return qfail(ETPIC_EINVAL, "null argument");
+    if (!qh->bound) return qfail(ETPIC_ESTATE, "no device buffer bound (etpic_qh_bytes, etpic_qh_bind)");
     if (!d_sigma && !d_lambda && !e_ns) return qfail(ETPIC_EINVAL, "no output requested");
     if (d_sigma == d || d_lambda == d || (d_sigma && d_sigma == d_lambda))
         return qfail(ETPIC_EINVAL, "outputs alias the input or each other");

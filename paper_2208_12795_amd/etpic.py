@@ -28,18 +28,19 @@ EM_SPLIT = 128
 HOP_CAP = 64
 
 EXPORTS = (
-    "etpic_last_error", "etpic_create", "etpic_destroy", "etpic_mesh_upload", "etpic_mesh_canonical",
+    "etpic_last_error", "etpic_create", "etpic_destroy", "etpic_workspace_bytes", "etpic_workspace_bind",
+    "etpic_mesh_sizes", "etpic_mesh_upload", "etpic_mesh_canonical",
     "etpic_mesh_counts", "etpic_mesh_edges", "etpic_mesh_faces", "etpic_gather_push_deposit", "etpic_sort",
     "etpic_vertex_charge", "etpic_gauss_residual", "etpic_gauss_residual_noalloc", "etpic_stream_probe",
     "etpic_last_push_slices", "etpic_kernel_time",
     "etpic_check",
     "etpic_adjoint_workspace", "etpic_forward_checkpointed", "etpic_backward",
-    "etpic_field_setup", "etpic_field_nnz", "etpic_field_spmv", "etpic_field_step",
+    "etpic_field_bytes", "etpic_field_setup", "etpic_field_nnz", "etpic_field_spmv", "etpic_field_step",
     "etpic_particles_locate", "etpic_particles_positions", "etpic_coarse_step", "etpic_run_steps",
-    "etpic_sort_run_steps", "etpic_ds_history_bytes", "etpic_ds_steps", "etpic_ds_sort",
-    "etpic_ns_setup", "etpic_ns_info", "etpic_ns_solve", "etpic_ns_run_steps", "etpic_ns_correct", "etpic_em_steps",
+    "etpic_sort_run_steps", "etpic_ds_rows_bytes", "etpic_ds_rows_bind", "etpic_ds_history_bytes", "etpic_ds_steps", "etpic_ds_sort",
+    "etpic_ns_bytes", "etpic_ns_setup", "etpic_ns_info", "etpic_ns_solve", "etpic_ns_run_steps", "etpic_ns_correct", "etpic_em_steps",
     "etpic_sol_source",
-    "etpic_qh_last_error", "etpic_qh_create", "etpic_qh_destroy", "etpic_qh_counts", "etpic_qh_project_b",
+    "etpic_qh_last_error", "etpic_qh_create", "etpic_qh_bytes", "etpic_qh_bind", "etpic_qh_destroy", "etpic_qh_counts", "etpic_qh_project_b",
     "etpic_qh_project_e", "etpic_tree_cotree",
 )
 
@@ -78,7 +79,17 @@ def lib():
     L.etpic_last_error.restype = C.c_char_p
     L.etpic_create.argtypes = [C.POINTER(vp), C.c_int]
     L.etpic_destroy.argtypes = [vp]
-    L.etpic_mesh_upload.argtypes = [vp, C.c_int64, dp, C.c_int64, i32p]
+    szp = C.POINTER(C.c_size_t)
+    L.etpic_workspace_bytes.argtypes = [szp]
+    L.etpic_workspace_bind.argtypes = [vp, vp, C.c_size_t]
+    L.etpic_mesh_sizes.argtypes = [C.c_int64, dp, C.c_int64, i32p, i64p, szp]
+    L.etpic_mesh_upload.argtypes = [vp, C.c_int64, dp, C.c_int64, i32p, vp, C.c_size_t]
+    L.etpic_field_bytes.argtypes = [vp, C.c_double, C.c_double, szp]
+    L.etpic_ns_bytes.argtypes = [vp, C.c_double, szp]
+    L.etpic_ds_rows_bytes.argtypes = [vp, szp]
+    L.etpic_ds_rows_bind.argtypes = [vp, vp, C.c_size_t]
+    L.etpic_qh_bytes.argtypes = [vp, szp]
+    L.etpic_qh_bind.argtypes = [vp, vp, C.c_size_t]
     L.etpic_mesh_canonical.argtypes = [C.c_int64, dp, C.c_int64, i32p, i64p, i32p, i32p]
     L.etpic_mesh_counts.argtypes = [vp, i64p]
     L.etpic_mesh_edges.argtypes = [vp, i32p]
@@ -114,12 +125,12 @@ def lib():
                                        C.c_double, vp, vp, C.c_uint32, vp]
     L.etpic_coarse_step.argtypes = [vp, C.POINTER(_Particles), C.c_int, C.POINTER(_Species), _Fields * 3,
                                     C.c_double, C.c_double, C.c_int, C.c_double, vp, vp, C.c_uint32, vp]
-    L.etpic_field_setup.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_double]
+    L.etpic_field_setup.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_double, vp, C.c_size_t]
     L.etpic_field_nnz.argtypes = [vp, i64p]
     L.etpic_field_spmv.argtypes = [vp, vp, vp, C.c_double, C.c_double, C.c_double, vp]
     L.etpic_field_step.argtypes = [vp, C.c_double, vp, vp, vp, vp, vp, C.c_double, C.c_int, C.POINTER(C.c_int),
                                    dp, vp]
-    L.etpic_ns_setup.argtypes = [vp, C.c_double]
+    L.etpic_ns_setup.argtypes = [vp, C.c_double, vp, C.c_size_t]
     L.etpic_ns_info.argtypes = [vp, i64p, i64p]
     L.etpic_ns_solve.argtypes = [vp, vp, vp, C.c_double, C.c_double, vp, vp, C.c_double, C.c_int, C.c_uint32,
                                  C.POINTER(C.c_int), dp, vp]
@@ -294,13 +305,29 @@ class Fields:
                        self.b_env.data_ptr(), None if self.b_dc is None else self.b_dc.data_ptr())
 
 
+def _device_buffer(nbytes, device):
+    """A caller-owned device buffer for the library (uint8 torch tensor; torch's
+    allocations are 512-byte aligned)."""
+    import torch
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=f"cuda:{device}")
+
+
 class Context:
-    """One etpic context bound to one HIP device."""
+    """One etpic context bound to one HIP device.  The device buffers the
+    library works in are torch tensors held here: the workspace (bound at
+    creation), the mesh tables, and the solver and downshifted buffers when
+    those are set up."""
 
     def __init__(self, device=0):
+        self.device = int(device)
         self._h = C.c_void_p()
-        _chk(lib().etpic_create(C.byref(self._h), int(device)))
+        _chk(lib().etpic_create(C.byref(self._h), self.device))
         self.counts = None
+        b = C.c_size_t(0)
+        _chk(lib().etpic_workspace_bytes(C.byref(b)))
+        self._ws = _device_buffer(b.value, self.device)
+        _chk(lib().etpic_workspace_bind(self._h, C.c_void_p(self._ws.data_ptr()), self._ws.numel()))
+        self._mesh_buf = self._field_buf = self._ns_buf = self._ds_rows = None
 
     def close(self):
         if self._h:
@@ -317,9 +344,15 @@ class Context:
     def upload_mesh(self, xyz, tet_vert):
         xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         tv = np.ascontiguousarray(tet_vert, dtype=np.int32)
-        _chk(lib().etpic_mesh_upload(self._h, xyz.shape[0], _np_ptr(xyz, C.c_double), tv.shape[0],
-                                     _np_ptr(tv, C.c_int32)))
         cnt = np.zeros(4, dtype=np.int64)
+        b = C.c_size_t(0)
+        _chk(lib().etpic_mesh_sizes(xyz.shape[0], _np_ptr(xyz, C.c_double), tv.shape[0], _np_ptr(tv, C.c_int32),
+                                    _np_ptr(cnt, C.c_int64), C.byref(b)))
+        buf = _device_buffer(b.value, self.device)
+        _chk(lib().etpic_mesh_upload(self._h, xyz.shape[0], _np_ptr(xyz, C.c_double), tv.shape[0],
+                                     _np_ptr(tv, C.c_int32), C.c_void_p(buf.data_ptr()), buf.numel()))
+        # the previous mesh's buffers (and those derived from it) are released
+        self._mesh_buf, self._field_buf, self._ns_buf, self._ds_rows = buf, None, None, None
         _chk(lib().etpic_mesh_counts(self._h, _np_ptr(cnt, C.c_int64)))
         self.counts = tuple(int(x) for x in cnt)
         return self.counts
@@ -412,6 +445,12 @@ class Context:
                  flags=STEP_XCD_REMAP, stream=None):
         """nsteps downshifted steps from step0 with hist0 earlier ones in hist."""
         assert hist.is_contiguous() and hist.dtype.is_floating_point
+        if self._ds_rows is None:
+            b = C.c_size_t(0)
+            _chk(lib().etpic_ds_rows_bytes(self._h, C.byref(b)))
+            buf = _device_buffer(b.value, self.device)
+            _chk(lib().etpic_ds_rows_bind(self._h, C.c_void_p(buf.data_ptr()), buf.numel()))
+            self._ds_rows = buf
         d = parts.desc()
         sp = species.c()
         fd = fields.desc()
@@ -523,7 +562,12 @@ class Context:
 
     # field update (side path) -------------------------------------------------------
     def field_setup(self, dt, omega, eps, mu):
-        _chk(lib().etpic_field_setup(self._h, float(dt), float(omega), float(eps), float(mu)))
+        b = C.c_size_t(0)
+        _chk(lib().etpic_field_bytes(self._h, float(eps), float(mu), C.byref(b)))
+        buf = _device_buffer(b.value, self.device)
+        _chk(lib().etpic_field_setup(self._h, float(dt), float(omega), float(eps), float(mu),
+                                     C.c_void_p(buf.data_ptr()), buf.numel()))
+        self._field_buf = buf
         n = C.c_int64(0)
         _chk(lib().etpic_field_nnz(self._h, C.byref(n)))
         return n.value
@@ -547,7 +591,11 @@ class Context:
     def ns_setup(self, eps):
         """Assemble the nodal operator of the non-solenoidal solve; returns
         (stored entries, grounded wall nodes)."""
-        _chk(lib().etpic_ns_setup(self._h, float(eps)))
+        b = C.c_size_t(0)
+        _chk(lib().etpic_ns_bytes(self._h, float(eps), C.byref(b)))
+        buf = _device_buffer(b.value, self.device)
+        _chk(lib().etpic_ns_setup(self._h, float(eps), C.c_void_p(buf.data_ptr()), buf.numel()))
+        self._ns_buf = buf
         nnz, wall = C.c_int64(0), C.c_int64(0)
         _chk(lib().etpic_ns_info(self._h, C.byref(nnz), C.byref(wall)))
         return nnz.value, wall.value
@@ -639,8 +687,8 @@ def _qchk(rc):
 
 class QhProjectors:
     """Quasi-Helmholtz projectors on one mesh (its own copy of the mesh tables;
-    same canonical numbering as Context.upload_mesh).  Vectors are float64
-    [N, 2] (complex) device tensors."""
+    same canonical numbering as Context.upload_mesh), in a device buffer held
+    here.  Vectors are float64 [N, 2] (complex) device tensors."""
 
     def __init__(self, xyz, tet_vert, eps, device=0):
         xyz = np.ascontiguousarray(xyz, dtype=np.float64)
@@ -648,6 +696,10 @@ class QhProjectors:
         self._h = C.c_void_p()
         _qchk(lib().etpic_qh_create(C.byref(self._h), int(device), xyz.shape[0], _np_ptr(xyz, C.c_double),
                                     tv.shape[0], _np_ptr(tv, C.c_int32), float(eps)))
+        b = C.c_size_t(0)
+        _qchk(lib().etpic_qh_bytes(self._h, C.byref(b)))
+        self._buf = _device_buffer(b.value, int(device))
+        _qchk(lib().etpic_qh_bind(self._h, C.c_void_p(self._buf.data_ptr()), self._buf.numel()))
         cnt = (C.c_int64 * 5)()
         _qchk(lib().etpic_qh_counts(self._h, cnt))
         self.n_vert, self.n_edge, self.n_face, self.n_tet, self.nnz = (int(v) for v in cnt)

@@ -76,3 +76,39 @@ def test_binding_constants_match_header():
         name = alias.get(k, k.replace("STEP_", "STEP_"))
         assert getattr(etpic, name) == v, k
     assert etpic.HOP_CAP == int(re.search(r"ETPIC_HOP_CAP\s+(\d+)", txt).group(1))
+
+
+def test_workspace_and_mesh_sizes_are_host_queries():
+    """The size queries of the caller-owned buffers run on the host: the
+    context workspace is a fixed size (two walk queues of 2^23 entries and a
+    few words), the mesh buffer grows with the mesh and reports the canonical
+    counts; a bad mesh is refused before any size is given."""
+    import ctypes as C
+    L = etpic.lib()
+    b = C.c_size_t(0)
+    assert L.etpic_workspace_bytes(C.byref(b)) == 0
+    assert b.value >= 2 * 4 * (1 << 23)
+    sizes = []
+    for n in [(2, 2, 2), (4, 3, 5)]:
+        xyz, tv = synth.kuhn_mesh(n, (1.0, 1.0, 1.0), 0.1, np.random.default_rng(1))
+        cnt = np.zeros(4, dtype=np.int64)
+        mb = C.c_size_t(0)
+        rc = L.etpic_mesh_sizes(xyz.shape[0], xyz.ctypes.data_as(C.POINTER(C.c_double)), tv.shape[0],
+                                np.ascontiguousarray(tv, np.int32).ctypes.data_as(C.POINTER(C.c_int32)),
+                                cnt.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(mb))
+        assert rc == 0
+        ref, _, _ = etpic.mesh_canonical(xyz, tv)
+        assert tuple(cnt) == tuple(ref)
+        nt = tv.shape[0]
+        # at least the per-tet rows it holds: topology 80 B, gradients 96 B, coefficient table 192 B,
+        # two slot buffers 2 x 64 B per tet
+        assert mb.value >= nt * (80 + 96 + 192 + 128)
+        sizes.append(mb.value)
+    assert sizes[1] > sizes[0]
+    xyz = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1.0]])
+    cnt = np.zeros(4, dtype=np.int64)
+    bad = np.array([[0, 2, 1, 3]], np.int32)
+    rc = L.etpic_mesh_sizes(4, xyz.ctypes.data_as(C.POINTER(C.c_double)), 1,
+                            bad.ctypes.data_as(C.POINTER(C.c_int32)), cnt.ctypes.data_as(C.POINTER(C.c_int64)),
+                            C.byref(b))
+    assert rc == etpic.EMESH

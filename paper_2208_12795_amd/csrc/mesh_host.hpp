@@ -47,6 +47,14 @@ struct StartGrid {
 // About one cell per `tets_per_cell` tets (at least one cell per axis).
 void build_start_grid(const HostMesh &m, const double *xyz, double tets_per_cell, StartGrid &g);
 
+// Tree-cotree split: edge_tree[ne] marks the edges of a spanning tree of the
+// vertex graph (breadth first from the lowest vertex of each component,
+// incident edges in ascending id); face_tree[nf] the faces of a spanning tree
+// of the dual graph of tets plus one exterior node (every boundary face joins
+// its tet to the exterior; tets reached first from the exterior in ascending
+// id, then breadth first through interior faces).
+void tree_cotree(const HostMesh &H, uint8_t *edge_tree, uint8_t *face_tree);
+
 // Builds every table from the raw mesh.  Returns 0, -1 (bad input) or -4
 // (unsorted row, degenerate tet, non-manifold face); err gets the reason.
 int build_host_mesh(int64_t nv, const double *xyz, int64_t nt, const int32_t *tv, HostMesh &out,

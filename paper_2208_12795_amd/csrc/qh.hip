@@ -642,59 +642,6 @@ int finish(const double hs[12], double tol, int *iters_out, double *resid_out) {
 
 }  // namespace
 
-namespace {
-
-// Spanning tree of the vertex graph (breadth first from the lowest vertex of
-// each component, incident edges in ascending id) and of the dual graph of
-// tets plus one exterior node (every boundary face joins its tet to the
-// exterior; tets reached first from the exterior in ascending id, then
-// breadth first through interior faces).
-void tree_cotree(const etpic::HostMesh &H, uint8_t *edge_tree, uint8_t *face_tree) {
-    std::vector<uint8_t> seen((size_t)H.nv, 0);
-    std::vector<int32_t> queue;
-    queue.reserve((size_t)H.nv);
-    std::fill(edge_tree, edge_tree + H.ne, (uint8_t)0);
-    for (int32_t root = 0; root < (int32_t)H.nv; ++root) {
-        if (seen[root]) continue;
-        seen[root] = 1;
-        queue.assign(1, root);
-        for (size_t h = 0; h < queue.size(); ++h) {
-            const int32_t u = queue[h];
-            for (int32_t k = H.v2e_ptr[u]; k < H.v2e_ptr[u + 1]; ++k) {
-                const int32_t e = H.v2e_code[k] >> 1;
-                const int32_t w = (H.v2e_code[k] & 1) ? H.edges[2 * e] : H.edges[2 * e + 1];
-                if (seen[w]) continue;
-                seen[w] = 1;
-                edge_tree[e] = 1;
-                queue.push_back(w);
-            }
-        }
-    }
-    std::vector<uint8_t> tseen((size_t)H.nt, 0);
-    std::fill(face_tree, face_tree + H.nf, (uint8_t)0);
-    queue.clear();
-    for (int64_t t = 0; t < H.nt; ++t)
-        for (int k = 0; k < 4; ++k)
-            if (H.topo[t].n[k] < 0) {
-                tseen[t] = 1;
-                face_tree[H.topo[t].f[k]] = 1;
-                queue.push_back((int32_t)t);
-                break;
-            }
-    for (size_t h = 0; h < queue.size(); ++h) {
-        const etpic::TetTopo &tp = H.topo[queue[h]];
-        for (int k = 0; k < 4; ++k) {
-            const int32_t nb = tp.n[k];
-            if (nb < 0 || tseen[nb]) continue;
-            tseen[nb] = 1;
-            face_tree[tp.f[k]] = 1;
-            queue.push_back(nb);
-        }
-    }
-}
-
-}  // namespace
-
 extern "C" {
 
 const char *etpic_qh_last_error(void) { return g_qh_error.c_str(); }
@@ -877,7 +824,7 @@ int etpic_tree_cotree(int64_t n_vert, const double *xyz_host, int64_t n_tet, con
     etpic::HostMesh H;
     if (int r = etpic::build_host_mesh(n_vert, xyz_host, n_tet, tet_vert_host, H, err))
         return qfail(r == -4 ? ETPIC_EMESH : ETPIC_EINVAL, "mesh: %s", err.c_str());
-    tree_cotree(H, edge_tree_host, face_tree_host);
+    etpic::tree_cotree(H, edge_tree_host, face_tree_host);
     int64_t te = 0, tf = 0;
     for (int64_t e = 0; e < H.ne; ++e) te += edge_tree_host[e];
     for (int64_t f = 0; f < H.nf; ++f) tf += face_tree_host[f];

@@ -16,7 +16,9 @@ Inputs are resident in HBM before the timed region starts.
 
 Prints ONE JSON line.  `value` is the float64 form; the mixed form (float32
 gather/push on barycentrics, float64 positions and deposit) is reported under
-"mixed".  The roofline figure is for the dominant kernel (the particle
+"mixed", and the compact mixed form (the same arithmetic, barycentrics stored
+as 32-bit fixed point, so 52 instead of 76 bytes of particle state move per
+step) under "mixed_fixed".  The roofline figure is for the dominant kernel (the particle
 kernel), timed with HIP events recorded on its launch stream; beside it the
 rate its access pattern alone reaches (a stream probe over the same particle
 arrays), a device copy, and the whole step's algorithmic bytes over the time
@@ -43,15 +45,17 @@ HBM_PEAK_GBS = 8000.0
 # Algorithmic bytes of the particle kernel (what it must move per unit):
 #  per particle-step: state read (tet 4 B, lam 3x8, v 3x8) and written back
 #                     (lam 3x8, v 3x8): 100 B in float64; v is float32 in the
-#                     mixed form: 76 B.  (The tet id is rewritten only for the
-#                     particles that leave their tet, by the walk kernel.)
+#                     mixed form: 76 B; with the barycentrics also in 32-bit
+#                     fixed point (compact mixed form): 4 + 2 x (12 + 12) = 52 B.
+#                     (The tet id is rewritten only for the particles that
+#                     leave their tet, by the walk kernel.)
 #  per tet and step : its coefficient row (24 reals), gradient row (9 reals) and
 #                     edge ids (6 x 4 B), read once: 288 B (float64), 156 B (mixed)
 #  per edge and step: the current accumulator read + written once (16 B)
-BYTES_PER_PARTICLE = {"fp64": 100, "mixed": 76}
-BYTES_PER_TET = {"fp64": 288, "mixed": 156}
+BYTES_PER_PARTICLE = {"fp64": 100, "mixed": 76, "mixed_fixed": 52}
+BYTES_PER_TET = {"fp64": 288, "mixed": 156, "mixed_fixed": 156}
 BYTES_PER_EDGE = 16
-KERNEL_NAME = {"fp64": "k_push<double>", "mixed": "k_push<float>"}
+KERNEL_NAME = {"fp64": "k_push<double>", "mixed": "k_push<float>", "mixed_fixed": "k_push<float>"}
 # Algorithmic bytes of a whole step (what the method must move per particle-step
 # and per tet, independent of how the kernels split the work): the particle
 # state read and written, tet included (2 x (lam 24 + v 24 + tet 4) = 104 B in
@@ -59,10 +63,18 @@ KERNEL_NAME = {"fp64": "k_push<double>", "mixed": "k_push<float>"}
 # its field DoFs, geometry and ids (~320 B); and the periodic sort amortised:
 # per particle and sort its state and id read and written plus key and offset
 # (2 x (52 + 8) + 8 = 128 B in float64, 2 x (40 + 8) + 8 = 104 B mixed).
-STEP_BYTES_PER_PARTICLE = {"fp64": 104, "mixed": 80}
+# The compact mixed form stores the barycentrics as 32-bit fixed point:
+# 2 x (12 + 12 + 4) = 56 B per particle-step, 2 x (28 + 8) + 8 = 80 B per sort.
+STEP_BYTES_PER_PARTICLE = {"fp64": 104, "mixed": 80, "mixed_fixed": 56}
 STEP_BYTES_PER_TET = 320
-SORT_BYTES_PER_PARTICLE = {"fp64": 128, "mixed": 104}
-REAL = {"fp64": "double", "mixed": "float"}
+SORT_BYTES_PER_PARTICLE = {"fp64": 128, "mixed": 104, "mixed_fixed": 80}
+REAL = {"fp64": "double", "mixed": "float", "mixed_fixed": "float"}
+FORM_DTYPE = {"fp64": "f64", "mixed": "f32 gather/push, f64 deposit",
+              "mixed_fixed": "f32 gather/push, f64 deposit, barycentrics stored as u32 (2^-32 fixed point)"}
+
+
+def precision_of(E, form):
+    return {"fp64": E.FP64, "mixed": E.MIXED, "mixed_fixed": E.MIXED_FIXED}[form]
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_push_hbm_traffic_40cube_1e7.md")
 COPY_CALIB_BYTES = 1 << 30
 CPU_SAMPLE_MAX = 10_000_000
@@ -586,7 +598,8 @@ def roofline(res, form, n_p, n_t, n_e, sort_every, copy_gbs, traffic_path=None):
                                    % (STEP_BYTES_PER_PARTICLE[form], STEP_BYTES_PER_TET)}}
 
 
-def config_entry(E, torch, synth, key, steps, warmup, sort_every, nlog, copy_gbs, forms=("fp64", "mixed")):
+def config_entry(E, torch, synth, key, steps, warmup, sort_every, nlog, copy_gbs,
+                 forms=("fp64", "mixed", "mixed_fixed")):
     """A second workload measured beside the metric's: both forms, its own
     roofline entries and a logged phase of single steps with the continuity
     residual of every step timed apart."""
@@ -600,8 +613,8 @@ def config_entry(E, torch, synth, key, steps, warmup, sort_every, nlog, copy_gbs
     fields = E.Fields.from_numpy(w.e_env, w.b_env, None, w.b_dc)
     res = {}
     for form in forms:
-        prec = E.FP64 if form == "fp64" else E.MIXED
-        res[form] = run_form(E, torch, ctx, w, prec, steps, warmup, sort_every, fields, nlog=nlog)
+        res[form] = run_form(E, torch, ctx, w, precision_of(E, form), steps, warmup, sort_every, fields,
+                             nlog=nlog)
         log(f"[bench] {key} {form}: {json.dumps(res[form])}")
         torch.cuda.empty_cache()
     n_p, n_t, n_e = w.tet.shape[0], w.tet_vert.shape[0], ctx.n_edge
@@ -610,10 +623,12 @@ def config_entry(E, torch, synth, key, steps, warmup, sort_every, nlog, copy_gbs
     for form in forms:
         r = res[form]
         out[form] = {"value": r["value"], "ms_per_step": r["ms_per_step"], "sort_ms": r["sort_ms"],
+                     "dtype": FORM_DTYPE[form],
                      "gauss_rel": r["gauss_rel"], "logged": r["logged"],
                      "roofline": roofline(res, form, n_p, n_t, n_e, sort_every, copy_gbs)}
-    if "fp64" in res and "mixed" in res:
-        out["mixed_speedup_vs_fp64"] = res["mixed"]["value"] / res["fp64"]["value"]
+    for form in ("mixed", "mixed_fixed"):
+        if "fp64" in res and form in res:
+            out[form]["speedup_vs_fp64"] = res[form]["value"] / res["fp64"]["value"]
     ctx.close()
     del w
     return out
@@ -629,7 +644,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--particles", type=int, default=None, help="override the particle count (default 1e7)")
     ap.add_argument("--sort-every", type=int, default=10)
-    ap.add_argument("--forms", default="fp64,mixed")
+    ap.add_argument("--forms", default="fp64,mixed,mixed_fixed")
     ap.add_argument("--log-steps", type=int, default=10,
                     help="single steps with the continuity residual of each, after the timed run")
     ap.add_argument("--precision-steps", type=int, default=20,
@@ -686,8 +701,7 @@ def main():
     fields = E.Fields.from_numpy(w.e_env, w.b_env, None, w.b_dc)
     res = {}
     for form in args.forms.split(","):
-        prec = E.FP64 if form == "fp64" else E.MIXED
-        res[form] = run_form(E, torch, ctx, w, prec, args.steps, args.warmup, args.sort_every, fields,
+        res[form] = run_form(E, torch, ctx, w, precision_of(E, form), args.steps, args.warmup, args.sort_every, fields,
                              nlog=args.log_steps)
         log(f"[bench] {form}: {json.dumps(res[form])}")
     n_p, n_t, n_e = w.tet.shape[0], w.tet_vert.shape[0], ctx.n_edge
@@ -716,12 +730,14 @@ def main():
         "gauss_ms": r["gauss_ms"],
         "logged": r["logged"],
     }
-    if "mixed" in res and main_form != "mixed":
-        m = res["mixed"]
-        line["mixed"] = {"value": m["value"], "ms_per_step": m["ms_per_step"], "dtype": "f32 gather/push, f64 deposit",
-                         "speedup_vs_fp64": m["value"] / r["value"],
-                         "roofline": roofline(res, "mixed", n_p, n_t, n_e, args.sort_every, copy_gbs, traffic_path),
-                         "gauss_rel": m["gauss_rel"], "logged": m["logged"]}
+    for form in ("mixed", "mixed_fixed"):
+        if form in res and main_form != form:
+            m = res[form]
+            line[form] = {"value": m["value"], "ms_per_step": m["ms_per_step"], "dtype": FORM_DTYPE[form],
+                          "speedup_vs_fp64": m["value"] / r["value"],
+                          "roofline": roofline(res, form, n_p, n_t, n_e, args.sort_every, copy_gbs,
+                                               traffic_path if form == "mixed" else None),
+                          "gauss_rel": m["gauss_rel"], "logged": m["logged"]}
     if not args.no_side and args.workload == "40cube":
         line["field_update"] = field_update_timing(E, torch, ctx, w)
         log(f"[bench] field update: {json.dumps(line['field_update'])}")

@@ -81,8 +81,23 @@ enum etpic_status {
 
 enum etpic_precision {
     ETPIC_FP64 = 0,  /* gather, push and deposit in float64; velocities float64 */
-    ETPIC_MIXED = 1  /* gather and push in float32 on tet-local barycentrics,
+    ETPIC_MIXED = 1, /* gather and push in float32 on tet-local barycentrics,
                         velocities float32; positions, deposit and charge float64 */
+    ETPIC_MIXED_FIXED = 2 /* ETPIC_MIXED with the barycentrics stored as uint32
+                        fixed point (lam = u * 2^-32; the lam[k] arrays hold
+                        uint32): 56 B per particle-step instead of 80.  Each
+                        step's end point is rounded to that grid (lam_0 =
+                        1 - sum stays >= 0) and the step's piece is deposited
+                        up to the rounded point, so the stored end points and
+                        the deposit agree exactly (continuity to float64
+                        rounding); the position quantum is 2^-32 of the tet
+                        size.  The particle steps (etpic_gather_push_deposit,
+                        etpic_run_steps, etpic_sort_run_steps,
+                        etpic_coarse_step), etpic_sort, etpic_vertex_charge,
+                        etpic_particles_locate / _positions and
+                        etpic_stream_probe take it; the downshifted, Gauss-law
+                        loop and electromagnetic loop entry points return
+                        EINVAL for it */
 };
 
 /* bits of the device status word read by etpic_check */
@@ -110,6 +125,7 @@ enum etpic_step_flags {
      * etpic_sort_run_steps, whose overflow path is a scan of all particles,
      * take that scan instead */
     ETPIC_STEP_WALK_BY_SLICE = 32u
+    /* bit 31 is the library's own and is ignored in the flags passed in */
 };
 
 #define ETPIC_HOP_CAP 64
@@ -117,7 +133,9 @@ enum etpic_step_flags {
 typedef struct etpic_ctx etpic_ctx;
 
 /* Particle state, structure of arrays on the device, length n each (n <= 2^29).
- * lam[k]: float64 barycentric lam_{k+1} in the particle's tet.
+ * lam[k]: float64 barycentric lam_{k+1} in the particle's tet (for
+ *         ETPIC_MIXED_FIXED: uint32 fixed point, u = lam * 2^32, the pointer
+ *         reinterpreted).
  * vel[k]: velocity component k at the half step (v^{n-1/2} in, v^{n+1/2} out);
  *         float64 for ETPIC_FP64, float32 for ETPIC_MIXED.
  * tet:    int32 tet index.  id: int64 particle id, carried by etpic_sort (may be NULL). */
@@ -217,14 +235,17 @@ int etpic_mesh_faces(const etpic_ctx *ctx, int32_t *face_vert_host);
  * the mesh, non-finite points, and points the straight
  * walk cannot reach (a non-convex domain without a good hint) get tet -1 and
  * make the call return EPARTICLE with their count; the others are located.
- * Errors: EINVAL, ESTATE, EPARTICLE, EHIP. */
-int etpic_particles_locate(etpic_ctx *ctx, const etpic_particles *p, const double *const xyz[3],
+ * precision says how lam is stored (ETPIC_MIXED_FIXED: rounded to the
+ * fixed-point grid).  Errors: EINVAL, ESTATE, EPARTICLE, EHIP. */
+int etpic_particles_locate(etpic_ctx *ctx, const etpic_particles *p, int precision, const double *const xyz[3],
                            const int32_t *hint, void *stream);
 
 /* Cartesian positions x = sum_k lam_k r_k of the particles into the device
  * float64 arrays xyz[0..2] (length p->n).  A tet index outside [0, N_t) gives
- * NaN and the BADTET device flag.  Asynchronous on `stream`. */
-int etpic_particles_positions(etpic_ctx *ctx, const etpic_particles *p, double *const xyz[3], void *stream);
+ * NaN and the BADTET device flag.  precision says how lam is stored.
+ * Asynchronous on `stream`. */
+int etpic_particles_positions(etpic_ctx *ctx, const etpic_particles *p, int precision, double *const xyz[3],
+                              void *stream);
 
 /* One fine step of every particle, asynchronous on `stream`:
  * gather E, B at (x^n, t_n = step*dt) with the carrier (cos w t_n, sin w t_n)
@@ -294,7 +315,7 @@ int etpic_sort_run_steps(etpic_ctx *ctx, const etpic_particles *src, const etpic
 
 /* rho[N_n] += q w * lam_k for the four vertices of every particle's tet
  * (the W0 shape; Formulation, the particle charge density). Asynchronous. */
-int etpic_vertex_charge(etpic_ctx *ctx, const etpic_particles *p, const etpic_species *sp, double *rho,
+int etpic_vertex_charge(etpic_ctx *ctx, const etpic_particles *p, int precision, const etpic_species *sp, double *rho,
                         void *stream);
 
 /* Discrete continuity residual r = D^T dG - (rho_new - rho_old), D the edge-vertex

@@ -75,6 +75,9 @@ int fail(int code, const char *fmt, ...) {
 
 constexpr int kBlock = 256;
 constexpr int kTimingSets = 512;             // event sets of the step-timing pool
+// Internal step flag (the public flags leave bit 31 free): the particle arrays
+// hold fixed-point barycentrics (ETPIC_MIXED_FIXED).
+constexpr uint32_t kFlagFixed = 1u << 31;
 constexpr unsigned kWalkQueueCap = 1u << 23;  // entries of each walk queue; N_p <= 64 * kWalkQueueCap
 constexpr unsigned kQueueSkip = 0xffffffffu;  // particle-queue entry to skip
 // grid of the walk kernel (and the walk half of k_walk_coef): the walk is
@@ -301,6 +304,7 @@ struct StepArgs {
     const TetTopo *topo;
     double *dG;
     double *rho;
+    int fixed;                 // lam1..3 hold uint32 fixed-point barycentrics (float kernels only)
     double *tetG;              // nt*8 per-tet current slots (q w * the six path-integral sums of
                                // the tet's runs), or null: the runs then add to dG directly
     unsigned *status;
@@ -363,6 +367,43 @@ __device__ __forceinline__ double lam0_of(double l1, double l2, double l3) {
     return (1.0 - t) - e;
 }
 
+// Fixed-point barycentrics (the compact mixed form): lambda_k = u_k * 2^-32,
+// u_k uint32, lambda_0 = 1 - the sum, which is exact.  Every such number and
+// every difference of two of them is exact in float64.
+constexpr double kFix = 2.3283064365386962890625e-10;   // 2^-32
+constexpr double kFixScale = 4294967296.0;              // 2^32
+
+__device__ __forceinline__ double fix_to_real(uint32_t u) { return (double)u * kFix; }
+
+// The nearest fixed-point barycentrics to (l1, l2, l3) that keep lambda_0 =
+// 1 - l1 - l2 - l3 >= 0: each rounded to the nearest multiple of 2^-32 (in
+// [0, 1 - 2^-32]); if the three then sum past 1 (by at most the rounding of
+// the three, for a point with lambda_0 >= 0) the largest gives up the excess.
+// (A point far outside the tet, which no step stores, would have the excess
+// taken from the largest remaining coordinates in turn, none below zero.)
+__device__ __forceinline__ void fix_round3(double l1, double l2, double l3, uint32_t u[3]) {
+    const double l[3] = {l1, l2, l3};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) u[k] = (uint32_t)fmin(fmax(rint(l[k] * kFixScale), 0.0), kFixScale - 1.0);
+    const uint64_t sum = (uint64_t)u[0] + u[1] + u[2];
+    if (sum > (1ull << 32)) {
+        uint64_t excess = sum - (1ull << 32);
+        for (int pass = 0; pass < 3 && excess > 0; ++pass) {
+            const int big = (u[0] >= u[1] && u[0] >= u[2]) ? 0 : (u[1] >= u[2] ? 1 : 2);
+            const uint32_t take = (uint32_t)(excess < u[big] ? excess : u[big]);
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                if (k == big) u[k] -= take;
+            excess -= take;
+        }
+    }
+}
+
+// Barycentric k of particle p from an array of either storage.
+__device__ __forceinline__ double lam_at(const double *arr, int64_t p, int fixed) {
+    return fixed ? fix_to_real(reinterpret_cast<const uint32_t *>(arr)[p]) : arr[p];
+}
+
 // Walk of the straight path with Cartesian remaining displacement d, starting in
 // tet T at barycentrics l (l[0] is recomputed from l[1..3] by lam0_of).  Each piece is deposited.  At a face crossing the exit
 // coordinate is set to exactly 0, the other three are rescaled to sum to one and
@@ -373,9 +414,12 @@ __device__ __forceinline__ double lam0_of(double l1, double l2, double l3) {
 // the end point is R (x + dt v) + const and the stored velocity is R v.
 // kExtra further vectors ext[0..kExtra-1] (the velocity samples a multistep
 // integrator keeps) are reflected with the velocity at a wall.
+// With `fixed` the end point is rounded to the fixed-point barycentrics (as
+// fix_round3) and the last piece runs to that rounded point, so that the
+// deposit and the stored end point agree exactly.
 template <typename Real, bool kTrack, int kExtra = 0>
 __device__ __forceinline__ int walk(const StepArgs<Real> &a, int T, double l[4], double d[3], Real v[3], double *R,
-                                   double (*ext)[3] = nullptr) {
+                                   double (*ext)[3] = nullptr, bool fixed = false) {
     int hops = 0;
     l[0] = lam0_of(l[1], l[2], l[3]);
     for (;;) {
@@ -414,6 +458,16 @@ __device__ __forceinline__ int walk(const StepArgs<Real> &a, int T, double l[4],
                 nb = tp.n[k];
             }
         if (kmin < 0) {
+            if (fixed) {
+                uint32_t u[3];
+                fix_round3(l[1] + dl[1], l[2] + dl[2], l[3] + dl[3], u);
+                double lq[4];
+#pragma unroll
+                for (int k = 1; k < 4; ++k) lq[k] = fix_to_real(u[k - 1]);
+                lq[0] = 1.0 - lq[1] - lq[2] - lq[3];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) dl[k] = lq[k] - l[k];
+            }
             if (!kTrack) deposit_piece(a.dG, tp, l, dl, a.qw);
 #pragma unroll
             for (int k = 0; k < 4; ++k) l[k] += dl[k];
@@ -631,19 +685,32 @@ __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) 
         // round trip (measured on both).
         constexpr bool kEarly = kSlices == 1;
         constexpr bool kSlots = push_uses_slots<Real>(kSlices);
+        // the compact mixed form: barycentrics stored as uint32 fixed point
+        const bool fx = std::is_same<Real, float>::value && a.fixed;
+        uint32_t *__restrict__ f1 = reinterpret_cast<uint32_t *>(a.lam1) + b0;
+        uint32_t *__restrict__ f2 = reinterpret_cast<uint32_t *>(a.lam2) + b0;
+        uint32_t *__restrict__ f3 = reinterpret_cast<uint32_t *>(a.lam3) + b0;
         int T = -1;
         double sl1 = 0.0, sl2 = 0.0, sl3 = 0.0;
+        uint32_t su1 = 0, su2 = 0, su3 = 0;
         Real sv0 = 0, sv1 = 0, sv2 = 0;
-        if (p < a.n) {
-            T = __builtin_nontemporal_load(&tetp[ln]);
-            if (kEarly) {
+        auto load_state = [&]() {
+            if (fx) {
+                su1 = __builtin_nontemporal_load(&f1[ln]);
+                su2 = __builtin_nontemporal_load(&f2[ln]);
+                su3 = __builtin_nontemporal_load(&f3[ln]);
+            } else {
                 sl1 = __builtin_nontemporal_load(&lam1[ln]);
                 sl2 = __builtin_nontemporal_load(&lam2[ln]);
                 sl3 = __builtin_nontemporal_load(&lam3[ln]);
-                sv0 = __builtin_nontemporal_load(&v0[ln]);
-                sv1 = __builtin_nontemporal_load(&v1[ln]);
-                sv2 = __builtin_nontemporal_load(&v2[ln]);
             }
+            sv0 = __builtin_nontemporal_load(&v0[ln]);
+            sv1 = __builtin_nontemporal_load(&v1[ln]);
+            sv2 = __builtin_nontemporal_load(&v2[ln]);
+        };
+        if (p < a.n) {
+            T = __builtin_nontemporal_load(&tetp[ln]);
+            if (kEarly) load_state();
             if ((unsigned)T >= (unsigned)a.nt) {
                 atomicOr(a.status, (unsigned)ETPIC_DEV_BADTET);
                 T = -1;
@@ -665,13 +732,11 @@ __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) 
         int walker = 0;
         if (act) {
             double l[4];
-            if (!kEarly) {
-                sl1 = __builtin_nontemporal_load(&lam1[ln]);
-                sl2 = __builtin_nontemporal_load(&lam2[ln]);
-                sl3 = __builtin_nontemporal_load(&lam3[ln]);
-                sv0 = __builtin_nontemporal_load(&v0[ln]);
-                sv1 = __builtin_nontemporal_load(&v1[ln]);
-                sv2 = __builtin_nontemporal_load(&v2[ln]);
+            if (!kEarly) load_state();
+            if (fx) {
+                sl1 = fix_to_real(su1);
+                sl2 = fix_to_real(su2);
+                sl3 = fix_to_real(su3);
             }
             l[1] = sl1;
             l[2] = sl2;
@@ -715,6 +780,17 @@ __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) 
             const bool stays = (l[0] + dl[0] >= 0.0) && (l[1] + dl[1] >= 0.0) && (l[2] + dl[2] >= 0.0) &&
                                (l[3] + dl[3] >= 0.0);
             if (stays) {
+                // compact form: the end point rounded to the fixed-point grid, and
+                // the piece taken to that point, so that deposit and stored end
+                // point agree exactly (the differences are exact in float64)
+                uint32_t un[3] = {0, 0, 0};
+                if (fx) {
+                    fix_round3(l[1] + dl[1], l[2] + dl[2], l[3] + dl[3], un);
+                    dl[1] = ((double)un[0] - (double)su1) * kFix;
+                    dl[2] = ((double)un[1] - (double)su2) * kFix;
+                    dl[3] = ((double)un[2] - (double)su3) * kFix;
+                    dl[0] = -(dl[1] + dl[2] + dl[3]);
+                }
                 // path integral of W1_ij along the straight piece: m_i dl_j - m_j dl_i,
                 // m the midpoint barycentrics (exact: the integrand is affine on the piece)
                 double m[4];
@@ -726,10 +802,20 @@ __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) 
 #pragma unroll
                 for (int k = 1; k < 4; ++k) l[k] += dl[k];
                 if (kScatter) {
-                    __builtin_nontemporal_store(l[1], &a.o_lam1[dq]);
-                    __builtin_nontemporal_store(l[2], &a.o_lam2[dq]);
-                    __builtin_nontemporal_store(l[3], &a.o_lam3[dq]);
+                    if (fx) {
+                        __builtin_nontemporal_store(un[0], reinterpret_cast<uint32_t *>(a.o_lam1) + dq);
+                        __builtin_nontemporal_store(un[1], reinterpret_cast<uint32_t *>(a.o_lam2) + dq);
+                        __builtin_nontemporal_store(un[2], reinterpret_cast<uint32_t *>(a.o_lam3) + dq);
+                    } else {
+                        __builtin_nontemporal_store(l[1], &a.o_lam1[dq]);
+                        __builtin_nontemporal_store(l[2], &a.o_lam2[dq]);
+                        __builtin_nontemporal_store(l[3], &a.o_lam3[dq]);
+                    }
                     a.o_tet[dq] = T;
+                } else if (fx) {
+                    __builtin_nontemporal_store(un[0], &f1[ln]);
+                    __builtin_nontemporal_store(un[1], &f2[ln]);
+                    __builtin_nontemporal_store(un[2], &f3[ln]);
                 } else {
                     __builtin_nontemporal_store(l[1], &lam1[ln]);
                     __builtin_nontemporal_store(l[2], &lam2[ln]);
@@ -743,9 +829,15 @@ __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) 
                 }
             } else if (kScatter) {
                 // the walk starts from the old barycentrics at the new position
-                a.o_lam1[dq] = l[1];
-                a.o_lam2[dq] = l[2];
-                a.o_lam3[dq] = l[3];
+                if (fx) {
+                    reinterpret_cast<uint32_t *>(a.o_lam1)[dq] = su1;
+                    reinterpret_cast<uint32_t *>(a.o_lam2)[dq] = su2;
+                    reinterpret_cast<uint32_t *>(a.o_lam3)[dq] = su3;
+                } else {
+                    a.o_lam1[dq] = l[1];
+                    a.o_lam2[dq] = l[2];
+                    a.o_lam3[dq] = l[3];
+                }
                 a.o_tet[dq] = walker_mark(T);
                 walker = 1;
             } else {
@@ -851,19 +943,30 @@ template <typename Real>
 __global__ void __launch_bounds__(kBlock) k_stream(int64_t n, double *__restrict__ lam1, double *__restrict__ lam2,
                                                    double *__restrict__ lam3, Real *__restrict__ v0,
                                                    Real *__restrict__ v1, Real *__restrict__ v2,
-                                                   const int32_t *__restrict__ tet, double zero, int remap) {
+                                                   const int32_t *__restrict__ tet, double zero, int remap, int fixed) {
     unsigned blk = blockIdx.x;
     if (remap) blk = xcd_block(blk, gridDim.x);
     const int64_t p = (int64_t)blk * kBlock + threadIdx.x;
     if (p >= n) return;
     const double z = zero * (double)__builtin_nontemporal_load(&tet[p]);
-    const double l1 = __builtin_nontemporal_load(&lam1[p]), l2 = __builtin_nontemporal_load(&lam2[p]),
-                 l3 = __builtin_nontemporal_load(&lam3[p]);
     const Real a = __builtin_nontemporal_load(&v0[p]), b = __builtin_nontemporal_load(&v1[p]),
                c = __builtin_nontemporal_load(&v2[p]);
-    __builtin_nontemporal_store(l1 + z, &lam1[p]);
-    __builtin_nontemporal_store(l2 + z, &lam2[p]);
-    __builtin_nontemporal_store(l3 + z, &lam3[p]);
+    if (fixed) {
+        uint32_t *u1 = reinterpret_cast<uint32_t *>(lam1), *u2 = reinterpret_cast<uint32_t *>(lam2),
+                 *u3 = reinterpret_cast<uint32_t *>(lam3);
+        const uint32_t zi = (uint32_t)z;
+        const uint32_t k1 = __builtin_nontemporal_load(&u1[p]), k2 = __builtin_nontemporal_load(&u2[p]),
+                       k3 = __builtin_nontemporal_load(&u3[p]);
+        __builtin_nontemporal_store(k1 + zi, &u1[p]);
+        __builtin_nontemporal_store(k2 + zi, &u2[p]);
+        __builtin_nontemporal_store(k3 + zi, &u3[p]);
+    } else {
+        const double l1 = __builtin_nontemporal_load(&lam1[p]), l2 = __builtin_nontemporal_load(&lam2[p]),
+                     l3 = __builtin_nontemporal_load(&lam3[p]);
+        __builtin_nontemporal_store(l1 + z, &lam1[p]);
+        __builtin_nontemporal_store(l2 + z, &lam2[p]);
+        __builtin_nontemporal_store(l3 + z, &lam3[p]);
+    }
     __builtin_nontemporal_store(a + (Real)z, &v0[p]);
     __builtin_nontemporal_store(b + (Real)z, &v1[p]);
     __builtin_nontemporal_store(c + (Real)z, &v2[p]);
@@ -897,19 +1000,38 @@ __device__ __forceinline__ void walk_particle(const StepArgs<Real> &a, int64_t p
     if (marked > -2) return;
     int T = walker_tet(marked);
     if (T >= a.nt) return;
+    const bool fx = std::is_same<Real, float>::value && a.fixed;
+    uint32_t *fl[3] = {reinterpret_cast<uint32_t *>(a.lam1), reinterpret_cast<uint32_t *>(a.lam2),
+                       reinterpret_cast<uint32_t *>(a.lam3)};
     double l[4];
-    l[1] = a.lam1[p];
-    l[2] = a.lam2[p];
-    l[3] = a.lam3[p];
+    if (fx) {
+        l[1] = fix_to_real(fl[0][p]);
+        l[2] = fix_to_real(fl[1][p]);
+        l[3] = fix_to_real(fl[2][p]);
+    } else {
+        l[1] = a.lam1[p];
+        l[2] = a.lam2[p];
+        l[3] = a.lam3[p];
+    }
     l[0] = 1.0 - l[1] - l[2] - l[3];
     Real v[3] = {a.v0[p], a.v1[p], a.v2[p]};
     const Real dx[3] = {a.dt_r * v[0], a.dt_r * v[1], a.dt_r * v[2]};
     double d[3] = {(double)dx[0], (double)dx[1], (double)dx[2]};
-    T = walk<Real, false>(a, T, l, d, v, nullptr);
+    T = walk<Real, false>(a, T, l, d, v, nullptr, nullptr, fx);
     a.tet[p] = T;
-    a.lam1[p] = l[1];
-    a.lam2[p] = l[2];
-    a.lam3[p] = l[3];
+    if (fx) {
+        // the walk ended on the fixed-point grid (rounding leaves such a point
+        // as it is; a walk stopped at the hop cap is rounded onto the grid)
+        uint32_t u[3];
+        fix_round3(l[1], l[2], l[3], u);
+        fl[0][p] = u[0];
+        fl[1][p] = u[1];
+        fl[2][p] = u[2];
+    } else {
+        a.lam1[p] = l[1];
+        a.lam2[p] = l[2];
+        a.lam3[p] = l[3];
+    }
     a.v0[p] = v[0];
     a.v1[p] = v[1];
     a.v2[p] = v[2];
@@ -1525,7 +1647,7 @@ __global__ void __launch_bounds__(kBlock) k_locate(int64_t n, const double *__re
                                                    const double *__restrict__ xyz, GridArgs G,
                                                    double *__restrict__ lam1, double *__restrict__ lam2,
                                                    double *__restrict__ lam3, int32_t *__restrict__ tet,
-                                                   unsigned *__restrict__ fails) {
+                                                   unsigned *__restrict__ fails, int fixed) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     const double x[3] = {x0[p], x1[p], x2[p]};
@@ -1607,9 +1729,20 @@ __global__ void __launch_bounds__(kBlock) k_locate(int64_t n, const double *__re
     const double *r0 = xyz + 3 * (int64_t)tp.v[0];
     const double dx[3] = {x[0] - r0[0], x[1] - r0[1], x[2] - r0[2]};
     const double *gp = grad + (int64_t)T * 12;
-    lam1[p] = gp[3] * dx[0] + gp[4] * dx[1] + gp[5] * dx[2];
-    lam2[p] = gp[6] * dx[0] + gp[7] * dx[1] + gp[8] * dx[2];
-    lam3[p] = gp[9] * dx[0] + gp[10] * dx[1] + gp[11] * dx[2];
+    const double l1 = gp[3] * dx[0] + gp[4] * dx[1] + gp[5] * dx[2];
+    const double l2 = gp[6] * dx[0] + gp[7] * dx[1] + gp[8] * dx[2];
+    const double l3 = gp[9] * dx[0] + gp[10] * dx[1] + gp[11] * dx[2];
+    if (fixed) {
+        uint32_t u[3];
+        fix_round3(l1, l2, l3, u);
+        reinterpret_cast<uint32_t *>(lam1)[p] = u[0];
+        reinterpret_cast<uint32_t *>(lam2)[p] = u[1];
+        reinterpret_cast<uint32_t *>(lam3)[p] = u[2];
+    } else {
+        lam1[p] = l1;
+        lam2[p] = l2;
+        lam3[p] = l3;
+    }
     tet[p] = T;
 }
 
@@ -1619,7 +1752,7 @@ __global__ void __launch_bounds__(kBlock) k_positions(int64_t n, int64_t nt, con
                                                       const int32_t *__restrict__ tet, const TetTopo *__restrict__ topo,
                                                       const double *__restrict__ xyz, double *__restrict__ x0,
                                                       double *__restrict__ x1, double *__restrict__ x2,
-                                                      unsigned *__restrict__ status) {
+                                                      unsigned *__restrict__ status, int fixed) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     const int T = tet[p];
@@ -1628,7 +1761,8 @@ __global__ void __launch_bounds__(kBlock) k_positions(int64_t n, int64_t nt, con
         x0[p] = x1[p] = x2[p] = NAN;
         return;
     }
-    const double l[4] = {1.0 - lam1[p] - lam2[p] - lam3[p], lam1[p], lam2[p], lam3[p]};
+    const double a1 = lam_at(lam1, p, fixed), a2 = lam_at(lam2, p, fixed), a3 = lam_at(lam3, p, fixed);
+    const double l[4] = {1.0 - a1 - a2 - a3, a1, a2, a3};
     const TetTopo tp = topo[T];
     double x[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -1644,7 +1778,7 @@ __global__ void __launch_bounds__(kBlock) k_positions(int64_t n, int64_t nt, con
 __global__ void __launch_bounds__(kBlock) k_charge(int64_t n, int64_t nt, const double *__restrict__ lam1,
                                                    const double *__restrict__ lam2, const double *__restrict__ lam3,
                                                    const int32_t *__restrict__ tet, const TetTopo *__restrict__ topo,
-                                                   double qw, double *__restrict__ rho, unsigned *status) {
+                                                   double qw, double *__restrict__ rho, unsigned *status, int fixed) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int T = -1;
     double l[4] = {0.0, 0.0, 0.0, 0.0};
@@ -1654,9 +1788,9 @@ __global__ void __launch_bounds__(kBlock) k_charge(int64_t n, int64_t nt, const 
             atomicOr(status, (unsigned)ETPIC_DEV_BADTET);
             T = -1;
         } else {
-            l[1] = lam1[p];
-            l[2] = lam2[p];
-            l[3] = lam3[p];
+            l[1] = lam_at(lam1, p, fixed);
+            l[2] = lam_at(lam2, p, fixed);
+            l[3] = lam_at(lam3, p, fixed);
             l[0] = 1.0 - l[1] - l[2] - l[3];
         }
     }
@@ -1894,7 +2028,7 @@ template <typename Real>
 __global__ void __launch_bounds__(kBlock) k_scatter(int64_t n, int64_t nt, const int32_t *__restrict__ tet,
                                                     unsigned *__restrict__ cursor, etpic_particles src,
                                                     etpic_particles dst, const Real *__restrict__ hsrc = nullptr,
-                                                    Real *__restrict__ hdst = nullptr, int nh = 0) {
+                                                    Real *__restrict__ hdst = nullptr, int nh = 0, int fixed = 0) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int T = -1;
     if (p < n) {
@@ -1911,7 +2045,10 @@ __global__ void __launch_bounds__(kBlock) k_scatter(int64_t n, int64_t nt, const
     dst.tet[q] = T;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        dst.lam[k][q] = src.lam[k][p];
+        if (fixed)
+            reinterpret_cast<uint32_t *>(dst.lam[k])[q] = reinterpret_cast<const uint32_t *>(src.lam[k])[p];
+        else
+            dst.lam[k][q] = src.lam[k][p];
         static_cast<Real *>(dst.vel[k])[q] = static_cast<const Real *>(src.vel[k])[p];
     }
     if (src.id && dst.id) dst.id[q] = src.id[p];
@@ -2757,10 +2894,10 @@ struct etpic_ctx {
 
     template <typename Real>
     int sort(const etpic_particles *src, const etpic_particles *dst, hipStream_t st, const Real *hsrc = nullptr,
-             Real *hdst = nullptr, int nh = 0) {
+             Real *hdst = nullptr, int nh = 0, int fixed = 0) {
         if (int r = sort_count(src, st)) return r;
         k_scatter<Real><<<grid_for(src->n), kBlock, 0, st>>>(src->n, host.nt, src->tet, d_count, *src, *dst, hsrc,
-                                                              hdst, nh);
+                                                              hdst, nh, fixed);
         HIP_TRY(hipGetLastError());
         return ETPIC_OK;
     }
@@ -2794,6 +2931,7 @@ struct etpic_ctx {
         for (int j = 0; j < nsteps; ++j) {
             StepArgs<Real> a = step_args<Real>(p, sp, dt, dG, j == nsteps - 1 ? rho : nullptr);
             a.walk_by_slice = (flags & ETPIC_STEP_WALK_BY_SLICE) ? 1 : 0;
+            a.fixed = (flags & kFlagFixed) ? 1 : 0;
             a.tetG = slots;
             if (ev) HIP_TRY(hipEventRecord(ev[2], st));
             if (j == 0 && src) {
@@ -3109,6 +3247,22 @@ int set_device(const etpic_ctx *ctx) {
 int set_device_only(const etpic_ctx *ctx) {
     HIP_TRY(hipSetDevice(ctx->device));
     return ETPIC_OK;
+}
+
+// ETPIC_FP64, ETPIC_MIXED, and ETPIC_MIXED_FIXED where the entry point has the
+// fixed-point form.
+int check_precision(int precision, bool fixed_ok) {
+    if (precision == ETPIC_FP64 || precision == ETPIC_MIXED) return ETPIC_OK;
+    if (precision == ETPIC_MIXED_FIXED) {
+        if (fixed_ok) return ETPIC_OK;
+        return fail(ETPIC_EINVAL, "this entry point has no fixed-point (ETPIC_MIXED_FIXED) form");
+    }
+    return fail(ETPIC_EINVAL, "bad precision %d", precision);
+}
+
+// Public step flags: bit 31 is the library's own.
+uint32_t step_flags(uint32_t flags, int precision) {
+    return (flags & ~kFlagFixed) | (precision == ETPIC_MIXED_FIXED ? kFlagFixed : 0u);
 }
 
 int check_particles(const etpic_ctx *ctx, const etpic_particles *p) {
@@ -3511,9 +3665,10 @@ int etpic_gather_push_deposit(etpic_ctx *ctx, const etpic_particles *p, int prec
     if (int r = check_step_args(ctx, sp, f, dt, omega)) return r;
     if (!dG) return fail(ETPIC_EINVAL, "null current accumulator");
     if (int r = check_particles(ctx, p)) return r;
-    if (precision != ETPIC_FP64 && precision != ETPIC_MIXED) return fail(ETPIC_EINVAL, "bad precision %d", precision);
+    if (int r = check_precision(precision, true)) return r;
     if (p->n == 0) return ETPIC_OK;
     if (int r = set_device(ctx)) return r;
+    flags = step_flags(flags, precision);
     if (precision == ETPIC_FP64) return ctx->step<double>(p, sp, f, step, dt, omega, dG, rho, flags, stream);
     return ctx->step<float>(p, sp, f, step, dt, omega, dG, rho, flags, stream);
 }
@@ -3528,7 +3683,7 @@ int etpic_coarse_step(etpic_ctx *ctx, const etpic_particles *p, int precision, c
     if (fine_steps < 1 || !(dt_coarse > 0.0) || !std::isfinite(t_coarse))
         return fail(ETPIC_EINVAL, "need fine_steps >= 1, dt_coarse > 0 and a finite t_coarse");
     if (int r = check_particles(ctx, p)) return r;
-    if (precision != ETPIC_FP64 && precision != ETPIC_MIXED) return fail(ETPIC_EINVAL, "bad precision %d", precision);
+    if (int r = check_precision(precision, true)) return r;
     if (p->n == 0) return ETPIC_OK;
     if (int r = set_device(ctx)) return r;
     const double dt = dt_coarse / fine_steps;
@@ -3542,6 +3697,7 @@ int etpic_coarse_step(etpic_ctx *ctx, const etpic_particles *p, int precision, c
                             {0.5 * u * (u - 1.0), 1.0 - u * u, 0.5 * u * (u + 1.0)},
                             t_coarse + j * dt};
     }
+    flags = step_flags(flags, precision);
     if (precision == ETPIC_FP64)
         return ctx->run_steps<double>(p, sp, plans.data(), fine_steps, dt, omega, dG, rho, flags, stream);
     return ctx->run_steps<float>(p, sp, plans.data(), fine_steps, dt, omega, dG, rho, flags, stream);
@@ -3554,11 +3710,12 @@ int etpic_run_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, con
     if (!dG) return fail(ETPIC_EINVAL, "null current accumulator");
     if (nsteps < 0) return fail(ETPIC_EINVAL, "negative step count");
     if (int r = check_particles(ctx, p)) return r;
-    if (precision != ETPIC_FP64 && precision != ETPIC_MIXED) return fail(ETPIC_EINVAL, "bad precision %d", precision);
+    if (int r = check_precision(precision, true)) return r;
     if (p->n == 0 || nsteps == 0) return ETPIC_OK;
     if (int r = set_device(ctx)) return r;
     std::vector<StepPlan> plans((size_t)nsteps);
     for (int j = 0; j < nsteps; ++j) plans[j] = StepPlan{{f, nullptr, nullptr}, {1.0, 0.0, 0.0}, (double)(step0 + j) * dt};
+    flags = step_flags(flags, precision);
     if (precision == ETPIC_FP64)
         return ctx->run_steps<double>(p, sp, plans.data(), nsteps, dt, omega, dG, rho, flags, stream);
     return ctx->run_steps<float>(p, sp, plans.data(), nsteps, dt, omega, dG, rho, flags, stream);
@@ -3571,11 +3728,12 @@ int etpic_sort_run_steps(etpic_ctx *ctx, const etpic_particles *src, const etpic
     if (int r = check_step_args(ctx, sp, f, dt, omega)) return r;
     if (!dG) return fail(ETPIC_EINVAL, "null current accumulator");
     if (nsteps < 1) return fail(ETPIC_EINVAL, "need at least one step");
-    if (precision != ETPIC_FP64 && precision != ETPIC_MIXED) return fail(ETPIC_EINVAL, "bad precision %d", precision);
+    if (int r = check_precision(precision, true)) return r;
     if (src->n == 0) return ETPIC_OK;
     if (int r = set_device(ctx)) return r;
     std::vector<StepPlan> plans((size_t)nsteps);
     for (int j = 0; j < nsteps; ++j) plans[j] = StepPlan{{f, nullptr, nullptr}, {1.0, 0.0, 0.0}, (double)(step0 + j) * dt};
+    flags = step_flags(flags, precision);
     if (precision == ETPIC_FP64)
         return ctx->run_steps<double>(dst, sp, plans.data(), nsteps, dt, omega, dG, rho, flags, stream, src);
     return ctx->run_steps<float>(dst, sp, plans.data(), nsteps, dt, omega, dG, rho, flags, stream, src);
@@ -3603,7 +3761,7 @@ int etpic_ds_rows_bind(etpic_ctx *ctx, void *dev_buf, size_t bytes) {
 
 int etpic_ds_history_bytes(int64_t n, int precision, size_t *bytes_out) {
     if (!bytes_out || n < 0) return fail(ETPIC_EINVAL, "bad arguments");
-    if (precision != ETPIC_FP64 && precision != ETPIC_MIXED) return fail(ETPIC_EINVAL, "bad precision %d", precision);
+    if (int r = check_precision(precision, false)) return r;
     *bytes_out = ds_history_size(n, precision);
     return ETPIC_OK;
 }
@@ -3615,7 +3773,7 @@ int etpic_ds_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, void
     if (!dG) return fail(ETPIC_EINVAL, "null current accumulator");
     if (int r = check_particles(ctx, p)) return r;
     if (nsteps < 1 || hist0 < 0) return fail(ETPIC_EINVAL, "need nsteps >= 1 and hist0 >= 0");
-    if (precision != ETPIC_FP64 && precision != ETPIC_MIXED) return fail(ETPIC_EINVAL, "bad precision %d", precision);
+    if (int r = check_precision(precision, false)) return r;
     if (!hist || hist_bytes < ds_history_size(p->n, precision))
         return fail(ETPIC_EINVAL, "history buffer missing or smaller than etpic_ds_history_bytes");
     if ((reinterpret_cast<uintptr_t>(hist) & 7) != 0) return fail(ETPIC_EINVAL, "history buffer not 8-byte aligned");
@@ -3629,7 +3787,7 @@ int etpic_ds_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, void
 int etpic_ds_sort(etpic_ctx *ctx, const etpic_particles *src, const etpic_particles *dst, int precision,
                   const void *hist_src, void *hist_dst, size_t hist_bytes, void *stream) {
     if (int r = check_sort_pair(ctx, src, dst)) return r;
-    if (precision != ETPIC_FP64 && precision != ETPIC_MIXED) return fail(ETPIC_EINVAL, "bad precision %d", precision);
+    if (int r = check_precision(precision, false)) return r;
     const size_t need = ds_history_size(src->n, precision);
     if (!hist_src || !hist_dst || hist_bytes < need)
         return fail(ETPIC_EINVAL, "history buffers missing or smaller than etpic_ds_history_bytes");
@@ -3744,9 +3902,10 @@ int etpic_backward(etpic_ctx *ctx, int64_t n, const etpic_species *sp, const etp
     return ETPIC_OK;
 }
 
-int etpic_particles_locate(etpic_ctx *ctx, const etpic_particles *p, const double *const xyz[3],
+int etpic_particles_locate(etpic_ctx *ctx, const etpic_particles *p, int precision, const double *const xyz[3],
                            const int32_t *hint, void *stream) {
     if (!ctx || !p || !xyz) return fail(ETPIC_EINVAL, "null argument");
+    if (int r = check_precision(precision, true)) return r;
     if (!ctx->has_mesh) return fail(ETPIC_ESTATE, "no mesh uploaded");
     if (p->n < 0 || p->n > (int64_t)kWalkQueueCap * 64) return fail(ETPIC_EINVAL, "particle count outside [0, 2^29]");
     if (p->n == 0) return ETPIC_OK;
@@ -3758,7 +3917,7 @@ int etpic_particles_locate(etpic_ctx *ctx, const etpic_particles *p, const doubl
     k_fill_u32<<<1, kBlock, 0, st>>>(fails, 1, 0u);
     k_locate<<<grid_for(p->n), kBlock, 0, st>>>(p->n, xyz[0], xyz[1], xyz[2], hint, ctx->host.nt, ctx->d_topo,
                                                 ctx->d_grad64, ctx->d_xyz, ctx->grid, p->lam[0], p->lam[1],
-                                                p->lam[2], p->tet, fails);
+                                                p->lam[2], p->tet, fails, precision == ETPIC_MIXED_FIXED ? 1 : 0);
     HIP_TRY(hipGetLastError());
     unsigned nfail = 0;
     HIP_TRY(hipMemcpyAsync(&nfail, fails, sizeof nfail, hipMemcpyDeviceToHost, st));
@@ -3769,8 +3928,10 @@ int etpic_particles_locate(etpic_ctx *ctx, const etpic_particles *p, const doubl
     return ETPIC_OK;
 }
 
-int etpic_particles_positions(etpic_ctx *ctx, const etpic_particles *p, double *const xyz[3], void *stream) {
+int etpic_particles_positions(etpic_ctx *ctx, const etpic_particles *p, int precision, double *const xyz[3],
+                              void *stream) {
     if (!ctx || !p || !xyz) return fail(ETPIC_EINVAL, "null argument");
+    if (int r = check_precision(precision, true)) return r;
     if (!ctx->has_mesh) return fail(ETPIC_ESTATE, "no mesh uploaded");
     if (p->n < 0 || p->n > (int64_t)kWalkQueueCap * 64) return fail(ETPIC_EINVAL, "particle count outside [0, 2^29]");
     if (p->n == 0) return ETPIC_OK;
@@ -3779,21 +3940,22 @@ int etpic_particles_positions(etpic_ctx *ctx, const etpic_particles *p, double *
     if (int r = set_device(ctx)) return r;
     k_positions<<<grid_for(p->n), kBlock, 0, static_cast<hipStream_t>(stream)>>>(
         p->n, ctx->host.nt, p->lam[0], p->lam[1], p->lam[2], p->tet, ctx->d_topo, ctx->d_xyz, xyz[0], xyz[1], xyz[2],
-        ctx->d_status);
+        ctx->d_status, precision == ETPIC_MIXED_FIXED ? 1 : 0);
     HIP_TRY(hipGetLastError());
     return ETPIC_OK;
 }
 
-int etpic_vertex_charge(etpic_ctx *ctx, const etpic_particles *p, const etpic_species *sp, double *rho,
+int etpic_vertex_charge(etpic_ctx *ctx, const etpic_particles *p, int precision, const etpic_species *sp, double *rho,
                         void *stream) {
     if (!ctx || !sp || !rho) return fail(ETPIC_EINVAL, "null argument");
+    if (int r = check_precision(precision, true)) return r;
     if (!ctx->has_mesh) return fail(ETPIC_ESTATE, "no mesh uploaded");
     if (int r = check_particles(ctx, p)) return r;
     if (p->n == 0) return ETPIC_OK;
     if (int r = set_device(ctx)) return r;
     k_charge<<<grid_for(p->n), kBlock, 0, static_cast<hipStream_t>(stream)>>>(
         p->n, ctx->host.nt, p->lam[0], p->lam[1], p->lam[2], p->tet, ctx->d_topo, sp->q * sp->w, rho,
-        ctx->d_status);
+        ctx->d_status, precision == ETPIC_MIXED_FIXED ? 1 : 0);
     HIP_TRY(hipGetLastError());
     return ETPIC_OK;
 }
@@ -3821,7 +3983,7 @@ int etpic_gauss_residual(etpic_ctx *ctx, const double *dG, const double *rho_new
 int etpic_stream_probe(etpic_ctx *ctx, const etpic_particles *p, int precision, uint32_t flags, void *stream) {
     if (!ctx) return fail(ETPIC_EINVAL, "null context");
     if (int r = check_particles(ctx, p)) return r;
-    if (precision != ETPIC_FP64 && precision != ETPIC_MIXED) return fail(ETPIC_EINVAL, "bad precision %d", precision);
+    if (int r = check_precision(precision, true)) return r;
     if (p->n == 0) return ETPIC_OK;
     if (int r = set_device(ctx)) return r;
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -3829,11 +3991,11 @@ int etpic_stream_probe(etpic_ctx *ctx, const etpic_particles *p, int precision, 
     if (precision == ETPIC_FP64)
         k_stream<double><<<grid_for(p->n), kBlock, 0, st>>>(
             p->n, p->lam[0], p->lam[1], p->lam[2], static_cast<double *>(p->vel[0]), static_cast<double *>(p->vel[1]),
-            static_cast<double *>(p->vel[2]), p->tet, 0.0, remap);
+            static_cast<double *>(p->vel[2]), p->tet, 0.0, remap, 0);
     else
         k_stream<float><<<grid_for(p->n), kBlock, 0, st>>>(
             p->n, p->lam[0], p->lam[1], p->lam[2], static_cast<float *>(p->vel[0]), static_cast<float *>(p->vel[1]),
-            static_cast<float *>(p->vel[2]), p->tet, 0.0, remap);
+            static_cast<float *>(p->vel[2]), p->tet, 0.0, remap, precision == ETPIC_MIXED_FIXED ? 1 : 0);
     HIP_TRY(hipGetLastError());
     return ETPIC_OK;
 }
@@ -3863,12 +4025,12 @@ int etpic_gauss_residual_noalloc(etpic_ctx *ctx, const double *dG, const double 
 int etpic_sort(etpic_ctx *ctx, const etpic_particles *src, const etpic_particles *dst, int precision,
                void *stream) {
     if (int r = check_sort_pair(ctx, src, dst)) return r;
-    if (precision != ETPIC_FP64 && precision != ETPIC_MIXED) return fail(ETPIC_EINVAL, "bad precision %d", precision);
+    if (int r = check_precision(precision, true)) return r;
     if (src->n == 0) return ETPIC_OK;
     if (int r = set_device(ctx)) return r;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (precision == ETPIC_FP64) return ctx->sort<double>(src, dst, st);
-    return ctx->sort<float>(src, dst, st);
+    return ctx->sort<float>(src, dst, st, nullptr, nullptr, 0, precision == ETPIC_MIXED_FIXED ? 1 : 0);
 }
 
 }  // extern "C"
@@ -4317,11 +4479,11 @@ int etpic_ns_run_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, 
                          ext ? ext->b_dc : nullptr};
     if (int r = check_step_args(ctx, sp, &f, dt, omega)) return r;
     if (int r = check_particles(ctx, p)) return r;
-    if (precision != ETPIC_FP64 && precision != ETPIC_MIXED) return fail(ETPIC_EINVAL, "bad precision %d", precision);
+    if (int r = check_precision(precision, false)) return r;
     if (nsteps == 0) return ETPIC_OK;
     if (int r = set_device(ctx)) return r;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const uint32_t sf = flags & ~(uint32_t)ETPIC_NS_WARM;
+    const uint32_t sf = flags & ~((uint32_t)ETPIC_NS_WARM | kFlagFixed);
     std::vector<StepPlan> plans((size_t)std::min(steps_per_solve, nsteps));
     int total = 0;
     for (int j = 0; j < nsteps; j += steps_per_solve) {
@@ -4408,13 +4570,13 @@ int etpic_em_steps(etpic_ctx *ctx, const etpic_particles *p, int precision, cons
     const etpic_fields f{e, nullptr, b, nullptr};
     if (int r = check_step_args(ctx, sp, &f, dt, omega)) return r;
     if (int r = check_particles(ctx, p)) return r;
-    if (precision != ETPIC_FP64 && precision != ETPIC_MIXED) return fail(ETPIC_EINVAL, "bad precision %d", precision);
+    if (int r = check_precision(precision, false)) return r;
     if (nsteps == 0) return ETPIC_OK;
     if (int r = set_device(ctx)) return r;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t ne = ctx->field.ne;
     double *h1 = G_hist, *h2 = G_hist + ne;
-    const uint32_t sf = flags & ~(uint32_t)(ETPIC_NS_WARM | ETPIC_EM_SPLIT);
+    const uint32_t sf = flags & ~((uint32_t)(ETPIC_NS_WARM | ETPIC_EM_SPLIT) | kFlagFixed);
     const bool split = (flags & ETPIC_EM_SPLIT) != 0;
     int total = 0;
     for (int j = 0; j < nsteps; ++j) {

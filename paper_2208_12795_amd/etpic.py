@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libetpic.so")
 
 OK, EINVAL, ESTATE, EHIP, EMESH, EPARTICLE, EWALK, ENAN, ENOCONV = 0, -1, -2, -3, -4, -5, -6, -7, -8
-FP64, MIXED = 0, 1
+FP64, MIXED, MIXED_FIXED = 0, 1, 2
 DEV_HOPCAP, DEV_NAN, DEV_BADTET = 1, 2, 4
 STEP_XCD_REMAP = 1
 STEP_TIMING = 2
@@ -98,7 +98,7 @@ def lib():
                                             C.POINTER(_Fields), C.c_int64, C.c_double, C.c_double, vp, vp,
                                             C.c_uint32, vp]
     L.etpic_sort.argtypes = [vp, C.POINTER(_Particles), C.POINTER(_Particles), C.c_int, vp]
-    L.etpic_vertex_charge.argtypes = [vp, C.POINTER(_Particles), C.POINTER(_Species), vp, vp]
+    L.etpic_vertex_charge.argtypes = [vp, C.POINTER(_Particles), C.c_int, C.POINTER(_Species), vp, vp]
     L.etpic_gauss_residual.argtypes = [vp, vp, vp, vp, dp, vp]
     L.etpic_gauss_residual_noalloc.argtypes = [vp, vp, vp, vp, dp, vp]
     L.etpic_stream_probe.argtypes = [vp, C.POINTER(_Particles), C.c_int, C.c_uint32, vp]
@@ -112,8 +112,8 @@ def lib():
                                  C.c_double, C.c_double, C.c_int, vp, C.c_size_t, C.c_void_p * 3, C.c_void_p * 3,
                                  vp, vp]
     L.etpic_check.argtypes = [vp, vp, C.POINTER(C.c_uint32)]
-    L.etpic_particles_locate.argtypes = [vp, C.POINTER(_Particles), C.c_void_p * 3, vp, vp]
-    L.etpic_particles_positions.argtypes = [vp, C.POINTER(_Particles), C.c_void_p * 3, vp]
+    L.etpic_particles_locate.argtypes = [vp, C.POINTER(_Particles), C.c_int, C.c_void_p * 3, vp, vp]
+    L.etpic_particles_positions.argtypes = [vp, C.POINTER(_Particles), C.c_int, C.c_void_p * 3, vp]
     L.etpic_run_steps.argtypes = [vp, C.POINTER(_Particles), C.c_int, C.POINTER(_Species), C.POINTER(_Fields),
                                   C.c_int64, C.c_int, C.c_double, C.c_double, vp, vp, C.c_uint32, vp]
     L.etpic_ds_history_bytes.argtypes = [C.c_int64, C.c_int, C.POINTER(C.c_size_t)]
@@ -224,11 +224,36 @@ class Species:
         return _Species(self.q, self.m, self.w)
 
 
+def lam_to_fixed(lam):
+    """float64 barycentrics [N, 3] -> the fixed-point storage of MIXED_FIXED
+    (uint32 u = lam * 2^32, as int32 bits): each rounded to the nearest grid
+    value in [0, 1 - 2^-32]; where the three then sum past 1 the largest gives
+    up the excess (the library's own rule for the points it stores; for a
+    point far outside the tet the excess is taken from the largest remaining
+    coordinates in turn, none below zero)."""
+    lam = np.asarray(lam, dtype=np.float64)
+    u = np.clip(np.rint(lam * 4294967296.0), 0.0, 4294967295.0).astype(np.int64)
+    excess = np.maximum(u.sum(axis=1) - (1 << 32), 0)
+    rows = np.arange(len(u))
+    for _ in range(3):
+        big = np.argmax(u, axis=1)
+        take = np.minimum(excess, u[rows, big])
+        u[rows, big] -= take
+        excess -= take
+    return u.astype(np.uint32).view(np.int32)
+
+
+def fixed_to_lam(u):
+    """the fixed-point storage [N, 3] (int32 bits) -> float64 barycentrics (exact)"""
+    return np.asarray(u).view(np.uint32).astype(np.float64) * (1.0 / 4294967296.0)
+
+
 class Particles:
     """Structure-of-arrays particle state on the device (torch tensors).
 
-    lam: float64 [3, N] (lam1, lam2, lam3); vel: [3, N] float64 (FP64) or
-    float32 (MIXED); tet: int32 [N]; ids: int64 [N] or None."""
+    lam: float64 [3, N] (lam1, lam2, lam3), or for MIXED_FIXED int32 [3, N]
+    holding the uint32 fixed-point values; vel: [3, N] float64 (FP64) or
+    float32 (MIXED, MIXED_FIXED); tet: int32 [N]; ids: int64 [N] or None."""
 
     def __init__(self, lam, vel, tet, ids=None):
         self.lam, self.vel, self.tet, self.ids = lam, vel, tet, ids
@@ -240,13 +265,16 @@ class Particles:
     @property
     def precision(self):
         import torch
+        if self.lam.dtype == torch.int32:
+            return MIXED_FIXED
         return FP64 if self.vel.dtype == torch.float64 else MIXED
 
     @classmethod
     def from_numpy(cls, tet, lam, vel, ids=None, precision=FP64, device="cuda"):
         import torch
         vdt = torch.float64 if precision == FP64 else torch.float32
-        lam_t = torch.from_numpy(np.ascontiguousarray(np.asarray(lam, np.float64).T)).to(device)
+        lam_h = lam_to_fixed(lam) if precision == MIXED_FIXED else np.asarray(lam, np.float64)
+        lam_t = torch.from_numpy(np.ascontiguousarray(lam_h.T)).to(device)
         vel_t = torch.from_numpy(np.ascontiguousarray(np.asarray(vel, np.float64).T)).to(device=device, dtype=vdt)
         tet_t = torch.from_numpy(np.ascontiguousarray(tet, dtype=np.int32)).to(device)
         ids_t = None if ids is None else torch.from_numpy(np.ascontiguousarray(ids, dtype=np.int64)).to(device)
@@ -262,8 +290,13 @@ class Particles:
                          None if self.ids is None else self.ids.clone())
 
     def to_numpy(self):
-        return (self.tet.cpu().numpy(), self.lam.double().cpu().numpy().T.copy(),
-                self.vel.double().cpu().numpy().T.copy(), None if self.ids is None else self.ids.cpu().numpy())
+        import torch
+        if self.lam.dtype == torch.int32:
+            lam = fixed_to_lam(self.lam.cpu().numpy().T.copy())
+        else:
+            lam = self.lam.double().cpu().numpy().T.copy()
+        return (self.tet.cpu().numpy(), lam, self.vel.double().cpu().numpy().T.copy(),
+                None if self.ids is None else self.ids.cpu().numpy())
 
     def desc(self):
         for t in (self.lam, self.vel):
@@ -476,7 +509,7 @@ class Context:
         assert xyz.is_contiguous() and xyz.dim() == 2 and xyz.shape[0] == 3 and xyz.shape[1] == parts.n
         d = parts.desc()
         x = (C.c_void_p * 3)(*[xyz[k].data_ptr() for k in range(3)])
-        rc = lib().etpic_particles_locate(self._h, C.byref(d), x, _dptr(hint), _stream(stream))
+        rc = lib().etpic_particles_locate(self._h, C.byref(d), parts.precision, x, _dptr(hint), _stream(stream))
         if rc != OK and (raise_on_error or rc != EPARTICLE):
             _chk(rc)
         return rc
@@ -488,13 +521,14 @@ class Context:
             xyz = torch.empty((3, parts.n), dtype=torch.float64, device=parts.lam.device)
         d = parts.desc()
         x = (C.c_void_p * 3)(*[xyz[k].data_ptr() for k in range(3)])
-        _chk(lib().etpic_particles_positions(self._h, C.byref(d), x, _stream(stream)))
+        _chk(lib().etpic_particles_positions(self._h, C.byref(d), parts.precision, x, _stream(stream)))
         return xyz
 
     def vertex_charge(self, parts, species, rho, stream=None):
         d = parts.desc()
         sp = species.c()
-        _chk(lib().etpic_vertex_charge(self._h, C.byref(d), C.byref(sp), _dptr(rho), _stream(stream)))
+        _chk(lib().etpic_vertex_charge(self._h, C.byref(d), parts.precision, C.byref(sp), _dptr(rho),
+                                       _stream(stream)))
 
     def gauss_residual(self, dG, rho_new, rho_old, stream=None):
         out = np.zeros(2)

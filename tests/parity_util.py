@@ -12,7 +12,10 @@ coordinate of that point is rounded there (an absolute quantum of a few units
 of float64 epsilon, whatever the implementation: the kernel sets the exit
 coordinate to zero and rescales, the oracle solves for the point's
 barycentrics by Cramer's rule), so for crossed particles the quantum also
-holds 4 epsilon absolute per coordinate.
+holds 4 epsilon absolute per coordinate.  Barycentrics stored in fixed point
+(the compact mixed form, a grid of 2^-32) carry that grid's quantum instead:
+lam_quantum = 2^-31 absolute (rounding to the grid, and the largest coordinate
+giving up the excess when the three sum past one).
 """
 import numpy as np
 
@@ -25,8 +28,10 @@ def positions(xyz, tv, tet, lam):
     return l0[:, None] * r[:, 0] + lam[:, 0:1] * r[:, 1] + lam[:, 1:2] * r[:, 2] + lam[:, 2:3] * r[:, 3]
 
 
-def step_errors(xyz, tv, state_in, gpu, ora, dG_gpu, dG_ora):
-    """state_in/gpu/ora = (tet, lam[N,3], vel[N,3]); returns a dict of errors."""
+def step_errors(xyz, tv, state_in, gpu, ora, dG_gpu, dG_ora, lam_quantum=0.0):
+    """state_in/gpu/ora = (tet, lam[N,3], vel[N,3]); returns a dict of errors.
+    lam_quantum: absolute quantum of the GPU's stored barycentrics beyond
+    float64 (2^-31 for fixed-point storage)."""
     t0, l0, v0 = state_in
     tg, lg, vg = gpu
     to, lo, vo = ora
@@ -40,6 +45,7 @@ def step_errors(xyz, tv, state_in, gpu, ora, dG_gpu, dG_ora):
         quantum = 2.0 * ULP1 * np.maximum(np.abs(lg[same]), np.abs(lo[same]))
         crossed = ((tg != t0) | (to != t0))[same]
         quantum[crossed] += 4.0 * ULP1
+        quantum += lam_quantum
         excess = np.maximum(np.abs(lg[same] - lo[same]) - quantum, 0.0)
         out["lam_rel"] = float(excess.max() / scale) if scale > 0 else float(excess.max())
     else:
@@ -48,7 +54,8 @@ def step_errors(xyz, tv, state_in, gpu, ora, dG_gpu, dG_ora):
         xg = positions(xyz, tv, tg[~same], lg[~same])
         xo = positions(xyz, tv, to[~same], lo[~same])
         dx = np.abs(positions(xyz, tv, to, lo) - positions(xyz, tv, t0, l0)).max()
-        out["x_mismatch_rel"] = float((np.abs(xg - xo).max() - 8 * ULP1 * np.abs(xyz).max()) / dx)
+        h = np.abs(xyz[tv[:, 1]] - xyz[tv[:, 0]]).max()
+        out["x_mismatch_rel"] = float((np.abs(xg - xo).max() - 8 * ULP1 * np.abs(xyz).max() - 4 * lam_quantum * h) / dx)
     else:
         out["x_mismatch_rel"] = 0.0
     nrm2 = np.linalg.norm(dG_ora)

@@ -48,13 +48,19 @@ def case(request, E, torch_cuda, ora):
     ctx.close()
 
 
-def test_vertex_charge_vs_oracle(E, torch_cuda, case):
+@pytest.mark.parametrize("fixed", [False, True], ids=["lam_f64", "lam_fixed"])
+def test_vertex_charge_vs_oracle(E, torch_cuda, case, fixed):
     """k_charge (same-tet runs summed over the wavefront, float64 atomics)
     against ora_charge (plain loop over particles), vertex by vertex.  All
     terms of a vertex carry the sign of q, so the sums have no cancellation and
-    agree to a few units of rounding relative to each vertex's own charge."""
+    agree to a few units of rounding relative to each vertex's own charge.
+    Also with the barycentrics in fixed point (the compact mixed form), the
+    oracle taking their exact float64 values."""
     torch = torch_cuda
     w, ctx, parts, M = case
+    if fixed:
+        t_, l_, v_, i_ = parts.to_numpy()
+        parts = E.Particles.from_numpy(t_, l_, v_, i_, precision=E.MIXED_FIXED)
     sp = E.Species(w.q, w.m, w.w)
     rho = torch.zeros(ctx.n_vert, dtype=torch.float64, device="cuda")
     ctx.vertex_charge(parts, sp, rho)

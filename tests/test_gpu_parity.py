@@ -35,6 +35,11 @@ def E():
     return etpic
 
 
+def fixed_quantum(E, precision):
+    """absolute quantum of fixed-point barycentric storage (0 for float64 storage)"""
+    return 2.0 ** -31 if precision == E.MIXED_FIXED else 0.0
+
+
 def setup(E, torch, w, precision):
     ctx = E.Context(0)
     ctx.upload_mesh(w.xyz, w.tet_vert)
@@ -79,7 +84,8 @@ def run_case(E, torch, ora, w, steps, precision, tol, check_every=1, dt=None, fl
             rc, o, dGo = oracle_step(M, (tin, lin, vin), w, s, nthreads=NTH, dt=dt)
             assert rc == 0
             tg, lg, vg, _ = parts.to_numpy()
-            err = step_errors(w.xyz, w.tet_vert, (tin, lin, vin), (tg, lg, vg), o, dG.cpu().numpy(), dGo)
+            err = step_errors(w.xyz, w.tet_vert, (tin, lin, vin), (tg, lg, vg), o, dG.cpu().numpy(), dGo,
+                              lam_quantum=fixed_quantum(E, precision))
             assert err["tet_mismatch"] <= 2 + 1e-4 * len(tg), err
             assert_within(err, tol, f"step {s}")
             for k, v in err.items():
@@ -104,8 +110,15 @@ def test_small_config_mixed(E, torch_cuda, ora):
     run_case(E, torch_cuda, ora, synth.make_workload(1), 30, E.MIXED, 2e-5)
 
 
+def test_small_config_mixed_fixed(E, torch_cuda, ora):
+    """The compact mixed form (barycentrics stored in 2^-32 fixed point) on the
+    small workload, every step against the float64 oracle; continuity checked
+    every step on the GPU (the deposit runs to the stored end points)."""
+    run_case(E, torch_cuda, ora, synth.make_workload(1), 30, E.MIXED_FIXED, 2e-5)
+
+
 @pytest.mark.parametrize("by_slice", [False, True])
-@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 2e-5)])
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 2e-5), (2, 2e-5)])
 def test_crossing_heavy(E, torch_cuda, ora, precision, tol, by_slice):
     """Steps of 0.1-0.5 cell: most particles cross faces, several per step, and
     many hit the walls (reflection).  Walkers queued one by one, and by slice
@@ -129,7 +142,7 @@ def test_ragged_and_multi_tile(E, torch_cuda, ora, presort):
 
 
 @pytest.mark.parametrize("slices", [1, 4, 16])
-@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 2e-5)])
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 2e-5), (2, 2e-5)])
 def test_dense_tets_slices(E, torch_cuda, ora, slices, precision, tol):
     """About 400 particles per tet on the 750-tet cube, sorted by tet, so runs of
     one tet span several wavefronts; 1, 4 and 16 slices of 64 particles per
@@ -156,7 +169,8 @@ def test_dense_tets_slices(E, torch_cuda, ora, slices, precision, tol):
         rc, o, dGo = oracle_step(M, (tin, lin, vin.astype(np.float64)), w, s, nthreads=NTH)
         assert rc == 0
         tg, lg, vg, _ = parts.to_numpy()
-        err = step_errors(w.xyz, w.tet_vert, (tin, lin, vin), (tg, lg, vg), o, dG.cpu().numpy(), dGo)
+        err = step_errors(w.xyz, w.tet_vert, (tin, lin, vin), (tg, lg, vg), o, dG.cpu().numpy(), dGo,
+                          lam_quantum=fixed_quantum(E, precision))
         assert err["tet_mismatch"] <= 2 + 1e-4 * len(tg), err
         assert_within(err, tol, f"slices {slices} step {s}")
     ctx.check()
@@ -309,7 +323,8 @@ def full_size_step(E, torch, ora, w, precision, tol, sort_first=True):
     rc, o, dGo = oracle_step(M, (tin, lin, vin64), w, 17, nthreads=NTH)
     assert rc == 0
     tg, lg, vg, _ = parts.to_numpy()
-    err = step_errors(w.xyz, w.tet_vert, (tin, lin, vin64), (tg, lg, vg), o, dG.cpu().numpy(), dGo)
+    err = step_errors(w.xyz, w.tet_vert, (tin, lin, vin64), (tg, lg, vg), o, dG.cpu().numpy(), dGo,
+                      lam_quantum=fixed_quantum(E, precision))
     print(f"[full-size {w.name} N={len(tg)} precision={precision}] {err} gauss {r / p:.2e}", flush=True)
     assert r / p <= 1e-12
     assert err["tet_mismatch"] <= 2 + 1e-5 * len(tg), err
@@ -393,8 +408,11 @@ def test_full_size_fp64_40cube(E, torch_cuda, ora):
 
 def test_full_size_mixed_40cube_5e7(E, torch_cuda, ora):
     """Precision form at its real size: 40^3 x 6 tets, 5e7 electrons, float32
-    gather/push with float64 positions and deposit, against the float64 oracle."""
-    full_size_step(E, torch_cuda, ora, synth.make_workload(3), E.MIXED, 2e-5)
+    gather/push with float64 positions and deposit, against the float64 oracle;
+    then the compact form (fixed-point barycentrics) on the same workload."""
+    w = synth.make_workload(3)
+    full_size_step(E, torch_cuda, ora, w, E.MIXED, 2e-5)
+    full_size_step(E, torch_cuda, ora, w, E.MIXED_FIXED, 2e-5)
 
 
 def test_large_box_bunch_one_gpu_share(E, torch_cuda, ora):
@@ -404,4 +422,5 @@ def test_large_box_bunch_one_gpu_share(E, torch_cuda, ora):
     B = 1 T along x; mixed and float64 forms against the float64 oracle."""
     w = synth.make_workload(5, n_particles=25_000_000)
     full_size_step(E, torch_cuda, ora, w, E.MIXED, 2e-5)
+    full_size_step(E, torch_cuda, ora, w, E.MIXED_FIXED, 2e-5)
     full_size_step(E, torch_cuda, ora, w, E.FP64, 1e-12)

@@ -69,7 +69,7 @@ def two_ways(E, torch, w, precision, nsteps, dt, flags, step0=5):
     return before, out
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 @pytest.mark.parametrize("dt_scale,flags", [(1.0, "remap"), (60.0, "remap"), (60.0, "scan")])
 def test_fused_sort_equals_sort_then_steps(E, torch_cuda, precision, dt_scale, flags):
     """300k unsorted electrons on the 40^3 mesh, 4 steps; dt x60 makes a few
@@ -97,7 +97,7 @@ def test_fused_sort_equals_sort_then_steps(E, torch_cuda, precision, dt_scale, f
 
 
 @pytest.mark.parametrize("slices", [4, 16])
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_fused_sort_with_slices(E, torch_cuda, slices, precision):
     """The sliced particle kernels (several 64-particle slices per wavefront,
     the open run carried across slices) in their sorting form."""
@@ -113,7 +113,8 @@ def test_fused_sort_with_slices(E, torch_cuda, slices, precision):
 
 
 @pytest.mark.parametrize("precision,tol,case", [(0, 1e-12, "plain"), (1, 2e-5, "plain"), (0, 1e-12, "heavy"),
-                                                (0, 1e-12, "heavy-scan"), (1, 2e-5, "heavy-scan")])
+                                                (0, 1e-12, "heavy-scan"), (1, 2e-5, "heavy-scan"),
+                                                (2, 2e-5, "plain"), (2, 2e-5, "heavy-scan")])
 def test_fused_sort_step_matches_oracle(E, torch_cuda, ora, precision, tol, case):
     """One fused sort+step of the small workload (750 tets) against the
     oracle's step of the unsorted input, matched by id: 1000 electrons, or
@@ -147,7 +148,8 @@ def test_fused_sort_step_matches_oracle(E, torch_cuda, ora, precision, tol, case
                    b_dc=w.b_dc, dG=dGo, nthreads=NTH)
     assert rc == 0
     tg, lg, vg = by_id(dst.to_numpy())
-    err = step_errors(w.xyz, w.tet_vert, (tin[o], lin[o], vin[o]), (tg, lg, vg), (t, l, v), dG.cpu().numpy(), dGo)
+    err = step_errors(w.xyz, w.tet_vert, (tin[o], lin[o], vin[o]), (tg, lg, vg), (t, l, v), dG.cpu().numpy(), dGo,
+                      lam_quantum=2.0 ** -31 if precision == E.MIXED_FIXED else 0.0)
     print(f"[sort-step] oracle {err}", flush=True)
     if heavy:
         assert (tg != tin[o]).mean() > 0.1

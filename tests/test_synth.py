@@ -37,3 +37,23 @@ def test_workloads_are_reproducible():
     for x, y in ((a.tet, b.tet), (a.lam, b.lam), (a.vel, b.vel), (a.e_env, b.e_env), (a.xyz, b.xyz)):
         assert np.array_equal(x, y)
     assert a.tet.shape == (1000,) and a.tet_vert.shape == (750, 4)
+
+
+def test_fixed_point_barycentrics_storage():
+    """The compact mixed form's storage of barycentrics (uint32, 2^-32): the
+    nearest grid point, lam_0 = 1 - sum never negative, exact round trip of
+    grid values, and the edge cases (a vertex, a face, lam_0 slightly
+    negative after rounding)."""
+    import numpy as np
+    from paper_2208_12795_amd.etpic import fixed_to_lam, lam_to_fixed
+    rng = np.random.default_rng(3)
+    g = rng.standard_exponential((100_000, 4))
+    lam = (g / g.sum(1, keepdims=True))[:, 1:]
+    lam[:6] = [[1.0, 0, 0], [0, 0, 0], [0.5, 0.5, 0], [1 / 3] * 3, [0.2, 0.3, 0.5 + 1e-12], [0.5, 0.5, 1e-13]]
+    u = lam_to_fixed(lam)
+    back = fixed_to_lam(u)
+    uu = u.view(np.uint32).astype(np.int64)
+    assert np.all(uu.sum(1) <= 1 << 32)
+    assert np.all(np.abs(back - lam) <= 1.5 * 2.0 ** -32)
+    assert np.array_equal(lam_to_fixed(back), u)
+    assert np.all(1.0 - back.sum(1) >= 0.0)

@@ -169,6 +169,18 @@ def run_form(E, torch, ctx, w, precision, steps, warmup, sort_every, fields, nlo
     kt, launches = ctx.kernel_time(reset=True)
     slices = ctx.last_push_slices()
     ctx.check()
+    # per-kernel breakdown, after the timed region: one sort block with every
+    # kernel of the step timed (each timed dispatch idles the stream for a few
+    # microseconds after it, so the timed region times the particle kernel only)
+    nbd = min(block, 10)
+    if sort_every:
+        ctx.sort_run_steps(parts, spare, sp, fields, step, nbd, w.dt, w.omega, dG,
+                           flags=E.STEP_XCD_REMAP | E.STEP_TIMING_ALL)
+        parts, spare = spare, parts
+    else:
+        ctx.run_steps(parts, sp, fields, step, nbd, w.dt, w.omega, dG, flags=E.STEP_XCD_REMAP | E.STEP_TIMING_ALL)
+    step += nbd
+    kb, nbl = ctx.kernel_time(reset=True)
     # the particle kernel's access pattern alone over the same arrays
     ctx.stream_probe(parts)
     torch.cuda.synchronize()
@@ -216,12 +228,15 @@ def run_form(E, torch, ctx, w, precision, steps, warmup, sort_every, fields, nlo
         "wall_s": wall,
         "kernel_ms": kt["push"] / max(kt["steps_push"], 1),
         "sort_step_kernel_ms": kt["push_sort"] / max(kt["steps_sort"], 1),
-        "coef_ms": kt["coef"] / max(launches, 1),
-        "walk_ms": kt["walk"] / max(launches, 1),
+        "coef_ms": kb["coef"] / max(nbl, 1),
+        "walk_ms": kb["walk"] / max(nbl, 1),
         "timing_note": "kernel_ms: particle kernel of the in-place steps; sort_step_kernel_ms: the one of the "
-                       "first step after each re-sort, which also scatters the particles to their sorted places; "
-                       "walk_ms covers the walk and, except before a sort, the next step's coefficient pass "
-                       "(one launch); coef_ms averages the stand-alone passes over all steps",
+                       "first step after each re-sort, which also scatters the particles to their sorted places "
+                       "(both from HIP events bound to the kernel's dispatches over the timed region); walk_ms "
+                       "and coef_ms per step from a block of %d steps after the timed region with every kernel "
+                       "timed: walk_ms covers the walk and, except before a sort, the next step's coefficient "
+                       "pass (one launch), and the edge gather of the per-tet sums at the end of the block; "
+                       "coef_ms averages the stand-alone passes over the steps" % nbd,
         "launches": launches,
         "sort_ms": sort_ms,
         "gauss_rel": r / p,
@@ -431,10 +446,14 @@ def coarse_step_timing(E, torch, synth, ctx, w, fine=10, reps=5):
     e1.record()
     torch.cuda.synchronize()
     kt, launches = ctx.kernel_time(reset=True)
+    ctx.coarse_step(parts, sp, snaps, (2 + reps) * dtc, dtc, fine, w.omega, dG,
+                    flags=E.STEP_XCD_REMAP | E.STEP_TIMING_ALL)
+    kb, nbl = ctx.kernel_time(reset=True)
     ctx.check()
     ms = e0.elapsed_time(e1) / (reps * fine)
     return {"fine_steps_per_coarse": fine, "ms_per_fine_step": ms, "value": parts.n / (ms * 1e-3),
-            "coef_ms": kt["coef"] / max(launches, 1), "push_ms": kt["push"] / max(kt["steps_push"], 1),
+            "coef_ms": kb["coef"] / max(nbl, 1), "walk_coef_ms": kb["walk"] / max(nbl, 1),
+            "push_ms": kt["push"] / max(kt["steps_push"], 1),
             "note": "float64, three envelope snapshots interpolated at every fine step; no sort inside"}
 
 
@@ -471,6 +490,9 @@ def ds_step_timing(E, torch, ctx, w, form="fp64", nsteps=10, reps=3):
     e1.record()
     torch.cuda.synchronize()
     kt, launches = ctx.kernel_time(reset=True)
+    s0 = 3 + reps * nsteps
+    ctx.ds_steps(parts, hist, sp, f, s0, nsteps, s0, w.dt, w.omega, dG, flags=E.STEP_XCD_REMAP | E.STEP_TIMING_ALL)
+    kb, nbl = ctx.kernel_time(reset=True)
     ctx.check()
     ms = e0.elapsed_time(e1) / (reps * nsteps)
     push_ms = kt["push"] / max(kt["steps_push"], 1)
@@ -478,7 +500,7 @@ def ds_step_timing(E, torch, ctx, w, form="fp64", nsteps=10, reps=3):
     ach = nbytes / (push_ms * 1e-3) / 1e9
     del hist
     return {"ms_per_step": ms, "value": parts.n / (ms * 1e-3), "push_ms": push_ms,
-            "walk_ms": kt["walk"] / max(launches, 1), "coef_env_ms": kt["coef"] / reps,
+            "walk_ms": kb["walk"] / max(nbl, 1), "coef_env_ms": kb["coef"],
             "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(ach / HBM_PEAK_GBS, 4),
                          "kernel": "k_push_ds<double, false>" if form == "fp64" else "k_push_ds<float, false>",

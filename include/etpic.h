@@ -110,7 +110,7 @@ enum etpic_device_flags {
 /* flags of etpic_gather_push_deposit */
 enum etpic_step_flags {
     ETPIC_STEP_XCD_REMAP = 1u, /* map consecutive particle blocks to one XCD (default on) */
-    ETPIC_STEP_TIMING = 2u,    /* bracket the step's kernels with HIP events (etpic_kernel_time) */
+    ETPIC_STEP_TIMING = 2u,    /* time the particle kernel of each step with HIP events (etpic_kernel_time) */
     /* slices of 64 particles per wavefront of the particle kernel; without one
      * of these the library picks 1, 4 or 16 from the last sort's (etpic_sort,
      * etpic_sort_run_steps, etpic_ds_sort) mean, over particles, of the number
@@ -124,7 +124,12 @@ enum etpic_step_flags {
      * their tet in one step (exercises that path); in the sorting step of
      * etpic_sort_run_steps, whose overflow path is a scan of all particles,
      * take that scan instead */
-    ETPIC_STEP_WALK_BY_SLICE = 32u
+    ETPIC_STEP_WALK_BY_SLICE = 32u,
+    /* as ETPIC_STEP_TIMING, and also the coefficient, walk and edge-gather
+     * kernels.  Each timed dispatch costs the stream a few microseconds of
+     * idle time after it, so a throughput measurement times the particle
+     * kernel only and takes this breakdown in a run of its own. */
+    ETPIC_STEP_TIMING_ALL = 256u
     /* bit 31 is the library's own and is ignored in the flags passed in */
 };
 
@@ -718,13 +723,18 @@ int etpic_tree_cotree(int64_t n_vert, const double *xyz_host, int64_t n_tet, con
                       uint8_t *edge_tree_host, uint8_t *face_tree_host, int64_t counts_out[4]);
 
 /* Kernel times of the steps launched with ETPIC_STEP_TIMING since the last
- * reset, from HIP events recorded on the launch stream around each kernel,
- * summed over the steps: ms_out[0] = particle kernel (gather, push, in-tet
- * deposit) of the steps that update the particles in place, ms_out[1] =
- * per-tet coefficient kernel, ms_out[2] = walk kernel, ms_out[3] = particle
- * kernel of the steps that also sort (the first step of
- * etpic_sort_run_steps).  launches_out (may be NULL) = number of timed steps
- * of each kind: [0] in place, [1] sorting.  Synchronises on the last event;
+ * reset, from HIP start and stop events bound to each kernel's own dispatch
+ * on the launch stream (hipExtLaunchKernel: no marker packets between the
+ * kernels, so the timing does not stretch the step), summed over the steps:
+ * ms_out[0] = particle kernel (gather, push, in-tet deposit) of the steps
+ * that update the particles in place, ms_out[1] = per-tet coefficient kernel
+ * where it runs alone, ms_out[2] = walk kernel (with the next step's
+ * coefficient pass where the two share a launch, and the gather of the
+ * per-tet current sums onto the edges at the end of a call), ms_out[3] =
+ * particle kernel of the steps that also sort (the first step of
+ * etpic_sort_run_steps); [1] and [2] only for steps run with
+ * ETPIC_STEP_TIMING_ALL (0 otherwise).  launches_out (may be NULL) = number of timed steps
+ * of each kind: [0] in place, [1] sorting.  Synchronises on the events;
  * reset != 0 clears the record afterwards. */
 int etpic_kernel_time(etpic_ctx *ctx, double ms_out[4], int64_t launches_out[2], int reset);
 

@@ -33,6 +33,7 @@
 //   k_field_spmv, k_nm_*, k_cocg_*   implicit envelope field step.
 //   k_ns_*        Gauss-law (non-solenoidal) field solve: CG on the nodal operator.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cmath>
 #include <cstdarg>
@@ -242,41 +243,82 @@ template <typename Real, int kSnap>
 __device__ __forceinline__ void tet_coef(int64_t nt, const double *__restrict__ prow,
                                          const int32_t *__restrict__ tetface, const FieldPtrs &F,
                                          Real *__restrict__ coef, unsigned blk) {
-    // a block covers kBlock/2 tets: its first half of lanes builds A_0..3
-    // (edges), the second half C_0..3 (faces), so each wavefront takes one
-    // branch with all its lanes
-    const int part = (int)(threadIdx.x >= kBlock / 2);
-    const int64_t T = (int64_t)blk * (kBlock / 2) + (threadIdx.x & (kBlock / 2 - 1));
-    if (T >= nt) return;
-    const double *row = prow + T * PushRow<double>::kStride;
-    double g[4][3];
-#pragma unroll
-    for (int k = 1; k < 4; ++k)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) g[k][d] = row[3 * (k - 1) + d];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) g[0][d] = -(g[1][d] + g[2][d] + g[3][d]);
-    int32_t tp[10];   // edge ids 0..5, face ids 6..9
-    const int32_t *re = reinterpret_cast<const int32_t *>(row + PushRow<double>::kEdges);
-#pragma unroll
-    for (int k = 0; k < 6; ++k) tp[k] = re[k];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) tp[6 + k] = tetface[4 * T + k];
-    double o[12];
-    if (part == 0) {
-        coef_A<0, kSnap>(tp, g, F, o);
-        coef_A<1, kSnap>(tp, g, F, o + 3);
-        coef_A<2, kSnap>(tp, g, F, o + 6);
-        coef_A<3, kSnap>(tp, g, F, o + 9);
-    } else {
-        coef_C<0, kSnap>(tp, g, F, o);
-        coef_C<1, kSnap>(tp, g, F, o + 3);
-        coef_C<2, kSnap>(tp, g, F, o + 6);
-        coef_C<3, kSnap>(tp, g, F, o + 9);
+    // A block covers kTets tets.  Their push rows and face ids are staged in
+    // LDS with coalesced 16-byte loads; then the block's first kTets lanes
+    // build A_0..3 (edges) and the other kTets lanes C_0..3 (faces), so each
+    // wavefront takes one branch with all its lanes; the 24-real rows go back
+    // through LDS and out with coalesced stores.  (Each lane reading its own
+    // 96-byte row and writing its own 96- or 48-byte half row strides every
+    // load and store instruction over 64 rows.)  Row strides in LDS are odd
+    // numbers of reals, so that the lanes' rows start in different banks.
+    constexpr int kTets = kBlock / 2;
+    constexpr int kRow = PushRow<double>::kStride + 1;   // staged push row, doubles
+    constexpr int kOut = 25;                             // staged coefficient row, Reals
+    constexpr int kIn = kTets * kRow + kTets * 4 / 2;    // rows + face ids, in doubles
+    constexpr int kOutD = (kTets * kOut * (int)sizeof(Real) + 7) / 8;
+    __shared__ double lds[kIn > kOutD ? kIn : kOutD];
+    const int64_t T0 = (int64_t)blk * kTets;
+    if (T0 >= nt) return;   // uniform over the block
+    const int nloc = (int)min<int64_t>(kTets, nt - T0);
+    double *srow = lds;
+    int4 *sface = reinterpret_cast<int4 *>(lds + kTets * kRow);
+    {
+        const double2 *src = reinterpret_cast<const double2 *>(prow + T0 * PushRow<double>::kStride);
+        constexpr int kHalf = PushRow<double>::kStride / 2;   // double2 per row
+        for (int i = threadIdx.x; i < nloc * kHalf; i += kBlock) {
+            const double2 v = src[i];
+            const int t = i / kHalf, c = 2 * (i - t * kHalf);
+            srow[t * kRow + c] = v.x;
+            srow[t * kRow + c + 1] = v.y;
+        }
+        const int4 *tf = reinterpret_cast<const int4 *>(tetface) + T0;
+        for (int i = threadIdx.x; i < nloc; i += kBlock) sface[i] = tf[i];
     }
-    Real *dst = coef + T * 24 + 12 * part;   // A_k at 3k, C_k at 12 + 3k
+    __syncthreads();
+    const int part = (int)(threadIdx.x >= kTets);
+    const int t = threadIdx.x & (kTets - 1);
+    double o[12];
+    if (t < nloc) {
+        const double *row = srow + t * kRow;
+        double g[4][3];
 #pragma unroll
-    for (int d = 0; d < 12; ++d) dst[d] = (Real)o[d];
+        for (int k = 1; k < 4; ++k)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) g[k][d] = row[3 * (k - 1) + d];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) g[0][d] = -(g[1][d] + g[2][d] + g[3][d]);
+        int32_t tp[10];   // edge ids 0..5, face ids 6..9
+        const int32_t *re = reinterpret_cast<const int32_t *>(row + PushRow<double>::kEdges);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) tp[k] = re[k];
+        const int4 fc = sface[t];
+        tp[6] = fc.x;
+        tp[7] = fc.y;
+        tp[8] = fc.z;
+        tp[9] = fc.w;
+        if (part == 0) {
+            coef_A<0, kSnap>(tp, g, F, o);
+            coef_A<1, kSnap>(tp, g, F, o + 3);
+            coef_A<2, kSnap>(tp, g, F, o + 6);
+            coef_A<3, kSnap>(tp, g, F, o + 9);
+        } else {
+            coef_C<0, kSnap>(tp, g, F, o);
+            coef_C<1, kSnap>(tp, g, F, o + 3);
+            coef_C<2, kSnap>(tp, g, F, o + 6);
+            coef_C<3, kSnap>(tp, g, F, o + 9);
+        }
+    }
+    __syncthreads();   // every staged row read: the space takes the output
+    Real *sout = reinterpret_cast<Real *>(lds);
+    if (t < nloc)
+#pragma unroll
+        for (int d = 0; d < 12; ++d) sout[t * kOut + 12 * part + d] = (Real)o[d];   // A_k at 3k, C_k at 12 + 3k
+    __syncthreads();
+    Real *dst = coef + T0 * 24;
+    for (int i = threadIdx.x; i < nloc * 24; i += kBlock) {
+        const int tt = i / 24;
+        dst[i] = sout[tt * kOut + (i - tt * 24)];
+    }
 }
 
 template <typename Real, int kSnap = 1>
@@ -2714,6 +2756,18 @@ struct StepPlan {
     double t;
 };
 
+// Launch of one kernel of a timed step sequence.  With events the kernel's
+// own dispatch carries them (hipExtLaunchKernel binds e0 to its start and e1
+// to its end), so timing inserts no marker packets between the kernels of a
+// step; without, a plain launch.  Errors are left for hipGetLastError.
+template <typename... P, typename... A>
+void launch_timed(void (*k)(P...), dim3 grid, hipStream_t st, hipEvent_t e0, hipEvent_t e1, A... args) {
+    if (e0)
+        hipExtLaunchKernelGGL(k, grid, dim3(kBlock), 0, st, e0, e1, 0, static_cast<P>(args)...);
+    else
+        hipLaunchKernelGGL(k, grid, dim3(kBlock), 0, st, static_cast<P>(args)...);
+}
+
 struct etpic_ctx {
     int device = 0;
     etpic::HostMesh host;
@@ -2756,31 +2810,46 @@ struct etpic_ctx {
     int64_t tiles = 0;
     FieldState field;
     NsState ns;
-    // HIP events bracketing the kernels of steps run with ETPIC_STEP_TIMING:
-    // 5 events per step (before and after the coefficient kernel, before and
-    // after the particle kernel, after the walk kernel), and whether the
-    // step's particle kernel also sorted (k_push_sort)
-    // The event sets are created with the context (a fixed pool of kTimingSets);
+    // Timing of steps run with ETPIC_STEP_TIMING: per step a set of start and
+    // stop events of its kernels, interval k = 0 coefficient pass, 1 particle
+    // kernel, 2 walk, 3 edge gather of the per-tet sums, each bound to its
+    // kernel's dispatch (launch_timed); `has` marks the intervals launched
+    // (a coefficient pass that ran inside the previous walk launch has none),
+    // `sorting` whether the particle kernel also sorted (k_push_sort).  The
+    // sets are created with the context (a fixed pool of kTimingSets, the
+    // vectors reserved so that pointers to sets stay valid);
     // etpic_kernel_time returns the read sets to the pool.
-    std::vector<std::array<hipEvent_t, 5>> timing;
-    std::vector<char> timing_sorting;
-    std::vector<std::array<hipEvent_t, 5>> spare;
+    struct TimingSet {
+        std::array<hipEvent_t, 8> ev{};
+        unsigned has = 0;
+        bool sorting = false;
+    };
+    std::vector<TimingSet> timing;
+    std::vector<TimingSet> spare;
     // host-side systems built by a size query, kept for the setup call that follows
     std::unique_ptr<etpic::FieldSystem> field_pending;
     double field_pending_eps = 0, field_pending_mu = 0;
     std::unique_ptr<etpic::NsSystem> ns_pending;
     double ns_pending_eps = 0;
 
-    int timing_events(hipEvent_t **ev, bool sorting = false) {
+    int timing_events(TimingSet **ts, bool sorting = false) {
         if (spare.empty())
             return fail(ETPIC_EINVAL, "step timing: all %d event sets in use (etpic_kernel_time returns them)",
                         kTimingSets);
         timing.push_back(spare.back());
-        timing_sorting.push_back(sorting ? 1 : 0);
         spare.pop_back();
-        *ev = timing.back().data();
+        timing.back().has = 0;
+        timing.back().sorting = sorting;
+        *ts = &timing.back();
         return ETPIC_OK;
     }
+    // start / stop event of interval k of a timing set (none without a set)
+    static hipEvent_t ev_start(TimingSet *ts, int k) {
+        if (!ts) return nullptr;
+        ts->has |= 1u << k;
+        return ts->ev[2 * k];
+    }
+    static hipEvent_t ev_stop(TimingSet *ts, int k) { return ts ? ts->ev[2 * k + 1] : nullptr; }
 
     template <typename Real>
     StepArgs<Real> step_args(const etpic_particles *p, const etpic_species *sp, double dt, double *dG,
@@ -2827,43 +2896,44 @@ struct etpic_ctx {
     int coef_xcd() const { return (16 * host.ne + 24 * host.nf) / 8 <= (int64_t)4 << 20 ? 1 : 0; }
 
     template <typename Real>
-    int launch_coef(const StepPlan &plan, double omega, hipStream_t s) {
+    int launch_coef(const StepPlan &plan, double omega, hipStream_t s, TimingSet *ts = nullptr) {
         const int64_t nt = host.nt;
         FieldPtrs F = field_ptrs(plan.snap, plan.w, std::cos(omega * plan.t), std::sin(omega * plan.t));
         F.xcd = coef_xcd();
+        hipEvent_t e0 = ev_start(ts, 0), e1 = ev_stop(ts, 0);
+        Real *coef = static_cast<Real *>(d_coef);
         if (plan.snap[1])
-            k_tet_coef<Real, 3><<<grid_for(2 * nt), kBlock, 0, s>>>(nt, d_gpush64, d_tetface, F,
-                                                                   static_cast<Real *>(d_coef));
+            launch_timed(k_tet_coef<Real, 3>, grid_for(2 * nt), s, e0, e1, nt, d_gpush64, d_tetface, F, coef);
         else
-            k_tet_coef<Real, 1><<<grid_for(2 * nt), kBlock, 0, s>>>(nt, d_gpush64, d_tetface, F,
-                                                                   static_cast<Real *>(d_coef));
+            launch_timed(k_tet_coef<Real, 1>, grid_for(2 * nt), s, e0, e1, nt, d_gpush64, d_tetface, F, coef);
         HIP_TRY(hipGetLastError());
         return ETPIC_OK;
     }
 
     template <typename Real, bool kRho, bool kSort>
-    bool launch_push(const StepArgs<Real> &a, int slices, int remap, hipStream_t st) {
+    bool launch_push(const StepArgs<Real> &a, int slices, int remap, hipStream_t st, TimingSet *ts = nullptr) {
         const int64_t n = a.n;
+        hipEvent_t e0 = ev_start(ts, 1), e1 = ev_stop(ts, 1);
         switch (slices) {
         case 16:
             if (kSort)
-                k_push_sort_slices<Real, 16, kRho><<<grid_for((n + 15) / 16), kBlock, 0, st>>>(a, remap);
+                launch_timed(k_push_sort_slices<Real, 16, kRho>, grid_for((n + 15) / 16), st, e0, e1, a, remap);
             else
-                k_push_slices<Real, 16, kRho><<<grid_for((n + 15) / 16), kBlock, 0, st>>>(a, remap);
+                launch_timed(k_push_slices<Real, 16, kRho>, grid_for((n + 15) / 16), st, e0, e1, a, remap);
             break;
         case 4:
             if (kSort)
-                k_push_sort_slices<Real, 4, kRho><<<grid_for((n + 3) / 4), kBlock, 0, st>>>(a, remap);
+                launch_timed(k_push_sort_slices<Real, 4, kRho>, grid_for((n + 3) / 4), st, e0, e1, a, remap);
             else
-                k_push_slices<Real, 4, kRho><<<grid_for((n + 3) / 4), kBlock, 0, st>>>(a, remap);
+                launch_timed(k_push_slices<Real, 4, kRho>, grid_for((n + 3) / 4), st, e0, e1, a, remap);
             break;
         default:
             if (kSort)
-                k_push_sort<Real, kRho><<<grid_for(n), kBlock, 0, st>>>(a, remap);
+                launch_timed(k_push_sort<Real, kRho>, grid_for(n), st, e0, e1, a, remap);
             else if (kRho)
-                k_push_rho<Real><<<grid_for(n), kBlock, 0, st>>>(a, remap);
+                launch_timed(k_push_rho<Real>, grid_for(n), st, e0, e1, a, remap);
             else
-                k_push<Real><<<grid_for(n), kBlock, 0, st>>>(a, remap);
+                launch_timed(k_push<Real>, grid_for(n), st, e0, e1, a, remap);
             slices = 1;
             break;
         }
@@ -2919,13 +2989,13 @@ struct etpic_ctx {
         const unsigned coef_blocks = grid_for(2 * nt);
         if (src)
             if (int r = sort_count(src, st)) return r;
-        hipEvent_t *ev = nullptr;
-        if (flags & ETPIC_STEP_TIMING) {
-            if (int r = timing_events(&ev, src != nullptr)) return r;
-            HIP_TRY(hipEventRecord(ev[0], st));
-        }
-        if (int r = launch_coef<Real>(plans[0], omega, st)) return r;
-        if (ev) HIP_TRY(hipEventRecord(ev[1], st));
+        // ts: this step's timing set; ta: the same where every kernel is timed
+        TimingSet *ts = nullptr;
+        const bool time_all = (flags & ETPIC_STEP_TIMING_ALL) != 0;
+        if (flags & (ETPIC_STEP_TIMING | ETPIC_STEP_TIMING_ALL))
+            if (int r = timing_events(&ts, src != nullptr)) return r;
+        TimingSet *ta = time_all ? ts : nullptr;
+        if (int r = launch_coef<Real>(plans[0], omega, st, ta)) return r;
         double *slots = d_tetG[tetG_cur];
         bool used_slots = false;
         for (int j = 0; j < nsteps; ++j) {
@@ -2933,7 +3003,6 @@ struct etpic_ctx {
             a.walk_by_slice = (flags & ETPIC_STEP_WALK_BY_SLICE) ? 1 : 0;
             a.fixed = (flags & kFlagFixed) ? 1 : 0;
             a.tetG = slots;
-            if (ev) HIP_TRY(hipEventRecord(ev[2], st));
             if (j == 0 && src) {
                 // read src, write p at the sorted positions; the walk then runs on p
                 StepArgs<Real> as = a;
@@ -2955,48 +3024,44 @@ struct etpic_ctx {
                 as.o_id = p->id;
                 as.cursor = d_count;
                 if (as.rho)
-                    used_slots |= launch_push<Real, true, true>(as, push_slices_for(flags, n), remap, st);
+                    used_slots |= launch_push<Real, true, true>(as, push_slices_for(flags, n), remap, st, ts);
                 else
-                    used_slots |= launch_push<Real, false, true>(as, push_slices_for(flags, n), remap, st);
+                    used_slots |= launch_push<Real, false, true>(as, push_slices_for(flags, n), remap, st, ts);
                 a.scatter = 1;
             } else if (a.rho) {
-                used_slots |= launch_push<Real, true, false>(a, push_slices_for(flags, n), remap, st);
+                used_slots |= launch_push<Real, true, false>(a, push_slices_for(flags, n), remap, st, ts);
             } else {
-                used_slots |= launch_push<Real, false, false>(a, push_slices_for(flags, n), remap, st);
+                used_slots |= launch_push<Real, false, false>(a, push_slices_for(flags, n), remap, st, ts);
             }
             HIP_TRY(hipGetLastError());
-            if (ev) HIP_TRY(hipEventRecord(ev[3], st));
+            hipEvent_t w0 = ev_start(ta, 2), w1 = ev_stop(ta, 2);
             if (j + 1 < nsteps) {
                 const StepPlan &nx = plans[j + 1];
                 FieldPtrs F = field_ptrs(nx.snap, nx.w, std::cos(omega * nx.t), std::sin(omega * nx.t));
                 F.xcd = coef_xcd();
                 if (nx.snap[1])
-                    k_walk_coef<Real, 3><<<kWalkBlocks + coef_blocks, kBlock, 0, st>>>(a, nt, F);
+                    launch_timed(k_walk_coef<Real, 3>, kWalkBlocks + coef_blocks, st, w0, w1, a, nt, F);
                 else
-                    k_walk_coef<Real, 1><<<kWalkBlocks + coef_blocks, kBlock, 0, st>>>(a, nt, F);
+                    launch_timed(k_walk_coef<Real, 1>, kWalkBlocks + coef_blocks, st, w0, w1, a, nt, F);
             } else {
-                k_walk<Real><<<kWalkBlocks, kBlock, 0, st>>>(a);
+                launch_timed(k_walk<Real>, kWalkBlocks, st, w0, w1, a);
                 if (used_slots) {
                     // the call's per-tet sums onto the edges; the other slot
                     // buffer is cleared for the next call
                     HIP_TRY(hipGetLastError());
                     const int64_t ne = host.ne;
                     const unsigned gb = (unsigned)std::min<int64_t>(grid_for(std::max<int64_t>(ne, 8 * nt)), 4096);
-                    k_slots_to_edges<<<gb, kBlock, 0, st>>>(ne, d_e2s_ptr, d_e2s_slot, slots, dG,
-                                                            d_tetG[tetG_cur ^ 1], 8 * nt);
+                    launch_timed(k_slots_to_edges, gb, st, ev_start(ta, 3), ev_stop(ta, 3), ne, d_e2s_ptr,
+                                 d_e2s_slot, slots, dG, d_tetG[tetG_cur ^ 1], 8 * nt);
                     tetG_cur ^= 1;
                 }
             }
             HIP_TRY(hipGetLastError());
-            if (ev) {
-                HIP_TRY(hipEventRecord(ev[4], st));
-                // the next step's coefficient pass ran inside this launch: it
-                // gets an empty interval, and the shared launch is booked as walk
-                if (j + 1 < nsteps) {
-                    if (int r = timing_events(&ev)) return r;
-                    HIP_TRY(hipEventRecord(ev[0], st));
-                    HIP_TRY(hipEventRecord(ev[1], st));
-                }
+            // the next step's coefficient pass ran inside this launch (booked
+            // as walk): its set has no coefficient interval
+            if (ts && j + 1 < nsteps) {
+                if (int r = timing_events(&ts)) return r;
+                ta = time_all ? ts : nullptr;
             }
         }
         return ETPIC_OK;
@@ -3035,19 +3100,19 @@ struct etpic_ctx {
         const int64_t n = p->n, nt = host.nt;
         if (!d_coef_env)
             return fail(ETPIC_ESTATE, "no downshifted rows bound (etpic_ds_rows_bytes, etpic_ds_rows_bind)");
-        hipEvent_t *ev = nullptr;
-        if (flags & ETPIC_STEP_TIMING) {
-            if (int r = timing_events(&ev)) return r;
-            HIP_TRY(hipEventRecord(ev[0], st));
-        }
+        TimingSet *ts = nullptr;
+        const bool time_all = (flags & ETPIC_STEP_TIMING_ALL) != 0;
+        if (flags & (ETPIC_STEP_TIMING | ETPIC_STEP_TIMING_ALL))
+            if (int r = timing_events(&ts)) return r;
+        TimingSet *ta = time_all ? ts : nullptr;
         {
             const etpic_fields *snap[3] = {f, nullptr, nullptr};
             const double w1[3] = {1.0, 0.0, 0.0};
             const FieldPtrs F = field_ptrs(snap, w1, 1.0, 0.0);
-            k_tet_coef_env<<<dim3(grid_for(nt), 6), kBlock, 0, st>>>(nt, d_gpush64, d_tetface, F, d_coef_env);
+            launch_timed(k_tet_coef_env, dim3(grid_for(nt), 6), st, ev_start(ta, 0), ev_stop(ta, 0), nt, d_gpush64,
+                         d_tetface, F, d_coef_env);
             HIP_TRY(hipGetLastError());
         }
-        if (ev) HIP_TRY(hipEventRecord(ev[1], st));
         for (int j = 0; j < nsteps; ++j) {
             const int64_t sn = step0 + j;
             const int H = hist0 + j;
@@ -3079,22 +3144,16 @@ struct etpic_ctx {
             for (int k = 0; k < 4; ++k) d.ab[k] = (Real)W.ab[k];
             d.qm = (Real)(sp->q / sp->m);
             d.edc = f->e_dc ? 1 : 0;
-            if (ev) HIP_TRY(hipEventRecord(ev[2], st));
             if (a.rho)
-                k_push_ds<Real, true><<<grid_for(n), kBlock, 0, st>>>(a, d, remap);
+                launch_timed(k_push_ds<Real, true>, grid_for(n), st, ev_start(ts, 1), ev_stop(ts, 1), a, d, remap);
             else
-                k_push_ds<Real, false><<<grid_for(n), kBlock, 0, st>>>(a, d, remap);
+                launch_timed(k_push_ds<Real, false>, grid_for(n), st, ev_start(ts, 1), ev_stop(ts, 1), a, d, remap);
             HIP_TRY(hipGetLastError());
-            if (ev) HIP_TRY(hipEventRecord(ev[3], st));
-            k_walk_ds<Real><<<kWalkBlocks, kBlock, 0, st>>>(a, d);
+            launch_timed(k_walk_ds<Real>, kWalkBlocks, st, ev_start(ta, 2), ev_stop(ta, 2), a, d);
             HIP_TRY(hipGetLastError());
-            if (ev) {
-                HIP_TRY(hipEventRecord(ev[4], st));
-                if (j + 1 < nsteps) {
-                    if (int r = timing_events(&ev)) return r;
-                    HIP_TRY(hipEventRecord(ev[0], st));
-                    HIP_TRY(hipEventRecord(ev[1], st));
-                }
+            if (ts && j + 1 < nsteps) {
+                if (int r = timing_events(&ts)) return r;
+                ta = time_all ? ts : nullptr;
             }
         }
         return ETPIC_OK;
@@ -3351,16 +3410,20 @@ int etpic_create(etpic_ctx **out, int device) {
     hipError_t e = hipSetDevice(device);
     if (e == hipSuccess) e = hipHostMalloc(&c->h_runstat, sizeof(unsigned long long), hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->runstat_ev, hipEventDisableTiming);
+    c->spare.reserve(kTimingSets);
+    c->timing.reserve(kTimingSets);
     for (int k = 0; k < kTimingSets && e == hipSuccess; ++k) {
-        std::array<hipEvent_t, 5> set{};
+        etpic_ctx::TimingSet set{};
         int made = 0;
-        for (auto &x : set) {
-            e = hipEventCreate(&x);
+        for (auto &x : set.ev) {
+            // timing only: no system-scope fence when the event completes (no
+            // cache writeback and invalidation between the kernels it times)
+            e = hipEventCreateWithFlags(&x, hipEventDisableSystemFence);
             if (e != hipSuccess) break;
             ++made;
         }
         if (e != hipSuccess)
-            for (int i = 0; i < made; ++i) (void)hipEventDestroy(set[i]);
+            for (int i = 0; i < made; ++i) (void)hipEventDestroy(set.ev[i]);
         else
             c->spare.push_back(set);
     }
@@ -3370,7 +3433,7 @@ int etpic_create(etpic_ctx **out, int device) {
         if (c->h_runstat) (void)hipHostFree(c->h_runstat);
         if (c->runstat_ev) (void)hipEventDestroy(c->runstat_ev);
         for (auto &set : c->spare)
-            for (auto x : set) (void)hipEventDestroy(x);
+            for (auto x : set.ev) (void)hipEventDestroy(x);
         delete c;
         if (rs != ETPIC_OK) return rs;
         return fail(ETPIC_EHIP, "context setup: %s", hipGetErrorString(e));
@@ -3387,9 +3450,9 @@ int etpic_destroy(etpic_ctx *ctx) {
     (void)hipHostFree(ctx->h_runstat);
     (void)hipEventDestroy(ctx->runstat_ev);
     for (auto &e : ctx->timing)
-        for (auto x : e) (void)hipEventDestroy(x);
+        for (auto x : e.ev) (void)hipEventDestroy(x);
     for (auto &e : ctx->spare)
-        for (auto x : e) (void)hipEventDestroy(x);
+        for (auto x : e.ev) (void)hipEventDestroy(x);
     delete ctx;
     return ETPIC_OK;
 }
@@ -4633,18 +4696,19 @@ int etpic_kernel_time(etpic_ctx *ctx, double ms_out[4], int64_t launches_out[2],
     if (int r = set_device(ctx)) return r;
     double tot[4] = {0.0, 0.0, 0.0, 0.0};
     int64_t cnt[2] = {0, 0};
-    for (size_t i = 0; i < ctx->timing.size(); ++i) {
-        const auto &e = ctx->timing[i];
-        const int sorting = ctx->timing_sorting[i] ? 1 : 0;
-        HIP_TRY(hipEventSynchronize(e[4]));
-        float m[3] = {0.f, 0.f, 0.f};
-        HIP_TRY(hipEventElapsedTime(&m[0], e[2], e[3]));   // particle kernel
-        HIP_TRY(hipEventElapsedTime(&m[1], e[0], e[1]));   // coefficient kernel
-        HIP_TRY(hipEventElapsedTime(&m[2], e[3], e[4]));   // walk kernel
-        tot[sorting ? 3 : 0] += m[0];
-        tot[1] += m[1];
-        tot[2] += m[2];
-        ++cnt[sorting];
+    for (const auto &t : ctx->timing) {
+        const int sorting = t.sorting ? 1 : 0;
+        // intervals: coefficient pass, particle kernel, walk, edge gather
+        float m[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int k = 0; k < 4; ++k)
+            if (t.has & (1u << k)) {
+                HIP_TRY(hipEventSynchronize(t.ev[2 * k + 1]));
+                HIP_TRY(hipEventElapsedTime(&m[k], t.ev[2 * k], t.ev[2 * k + 1]));
+            }
+        tot[sorting ? 3 : 0] += m[1];
+        tot[1] += m[0];
+        tot[2] += m[2] + m[3];
+        if (t.has & 2u) ++cnt[sorting];
     }
     for (int k = 0; k < 4; ++k) ms_out[k] = tot[k];
     if (launches_out) {
@@ -4654,7 +4718,6 @@ int etpic_kernel_time(etpic_ctx *ctx, double ms_out[4], int64_t launches_out[2],
     if (reset) {
         for (auto &e : ctx->timing) ctx->spare.push_back(e);
         ctx->timing.clear();
-        ctx->timing_sorting.clear();
     }
     return ETPIC_OK;
 }

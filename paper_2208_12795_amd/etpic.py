@@ -21,6 +21,7 @@ FP64, MIXED, MIXED_FIXED = 0, 1, 2
 DEV_HOPCAP, DEV_NAN, DEV_BADTET = 1, 2, 4
 STEP_XCD_REMAP = 1
 STEP_TIMING = 2
+STEP_TIMING_ALL = 256
 STEP_SLICES_1, STEP_SLICES_4, STEP_SLICES_16 = 4, 8, 16
 STEP_WALK_BY_SLICE = 32
 NS_WARM = 64
@@ -556,7 +557,8 @@ class Context:
 
     def kernel_time(self, reset=True):
         """({"push", "coef", "walk", "push_sort"} total ms, steps) of the kernels
-        of the steps run with STEP_TIMING; "push" covers the steps that update
+        of the steps run with STEP_TIMING (particle kernel only) or
+        STEP_TIMING_ALL (every kernel); "push" covers the steps that update
         the particles in place, "push_sort" the sorting first steps of
         sort_run_steps, and the dict's "steps_push" / "steps_sort" count them."""
         ms = np.zeros(4)

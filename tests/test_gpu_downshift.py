@@ -122,7 +122,7 @@ def test_multi_step_call_equals_single_calls(E, torch_cuda, precision):
     rho = torch.zeros(ctx.n_vert, dtype=torch.float64, device="cuda")
     dt = 5 * w.dt
     ctx.kernel_time(reset=True)
-    ctx.ds_steps(p1, h1, sp, f, 11, 7, 0, dt, w.omega, g1, rho=rho, flags=E.STEP_XCD_REMAP | E.STEP_TIMING)
+    ctx.ds_steps(p1, h1, sp, f, 11, 7, 0, dt, w.omega, g1, rho=rho, flags=E.STEP_XCD_REMAP | E.STEP_TIMING_ALL)
     kt, nl = ctx.kernel_time(reset=True)
     assert nl == 7 and kt["push"] > 0 and kt["walk"] > 0
     for j in range(7):

@@ -103,8 +103,8 @@ def test_equal_snapshots_are_fine_steps(E, torch_cuda):
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_run_steps_equals_single_steps(E, torch_cuda, precision):
-    """Ten steps in one call (the coefficient pass of the next step overlapping
-    the walk on the library's side stream) against ten single-step calls: the
+    """Ten steps in one call (the coefficient pass of the next step sharing a
+    launch with the walk of this one) against ten single-step calls: the
     particle state is identical, the currents equal to the atomics' rounding,
     the charge after the last step matches a separate scatter, and the kernel
     timings cover every step."""
@@ -122,7 +122,7 @@ def test_run_steps_equals_single_steps(E, torch_cuda, precision):
     g2 = torch.zeros_like(g1)
     rho = torch.zeros(ctx.n_vert, dtype=torch.float64, device="cuda")
     ctx.kernel_time(reset=True)
-    ctx.run_steps(p1, sp, f, 3, 10, w.dt, w.omega, g1, rho=rho, flags=E.STEP_XCD_REMAP | E.STEP_TIMING)
+    ctx.run_steps(p1, sp, f, 3, 10, w.dt, w.omega, g1, rho=rho, flags=E.STEP_XCD_REMAP | E.STEP_TIMING_ALL)
     kt, nl = ctx.kernel_time(reset=True)
     assert nl == 10 and kt["steps_push"] == 10 and kt["steps_sort"] == 0
     assert min(kt["push"], kt["coef"], kt["walk"]) > 0.0 and kt["push_sort"] == 0.0
@@ -136,4 +136,37 @@ def test_run_steps_equals_single_steps(E, torch_cuda, precision):
     rho2 = torch.zeros_like(rho)
     ctx.vertex_charge(p1, sp, rho2)
     assert torch.allclose(rho, rho2, rtol=0, atol=1e-13 * rho2.abs().max().item())
+    ctx.close()
+
+
+def test_step_timing_modes(E, torch_cuda):
+    """STEP_TIMING times the particle kernel of every step and nothing else;
+    STEP_TIMING_ALL also the coefficient, walk and edge-gather kernels; a
+    sorting call books its first particle kernel apart.  Timing changes no
+    result: the same steps without timing give identical particles."""
+    torch = torch_cuda
+    w = synth.make_workload(2, n_particles=200_000)
+    ctx = E.Context(0)
+    ctx.upload_mesh(w.xyz, w.tet_vert)
+    f = E.Fields.from_numpy(w.e_env, w.b_env, None, w.b_dc)
+    sp = E.Species(w.q, w.m, w.w)
+    p = E.Particles.from_numpy(w.tet, w.lam, w.vel, w.ids)
+    q = p.clone()
+    g = torch.zeros(ctx.n_edge, dtype=torch.float64, device="cuda")
+    ctx.kernel_time(reset=True)
+    ctx.run_steps(p, sp, f, 0, 6, w.dt, w.omega, g, flags=E.STEP_XCD_REMAP | E.STEP_TIMING)
+    kt, nl = ctx.kernel_time(reset=True)
+    assert nl == 6 and kt["steps_push"] == 6 and kt["push"] > 0.0
+    assert kt["coef"] == 0.0 and kt["walk"] == 0.0 and kt["push_sort"] == 0.0
+    ctx.run_steps(q, sp, f, 0, 6, w.dt, w.omega, g, flags=E.STEP_XCD_REMAP)
+    ctx.kernel_time(reset=True)
+    assert ctx.kernel_time(reset=True)[1] == 0
+    for x, y in zip(p.to_numpy(), q.to_numpy()):
+        assert np.array_equal(x, y)
+    dst = p.empty_like()
+    ctx.sort_run_steps(p, dst, sp, f, 6, 4, w.dt, w.omega, g, flags=E.STEP_XCD_REMAP | E.STEP_TIMING_ALL)
+    kt, nl = ctx.kernel_time(reset=True)
+    assert nl == 4 and kt["steps_sort"] == 1 and kt["steps_push"] == 3
+    assert min(kt["push"], kt["push_sort"], kt["coef"], kt["walk"]) > 0.0
+    ctx.check()
     ctx.close()

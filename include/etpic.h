@@ -76,7 +76,8 @@ enum etpic_status {
     ETPIC_EPARTICLE = -5, /* particle tet index out of range */
     ETPIC_EWALK = -6,     /* a particle exceeded the walk hop cap */
     ETPIC_ENAN = -7,      /* non-finite value met in a kernel */
-    ETPIC_ENOCONV = -8    /* iterative solve did not converge */
+    ETPIC_ENOCONV = -8,   /* iterative solve did not converge */
+    ETPIC_EIO = -9        /* checkpoint file missing, unreadable, corrupt or not writable */
 };
 
 enum etpic_precision {
@@ -244,6 +245,39 @@ int etpic_mesh_faces(const etpic_ctx *ctx, int32_t *face_vert_host);
  * fixed-point grid).  Errors: EINVAL, ESTATE, EPARTICLE, EHIP. */
 int etpic_particles_locate(etpic_ctx *ctx, const etpic_particles *p, int precision, const double *const xyz[3],
                            const int32_t *hint, void *stream);
+
+/* Host checkpoint of the particle state of a time loop, so that a run
+ * resumes where it stopped: (tet, lam_1..3, v, id) and the step index.
+ * Fields, currents and charges are the caller's arrays and are not part of
+ * it.  The file (a 136-byte header, then the arrays as stored on the device,
+ * see checkpoint_host.hpp) carries the FNV-1a checksum of every array and of
+ * the header, and a hash of the uploaded mesh: a checkpoint is read back only
+ * on the same mesh (same vertex coordinates and tet vertex ids, bit for bit).
+ *
+ * etpic_checkpoint_write: copies the particles (device, p->n of them, stored
+ * as `precision` says) to `path` through host chunks of 16 MiB on `stream`
+ * (ordered after the work already queued there; synchronous on return).  It
+ * writes `path`.tmp and renames it, so an existing checkpoint is replaced
+ * whole or not at all.  The id array is saved when p->id is non-null.
+ * Errors: EINVAL, ESTATE (no mesh), EIO (file), EHIP. */
+int etpic_checkpoint_write(etpic_ctx *ctx, const etpic_particles *p, int precision, int64_t step, const char *path,
+                           void *stream);
+
+/* Header of a checkpoint file, host only (no context, no GPU): particle
+ * count, precision, step index, whether ids are stored (each output may be
+ * NULL).  EIO for a missing, short, foreign or corrupt header or a file whose
+ * size does not match it. */
+int etpic_checkpoint_info(const char *path, int64_t *n, int *precision, int64_t *step, int *has_id);
+
+/* Reads a checkpoint into the particle arrays of p (device, allocated by the
+ * caller with p->n = the checkpoint's count; etpic_checkpoint_info gives it)
+ * and returns its step index in *step (may be NULL).  The checkpoint's
+ * precision must equal `precision`, and p->id must be given exactly when the
+ * checkpoint holds ids (EINVAL otherwise); a checkpoint of another mesh is
+ * EMESH.  Every array's checksum is checked as it is read: EIO on a mismatch,
+ * after which the particle arrays hold partly read data.  Synchronous. */
+int etpic_checkpoint_read(etpic_ctx *ctx, const etpic_particles *p, int precision, const char *path, int64_t *step,
+                          void *stream);
 
 /* Cartesian positions x = sum_k lam_k r_k of the particles into the device
  * float64 arrays xyz[0..2] (length p->n).  A tet index outside [0, N_t) gives

@@ -7,7 +7,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libetpic.so")
 SOURCES = [os.path.join(HERE, "csrc", "etpic.hip"), os.path.join(HERE, "csrc", "mesh_host.cpp"),
-           os.path.join(HERE, "csrc", "field_host.cpp"), os.path.join(HERE, "csrc", "qh.hip")]
+           os.path.join(HERE, "csrc", "field_host.cpp"), os.path.join(HERE, "csrc", "checkpoint_host.cpp"),
+           os.path.join(HERE, "csrc", "qh.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -51,6 +51,7 @@
 #include "etpic.h"
 #include "field_host.hpp"
 #include "mesh_host.hpp"
+#include "checkpoint_host.hpp"
 
 using etpic::TetTopo;
 
@@ -2772,6 +2773,7 @@ struct etpic_ctx {
     int device = 0;
     etpic::HostMesh host;
     bool has_mesh = false;
+    uint64_t mesh_hash = 0;   // hash of the uploaded mesh (particle checkpoints resume on it only)
     TetTopo *d_topo = nullptr;
     double *d_grad64 = nullptr;
     double *d_gpush64 = nullptr;     // nt rows of PushRow<double>
@@ -3663,6 +3665,7 @@ int etpic_mesh_upload(etpic_ctx *ctx, int64_t n_vert, const double *xyz_host, in
     HIP_TRY(hipDeviceSynchronize());
     ctx->host = std::move(M);
     ctx->has_mesh = true;
+    ctx->mesh_hash = etpic::ckpt::mesh_hash(n_vert, xyz_host, n_tet, tet_vert_host);
     return ETPIC_OK;
 }
 
@@ -4005,6 +4008,97 @@ int etpic_particles_positions(etpic_ctx *ctx, const etpic_particles *p, int prec
         p->n, ctx->host.nt, p->lam[0], p->lam[1], p->lam[2], p->tet, ctx->d_topo, ctx->d_xyz, xyz[0], xyz[1], xyz[2],
         ctx->d_status, precision == ETPIC_MIXED_FIXED ? 1 : 0);
     HIP_TRY(hipGetLastError());
+    return ETPIC_OK;
+}
+
+// ------------------------------------------------------------------ checkpoints
+namespace {
+// the particle arrays in the checkpoint file's order
+void particle_arrays(const etpic_particles *p, void *arr[etpic::ckpt::kArrays]) {
+    arr[0] = p->tet;
+    for (int k = 0; k < 3; ++k) {
+        arr[1 + k] = p->lam[k];
+        arr[4 + k] = p->vel[k];
+    }
+    arr[7] = p->id;
+}
+}  // namespace
+
+int etpic_checkpoint_write(etpic_ctx *ctx, const etpic_particles *p, int precision, int64_t step, const char *path,
+                           void *stream) {
+    if (!ctx || !p || !path) return fail(ETPIC_EINVAL, "null argument");
+    if (int r = check_precision(precision, true)) return r;
+    if (!ctx->has_mesh) return fail(ETPIC_ESTATE, "no mesh uploaded");
+    if (int r = check_particles(ctx, p)) return r;
+    if (int r = set_device_only(ctx)) return r;
+    etpic::ckpt::Header h{};
+    h.precision = (uint32_t)precision;
+    h.n = p->n;
+    h.step = step;
+    h.n_tet = ctx->host.nt;
+    h.n_vert = ctx->host.nv;
+    h.mesh_hash = ctx->mesh_hash;
+    h.has_id = p->id ? 1u : 0u;
+    void *arr[etpic::ckpt::kArrays];
+    particle_arrays(p, arr);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t herr = hipSuccess;
+    auto fetch = [&](int k, size_t off, void *buf, size_t len) -> std::string {
+        herr = hipMemcpyAsync(buf, static_cast<const char *>(arr[k]) + off, len, hipMemcpyDeviceToHost, st);
+        if (herr == hipSuccess) herr = hipStreamSynchronize(st);
+        return herr == hipSuccess ? std::string() : std::string("device to host copy: ") + hipGetErrorString(herr);
+    };
+    const std::string e = etpic::ckpt::write(path, h, fetch);
+    if (!e.empty()) return fail(herr != hipSuccess ? ETPIC_EHIP : ETPIC_EIO, "checkpoint write: %s", e.c_str());
+    return ETPIC_OK;
+}
+
+int etpic_checkpoint_info(const char *path, int64_t *n, int *precision, int64_t *step, int *has_id) {
+    if (!path) return fail(ETPIC_EINVAL, "null path");
+    etpic::ckpt::Header h{};
+    const std::string e = etpic::ckpt::read_header(path, h);
+    if (!e.empty()) return fail(ETPIC_EIO, "checkpoint: %s", e.c_str());
+    if (n) *n = h.n;
+    if (precision) *precision = (int)h.precision;
+    if (step) *step = h.step;
+    if (has_id) *has_id = (int)h.has_id;
+    return ETPIC_OK;
+}
+
+int etpic_checkpoint_read(etpic_ctx *ctx, const etpic_particles *p, int precision, const char *path, int64_t *step,
+                          void *stream) {
+    if (!ctx || !p || !path) return fail(ETPIC_EINVAL, "null argument");
+    if (int r = check_precision(precision, true)) return r;
+    if (!ctx->has_mesh) return fail(ETPIC_ESTATE, "no mesh uploaded");
+    if (int r = check_particles(ctx, p)) return r;
+    etpic::ckpt::Header h{};
+    {
+        const std::string e = etpic::ckpt::read_header(path, h);
+        if (!e.empty()) return fail(ETPIC_EIO, "checkpoint: %s", e.c_str());
+    }
+    if ((int)h.precision != precision)
+        return fail(ETPIC_EINVAL, "checkpoint precision %u, particles given as %d", h.precision, precision);
+    if (h.n != p->n)
+        return fail(ETPIC_EINVAL, "checkpoint holds %lld particles, arrays hold %lld", (long long)h.n, (long long)p->n);
+    if (h.n > 0 && (h.has_id != 0) != (p->id != nullptr))
+        return fail(ETPIC_EINVAL, h.has_id ? "checkpoint has particle ids, no id array given"
+                                           : "checkpoint has no particle ids, an id array was given");
+    if (h.n_tet != ctx->host.nt || h.n_vert != ctx->host.nv || h.mesh_hash != ctx->mesh_hash)
+        return fail(ETPIC_EMESH, "checkpoint taken on another mesh (%lld tets, %lld vertices)", (long long)h.n_tet,
+                    (long long)h.n_vert);
+    if (int r = set_device_only(ctx)) return r;
+    void *arr[etpic::ckpt::kArrays];
+    particle_arrays(p, arr);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t herr = hipSuccess;
+    auto store = [&](int k, size_t off, void *buf, size_t len) -> std::string {
+        herr = hipMemcpyAsync(static_cast<char *>(arr[k]) + off, buf, len, hipMemcpyHostToDevice, st);
+        if (herr == hipSuccess) herr = hipStreamSynchronize(st);
+        return herr == hipSuccess ? std::string() : std::string("host to device copy: ") + hipGetErrorString(herr);
+    };
+    const std::string e = etpic::ckpt::read(path, h, store);
+    if (!e.empty()) return fail(herr != hipSuccess ? ETPIC_EHIP : ETPIC_EIO, "checkpoint read: %s", e.c_str());
+    if (step) *step = h.step;
     return ETPIC_OK;
 }
 

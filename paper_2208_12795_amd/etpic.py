@@ -16,7 +16,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libetpic.so")
 
-OK, EINVAL, ESTATE, EHIP, EMESH, EPARTICLE, EWALK, ENAN, ENOCONV = 0, -1, -2, -3, -4, -5, -6, -7, -8
+OK, EINVAL, ESTATE, EHIP, EMESH, EPARTICLE, EWALK, ENAN, ENOCONV, EIO = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9
 FP64, MIXED, MIXED_FIXED = 0, 1, 2
 DEV_HOPCAP, DEV_NAN, DEV_BADTET = 1, 2, 4
 STEP_XCD_REMAP = 1
@@ -42,8 +42,18 @@ EXPORTS = (
     "etpic_ns_bytes", "etpic_ns_setup", "etpic_ns_info", "etpic_ns_solve", "etpic_ns_run_steps", "etpic_ns_correct", "etpic_em_steps",
     "etpic_sol_source",
     "etpic_qh_last_error", "etpic_qh_create", "etpic_qh_bytes", "etpic_qh_bind", "etpic_qh_destroy", "etpic_qh_counts", "etpic_qh_project_b",
-    "etpic_qh_project_e", "etpic_tree_cotree",
+    "etpic_qh_project_e", "etpic_tree_cotree", "etpic_checkpoint_write", "etpic_checkpoint_info",
+    "etpic_checkpoint_read",
 )
+
+
+def checkpoint_info(path):
+    """Header of a particle checkpoint file (host only): n, precision, step,
+    has_id."""
+    n, step = C.c_int64(0), C.c_int64(0)
+    prec, has_id = C.c_int(0), C.c_int(0)
+    _chk(lib().etpic_checkpoint_info(os.fsencode(path), C.byref(n), C.byref(prec), C.byref(step), C.byref(has_id)))
+    return {"n": int(n.value), "precision": int(prec.value), "step": int(step.value), "has_id": bool(has_id.value)}
 
 
 class EtpicError(RuntimeError):
@@ -113,6 +123,9 @@ def lib():
                                  C.c_double, C.c_double, C.c_int, vp, C.c_size_t, C.c_void_p * 3, C.c_void_p * 3,
                                  vp, vp]
     L.etpic_check.argtypes = [vp, vp, C.POINTER(C.c_uint32)]
+    L.etpic_checkpoint_write.argtypes = [vp, C.POINTER(_Particles), C.c_int, C.c_int64, C.c_char_p, vp]
+    L.etpic_checkpoint_info.argtypes = [C.c_char_p, i64p, C.POINTER(C.c_int), i64p, C.POINTER(C.c_int)]
+    L.etpic_checkpoint_read.argtypes = [vp, C.POINTER(_Particles), C.c_int, C.c_char_p, i64p, vp]
     L.etpic_particles_locate.argtypes = [vp, C.POINTER(_Particles), C.c_int, C.c_void_p * 3, vp, vp]
     L.etpic_particles_positions.argtypes = [vp, C.POINTER(_Particles), C.c_int, C.c_void_p * 3, vp]
     L.etpic_run_steps.argtypes = [vp, C.POINTER(_Particles), C.c_int, C.POINTER(_Species), C.POINTER(_Fields),
@@ -706,6 +719,34 @@ class Context:
                                   _dptr(u), _dptr(v), _dptr(a), _dptr(b), _dptr(e), _dptr(G), _dptr(G_hist),
                                   _dptr(rho0), float(tol), int(max_iter), fl, C.byref(it), _stream(stream)))
         return it.value
+
+    # checkpoint / resume of the particle state --------------------------------
+    def checkpoint_write(self, parts, step, path, stream=None):
+        """Saves parts (and the step index) to the host file `path`."""
+        d = parts.desc()
+        _chk(lib().etpic_checkpoint_write(self._h, C.byref(d), parts.precision, int(step), os.fsencode(path),
+                                          _stream(stream)))
+
+    def checkpoint_read(self, parts, path, stream=None):
+        """Reads the checkpoint `path` into parts (same count, precision and id
+        presence); returns its step index."""
+        d = parts.desc()
+        step = C.c_int64(0)
+        _chk(lib().etpic_checkpoint_read(self._h, C.byref(d), parts.precision, os.fsencode(path), C.byref(step),
+                                         _stream(stream)))
+        return int(step.value)
+
+    def checkpoint_load(self, path, device="cuda", stream=None):
+        """(Particles, step) of the checkpoint `path`, in new device arrays."""
+        import torch
+        info = checkpoint_info(path)
+        n, prec = info["n"], info["precision"]
+        lam = torch.empty((3, n), dtype=torch.int32 if prec == MIXED_FIXED else torch.float64, device=device)
+        vel = torch.empty((3, n), dtype=torch.float64 if prec == FP64 else torch.float32, device=device)
+        tet = torch.empty(n, dtype=torch.int32, device=device)
+        ids = torch.empty(n, dtype=torch.int64, device=device) if info["has_id"] else None
+        parts = Particles(lam, vel, tet, ids)
+        return parts, self.checkpoint_read(parts, path, stream=stream)
 
     def check(self, stream=None, raise_on_error=True):
         word = C.c_uint32(0)

@@ -1,5 +1,6 @@
 // Exercise of the library's host-side C++ (mesh canonicalisation, start grid,
-// tree-cotree split, field and Gauss-law system assembly) built with
+// tree-cotree split, field and Gauss-law system assembly, the particle
+// checkpoint file) built with
 // AddressSanitizer and UndefinedBehaviorSanitizer on the CPU.  Meshes are
 // jittered Kuhn boxes made here; every call's output is checked for the
 // invariants it must satisfy, and the rejection paths are driven with bad
@@ -7,9 +8,12 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <cstring>
 #include <string>
+#include <unistd.h>
 #include <vector>
 
+#include "checkpoint_host.hpp"
 #include "field_host.hpp"
 #include "mesh_host.hpp"
 
@@ -153,12 +157,96 @@ void rejections() {
     check(etpic::build_host_mesh(7, xyz, 3, three, M, err) != 0, "non-manifold face refused");
 }
 
+// Particle checkpoint: write from host arrays and read back through small
+// chunks (so that arrays span several), every precision with and without ids;
+// a corrupted array byte, a truncated file and a failing transfer are
+// reported, and a failed write leaves the previous checkpoint in place.
+void checkpoints(const std::string &dir) {
+    namespace ck = etpic::ckpt;
+    const std::string path = dir + "/host_driver_ckpt.bin";
+    for (uint32_t prec = 0; prec <= 2; ++prec)
+        for (int has_id = 0; has_id <= 1; ++has_id) {
+            const int64_t n = 1003;
+            std::vector<std::vector<unsigned char>> src(ck::kArrays), dst(ck::kArrays);
+            for (int k = 0; k < ck::kArrays; ++k) {
+                src[k].resize(ck::array_bytes(prec, n, k, has_id != 0));
+                for (auto &b : src[k]) b = (unsigned char)(uniform() * 256.0);
+                dst[k].assign(src[k].size(), 0);
+            }
+            ck::Header h{};
+            h.precision = prec;
+            h.n = n;
+            h.step = 77;
+            h.n_tet = 5;
+            h.n_vert = 9;
+            h.mesh_hash = 42;
+            h.has_id = (uint32_t)has_id;
+            auto fetch = [&](int k, size_t off, void *buf, size_t len) -> std::string {
+                if (off + len > src[k].size()) return "fetch out of range";
+                std::memcpy(buf, src[k].data() + off, len);
+                return "";
+            };
+            auto store = [&](int k, size_t off, void *buf, size_t len) -> std::string {
+                if (off + len > dst[k].size()) return "store out of range";
+                std::memcpy(dst[k].data() + off, buf, len);
+                return "";
+            };
+            check(ck::write(path, h, fetch, 1000).empty(), "checkpoint written", prec, has_id);
+            ck::Header r{};
+            check(ck::read_header(path, r).empty(), "checkpoint header read", prec, has_id);
+            check(r.n == n && r.step == 77 && r.precision == prec && r.has_id == (uint32_t)has_id &&
+                      r.mesh_hash == 42,
+                  "checkpoint header fields", prec, has_id);
+            check(ck::read(path, r, store, 777).empty(), "checkpoint arrays read", prec, has_id);
+            for (int k = 0; k < ck::kArrays; ++k) check(src[k] == dst[k], "checkpoint array round trip", k, prec);
+            // a failing transfer: the write fails and the previous file stays
+            auto broken = [&](int k, size_t, void *, size_t) -> std::string { return k == 5 ? "device gone" : ""; };
+            check(!ck::write(path, h, broken, 1000).empty(), "failed write reported", prec);
+            check(ck::read_header(path, r).empty(), "previous checkpoint intact", prec);
+            FILE *t = std::fopen((path + ".tmp").c_str(), "rb");
+            check(t == nullptr, "temporary file removed", prec);
+            if (t) std::fclose(t);
+        }
+    // corruption of one array byte and truncation
+    {
+        ck::Header r{};
+        check(ck::read_header(path, r).empty(), "header before corruption");
+        FILE *f = std::fopen(path.c_str(), "r+b");
+        check(f != nullptr, "open for corruption");
+        if (f) {
+            std::fseek(f, (long)sizeof(ck::Header) + 10, SEEK_SET);
+            int c = std::fgetc(f);
+            std::fseek(f, (long)sizeof(ck::Header) + 10, SEEK_SET);
+            std::fputc(c ^ 0x40, f);
+            std::fclose(f);
+        }
+        std::vector<unsigned char> sink(8 * 1003);
+        auto store = [&](int, size_t off, void *buf, size_t len) -> std::string {
+            if (off + len > sink.size()) return "store out of range";
+            std::memcpy(sink.data() + off, buf, len);
+            return "";
+        };
+        const std::string e = ck::read(path, r, store, 4096);
+        check(e.find("checksum") != std::string::npos, "corrupted array detected");
+        f = std::fopen(path.c_str(), "r+b");
+        if (f) {
+            std::fseek(f, 0, SEEK_END);
+            const long len = std::ftell(f);
+            std::fclose(f);
+            check(truncate(path.c_str(), len - 3) == 0, "truncate");
+        }
+        check(!ck::read_header(path, r).empty(), "truncated file refused");
+    }
+    std::remove(path.c_str());
+}
+
 }  // namespace
 
-int main() {
+int main(int argc, char **argv) {
     const int sizes[][3] = {{1, 1, 1}, {2, 3, 2}, {5, 4, 6}, {8, 8, 8}};
     for (auto &n : sizes) exercise(n);
     rejections();
+    checkpoints(argc > 1 ? argv[1] : ".");
     if (failures) {
         std::fprintf(stderr, "%d check(s) failed\n", failures);
         return 1;

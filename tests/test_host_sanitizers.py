@@ -1,5 +1,6 @@
 """The library's host-side C++ (mesh canonicalisation, start grid,
-tree-cotree split, field and Gauss-law assembly) and the C oracle built with
+tree-cotree split, field and Gauss-law assembly, the particle checkpoint
+file) and the C oracle built with
 AddressSanitizer and UndefinedBehaviorSanitizer on the CPU (gcc/g++ only, no
 GPU code) and driven through their paths by the programs in tests/sanitize/:
 no sanitizer report, and every driver check holds."""
@@ -30,9 +31,10 @@ def outdir(tmp_path_factory):
 def test_host_cpp_under_asan_ubsan(outdir):
     exe = str(outdir / "host_driver")
     b = _run(["g++", "-std=c++17", *SAN, "-I", CSRC, os.path.join(ROOT, "tests", "sanitize", "host_driver.cpp"),
-              os.path.join(CSRC, "mesh_host.cpp"), os.path.join(CSRC, "field_host.cpp"), "-o", exe])
+              os.path.join(CSRC, "mesh_host.cpp"), os.path.join(CSRC, "field_host.cpp"),
+              os.path.join(CSRC, "checkpoint_host.cpp"), "-o", exe])
     assert b.returncode == 0, b.stderr[-4000:]
-    r = _run([exe], env=ENV)
+    r = _run([exe, str(outdir)], env=ENV)
     assert r.returncode == 0 and "runtime error" not in r.stderr and "ERROR: AddressSanitizer" not in r.stderr, \
         (r.stdout[-2000:], r.stderr[-4000:])
     assert "all checks passed" in r.stdout

@@ -18,8 +18,8 @@ decomposition of the flux density (eq. efld_projected) is
 D = Sigma E_ns + P^Lambda_e D with E_ns = (Sigma^T Sigma)^+ Sigma^T D.
 
 The end of the module builds the Z blocks of the solenoidal system (eq.
-sol_disc) densely on small meshes, for a study of its spectrum (no GPU
-counterpart).
+sol_disc) densely on small meshes: a study of its spectrum, and the
+reference for the library's matrix-free blocks and its step of the system.
 """
 from __future__ import annotations
 
@@ -219,3 +219,60 @@ def solenoidal_spectrum(mesh, eps, mu, weighted):
     Z11 B' = -Z12 E and Z21 E' = Z22 B."""
     Z11, Z12, Z21, Z22, _ = solenoidal_blocks(mesh, eps, mu, weighted)
     return np.linalg.eigvals(np.linalg.solve(Z21, Z22) @ np.linalg.solve(Z11, Z12))
+
+
+def inner_nodes(mesh):
+    """Indices of the nodes off the conducting wall, ascending ([C^e_z] of
+    eq. ns_equation selects them)."""
+    return np.flatnonzero(~gauss.wall_nodes(mesh))
+
+
+def solenoidal_source_blocks(mesh, eps):
+    """Dense (Z13, Z23, Cz) of eq. sol_disc as printed in App. A:
+    Z13 = C_b^T [curl] [*eps]^-1 Sigma C_z and Z23 = C_e^T Sigma C_z, with
+    Sigma = [*eps] D and [*eps]^-1 as a dense inverse."""
+    Q = QhOracle(mesh, eps)
+    M = Q.M.toarray()
+    Sig = M @ Q.D.toarray()
+    C = curl_incidence(mesh)
+    et, ft = spanning_trees(mesh)
+    Ce = np.eye(mesh.ne)[:, ~et]
+    Cb = np.eye(mesh.nf)[:, ~ft]
+    Cz = np.eye(mesh.nv)[:, inner_nodes(mesh)]
+    return Cb.T @ C @ np.linalg.solve(M, Sig @ Cz), Ce.T @ Sig @ Cz, Cz
+
+
+def solenoidal_step(mesh, eps, mu, dt, omega, Bs, Es, src_b=None, src_e=None):
+    """One step of eq. sol_disc as printed (Euclidean projectors), the time
+    derivatives by the trapezoidal rule over [t_n, t_n + dt]:
+        Z11 (B1 - B0)/dt + j w Z11 (B1 + B0)/2 + Z12 (E1 + E0)/2 = src_b,
+        Z21 (E1 - E0)/dt + j w Z21 (E1 + E0)/2 - Z22 (B1 + B0)/2 = src_e,
+    solved densely for (B1, E1) on the cotree unknowns; src_b, src_e are the
+    right-hand sides at the midpoint (zero if None)."""
+    Z11, Z12, Z21, Z22, _ = solenoidal_blocks(mesh, eps, mu, weighted=False)
+    nb, ne_ = Z11.shape[0], Z21.shape[0]
+    a, ab = 1.0 / dt + 0.5j * omega, 1.0 / dt - 0.5j * omega
+    A = np.block([[a * Z11, 0.5 * Z12], [-0.5 * Z22, a * Z21]])
+    rb = ab * (Z11 @ Bs) - 0.5 * (Z12 @ Es) + (0 if src_b is None else src_b)
+    re = ab * (Z21 @ Es) + 0.5 * (Z22 @ Bs) + (0 if src_e is None else src_e)
+    # B and E carry units a factor ~c apart and the rows scale with 1/dt and
+    # eps: equilibrate rows and columns (Ruiz) before the dense solve, or its
+    # error grows with the raw condition number (~1e15)
+    r, c = np.ones(nb + ne_), np.ones(nb + ne_)
+    As = A.copy()
+    for _ in range(5):
+        rr, cc = 1.0 / np.sqrt(np.abs(As).max(axis=1)), 1.0 / np.sqrt(np.abs(As).max(axis=0))
+        As = rr[:, None] * As * cc[None, :]
+        r, c = r * rr, c * cc
+    x = c * np.linalg.solve(As, r * np.concatenate([rb, re]))
+    return x[:nb], x[nb:]
+
+
+def solenoidal_b_field(mesh, eps, Bs):
+    """The face field P^Lambda_b C_b B_s of the cotree unknowns B_s (the
+    divergence-free magnetic flux the printed blocks act on)."""
+    Q = QhOracle(mesh, eps)
+    _, ft = spanning_trees(mesh)
+    b = np.zeros(mesh.nf, dtype=np.result_type(Bs, np.float64))
+    b[~ft] = Bs
+    return Q.project_b(b)

@@ -157,3 +157,68 @@ def test_solenoidal_system_is_the_curl_curl_pencil_off_gradients(ora):
     nz = np.sort(w[w > 1e-6 * w.max()])
     assert len(nz) == len(ev) == m.ne - m.nv + 1
     assert np.abs(nz / ev - 1).max() < 1e-10
+
+
+MU0 = 1.25663706212e-6
+
+
+def test_z13_is_the_curl_of_a_gradient(mesh):
+    """Z13 = C_b^T [curl] [*eps]^-1 Sigma C_z: [*eps]^-1 Sigma is the
+    node-to-edge incidence and the curl of a gradient vanishes, so the block
+    is zero to rounding (Faraday's law gets no source from E_ns); Z23 =
+    C_e^T [*eps] D C_z is not."""
+    from oracle import qh
+    Z13, Z23, Cz = qh.solenoidal_source_blocks(mesh, EPS0)
+    assert Cz.shape == (mesh.nv, len(qh.inner_nodes(mesh)))
+    assert np.abs(Z13).max() < 1e-12
+    assert np.abs(Z23).max() > 1e-13
+
+
+def test_printed_step_faraday_closed_form(mesh):
+    """The dense trapezoidal step of eq. sol_disc as printed: the face field
+    b = P^Lambda_b C_b B_s it produces satisfies Faraday's law on every face,
+    b1 = ((1/dt - j w/2) b0 - C C_e (E0 + E1)/2) / (1/dt + j w/2): b and
+    C C_e E are divergence-free and a divergence-free face field vanishing on
+    the cotree faces vanishes.  Ampere's rows hold in the full-space form
+    C_e^T (P^Lambda_e [*eps] e - C^T [*mu^-1] (b0 + b1)/2) = src_e with
+    e = C_e (a E1 - conj(a) E0) and the projector from the sparse solves
+    (not the dense pseudoinverse of the blocks)."""
+    from oracle import qh
+    rng = np.random.default_rng(4)
+    et, ft = qh.spanning_trees(mesh)
+    nec, nfc = int((~et).sum()), int((~ft).sum())
+    Bs = (rng.standard_normal(nfc) + 1j * rng.standard_normal(nfc)) * 1e-6
+    Es = (rng.standard_normal(nec) + 1j * rng.standard_normal(nec)) * 1e2
+    src = (rng.standard_normal(nec) + 1j * rng.standard_normal(nec)) * 1e-1
+    dt, w = 2e-11, 2 * np.pi * 1e9
+    B1, E1 = qh.solenoidal_step(mesh, EPS0, MU0, dt, w, Bs, Es, src_e=src)
+    b0, b1 = qh.solenoidal_b_field(mesh, EPS0, Bs), qh.solenoidal_b_field(mesh, EPS0, B1)
+    a, ab = 1 / dt + 0.5j * w, 1 / dt - 0.5j * w
+    C = qh.curl_incidence(mesh)
+    e0, e1 = np.zeros(mesh.ne, complex), np.zeros(mesh.ne, complex)
+    e0[~et], e1[~et] = Es, E1
+    assert rel(b1, (ab * b0 - 0.5 * C @ (e0 + e1)) / a) < 1e-10
+    Q = qh.QhOracle(mesh, EPS0)
+    F = qh.face_mass(mesh, MU0)
+    _, pl, _ = Q.project_e(Q.M @ (a * e1 - ab * e0))
+    lhs = (pl - 0.5 * C.T @ F @ (b0 + b1))[~et]
+    assert np.abs(lhs - src).max() < 1e-10 * np.abs(pl[~et]).max()
+
+
+def test_printed_ampere_block_is_indefinite(ora):
+    """Z21 = C_e^T P^Lambda_e [*eps] C_e (Euclidean projector) is not a mass
+    matrix: from 6^3 cells of the unit cube on it has eigenvalues with a
+    negative real part, while the energy-orthogonal form's Z21 is symmetric
+    positive definite.  (On 3^3 and 4^3 cells all its eigenvalues still lie
+    in the right half plane.)"""
+    from oracle import qh
+    for n, negative in ((4, False), (6, True)):
+        xyz, tv = synth.kuhn_mesh((n, n, n), (1.0, 1.0, 1.0), 0.0)
+        m = ora.OracleMesh(xyz, tv)
+        _, _, Z21, _, _ = qh.solenoidal_blocks(m, EPS0, MU0, weighted=False)
+        ev = np.linalg.eigvals(Z21 / np.abs(np.diag(Z21)).mean())
+        assert (ev.real.min() < 0) == negative, (n, ev.real.min())
+        if negative:
+            _, _, W21, _, _ = qh.solenoidal_blocks(m, EPS0, MU0, weighted=True)
+            assert np.abs(W21 - W21.T).max() < 1e-12 * np.abs(W21).max()
+            assert np.linalg.eigvalsh(W21).min() > 0

@@ -756,6 +756,61 @@ int etpic_qh_project_e(etpic_qh *qh, const double *d, double *d_sigma, double *d
 int etpic_tree_cotree(int64_t n_vert, const double *xyz_host, int64_t n_tet, const int32_t *tet_vert_host,
                       uint8_t *edge_tree_host, uint8_t *face_tree_host, int64_t counts_out[4]);
 
+/* The solenoidal system of eq. sol_disc (Quasi Helmholtz section, Discrete
+ * System) on the cotree unknowns, with the blocks as App. A prints them
+ * (Euclidean projectors P^Lambda_b, P^Lambda_e of the object `qh` of the same
+ * mesh; [curl] = C the signed face-edge incidence; [*mu^-1] the Whitney face
+ * mass; C_e, C_b the cotree edges and faces of etpic_tree_cotree, ascending;
+ * C_z the nodes off the conducting wall, ascending).  Created on the host
+ * from the mesh (as given to etpic_qh_create) and mu; the device part lives
+ * in the caller's buffer (etpic_cotree_bytes, etpic_cotree_bind: 256-byte
+ * aligned).  Vectors are complex (re, im) float64 pairs on the device; the
+ * calls synchronise.  Errors: EINVAL, ESTATE (not bound), EMESH, EHIP,
+ * ENOCONV (an inner projector solve or the step's GMRES did not reach its
+ * tolerance); message from etpic_qh_last_error(). */
+typedef struct etpic_cotree etpic_cotree;
+int etpic_cotree_create(etpic_cotree **out, const etpic_qh *qh, int64_t nv, const double *xyz, int64_t nt,
+                        const int32_t *tet_vert, double mu);
+int etpic_cotree_bytes(const etpic_cotree *z, size_t *bytes);
+int etpic_cotree_bind(etpic_cotree *z, void *dev_buf, size_t bytes);
+void etpic_cotree_destroy(etpic_cotree *z);
+
+/* counts_out = {cotree edges N_ec, cotree faces N_fc, nodes off the wall N_z,
+ * stored face-mass entries} */
+int etpic_cotree_counts(const etpic_cotree *z, int64_t counts_out[4]);
+
+/* y = Z_block x for block 11 (x: N_fc -> y: N_fc), 12 (N_ec -> N_fc), 13
+ * (N_z -> N_fc), 21 (N_ec -> N_ec), 22 (N_fc -> N_ec), 23 (N_z -> N_ec), each
+ * applied matrix-free; tol and max_iter bound the projector solve it needs
+ * (blocks 11, 12, 21, 22).  Z13 is the curl of a gradient and comes out at
+ * rounding level. */
+int etpic_cotree_apply(etpic_cotree *z, etpic_qh *qh, int block, const double *x, double *y, double tol,
+                       int max_iter, void *stream);
+
+/* b_out = P^Lambda_b C_b bs: the divergence-free face field (N_f) the
+ * blocks attach to the cotree unknowns bs (N_fc). */
+int etpic_cotree_b_field(etpic_cotree *z, etpic_qh *qh, const double *bs, double *b_out, double tol, int max_iter,
+                         void *stream);
+
+/* One step of eq. sol_disc, time derivatives by the trapezoidal rule over
+ * [t_n, t_n + dt] with carrier frequency omega (a = 1/dt + j omega/2):
+ *   Z11 (a B1 - conj(a) B0) + Z12 (E1 + E0)/2 = 0,
+ *   Z21 (a E1 - conj(a) E0) - Z22 (B1 + B0)/2 = src
+ * (Z13 E_ns = 0 identically; src, N_ec or NULL, is the Ampere right-hand side
+ * at the midpoint: the current and E_ns terms on the cotree edges).  The
+ * state is b (N_f, the face field P^Lambda_b C_b B_s, in/out) and es (N_ec,
+ * in/out).  Faraday's rows hold on every face, so b advances explicitly; the
+ * Ampere rows are one system on the cotree edges, solved by restarted GMRES
+ * (relative residual tol, at most max_iter iterations, each with one
+ * P^Lambda_e solve to inner_tol / inner_max) from the guess es; iters_out and
+ * resid_out (may be NULL) report it.  The printed Z21 is not symmetric and,
+ * from a few cells per side on, indefinite: GMRES then needs many iterations
+ * or does not converge (ENOCONV: es holds the last iterate, b is left as it
+ * was). */
+int etpic_cotree_step(etpic_cotree *z, etpic_qh *qh, double dt, double omega, double *b, double *es,
+                      const double *src, double tol, int max_iter, double inner_tol, int inner_max, int *iters_out,
+                      double *resid_out, void *stream);
+
 /* Kernel times of the steps launched with ETPIC_STEP_TIMING since the last
  * reset, from HIP start and stop events bound to each kernel's own dispatch
  * on the launch stream (hipExtLaunchKernel: no marker packets between the

@@ -43,7 +43,8 @@ EXPORTS = (
     "etpic_sol_source",
     "etpic_qh_last_error", "etpic_qh_create", "etpic_qh_bytes", "etpic_qh_bind", "etpic_qh_destroy", "etpic_qh_counts", "etpic_qh_project_b",
     "etpic_qh_project_e", "etpic_tree_cotree", "etpic_checkpoint_write", "etpic_checkpoint_info",
-    "etpic_checkpoint_read",
+    "etpic_checkpoint_read", "etpic_cotree_create", "etpic_cotree_bytes", "etpic_cotree_bind", "etpic_cotree_destroy",
+    "etpic_cotree_counts", "etpic_cotree_apply", "etpic_cotree_b_field", "etpic_cotree_step",
 )
 
 
@@ -165,8 +166,18 @@ def lib():
     L.etpic_qh_project_e.argtypes = [vp, vp, vp, vp, vp, C.c_double, C.c_int, C.POINTER(C.c_int), dp, vp]
     L.etpic_tree_cotree.argtypes = [C.c_int64, dp, C.c_int64, i32p, C.POINTER(C.c_uint8), C.POINTER(C.c_uint8),
                                     i64p]
+    L.etpic_cotree_create.argtypes = [C.POINTER(vp), vp, C.c_int64, dp, C.c_int64, i32p, C.c_double]
+    L.etpic_cotree_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
+    L.etpic_cotree_bind.argtypes = [vp, vp, C.c_size_t]
+    L.etpic_cotree_destroy.argtypes = [vp]
+    L.etpic_cotree_destroy.restype = None
+    L.etpic_cotree_counts.argtypes = [vp, i64p]
+    L.etpic_cotree_apply.argtypes = [vp, vp, C.c_int, vp, vp, C.c_double, C.c_int, vp]
+    L.etpic_cotree_b_field.argtypes = [vp, vp, vp, vp, C.c_double, C.c_int, vp]
+    L.etpic_cotree_step.argtypes = [vp, vp, C.c_double, C.c_double, vp, vp, vp, C.c_double, C.c_int, C.c_double,
+                                    C.c_int, C.POINTER(C.c_int), dp, vp]
     for name in EXPORTS:
-        if name in ("etpic_qh_last_error", "etpic_qh_destroy"):
+        if name in ("etpic_qh_last_error", "etpic_qh_destroy", "etpic_cotree_destroy"):
             continue
         if name != "etpic_last_error":
             getattr(L, name).restype = C.c_int
@@ -760,6 +771,61 @@ def _qchk(rc):
     if rc != OK:
         raise EtpicError(rc, lib().etpic_qh_last_error().decode())
     return rc
+
+
+class CotreeSystem:
+    """The solenoidal system of eq. sol_disc on the cotree unknowns (blocks as
+    App. A prints them), on the mesh of the QhProjectors `qh`, in a device
+    buffer held here.  Vectors are float64 [N, 2] (complex) device tensors:
+    N_ec cotree edges, N_fc cotree faces, N_z nodes off the wall, N_f faces."""
+
+    def __init__(self, qh, xyz, tet_vert, mu):
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        tv = np.ascontiguousarray(tet_vert, dtype=np.int32)
+        self.qh = qh
+        self._h = C.c_void_p()
+        _qchk(lib().etpic_cotree_create(C.byref(self._h), qh._h, xyz.shape[0], _np_ptr(xyz, C.c_double), tv.shape[0],
+                                        _np_ptr(tv, C.c_int32), float(mu)))
+        b = C.c_size_t(0)
+        _qchk(lib().etpic_cotree_bytes(self._h, C.byref(b)))
+        self._buf = _device_buffer(b.value, qh._buf.device.index or 0)
+        _qchk(lib().etpic_cotree_bind(self._h, C.c_void_p(self._buf.data_ptr()), self._buf.numel()))
+        cnt = (C.c_int64 * 4)()
+        _qchk(lib().etpic_cotree_counts(self._h, cnt))
+        self.n_cotree_edge, self.n_cotree_face, self.n_inner_node, self.face_nnz = (int(v) for v in cnt)
+
+    def close(self):
+        if self._h:
+            lib().etpic_cotree_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def apply(self, block, x, y, tol=1e-13, max_iter=20000, stream=None):
+        """y = Z_block x, block in 11, 12, 13, 21, 22, 23."""
+        _qchk(lib().etpic_cotree_apply(self._h, self.qh._h, int(block), _dptr(x), _dptr(y), float(tol),
+                                       int(max_iter), _stream(stream)))
+
+    def b_field(self, bs, b_out, tol=1e-13, max_iter=20000, stream=None):
+        """b_out = P^Lambda_b C_b bs."""
+        _qchk(lib().etpic_cotree_b_field(self._h, self.qh._h, _dptr(bs), _dptr(b_out), float(tol), int(max_iter),
+                                         _stream(stream)))
+
+    def step(self, dt, omega, b, es, src=None, tol=1e-11, max_iter=5000, inner_tol=1e-13, inner_max=20000,
+             stream=None, raise_on_error=True):
+        """One trapezoidal step of eq. sol_disc on (b, es) in place;
+        returns (status, GMRES iterations, relative residual)."""
+        it, res = C.c_int(0), C.c_double(0.0)
+        rc = lib().etpic_cotree_step(self._h, self.qh._h, float(dt), float(omega), _dptr(b), _dptr(es), _dptr(src),
+                                     float(tol), int(max_iter), float(inner_tol), int(inner_max), C.byref(it),
+                                     C.byref(res), _stream(stream))
+        if raise_on_error:
+            _qchk(rc)
+        return rc, it.value, res.value
 
 
 class QhProjectors:

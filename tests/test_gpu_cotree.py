@@ -1,0 +1,146 @@
+"""GPU solenoidal system of eq. sol_disc on the cotree unknowns (blocks as
+App. A prints them) against the oracle's dense blocks and its dense
+trapezoidal step: each of Z11, Z12, Z13, Z21, Z22, Z23 applied matrix-free
+with the tree-cotree maps on the device, the face field of the cotree
+unknowns, and steps of the system (Faraday explicit on every face, Ampere's
+cotree rows by GMRES) on small meshes."""
+import numpy as np
+import pytest
+
+from paper_2208_12795_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+EPS0 = 8.8541878128e-12
+MU0 = 1.25663706212e-6
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def E():
+    from paper_2208_12795_amd import etpic
+    return etpic
+
+
+MESHES = {"cube3": ((3, 3, 3), (1.0, 1.0, 1.0), 0.0, 0), "jit435": ((4, 3, 5), (1.0, 0.8, 1.2), 0.15, 12)}
+
+
+@pytest.fixture(scope="module", params=sorted(MESHES))
+def setup(request, E, torch_cuda, ora):
+    from oracle import qh as oqh
+    n, box, jit, seed = MESHES[request.param]
+    xyz, tv = synth.kuhn_mesh(n, box, jit, np.random.default_rng(seed))
+    Q = E.QhProjectors(xyz, tv, EPS0)
+    Z = E.CotreeSystem(Q, xyz, tv, MU0)
+    m = ora.OracleMesh(xyz, tv)
+    blocks = oqh.solenoidal_blocks(m, EPS0, MU0, weighted=False)
+    src_blocks = oqh.solenoidal_source_blocks(m, EPS0)
+    print(f"[cotree {request.param}] N_ec={Z.n_cotree_edge} N_fc={Z.n_cotree_face} N_z={Z.n_inner_node}", flush=True)
+    yield request.param, m, Q, Z, blocks, src_blocks
+    Z.close()
+    Q.close()
+
+
+def c2t(torch, z):
+    return torch.from_numpy(np.ascontiguousarray(np.stack([z.real, z.imag], axis=1))).cuda()
+
+
+def t2c(t):
+    a = t.cpu().numpy()
+    return a[:, 0] + 1j * a[:, 1]
+
+
+def rand(rng, n, scale=1.0):
+    return (rng.standard_normal(n) + 1j * rng.standard_normal(n)) * scale
+
+
+def test_counts_are_the_cotree_dimensions(setup):
+    name, m, Q, Z, blocks, src_blocks = setup
+    from oracle import qh as oqh
+    assert Z.n_cotree_edge == m.ne - m.nv + 1
+    assert Z.n_cotree_face == m.nf - m.nt
+    assert Z.n_inner_node == len(oqh.inner_nodes(m))
+
+
+@pytest.mark.parametrize("block", [11, 12, 13, 21, 22, 23])
+def test_block_matches_dense_oracle(E, torch_cuda, setup, block):
+    torch = torch_cuda
+    name, m, Q, Z, (Z11, Z12, Z21, Z22, _), (Z13, Z23, Cz) = setup
+    dense = {11: Z11, 12: Z12, 13: Z13, 21: Z21, 22: Z22, 23: Z23}[block]
+    rng = np.random.default_rng(block)
+    x = rand(rng, dense.shape[1])
+    y = torch.zeros((dense.shape[0], 2), dtype=torch.float64, device="cuda")
+    Z.apply(block, c2t(torch, x), y, tol=1e-14)
+    got, ref = t2c(y), dense @ x
+    if block == 13:
+        # the curl of a gradient: rounding on both sides
+        scale = np.abs(x).max() * 4
+        print(f"[cotree {name}] Z13 max |gpu| {np.abs(got).max():.1e} |oracle| {np.abs(ref).max():.1e}", flush=True)
+        assert np.abs(got).max() < 1e-12 * scale and np.abs(ref).max() < 1e-12 * scale
+        return
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print(f"[cotree {name}] Z{block} rel {err:.1e}", flush=True)
+    assert err < 1e-10
+
+
+def test_face_field_of_cotree_unknowns(E, torch_cuda, setup):
+    torch = torch_cuda
+    name, m, Q, Z, blocks, _ = setup
+    from oracle import qh as oqh
+    rng = np.random.default_rng(3)
+    bs = rand(rng, Z.n_cotree_face)
+    b = torch.zeros((m.nf, 2), dtype=torch.float64, device="cuda")
+    Z.b_field(c2t(torch, bs), b, tol=1e-14)
+    ref = oqh.solenoidal_b_field(m, EPS0, bs)
+    assert np.abs(t2c(b) - ref).max() < 1e-11 * np.abs(ref).max()
+    div = oqh.div_matrix(m)
+    assert np.abs(div @ t2c(b)).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_steps_match_dense_oracle(E, torch_cuda, setup):
+    """Three steps of eq. sol_disc from random cotree unknowns with a random
+    Ampere source, on the GPU (the state (b, E_s) carried in place) and by
+    the oracle's dense block solve: E_s and b to 1e-8 relative; b stays
+    divergence-free."""
+    torch = torch_cuda
+    name, m, Q, Z, blocks, _ = setup
+    from oracle import qh as oqh
+    rng = np.random.default_rng(8)
+    Bs = rand(rng, Z.n_cotree_face, 1e-6)
+    Es = rand(rng, Z.n_cotree_edge, 1e2)
+    dt, w = 2e-11, 2 * np.pi * 1e9
+    b = torch.zeros((m.nf, 2), dtype=torch.float64, device="cuda")
+    Z.b_field(c2t(torch, Bs), b, tol=1e-14)
+    es = c2t(torch, Es)
+    div = oqh.div_matrix(m)
+    for k in range(3):
+        src = rand(rng, Z.n_cotree_edge, 1e-1)
+        rc, it, res = Z.step(dt, w, b, es, src=c2t(torch, src), tol=1e-12, max_iter=20000, inner_tol=1e-14)
+        Bs, Es = oqh.solenoidal_step(m, EPS0, MU0, dt, w, Bs, Es, src_e=src)
+        bref = oqh.solenoidal_b_field(m, EPS0, Bs)
+        e_err = np.abs(t2c(es) - Es).max() / np.abs(Es).max()
+        b_err = np.abs(t2c(b) - bref).max() / np.abs(bref).max()
+        print(f"[cotree {name}] step {k}: GMRES {it} iterations, residual {res:.1e}; E_s rel {e_err:.1e}, "
+              f"b rel {b_err:.1e}", flush=True)
+        assert e_err < 1e-8 and b_err < 1e-8
+        assert np.abs(div @ t2c(b)).max() < 1e-10 * np.abs(bref).max()
+
+
+def test_bad_arguments(E, torch_cuda, setup):
+    torch = torch_cuda
+    name, m, Q, Z, blocks, _ = setup
+    x = torch.zeros((Z.n_cotree_edge, 2), dtype=torch.float64, device="cuda")
+    with pytest.raises(E.EtpicError) as ei:
+        Z.apply(31, x, x)
+    assert ei.value.code == E.EINVAL
+    b = torch.zeros((m.nf, 2), dtype=torch.float64, device="cuda")
+    with pytest.raises(E.EtpicError) as ei:
+        Z.step(-1.0, 0.0, b, x)
+    assert ei.value.code == E.EINVAL

@@ -55,7 +55,7 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_PARTICLE = {"fp64": 100, "mixed": 76, "mixed_fixed": 52}
 BYTES_PER_TET = {"fp64": 288, "mixed": 156, "mixed_fixed": 156}
 BYTES_PER_EDGE = 16
-KERNEL_NAME = {"fp64": "k_push<double>", "mixed": "k_push<float>", "mixed_fixed": "k_push<float>"}
+KERNEL_NAME = {"fp64": "k_push<double>", "mixed": "k_push<float>", "mixed_fixed": "k_push_fixed"}
 # Algorithmic bytes of a whole step (what the method must move per particle-step
 # and per tet, independent of how the kernels split the work): the particle
 # state read and written, tet included (2 x (lam 24 + v 24 + tet 4) = 104 B in
@@ -94,7 +94,11 @@ def log(*a):
 
 
 def kernel_name(form, slices):
-    return KERNEL_NAME[form] if slices <= 1 else f"k_push_slices<{REAL[form]}, {slices}>"
+    if slices <= 1:
+        return KERNEL_NAME[form]
+    if form == "mixed_fixed":
+        return f"k_push_slices_fixed<{slices}, false>"
+    return f"k_push_slices<{REAL[form]}, {slices}, false>"
 
 
 def logged_steps(E, torch, ctx, parts, sp, fields, w, step0, nlog):
@@ -757,8 +761,7 @@ def main():
             m = res[form]
             line[form] = {"value": m["value"], "ms_per_step": m["ms_per_step"], "dtype": FORM_DTYPE[form],
                           "speedup_vs_fp64": m["value"] / r["value"],
-                          "roofline": roofline(res, form, n_p, n_t, n_e, args.sort_every, copy_gbs,
-                                               traffic_path if form == "mixed" else None),
+                          "roofline": roofline(res, form, n_p, n_t, n_e, args.sort_every, copy_gbs, traffic_path),
                           "gauss_rel": m["gauss_rel"], "logged": m["logged"]}
     if not args.no_side and args.workload == "40cube":
         line["field_update"] = field_update_timing(E, torch, ctx, w)

@@ -353,7 +353,11 @@ int etpic_sort_run_steps(etpic_ctx *ctx, const etpic_particles *src, const etpic
                          double omega, double *dG, double *rho, uint32_t flags, void *stream);
 
 /* rho[N_n] += q w * lam_k for the four vertices of every particle's tet
- * (the W0 shape; Formulation, the particle charge density). Asynchronous. */
+ * (the W0 shape; Formulation, the particle charge density).  Same-tet runs of
+ * consecutive particles are summed in the wavefront before the float64
+ * atomics; where the last sort found long runs (as the particle kernel picks
+ * its slices) each wavefront covers 4 or 16 slices of 64 particles and carries
+ * a run across them.  precision says how lam is stored.  Asynchronous. */
 int etpic_vertex_charge(etpic_ctx *ctx, const etpic_particles *p, int precision, const etpic_species *sp, double *rho,
                         void *stream);
 

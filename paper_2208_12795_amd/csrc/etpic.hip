@@ -686,8 +686,9 @@ constexpr __host__ __device__ bool push_uses_slots(int slices) {
     return std::is_same<Real, float>::value || slices == 1;
 }
 
-template <typename Real, int kSlices, bool kRho, bool kScatter = false>
+template <typename Real, int kSlices, bool kRho, bool kScatter = false, bool kFixed = false>
 __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) {
+    static_assert(!kFixed || std::is_same<Real, float>::value, "fixed-point barycentrics are a mixed-form storage");
     unsigned blk = blockIdx.x;
     if (remap) {
         // the dispatcher deals blocks round-robin over the 8 XCDs; give each XCD
@@ -729,7 +730,7 @@ __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) 
         constexpr bool kEarly = kSlices == 1;
         constexpr bool kSlots = push_uses_slots<Real>(kSlices);
         // the compact mixed form: barycentrics stored as uint32 fixed point
-        const bool fx = std::is_same<Real, float>::value && a.fixed;
+        constexpr bool fx = kFixed;
         uint32_t *__restrict__ f1 = reinterpret_cast<uint32_t *>(a.lam1) + b0;
         uint32_t *__restrict__ f2 = reinterpret_cast<uint32_t *>(a.lam2) + b0;
         uint32_t *__restrict__ f3 = reinterpret_cast<uint32_t *>(a.lam3) + b0;
@@ -1033,6 +1034,34 @@ template <typename Real, int kSlices, bool kRho>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7)))
 k_push_sort_slices(StepArgs<Real> a, int remap) {
     push_slices<Real, kSlices, kRho, true>(a, remap);
+}
+
+// The compact mixed form (barycentrics stored as uint32 fixed point): the same
+// kernels with that storage compiled in.
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7)))
+k_push_fixed(StepArgs<float> a, int remap) {
+    push_slices<float, 1, false, false, true>(a, remap);
+}
+
+__global__ void __launch_bounds__(kBlock) k_push_rho_fixed(StepArgs<float> a, int remap) {
+    push_slices<float, 1, true, false, true>(a, remap);
+}
+
+template <int kSlices, bool kRho>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7)))
+k_push_slices_fixed(StepArgs<float> a, int remap) {
+    push_slices<float, kSlices, kRho, false, true>(a, remap);
+}
+
+template <bool kRho>
+__global__ void __launch_bounds__(kBlock) k_push_sort_fixed(StepArgs<float> a, int remap) {
+    push_slices<float, 1, kRho, true, true>(a, remap);
+}
+
+template <int kSlices, bool kRho>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7)))
+k_push_sort_slices_fixed(StepArgs<float> a, int remap) {
+    push_slices<float, kSlices, kRho, true, true>(a, remap);
 }
 
 // Walk of one marked particle p: every piece of its path is deposited with
@@ -1845,6 +1874,68 @@ __global__ void __launch_bounds__(kBlock) k_charge(int64_t n, int64_t nt, const 
 #pragma unroll
         for (int k = 0; k < 4; ++k) unsafeAtomicAdd(&rho[tp.v[k]], qw * l[k]);
     }
+}
+
+// The same over kSlices consecutive slices of 64 particles per wavefront: the
+// run of one tet that reaches lane 63 of a slice is carried (as a
+// wavefront-uniform partial sum) into the next slice instead of being flushed,
+// so a tet holding thousands of sorted particles costs kSlices times fewer
+// same-address atomics.
+template <int kSlices>
+__global__ void __launch_bounds__(kBlock) k_charge_slices(int64_t n, int64_t nt, const double *__restrict__ lam1,
+                                                          const double *__restrict__ lam2,
+                                                          const double *__restrict__ lam3,
+                                                          const int32_t *__restrict__ tet,
+                                                          const TetTopo *__restrict__ topo, double qw,
+                                                          double *__restrict__ rho, unsigned *status, int fixed) {
+    const int lane = threadIdx.x & 63;
+    const int64_t base = (((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6) * 64 * kSlices;
+    auto flush = [&](int T, const double v[4]) {
+        const TetTopo tp = topo[T];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) unsafeAtomicAdd(&rho[tp.v[k]], qw * v[k]);
+    };
+    int carry_t = -1;   // tet of the carried run (uniform over the wavefront), -1: none
+    double carry[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int s = 0; s < kSlices; ++s) {
+        const int64_t p = base + (int64_t)s * 64 + lane;
+        int T = -1;
+        double l[4] = {0.0, 0.0, 0.0, 0.0};
+        if (p < n) {
+            T = tet[p];
+            if ((unsigned)T >= (unsigned)nt) {
+                atomicOr(status, (unsigned)ETPIC_DEV_BADTET);
+                T = -1;
+            } else {
+                l[1] = lam_at(lam1, p, fixed);
+                l[2] = lam_at(lam2, p, fixed);
+                l[3] = lam_at(lam3, p, fixed);
+                l[0] = 1.0 - l[1] - l[2] - l[3];
+            }
+        }
+        const int t0 = __shfl(T, 0);
+        if (carry_t >= 0 && carry_t != t0) {   // the carried run ended with the previous slice
+            if (lane == 0) flush(carry_t, carry);
+            carry_t = -1;
+        }
+        const WaveRuns r = wave_runs(T);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) l[k] = run_total(l[k], r);
+        const int first_end = __shfl(r.run_end, 0);
+        if (carry_t >= 0 && lane == first_end)   // the slice's first run continues the carried one
+#pragma unroll
+            for (int k = 0; k < 4; ++k) l[k] += carry[k];
+        const int t63 = __shfl(T, 63);
+        double last[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) last[k] = __shfl(l[k], 63);
+        const bool keep = s + 1 < kSlices && t63 >= 0;   // the run through lane 63 may go on
+        if (lane == r.run_end && T >= 0 && !(keep && r.run_end == 63)) flush(T, l);
+        carry_t = keep ? t63 : -1;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) carry[k] = keep ? last[k] : 0.0;
+    }
+    if (carry_t >= 0 && lane == 0) flush(carry_t, carry);
 }
 
 // ------------------------------------------------------------------ continuity residual
@@ -2916,6 +3007,34 @@ struct etpic_ctx {
     bool launch_push(const StepArgs<Real> &a, int slices, int remap, hipStream_t st, TimingSet *ts = nullptr) {
         const int64_t n = a.n;
         hipEvent_t e0 = ev_start(ts, 1), e1 = ev_stop(ts, 1);
+        if constexpr (std::is_same<Real, float>::value) {
+            if (a.fixed) {
+                switch (slices) {
+                case 16:
+                    if (kSort)
+                        launch_timed(k_push_sort_slices_fixed<16, kRho>, grid_for((n + 15) / 16), st, e0, e1, a, remap);
+                    else
+                        launch_timed(k_push_slices_fixed<16, kRho>, grid_for((n + 15) / 16), st, e0, e1, a, remap);
+                    break;
+                case 4:
+                    if (kSort)
+                        launch_timed(k_push_sort_slices_fixed<4, kRho>, grid_for((n + 3) / 4), st, e0, e1, a, remap);
+                    else
+                        launch_timed(k_push_slices_fixed<4, kRho>, grid_for((n + 3) / 4), st, e0, e1, a, remap);
+                    break;
+                default:
+                    if (kSort)
+                        launch_timed(k_push_sort_fixed<kRho>, grid_for(n), st, e0, e1, a, remap);
+                    else if (kRho)
+                        launch_timed(k_push_rho_fixed, grid_for(n), st, e0, e1, a, remap);
+                    else
+                        launch_timed(k_push_fixed, grid_for(n), st, e0, e1, a, remap);
+                    slices = 1;
+                    break;
+                }
+                return push_uses_slots<Real>(slices);
+            }
+        }
         switch (slices) {
         case 16:
             if (kSort)
@@ -3080,6 +3199,12 @@ struct etpic_ctx {
         if (flags & ETPIC_STEP_SLICES_16) return last_slices = 16;
         if (flags & ETPIC_STEP_SLICES_4) return last_slices = 4;
         if (flags & ETPIC_STEP_SLICES_1) return last_slices = 1;
+        return last_slices = slices_from_runs(n);
+    }
+
+    // 1, 4 or 16 slices from the last sort's mean same-tet run length (read
+    // back without blocking: a statistic still in flight leaves the previous)
+    int slices_from_runs(int64_t n) {
         if (runstat_pending && hipEventQuery(runstat_ev) == hipSuccess) {
             run_len = runstat_n > 0 ? (double)*h_runstat / (double)runstat_n : 0.0;
             runstat_pending = false;
@@ -3087,7 +3212,6 @@ struct etpic_ctx {
         (void)hipGetLastError();   // an unfinished query is not an error
         int s = run_len >= 256.0 ? 16 : (run_len >= 96.0 ? 4 : 1);
         while (s > 1 && n / (64 * (int64_t)s) < kMinPushWaves) s /= 4;
-        last_slices = s;
         return s;
     }
 
@@ -4110,9 +4234,25 @@ int etpic_vertex_charge(etpic_ctx *ctx, const etpic_particles *p, int precision,
     if (int r = check_particles(ctx, p)) return r;
     if (p->n == 0) return ETPIC_OK;
     if (int r = set_device(ctx)) return r;
-    k_charge<<<grid_for(p->n), kBlock, 0, static_cast<hipStream_t>(stream)>>>(
-        p->n, ctx->host.nt, p->lam[0], p->lam[1], p->lam[2], p->tet, ctx->d_topo, sp->q * sp->w, rho,
-        ctx->d_status, precision == ETPIC_MIXED_FIXED ? 1 : 0);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int fixed = precision == ETPIC_MIXED_FIXED ? 1 : 0;
+    const int64_t n = p->n;
+    switch (ctx->slices_from_runs(n)) {
+    case 16:
+        k_charge_slices<16><<<grid_for((n + 15) / 16), kBlock, 0, st>>>(n, ctx->host.nt, p->lam[0], p->lam[1],
+                                                                        p->lam[2], p->tet, ctx->d_topo, sp->q * sp->w,
+                                                                        rho, ctx->d_status, fixed);
+        break;
+    case 4:
+        k_charge_slices<4><<<grid_for((n + 3) / 4), kBlock, 0, st>>>(n, ctx->host.nt, p->lam[0], p->lam[1], p->lam[2],
+                                                                     p->tet, ctx->d_topo, sp->q * sp->w, rho,
+                                                                     ctx->d_status, fixed);
+        break;
+    default:
+        k_charge<<<grid_for(n), kBlock, 0, st>>>(n, ctx->host.nt, p->lam[0], p->lam[1], p->lam[2], p->tet, ctx->d_topo,
+                                                 sp->q * sp->w, rho, ctx->d_status, fixed);
+        break;
+    }
     HIP_TRY(hipGetLastError());
     return ETPIC_OK;
 }

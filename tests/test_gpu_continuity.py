@@ -30,18 +30,22 @@ def E():
     return etpic
 
 
-@pytest.fixture(scope="module", params=[1, 2], ids=["small", "40cube_1e7"])
+@pytest.fixture(scope="module", params=[1, 2, 5], ids=["small", "40cube_1e7", "largebox_2e7"])
 def case(request, E, torch_cuda, ora):
     """(workload, context, particles, oracle mesh); the 40^3 case is the
-    benchmark workload (1e7 electrons), sorted by tet as the benchmark runs it."""
-    w = synth.make_workload(request.param)
+    benchmark workload (1e7 electrons), sorted by tet as the benchmark runs it;
+    the large-box case holds 2e7 electrons of the bunch workload on its 6.1M
+    tets, sorted: hundreds of particles share a tet in the bunch, so the charge
+    runs through the 16-slice kernel that carries runs across slices."""
+    w = synth.make_workload(request.param, n_particles=20_000_000 if request.param == 5 else None)
     print(f"[continuity] {w.name} N={len(w.tet)}", flush=True)
     ctx = E.Context(0)
     ctx.upload_mesh(w.xyz, w.tet_vert)
     parts = E.Particles.from_numpy(w.tet, w.lam, w.vel, w.ids)
-    if request.param == 2:
+    if request.param != 1:
         dst = parts.empty_like()
         ctx.sort(parts, dst)
+        torch_cuda.cuda.synchronize()
         parts = dst
     M = ora.OracleMesh(w.xyz, w.tet_vert)
     yield w, ctx, parts, M

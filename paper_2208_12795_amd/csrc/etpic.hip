@@ -3199,18 +3199,23 @@ struct etpic_ctx {
         if (flags & ETPIC_STEP_SLICES_16) return last_slices = 16;
         if (flags & ETPIC_STEP_SLICES_4) return last_slices = 4;
         if (flags & ETPIC_STEP_SLICES_1) return last_slices = 1;
-        return last_slices = slices_from_runs(n);
+        // The particle kernel adds a run's currents to its tet's slots, so
+        // long runs cost it few same-address atomics: one slice measured
+        // fastest up to hundreds of particles per tet (5e7 on 40^3 x 6 tets,
+        // the 2e8 bunch), and slices are kept for thousands
+        return last_slices = slices_from_runs(n, 1024.0, 4096.0);
     }
 
     // 1, 4 or 16 slices from the last sort's mean same-tet run length (read
-    // back without blocking: a statistic still in flight leaves the previous)
-    int slices_from_runs(int64_t n) {
+    // back without blocking: a statistic still in flight leaves the previous):
+    // 4 from run length lo on, 16 from hi on
+    int slices_from_runs(int64_t n, double lo, double hi) {
         if (runstat_pending && hipEventQuery(runstat_ev) == hipSuccess) {
             run_len = runstat_n > 0 ? (double)*h_runstat / (double)runstat_n : 0.0;
             runstat_pending = false;
         }
         (void)hipGetLastError();   // an unfinished query is not an error
-        int s = run_len >= 256.0 ? 16 : (run_len >= 96.0 ? 4 : 1);
+        int s = run_len >= hi ? 16 : (run_len >= lo ? 4 : 1);
         while (s > 1 && n / (64 * (int64_t)s) < kMinPushWaves) s /= 4;
         return s;
     }
@@ -4237,7 +4242,8 @@ int etpic_vertex_charge(etpic_ctx *ctx, const etpic_particles *p, int precision,
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int fixed = precision == ETPIC_MIXED_FIXED ? 1 : 0;
     const int64_t n = p->n;
-    switch (ctx->slices_from_runs(n)) {
+    // the charge's atomics go straight to the vertices: slices from shorter runs on
+    switch (ctx->slices_from_runs(n, 96.0, 256.0)) {
     case 16:
         k_charge_slices<16><<<grid_for((n + 15) / 16), kBlock, 0, st>>>(n, ctx->host.nt, p->lam[0], p->lam[1],
                                                                         p->lam[2], p->tet, ctx->d_topo, sp->q * sp->w,

@@ -802,7 +802,8 @@ def main():
             log(f"[bench] precision: {json.dumps(line['precision'])}")
         if args.large_box_steps:
             line["large_box"] = config_entry(E, torch, synth, "large-box", args.large_box_steps, 2,
-                                             args.sort_every, args.log_steps, copy_gbs, forms=("mixed", "fp64"))
+                                             args.sort_every, args.log_steps, copy_gbs,
+                                             forms=("mixed_fixed", "mixed", "fp64"))
             log(f"[bench] large box: {json.dumps(line['large_box'])}")
     print(json.dumps(line), flush=True)
 

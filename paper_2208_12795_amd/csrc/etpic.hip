@@ -3145,9 +3145,9 @@ struct etpic_ctx {
                 as.o_id = p->id;
                 as.cursor = d_count;
                 if (as.rho)
-                    used_slots |= launch_push<Real, true, true>(as, push_slices_for(flags, n), remap, st, ts);
+                    used_slots |= launch_push<Real, true, true>(as, push_slices_for(flags, n, true), remap, st, ts);
                 else
-                    used_slots |= launch_push<Real, false, true>(as, push_slices_for(flags, n), remap, st, ts);
+                    used_slots |= launch_push<Real, false, true>(as, push_slices_for(flags, n, true), remap, st, ts);
                 a.scatter = 1;
             } else if (a.rho) {
                 used_slots |= launch_push<Real, true, false>(a, push_slices_for(flags, n), remap, st, ts);
@@ -3195,15 +3195,17 @@ struct etpic_ctx {
     // the mean same-tet run length of the last sort (one slice while runs fit
     // in a wavefront; 4 or 16 for longer runs), kept to >= kMinPushWaves
     // wavefronts so that the chip stays full.
-    int push_slices_for(uint32_t flags, int64_t n) {
+    int push_slices_for(uint32_t flags, int64_t n, bool sorting = false) {
         if (flags & ETPIC_STEP_SLICES_16) return last_slices = 16;
         if (flags & ETPIC_STEP_SLICES_4) return last_slices = 4;
         if (flags & ETPIC_STEP_SLICES_1) return last_slices = 1;
         // The particle kernel adds a run's currents to its tet's slots, so
         // long runs cost it few same-address atomics: one slice measured
         // fastest up to hundreds of particles per tet (5e7 on 40^3 x 6 tets,
-        // the 2e8 bunch), and slices are kept for thousands
-        return last_slices = slices_from_runs(n, 1024.0, 4096.0);
+        // the 2e8 bunch), and slices are kept for thousands.  The sorting
+        // form takes one cursor atomic per run and tet, which slices divide:
+        // it keeps them from a hundred particles per tet on
+        return last_slices = sorting ? slices_from_runs(n, 96.0, 256.0) : slices_from_runs(n, 1024.0, 4096.0);
     }
 
     // 1, 4 or 16 slices from the last sort's mean same-tet run length (read

@@ -76,6 +76,7 @@ FORM_DTYPE = {"fp64": "f64", "mixed": "f32 gather/push, f64 deposit",
 def precision_of(E, form):
     return {"fp64": E.FP64, "mixed": E.MIXED, "mixed_fixed": E.MIXED_FIXED}[form]
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_push_hbm_traffic_40cube_1e7.md")
+TRAFFIC_SUMMARY_LARGE = os.path.join(ROOT, "profiles", "k_push_hbm_traffic_large_box_2e8.md")
 COPY_CALIB_BYTES = 1 << 30
 CPU_SAMPLE_MAX = 10_000_000
 WORKLOADS = {
@@ -651,7 +652,8 @@ def config_entry(E, torch, synth, key, steps, warmup, sort_every, nlog, copy_gbs
         out[form] = {"value": r["value"], "ms_per_step": r["ms_per_step"], "sort_ms": r["sort_ms"],
                      "dtype": FORM_DTYPE[form],
                      "gauss_rel": r["gauss_rel"], "logged": r["logged"],
-                     "roofline": roofline(res, form, n_p, n_t, n_e, sort_every, copy_gbs)}
+                     "roofline": roofline(res, form, n_p, n_t, n_e, sort_every, copy_gbs,
+                                          TRAFFIC_SUMMARY_LARGE if key == "large-box" else None)}
     for form in ("mixed", "mixed_fixed"):
         if "fp64" in res and form in res:
             out[form]["speedup_vs_fp64"] = res[form]["value"] / res["fp64"]["value"]

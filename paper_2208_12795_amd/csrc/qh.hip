@@ -1519,10 +1519,15 @@ int etpic_cotree_counts(const etpic_cotree *z, int64_t counts_out[4]) {
 int etpic_cotree_apply(etpic_cotree *z, etpic_qh *qh, int block, const double *x, double *y, double tol,
                        int max_iter, void *stream) {
     if (int r = z_check(z, qh)) return r;
-    if (!x || !y) return qfail(ETPIC_EINVAL, "null vector");
     if (!(tol > 0.0) || max_iter < 1) return qfail(ETPIC_EINVAL, "bad tol / max_iter");
+    if (block != 11 && block != 12 && block != 13 && block != 21 && block != 22 && block != 23)
+        return qfail(ETPIC_EINVAL, "block %d is not one of 11, 12, 13, 21, 22, 23", block);
+    const int64_t nin = (block == 11 || block == 22) ? z->nfc : (block == 12 || block == 21) ? z->nec : z->nz;
+    const int64_t nout = (block / 10 == 1) ? z->nfc : z->nec;
+    if ((!x && nin > 0) || (!y && nout > 0)) return qfail(ETPIC_EINVAL, "null vector");
     QH_TRY(hipSetDevice(z->device));
     hipStream_t st = static_cast<hipStream_t>(stream);
+    if (nout == 0) return ETPIC_OK;
     const double2 *X = reinterpret_cast<const double2 *>(x);
     double2 *Y = reinterpret_cast<double2 *>(y);
     const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);

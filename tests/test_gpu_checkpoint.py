@@ -155,3 +155,17 @@ def test_mismatches_are_refused(E, torch_cuda, setup, tmp_path):
     # writing over an existing checkpoint replaces it whole
     ctx.checkpoint_write(parts, 4, path)
     assert E.checkpoint_info(path)["step"] == 4
+
+
+def test_empty_particle_set_round_trip(E, torch_cuda, setup, tmp_path):
+    """No particles: the file is a header alone and reads back as such."""
+    torch = torch_cuda
+    w, ctx, f, sp = setup
+    empty = E.Particles.from_numpy(w.tet[:0], w.lam[:0], w.vel[:0], None)
+    path = str(tmp_path / "empty.bin")
+    ctx.checkpoint_write(empty, 42, path)
+    import os
+    assert os.path.getsize(path) == 136
+    assert E.checkpoint_info(path) == {"n": 0, "precision": 0, "step": 42, "has_id": False}
+    back, step = ctx.checkpoint_load(path)
+    assert step == 42 and back.n == 0

@@ -144,3 +144,29 @@ def test_bad_arguments(E, torch_cuda, setup):
     with pytest.raises(E.EtpicError) as ei:
         Z.step(-1.0, 0.0, b, x)
     assert ei.value.code == E.EINVAL
+
+
+def test_one_cell_mesh_without_inner_nodes(E, torch_cuda, ora):
+    """A single Kuhn cube (6 tets): every node on the wall, so Z13 and Z23 act
+    on an empty vector and give zero; the other blocks still match the dense
+    oracle."""
+    torch = torch_cuda
+    from oracle import qh as oqh
+    xyz, tv = synth.kuhn_mesh((1, 1, 1), (1.0, 1.0, 1.0), 0.0)
+    Q = E.QhProjectors(xyz, tv, EPS0)
+    Z = E.CotreeSystem(Q, xyz, tv, MU0)
+    m = ora.OracleMesh(xyz, tv)
+    assert Z.n_inner_node == 0 and Z.n_cotree_edge == m.ne - m.nv + 1
+    empty = torch.zeros((0, 2), dtype=torch.float64, device="cuda")
+    for block, n_out in ((13, Z.n_cotree_face), (23, Z.n_cotree_edge)):
+        y = torch.full((n_out, 2), 7.0, dtype=torch.float64, device="cuda")
+        Z.apply(block, empty, y)
+        assert torch.count_nonzero(y).item() == 0
+    Z11, Z12, Z21, Z22, _ = oqh.solenoidal_blocks(m, EPS0, MU0, weighted=False)
+    rng = np.random.default_rng(0)
+    x = rand(rng, Z.n_cotree_edge)
+    y = torch.zeros((Z.n_cotree_edge, 2), dtype=torch.float64, device="cuda")
+    Z.apply(21, c2t(torch, x), y, tol=1e-14)
+    assert np.abs(t2c(y) - Z21 @ x).max() < 1e-10 * np.abs(Z21 @ x).max()
+    Z.close()
+    Q.close()

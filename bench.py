@@ -12,7 +12,10 @@ kernel launch.  Default workload: the 40^3 x 6 jittered Kuhn mesh (384,000
 tets) with 10,000,000 electrons (Maxwellian, 1e6 m/s), an 8-mode envelope on a
 10 GHz carrier, B = 0.5 T, dt = 1e-12 s; `--workload large-box` runs the 2:1:1
 160x80x80 x 6 mesh with 2e8 electrons (bunch + background, B = 1 T along x).
-Inputs are resident in HBM before the timed region starts.
+Inputs are resident in HBM before the timed region starts, and before each
+form's warmup steps ~50 ms of untimed streaming over its particle arrays lets
+the GPU's clocks settle (without it the first timed steps of a short run are
+~3 % slower).
 
 Prints ONE JSON line.  `value` is the float64 form; the mixed form (float32
 gather/push on barycentrics, float64 positions and deposit) is reported under
@@ -25,7 +28,9 @@ arrays), a device copy, and the whole step's algorithmic bytes over the time
 per step.  After the timed steps a few single steps are run with the
 continuity residual of each, timed apart ("logged").  Side entries (not in
 `value`): the precision workload (same mesh, 5e7 electrons) and the large box
-(2e8 electrons on 6.1M tets), both forms, each with its own roofline; the
+(2e8 electrons on 6.1M tets), all three forms, each with its own roofline,
+and on the large box a run of 1,000 mixed-form steps (re-sort every 10) with
+the continuity residual computed and checked after every step; the
 field update, the Gauss-law solve and loops, the projectors, the multi-rate
 and downshifted steps, the adjoint; and the float64 oracle on the host's
 cores (`cpu_baseline`).
@@ -78,6 +83,7 @@ def precision_of(E, form):
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_push_hbm_traffic_40cube_1e7.md")
 TRAFFIC_SUMMARY_LARGE = os.path.join(ROOT, "profiles", "k_push_hbm_traffic_large_box_2e8.md")
 COPY_CALIB_BYTES = 1 << 30
+SPIN_UP_MS = 50.0
 CPU_SAMPLE_MAX = 10_000_000
 WORKLOADS = {
     "40cube": (2, "40^3x6 jittered Kuhn tet mesh (384,000 tets), 1e7 electrons (Maxwellian 1e6 m/s), "
@@ -133,14 +139,32 @@ def logged_steps(E, torch, ctx, parts, sp, fields, w, step0, nlog):
                     "(timed apart from the step)"}
 
 
+def spin_up(torch, ctx, parts, min_ms=SPIN_UP_MS):
+    """Untimed streaming over the particle arrays (the stream probe, which
+    leaves them as they are) until min_ms of device time have passed: the
+    GPU's clocks settle under sustained load, and a handful of warmup steps
+    alone leaves the first timed steps ~3 % slower."""
+    done = 0.0
+    while done < min_ms:
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            ctx.stream_probe(parts)
+        e1.record()
+        torch.cuda.synchronize()
+        done += e0.elapsed_time(e1)
+    return done
+
+
 def run_form(E, torch, ctx, w, precision, steps, warmup, sort_every, fields, nlog=0, stream_reps=10):
     sp = E.Species(w.q, w.m, w.w)
     parts = E.Particles.from_numpy(w.tet, w.lam, w.vel, w.ids, precision=precision)
     spare = parts.empty_like()
     dG = torch.zeros(ctx.n_edge, dtype=torch.float64, device="cuda")
-    # initial sort, then warmup
+    # initial sort, clocks settled, then warmup
     ctx.sort(parts, spare)
     parts, spare = spare, parts
+    spin_ms = spin_up(torch, ctx, parts)
     step = 0
     for _ in range(warmup):
         ctx.gather_push_deposit(parts, sp, fields, step, w.dt, w.omega, dG)
@@ -227,6 +251,7 @@ def run_form(E, torch, ctx, w, precision, steps, warmup, sort_every, fields, nlo
     logged = logged_steps(E, torch, ctx, parts, sp, fields, w, step + 1, nlog) if nlog else None
     return {
         "slices": slices,
+        "spin_up_ms": round(spin_ms, 1),
         "stream_ms": stream_ms,
         "logged": logged,
         "ms_per_step": total_ms / steps,
@@ -625,11 +650,61 @@ def roofline(res, form, n_p, n_t, n_e, sort_every, copy_gbs, traffic_path=None):
                                    % (STEP_BYTES_PER_PARTICLE[form], STEP_BYTES_PER_TET)}}
 
 
+def logged_run(E, torch, ctx, w, fields, form, nsteps, sort_every):
+    """nsteps single steps of one form, re-sorted every sort_every steps (the
+    sort folded into that step), each followed by the vertex charge and the
+    continuity residual of that step: the largest relative residual over the
+    run, and the mean time of a step and of its residual, each from events on
+    the stream apart from the other (the residual's host read synchronises
+    every step, so the steps do not overlap)."""
+    sp = E.Species(w.q, w.m, w.w)
+    parts = E.Particles.from_numpy(w.tet, w.lam, w.vel, w.ids, precision=precision_of(E, form))
+    spare = parts.empty_like()
+    ctx.sort(parts, spare)
+    parts, spare = spare, parts
+    dG = torch.zeros(ctx.n_edge, dtype=torch.float64, device="cuda")
+    rho_a = torch.zeros(ctx.n_vert, dtype=torch.float64, device="cuda")
+    rho_b = torch.zeros_like(rho_a)
+    ctx.vertex_charge(parts, sp, rho_a)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    worst, step_ms, res_ms = 0.0, 0.0, 0.0
+    t0 = time.perf_counter()
+    for k in range(nsteps):
+        dG.zero_()
+        rho_b.zero_()
+        ev[0].record()
+        if sort_every and k % sort_every == 0:
+            ctx.sort_run_steps(parts, spare, sp, fields, k, 1, w.dt, w.omega, dG, flags=E.STEP_XCD_REMAP)
+            parts, spare = spare, parts
+        else:
+            ctx.gather_push_deposit(parts, sp, fields, k, w.dt, w.omega, dG, flags=E.STEP_XCD_REMAP)
+        ev[1].record()
+        ctx.vertex_charge(parts, sp, rho_b)
+        r, p = ctx.gauss_residual(dG, rho_b, rho_a)
+        ev[2].record()
+        ev[2].synchronize()
+        worst = max(worst, r / p)
+        step_ms += ev[0].elapsed_time(ev[1])
+        res_ms += ev[1].elapsed_time(ev[2])
+        rho_a, rho_b = rho_b, rho_a
+    wall = time.perf_counter() - t0
+    ctx.check()
+    n = parts.n
+    del parts, spare
+    torch.cuda.empty_cache()
+    return {"form": form, "steps": nsteps, "sort_every": sort_every, "gauss_rel_max": worst,
+            "step_ms": step_ms / nsteps, "charge_and_residual_ms": res_ms / nsteps, "wall_s": round(wall, 2),
+            "value": n / (step_ms / nsteps * 1e-3),
+            "note": "every step followed by the vertex charge and the continuity residual of that step; value is "
+                    "particle-steps/s over the mean step time without the residual"}
+
+
 def config_entry(E, torch, synth, key, steps, warmup, sort_every, nlog, copy_gbs,
-                 forms=("fp64", "mixed", "mixed_fixed")):
+                 forms=("fp64", "mixed", "mixed_fixed"), logged_steps_run=0, logged_form="mixed"):
     """A second workload measured beside the metric's: both forms, its own
     roofline entries and a logged phase of single steps with the continuity
-    residual of every step timed apart."""
+    residual of every step timed apart; with logged_steps_run, also a run of
+    that many single steps of logged_form with the residual after every one."""
     cfg, desc = WORKLOADS[key]
     t0 = time.perf_counter()
     w = synth.make_workload(cfg, progress=lambda m: log(f"[bench] {key}: generated {m}"))
@@ -657,6 +732,9 @@ def config_entry(E, torch, synth, key, steps, warmup, sort_every, nlog, copy_gbs
     for form in ("mixed", "mixed_fixed"):
         if "fp64" in res and form in res:
             out[form]["speedup_vs_fp64"] = res[form]["value"] / res["fp64"]["value"]
+    if logged_steps_run:
+        out["logged_run"] = logged_run(E, torch, ctx, w, fields, logged_form, logged_steps_run, sort_every)
+        log(f"[bench] {key} logged run: {json.dumps(out['logged_run'])}")
     ctx.close()
     del w
     return out
@@ -677,6 +755,9 @@ def main():
                     help="single steps with the continuity residual of each, after the timed run")
     ap.add_argument("--precision-steps", type=int, default=20,
                     help="steps of the 5e7-particle side entry (0: skip it)")
+    ap.add_argument("--large-box-logged-steps", type=int, default=1000,
+                    help="single mixed-form steps of the large box, each followed by the continuity residual "
+                         "(0: skip)")
     ap.add_argument("--large-box-steps", type=int, default=100,
                     help="steps of the 2e8-particle large-box side entry (0: skip it)")
     ap.add_argument("--cpu-steps", type=int, default=3)
@@ -805,7 +886,8 @@ def main():
         if args.large_box_steps:
             line["large_box"] = config_entry(E, torch, synth, "large-box", args.large_box_steps, 2,
                                              args.sort_every, args.log_steps, copy_gbs,
-                                             forms=("mixed_fixed", "mixed", "fp64"))
+                                             forms=("mixed_fixed", "mixed", "fp64"),
+                                             logged_steps_run=args.large_box_logged_steps)
             log(f"[bench] large box: {json.dumps(line['large_box'])}")
     print(json.dumps(line), flush=True)
 

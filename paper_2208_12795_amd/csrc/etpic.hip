@@ -297,16 +297,58 @@ __device__ __forceinline__ void tet_coef(int64_t nt, const double *__restrict__ 
         tp[7] = fc.y;
         tp[8] = fc.z;
         tp[9] = fc.w;
+        // the DoFs first, all gathers in flight together (each edge serves
+        // two of the A_k, each face three of the C_k), then the sums in the
+        // order and with the operations of coef_A / coef_C
         if (part == 0) {
-            coef_A<0, kSnap>(tp, g, F, o);
-            coef_A<1, kSnap>(tp, g, F, o + 3);
-            coef_A<2, kSnap>(tp, g, F, o + 6);
-            coef_A<3, kSnap>(tp, g, F, o + 9);
+            double ev[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                const double2 z = envelope<kSnap>(F.e_env, F.w, tp[k]);
+                ev[k] = z.x * F.c - z.y * F.s;
+            }
+            if (F.e_dc)
+#pragma unroll
+                for (int k = 0; k < 6; ++k) ev[k] += F.e_dc[tp[k]];
+#pragma unroll
+            for (int K = 0; K < 4; ++K) {
+                double *A = o + 3 * K;
+                A[0] = A[1] = A[2] = 0.0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (j == K) continue;
+                    double eps = ev[local_edge(j < K ? j : K, j < K ? K : j)];
+                    if (j < K) eps = -eps;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) A[d] += eps * g[j][d];
+                }
+            }
         } else {
-            coef_C<0, kSnap>(tp, g, F, o);
-            coef_C<1, kSnap>(tp, g, F, o + 3);
-            coef_C<2, kSnap>(tp, g, F, o + 6);
-            coef_C<3, kSnap>(tp, g, F, o + 9);
+            double bv[4];
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                const double2 z = envelope<kSnap>(F.b_env, F.w, tp[6 + f]);
+                bv[f] = z.x * F.c - z.y * F.s;
+            }
+            if (F.b_dc)
+#pragma unroll
+                for (int f = 0; f < 4; ++f) bv[f] += F.b_dc[tp[6 + f]];
+            constexpr int lf[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+#pragma unroll
+            for (int K = 0; K < 4; ++K) {
+                double *Cv = o + 3 * K;
+                Cv[0] = Cv[1] = Cv[2] = 0.0;
+#pragma unroll
+                for (int f = 0; f < 4; ++f) {
+                    if (f == K) continue;
+                    const int a = lf[f][0] == K ? lf[f][1] : (lf[f][1] == K ? lf[f][2] : lf[f][0]);
+                    const int b = lf[f][0] == K ? lf[f][2] : (lf[f][1] == K ? lf[f][0] : lf[f][1]);
+                    const double beta = bv[f] * 2.0;
+                    Cv[0] += beta * (g[a][1] * g[b][2] - g[a][2] * g[b][1]);
+                    Cv[1] += beta * (g[a][2] * g[b][0] - g[a][0] * g[b][2]);
+                    Cv[2] += beta * (g[a][0] * g[b][1] - g[a][1] * g[b][0]);
+                }
+            }
         }
     }
     __syncthreads();   // every staged row read: the space takes the output

@@ -155,3 +155,33 @@ def test_positions_match_oracle_and_round_trip(E, torch_cuda, ora):
     assert np.array_equal(back.tet.cpu().numpy()[off], w.tet[off])
     assert np.abs(lam_b[off] - w.lam[off]).max() < 1e-13
     ctx.close()
+
+
+def test_positions_and_locate_in_fixed_point_storage(E, torch_cuda, ora):
+    """The compact mixed form's storage (barycentrics as uint32, 2^-32):
+    positions() from the stored grid values against the oracle's positions of
+    the same (exact) barycentrics, and locate() of those points stores the
+    same grid values back up to one grid step (the point's barycentrics are
+    recomputed in float64 and rounded to the grid again)."""
+    torch = torch_cuda
+    w = synth.make_workload(1)
+    M = ora.OracleMesh(w.xyz, w.tet_vert)
+    ctx = E.Context(0)
+    ctx.upload_mesh(w.xyz, w.tet_vert)
+    parts = E.Particles.from_numpy(w.tet, w.lam, w.vel, precision=E.MIXED_FIXED)
+    t, lam, _, _ = parts.to_numpy()
+    x = ctx.positions(parts)
+    ref = M.positions(t, lam)
+    assert np.abs(x.cpu().numpy().T - ref).max() < 1e-15
+    back = E.Particles(torch.full((3, parts.n), -1, dtype=torch.int32, device="cuda"),
+                       torch.zeros((3, parts.n), dtype=torch.float32, device="cuda"),
+                       torch.full((parts.n,), -9, dtype=torch.int32, device="cuda"))
+    assert back.precision == E.MIXED_FIXED
+    ctx.locate(x, back)
+    tb, lb, _, _ = back.to_numpy()
+    l4 = np.concatenate([1.0 - lam.sum(axis=1, keepdims=True), lam], axis=1)
+    off = l4.min(axis=1) > 1e-9
+    assert np.array_equal(tb[off], t[off])
+    assert np.abs(lb[off] - lam[off]).max() <= 2.0 ** -32 + 1e-15
+    assert np.all(1.0 - lb.sum(axis=1) >= 0.0)
+    ctx.close()

@@ -47,6 +47,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# vector-ALU issue ceiling: 256 CUs x 4 SIMDs, one 64-lane wavefront instruction
+# per 4 cycles of a 16-lane SIMD, at 2.4 GHz (wavefront instructions per second)
+VALU_PEAK_PER_S = 256 * 4 * 2.4e9 / 4
 # Algorithmic bytes of the particle kernel (what it must move per unit):
 #  per particle-step: state read (tet 4 B, lam 3x8, v 3x8) and written back
 #                     (lam 3x8, v 3x8): 100 B in float64; v is float32 in the
@@ -82,6 +85,8 @@ def precision_of(E, form):
     return {"fp64": E.FP64, "mixed": E.MIXED, "mixed_fixed": E.MIXED_FIXED}[form]
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_push_hbm_traffic_40cube_1e7.md")
 TRAFFIC_SUMMARY_LARGE = os.path.join(ROOT, "profiles", "k_push_hbm_traffic_large_box_2e8.md")
+VALU_SUMMARY = os.path.join(ROOT, "profiles", "k_push_valu_issue_40cube_1e7.md")
+VALU_SUMMARY_LARGE = os.path.join(ROOT, "profiles", "k_push_valu_issue_large_box_2e8.md")
 COPY_CALIB_BYTES = 1 << 30
 SPIN_UP_MS = 50.0
 CPU_SAMPLE_MAX = 10_000_000
@@ -619,12 +624,32 @@ def cpu_baseline(w, nthreads, steps, stride):
     return tet.shape[0] * steps / wall, wall, cpu
 
 
-def roofline(res, form, n_p, n_t, n_e, sort_every, copy_gbs, traffic_path=None):
+def alu_roofline(valu_path, name, kernel_ms):
+    """The particle kernel against the vector-ALU issue ceiling: its VALU
+    wavefront instructions per launch (counted by rocprofv3 on this source and
+    workload, from the committed summary) over its mean duration measured here;
+    None without a matching summary."""
+    if valu_path is None:
+        return None
+    from paper_2208_12795_amd import rocprof_summary
+    v = rocprof_summary.read_valu(valu_path, name)
+    if v is None:
+        return None
+    insts, busy = v
+    ach = insts / (kernel_ms * 1e-3)
+    return {"bound": "alu", "achieved": round(ach / 1e9, 1), "peak": round(VALU_PEAK_PER_S / 1e9, 1),
+            "unit": "G VALU wavefront instructions/s", "frac": round(ach / VALU_PEAK_PER_S, 4),
+            "valu_insts_per_launch": insts, "valu_busy_pct_profiled": busy}
+
+
+def roofline(res, form, n_p, n_t, n_e, sort_every, copy_gbs, traffic_path=None, valu_path=None):
     """Roofline entry of one form's run: the dominant kernel (the particle
     kernel: its algorithmic bytes per launch over its mean duration from HIP
     events on its launch stream), the attainable rate of its access pattern
     alone (stream probe) and of a device copy, and the whole step's
-    algorithmic bytes over the measured time per step."""
+    algorithmic bytes over the measured time per step; with a VALU summary, the
+    same kernel against the vector-ALU issue ceiling (the binding one for the
+    compact mixed form)."""
     r = res[form]
     name = kernel_name(form, r["slices"])
     bytes_launch = BYTES_PER_PARTICLE[form] * n_p + BYTES_PER_TET[form] * n_t + BYTES_PER_EDGE * n_e
@@ -643,6 +668,7 @@ def roofline(res, form, n_p, n_t, n_e, sort_every, copy_gbs, traffic_path=None):
             "bytes_per_launch": bytes_launch, "kernel_ms": round(r["kernel_ms"], 5),
             "stream_GBs": round(stream_gbs, 1), "frac_of_stream": round(ach / stream_gbs, 4),
             "copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(ach / copy_gbs, 4),
+            "alu": alu_roofline(valu_path, name, r["kernel_ms"]),
             "whole_step": {"bytes_per_step": int(step_bytes), "ms_per_step": round(r["ms_per_step"], 5),
                            "achieved": round(step_gbs, 1), "frac": round(step_gbs / HBM_PEAK_GBS, 4),
                            "note": "algorithmic bytes of the whole step (state %d B per particle, %d B per "
@@ -728,7 +754,8 @@ def config_entry(E, torch, synth, key, steps, warmup, sort_every, nlog, copy_gbs
                      "dtype": FORM_DTYPE[form],
                      "gauss_rel": r["gauss_rel"], "logged": r["logged"],
                      "roofline": roofline(res, form, n_p, n_t, n_e, sort_every, copy_gbs,
-                                          TRAFFIC_SUMMARY_LARGE if key == "large-box" else None)}
+                                          TRAFFIC_SUMMARY_LARGE if key == "large-box" else None,
+                                          VALU_SUMMARY_LARGE if key == "large-box" else None)}
     for form in ("mixed", "mixed_fixed"):
         if "fp64" in res and form in res:
             out[form]["speedup_vs_fp64"] = res[form]["value"] / res["fp64"]["value"]
@@ -815,6 +842,7 @@ def main():
         log(f"[bench] {form}: {json.dumps(res[form])}")
     n_p, n_t, n_e = w.tet.shape[0], w.tet_vert.shape[0], ctx.n_edge
     traffic_path = TRAFFIC_SUMMARY if (args.particles is None and args.workload == "40cube") else None
+    valu_path = VALU_SUMMARY if (args.particles is None and args.workload == "40cube") else None
 
     main_form = "fp64" if "fp64" in res else next(iter(res))
     r = res[main_form]
@@ -833,7 +861,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc + ", sort every %d steps" % args.sort_every,
                    "n_particles": n_p, "n_tets": n_t, "n_edges": n_e, "parallelism": "single GPU"},
-        "roofline": roofline(res, main_form, n_p, n_t, n_e, args.sort_every, copy_gbs, traffic_path),
+        "roofline": roofline(res, main_form, n_p, n_t, n_e, args.sort_every, copy_gbs, traffic_path, valu_path),
         "sort_ms": r["sort_ms"],
         "gauss_rel": r["gauss_rel"],
         "gauss_ms": r["gauss_ms"],
@@ -844,7 +872,8 @@ def main():
             m = res[form]
             line[form] = {"value": m["value"], "ms_per_step": m["ms_per_step"], "dtype": FORM_DTYPE[form],
                           "speedup_vs_fp64": m["value"] / r["value"],
-                          "roofline": roofline(res, form, n_p, n_t, n_e, args.sort_every, copy_gbs, traffic_path),
+                          "roofline": roofline(res, form, n_p, n_t, n_e, args.sort_every, copy_gbs, traffic_path,
+                                               valu_path),
                           "gauss_rel": m["gauss_rel"], "logged": m["logged"]}
     if not args.no_side and args.workload == "40cube":
         line["field_update"] = field_update_timing(E, torch, ctx, w)

@@ -728,6 +728,15 @@ constexpr __host__ __device__ bool push_uses_slots(int slices) {
     return std::is_same<Real, float>::value || slices == 1;
 }
 
+// Element ln of a wavefront-uniform array: the scalar base plus a 32-bit byte
+// offset, which the global loads and stores take as such (base in scalar
+// registers, one offset register shared by every array of the same element
+// size) instead of a 64-bit address per array and lane.
+template <typename T>
+__device__ __forceinline__ T *lane_at(T *base, unsigned ln) {
+    return reinterpret_cast<T *>(reinterpret_cast<char *>(base) + ln * (unsigned)sizeof(T));
+}
+
 template <typename Real, int kSlices, bool kRho, bool kScatter = false, bool kFixed = false>
 __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) {
     static_assert(!kFixed || std::is_same<Real, float>::value, "fixed-point barycentrics are a mixed-form storage");
@@ -757,8 +766,9 @@ __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) 
         // non-temporal loads and stores, which leaves the caches to the per-tet
         // rows, the field DoFs and the current accumulator.
         const int64_t b0 = slice * 64;
-        int ln = lane;
+        unsigned ln = lane;
         asm volatile("" : "+v"(ln));
+        __builtin_assume(ln < 64u);
         const int64_t p = b0 + ln;
         double *__restrict__ lam1 = a.lam1 + b0, *__restrict__ lam2 = a.lam2 + b0, *__restrict__ lam3 = a.lam3 + b0;
         Real *__restrict__ v0 = a.v0 + b0, *__restrict__ v1 = a.v1 + b0, *__restrict__ v2 = a.v2 + b0;
@@ -782,20 +792,20 @@ __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) 
         Real sv0 = 0, sv1 = 0, sv2 = 0;
         auto load_state = [&]() {
             if (fx) {
-                su1 = __builtin_nontemporal_load(&f1[ln]);
-                su2 = __builtin_nontemporal_load(&f2[ln]);
-                su3 = __builtin_nontemporal_load(&f3[ln]);
+                su1 = __builtin_nontemporal_load(lane_at(f1, ln));
+                su2 = __builtin_nontemporal_load(lane_at(f2, ln));
+                su3 = __builtin_nontemporal_load(lane_at(f3, ln));
             } else {
-                sl1 = __builtin_nontemporal_load(&lam1[ln]);
-                sl2 = __builtin_nontemporal_load(&lam2[ln]);
-                sl3 = __builtin_nontemporal_load(&lam3[ln]);
+                sl1 = __builtin_nontemporal_load(lane_at(lam1, ln));
+                sl2 = __builtin_nontemporal_load(lane_at(lam2, ln));
+                sl3 = __builtin_nontemporal_load(lane_at(lam3, ln));
             }
-            sv0 = __builtin_nontemporal_load(&v0[ln]);
-            sv1 = __builtin_nontemporal_load(&v1[ln]);
-            sv2 = __builtin_nontemporal_load(&v2[ln]);
+            sv0 = __builtin_nontemporal_load(lane_at(v0, ln));
+            sv1 = __builtin_nontemporal_load(lane_at(v1, ln));
+            sv2 = __builtin_nontemporal_load(lane_at(v2, ln));
         };
         if (p < a.n) {
-            T = __builtin_nontemporal_load(&tetp[ln]);
+            T = __builtin_nontemporal_load(lane_at(tetp, ln));
             if (kEarly) load_state();
             if ((unsigned)T >= (unsigned)a.nt) {
                 atomicOr(a.status, (unsigned)ETPIC_DEV_BADTET);
@@ -899,13 +909,13 @@ __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) 
                     }
                     a.o_tet[dq] = T;
                 } else if (fx) {
-                    __builtin_nontemporal_store(un[0], &f1[ln]);
-                    __builtin_nontemporal_store(un[1], &f2[ln]);
-                    __builtin_nontemporal_store(un[2], &f3[ln]);
+                    __builtin_nontemporal_store(un[0], lane_at(f1, ln));
+                    __builtin_nontemporal_store(un[1], lane_at(f2, ln));
+                    __builtin_nontemporal_store(un[2], lane_at(f3, ln));
                 } else {
-                    __builtin_nontemporal_store(l[1], &lam1[ln]);
-                    __builtin_nontemporal_store(l[2], &lam2[ln]);
-                    __builtin_nontemporal_store(l[3], &lam3[ln]);
+                    __builtin_nontemporal_store(l[1], lane_at(lam1, ln));
+                    __builtin_nontemporal_store(l[2], lane_at(lam2, ln));
+                    __builtin_nontemporal_store(l[3], lane_at(lam3, ln));
                 }
                 if (kRho) {
                     r4[0] = 1.0 - l[1] - l[2] - l[3];
@@ -927,7 +937,7 @@ __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) 
                 a.o_tet[dq] = walker_mark(T);
                 walker = 1;
             } else {
-                tetp[ln] = walker_mark(T);
+                *lane_at(tetp, ln) = walker_mark(T);
                 walker = 1;
             }
             if (kScatter) {
@@ -936,9 +946,9 @@ __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) 
                 __builtin_nontemporal_store(v[2], &a.o_v2[dq]);
                 if (a.id) __builtin_nontemporal_store(__builtin_nontemporal_load(&a.id[p]), &a.o_id[dq]);
             } else {
-                __builtin_nontemporal_store(v[0], &v0[ln]);
-                __builtin_nontemporal_store(v[1], &v1[ln]);
-                __builtin_nontemporal_store(v[2], &v2[ln]);
+                __builtin_nontemporal_store(v[0], lane_at(v0, ln));
+                __builtin_nontemporal_store(v[1], lane_at(v1, ln));
+                __builtin_nontemporal_store(v[2], lane_at(v2, ln));
             }
         }
         const WaveRuns runs = wave_runs(T, ln);

@@ -1,6 +1,6 @@
 """Condense rocprofv3 CSV output into the short text summaries kept under profiles/.
 
-Two summaries:
+Three summaries:
 
 * kernel statistics (``--kernel-trace --stats``): calls and average / min / max
   duration per kernel;
@@ -8,13 +8,18 @@ Two summaries:
   WRITE_SIZE``, both in KiB per dispatch).  Each counter is scaled by what it
   reads for a plain device copy of known size in the same run (the largest
   ``__amd_rocclr_copyBuffer`` dispatch, ``bench.py --calibrate-copy``: 1 GiB read
-  and 1 GiB written), so the scaled figure is in bytes of HBM traffic.
+  and 1 GiB written), so the scaled figure is in bytes of HBM traffic;
+* vector-ALU issue from one counter run (``--pmc SQ_WAVES SQ_INSTS_VALU
+  VALUBusy``): wavefronts, VALU instructions issued (counted once per
+  wavefront instruction) and the share of the kernel's time the CUs' vector
+  ALUs were busy, per dispatch.
 
-The counter summary records the SHA-256 of the HIP source the counters were
-taken on; ``bench.py`` reports the traffic only while that source is unchanged.
+The counter summaries record the SHA-256 of the HIP source the counters were
+taken on; ``bench.py`` uses their figures only while that source is unchanged.
 
     python -m paper_2208_12795_amd.rocprof_summary stats  <dir> <prefix> <out.md> --command "..."
     python -m paper_2208_12795_amd.rocprof_summary traffic <fetch_dir> <write_dir> <prefix> <out.md> --command "..."
+    python -m paper_2208_12795_amd.rocprof_summary valu <dir> <prefix> <out.md> --command "..."
 """
 from __future__ import annotations
 
@@ -47,6 +52,15 @@ def load_counters(path: str) -> dict:
     with open(path) as f:
         for r in csv.DictReader(f):
             per[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return per
+
+
+def load_counter_table(path: str) -> dict:
+    """kernel -> counter -> list of per-dispatch values (a run of several counters)"""
+    per = collections.defaultdict(lambda: collections.defaultdict(list))
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            per[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
     return per
 
 
@@ -86,6 +100,56 @@ def traffic_summary(fetch_dir: str, write_dir: str, prefix: str, command: str, s
     return "\n".join(out + ["", "Machine-readable:", "", "```"] + tagged + ["```"]) + "\n"
 
 
+def valu_summary(prof_dir: str, prefix: str, command: str, sha: str) -> str:
+    per = load_counter_table(os.path.join(prof_dir, f"{prefix}_counter_collection.csv"))
+    out = ["# Vector-ALU issue per dispatch from SQ_WAVES / SQ_INSTS_VALU / VALUBusy", "", "Command:", "", "```",
+           command, "```", "", f"source_sha256: {sha}", "",
+           "SQ_INSTS_VALU counts one per wavefront instruction; a wavefront (64 lanes) occupies a 16-lane SIMD "
+           "for 4 cycles per VALU instruction, so the issue ceiling is 256 CUs x 4 SIMDs x 2.4 GHz / 4 = "
+           "614.4e9 wavefront instructions per second.  VALUBusy is rocprofv3's derived share of the "
+           "dispatch's GPU-active time the CUs' vector ALUs were busy.", "",
+           "| kernel | dispatches | wavefronts | VALU instructions | per wavefront | VALUBusy % |",
+           "|---|---|---|---|---|---|"]
+    tagged = []
+    rows = []
+    for k, d in per.items():
+        if "SQ_INSTS_VALU" not in d or "SQ_WAVES" not in d:
+            continue
+        mean = {c: sum(v) / len(v) for c, v in d.items()}
+        rows.append((k, len(d["SQ_INSTS_VALU"]), mean))
+    for k, nd, mean in sorted(rows, key=lambda r: -r[2]["SQ_INSTS_VALU"]):
+        waves, insts = mean["SQ_WAVES"], mean["SQ_INSTS_VALU"]
+        busy = mean.get("VALUBusy")
+        out.append(f"| `{short_name(k)}` | {nd} | {waves:.0f} | {insts:.4g} | {insts / max(waves, 1):.1f} | "
+                   f"{'' if busy is None else f'{busy:.1f}'} |")
+        tagged.append(f"valu_insts {short_name(k)}: {int(round(insts))}")
+        if busy is not None:
+            tagged.append(f"valu_busy {short_name(k)}: {busy:.2f}")
+    return "\n".join(out + ["", "Machine-readable:", "", "```"] + tagged + ["```"]) + "\n"
+
+
+def _tagged(path: str, tag: str, kernel: str, sha: str | None):
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"^source_sha256: ([0-9a-f]{64})$", text, re.M)
+    if not m or m.group(1) != (sha or source_sha256()):
+        return None
+    m = re.search(r"^" + tag + " " + re.escape(kernel) + r": ([0-9.]+)$", text, re.M)
+    return m.group(1) if m else None
+
+
+def read_valu(path: str, kernel: str, sha: str | None = None):
+    """(VALU instructions per dispatch, VALUBusy %) of `kernel` from a VALU
+    summary, or None if the file is missing, lacks the kernel, or was taken on
+    another source."""
+    n = _tagged(path, "valu_insts", kernel, sha)
+    if n is None:
+        return None
+    b = _tagged(path, "valu_busy", kernel, sha)
+    return int(n), (None if b is None else float(b))
+
+
 def read_traffic(path: str, kernel: str, sha: str | None = None):
     """Scaled HBM bytes per dispatch of `kernel` from a traffic summary, or None
     if the file is missing, lacks the kernel, or was taken on another source."""
@@ -114,9 +178,17 @@ def main():
     t.add_argument("out")
     t.add_argument("--command", required=True)
     t.add_argument("--sha", default=None, help="SHA-256 of the HIP source profiled (default: the current one)")
+    v = sub.add_parser("valu")
+    v.add_argument("dir")
+    v.add_argument("prefix")
+    v.add_argument("out")
+    v.add_argument("--command", required=True)
+    v.add_argument("--sha", default=None, help="SHA-256 of the HIP source profiled (default: the current one)")
     a = ap.parse_args()
     if a.mode == "stats":
         text = stats_summary(a.dir, a.prefix, a.command)
+    elif a.mode == "valu":
+        text = valu_summary(a.dir, a.prefix, a.command, a.sha or source_sha256())
     else:
         text = traffic_summary(a.fetch_dir, a.write_dir, a.prefix, a.command, a.sha or source_sha256())
     with open(a.out, "w") as f:

@@ -119,20 +119,39 @@ __device__ __forceinline__ double dpp_get(double x) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+// As dpp_get, but lanes whose row is off in kRowMask keep `old` (a value the
+// caller no longer needs, so its registers take the result and no zeroing
+// move is issued; the caller's factor for those lanes is 0).
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ double dpp_get_or(double old, double x) {
+    const long long b = __double_as_longlong(x), o = __double_as_longlong(old);
+    const int lo = __builtin_amdgcn_update_dpp((int)(o & 0xffffffffll), (int)(b & 0xffffffffll), kCtrl, kRowMask,
+                                               0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(b >> 32), kCtrl, kRowMask, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // Segmented inclusive prefix sum over the wave: after the call the LAST lane of
 // each run (lane == run_end) holds the run's total.  Hillis-Steele within rows
 // of 16 lanes by DPP row shifts (1, 2, 4, 8), then the row broadcasts of lane 15
 // (into rows 1, 3) and lane 31 (into rows 2, 3); a lane only adds a partial sum
 // whose lanes all belong to its own run, selected by a 0/1 factor rather than a
-// branch.
+// branch.  The broadcasts leave the rows they skip holding the previous round's
+// fetched partial sum (finite), which their factor 0 discards.
 __device__ __forceinline__ double run_total(double x, const WaveRuns &r) {
     const int h = r.head_lane, l = r.lane;
-    x = fma(dpp_get<0x111, 0xf>(x), l - 1 >= h ? 1.0 : 0.0, x);   // row_shr:1
-    x = fma(dpp_get<0x112, 0xf>(x), l - 2 >= h ? 1.0 : 0.0, x);   // row_shr:2
-    x = fma(dpp_get<0x114, 0xf>(x), l - 4 >= h ? 1.0 : 0.0, x);   // row_shr:4
-    x = fma(dpp_get<0x118, 0xf>(x), l - 8 >= h ? 1.0 : 0.0, x);   // row_shr:8
-    x = fma(dpp_get<0x142, 0xa>(x), h < (l & 48) ? 1.0 : 0.0, x); // row_bcast:15
-    x = fma(dpp_get<0x143, 0xc>(x), h < 32 ? 1.0 : 0.0, x);       // row_bcast:31
+    double t = dpp_get<0x111, 0xf>(x);                                // row_shr:1
+    x = fma(t, l - 1 >= h ? 1.0 : 0.0, x);
+    t = dpp_get<0x112, 0xf>(x);                                       // row_shr:2
+    x = fma(t, l - 2 >= h ? 1.0 : 0.0, x);
+    t = dpp_get<0x114, 0xf>(x);                                       // row_shr:4
+    x = fma(t, l - 4 >= h ? 1.0 : 0.0, x);
+    t = dpp_get<0x118, 0xf>(x);                                       // row_shr:8
+    x = fma(t, l - 8 >= h ? 1.0 : 0.0, x);
+    t = dpp_get_or<0x142, 0xa>(t, x);                                 // row_bcast:15
+    x = fma(t, (l & 16) != 0 && h < (l & 48) ? 1.0 : 0.0, x);
+    t = dpp_get_or<0x143, 0xc>(t, x);                                 // row_bcast:31
+    x = fma(t, l >= 32 && h < 32 ? 1.0 : 0.0, x);
     return x;
 }
 
@@ -645,7 +664,10 @@ __device__ __forceinline__ void flush_run(const StepArgs<Real> &a, int T, const 
 // The six edge sums of the runs that end in this wavefront, added by the last
 // six lanes of each run together (lane run_end - k adds local edge k, its sum
 // fetched from the run's last lane): the wavefront issues one atomic
-// instruction where the run-end lanes alone would issue six.  With kSlots the
+// instruction where the run-end lanes alone would issue six.  The run-end
+// lanes hand their six sums over through a wavefront-private LDS row (three
+// 16-byte stores, one 8-byte load per flushing lane), which costs fewer
+// vector instructions than five 64-bit lane shuffles and their selects.  With kSlots the
 // sums go to the run's per-tet current slots (8 * T + k: the six lanes of a
 // run address one 64-byte line), else to the six edges.  A run shorter than
 // six lanes leaves its remaining edges to its last lane.  `flush` marks the
@@ -653,17 +675,25 @@ __device__ __forceinline__ void flush_run(const StepArgs<Real> &a, int T, const 
 template <typename Real, bool kSlots>
 __device__ __forceinline__ void flush_runs_together(const StepArgs<Real> &a, int T, const double g6[6],
                                                    const WaveRuns &r, bool flush) {
+    __shared__ double2 s_sum[kBlock / 64][64 * 3];
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const unsigned long long fm = __ballot(flush);
     const bool mine = (fm >> r.run_end) & 1ull;
     const int k = r.run_end - r.lane;
     const int len = r.run_end - r.head_lane + 1;
-    double val = g6[0];
-#pragma unroll
-    for (int j = 1; j < 6; ++j) {
-        const double t = __shfl_down(g6[j], j);
-        if (k == j) val = t;
+    if (flush) {
+        double2 *row = &s_sum[wv][3 * r.lane];
+        row[0] = make_double2(g6[0], g6[1]);
+        row[1] = make_double2(g6[2], g6[3]);
+        row[2] = make_double2(g6[4], g6[5]);
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double val = 0.0;
     if (mine && k < 6 && k < len) {
+        const double *sr = reinterpret_cast<const double *>(&s_sum[wv][3 * r.run_end]);
+        val = sr[k];
         if (kSlots) {
             double *slot = a.tetG + (int64_t)T * 8;
             if (val != 0.0) unsafeAtomicAdd(&slot[k], a.qw * val);

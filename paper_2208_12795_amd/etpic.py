@@ -200,6 +200,37 @@ def _dptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+def _vec(t, n, name, dtype="float64", optional=True):
+    """Device pointer of t after checking that it is a contiguous CUDA tensor
+    of `dtype` holding exactly n elements (the library reads and writes that
+    many through the pointer); None -> NULL when optional (the library then
+    decides whether NULL is allowed).  A mismatch raises EtpicError(EINVAL)
+    before anything is launched."""
+    import torch
+    if t is None:
+        if optional:
+            return None
+        raise EtpicError(EINVAL, f"{name} is required")
+    want = getattr(torch, dtype)
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise EtpicError(EINVAL, f"{name} must be a CUDA tensor")
+    if t.dtype != want:
+        raise EtpicError(EINVAL, f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise EtpicError(EINVAL, f"{name} must be contiguous")
+    if t.numel() != n:
+        raise EtpicError(EINVAL, f"{name} must hold {n} elements, got {t.numel()} (shape {tuple(t.shape)})")
+    return C.c_void_p(t.data_ptr())
+
+
+def _rows3(t, n, name, dtype="float64"):
+    """The three row pointers of a contiguous [3, n] CUDA tensor of `dtype`."""
+    _vec(t, 3 * n, name, dtype, optional=False)
+    if t.dim() != 2 or t.shape[0] != 3:
+        raise EtpicError(EINVAL, f"{name} must have shape [3, {n}], got {tuple(t.shape)}")
+    return (C.c_void_p * 3)(*[t[k].data_ptr() for k in range(3)])
+
+
 def _stream(stream):
     import torch
     s = torch.cuda.current_stream() if stream is None else stream
@@ -427,6 +458,18 @@ class Context:
     def n_face(self):
         return self.counts[2]
 
+    def _dg(self, t, name="dG", optional=True):
+        return _vec(t, self.n_edge, name, optional=optional)
+
+    def _rho(self, t, name="rho"):
+        return _vec(t, self.n_vert, name)
+
+    def _ecplx(self, t, name):
+        return _vec(t, 2 * self.n_edge, name)
+
+    def _fcplx(self, t, name):
+        return _vec(t, 2 * self.n_face, name)
+
     @property
     def n_tet(self):
         return self.counts[3]
@@ -448,7 +491,7 @@ class Context:
         sp = species.c()
         fd = fields.desc()
         _chk(lib().etpic_gather_push_deposit(self._h, C.byref(d), parts.precision, C.byref(sp), C.byref(fd),
-                                             int(step), float(dt), float(omega), _dptr(dG), _dptr(rho),
+                                             int(step), float(dt), float(omega), self._dg(dG), self._rho(rho),
                                              int(flags), _stream(stream)))
 
     def run_steps(self, parts, species, fields, step0, nsteps, dt, omega, dG, rho=None, flags=STEP_XCD_REMAP,
@@ -458,7 +501,7 @@ class Context:
         sp = species.c()
         fd = fields.desc()
         _chk(lib().etpic_run_steps(self._h, C.byref(d), parts.precision, C.byref(sp), C.byref(fd), int(step0),
-                                   int(nsteps), float(dt), float(omega), _dptr(dG), _dptr(rho), int(flags),
+                                   int(nsteps), float(dt), float(omega), self._dg(dG), self._rho(rho), int(flags),
                                    _stream(stream)))
 
     def coarse_step(self, parts, species, snaps, t_coarse, dt_coarse, fine_steps, omega, dG, rho=None,
@@ -471,7 +514,7 @@ class Context:
         sp = species.c()
         arr = (_Fields * 3)(*[f.desc() for f in snaps])
         _chk(lib().etpic_coarse_step(self._h, C.byref(d), parts.precision, C.byref(sp), arr, float(t_coarse),
-                                     float(dt_coarse), int(fine_steps), float(omega), _dptr(dG), _dptr(rho),
+                                     float(dt_coarse), int(fine_steps), float(omega), self._dg(dG), self._rho(rho),
                                      int(flags), _stream(stream)))
 
     def sort(self, src, dst, stream=None):
@@ -487,7 +530,7 @@ class Context:
         sp = species.c()
         fd = fields.desc()
         _chk(lib().etpic_sort_run_steps(self._h, C.byref(a), C.byref(b), src.precision, C.byref(sp), C.byref(fd),
-                                        int(step0), int(nsteps), float(dt), float(omega), _dptr(dG), _dptr(rho),
+                                        int(step0), int(nsteps), float(dt), float(omega), self._dg(dG), self._rho(rho),
                                         int(flags), _stream(stream)))
 
     # downshifted integrator (float64) --------------------------------------------
@@ -514,7 +557,7 @@ class Context:
         fd = fields.desc()
         _chk(lib().etpic_ds_steps(self._h, C.byref(d), parts.precision, C.c_void_p(hist.data_ptr()),
                                   hist.numel() * hist.element_size(), C.byref(sp), C.byref(fd), int(step0),
-                                  int(nsteps), int(hist0), float(dt), float(omega), _dptr(dG), _dptr(rho),
+                                  int(nsteps), int(hist0), float(dt), float(omega), self._dg(dG), self._rho(rho),
                                   int(flags), _stream(stream)))
 
     def ds_sort(self, src, dst, hist_src, hist_dst, stream=None):
@@ -531,10 +574,10 @@ class Context:
         parts.lam (parts.vel is not touched).  hint: int32 [N] start tets or None.
         Returns the status (OK, or EPARTICLE when some points were not located
         and raise_on_error is False; those get tet -1)."""
-        assert xyz.is_contiguous() and xyz.dim() == 2 and xyz.shape[0] == 3 and xyz.shape[1] == parts.n
+        x = _rows3(xyz, parts.n, "xyz")
+        h = _vec(hint, parts.n, "hint", "int32")
         d = parts.desc()
-        x = (C.c_void_p * 3)(*[xyz[k].data_ptr() for k in range(3)])
-        rc = lib().etpic_particles_locate(self._h, C.byref(d), parts.precision, x, _dptr(hint), _stream(stream))
+        rc = lib().etpic_particles_locate(self._h, C.byref(d), parts.precision, x, h, _stream(stream))
         if rc != OK and (raise_on_error or rc != EPARTICLE):
             _chk(rc)
         return rc
@@ -544,20 +587,21 @@ class Context:
         import torch
         if xyz is None:
             xyz = torch.empty((3, parts.n), dtype=torch.float64, device=parts.lam.device)
+        x = _rows3(xyz, parts.n, "xyz")
         d = parts.desc()
-        x = (C.c_void_p * 3)(*[xyz[k].data_ptr() for k in range(3)])
         _chk(lib().etpic_particles_positions(self._h, C.byref(d), parts.precision, x, _stream(stream)))
         return xyz
 
     def vertex_charge(self, parts, species, rho, stream=None):
         d = parts.desc()
         sp = species.c()
-        _chk(lib().etpic_vertex_charge(self._h, C.byref(d), parts.precision, C.byref(sp), _dptr(rho),
+        _chk(lib().etpic_vertex_charge(self._h, C.byref(d), parts.precision, C.byref(sp), self._rho(rho),
                                        _stream(stream)))
 
     def gauss_residual(self, dG, rho_new, rho_old, stream=None):
         out = np.zeros(2)
-        _chk(lib().etpic_gauss_residual(self._h, _dptr(dG), _dptr(rho_new), _dptr(rho_old),
+        _chk(lib().etpic_gauss_residual(self._h, self._dg(dG), self._rho(rho_new, "rho_new"),
+                                        self._rho(rho_old, "rho_old"),
                                         _np_ptr(out, C.c_double), _stream(stream)))
         return float(out[0]), float(out[1])
 
@@ -575,7 +619,8 @@ class Context:
     def gauss_residual_noalloc(self, dG, rho_new, rho_old, stream=None):
         """gauss_residual through the allocation-free entry point."""
         out = np.zeros(2)
-        _chk(lib().etpic_gauss_residual_noalloc(self._h, _dptr(dG), _dptr(rho_new), _dptr(rho_old),
+        _chk(lib().etpic_gauss_residual_noalloc(self._h, self._dg(dG), self._rho(rho_new, "rho_new"),
+                                                self._rho(rho_old, "rho_old"),
                                                 _np_ptr(out, C.c_double), _stream(stream)))
         return float(out[0]), float(out[1])
 
@@ -604,21 +649,20 @@ class Context:
         fd = fields.desc()
         _chk(lib().etpic_forward_checkpointed(self._h, C.byref(d), C.byref(sp), C.byref(fd), int(step0), int(nsteps),
                                               float(dt), float(omega), int(checkpoint_every),
-                                              C.c_void_p(workspace.data_ptr()), workspace.numel(), _dptr(dG),
+                                              C.c_void_p(workspace.data_ptr()), workspace.numel(), self._dg(dG),
                                               _stream(stream)))
 
     def backward(self, n, species, fields, step0, nsteps, dt, omega, checkpoint_every, workspace, vbar, xbar,
                  grad_e, stream=None):
         """vbar, xbar: float64 [3, n] (in: final adjoints, out: initial); grad_e float64 [N_e, 2] accumulates."""
-        for t in (vbar, xbar):
-            assert t.is_contiguous() and t.shape[0] == 3
+        vb = _rows3(vbar, int(n), "vbar")
+        xb = _rows3(xbar, int(n), "xbar")
+        ge = _vec(grad_e, 2 * self.n_edge, "grad_e")
         sp = species.c()
         fd = fields.desc()
-        vb = (C.c_void_p * 3)(*[vbar[k].data_ptr() for k in range(3)])
-        xb = (C.c_void_p * 3)(*[xbar[k].data_ptr() for k in range(3)])
         _chk(lib().etpic_backward(self._h, int(n), C.byref(sp), C.byref(fd), int(step0), int(nsteps), float(dt),
                                   float(omega), int(checkpoint_every), C.c_void_p(workspace.data_ptr()),
-                                  workspace.numel(), vb, xb, _dptr(grad_e), _stream(stream)))
+                                  workspace.numel(), vb, xb, ge, _stream(stream)))
 
     # field update (side path) -------------------------------------------------------
     def field_setup(self, dt, omega, eps, mu):
@@ -634,7 +678,8 @@ class Context:
 
     def field_spmv(self, x, y, alpha, beta, stream=None):
         """y = alpha M x + beta K x; x, y float64 [N_e, 2] (complex)."""
-        _chk(lib().etpic_field_spmv(self._h, _dptr(x), _dptr(y), float(np.real(alpha)), float(np.imag(alpha)),
+        _chk(lib().etpic_field_spmv(self._h, self._ecplx(x, "x"), self._ecplx(y, "y"), float(np.real(alpha)),
+                                    float(np.imag(alpha)),
                                     float(beta), _stream(stream)))
 
     def field_step(self, t_next, u, v, a, b, gdd=None, tol=1e-12, max_iter=500, stream=None, raise_on_error=True):
@@ -642,7 +687,8 @@ class Context:
         returns (status, iterations, relative residual)."""
         it = C.c_int(0)
         res = C.c_double(0.0)
-        rc = lib().etpic_field_step(self._h, float(t_next), _dptr(u), _dptr(v), _dptr(a), _dptr(b), _dptr(gdd),
+        rc = lib().etpic_field_step(self._h, float(t_next), self._ecplx(u, "u"), self._ecplx(v, "v"),
+                                    self._ecplx(a, "a"), self._fcplx(b, "b"), self._dg(gdd, "gdd"),
                                     float(tol), int(max_iter), C.byref(it), C.byref(res), _stream(stream))
         if raise_on_error:
             _chk(rc)
@@ -667,7 +713,8 @@ class Context:
         None.  Returns (status, iterations, relative residual)."""
         it = C.c_int(0)
         res = C.c_double(0.0)
-        rc = lib().etpic_ns_solve(self._h, _dptr(G), _dptr(rho0), float(t), float(omega), _dptr(x_out), _dptr(e_out),
+        rc = lib().etpic_ns_solve(self._h, self._dg(G, "G"), self._rho(rho0, "rho0"), float(t), float(omega),
+                                  _vec(x_out, 2 * self.n_vert, "x_out"), self._ecplx(e_out, "e_out"),
                                   float(tol), int(max_iter), NS_WARM if warm else 0, C.byref(it), C.byref(res),
                                   _stream(stream))
         if raise_on_error:
@@ -687,8 +734,8 @@ class Context:
         it = C.c_int(0)
         rc = lib().etpic_ns_run_steps(self._h, C.byref(d), parts.precision, C.byref(sp),
                                       None if fd is None else C.byref(fd), int(step0), int(nsteps),
-                                      int(steps_per_solve), float(dt), float(omega), _dptr(G), _dptr(rho0),
-                                      _dptr(e_work), float(tol), int(max_iter), int(flags) | (NS_WARM if warm else 0),
+                                      int(steps_per_solve), float(dt), float(omega), self._dg(G, "G"),
+                                      self._rho(rho0, "rho0"), self._dg(e_work, "e_work"), float(tol), int(max_iter), int(flags) | (NS_WARM if warm else 0),
                                       C.byref(it), _stream(stream))
         _chk(rc)
         return it.value
@@ -698,7 +745,8 @@ class Context:
         """e_out = u + D y with Gauss' law exact for e_out (u, e_out float64
         [N_e, 2] complex); returns (status, iterations, residual)."""
         it, res = C.c_int(0), C.c_double(0.0)
-        rc = lib().etpic_ns_correct(self._h, _dptr(G), _dptr(rho0), float(t), float(omega), _dptr(u), _dptr(e_out),
+        rc = lib().etpic_ns_correct(self._h, self._dg(G, "G"), self._rho(rho0, "rho0"), float(t), float(omega),
+                                    self._ecplx(u, "u"), self._ecplx(e_out, "e_out"),
                                     float(tol), int(max_iter), NS_WARM if warm else 0, C.byref(it), C.byref(res),
                                     _stream(stream))
         if raise_on_error:
@@ -710,7 +758,8 @@ class Context:
         in the [*eps] inner product (float64 [N_e] device tensors; gs_out may be
         gdd); returns (status, iterations, residual)."""
         it, res = C.c_int(0), C.c_double(0.0)
-        rc = lib().etpic_sol_source(self._h, _dptr(gdd), _dptr(gs_out), float(tol), int(max_iter),
+        rc = lib().etpic_sol_source(self._h, self._dg(gdd, "gdd"), self._dg(gs_out, "gs_out"), float(tol),
+                                    int(max_iter),
                                     NS_WARM if warm else 0, C.byref(it), C.byref(res), _stream(stream))
         if raise_on_error:
             _chk(rc)
@@ -727,8 +776,10 @@ class Context:
         it = C.c_int(0)
         fl = int(flags) | (NS_WARM if warm else 0) | (EM_SPLIT if split else 0)
         _chk(lib().etpic_em_steps(self._h, C.byref(d), parts.precision, C.byref(sp), int(step0), int(nsteps),
-                                  _dptr(u), _dptr(v), _dptr(a), _dptr(b), _dptr(e), _dptr(G), _dptr(G_hist),
-                                  _dptr(rho0), float(tol), int(max_iter), fl, C.byref(it), _stream(stream)))
+                                  self._ecplx(u, "u"), self._ecplx(v, "v"), self._ecplx(a, "a"),
+                                  self._fcplx(b, "b"), self._ecplx(e, "e"), self._dg(G, "G"),
+                                  _vec(G_hist, 2 * self.n_edge, "G_hist"), self._rho(rho0, "rho0"), float(tol),
+                                  int(max_iter), fl, C.byref(it), _stream(stream)))
         return it.value
 
     # checkpoint / resume of the particle state --------------------------------
@@ -805,14 +856,25 @@ class CotreeSystem:
         except Exception:
             pass
 
+    def _dims(self, block):
+        """(input, output) lengths of block, or None for a number that is not a block"""
+        e, f, z = self.n_cotree_edge, self.n_cotree_face, self.n_inner_node
+        return {11: (f, f), 12: (e, f), 13: (z, f), 21: (e, e), 22: (f, e), 23: (z, e)}.get(int(block))
+
     def apply(self, block, x, y, tol=1e-13, max_iter=20000, stream=None):
         """y = Z_block x, block in 11, 12, 13, 21, 22, 23."""
-        _qchk(lib().etpic_cotree_apply(self._h, self.qh._h, int(block), _dptr(x), _dptr(y), float(tol),
+        dims = self._dims(block)
+        if dims is None:   # the library reports the bad block number
+            xp, yp = _dptr(x), _dptr(y)
+        else:
+            xp, yp = _vec(x, 2 * dims[0], "x", optional=False), _vec(y, 2 * dims[1], "y", optional=False)
+        _qchk(lib().etpic_cotree_apply(self._h, self.qh._h, int(block), xp, yp, float(tol),
                                        int(max_iter), _stream(stream)))
 
     def b_field(self, bs, b_out, tol=1e-13, max_iter=20000, stream=None):
         """b_out = P^Lambda_b C_b bs."""
-        _qchk(lib().etpic_cotree_b_field(self._h, self.qh._h, _dptr(bs), _dptr(b_out), float(tol), int(max_iter),
+        _qchk(lib().etpic_cotree_b_field(self._h, self.qh._h, _vec(bs, 2 * self.n_cotree_face, "bs"),
+                                         _vec(b_out, 2 * self.qh.n_face, "b_out"), float(tol), int(max_iter),
                                          _stream(stream)))
 
     def step(self, dt, omega, b, es, src=None, tol=1e-11, max_iter=5000, inner_tol=1e-13, inner_max=20000,
@@ -820,7 +882,9 @@ class CotreeSystem:
         """One trapezoidal step of eq. sol_disc on (b, es) in place;
         returns (status, GMRES iterations, relative residual)."""
         it, res = C.c_int(0), C.c_double(0.0)
-        rc = lib().etpic_cotree_step(self._h, self.qh._h, float(dt), float(omega), _dptr(b), _dptr(es), _dptr(src),
+        ne = 2 * self.n_cotree_edge
+        rc = lib().etpic_cotree_step(self._h, self.qh._h, float(dt), float(omega),
+                                     _vec(b, 2 * self.qh.n_face, "b"), _vec(es, ne, "es"), _vec(src, ne, "src"),
                                      float(tol), int(max_iter), float(inner_tol), int(inner_max), C.byref(it),
                                      C.byref(res), _stream(stream))
         if raise_on_error:
@@ -861,8 +925,9 @@ class QhProjectors:
     def project_b(self, b, b_out, tol=1e-12, max_iter=5000, stream=None, raise_on_error=True):
         """b_out = P^Lambda_b b; returns (status, iterations, relative residual)."""
         it, res = C.c_int(0), C.c_double(0.0)
-        rc = lib().etpic_qh_project_b(self._h, _dptr(b), _dptr(b_out), float(tol), int(max_iter), C.byref(it),
-                                      C.byref(res), _stream(stream))
+        nf = 2 * self.n_face
+        rc = lib().etpic_qh_project_b(self._h, _vec(b, nf, "b"), _vec(b_out, nf, "b_out"), float(tol), int(max_iter),
+                                      C.byref(it), C.byref(res), _stream(stream))
         if raise_on_error:
             _qchk(rc)
         return rc, it.value, res.value
@@ -872,7 +937,9 @@ class QhProjectors:
         """d_sigma = P^Sigma_e d, d_lambda = P^Lambda_e d, e_ns = (Sigma^T Sigma)^+ Sigma^T d;
         returns (status, iterations, relative residual)."""
         it, res = C.c_int(0), C.c_double(0.0)
-        rc = lib().etpic_qh_project_e(self._h, _dptr(d), _dptr(d_sigma), _dptr(d_lambda), _dptr(e_ns), float(tol),
+        ne = 2 * self.n_edge
+        rc = lib().etpic_qh_project_e(self._h, _vec(d, ne, "d"), _vec(d_sigma, ne, "d_sigma"),
+                                      _vec(d_lambda, ne, "d_lambda"), _vec(e_ns, 2 * self.n_vert, "e_ns"), float(tol),
                                       int(max_iter), C.byref(it), C.byref(res), _stream(stream))
         if raise_on_error:
             _qchk(rc)

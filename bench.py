@@ -87,6 +87,12 @@ TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_push_hbm_traffic_40cube_1e7.
 TRAFFIC_SUMMARY_LARGE = os.path.join(ROOT, "profiles", "k_push_hbm_traffic_large_box_2e8.md")
 VALU_SUMMARY = os.path.join(ROOT, "profiles", "k_push_valu_issue_40cube_1e7.md")
 VALU_SUMMARY_LARGE = os.path.join(ROOT, "profiles", "k_push_valu_issue_large_box_2e8.md")
+TRAFFIC_SUMMARY_PRECISION = os.path.join(ROOT, "profiles", "k_push_hbm_traffic_40cube_5e7.md")
+VALU_SUMMARY_PRECISION = os.path.join(ROOT, "profiles", "k_push_valu_issue_40cube_5e7.md")
+# counter summaries (HBM traffic, VALU issue) of each workload's particle kernels
+PROFILE_SUMMARIES = {"40cube": (TRAFFIC_SUMMARY, VALU_SUMMARY),
+                     "precision": (TRAFFIC_SUMMARY_PRECISION, VALU_SUMMARY_PRECISION),
+                     "large-box": (TRAFFIC_SUMMARY_LARGE, VALU_SUMMARY_LARGE)}
 COPY_CALIB_BYTES = 1 << 30
 SPIN_UP_MS = 50.0
 CPU_SAMPLE_MAX = 10_000_000
@@ -754,8 +760,7 @@ def config_entry(E, torch, synth, key, steps, warmup, sort_every, nlog, copy_gbs
                      "dtype": FORM_DTYPE[form],
                      "gauss_rel": r["gauss_rel"], "logged": r["logged"],
                      "roofline": roofline(res, form, n_p, n_t, n_e, sort_every, copy_gbs,
-                                          TRAFFIC_SUMMARY_LARGE if key == "large-box" else None,
-                                          VALU_SUMMARY_LARGE if key == "large-box" else None)}
+                                          *PROFILE_SUMMARIES.get(key, (None, None)))}
     for form in ("mixed", "mixed_fixed"):
         if "fp64" in res and form in res:
             out[form]["speedup_vs_fp64"] = res[form]["value"] / res["fp64"]["value"]
@@ -841,8 +846,8 @@ def main():
                              nlog=args.log_steps)
         log(f"[bench] {form}: {json.dumps(res[form])}")
     n_p, n_t, n_e = w.tet.shape[0], w.tet_vert.shape[0], ctx.n_edge
-    traffic_path = TRAFFIC_SUMMARY if (args.particles is None and args.workload == "40cube") else None
-    valu_path = VALU_SUMMARY if (args.particles is None and args.workload == "40cube") else None
+    traffic_path, valu_path = (PROFILE_SUMMARIES.get(args.workload, (None, None)) if args.particles is None
+                               else (None, None))
 
     main_form = "fp64" if "fp64" in res else next(iter(res))
     r = res[main_form]

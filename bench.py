@@ -61,7 +61,11 @@ VALU_PEAK_PER_S = 256 * 4 * 2.4e9 / 4
 #                     edge ids (6 x 4 B), read once: 288 B (float64), 156 B (mixed)
 #  per edge and step: the current accumulator read + written once (16 B)
 BYTES_PER_PARTICLE = {"fp64": 100, "mixed": 76, "mixed_fixed": 52}
-BYTES_PER_TET = {"fp64": 288, "mixed": 156, "mixed_fixed": 156}
+# per tet and launch: the step's coefficient row (A_0, beta, C_0, b: 10 reals),
+# the gradient row (grad l_1..3: 9 reals), the six edge ids (24 B) and the
+# geometry row (r_k - r_0, k = 1..3: 9 reals); reals float64, or float32 in
+# both mixed forms
+BYTES_PER_TET = {"fp64": 248, "mixed": 136, "mixed_fixed": 136}
 BYTES_PER_EDGE = 16
 KERNEL_NAME = {"fp64": "k_push<double>", "mixed": "k_push<float>", "mixed_fixed": "k_push_fixed"}
 # Algorithmic bytes of a whole step (what the method must move per particle-step

@@ -244,6 +244,37 @@ struct PushRow<float> {
     static constexpr int kEdges = 10;
 };
 
+// The particle step's per-step coefficient row.  Inside a tet a Whitney edge
+// field is E(x) = A_0 + beta x (x - r_0) (its Jacobian is antisymmetric,
+// beta = sum over edges (i<j) of eps_ij grad l_i x grad l_j, half its curl) and
+// a Whitney face field is B(x) = C_0 + b (x - r_0) (its Jacobian is b times
+// the identity, b = div B / 3 = (sum_k C_k . grad l_k) / 3): A_0 (3), beta (3),
+// C_0 (3), b, with x - r_0 = sum_{k>0} l_k (r_k - r_0) from the static
+// geometry row.  10 reals; float rows are padded to 12 (16-byte aligned).
+template <typename Real>
+struct CoefRow;
+template <>
+struct CoefRow<double> {
+    static constexpr int kStride = 10;
+};
+template <>
+struct CoefRow<float> {
+    static constexpr int kStride = 12;
+};
+
+// Static per-tet geometry row: the edge vectors r_1 - r_0, r_2 - r_0, r_3 - r_0
+// of the canonical vertex order (9 reals, padded to 16-byte rows).
+template <typename Real>
+struct GeoRow;
+template <>
+struct GeoRow<double> {
+    static constexpr int kStride = 10;
+};
+template <>
+struct GeoRow<float> {
+    static constexpr int kStride = 12;
+};
+
 // The coefficient pass reads the float64 push row (grad l_1..3 and the edge ids;
 // grad l_0 = -(grad l_1 + grad l_2 + grad l_3), the sum the mesh tables define it
 // by) and the four face ids of the tet: 112 B per tet.
@@ -259,7 +290,7 @@ __device__ __forceinline__ unsigned xcd_block(unsigned c, unsigned G) {
     return x * q + min(x, r) + j;
 }
 
-template <typename Real, int kSnap>
+template <typename Real, int kSnap, bool kCompact = false>
 __device__ __forceinline__ void tet_coef(int64_t nt, const double *__restrict__ prow,
                                          const int32_t *__restrict__ tetface, const FieldPtrs &F,
                                          Real *__restrict__ coef, unsigned blk) {
@@ -271,9 +302,13 @@ __device__ __forceinline__ void tet_coef(int64_t nt, const double *__restrict__ 
     // 96-byte row and writing its own 96- or 48-byte half row strides every
     // load and store instruction over 64 rows.)  Row strides in LDS are odd
     // numbers of reals, so that the lanes' rows start in different banks.
+    // kCompact: the particle step's 10-real row (CoefRow: A_0 and beta from the
+    // edge lanes, C_0 and b from the face lanes) instead of A_0..3, C_0..3.
     constexpr int kTets = kBlock / 2;
     constexpr int kRow = PushRow<double>::kStride + 1;   // staged push row, doubles
-    constexpr int kOut = 25;                             // staged coefficient row, Reals
+    constexpr int kOut = kCompact ? 11 : 25;             // staged coefficient row, Reals
+    constexpr int kPart0 = kCompact ? 6 : 12, kPart1 = kCompact ? 4 : 12;   // reals from each half
+    constexpr int kOutRow = kCompact ? CoefRow<Real>::kStride : 24;       // row in memory, Reals
     constexpr int kIn = kTets * kRow + kTets * 4 / 2;    // rows + face ids, in doubles
     constexpr int kOutD = (kTets * kOut * (int)sizeof(Real) + 7) / 8;
     __shared__ double lds[kIn > kOutD ? kIn : kOutD];
@@ -329,6 +364,24 @@ __device__ __forceinline__ void tet_coef(int64_t nt, const double *__restrict__ 
             if (F.e_dc)
 #pragma unroll
                 for (int k = 0; k < 6; ++k) ev[k] += F.e_dc[tp[k]];
+            if (kCompact) {
+                // A_0 = E(r_0) = sum_j eps_0j grad l_j; beta = sum_(i<j) eps_ij grad l_i x grad l_j
+#pragma unroll
+                for (int d = 0; d < 6; ++d) o[d] = 0.0;
+#pragma unroll
+                for (int j = 1; j < 4; ++j)
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) o[d] += ev[local_edge(0, j)] * g[j][d];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = i + 1; j < 4; ++j) {
+                        const double e = ev[local_edge(i, j)];
+                        o[3] += e * (g[i][1] * g[j][2] - g[i][2] * g[j][1]);
+                        o[4] += e * (g[i][2] * g[j][0] - g[i][0] * g[j][2]);
+                        o[5] += e * (g[i][0] * g[j][1] - g[i][1] * g[j][0]);
+                    }
+            } else
 #pragma unroll
             for (int K = 0; K < 4; ++K) {
                 double *A = o + 3 * K;
@@ -368,26 +421,43 @@ __device__ __forceinline__ void tet_coef(int64_t nt, const double *__restrict__ 
                     Cv[2] += beta * (g[a][0] * g[b][1] - g[a][1] * g[b][0]);
                 }
             }
+            if (kCompact) {
+                // C_0 stays in o[0..2]; b = (sum_k C_k . grad l_k) / 3
+                double dv = 0.0;
+#pragma unroll
+                for (int K = 0; K < 4; ++K)
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) dv += o[3 * K + d] * g[K][d];
+                o[3] = dv * (1.0 / 3.0);
+            }
         }
     }
     __syncthreads();   // every staged row read: the space takes the output
     Real *sout = reinterpret_cast<Real *>(lds);
-    if (t < nloc)
+    if (t < nloc) {
+        // full rows: A_k at 3k, C_k at 12 + 3k; compact rows: A_0, beta, C_0, b
+        if (part == 0) {
 #pragma unroll
-        for (int d = 0; d < 12; ++d) sout[t * kOut + 12 * part + d] = (Real)o[d];   // A_k at 3k, C_k at 12 + 3k
+            for (int d = 0; d < kPart0; ++d) sout[t * kOut + d] = (Real)o[d];
+        } else {
+#pragma unroll
+            for (int d = 0; d < kPart1; ++d) sout[t * kOut + kPart0 + d] = (Real)o[d];
+        }
+    }
     __syncthreads();
-    Real *dst = coef + T0 * 24;
-    for (int i = threadIdx.x; i < nloc * 24; i += kBlock) {
-        const int tt = i / 24;
-        dst[i] = sout[tt * kOut + (i - tt * 24)];
+    Real *dst = coef + T0 * kOutRow;
+    for (int i = threadIdx.x; i < nloc * kOutRow; i += kBlock) {
+        const int tt = i / kOutRow, c = i - tt * kOutRow;
+        dst[i] = c < kPart0 + kPart1 ? sout[tt * kOut + c] : (Real)0;
     }
 }
 
-template <typename Real, int kSnap = 1>
+template <typename Real, int kSnap = 1, bool kCompact = false>
 __global__ void __launch_bounds__(kBlock) k_tet_coef(int64_t nt, const double *__restrict__ prow,
                                                      const int32_t *__restrict__ tetface, FieldPtrs F,
                                                      Real *__restrict__ coef) {
-    tet_coef<Real, kSnap>(nt, prow, tetface, F, coef, F.xcd ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x);
+    tet_coef<Real, kSnap, kCompact>(nt, prow, tetface, F, coef,
+                                    F.xcd ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x);
 }
 
 // ------------------------------------------------------------------ particle step
@@ -402,8 +472,9 @@ struct StepArgs {
     double *lam1, *lam2, *lam3;
     Real *v0, *v1, *v2;
     int32_t *tet;
-    const Real *coef;          // nt*24: A_0..3, C_0..3 of this step (k_tet_coef)
+    const Real *coef;          // nt rows of CoefRow<Real>: A_0, beta, C_0, b of this step (k_tet_coef)
     const Real *gpush;         // nt rows of PushRow<Real>::kStride: grad l_1..3, then the 6 edge ids
+    const Real *geo;           // nt rows of GeoRow<Real>: r_1 - r_0, r_2 - r_0, r_3 - r_0
     const double *grad;        // nt*12 float64 barycentric gradients grad l_0..3
     const TetTopo *topo;
     double *dG;
@@ -869,13 +940,19 @@ __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) 
             l[3] = sl3;
             l[0] = 1.0 - l[1] - l[2] - l[3];
             Real v[3] = {sv0, sv1, sv2};
-            const Real *cf = a.coef + (int64_t)T * 24;
-            Real E[3], B[3];
+            // E = A_0 + beta x u, B = C_0 + b u at u = x - r_0 = sum_{k>0} l_k (r_k - r_0)
+            const Real *cf = a.coef + (int64_t)T * CoefRow<Real>::kStride;
+            const Real *gm = a.geo + (int64_t)T * GeoRow<Real>::kStride;
+            const Real x1 = (Real)l[1], x2 = (Real)l[2], x3 = (Real)l[3];
+            Real u[3];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                E[d] = (Real)l[0] * cf[d] + (Real)l[1] * cf[3 + d] + (Real)l[2] * cf[6 + d] + (Real)l[3] * cf[9 + d];
-                B[d] = (Real)l[0] * cf[12 + d] + (Real)l[1] * cf[15 + d] + (Real)l[2] * cf[18 + d] + (Real)l[3] * cf[21 + d];
-            }
+            for (int d = 0; d < 3; ++d) u[d] = x1 * gm[d] + x2 * gm[3 + d] + x3 * gm[6 + d];
+            Real E[3], B[3];
+            E[0] = cf[0] + (cf[4] * u[2] - cf[5] * u[1]);
+            E[1] = cf[1] + (cf[5] * u[0] - cf[3] * u[2]);
+            E[2] = cf[2] + (cf[3] * u[1] - cf[4] * u[0]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) B[d] = cf[6 + d] + cf[9] * u[d];
             // Boris: half kick, rotation (implicit midpoint in v x B), half kick
             const Real h = a.h;
             Real vm[3], tau[3];
@@ -1251,7 +1328,7 @@ __global__ void __launch_bounds__(kBlock) k_walk_coef(StepArgs<Real> a, int64_t 
     if (blockIdx.x < kWalkBlocks)
         walk_queued(a, blockIdx.x, kWalkBlocks, [&](int64_t p) { walk_particle(a, p); });
     else
-        tet_coef<Real, kSnap>(nt, a.gpush64, a.tetface, F, const_cast<Real *>(a.coef),
+        tet_coef<Real, kSnap, true>(nt, a.gpush64, a.tetface, F, const_cast<Real *>(a.coef),
                               F.xcd ? xcd_block(blockIdx.x - kWalkBlocks, gridDim.x - kWalkBlocks)
                                     : blockIdx.x - kWalkBlocks);
 }
@@ -2951,8 +3028,10 @@ struct etpic_ctx {
     double *d_grad64 = nullptr;
     double *d_gpush64 = nullptr;     // nt rows of PushRow<double>
     float *d_gpush32 = nullptr;       // nt rows of PushRow<float>
+    double *d_geo64 = nullptr;        // nt rows of GeoRow<double>
+    float *d_geo32 = nullptr;         // nt rows of GeoRow<float>
     int32_t *d_tetface = nullptr;     // nt*4 face ids (face k opposite vertex k)
-    void *d_coef = nullptr;          // nt*24 doubles (float table uses the first half)
+    void *d_coef = nullptr;          // nt*24 doubles: the step's CoefRow rows, or A_0..3, C_0..3 for the adjoint
     double *d_coef_env = nullptr;    // nt*kEnvRow complex-envelope rows (bound by etpic_ds_rows_bind)
     int32_t *d_v2e_ptr = nullptr;
     int32_t *d_v2e_code = nullptr;
@@ -3041,6 +3120,7 @@ struct etpic_ctx {
         a.tet = p->tet;
         a.coef = static_cast<const Real *>(d_coef);
         a.gpush = gpush_table<Real>();
+        a.geo = geo_table<Real>();
         a.grad = d_grad64;
         a.topo = d_topo;
         a.dG = dG;
@@ -3078,9 +3158,9 @@ struct etpic_ctx {
         hipEvent_t e0 = ev_start(ts, 0), e1 = ev_stop(ts, 0);
         Real *coef = static_cast<Real *>(d_coef);
         if (plan.snap[1])
-            launch_timed(k_tet_coef<Real, 3>, grid_for(2 * nt), s, e0, e1, nt, d_gpush64, d_tetface, F, coef);
+            launch_timed(k_tet_coef<Real, 3, true>, grid_for(2 * nt), s, e0, e1, nt, d_gpush64, d_tetface, F, coef);
         else
-            launch_timed(k_tet_coef<Real, 1>, grid_for(2 * nt), s, e0, e1, nt, d_gpush64, d_tetface, F, coef);
+            launch_timed(k_tet_coef<Real, 1, true>, grid_for(2 * nt), s, e0, e1, nt, d_gpush64, d_tetface, F, coef);
         HIP_TRY(hipGetLastError());
         return ETPIC_OK;
     }
@@ -3272,6 +3352,8 @@ struct etpic_ctx {
 
     template <typename Real>
     const Real *gpush_table() const;
+    template <typename Real>
+    const Real *geo_table() const;
 
     // Slices per wavefront of the particle kernel: forced by a flag, else from
     // the mean same-tet run length of the last sort (one slice while runs fit
@@ -3452,6 +3534,8 @@ struct etpic_ctx {
         d_grad64 = nullptr;
         d_gpush64 = nullptr;
         d_gpush32 = nullptr;
+        d_geo64 = nullptr;
+        d_geo32 = nullptr;
         d_tetface = nullptr;
         d_coef = nullptr;
         d_coef_env = nullptr;
@@ -3505,6 +3589,10 @@ template <>
 const double *etpic_ctx::gpush_table<double>() const { return d_gpush64; }
 template <>
 const float *etpic_ctx::gpush_table<float>() const { return d_gpush32; }
+template <>
+const double *etpic_ctx::geo_table<double>() const { return d_geo64; }
+template <>
+const float *etpic_ctx::geo_table<float>() const { return d_geo32; }
 
 namespace {
 
@@ -3701,13 +3789,14 @@ int check_buffer(const void *buf, size_t bytes, size_t need, const char *what) {
 }
 
 // Mesh tables, in this order: tet topology, float64 gradients, float64 and
-// float32 push rows, tet-face ids, the coefficient table, vertex coordinates,
+// float32 push rows, float64 and float32 geometry rows, tet-face ids, the
+// coefficient table, vertex coordinates,
 // point-location start grid, vertex -> edge CSR, sort counters and tile sums,
 // edge -> tet-slot CSR, two per-tet current slot buffers.
 struct MeshPtrs {
     TetTopo *topo;
-    double *grad64, *gpush64;
-    float *gpush32;
+    double *grad64, *gpush64, *geo64;
+    float *gpush32, *geo32;
     int32_t *tetface;
     void *coef;
     double *xyz;
@@ -3723,6 +3812,8 @@ MeshPtrs mesh_layout(Carve &cv, const etpic::HostMesh &M, size_t grid_cells) {
     m.grad64 = cv.take<double>(12 * nt);
     m.gpush64 = cv.take<double>((size_t)PushRow<double>::kStride * nt);
     m.gpush32 = cv.take<float>((size_t)PushRow<float>::kStride * nt);
+    m.geo64 = cv.take<double>((size_t)GeoRow<double>::kStride * nt);
+    m.geo32 = cv.take<float>((size_t)GeoRow<float>::kStride * nt);
     m.tetface = cv.take<int32_t>(4 * nt);
     m.coef = cv.take<double>(24 * nt);
     m.xyz = cv.take<double>(3 * M.nv);
@@ -3827,6 +3918,8 @@ int etpic_mesh_upload(etpic_ctx *ctx, int64_t n_vert, const double *xyz_host, in
     ctx->d_grad64 = m.grad64;
     ctx->d_gpush64 = m.gpush64;
     ctx->d_gpush32 = m.gpush32;
+    ctx->d_geo64 = m.geo64;
+    ctx->d_geo32 = m.geo32;
     ctx->d_tetface = m.tetface;
     ctx->d_coef = m.coef;
     ctx->d_xyz = m.xyz;
@@ -3858,6 +3951,21 @@ int etpic_mesh_upload(etpic_ctx *ctx, int64_t n_vert, const double *xyz_host, in
         HIP_TRY(hipMemcpy(ctx->d_gpush64, gp64.data(), sizeof(double) * s64 * nt, hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(ctx->d_gpush32, gp32.data(), sizeof(float) * s32 * nt, hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(ctx->d_tetface, tf.data(), sizeof(int32_t) * 4 * nt, hipMemcpyHostToDevice));
+        // geometry rows: the edge vectors from local vertex 0 (canonical order)
+        constexpr int g64 = GeoRow<double>::kStride, g32 = GeoRow<float>::kStride;
+        std::vector<double> ge64((size_t)nt * g64, 0.0);
+        std::vector<float> ge32((size_t)nt * g32, 0.0f);
+        for (int64_t t = 0; t < nt; ++t) {
+            const int64_t v0 = M.topo[t].v[0];
+            for (int k = 1; k < 4; ++k)
+                for (int c = 0; c < 3; ++c) {
+                    const double d = xyz_host[3 * (int64_t)M.topo[t].v[k] + c] - xyz_host[3 * v0 + c];
+                    ge64[g64 * t + 3 * (k - 1) + c] = d;
+                    ge32[g32 * t + 3 * (k - 1) + c] = (float)d;
+                }
+        }
+        HIP_TRY(hipMemcpy(ctx->d_geo64, ge64.data(), sizeof(double) * g64 * nt, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(ctx->d_geo32, ge32.data(), sizeof(float) * g32 * nt, hipMemcpyHostToDevice));
     }
     HIP_TRY(hipMemcpy(ctx->d_xyz, xyz_host, sizeof(double) * 3 * M.nv, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(ctx->d_grid, sg.cell.data(), sizeof(int32_t) * sg.cell.size(), hipMemcpyHostToDevice));

@@ -204,7 +204,7 @@ int etpic_mesh_sizes(int64_t n_vert, const double *xyz_host, int64_t n_tet, cons
  * tet_vert_host[4*n_tet] ascending per row.  Builds the canonical
  * edges/faces, tet->edge/face/neighbour tables and the barycentric gradients
  * on the host and fills the device tables in dev_buf (synchronously): topology,
- * gradient and push rows, the per-step coefficient table, point-location
+ * gradient, push and geometry rows, the per-step coefficient table, point-location
  * grid, incidences, sort counters and the per-tet current slots.  Replaces any
  * previous mesh (and forgets its field, Gauss-law and downshifted buffers).
  * Errors: EINVAL (bad input, short buffer), EMESH, EHIP. */

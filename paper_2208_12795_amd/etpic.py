@@ -355,9 +355,24 @@ class Particles:
                 None if self.ids is None else self.ids.cpu().numpy())
 
     def desc(self):
-        for t in (self.lam, self.vel):
-            assert t.is_contiguous() and t.dim() == 2 and t.shape[0] == 3
-        assert self.tet.is_contiguous() and self.tet.dtype.itemsize == 4
+        """The C descriptor, after checking every array (CUDA memory, dtype,
+        contiguity, [3, N] / [N] shapes, one device; EtpicError EINVAL)."""
+        import torch
+        n = self.n
+        if self.lam.dtype == torch.int32:
+            lam_dt, vel_dts = "int32", ("float32",)
+        else:
+            lam_dt, vel_dts = "float64", ("float64", "float32")
+        _rows3(self.lam, n, "lam", lam_dt)
+        vdt = str(self.vel.dtype).replace("torch.", "")
+        if vdt not in vel_dts:
+            raise EtpicError(EINVAL, f"vel must be {' or '.join(vel_dts)} with {lam_dt} lam, got {vdt}")
+        _rows3(self.vel, n, "vel", vdt)
+        _vec(self.tet, n, "tet", "int32", optional=False)
+        _vec(self.ids, n, "ids", "int64")
+        devs = {t.device for t in (self.lam, self.vel, self.tet, self.ids) if t is not None}
+        if len(devs) != 1:
+            raise EtpicError(EINVAL, f"particle arrays on several devices: {sorted(map(str, devs))}")
         d = _Particles()
         d.n = self.n
         for k in range(3):
@@ -387,9 +402,18 @@ class Fields:
             return None if x is None else torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to(device)
         return cls(cplx(e_env), cplx(b_env), real(e_dc), real(b_dc))
 
-    def desc(self):
+    def desc(self, n_edge=None, n_face=None):
+        """The C descriptor; with the mesh's edge and face counts, after
+        checking every array against them (EtpicError EINVAL)."""
+        if n_edge is not None:
+            _vec(self.e_env, 2 * n_edge, "e_env", optional=False)
+            _vec(self.e_dc, n_edge, "e_dc")
+        if n_face is not None:
+            _vec(self.b_env, 2 * n_face, "b_env", optional=False)
+            _vec(self.b_dc, n_face, "b_dc")
         for t in (self.e_env, self.b_env, self.e_dc, self.b_dc):
-            assert t is None or t.is_contiguous()
+            if t is not None and not t.is_contiguous():
+                raise EtpicError(EINVAL, "field arrays must be contiguous")
         return _Fields(self.e_env.data_ptr(), None if self.e_dc is None else self.e_dc.data_ptr(),
                        self.b_env.data_ptr(), None if self.b_dc is None else self.b_dc.data_ptr())
 
@@ -489,7 +513,7 @@ class Context:
                             stream=None):
         d = parts.desc()
         sp = species.c()
-        fd = fields.desc()
+        fd = fields.desc(self.n_edge, self.n_face)
         _chk(lib().etpic_gather_push_deposit(self._h, C.byref(d), parts.precision, C.byref(sp), C.byref(fd),
                                              int(step), float(dt), float(omega), self._dg(dG), self._rho(rho),
                                              int(flags), _stream(stream)))
@@ -499,7 +523,7 @@ class Context:
         """nsteps steps from step0 with fixed fields (rho after the last step)."""
         d = parts.desc()
         sp = species.c()
-        fd = fields.desc()
+        fd = fields.desc(self.n_edge, self.n_face)
         _chk(lib().etpic_run_steps(self._h, C.byref(d), parts.precision, C.byref(sp), C.byref(fd), int(step0),
                                    int(nsteps), float(dt), float(omega), self._dg(dG), self._rho(rho), int(flags),
                                    _stream(stream)))
@@ -512,7 +536,7 @@ class Context:
         assert len(snaps) == 3
         d = parts.desc()
         sp = species.c()
-        arr = (_Fields * 3)(*[f.desc() for f in snaps])
+        arr = (_Fields * 3)(*[f.desc(self.n_edge, self.n_face) for f in snaps])
         _chk(lib().etpic_coarse_step(self._h, C.byref(d), parts.precision, C.byref(sp), arr, float(t_coarse),
                                      float(dt_coarse), int(fine_steps), float(omega), self._dg(dG), self._rho(rho),
                                      int(flags), _stream(stream)))
@@ -528,7 +552,7 @@ class Context:
         assert src.precision == dst.precision
         a, b = src.desc(), dst.desc()
         sp = species.c()
-        fd = fields.desc()
+        fd = fields.desc(self.n_edge, self.n_face)
         _chk(lib().etpic_sort_run_steps(self._h, C.byref(a), C.byref(b), src.precision, C.byref(sp), C.byref(fd),
                                         int(step0), int(nsteps), float(dt), float(omega), self._dg(dG), self._rho(rho),
                                         int(flags), _stream(stream)))
@@ -554,7 +578,7 @@ class Context:
             self._ds_rows = buf
         d = parts.desc()
         sp = species.c()
-        fd = fields.desc()
+        fd = fields.desc(self.n_edge, self.n_face)
         _chk(lib().etpic_ds_steps(self._h, C.byref(d), parts.precision, C.c_void_p(hist.data_ptr()),
                                   hist.numel() * hist.element_size(), C.byref(sp), C.byref(fd), int(step0),
                                   int(nsteps), int(hist0), float(dt), float(omega), self._dg(dG), self._rho(rho),
@@ -646,7 +670,7 @@ class Context:
                              dG=None, stream=None):
         d = parts.desc()
         sp = species.c()
-        fd = fields.desc()
+        fd = fields.desc(self.n_edge, self.n_face)
         _chk(lib().etpic_forward_checkpointed(self._h, C.byref(d), C.byref(sp), C.byref(fd), int(step0), int(nsteps),
                                               float(dt), float(omega), int(checkpoint_every),
                                               C.c_void_p(workspace.data_ptr()), workspace.numel(), self._dg(dG),
@@ -659,7 +683,7 @@ class Context:
         xb = _rows3(xbar, int(n), "xbar")
         ge = _vec(grad_e, 2 * self.n_edge, "grad_e")
         sp = species.c()
-        fd = fields.desc()
+        fd = fields.desc(self.n_edge, self.n_face)
         _chk(lib().etpic_backward(self._h, int(n), C.byref(sp), C.byref(fd), int(step0), int(nsteps), float(dt),
                                   float(omega), int(checkpoint_every), C.c_void_p(workspace.data_ptr()),
                                   workspace.numel(), vb, xb, ge, _stream(stream)))
@@ -730,7 +754,7 @@ class Context:
         Returns the CG iterations summed over the solves."""
         d = parts.desc()
         sp = species.c()
-        fd = None if ext is None else ext.desc()
+        fd = None if ext is None else ext.desc(self.n_edge, self.n_face)
         it = C.c_int(0)
         rc = lib().etpic_ns_run_steps(self._h, C.byref(d), parts.precision, C.byref(sp),
                                       None if fd is None else C.byref(fd), int(step0), int(nsteps),

@@ -106,3 +106,28 @@ def test_projector_and_cotree_vectors(E, torch_cuda):
     finally:
         Z.close()
         Q.close()
+
+
+def test_particle_and_field_arrays(E, torch_cuda, setup):
+    """Particle arrays of the wrong length, dtype or shape, and field arrays
+    that do not match the mesh, are refused before any launch."""
+    torch = torch_cuda
+    w, ctx, f, sp = setup
+    good = E.Particles.from_numpy(w.tet, w.lam, w.vel)
+    dG = torch.zeros(ctx.n_edge, dtype=torch.float64, device="cuda")
+    n = good.n
+    bad = {
+        "vel": E.Particles(good.lam, good.vel[:, : n - 1].contiguous(), good.tet),
+        "lam": E.Particles(good.lam.float(), good.vel, good.tet),
+        "tet": E.Particles(good.lam, good.vel, good.tet.long()),
+        "ids": E.Particles(good.lam, good.vel, good.tet, torch.arange(n + 1, device="cuda")),
+    }
+    for name, parts in bad.items():
+        einval(E, lambda: ctx.gather_push_deposit(parts, sp, f, 0, w.dt, w.omega, dG), name)
+    # the compact storage needs float32 velocities
+    fixed = E.Particles.from_numpy(w.tet, w.lam, w.vel, precision=E.MIXED_FIXED)
+    einval(E, lambda: ctx.gather_push_deposit(E.Particles(fixed.lam, good.vel, fixed.tet), sp, f, 0, w.dt,
+                                              w.omega, dG), "vel")
+    short_b = E.Fields(f.e_env, f.b_env[:-1].contiguous(), f.e_dc, f.b_dc)
+    einval(E, lambda: ctx.gather_push_deposit(good, sp, short_b, 0, w.dt, w.omega, dG), "b_env")
+    assert torch.count_nonzero(dG).item() == 0

@@ -118,6 +118,8 @@ def log(*a):
 def kernel_name(form, slices):
     if slices <= 1:
         return KERNEL_NAME[form]
+    if slices == 2:   # two pipelined slices per wavefront (float forms)
+        return f"k_push_pipe<{'true' if form == 'mixed_fixed' else 'false'}>"
     if form == "mixed_fixed":
         return f"k_push_slices_fixed<{slices}, false>"
     return f"k_push_slices<{REAL[form]}, {slices}, false>"

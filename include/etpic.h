@@ -120,6 +120,13 @@ enum etpic_step_flags {
     ETPIC_STEP_SLICES_1 = 4u,
     ETPIC_STEP_SLICES_4 = 8u,
     ETPIC_STEP_SLICES_16 = 16u,
+    /* two slices per wavefront, the second slice's particle state requested
+     * before the first one's per-tet rows are read (the float32 forms; float64
+     * and the sorting and charge-scattering forms run one slice instead).
+     * Without a slice flag the library takes it for the float32 forms where
+     * the sort left one slice and the mesh's float32 per-tet rows (160 B per
+     * tet) exceed the 256 MB Infinity Cache. */
+    ETPIC_STEP_SLICES_2 = 512u,
     /* queue the particles that leave their tet by 64-particle slice, the path
      * the library otherwise takes only when more than 2^23 particles leave
      * their tet in one step (exercises that path); in the sorting step of
@@ -371,8 +378,8 @@ int etpic_gauss_residual(etpic_ctx *ctx, const double *dG, const double *rho_new
                          double out_host[2], void *stream);
 
 /* Slices of 64 particles per wavefront that the last particle-kernel launch of
- * a step call used (1: k_push, else k_push_slices<S>; 0 before any step).
- * Host only. */
+ * a step call used (1: k_push; 2: k_push_pipe, two pipelined slices; 4 or 16:
+ * k_push_slices<S>; 0 before any step).  Host only. */
 int etpic_last_push_slices(const etpic_ctx *ctx, int *slices);
 
 /* Measurement aid, not a step of the method: the particle kernel's HBM access

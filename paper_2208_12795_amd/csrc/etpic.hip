@@ -87,6 +87,8 @@ constexpr unsigned kQueueSkip = 0xffffffffu;  // particle-queue entry to skip
 // leave the coefficient pass more of the chip and pay fewer end-of-walk fences
 constexpr unsigned kWalkBlocks = 64;
 constexpr int64_t kMinPushWaves = 16384;      // 256 CUs x 64 wavefronts
+constexpr int64_t kInfinityCacheBytes = (int64_t)256 << 20;
+constexpr int64_t kFloatRowBytes = 48 + 64 + 48;   // float coefficient, push and geometry rows per tet
 
 // Runs of equal key among the 64 lanes of a wavefront (particles are kept
 // sorted by tet, so neighbouring lanes mostly share a key).  head: first lane
@@ -838,7 +840,7 @@ __device__ __forceinline__ T *lane_at(T *base, unsigned ln) {
     return reinterpret_cast<T *>(reinterpret_cast<char *>(base) + ln * (unsigned)sizeof(T));
 }
 
-template <typename Real, int kSlices, bool kRho, bool kScatter = false, bool kFixed = false>
+template <typename Real, int kSlices, bool kRho, bool kScatter = false, bool kFixed = false, bool kPipe = false>
 __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) {
     static_assert(!kFixed || std::is_same<Real, float>::value, "fixed-point barycentrics are a mixed-form storage");
     unsigned blk = blockIdx.x;
@@ -856,6 +858,35 @@ __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) 
     // and its sums, parked in LDS by lane 63 (6 path integrals, 4 barycentrics)
     __shared__ double s_carry[kBlock / 64][10];
     int carry_T = -1;
+    // kPipe: the next slice's tet and state are requested before this slice's
+    // tet rows, so that the rows' round trip overlaps those loads
+    int nT = -1;
+    double nl1 = 0.0, nl2 = 0.0, nl3 = 0.0;
+    uint32_t nu1 = 0, nu2 = 0, nu3 = 0;
+    Real nv0 = 0, nv1 = 0, nv2 = 0;
+    auto fetch = [&](int64_t sl) {
+        const int64_t bb = sl * 64;
+        unsigned lq = lane;
+        asm volatile("" : "+v"(lq));
+        __builtin_assume(lq < 64u);
+        nT = -1;
+        if (bb + lq < a.n) {
+            nT = __builtin_nontemporal_load(lane_at(a.tet + bb, lq));
+            if (kFixed) {
+                nu1 = __builtin_nontemporal_load(lane_at(reinterpret_cast<uint32_t *>(a.lam1) + bb, lq));
+                nu2 = __builtin_nontemporal_load(lane_at(reinterpret_cast<uint32_t *>(a.lam2) + bb, lq));
+                nu3 = __builtin_nontemporal_load(lane_at(reinterpret_cast<uint32_t *>(a.lam3) + bb, lq));
+            } else {
+                nl1 = __builtin_nontemporal_load(lane_at(a.lam1 + bb, lq));
+                nl2 = __builtin_nontemporal_load(lane_at(a.lam2 + bb, lq));
+                nl3 = __builtin_nontemporal_load(lane_at(a.lam3 + bb, lq));
+            }
+            nv0 = __builtin_nontemporal_load(lane_at(a.v0 + bb, lq));
+            nv1 = __builtin_nontemporal_load(lane_at(a.v1 + bb, lq));
+            nv2 = __builtin_nontemporal_load(lane_at(a.v2 + bb, lq));
+        }
+    };
+    if (kPipe) fetch(first);
 #pragma unroll 1
     for (int it = 0; it < kSlices; ++it) {
         const int64_t slice = first + it;
@@ -880,8 +911,8 @@ __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) 
         // that order when they sit behind the tet test).  The sliced forms keep
         // the later loads: the extra live registers cost them more than the
         // round trip (measured on both).
-        constexpr bool kEarly = kSlices == 1;
-        constexpr bool kSlots = push_uses_slots<Real>(kSlices);
+        constexpr bool kEarly = kSlices == 1 || kPipe;
+        constexpr bool kSlots = kPipe || push_uses_slots<Real>(kSlices);
         // the compact mixed form: barycentrics stored as uint32 fixed point
         constexpr bool fx = kFixed;
         uint32_t *__restrict__ f1 = reinterpret_cast<uint32_t *>(a.lam1) + b0;
@@ -905,9 +936,24 @@ __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) 
             sv1 = __builtin_nontemporal_load(lane_at(v1, ln));
             sv2 = __builtin_nontemporal_load(lane_at(v2, ln));
         };
+        if (kPipe) {
+            T = nT;
+            sl1 = nl1;
+            sl2 = nl2;
+            sl3 = nl3;
+            su1 = nu1;
+            su2 = nu2;
+            su3 = nu3;
+            sv0 = nv0;
+            sv1 = nv1;
+            sv2 = nv2;
+            if (it + 1 < kSlices) fetch(slice + 1);
+        }
         if (p < a.n) {
-            T = __builtin_nontemporal_load(lane_at(tetp, ln));
-            if (kEarly) load_state();
+            if (!kPipe) {
+                T = __builtin_nontemporal_load(lane_at(tetp, ln));
+                if (kEarly) load_state();
+            }
             if ((unsigned)T >= (unsigned)a.nt) {
                 atomicOr(a.status, (unsigned)ETPIC_DEV_BADTET);
                 T = -1;
@@ -1075,7 +1121,7 @@ __device__ __forceinline__ void push_slices(const StepArgs<Real> &a, int remap) 
 #pragma unroll
                     for (int k = 0; k < 4; ++k) r4[k] += cr[k];
                 } else {
-                    flush_run<Real, kRho, push_uses_slots<Real>(kSlices)>(a, carry_T, cg, cr);
+                    flush_run<Real, kRho, kPipe || push_uses_slots<Real>(kSlices)>(a, carry_T, cg, cr);
                 }
             }
         }
@@ -1193,6 +1239,17 @@ template <typename Real, int kSlices, bool kRho>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7)))
 k_push_sort_slices(StepArgs<Real> a, int remap) {
     push_slices<Real, kSlices, kRho, true>(a, remap);
+}
+
+// Two slices per wavefront with the second slice's state requested before the
+// first one's tet rows are read (float forms; the float64 kernel would need
+// 94 VGPRs for it).  Chosen where the mesh's float rows outgrow the Infinity
+// Cache, so that a wavefront's row reads are HBM round trips: there the state
+// loads of one slice overlap the row round trip of the other.
+template <bool kFixed>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7)))
+k_push_pipe(StepArgs<float> a, int remap) {
+    push_slices<float, 2, false, false, kFixed, true>(a, remap);
 }
 
 // The compact mixed form (barycentrics stored as uint32 fixed point): the same
@@ -3184,6 +3241,12 @@ struct etpic_ctx {
                     else
                         launch_timed(k_push_slices_fixed<4, kRho>, grid_for((n + 3) / 4), st, e0, e1, a, remap);
                     break;
+                case 2:
+                    if (!kSort && !kRho) {
+                        launch_timed(k_push_pipe<true>, grid_for((n + 1) / 2), st, e0, e1, a, remap);
+                        break;
+                    }
+                    [[fallthrough]];
                 default:
                     if (kSort)
                         launch_timed(k_push_sort_fixed<kRho>, grid_for(n), st, e0, e1, a, remap);
@@ -3194,7 +3257,8 @@ struct etpic_ctx {
                     slices = 1;
                     break;
                 }
-                return push_uses_slots<Real>(slices);
+                last_slices = slices;
+                return slices == 2 || push_uses_slots<Real>(slices);
             }
         }
         switch (slices) {
@@ -3210,6 +3274,14 @@ struct etpic_ctx {
             else
                 launch_timed(k_push_slices<Real, 4, kRho>, grid_for((n + 3) / 4), st, e0, e1, a, remap);
             break;
+        case 2:
+            if constexpr (std::is_same<Real, float>::value) {
+                if (!kSort && !kRho) {
+                    launch_timed(k_push_pipe<false>, grid_for((n + 1) / 2), st, e0, e1, a, remap);
+                    break;
+                }
+            }
+            [[fallthrough]];
         default:
             if (kSort)
                 launch_timed(k_push_sort<Real, kRho>, grid_for(n), st, e0, e1, a, remap);
@@ -3220,7 +3292,8 @@ struct etpic_ctx {
             slices = 1;
             break;
         }
-        return push_uses_slots<Real>(slices);
+        last_slices = slices;
+        return slices == 2 || push_uses_slots<Real>(slices);
     }
 
     // Counting sort, first half: tet counts of src, the run-length statistic
@@ -3362,6 +3435,7 @@ struct etpic_ctx {
     int push_slices_for(uint32_t flags, int64_t n, bool sorting = false) {
         if (flags & ETPIC_STEP_SLICES_16) return last_slices = 16;
         if (flags & ETPIC_STEP_SLICES_4) return last_slices = 4;
+        if (flags & ETPIC_STEP_SLICES_2) return last_slices = 2;
         if (flags & ETPIC_STEP_SLICES_1) return last_slices = 1;
         // The particle kernel adds a run's currents to its tet's slots, so
         // long runs cost it few same-address atomics: one slice measured
@@ -3369,7 +3443,15 @@ struct etpic_ctx {
         // the 2e8 bunch), and slices are kept for thousands.  The sorting
         // form takes one cursor atomic per run and tet, which slices divide:
         // it keeps them from a hundred particles per tet on
-        return last_slices = sorting ? slices_from_runs(n, 96.0, 256.0) : slices_from_runs(n, 1024.0, 4096.0);
+        if (sorting) return last_slices = slices_from_runs(n, 96.0, 256.0);
+        int s = slices_from_runs(n, 1024.0, 4096.0);
+        // one slice: two pipelined ones (float forms; float64 keeps one) where
+        // the float rows of the mesh (coefficient 48 B, push 64 B, geometry 48 B
+        // per tet) outgrow the 256 MB Infinity Cache (measured: large box
+        // mixed 4.09 -> 3.89 ms, compact 3.96 -> 3.79 ms; on the bench mesh,
+        // whose rows fit, 2-5 % slower)
+        if (s == 1 && host.nt * (int64_t)kFloatRowBytes > kInfinityCacheBytes && n / 128 >= kMinPushWaves) s = 2;
+        return last_slices = s;
     }
 
     // 1, 4 or 16 slices from the last sort's mean same-tet run length (read

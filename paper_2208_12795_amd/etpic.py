@@ -23,6 +23,7 @@ STEP_XCD_REMAP = 1
 STEP_TIMING = 2
 STEP_TIMING_ALL = 256
 STEP_SLICES_1, STEP_SLICES_4, STEP_SLICES_16 = 4, 8, 16
+STEP_SLICES_2 = 512
 STEP_WALK_BY_SLICE = 32
 NS_WARM = 64
 EM_SPLIT = 128

@@ -177,6 +177,53 @@ def test_dense_tets_slices(E, torch_cuda, ora, slices, precision, tol):
     ctx.close()
 
 
+@pytest.mark.parametrize("n_particles,dense", [(300_007, True), (20_011, False)])
+@pytest.mark.parametrize("precision", [1, 2])
+def test_pipelined_slices(E, torch_cuda, ora, n_particles, dense, precision):
+    """The float forms' two-slice kernel (the second slice's state requested
+    before the first one's rows; runs carried across the slice boundary),
+    forced by its flag: each step against the oracle, on runs of ~400
+    particles per tet (sorted) and on a sparse set with a ragged last slice;
+    continuity of the step's deposit against the charge moved.  float64 with
+    the same flag runs one slice."""
+    torch = torch_cuda
+    w = synth.make_workload(1, n_particles=n_particles)
+    if dense:
+        order = np.argsort(w.tet, kind="stable")
+        w.tet, w.lam, w.vel, w.ids = w.tet[order], w.lam[order], w.vel[order], w.ids[order]
+    flags = E.STEP_XCD_REMAP | E.STEP_SLICES_2
+    print(f"[pipe] N={n_particles} dense {dense} precision {precision}", flush=True)
+    ctx, parts, fields = setup(E, torch, w, precision)
+    M = ora.OracleMesh(w.xyz, w.tet_vert)
+    sp = E.Species(w.q, w.m, w.w)
+    for s in range(3):
+        tin, lin, vin, _ = parts.to_numpy()
+        dG = torch.zeros(ctx.n_edge, dtype=torch.float64, device="cuda")
+        rho0 = torch.zeros(ctx.n_vert, dtype=torch.float64, device="cuda")
+        rho1 = torch.zeros_like(rho0)
+        ctx.vertex_charge(parts, sp, rho0)
+        ctx.gather_push_deposit(parts, sp, fields, s, w.dt, w.omega, dG, flags=flags)
+        assert ctx.last_push_slices() == 2
+        ctx.vertex_charge(parts, sp, rho1)
+        r, p = ctx.gauss_residual(dG, rho1, rho0)
+        assert r <= 1e-12 * p, (r, p)
+        rc, o, dGo = oracle_step(M, (tin, lin, vin.astype(np.float64)), w, s, nthreads=NTH)
+        assert rc == 0
+        tg, lg, vg, _ = parts.to_numpy()
+        err = step_errors(w.xyz, w.tet_vert, (tin, lin, vin), (tg, lg, vg), o, dG.cpu().numpy(), dGo,
+                          lam_quantum=fixed_quantum(E, precision))
+        assert err["tet_mismatch"] <= 2 + 1e-4 * len(tg), err
+        assert_within(err, 2e-5, f"pipe step {s}")
+    ctx.check()
+    ctx.close()
+    ctx, parts, fields = setup(E, torch, w, E.FP64)
+    dG = torch.zeros(ctx.n_edge, dtype=torch.float64, device="cuda")
+    ctx.gather_push_deposit(parts, sp, fields, 0, w.dt, w.omega, dG, flags=flags)
+    assert ctx.last_push_slices() == 1
+    ctx.check()
+    ctx.close()
+
+
 def test_omega_zero_matches_regular(E, torch_cuda):
     """At w = 0 the GPU envelope run equals the GPU run with real DoFs Re(e~):
     the carrier factor is exactly one (reduction to the regular scheme)."""

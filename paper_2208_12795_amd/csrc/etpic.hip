@@ -1242,10 +1242,11 @@ k_push_sort_slices(StepArgs<Real> a, int remap) {
 }
 
 // Two slices per wavefront with the second slice's state requested before the
-// first one's tet rows are read (float forms; the float64 kernel would need
-// 94 VGPRs for it).  Chosen where the mesh's float rows outgrow the Infinity
-// Cache, so that a wavefront's row reads are HBM round trips: there the state
-// loads of one slice overlap the row round trip of the other.
+// first one's tet rows are read (float forms; in float64 the form needs 80
+// VGPRs, six wavefronts per SIMD, and measured no gain worth it).  Chosen where
+// the mesh's float rows outgrow the Infinity Cache, so that a wavefront's row
+// reads are HBM round trips: there the state loads of one slice overlap the
+// row round trip of the other.
 template <bool kFixed>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7)))
 k_push_pipe(StepArgs<float> a, int remap) {

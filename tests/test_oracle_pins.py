@@ -133,6 +133,37 @@ def test_constant_field_reproduction(mesh1):
         assert np.allclose(B, B0, rtol=1e-13, atol=1e-13)
 
 
+def test_whitney_fields_are_affine_in_the_low_order_form(mesh1):
+    """Inside a tet the lowest-order Whitney spaces are E = a + beta x x (edge
+    functions) and B = a + b x (face functions), the forms the particle
+    kernel's compact coefficient rows use: for random DoFs the oracle's
+    edge-by-edge fields satisfy E(x) = E(r_0) + beta x (x - r_0) with
+    beta = sum over local edges (i<j) of e_ij grad l_i x grad l_j, and
+    B(x) = B(r_0) + b (x - r_0) with b = (sum_k B(r_k) . grad l_k) / 3, to
+    rounding, at random points."""
+    rng = np.random.default_rng(11)
+    e_dc = rng.standard_normal(mesh1.ne)
+    b_dc = rng.standard_normal(mesh1.nf)
+    zero_e, zero_b = np.zeros(mesh1.ne, complex), np.zeros(mesh1.nf, complex)
+    te = mesh1.tet_edges()
+    pairs = [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]
+    eye = np.eye(4)
+    for T in rng.choice(mesh1.nt, 25, replace=False):
+        g = mesh1.grad(T)
+        beta = sum(e_dc[te[T, k]] * np.cross(g[i], g[j]) for k, (i, j) in enumerate(pairs))
+        E0, _ = mesh1.fields(T, eye[0], 0.0, 0.0, zero_e, zero_b, e_dc=e_dc, b_dc=b_dc)
+        Bv = [mesh1.fields(T, eye[k], 0.0, 0.0, zero_e, zero_b, e_dc=e_dc, b_dc=b_dc)[1] for k in range(4)]
+        b = sum(Bv[k] @ g[k] for k in range(4)) / 3.0
+        r0 = mesh1.point(T, eye[0])
+        for lam in rand_lam(rng, 4):
+            E, B = mesh1.fields(T, lam, 0.0, 0.0, zero_e, zero_b, e_dc=e_dc, b_dc=b_dc)
+            u = mesh1.point(T, lam) - r0
+            scale_e = np.abs(E0).max() + np.abs(np.cross(beta, u)).max()
+            assert np.abs(E - (E0 + np.cross(beta, u))).max() <= 1e-13 * scale_e
+            scale_b = np.abs(Bv[0]).max() + abs(b) * np.abs(u).max()
+            assert np.abs(B - (Bv[0] + b * u)).max() <= 1e-13 * scale_b
+
+
 def test_de_rham_curl(mesh1):
     """curl(sum e_e W1_e) = sum_f (circulation of e around f) W2_f inside each tet:
     the face DoFs of the curl are the discrete circulations (Stokes)."""

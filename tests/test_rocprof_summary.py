@@ -57,3 +57,18 @@ def test_valu_summary_from_counter_csv(tmp_path):
     out.write_text(text)
     assert "| `k_push<double>` | 2 | 100 | 4.2e+04 | 420.0 | 45.0 |" in text
     assert R.read_valu(str(out), "k_push<double>", sha) == (42000, 45.0)
+
+
+def test_committed_counter_summaries_match_the_source():
+    """Every committed counter summary that bench.py reads was taken on the
+    HIP source as it stands and names the particle kernels bench reports for
+    its workload (so the roofline's traffic and VALU figures are not null)."""
+    import bench
+    sha = R.source_sha256()
+    expect = {"40cube": ["k_push<double>", "k_push<float>", "k_push_fixed"],
+              "precision": ["k_push<double>", "k_push<float>", "k_push_fixed"],
+              "large-box": ["k_push<double>", "k_push_pipe<false>", "k_push_pipe<true>"]}
+    for key, (traffic, valu) in bench.PROFILE_SUMMARIES.items():
+        for k in expect[key]:
+            assert R.read_traffic(traffic, k, sha) is not None, (key, k, traffic)
+            assert R.read_valu(valu, k, sha) is not None, (key, k, valu)
